@@ -1,0 +1,377 @@
+"""CPU oracle for RO-MAP's per-object radiance-field training step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check and the CPU
+baseline leg of ``bench.py`` may import this package.  It shares no code with
+the GPU library (``paper_2304_05735_amd``) and the product path never calls it.
+
+``romap_oracle.c`` holds the arithmetic (FP64 values, FP32 position/index
+path).  This module wraps it with ctypes and keeps the host-side bookkeeping
+of the method in plain Python: the object registry, the keyframe sets with the
+incremental update rule of Eq. 5 (Sec. V-A "Data"), and dense Adam state.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "romap_oracle.c")
+_LIB = os.path.join(_HERE, "libromap_oracle.so")
+
+MAX_LEVELS = 16
+HIDDEN = 64
+GEO = 15
+DOUT = 16
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP32 path needs -ffp-contract=off)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+             "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Config(C.Structure):
+    _fields_ = [("L", C.c_int32), ("nmin", C.c_int32), ("nmax", C.c_int32), ("log2T", C.c_int32),
+                ("N", C.c_int32), ("margin_pct", C.c_int32),
+                ("lambda_depth", C.c_double), ("lambda_density", C.c_double),
+                ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("seed", C.c_uint64)]
+
+
+class Levels(C.Structure):
+    _fields_ = [("L", C.c_int32), ("N", C.c_int32 * MAX_LEVELS), ("T", C.c_int64 * MAX_LEVELS),
+                ("hashed", C.c_int32 * MAX_LEVELS), ("off", C.c_int64 * (MAX_LEVELS + 1))]
+
+
+class Keyframe(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("mask", C.c_void_p), ("depth", C.c_void_p),
+                ("W", C.c_int32), ("H", C.c_int32),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("M", C.c_float * 9), ("c", C.c_float * 3),
+                ("x0", C.c_int32), ("y0", C.c_int32), ("w", C.c_int32), ("h", C.c_int32)]
+
+
+class Ray(C.Structure):
+    _fields_ = [("kf", C.c_int32), ("u", C.c_int32), ("v", C.c_int32), ("cls", C.c_int32),
+                ("hit", C.c_int32), ("has_depth", C.c_int32),
+                ("C", C.c_float * 3), ("Crand", C.c_float * 3), ("D", C.c_float),
+                ("o", C.c_float * 3), ("d", C.c_float * 3), ("tn", C.c_float), ("tf", C.c_float),
+                ("delta", C.c_float),
+                ("Chat", C.c_double * 3), ("Dhat", C.c_double), ("Tend", C.c_double),
+                ("loss", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.c_void_p
+        _lib.or_grid_params.restype = C.c_int64
+        _lib.or_mlp_params.restype = C.c_int64
+        _lib.or_make_levels.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Levels)]
+        _lib.or_slab.argtypes = [P, P, P, P, P]
+        _lib.or_sample_positions.argtypes = [P, P, P, C.c_float, C.c_float, C.c_int, P, P, P]
+        _lib.or_pixel_ray.argtypes = [P, P, C.c_float, C.c_float, C.c_float, C.c_float,
+                                      C.c_int, C.c_int, P, P]
+        _lib.or_object_frame.argtypes = [P, P, C.c_float, P, P]
+        _lib.or_encode.argtypes = [C.POINTER(Levels), P, P, P, P, P]
+        _lib.or_mlp_forward.argtypes = [C.c_int, P, P, P, P, P, P, P]
+        _lib.or_composite.argtypes = [C.c_int, P, P, P, C.c_double, C.c_int, P, P, P, P, P]
+        _lib.or_candidate_rect.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P]
+        _lib.or_draw_ray.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, C.c_int,
+                                     C.POINTER(Keyframe), C.c_int, C.POINTER(Ray)]
+        _lib.or_object_step.argtypes = [C.POINTER(Config), C.POINTER(Levels), C.c_int, C.c_int, P,
+                                        C.c_int, C.POINTER(Keyframe), C.c_int, C.c_int, P, P, P,
+                                        C.POINTER(Ray), C.c_int]
+        _lib.or_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int, C.c_double, C.c_double,
+                                 C.c_double, C.c_double]
+        _lib.or_render.argtypes = [C.POINTER(Config), C.POINTER(Levels), P, C.POINTER(Keyframe), P,
+                                   P, P, P, C.c_int]
+        _lib.or_query_density.argtypes = [C.POINTER(Levels), P, P, C.c_int64, P, P]
+        _lib.or_philox4x32_10.argtypes = [P, P, P]
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# thin wrappers around single C functions (used by the pin tests)
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def levels(L, nmin, nmax, log2T) -> Levels:
+    lv = Levels()
+    if lib().or_make_levels(L, nmin, nmax, log2T, C.byref(lv)) != 0:
+        raise ValueError("bad level parameters")
+    return lv
+
+
+def grid_params(lv: Levels) -> int:
+    return int(lv.off[lv.L])
+
+
+def mlp_params(din: int) -> int:
+    return int(lib().or_mlp_params(din))
+
+
+def object_frame(Twc, t, yaw):
+    Twc = np.ascontiguousarray(Twc, np.float32).reshape(12)
+    t = np.ascontiguousarray(t, np.float32)
+    M = np.zeros(9, np.float32)
+    c = np.zeros(3, np.float32)
+    lib().or_object_frame(_p(Twc), _p(t), C.c_float(yaw), _p(M), _p(c))
+    return M, c
+
+
+def pixel_ray(M, c, fx, fy, cx, cy, u, v):
+    M = np.ascontiguousarray(M, np.float32)
+    c = np.ascontiguousarray(c, np.float32)
+    o = np.zeros(3, np.float32)
+    d = np.zeros(3, np.float32)
+    lib().or_pixel_ray(_p(M), _p(c), fx, fy, cx, cy, int(u), int(v), _p(o), _p(d))
+    return o, d
+
+
+def slab(o, d, half):
+    o = np.ascontiguousarray(o, np.float32)
+    d = np.ascontiguousarray(d, np.float32)
+    h = np.ascontiguousarray(half, np.float32)
+    tn = np.zeros(1, np.float32)
+    tf = np.zeros(1, np.float32)
+    hit = lib().or_slab(_p(o), _p(d), _p(h), _p(tn), _p(tf))
+    return bool(hit), float(tn[0]), float(tf[0])
+
+
+def sample_positions(o, d, half, tn, tf, N):
+    o = np.ascontiguousarray(o, np.float32)
+    d = np.ascontiguousarray(d, np.float32)
+    h = np.ascontiguousarray(half, np.float32)
+    delta = np.zeros(1, np.float32)
+    dist = np.zeros(N, np.float32)
+    pos = np.zeros((N, 3), np.float32)
+    lib().or_sample_positions(_p(o), _p(d), _p(h), tn, tf, N, _p(delta), _p(dist), _p(pos))
+    return float(delta[0]), dist, pos
+
+
+def encode(lv: Levels, p, grid):
+    p = np.ascontiguousarray(p, np.float32)
+    grid = np.ascontiguousarray(grid, np.float64)
+    L = lv.L
+    idx = np.zeros(8 * L, np.uint32)
+    w = np.zeros(8 * L, np.float64)
+    e = np.zeros(2 * L, np.float64)
+    lib().or_encode(C.byref(lv), _p(p), _p(grid), _p(idx), _p(w), _p(e))
+    return idx.reshape(L, 8), w.reshape(L, 8), e
+
+
+def mlp_forward(din, mlp, e):
+    mlp = np.ascontiguousarray(mlp, np.float64)
+    e = np.ascontiguousarray(e, np.float64)
+    h1 = np.zeros(HIDDEN)
+    y = np.zeros(DOUT)
+    h2 = np.zeros(HIDDEN)
+    sigma = np.zeros(1)
+    rgb = np.zeros(3)
+    lib().or_mlp_forward(din, _p(mlp), _p(e), _p(h1), _p(y), _p(h2), _p(sigma), _p(rgb))
+    return dict(h1=h1, y=y, h2=h2, sigma=float(sigma[0]), rgb=rgb)
+
+
+def composite(sigma, rgb, dist, delta, background=False, crand=(0.0, 0.0, 0.0)):
+    sigma = np.ascontiguousarray(sigma, np.float64)
+    rgb = np.ascontiguousarray(rgb, np.float64).reshape(-1, 3)
+    dist = np.ascontiguousarray(dist, np.float64)
+    N = sigma.shape[0]
+    cr = np.ascontiguousarray(crand, np.float64)
+    Cout = np.zeros(3)
+    D = np.zeros(1)
+    Tend = np.zeros(1)
+    w = np.zeros(N)
+    lib().or_composite(N, _p(sigma), _p(rgb), _p(dist), float(delta), int(background), _p(cr),
+                       _p(Cout), _p(D), _p(Tend), _p(w))
+    return Cout, float(D[0]), float(Tend[0]), w
+
+
+def candidate_rect(mask, instance, margin_pct=10):
+    mask = np.ascontiguousarray(mask, np.int32)
+    H, W = mask.shape
+    rect = np.zeros(4, np.int32)
+    ok = lib().or_candidate_rect(_p(mask), W, H, int(instance), int(margin_pct), _p(rect))
+    return tuple(int(x) for x in rect) if ok else None
+
+
+def adam(p, g, m, v, k, lr, b1, b2, eps):
+    """In-place dense Adam on float64 arrays; k is the step number (1 first)."""
+    lib().or_adam(p.size, _p(p), _p(g), _p(m), _p(v), int(k), lr, b1, b2, eps)
+
+
+# --------------------------------------------------------------------------
+# object / keyframe bookkeeping (same semantics as the GPU library's C ABI)
+
+def make_config(L=16, nmin=16, nmax=1024, log2T=19, N=64, margin_pct=10, lambda_depth=0.5,
+                lambda_density=0.01, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, seed=0) -> Config:
+    return Config(L, nmin, nmax, log2T, N, margin_pct, lambda_depth, lambda_density, lr, beta1,
+                  beta2, eps, seed)
+
+
+class _Kf:
+    """Keyframe as stored by the oracle: owned numpy copies of the images."""
+
+    def __init__(self, cam, rgb, mask, depth):
+        self.Twc = np.ascontiguousarray(cam["T_wc"], np.float32).reshape(12)
+        self.fx, self.fy, self.cx, self.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+        self.rgb = np.ascontiguousarray(rgb, np.uint8)
+        self.mask = np.ascontiguousarray(mask, np.int32)
+        self.depth = None if depth is None else np.ascontiguousarray(depth, np.float32)
+        self.H, self.W = self.mask.shape
+        self.centre = self.Twc.reshape(3, 4)[:, 3].astype(np.float64)
+
+
+class _Obj:
+    def __init__(self, instance, t, yaw, half, log2T, lv, params):
+        self.instance = int(instance)
+        self.t = np.asarray(t, np.float32)
+        self.yaw = float(np.float32(yaw))
+        self.half = np.asarray(half, np.float32)
+        self.log2T = log2T
+        self.lv = lv
+        self.params = params
+        self.m = np.zeros_like(params)
+        self.v = np.zeros_like(params)
+        self.grad = np.zeros_like(params)
+        self.k = 0
+        self.kfs: list[tuple[_Kf, tuple]] = []  # (keyframe, candidate rect)
+        self.last_centre = None
+
+
+class OracleContext:
+    """Plain CPU counterpart of the GPU library's context (same verbs)."""
+
+    def __init__(self, cfg: Config, alpha_deg: float = 25.0, nthreads: int | None = None):
+        self.cfg = cfg
+        self.alpha_deg = alpha_deg
+        self.nthreads = nthreads or os.cpu_count() or 1
+        self.objects: list[_Obj] = []
+        self.keyframes: list[_Kf] = []
+
+    # register object with box and table size (Sec. V: a new model per new instance)
+    def add_object(self, instance, t, yaw, half, log2T=None, params=None) -> int:
+        log2T = self.cfg.log2T if log2T is None else log2T
+        lv = levels(self.cfg.L, self.cfg.nmin, self.cfg.nmax, log2T)
+        P = grid_params(lv) + mlp_params(2 * self.cfg.L)
+        p = np.zeros(P) if params is None else np.array(params, np.float64)
+        assert p.size == P
+        self.objects.append(_Obj(instance, t, yaw, half, log2T, lv, p))
+        return len(self.objects) - 1
+
+    def n_params(self, oid) -> int:
+        return self.objects[oid].params.size
+
+    # add posed keyframe + mask; Eq. 5 decides per object whether it joins its set
+    def add_keyframe(self, cam, rgb, mask, depth=None) -> int:
+        kf = _Kf(cam, rgb, mask, depth)
+        self.keyframes.append(kf)
+        accepted = 0
+        for o in self.objects:
+            rect = candidate_rect(kf.mask, o.instance, self.cfg.margin_pct)
+            if rect is None:
+                continue  # the object is not observed in this image
+            if o.last_centre is not None:
+                a = o.last_centre - o.t.astype(np.float64)
+                b = kf.centre - o.t.astype(np.float64)
+                cosang = float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+                alpha = math.degrees(math.acos(max(-1.0, min(1.0, cosang))))
+                if not alpha > self.alpha_deg:
+                    continue
+            o.kfs.append((kf, rect))
+            o.last_centre = kf.centre
+            accepted += 1
+        return accepted
+
+    def _kf_array(self, o: _Obj):
+        arr = (Keyframe * len(o.kfs))()
+        for i, (kf, rect) in enumerate(o.kfs):
+            M, c = object_frame(kf.Twc, o.t, o.yaw)
+            k = arr[i]
+            k.rgb = kf.rgb.ctypes.data
+            k.mask = kf.mask.ctypes.data
+            k.depth = kf.depth.ctypes.data if kf.depth is not None else None
+            k.W, k.H = kf.W, kf.H
+            k.fx, k.fy, k.cx, k.cy = kf.fx, kf.fy, kf.cx, kf.cy
+            k.M[:] = M
+            k.c[:] = c
+            k.x0, k.y0, k.w, k.h = rect
+        return arr
+
+    def loss_and_grad(self, oid, step, B, rays=False, params=None, want_grad=True):
+        """Loss of one step and dL/dparams (no optimiser update)."""
+        o = self.objects[oid]
+        if not o.kfs:
+            raise RuntimeError("object has no keyframes")
+        kfa = self._kf_array(o)
+        p = o.params if params is None else np.ascontiguousarray(params, np.float64)
+        grad = np.zeros_like(p) if want_grad else None
+        loss = np.zeros(1)
+        ray_buf = (Ray * B)() if rays else None
+        rc = lib().or_object_step(C.byref(self.cfg), C.byref(o.lv), oid, o.instance, _p(o.half),
+                                  len(o.kfs), kfa, int(step), int(B), _p(p),
+                                  _p(grad) if want_grad else None, _p(loss), ray_buf,
+                                  self.nthreads)
+        if rc != 0:
+            raise RuntimeError("oracle step failed")
+        return float(loss[0]), grad, ray_buf
+
+    def train(self, oid, n_steps, B):
+        """n_steps of draw / render / loss / backward / dense Adam."""
+        o = self.objects[oid]
+        losses = []
+        for _ in range(n_steps):
+            loss, g, _ = self.loss_and_grad(oid, o.k, B)
+            o.k += 1
+            o.grad[:] = g
+            adam(o.params, o.grad, o.m, o.v, o.k, self.cfg.lr, self.cfg.beta1, self.cfg.beta2,
+                 self.cfg.eps)
+            losses.append(loss)
+        return losses
+
+    def render(self, oid, cam, W, H):
+        o = self.objects[oid]
+        kf = Keyframe()
+        M, c = object_frame(np.asarray(cam["T_wc"], np.float32), o.t, o.yaw)
+        kf.W, kf.H = W, H
+        kf.fx, kf.fy, kf.cx, kf.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+        kf.M[:] = M
+        kf.c[:] = c
+        rgb = np.zeros((H, W, 3))
+        depth = np.zeros((H, W))
+        opac = np.zeros((H, W))
+        lib().or_render(C.byref(self.cfg), C.byref(o.lv), _p(o.half), C.byref(kf), _p(o.params),
+                        _p(rgb), _p(depth), _p(opac), self.nthreads)
+        return rgb, depth, opac
+
+    def query_density(self, oid, xyz):
+        o = self.objects[oid]
+        xyz = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+        sig = np.zeros(xyz.shape[0])
+        lib().or_query_density(C.byref(o.lv), _p(o.half), _p(o.params), xyz.shape[0], _p(xyz),
+                               _p(sig))
+        return sig

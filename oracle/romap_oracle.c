@@ -1,0 +1,617 @@
+/*
+ * romap_oracle.c -- plain CPU oracle for one training step of RO-MAP's
+ * per-object radiance fields (arXiv 2304.05735, Sec. V "Multi-Object
+ * Reconstruction System").
+ *
+ * TEST INFRASTRUCTURE ONLY.  The GPU library is checked against this file.
+ * It shares no code with the GPU library, and nothing on the product path
+ * may load it.  It is written for clarity, not speed: one ray at a time, one
+ * sample at a time, in the order the paper states the steps.
+ *
+ * Precision: every value is FP64, except the ray / slab / sample-position /
+ * hash-index path, which is IEEE FP32 in the fixed expression order written
+ * below (build with -ffp-contract=off).  That path decides integers (grid
+ * cells, hash indices), so both sides must take those decisions in the same
+ * precision.
+ *
+ * Readings where the paper is silent (all listed in the design notes):
+ *  - hash grid: the multiresolution hash encoding the paper cites
+ *    (Mueller et al. 2022): per level resolution N_l, dense 1:1 indexing when
+ *    (N_l+1)^3 <= T, otherwise XOR of coordinate * {1, 2654435761, 805459861}
+ *    modulo T; trilinear blend of F = 2 features;
+ *  - N_l = floor(N_min * b^l + 1e-6), b = exp((ln N_max - ln N_min)/(L-1));
+ *  - the box maps to the unit cube anisotropically, p = (x + a) / (2a),
+ *    clamped to [0,1];
+ *  - uniform sampling (Sec. V-B) places N midpoints in [t_n, t_f] with equal
+ *    spacing delta, and every sample uses delta (the last one too);
+ *  - sigma = exp(min(y0, 15)); no MLP biases; colour = sigmoid;
+ *  - background rays composite the residual transmittance against their
+ *    random colour, object rays composite on black (Eq. 6, Eq. 9);
+ *  - L_rgb and L_rr use the squared per-channel error; every ray term is
+ *    divided by the number of rays drawn for the object;
+ *  - optimiser: dense Adam (the paper does not name its optimiser).
+ */
+#include "romap_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based generator Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+ * The paper draws its 4096 rays "randomly" from all training images and gives
+ * background rays random colours (Sec. V-B, Sec. VI implementation details);
+ * Philox makes every draw a pure function of (seed, object, step, ray). */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u; /* golden ratio */
+      k1 += 0xBB67AE85u; /* sqrt(3) - 1 */
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y1 = lo1;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    uint32_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level table of the multiresolution hash encoding (Sec. V: each object model
+ * is a hash encoding plus a small MLP; table size T and finest resolution are
+ * the model parameters of Sec. VI). */
+int or_make_levels(int L, int nmin, int nmax, int log2T, or_levels* out) {
+  if (L < 1 || L > OR_MAX_LEVELS || nmin < 1 || nmax < nmin || log2T < 4 || log2T > 24)
+    return -1;
+  memset(out, 0, sizeof(*out));
+  out->L = L;
+  double b = 1.0;
+  if (L > 1) b = exp((log((double)nmax) - log((double)nmin)) / (double)(L - 1));
+  int64_t T = (int64_t)1 << log2T;
+  int64_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    int N = (L > 1) ? (int)floor((double)nmin * pow(b, (double)l) + 1e-6) : nmin;
+    int64_t dense = (int64_t)(N + 1) * (N + 1) * (N + 1);
+    out->N[l] = N;
+    out->hashed[l] = dense > T;
+    out->T[l] = dense > T ? T : dense;
+    out->off[l] = off;
+    off += out->T[l] * 2;
+  }
+  out->off[L] = off;
+  return 0;
+}
+
+int64_t or_grid_params(const or_levels* lv) { return lv->off[lv->L]; }
+
+/* W1 (64 x din), W2 (16 x 64), W3 (64 x 15), W4 (3 x 64), row-major, no biases */
+int64_t or_mlp_params(int din) {
+  return (int64_t)OR_HIDDEN * din + OR_DOUT * OR_HIDDEN + OR_HIDDEN * OR_GEO + 3 * OR_HIDDEN;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Camera pose into the object frame (Sec. V-B: "transform the camera pose to
+ * the object coordinate system").  Objects have roll = pitch = 0 and a yaw
+ * theta about the world up axis, centre t (Sec. IV-B, Eq. 1); the camera pose
+ * T_wc maps camera to world (Eq. 3).  x_obj = R(theta)^T (R_wc x_cam + t_wc - t),
+ * so M = R^T R_wc and c = R^T (t_wc - t), computed in FP64, rounded once. */
+void or_object_frame(const float Twc[12], const float t[3], float yaw, float M[9], float c[3]) {
+  double ct = cos((double)yaw), st = sin((double)yaw);
+  for (int j = 0; j < 3; ++j) {
+    double r0 = (double)Twc[0 * 4 + j], r1 = (double)Twc[1 * 4 + j], r2 = (double)Twc[2 * 4 + j];
+    M[0 * 3 + j] = (float)(ct * r0 + st * r1);
+    M[1 * 3 + j] = (float)(-st * r0 + ct * r1);
+    M[2 * 3 + j] = (float)r2;
+  }
+  double dx = (double)Twc[3] - (double)t[0];
+  double dy = (double)Twc[7] - (double)t[1];
+  double dz = (double)Twc[11] - (double)t[2];
+  c[0] = (float)(ct * dx + st * dy);
+  c[1] = (float)(-st * dx + ct * dy);
+  c[2] = (float)dz;
+}
+
+/* Back-project pixel (u, v) (Sec. V-B).  Pinhole camera, x right, y down,
+ * z forward, pixel centres at +0.5.  FP32, fixed order. */
+void or_pixel_ray(const float M[9], const float c[3], float fx, float fy, float cx, float cy,
+                  int u, int v, float o[3], float d[3]) {
+  float x = (((float)u + 0.5f) - cx) / fx;
+  float y = (((float)v + 0.5f) - cy) / fy;
+  float dd[3];
+  for (int k = 0; k < 3; ++k) dd[k] = (M[3 * k + 0] * x + M[3 * k + 1] * y) + M[3 * k + 2];
+  float n = sqrtf((dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]);
+  for (int k = 0; k < 3; ++k) {
+    d[k] = dd[k] / n;
+    o[k] = c[k];
+  }
+}
+
+/* Ray / 3D box intersection giving the truncation interval (Sec. V-B).
+ * The box is [-a, a] in the object frame (a = half size, Eq. 4).  Slab test
+ * with NaN-ignoring min/max; the near end is clamped at the camera. */
+int or_slab(const float o[3], const float d[3], const float half[3], float* tn, float* tf) {
+  float tmin = -INFINITY, tmax = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    float inv = 1.0f / d[k];
+    float t0 = (-half[k] - o[k]) * inv;
+    float t1 = (half[k] - o[k]) * inv;
+    tmin = fmaxf(tmin, fminf(t0, t1));
+    tmax = fminf(tmax, fmaxf(t0, t1));
+  }
+  float n = fmaxf(tmin, 0.0f);
+  *tn = n;
+  *tf = tmax;
+  return tmax > n;
+}
+
+/* Uniform sampling of N points inside the truncation interval (Sec. V-B, no
+ * importance sampling).  Midpoints of N equal steps; delta_i = delta. */
+void or_sample_positions(const float o[3], const float d[3], const float half[3], float tn,
+                         float tf, int N, float* delta, float* dist, float* pos) {
+  float dl = (tf - tn) / (float)N;
+  *delta = dl;
+  for (int i = 0; i < N; ++i) {
+    float di = tn + ((float)i + 0.5f) * dl;
+    dist[i] = di;
+    for (int k = 0; k < 3; ++k) {
+      float x = o[k] + di * d[k];
+      float p = (x + half[k]) / (half[k] + half[k]);
+      p = fminf(fmaxf(p, 0.0f), 1.0f);
+      pos[3 * i + k] = p;
+    }
+  }
+}
+
+/* Multiresolution hash encoding of one point (the encoding of Sec. V, as
+ * defined by the cited Mueller et al. 2022).  idx/w: 8 corners per level;
+ * e: L*2 features.  Corner b uses bit0 = x, bit1 = y, bit2 = z. */
+void or_encode(const or_levels* lv, const float p[3], const double* grid, uint32_t* idx,
+               double* w, double* e) {
+  for (int l = 0; l < lv->L; ++l) {
+    int N = lv->N[l];
+    float Nf = (float)N;
+    int cell[3];
+    float fr[3];
+    for (int k = 0; k < 3; ++k) {
+      float g = p[k] * Nf;
+      int ci = (int)floorf(g);
+      if (ci < 0) ci = 0;
+      if (ci > N - 1) ci = N - 1;
+      cell[k] = ci;
+      fr[k] = g - (float)ci;
+    }
+    const double* G = grid + lv->off[l];
+    e[2 * l + 0] = 0.0;
+    e[2 * l + 1] = 0.0;
+    for (int b = 0; b < 8; ++b) {
+      uint32_t vx = (uint32_t)(cell[0] + (b & 1));
+      uint32_t vy = (uint32_t)(cell[1] + ((b >> 1) & 1));
+      uint32_t vz = (uint32_t)(cell[2] + ((b >> 2) & 1));
+      uint32_t id;
+      if (lv->hashed[l]) {
+        id = (vx * 1u) ^ (vy * 2654435761u) ^ (vz * 805459861u);
+        id &= (uint32_t)(lv->T[l] - 1);
+      } else {
+        uint32_t n1 = (uint32_t)N + 1u;
+        id = vx + vy * n1 + vz * n1 * n1;
+      }
+      double wb = 1.0;
+      for (int k = 0; k < 3; ++k) wb *= ((b >> k) & 1) ? (double)fr[k] : 1.0 - (double)fr[k];
+      idx[8 * l + b] = id;
+      w[8 * l + b] = wb;
+      e[2 * l + 0] += wb * G[2 * (int64_t)id + 0];
+      e[2 * l + 1] += wb * G[2 * (int64_t)id + 1];
+    }
+  }
+}
+
+/* Density / colour MLP (Sec. V: a single hidden layer of 64 per head; position
+ * only, no view direction, Sec. V-B).  h1 = ReLU(W1 e), y = W2 h1,
+ * sigma = exp(min(y0, 15)), h2 = ReLU(W3 y[1..15]), rgb = sigmoid(W4 h2). */
+void or_mlp_forward(int din, const double* mlp, const double* e, double* h1, double* y,
+                    double* h2, double* sigma, double* rgb) {
+  const double* W1 = mlp;
+  const double* W2 = W1 + OR_HIDDEN * din;
+  const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
+  const double* W4 = W3 + OR_HIDDEN * OR_GEO;
+  for (int i = 0; i < OR_HIDDEN; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < din; ++j) s += W1[i * din + j] * e[j];
+    h1[i] = s > 0.0 ? s : 0.0;
+  }
+  for (int i = 0; i < OR_DOUT; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) s += W2[i * OR_HIDDEN + j] * h1[j];
+    y[i] = s;
+  }
+  *sigma = exp(fmin(y[0], 15.0));
+  for (int i = 0; i < OR_HIDDEN; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < OR_GEO; ++j) s += W3[i * OR_GEO + j] * y[1 + j];
+    h2[i] = s > 0.0 ? s : 0.0;
+  }
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) s += W4[i * OR_HIDDEN + j] * h2[j];
+    rgb[i] = 1.0 / (1.0 + exp(-s));
+  }
+}
+
+/* Volume rendering (Sec. V-B, Eq. 6): o_i = 1 - exp(-sigma_i delta_i),
+ * w_i = o_i prod_{j<i} (1 - o_j), C = sum w_i c_i, D = sum w_i d_i.
+ * Background rays add T_end * C_random (reading of Eq. 9). */
+void or_composite(int N, const double* sigma, const double* rgb, const double* dist, double delta,
+                  int background, const double crand[3], double C[3], double* D, double* Tend,
+                  double* w) {
+  double S = 0.0;
+  C[0] = C[1] = C[2] = 0.0;
+  *D = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double tau = sigma[i] * delta;
+    double T = exp(-S);
+    double a = -expm1(-tau);
+    double wi = T * a;
+    w[i] = wi;
+    for (int k = 0; k < 3; ++k) C[k] += wi * rgb[3 * i + k];
+    *D += wi * dist[i];
+    S += tau;
+  }
+  *Tend = exp(-S);
+  if (background)
+    for (int k = 0; k < 3; ++k) C[k] += *Tend * crand[k];
+}
+
+/* Candidate pixels of one object in one keyframe: the object's 2D detection
+ * box (Sec. V-B back-projects "pixels within the object's detection box"),
+ * read as the bounding box of its mask pixels widened by margin_pct percent
+ * of its size on every side (integer ceiling), clamped to the image. */
+int or_candidate_rect(const int32_t* mask, int W, int H, int instance, int margin_pct,
+                      int32_t rect[4]) {
+  int xmin = W, xmax = -1, ymin = H, ymax = -1;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x)
+      if (mask[(int64_t)y * W + x] == instance) {
+        if (x < xmin) xmin = x;
+        if (x > xmax) xmax = x;
+        if (y < ymin) ymin = y;
+        if (y > ymax) ymax = y;
+      }
+  if (xmax < 0) return 0;
+  int w0 = xmax - xmin + 1, h0 = ymax - ymin + 1;
+  int mx = (w0 * margin_pct + 99) / 100, my = (h0 * margin_pct + 99) / 100;
+  int x0 = xmin - mx < 0 ? 0 : xmin - mx;
+  int y0 = ymin - my < 0 ? 0 : ymin - my;
+  int x1 = xmax + mx > W - 1 ? W - 1 : xmax + mx;
+  int y1 = ymax + my > H - 1 ? H - 1 : ymax + my;
+  rect[0] = x0;
+  rect[1] = y0;
+  rect[2] = x1 - x0 + 1;
+  rect[3] = y1 - y0 + 1;
+  return 1;
+}
+
+/* Draw ray r of step `step` for object `obj` (Sec. VI: rays drawn at random
+ * from all training images of the object; Sec. V-B: classified by the
+ * instance mask into object rays R_o, background rays R_b and occluder rays).
+ * Candidates are enumerated keyframe by keyframe, row-major inside each
+ * candidate rectangle; the draw is uniform with replacement. */
+void or_draw_ray(const or_config* cfg, int obj, int step, int r, int nkf, const or_keyframe* kfs,
+                 int instance, or_ray* out) {
+  memset(out, 0, sizeof(*out));
+  uint32_t key[2] = {(uint32_t)cfg->seed ^ (uint32_t)obj, (uint32_t)(cfg->seed >> 32)};
+  uint32_t ctr[4] = {(uint32_t)step, (uint32_t)r, 0u, 0u};
+  uint32_t x[4];
+  or_philox4x32_10(ctr, key, x);
+  int64_t ncand = 0;
+  for (int k = 0; k < nkf; ++k) ncand += (int64_t)kfs[k].w * kfs[k].h;
+  int64_t q = (int64_t)(((uint64_t)x[0] * (uint64_t)ncand) >> 32);
+  int k = 0;
+  while (q >= (int64_t)kfs[k].w * kfs[k].h) {
+    q -= (int64_t)kfs[k].w * kfs[k].h;
+    ++k;
+  }
+  const or_keyframe* kf = &kfs[k];
+  int u = kf->x0 + (int)(q % kf->w);
+  int v = kf->y0 + (int)(q / kf->w);
+  out->kf = k;
+  out->u = u;
+  out->v = v;
+  for (int j = 0; j < 3; ++j) out->Crand[j] = (float)(x[j + 1] >> 8) * (1.0f / 16777216.0f);
+  int64_t pix = (int64_t)v * kf->W + u;
+  int m = kf->mask[pix];
+  out->cls = (m == instance) ? 1 : (m == 0 ? 2 : 0);
+  for (int j = 0; j < 3; ++j) out->C[j] = (float)kf->rgb[3 * pix + j] / 255.0f;
+  out->has_depth = 0;
+  out->D = 0.0f;
+  if (kf->depth && out->cls == 1) {
+    float z = kf->depth[pix];
+    if (z > 0.0f && isfinite(z)) {
+      /* sparse depth is camera z; the loss compares ray distance (Eq. 8) */
+      float xn = (((float)u + 0.5f) - kf->cx) / kf->fx;
+      float yn = (((float)v + 0.5f) - kf->cy) / kf->fy;
+      out->has_depth = 1;
+      out->D = z * sqrtf((xn * xn + yn * yn) + 1.0f);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One training step of one object: draw, render, loss (Eq. 7-11), gradient
+ * of the loss with respect to every parameter.  `grad` (may be NULL) is
+ * overwritten with dL/dparams.  `rays` (may be NULL) receives the per-ray
+ * record.  The loss is L = (1/B) sum_r l_r. */
+typedef struct {
+  uint32_t* idx;
+  double *w, *e, *h1, *y, *h2, *sigma, *rgb, *dist, *wts, *dsig, *tnext;
+  float *pos, *dist32;
+} or_scratch;
+
+static void scratch_alloc(or_scratch* s, int N, int L) {
+  s->idx = (uint32_t*)malloc(sizeof(uint32_t) * N * L * 8);
+  s->w = (double*)malloc(sizeof(double) * N * L * 8);
+  s->e = (double*)malloc(sizeof(double) * N * L * 2);
+  s->h1 = (double*)malloc(sizeof(double) * N * OR_HIDDEN);
+  s->y = (double*)malloc(sizeof(double) * N * OR_DOUT);
+  s->h2 = (double*)malloc(sizeof(double) * N * OR_HIDDEN);
+  s->sigma = (double*)malloc(sizeof(double) * N);
+  s->rgb = (double*)malloc(sizeof(double) * N * 3);
+  s->dist = (double*)malloc(sizeof(double) * N);
+  s->wts = (double*)malloc(sizeof(double) * N);
+  s->dsig = (double*)malloc(sizeof(double) * N);
+  s->tnext = (double*)malloc(sizeof(double) * N);
+  s->pos = (float*)malloc(sizeof(float) * N * 3);
+  s->dist32 = (float*)malloc(sizeof(float) * N);
+}
+
+static void scratch_free(or_scratch* s) {
+  free(s->idx); free(s->w); free(s->e); free(s->h1); free(s->y); free(s->h2);
+  free(s->sigma); free(s->rgb); free(s->dist); free(s->wts); free(s->dsig); free(s->tnext);
+  free(s->pos); free(s->dist32);
+}
+
+/* Backward of one sample through the MLPs and the encoding.  dsig, dc are
+ * dl/dsigma and dl/dc of this sample; adds into grad (grid, then MLP). */
+static void sample_backward(const or_levels* lv, int din, const double* mlp, const uint32_t* idx,
+                            const double* w, const double* e, const double* h1, const double* y,
+                            const double* h2, double sigma, const double* rgb, double dsig,
+                            const double* dc, double* grad) {
+  const double* W1 = mlp;
+  const double* W2 = W1 + OR_HIDDEN * din;
+  const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
+  const double* W4 = W3 + OR_HIDDEN * OR_GEO;
+  double* gG = grad;
+  double* gW1 = grad + or_grid_params(lv);
+  double* gW2 = gW1 + OR_HIDDEN * din;
+  double* gW3 = gW2 + OR_DOUT * OR_HIDDEN;
+  double* gW4 = gW3 + OR_HIDDEN * OR_GEO;
+  double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], dh1[OR_HIDDEN], de[2 * OR_MAX_LEVELS];
+  for (int k = 0; k < 3; ++k) dz4[k] = dc[k] * rgb[k] * (1.0 - rgb[k]);
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < OR_HIDDEN; ++j) gW4[k * OR_HIDDEN + j] += dz4[k] * h2[j];
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) s += W4[k * OR_HIDDEN + j] * dz4[k];
+    dh2[j] = h2[j] > 0.0 ? s : 0.0;
+  }
+  for (int j = 0; j < OR_HIDDEN; ++j)
+    for (int g = 0; g < OR_GEO; ++g) gW3[j * OR_GEO + g] += dh2[j] * y[1 + g];
+  for (int g = 0; g < OR_GEO; ++g) {
+    double s = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) s += W3[j * OR_GEO + g] * dh2[j];
+    dy[1 + g] = s;
+  }
+  dy[0] = y[0] < 15.0 ? dsig * sigma : 0.0;
+  for (int i = 0; i < OR_DOUT; ++i)
+    for (int j = 0; j < OR_HIDDEN; ++j) gW2[i * OR_HIDDEN + j] += dy[i] * h1[j];
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < OR_DOUT; ++i) s += W2[i * OR_HIDDEN + j] * dy[i];
+    dh1[j] = h1[j] > 0.0 ? s : 0.0;
+  }
+  for (int j = 0; j < OR_HIDDEN; ++j)
+    for (int q = 0; q < din; ++q) gW1[j * din + q] += dh1[j] * e[q];
+  for (int q = 0; q < din; ++q) {
+    double s = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) s += W1[j * din + q] * dh1[j];
+    de[q] = s;
+  }
+  for (int l = 0; l < lv->L; ++l)
+    for (int b = 0; b < 8; ++b) {
+      int64_t at = lv->off[l] + 2 * (int64_t)idx[8 * l + b];
+      gG[at + 0] += w[8 * l + b] * de[2 * l + 0];
+      gG[at + 1] += w[8 * l + b] * de[2 * l + 1];
+    }
+}
+
+int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int instance,
+                   const float half[3], int nkf, const or_keyframe* kfs, int step, int B,
+                   const double* params, double* grad, double* loss, or_ray* rays, int nthreads) {
+  if (nkf < 1 || B < 1 || cfg->N < 1) return -1;
+  const int L = lv->L, N = cfg->N, din = 2 * L;
+  const int64_t Pg = or_grid_params(lv);
+  const int64_t P = Pg + or_mlp_params(din);
+  const double* mlp = params + Pg;
+  if (nthreads < 1) nthreads = 1;
+  double* ray_loss = (double*)calloc((size_t)B, sizeof(double));
+  double* tgrad = NULL;
+  if (grad) tgrad = (double*)calloc((size_t)P * nthreads, sizeof(double));
+
+#pragma omp parallel num_threads(nthreads)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    or_scratch s;
+    scratch_alloc(&s, N, L);
+    double* my_grad = grad ? tgrad + (int64_t)tid * P : NULL;
+#pragma omp for schedule(static)
+    for (int r = 0; r < B; ++r) {
+      or_ray ray;
+      or_draw_ray(cfg, obj, step, r, nkf, kfs, instance, &ray);
+      const or_keyframe* kf = &kfs[ray.kf];
+      or_pixel_ray(kf->M, kf->c, kf->fx, kf->fy, kf->cx, kf->cy, ray.u, ray.v, ray.o, ray.d);
+      ray.hit = or_slab(ray.o, ray.d, half, &ray.tn, &ray.tf);
+      ray.loss = 0.0;
+      /* occluder rays carry no loss (Sec. V-B); rays missing the box have no samples */
+      if (ray.cls != 0 && ray.hit) {
+        or_sample_positions(ray.o, ray.d, half, ray.tn, ray.tf, N, &ray.delta, s.dist32, s.pos);
+        for (int i = 0; i < N; ++i) s.dist[i] = (double)s.dist32[i];
+        for (int i = 0; i < N; ++i) {
+          or_encode(lv, s.pos + 3 * i, params, s.idx + 8 * L * i, s.w + 8 * L * i, s.e + 2 * L * i);
+          or_mlp_forward(din, mlp, s.e + 2 * L * i, s.h1 + OR_HIDDEN * i, s.y + OR_DOUT * i,
+                         s.h2 + OR_HIDDEN * i, s.sigma + i, s.rgb + 3 * i);
+        }
+        double crand[3] = {ray.Crand[0], ray.Crand[1], ray.Crand[2]};
+        int bg = ray.cls == 2;
+        or_composite(N, s.sigma, s.rgb, s.dist, (double)ray.delta, bg, crand, ray.Chat, &ray.Dhat,
+                     &ray.Tend, s.wts);
+        /* Eq. 7-11: squared colour error against the image (object rays) or
+         * the random colour (background rays); depth and density terms. */
+        double target[3];
+        for (int k = 0; k < 3; ++k) target[k] = bg ? crand[k] : (double)ray.C[k];
+        double l = 0.0;
+        for (int k = 0; k < 3; ++k) l += (ray.Chat[k] - target[k]) * (ray.Chat[k] - target[k]);
+        if (!bg && ray.has_depth) l += cfg->lambda_depth * fabs(ray.Dhat - (double)ray.D);
+        if (bg) {
+          double ssum = 0.0;
+          for (int i = 0; i < N; ++i) ssum += s.sigma[i];
+          l += cfg->lambda_density * ssum;
+        }
+        ray.loss = l / (double)B;
+        if (my_grad) {
+          double gC[3], gD = 0.0;
+          for (int k = 0; k < 3; ++k) gC[k] = 2.0 * (ray.Chat[k] - target[k]) / (double)B;
+          if (!bg && ray.has_depth) {
+            double diff = ray.Dhat - (double)ray.D;
+            gD = cfg->lambda_depth * (diff > 0.0 ? 1.0 : (diff < 0.0 ? -1.0 : 0.0)) / (double)B;
+          }
+          /* adjoint of Eq. 6: dC/dtau_i = T_{i+1} c_i - sum_{j>i} w_j c_j, and for
+           * background rays also - T_end C_rand (T_end = exp(-sum tau)). */
+          double suf_c[3] = {0.0, 0.0, 0.0}, suf_d = 0.0;
+          double S_i = 0.0;
+          for (int i = 0; i < N; ++i) {
+            S_i += s.sigma[i] * (double)ray.delta;
+            s.tnext[i] = exp(-S_i);
+          }
+          double* Tnext = s.tnext;
+          double Tend = ray.Tend;
+          for (int i = N - 1; i >= 0; --i) {
+            double a = 0.0;
+            for (int k = 0; k < 3; ++k) a += gC[k] * (Tnext[i] * s.rgb[3 * i + k] - suf_c[k]);
+            if (bg)
+              for (int k = 0; k < 3; ++k) a -= gC[k] * Tend * crand[k];
+            a += gD * (Tnext[i] * s.dist[i] - suf_d);
+            s.dsig[i] = a * (double)ray.delta + (bg ? cfg->lambda_density / (double)B : 0.0);
+            for (int k = 0; k < 3; ++k) suf_c[k] += s.wts[i] * s.rgb[3 * i + k];
+            suf_d += s.wts[i] * s.dist[i];
+          }
+          for (int i = 0; i < N; ++i) {
+            double dci[3];
+            for (int k = 0; k < 3; ++k) dci[k] = s.wts[i] * gC[k];
+            sample_backward(lv, din, mlp, s.idx + 8 * L * i, s.w + 8 * L * i, s.e + 2 * L * i,
+                            s.h1 + OR_HIDDEN * i, s.y + OR_DOUT * i, s.h2 + OR_HIDDEN * i,
+                            s.sigma[i], s.rgb + 3 * i, s.dsig[i], dci, my_grad);
+          }
+        }
+      }
+      ray_loss[r] = ray.loss;
+      if (rays) rays[r] = ray;
+    }
+    scratch_free(&s);
+  }
+  double total = 0.0;
+  for (int r = 0; r < B; ++r) total += ray_loss[r];
+  *loss = total;
+  if (grad) {
+    for (int64_t i = 0; i < P; ++i) {
+      double acc = 0.0;
+      for (int t = 0; t < nthreads; ++t) acc += tgrad[(int64_t)t * P + i];
+      grad[i] = acc;
+    }
+    free(tgrad);
+  }
+  free(ray_loss);
+  return 0;
+}
+
+/* Dense Adam (the paper's "backward and optimization" phase; optimiser not
+ * named).  k is the step number after increment (1 on the first step). */
+void or_adam(int64_t P, double* p, double* g, double* m, double* v, int k, double lr, double b1,
+             double b2, double eps) {
+  double bc1 = 1.0 - pow(b1, (double)k);
+  double bc2 = 1.0 - pow(b2, (double)k);
+  for (int64_t i = 0; i < P; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    p[i] -= lr * (m[i] / bc1) / (sqrt(v[i] / bc2) + eps);
+    g[i] = 0.0;
+  }
+}
+
+/* Render every pixel of a camera through the object's box (evaluation and
+ * meshing); composited on black, opacity = 1 - T_end.  Misses give 0. */
+int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
+              const or_keyframe* cam, const double* params, double* rgb, double* depth,
+              double* opacity, int nthreads) {
+  const int L = lv->L, N = cfg->N, din = 2 * L;
+  const double* mlp = params + or_grid_params(lv);
+  const int64_t npix = (int64_t)cam->W * cam->H;
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+  {
+    or_scratch s;
+    scratch_alloc(&s, N, L);
+#pragma omp for schedule(static)
+    for (int64_t px = 0; px < npix; ++px) {
+      int u = (int)(px % cam->W), v = (int)(px / cam->W);
+      float o[3], d[3], tn, tf, dl;
+      or_pixel_ray(cam->M, cam->c, cam->fx, cam->fy, cam->cx, cam->cy, u, v, o, d);
+      double C[3] = {0.0, 0.0, 0.0}, D = 0.0, Tend = 1.0;
+      if (or_slab(o, d, half, &tn, &tf)) {
+        or_sample_positions(o, d, half, tn, tf, N, &dl, s.dist32, s.pos);
+        for (int i = 0; i < N; ++i) {
+          s.dist[i] = (double)s.dist32[i];
+          or_encode(lv, s.pos + 3 * i, params, s.idx, s.w, s.e);
+          or_mlp_forward(din, mlp, s.e, s.h1, s.y, s.h2, s.sigma + i, s.rgb + 3 * i);
+        }
+        double zero[3] = {0.0, 0.0, 0.0};
+        or_composite(N, s.sigma, s.rgb, s.dist, (double)dl, 0, zero, C, &D, &Tend, s.wts);
+      }
+      for (int k = 0; k < 3; ++k) rgb[3 * px + k] = C[k];
+      if (depth) depth[px] = D;
+      if (opacity) opacity[px] = 1.0 - Tend;
+    }
+    scratch_free(&s);
+  }
+  return 0;
+}
+
+/* Density at object-frame points (used for meshing by marching cubes). */
+void or_query_density(const or_levels* lv, const float half[3], const double* params, int64_t n,
+                      const float* xyz, double* sigma) {
+  const int din = 2 * lv->L;
+  const double* mlp = params + or_grid_params(lv);
+  uint32_t idx[8 * OR_MAX_LEVELS];
+  double w[8 * OR_MAX_LEVELS], e[2 * OR_MAX_LEVELS], h1[OR_HIDDEN], y[OR_DOUT], h2[OR_HIDDEN],
+      rgb[3];
+  for (int64_t i = 0; i < n; ++i) {
+    float p[3];
+    for (int k = 0; k < 3; ++k) {
+      float q = (xyz[3 * i + k] + half[k]) / (half[k] + half[k]);
+      p[k] = fminf(fmaxf(q, 0.0f), 1.0f);
+    }
+    or_encode(lv, p, params, idx, w, e);
+    or_mlp_forward(din, mlp, e, h1, y, h2, sigma + i, rgb);
+  }
+}

@@ -1,0 +1,507 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks an oracle function against something other than itself:
+published test vectors, closed forms, invariants, brute force with Python
+integers, a library routine (numpy matmul), or central finite differences.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from tests.tiny import random_params, tiny_scene
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Philox
+def test_philox_known_answers():
+    for line in open(os.path.join(GOLD, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x, 16) for x in line.split()]
+        out = oracle.philox(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+# ---------------------------------------------------------------- levels
+def test_level_tables_match_golden():
+    for line in open(os.path.join(GOLD, "level_tables.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        head, res, ndense, nfloat = line.split(":")
+        _, L, nmin, nmax, lt = head.split()
+        lv = oracle.levels(int(L), int(nmin), int(nmax), int(lt))
+        assert [lv.N[i] for i in range(lv.L)] == [int(x) for x in res.split()]
+        assert sum(1 - lv.hashed[i] for i in range(lv.L)) == int(ndense)
+        assert oracle.grid_params(lv) == int(nfloat)
+        assert lv.N[0] == int(nmin) and lv.N[lv.L - 1] == int(nmax)
+
+
+# ---------------------------------------------------------------- hash / dense index
+def _py_index(N, T, hashed, v):
+    if hashed:
+        h = (v[0] * 1) ^ (v[1] * 2654435761) ^ (v[2] * 805459861)
+        return (h % (1 << 32)) & (T - 1)
+    return v[0] + v[1] * (N + 1) + v[2] * (N + 1) ** 2
+
+
+def test_hash_and_dense_indices_brute_force():
+    rng = np.random.default_rng(1)
+    for (L, nmin, nmax, lt) in [(16, 16, 1024, 19), (8, 16, 128, 12), (16, 16, 1024, 15)]:
+        lv = oracle.levels(L, nmin, nmax, lt)
+        grid = np.zeros(oracle.grid_params(lv))
+        for _ in range(200):
+            p = rng.random(3).astype(np.float32)
+            if rng.random() < 0.2:
+                p[rng.integers(3)] = rng.choice([0.0, 1.0])
+            idx, w, e = oracle.encode(lv, p, grid)
+            for l in range(L):
+                N = lv.N[l]
+                g = p.astype(np.float32) * np.float32(N)
+                cell = np.clip(np.floor(g).astype(np.int64), 0, N - 1)
+                for b in range(8):
+                    v = [int(cell[k]) + ((b >> k) & 1) for k in range(3)]
+                    want = _py_index(N, int(lv.T[l]), lv.hashed[l], v)
+                    assert int(idx[l, b]) == want
+                    assert 0 <= want < lv.T[l]
+
+
+# ---------------------------------------------------------------- trilinear blend
+def test_trilinear_partition_of_unity():
+    rng = np.random.default_rng(2)
+    lv = oracle.levels(16, 16, 1024, 19)
+    grid = np.zeros(oracle.grid_params(lv))
+    for _ in range(100):
+        _, w, _ = oracle.encode(lv, rng.random(3).astype(np.float32), grid)
+        assert np.allclose(w.sum(1), 1.0, atol=1e-12)
+        assert (w >= 0).all()
+
+
+def test_trilinear_reproduces_affine_field_on_dense_levels():
+    lv = oracle.levels(16, 16, 1024, 19)
+    grid = np.zeros(oracle.grid_params(lv))
+    A = np.array([[0.3, -1.2, 0.7], [2.0, 0.1, -0.4]])
+    b0 = np.array([0.25, -0.5])
+    for l in range(lv.L):
+        if lv.hashed[l]:
+            continue
+        N = lv.N[l]
+        n1 = N + 1
+        ids = np.arange(lv.T[l])
+        v = np.stack([ids % n1, (ids // n1) % n1, ids // (n1 * n1)], 1).astype(np.float64)
+        vals = v @ A.T + b0
+        grid[lv.off[l]:lv.off[l] + 2 * lv.T[l]] = vals.reshape(-1)
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        p = rng.random(3).astype(np.float32)
+        _, _, e = oracle.encode(lv, p, grid)
+        for l in range(lv.L):
+            if lv.hashed[l]:
+                continue
+            g = (p * np.float32(lv.N[l])).astype(np.float64)
+            assert np.allclose(e[2 * l:2 * l + 2], A @ g + b0, atol=1e-9)
+
+
+def test_encoding_at_vertex_returns_entry():
+    lv = oracle.levels(8, 16, 128, 12)
+    rng = np.random.default_rng(4)
+    grid = rng.standard_normal(oracle.grid_params(lv))
+    for _ in range(50):
+        k = rng.integers(0, 17, 3)
+        p = (k / 16.0).astype(np.float32)  # exact vertex of level 0 (N = 16)
+        idx, w, e = oracle.encode(lv, p, grid)
+        b = int(np.argmax(w[0]))
+        assert w[0, b] == 1.0
+        at = lv.off[0] + 2 * int(idx[0, b])
+        assert e[0] == grid[at] and e[1] == grid[at + 1]
+
+
+# ---------------------------------------------------------------- ray / slab / samples
+def test_slab_axis_aligned_exact():
+    hit, tn, tf = oracle.slab([0, 0, -2], [0, 0, 1], [0.5, 0.5, 0.5])
+    assert hit and tn == 1.5 and tf == 2.5
+    hit, tn, tf = oracle.slab([0.1, 0.2, 0.0], [1, 0, 0], [0.5, 0.5, 0.5])
+    assert hit and tn == 0.0 and tf == np.float32(0.5) - np.float32(0.1)
+    hit, _, _ = oracle.slab([0, 2, 0], [1, 0, 0], [0.5, 0.5, 0.5])  # parallel, outside
+    assert not hit
+    hit, _, _ = oracle.slab([0, 0, 2], [0, 0, 1], [0.5, 0.5, 0.5])  # box behind the camera
+    assert not hit
+
+
+def test_slab_entry_exit_on_box_surface_and_misses():
+    rng = np.random.default_rng(5)
+    half = np.array([0.4, 0.25, 0.6], np.float32)
+    n_hit = 0
+    for _ in range(400):
+        o = rng.uniform(-2, 2, 3).astype(np.float32)
+        d = rng.standard_normal(3)
+        if rng.random() < 0.6:  # aim most rays at a point of the box
+            d = rng.uniform(-1, 1, 3) * half - o
+        d = (d / np.linalg.norm(d)).astype(np.float32)
+        hit, tn, tf = oracle.slab(o, d, half)
+        ts = np.linspace(0, 6, 6001)
+        pts = o.astype(np.float64) + ts[:, None] * d.astype(np.float64)
+        inside = (np.abs(pts) < half.astype(np.float64) - 1e-6).all(1)
+        if not hit:
+            assert not inside.any()
+            continue
+        n_hit += 1
+        for t in (tf,) + ((tn,) if tn > 0 else ()):
+            x = o.astype(np.float64) + t * d.astype(np.float64)
+            assert abs(np.max(np.abs(x) / half) - 1.0) < 1e-5
+        if inside.any():
+            assert ts[inside].min() >= tn - 2e-3 and ts[inside].max() <= tf + 2e-3
+    assert n_hit > 50
+
+
+def test_uniform_samples_cover_interval():
+    o = np.array([0.1, -1.5, 0.2], np.float32)
+    d = np.array([0.0, 1.0, 0.0], np.float32)
+    half = np.array([0.5, 0.5, 0.5], np.float32)
+    hit, tn, tf = oracle.slab(o, d, half)
+    assert hit
+    for N in (32, 64, 128):
+        delta, dist, pos = oracle.sample_positions(o, d, half, tn, tf, N)
+        assert abs(N * delta - (tf - tn)) < 1e-6
+        assert np.allclose(np.diff(dist), delta, atol=1e-6)
+        assert abs(dist[0] - (tn + 0.5 * delta)) < 1e-6
+        # along the y axis the normalised coordinate is (y + a) / 2a
+        y = o[1] + dist.astype(np.float64) * d[1]
+        assert np.allclose(pos[:, 1], (y + 0.5) / 1.0, atol=1e-6)
+        assert np.allclose(pos[:, 0], 0.6) and np.allclose(pos[:, 2], 0.7)
+        assert (pos >= 0).all() and (pos <= 1).all()
+
+
+def test_pixel_ray_passes_through_projected_world_point():
+    rng = np.random.default_rng(6)
+    for _ in range(50):
+        eye = rng.uniform(-3, 3, 3)
+        T = scenes.look_at(eye, rng.uniform(-0.3, 0.3, 3)).astype(np.float64)
+        fx, fy, cx, cy = 300.0, 280.0, 160.0, 120.0
+        u, v = int(rng.integers(0, 320)), int(rng.integers(0, 240))
+        s = rng.uniform(1, 4)
+        dcam = np.array([(u + 0.5 - cx) / fx, (v + 0.5 - cy) / fy, 1.0])
+        X = T[:, :3] @ (s * dcam) + T[:, 3]
+        t = rng.uniform(-1, 1, 3).astype(np.float32)
+        yaw = np.float32(rng.uniform(-3, 3))
+        M, c = oracle.object_frame(T.astype(np.float32), t, float(yaw))
+        o, d = oracle.pixel_ray(M, c, fx, fy, cx, cy, u, v)
+        cy_, sy_ = math.cos(float(yaw)), math.sin(float(yaw))
+        R = np.array([[cy_, -sy_, 0], [sy_, cy_, 0], [0, 0, 1]])
+        Xo = R.T @ (X - t.astype(np.float64))
+        rel = Xo - o.astype(np.float64)
+        along = rel @ d.astype(np.float64)
+        assert along > 0
+        assert np.linalg.norm(rel - along * d.astype(np.float64)) < 2e-5 * max(1.0, along)
+        assert abs(np.linalg.norm(d.astype(np.float64)) - 1.0) < 1e-6
+
+
+# ---------------------------------------------------------------- MLP
+def test_mlp_forward_matches_numpy_matmul():
+    rng = np.random.default_rng(7)
+    for din in (4, 16, 32):
+        p = random_params(0, din, seed=din)
+        W1 = p[:64 * din].reshape(64, din)
+        W2 = p[64 * din:64 * din + 1024].reshape(16, 64)
+        W3 = p[64 * din + 1024:64 * din + 1984].reshape(64, 15)
+        W4 = p[64 * din + 1984:].reshape(3, 64)
+        for _ in range(20):
+            e = rng.standard_normal(din)
+            out = oracle.mlp_forward(din, p, e)
+            h1 = np.maximum(W1 @ e, 0)
+            y = W2 @ h1
+            h2 = np.maximum(W3 @ y[1:], 0)
+            rgb = 1 / (1 + np.exp(-(W4 @ h2)))
+            assert np.allclose(out["y"], y, rtol=1e-12, atol=1e-14)
+            assert np.allclose(out["rgb"], rgb, rtol=1e-12)
+            assert math.isclose(out["sigma"], math.exp(min(y[0], 15.0)), rel_tol=1e-12)
+
+
+def test_density_activation_is_clamped():
+    p = random_params(0, 4, seed=1)
+    p[256:256 + 64] = 0.0
+    p[256] = 100.0  # W2[0][0] large -> y0 huge
+    e = np.array([1.0, 1.0, 1.0, 1.0])
+    p[:256] = 1.0
+    out = oracle.mlp_forward(4, p, e)
+    assert out["y"][0] > 15
+    assert out["sigma"] == math.exp(15.0)
+
+
+# ---------------------------------------------------------------- compositing
+@pytest.mark.parametrize("N", [32, 64, 128])
+def test_composite_constant_density_slab_closed_form(N):
+    sigma, tn, tf = 3.7, 1.25, 2.0
+    delta = (tf - tn) / N
+    dist = tn + (np.arange(N) + 0.5) * delta
+    col = np.array([0.2, 0.5, 0.9])
+    Cout, D, Tend, w = oracle.composite(np.full(N, sigma), np.tile(col, (N, 1)), dist, delta)
+    d = tf - tn
+    assert math.isclose(Tend, math.exp(-sigma * d), rel_tol=1e-12)
+    assert np.allclose(Cout, col * (1 - math.exp(-sigma * d)), rtol=1e-12)
+    assert math.isclose(w.sum(), 1 - Tend, rel_tol=1e-12)
+    q = math.exp(-sigma * delta)
+    s_iq = q * (1 - N * q ** (N - 1) + (N - 1) * q ** N) / (1 - q) ** 2
+    D_closed = (1 - q ** N) * (tn + 0.5 * delta) + delta * (1 - q) * s_iq
+    assert math.isclose(D, D_closed, rel_tol=1e-11)
+
+
+def test_composite_weights_telescope_for_random_density():
+    rng = np.random.default_rng(8)
+    N = 64
+    sig = rng.exponential(5.0, N)
+    _, _, Tend, w = oracle.composite(sig, rng.random((N, 3)), np.arange(N) * 0.01, 0.01)
+    assert math.isclose(w.sum(), 1 - Tend, rel_tol=1e-12, abs_tol=1e-15)
+
+
+def test_composite_background_adds_residual_random_colour():
+    N = 32
+    cr = (0.1, 0.6, 0.3)
+    Cout, _, Tend, _ = oracle.composite(np.zeros(N), np.full((N, 3), 0.5), np.arange(N) * 0.1, 0.1,
+                                        background=True, crand=cr)
+    assert Tend == 1.0 and np.allclose(Cout, cr)
+    sig = np.full(N, 2.0)
+    Cb, _, Tb, _ = oracle.composite(sig, np.full((N, 3), 0.5), np.arange(N) * 0.1, 0.1,
+                                    background=True, crand=cr)
+    C0, _, _, _ = oracle.composite(sig, np.full((N, 3), 0.5), np.arange(N) * 0.1, 0.1)
+    assert np.allclose(Cb - C0, Tb * np.array(cr), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- candidates / draws
+def test_candidate_rect_margin_and_clamp():
+    m = np.zeros((40, 50), np.int32)
+    m[10:20, 5:25] = 4   # 20 wide, 10 high
+    assert oracle.candidate_rect(m, 4, 10) == (3, 9, 24, 12)
+    m2 = np.zeros((40, 50), np.int32)
+    m2[0:5, 45:50] = 2
+    assert oracle.candidate_rect(m2, 2, 10) == (44, 0, 6, 6)
+    assert oracle.candidate_rect(m2, 3, 10) is None
+
+
+def _tiny_ctx(N=8, L=2, nmin=16, nmax=32, log2T=8, n_views=3, lambda_density=0.01):
+    frames, box = tiny_scene(n_views=n_views)
+    cfg = oracle.make_config(L=L, nmin=nmin, nmax=nmax, log2T=log2T, N=N,
+                             lambda_density=lambda_density)
+    ctx = oracle.OracleContext(cfg, alpha_deg=25.0, nthreads=1)
+    oid = ctx.add_object(box["instance"], box["t"], box["yaw"], box["half"])
+    for cam, rgb, mask, depth in frames:
+        ctx.add_keyframe(cam, rgb, mask, depth)
+    return ctx, oid, frames
+
+
+def test_draws_stay_in_candidate_rects_and_classes_follow_mask():
+    ctx, oid, frames = _tiny_ctx()
+    o = ctx.objects[oid]
+    B = 3000
+    p = random_params(oracle.grid_params(o.lv), 4)
+    _, _, rays = ctx.loss_and_grad(oid, step=0, B=B, rays=True, params=p, want_grad=False)
+    counts = np.zeros(len(o.kfs))
+    classes = set()
+    for r in rays:
+        kf, rect = o.kfs[r.kf]
+        x0, y0, w, h = rect
+        assert x0 <= r.u < x0 + w and y0 <= r.v < y0 + h
+        m = kf.mask[r.v, r.u]
+        assert r.cls == (1 if m == 1 else (2 if m == 0 else 0))
+        classes.add(r.cls)
+        assert np.allclose(np.array(r.C), kf.rgb[r.v, r.u] / np.float32(255.0))
+        for c in r.Crand:
+            assert 0.0 <= c < 1.0 and float(c) * 2 ** 24 == int(float(c) * 2 ** 24)
+        counts[r.kf] += 1
+    assert classes == {0, 1, 2}
+    areas = np.array([rect[2] * rect[3] for _, rect in o.kfs], np.float64)
+    expect = B * areas / areas.sum()
+    chi2 = float(np.sum((counts - expect) ** 2 / expect))
+    assert chi2 < 20.0  # 2 degrees of freedom
+    # different steps draw different rays, equal steps the same
+    _, _, rays2 = ctx.loss_and_grad(oid, step=1, B=B, rays=True, params=p, want_grad=False)
+    _, _, rays0 = ctx.loss_and_grad(oid, step=0, B=B, rays=True, params=p, want_grad=False)
+    assert [(r.kf, r.u, r.v) for r in rays0] == [(r.kf, r.u, r.v) for r in rays]
+    assert [(r.kf, r.u, r.v) for r in rays2] != [(r.kf, r.u, r.v) for r in rays]
+
+
+def test_depth_target_is_ray_distance():
+    ctx, oid, frames = _tiny_ctx()
+    o = ctx.objects[oid]
+    p = random_params(oracle.grid_params(o.lv), 4)
+    _, _, rays = ctx.loss_and_grad(oid, step=0, B=2000, rays=True, params=p, want_grad=False)
+    n = 0
+    for r in rays:
+        if not r.has_depth:
+            continue
+        kf, _ = o.kfs[r.kf]
+        z = float(kf.depth[r.v, r.u])
+        dcam = np.array([(r.u + 0.5 - kf.cx) / kf.fx, (r.v + 0.5 - kf.cy) / kf.fy, 1.0])
+        X = z * dcam  # camera-frame point at camera depth z on this pixel's ray
+        assert math.isclose(r.D, float(np.linalg.norm(X)), rel_tol=1e-6)
+        n += 1
+    assert n > 10
+
+
+def test_keyframe_rule_alpha_threshold():
+    cfg = oracle.make_config(L=2, nmin=16, nmax=32, log2T=8, N=8)
+    ctx = oracle.OracleContext(cfg, alpha_deg=25.0, nthreads=1)
+    ctx.add_object(1, np.zeros(3, np.float32), 0.0, np.full(3, 0.5, np.float32))
+    mask = np.zeros((8, 8), np.int32)
+    mask[3:5, 3:5] = 1
+    rgb = np.zeros((8, 8, 3), np.uint8)
+
+    def cam_at(deg):
+        a = math.radians(deg)
+        return scenes.camera(scenes.look_at((2 * math.cos(a), 2 * math.sin(a), 0.5), (0, 0, 0)), 8, 8, 8.0)
+
+    assert ctx.add_keyframe(cam_at(0), rgb, mask) == 1     # first is always accepted
+    assert ctx.add_keyframe(cam_at(20), rgb, mask) == 0    # 20 deg < 25 deg
+    assert ctx.add_keyframe(cam_at(30), rgb, mask) == 1    # 30 deg > 25 deg
+    assert ctx.add_keyframe(cam_at(50), rgb, mask) == 0    # 20 deg from the last accepted
+    assert ctx.add_keyframe(cam_at(56), rgb, mask) == 1
+    empty = np.zeros((8, 8), np.int32)
+    assert ctx.add_keyframe(cam_at(150), rgb, empty) == 0  # object not observed
+    assert len(ctx.objects[0].kfs) == 3
+
+
+# ---------------------------------------------------------------- gradients (FD)
+@pytest.mark.parametrize("lambda_density", [0.01, 0.0])
+def test_gradient_matches_central_finite_differences(lambda_density):
+    """Every parameter of a 2-level 2^8 grid + MLP (4 -> 64 -> 16, 15 -> 64 -> 3)."""
+    ctx, oid, _ = _tiny_ctx(N=8, lambda_density=lambda_density)
+    o = ctx.objects[oid]
+    P = o.params.size
+    p = random_params(oracle.grid_params(o.lv), 4, seed=11, grid_scale=1.0)
+    B = 24
+    loss, g, rays = ctx.loss_and_grad(oid, 0, B, rays=True, params=p)
+    assert {r.cls for r in rays if r.hit} >= {1, 2}
+    fd = np.zeros(P)
+    for i in range(P):
+        h = 1e-6 * max(1.0, abs(p[i]))
+        pp = p.copy()
+        pp[i] += h
+        lp, _, _ = ctx.loss_and_grad(oid, 0, B, params=pp, want_grad=False)
+        pp[i] -= 2 * h
+        lm, _, _ = ctx.loss_and_grad(oid, 0, B, params=pp, want_grad=False)
+        fd[i] = (lp - lm) / (2 * h)
+    scale = np.abs(g).max()
+    assert scale > 0
+    err = np.abs(fd - g)
+    assert np.all(err <= 1e-6 * scale + 1e-5 * np.abs(g)), (np.argmax(err), err.max(), scale)
+    assert np.count_nonzero(g[:oracle.grid_params(o.lv)]) > 100
+
+
+def test_gradient_dot_product_directional():
+    """<grad, v> equals the directional derivative along a random v."""
+    ctx, oid, _ = _tiny_ctx(N=16)
+    o = ctx.objects[oid]
+    p = random_params(oracle.grid_params(o.lv), 4, seed=12, grid_scale=1.0)
+    _, g, _ = ctx.loss_and_grad(oid, 3, 48, params=p)
+    rng = np.random.default_rng(13)
+    for _ in range(3):
+        v = rng.standard_normal(p.size)
+        v /= np.linalg.norm(v)
+        h = 1e-6
+        lp, _, _ = ctx.loss_and_grad(oid, 3, 48, params=p + h * v, want_grad=False)
+        lm, _, _ = ctx.loss_and_grad(oid, 3, 48, params=p - h * v, want_grad=False)
+        assert math.isclose((lp - lm) / (2 * h), float(g @ v), rel_tol=1e-6)
+
+
+# ---------------------------------------------------------------- Adam
+def test_adam_first_step_and_recurrence():
+    lr, b1, b2, eps = 1e-2, 0.9, 0.99, 1e-15
+    g0 = np.array([0.5, -2e-3, 0.0, 7.0])
+    p = np.array([1.0, 2.0, 3.0, 4.0])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    g = g0.copy()
+    oracle.adam(p, g, m, v, 1, lr, b1, b2, eps)
+    step = np.where(g0 != 0, lr * np.abs(g0) / (np.abs(g0) + eps), 0.0) * np.sign(g0)
+    assert np.allclose(p, np.array([1.0, 2.0, 3.0, 4.0]) - step, rtol=0, atol=1e-15)
+    assert (g == 0).all()
+    # hand-evaluated recurrence for two more steps on a scalar
+    gs = [0.5, -0.25, 0.0]
+    P, Mm, Vv = 1.0, 0.0, 0.0
+    pa, ma, va = np.array([1.0]), np.zeros(1), np.zeros(1)
+    for k, gk in enumerate(gs, start=1):
+        Mm = b1 * Mm + (1 - b1) * gk
+        Vv = b2 * Vv + (1 - b2) * gk * gk
+        P -= lr * (Mm / (1 - b1 ** k)) / (math.sqrt(Vv / (1 - b2 ** k)) + eps)
+        oracle.adam(pa, np.array([gk]), ma, va, k, lr, b1, b2, eps)
+    assert math.isclose(pa[0], P, rel_tol=1e-14)
+    # dense semantics: a zero gradient at step 3 still moves the parameter
+    assert pa[0] != 1.0 - 0.0
+
+
+# ---------------------------------------------------------------- end to end forward
+def test_render_of_constant_field_is_slab_closed_form():
+    """Grid = 0 gives e = 0, hence h1 = 0, y = 0: sigma = 1 and colour = 0.5
+    everywhere; every pixel must render 0.5 (1 - exp(-(t_f - t_n)))."""
+    cfg = oracle.make_config(L=8, nmin=16, nmax=128, log2T=12, N=64)
+    ctx = oracle.OracleContext(cfg, nthreads=2)
+    half = np.array([0.5, 0.4, 0.3], np.float32)
+    oid = ctx.add_object(1, np.array([0.1, 0.0, 0.0], np.float32), 0.4, half)
+    o = ctx.objects[oid]
+    o.params[:] = random_params(oracle.grid_params(o.lv), 16, seed=3)
+    o.params[:oracle.grid_params(o.lv)] = 0.0
+    cam = scenes.camera(scenes.look_at((1.5, 0.8, 0.6), (0, 0, 0)), 24, 20, 20.0)
+    rgb, depth, opac = ctx.render(oid, cam, 24, 20)
+    M, c = oracle.object_frame(cam["T_wc"], o.t, o.yaw)
+    n_hit = 0
+    for v in range(20):
+        for u in range(24):
+            ro, rd = oracle.pixel_ray(M, c, cam["fx"], cam["fy"], cam["cx"], cam["cy"], u, v)
+            hit, tn, tf = oracle.slab(ro, rd, half)
+            want = 1 - math.exp(-(tf - tn)) if hit else 0.0
+            assert math.isclose(opac[v, u], want, rel_tol=1e-9, abs_tol=1e-12)
+            assert np.allclose(rgb[v, u], 0.5 * want, rtol=1e-9, atol=1e-12)
+            n_hit += hit
+    assert n_hit > 100
+
+
+def test_query_density_matches_encode_plus_mlp():
+    cfg = oracle.make_config(L=8, nmin=16, nmax=128, log2T=12, N=32)
+    ctx = oracle.OracleContext(cfg, nthreads=1)
+    half = np.array([0.5, 0.5, 0.5], np.float32)
+    oid = ctx.add_object(1, np.zeros(3, np.float32), 0.0, half)
+    o = ctx.objects[oid]
+    o.params[:] = random_params(oracle.grid_params(o.lv), 16, seed=5)
+    rng = np.random.default_rng(5)
+    xyz = rng.uniform(-0.5, 0.5, (20, 3)).astype(np.float32)
+    sig = ctx.query_density(oid, xyz)
+    for i in range(20):
+        p = ((xyz[i] + half) / (half + half)).astype(np.float32)
+        _, _, e = oracle.encode(o.lv, p, o.params)
+        out = oracle.mlp_forward(16, o.params[oracle.grid_params(o.lv):], e)
+        assert sig[i] == out["sigma"]
+
+
+# ---------------------------------------------------------------- training
+def test_config1_training_raises_psnr():
+    """Plain method, one object, 50 Adam steps at lr 1e-2: PSNR on the object
+    pixels of the training views must rise."""
+    wl = scenes.config1()
+    cfg = oracle.make_config(L=8, nmin=16, nmax=128, log2T=12, N=32)
+    ctx = oracle.OracleContext(cfg)
+    ob = wl.objects[0]
+    oid = ctx.add_object(ob.instance, ob.t, ob.yaw, ob.half)
+    o = ctx.objects[oid]
+    p = random_params(oracle.grid_params(o.lv), 16, seed=0)
+    p[:oracle.grid_params(o.lv)] *= 2e-4  # U(-1e-4, 1e-4)
+    o.params[:] = p
+    for cam, rgb, mask, depth in wl.frames:
+        ctx.add_keyframe(cam, rgb, mask, depth)
+    assert len(o.kfs) == 8
+
+    def mean_psnr():
+        vals = []
+        for cam, rgb, mask, _ in wl.frames:
+            pred, _, _ = ctx.render(oid, cam, cam["W"], cam["H"])
+            vals.append(scenes.psnr(pred, rgb / 255.0, mask == ob.instance))
+        return float(np.mean(vals))
+
+    before = mean_psnr()
+    losses = ctx.train(oid, 50, 256)
+    after = mean_psnr()
+    assert after > before + 3.0, (before, after)
+    assert np.mean(losses[-10:]) < np.mean(losses[:10])
