@@ -1,0 +1,227 @@
+"""Throughput benchmark of the per-object radiance-field training step.
+
+Prints one JSON line: trained rays/s (draw, forward, loss, backward, dense
+Adam) summed over all objects of the workload, measured on the batched path
+(all objects per launch, one hipGraph per step), with the roofline of the
+dominant kernel, the plain path (FP32, one launch per object per phase, no
+graph) beside it, PSNR of both after training, and the CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config4]
+
+Inputs are seeded synthetic scenes (the paper's datasets are not available).
+Only one GPU is used; --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "trained rays/s (fwd+bwd+Adam) all objects, batched BF16 vs plain FP32 @ equal PSNR"
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
+BF16_PEAK_TFLOPS = 2500.0  # dense
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    import scenes
+    if name == "config2":
+        return scenes.config2()
+    if name in ("config3", "config4"):
+        return scenes.config3(n_obj=24)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def make_ctx(wl, precision, batch_mode, use_graph, autotune=1, profile=0):
+    import paper_2304_05735_amd as pk
+    N = 64
+    cfg = pk.default_config(samples_per_ray=N, precision=precision, batch_mode=batch_mode,
+                            use_graph=use_graph, autotune=autotune, profile_phases=profile)
+    ctx = pk.Context(cfg)
+    ids = []
+    for ob in wl.objects:
+        ids.append(ctx.add_object(ob.instance, ob.t, ob.yaw, ob.half, ob.log2T))
+    for cam, rgb, mask, depth in wl.frames:
+        ctx.add_keyframe(cam, rgb, mask, depth)
+    keep, rays = [], []
+    for i, ob in zip(ids, wl.objects):
+        if ctx.object_info(i).n_keyframes > 0:
+            keep.append(i)
+            rays.append(wl.rays[ob.instance])
+    return ctx, keep, rays
+
+
+def timed_steps(ctx, ids, rays, warmup, steps):
+    if warmup:
+        ctx.train(warmup, ids, rays, stats=False)
+    ctx.sync()
+    t0 = time.perf_counter()
+    ctx.train(steps, ids, rays, stats=False)
+    ctx.sync()
+    return time.perf_counter() - t0
+
+
+def mean_psnr(ctx, wl, ids):
+    import scenes
+    vals = []
+    for v in wl.eval_views:
+        cam, rgb, mask, _ = wl.frames[v]
+        for i, ob in zip(ids, wl.objects):
+            m = mask == ob.instance
+            if m.sum() < 50:
+                continue
+            pred, _, _ = ctx.render(i, cam)
+            vals.append(scenes.psnr(pred, rgb / 255.0, m))
+    return float(sum(vals) / max(len(vals), 1))
+
+
+def algorithmic_bytes(ctx, ids, rays, phase):
+    """Algorithmic bytes of one launch of a kernel over the whole step."""
+    L, N = ctx.cfg.n_levels, ctx.cfg.samples_per_ray
+    S = sum(rays) * N
+    if phase == "encode_fwd":   # 8 corners x 8 B gathered + 8 B written, per sample and level
+        return S * L * (64 + 8)
+    if phase == "encode_bwd":   # 8 B adjoint read + 8 corners x 8 B scattered
+        return S * L * (8 + 64)
+    if phase == "adam":         # p, g, m, v read; p, m, v, g written
+        return sum(32 * (ctx.object_info(i).n_grid_params + ctx.object_info(i).n_mlp_params)
+                   for i in ids)
+    if phase == "field":        # encodings read twice (forward, recompute), adjoints written
+        return S * L * 8 * 3
+    return 0
+
+
+def field_flops(ctx, rays):
+    """MLP flops of the field kernel: forward 2*4224, recompute 2*4224,
+    adjoint 2*2*4224 (input and weight gradients) per sample."""
+    S = sum(rays) * ctx.cfg.samples_per_ray
+    return S * 4224 * 2 * 4
+
+
+def cpu_baseline(wl, seconds_target=15.0):
+    """The oracle as it stands on the host cores, on a bounded sample: as many
+    full 4096-ray steps of the first object as fit in ~seconds_target."""
+    import oracle
+    ob = wl.objects[0]
+    cfg = oracle.make_config(N=64, log2T=ob.log2T)
+    o = oracle.OracleContext(cfg)
+    oid = o.add_object(ob.instance, ob.t, ob.yaw, ob.half, ob.log2T)
+    for cam, rgb, mask, depth in wl.frames:
+        o.add_keyframe(cam, rgb, mask, depth)
+    B = wl.rays[ob.instance]
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < seconds_target and steps < 50:
+        o.train(oid, 1, B)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return dict(value=steps * B / dt, unit="rays/s", cores=o.nthreads, kind="oracle",
+                sample=f"{steps} full training steps x {B} rays x 64 samples of object "
+                       f"instance {ob.instance} (FP64, {o.nthreads} threads)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--psnr-steps", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-psnr", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the path is the "
+              "single-GPU share of the workload; sharding across GPUs is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2304_05735_amd as pk
+    assert torch.cuda.is_available(), "no GPU visible"
+    log("workload", args.workload)
+    t = time.perf_counter()
+    wl = build_workload(args.workload)
+    log(f"scene ready in {time.perf_counter() - t:.1f}s: {len(wl.objects)} objects, "
+        f"{len(wl.frames)} frames")
+    prec = pk.PREC_BF16 if args.workload == "config4" else pk.PREC_FP32
+    # ---- headline: batched path, one hipGraph per step
+    ctx, ids, rays = make_ctx(wl, prec, pk.BATCH_ALL, 1)
+    rays_per_step = sum(rays)
+    log(f"{len(ids)} trained objects, {rays_per_step} rays/step")
+    dt = timed_steps(ctx, ids, rays, args.warmup, args.steps)
+    value = rays_per_step * args.steps / dt
+    ms_step = dt / args.steps * 1e3
+    log(f"batched: {ms_step:.4f} ms/step, {value / 1e6:.3f} M rays/s")
+    # ---- per-kernel durations (HIP events on the context stream, same kernels)
+    pctx, _, _ = make_ctx(wl, prec, pk.BATCH_ALL, 0, profile=1)
+    pctx.train(args.warmup, ids, rays, stats=False)
+    pctx.train(args.steps, ids, rays, stats=False)
+    phases, nph = pctx.phase_times()
+    log("phase ms:", json.dumps({k: round(v, 5) for k, v in phases.items()}))
+    dominant = max(phases, key=phases.get)
+    if dominant in ("encode_fwd", "encode_bwd", "adam") or True:
+        byt = algorithmic_bytes(pctx, ids, rays, dominant)
+    achieved = byt / (phases[dominant] * 1e-3) / 1e9 if phases[dominant] > 0 else 0.0
+    roofline = dict(bound="hbm", kernel=dominant, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    avg_ms=round(phases[dominant], 5), algorithmic_bytes=int(byt),
+                    phase_ms={k: round(v, 5) for k, v in phases.items()})
+    fl = field_flops(pctx, rays)
+    peak_f = BF16_PEAK_TFLOPS if prec == pk.PREC_BF16 else FP32_MFMA_PEAK_TFLOPS
+    mlp = dict(kernel="field", tflops=round(fl / (phases["field"] * 1e-3) / 1e12, 2),
+               peak=peak_f, frac=round(fl / (phases["field"] * 1e-3) / 1e12 / peak_f, 4))
+    del pctx
+    # ---- plain path: FP32, one launch per object per phase, no graph
+    plain_ctx, _, _ = make_ctx(wl, pk.PREC_FP32, pk.BATCH_PER_OBJECT, 0)
+    dtp = timed_steps(plain_ctx, ids, rays, args.warmup, args.steps)
+    plain = rays_per_step * args.steps / dtp
+    log(f"plain FP32 per-object: {dtp / args.steps * 1e3:.4f} ms/step, {plain / 1e6:.3f} M rays/s")
+    del plain_ctx
+    quality = None
+    if not args.no_psnr:
+        qa, _, _ = make_ctx(wl, prec, pk.BATCH_ALL, 1)
+        qa.train(args.psnr_steps, ids, rays, stats=False)
+        qb, _, _ = make_ctx(wl, pk.PREC_FP32, pk.BATCH_PER_OBJECT, 0)
+        qb.train(args.psnr_steps, ids, rays, stats=False)
+        pa, pb = mean_psnr(qa, wl, ids), mean_psnr(qb, wl, ids)
+        quality = dict(steps=args.psnr_steps, psnr_batched=round(pa, 3), psnr_plain_fp32=round(pb, 3),
+                       equal_psnr=abs(pa - pb) <= 0.1)
+        log("psnr", quality)
+        del qa, qb
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(wl)
+        log("cpu", cpu)
+    dtype = "bf16-mfma/fp32" if prec == pk.PREC_BF16 else "fp32"
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "objects": len(ids), "rays_per_step": rays_per_step,
+                   "samples_per_ray": 64, "levels": 16, "batched": True, "graph": True},
+        "roofline": roofline,
+        "mlp_mfma": mlp,
+        "plain_fp32": {"value": round(plain, 1), "unit": "rays/s",
+                       "speedup": round(value / plain, 3)},
+        "quality": quality,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

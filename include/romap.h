@@ -1,0 +1,262 @@
+/*
+ * romap.h -- C ABI of the MI355X (gfx950) training path for RO-MAP's
+ * per-object radiance fields (Han, Yang et al., "RO-MAP: Real-Time
+ * Multi-Object Mapping with Neural Radiance Fields", arXiv 2304.05735).
+ *
+ * The verbs follow the paper's statement of the problem:
+ *  - a new object instance gets its own model: a multiresolution hash
+ *    encoding plus a small MLP (Sec. V), registered with its cuboid box
+ *    (centre t, yaw theta, half size a: Sec. IV-B, Eq. 1 and Eq. 4);
+ *  - posed keyframes with instance masks (and sparse depth) arrive over time
+ *    and join an object's training set by the view-angle rule of Eq. 5
+ *    (Sec. V-A "Data");
+ *  - objects train for a number of iterations on new observations and stop
+ *    when idle (Sec. V-A "Parallel Training", Sec. VI implementation details);
+ *  - each iteration draws rays inside the object's detection box, samples
+ *    uniformly inside its 3D box, volume-renders (Eq. 6), applies the loss of
+ *    Eq. 7-11, backpropagates and updates the parameters (Sec. V-B, Table 3);
+ *  - density is queried for meshing, and views are rendered for evaluation.
+ *
+ * Conventions
+ *  - Every call returns romap_status: 0 = ROMAP_OK, negative = error.
+ *    Nothing aborts or throws across the ABI.  romap_last_error() gives a
+ *    message for the last failing call on a context.
+ *  - Arguments are validated before any side effect: a failing call leaves
+ *    the context unchanged (except where stated for ROMAP_E_HIP).
+ *  - Host buffers are owned by the caller and copied before the call returns.
+ *    Pointers documented as device pointers must be device memory of the
+ *    current HIP device; work on them is ordered on the context's stream and
+ *    is complete once that stream has synchronised.
+ *  - One thread at a time per context; several contexts may coexist.
+ *  - Cameras are pinhole, x right, y down, z forward, pixel centres at +0.5;
+ *    T_wc is the row-major 3x4 camera-to-world pose.  World +z is up; an
+ *    object's yaw turns about +z (roll = pitch = 0, Sec. IV-B).
+ *  - Parameter order of an object (get/set_params): the grid level-major,
+ *    [level][entry][feature] with F = 2 features and level l holding
+ *    T_l = min(T, (N_l + 1)^3) entries; then the MLP weights W1 (64 x 2L),
+ *    W2 (16 x 64), W3 (64 x 15), W4 (3 x 64), row-major, no biases.
+ */
+#ifndef ROMAP_H
+#define ROMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t romap_status;
+#define ROMAP_OK 0
+#define ROMAP_E_INVALID_ARG (-1)
+#define ROMAP_E_OUT_OF_MEMORY (-2)
+#define ROMAP_E_NOT_FOUND (-3)
+#define ROMAP_E_HIP (-4)
+#define ROMAP_E_NUMERIC (-5) /* NaN/Inf in an object's loss */
+#define ROMAP_E_STATE (-6)   /* e.g. the object has no keyframe yet */
+
+typedef struct romap_ctx romap_ctx;
+
+#define ROMAP_PREC_FP32 0 /* MLP contractions on FP32 MFMA */
+#define ROMAP_PREC_BF16 1 /* MLP contractions on BF16 MFMA, FP32 accumulate */
+
+#define ROMAP_BATCH_ALL 0        /* every object of a step in one launch per phase */
+#define ROMAP_BATCH_PER_OBJECT 1 /* one launch per object per phase */
+
+/* Model and training hyperparameters.  Defaults: romap_default_config(). */
+typedef struct {
+  int32_t n_levels;        /* L, 1..16 */
+  int32_t base_res;        /* N_min */
+  int32_t max_res;         /* N_max */
+  int32_t log2_table_size; /* default log2 T for objects registered with 0 */
+  int32_t samples_per_ray; /* N: 32, 64 or 128 (uniform samples, Sec. V-B) */
+  int32_t rays_per_step;   /* default rays per object per step (4096 in Sec. VI) */
+  float lr, beta1, beta2, eps;             /* Adam */
+  float lambda_depth, lambda_density;      /* lambda_1, lambda_2 of Eq. 11 */
+  float alpha_deg;                         /* keyframe rule threshold of Eq. 5 */
+  int32_t bbox_margin_pct;                 /* detection-box margin, % per side */
+  int32_t precision;                       /* ROMAP_PREC_* */
+  int32_t batch_mode;                      /* ROMAP_BATCH_* */
+  int32_t use_graph;                       /* replay each step as one hipGraph */
+  int32_t autotune;                        /* pick tile shapes by timing */
+  int32_t profile_phases;                  /* time each kernel of a step with HIP
+                                              events (launches without a graph and
+                                              waits after every step) */
+  uint64_t seed;
+} romap_config;
+
+typedef struct {
+  float t[3];    /* centre in the world (Eq. 1) */
+  float yaw;     /* radians about world +z */
+  float half[3]; /* half extents a (Eq. 4), > 0 */
+} romap_box;
+
+typedef struct {
+  float T_wc[12]; /* row-major 3x4 camera-to-world */
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} romap_camera;
+
+typedef struct {
+  float loss_mean;        /* mean over objects and steps of the per-object loss */
+  int64_t rays_trained;   /* rays drawn in the call, all objects */
+  float seconds;          /* GPU time of the call */
+  int32_t n_objects_nan;  /* objects whose loss was not finite */
+} romap_train_stats;
+
+typedef struct {
+  int32_t instance_id;
+  int32_t log2_table_size;
+  int64_t n_grid_params;
+  int64_t n_mlp_params;
+  int32_t n_keyframes;
+  int32_t step;          /* Adam steps taken */
+  int64_t n_candidates;  /* candidate pixels over all its keyframes */
+  int32_t active;
+  int32_t level_res[16];
+  int32_t level_hashed[16];
+} romap_object_info;
+
+#define ROMAP_PARAMS 0 /* grid then MLP */
+#define ROMAP_ADAM_M 1
+#define ROMAP_ADAM_V 2
+#define ROMAP_GRAD 3   /* gradient buffer (left in place by romap_loss_and_grad) */
+
+/* Fills *cfg with the defaults: L 16, N_min 16, N_max 1024, T 2^19, N 64,
+ * 4096 rays, Adam lr 1e-2 b1 0.9 b2 0.99 eps 1e-15, lambda_1 0.5,
+ * lambda_2 0.01 (Sec. VI), alpha 25 deg (Sec. VI), margin 10 %, FP32,
+ * batched, graph on, autotune on, seed 0.  Always succeeds for non-NULL cfg. */
+romap_status romap_default_config(romap_config* cfg);
+
+/* Creates a context on the current HIP device.  hip_stream: a hipStream_t to
+ * order all work on, or NULL for a stream owned by the context.  On success
+ * *out owns every device allocation the context makes. */
+romap_status romap_create(const romap_config* cfg, void* hip_stream, romap_ctx** out);
+romap_status romap_destroy(romap_ctx* ctx);
+/* Message of the last failing call on ctx (or of the last failing create if
+ * ctx is NULL).  Owned by the library, valid until the next call. */
+const char* romap_last_error(const romap_ctx* ctx);
+
+/* Registers an object (Sec. V: a new model when a new instance is detected)
+ * with its box and hash table size log2 T in [8, 24] (0 = config default).
+ * Parameters start as grid U(-1e-4, 1e-4), MLP Glorot-uniform, drawn from
+ * Philox keyed on (seed, object id).  *object_id receives the new id
+ * (0, 1, ... in registration order).  Keyframes added earlier are not used. */
+romap_status romap_add_object(romap_ctx* ctx, int32_t instance_id, const romap_box* box,
+                              int32_t log2_table_size, int32_t* object_id);
+/* Idle objects stop training (Sec. V-A): inactive objects are skipped when
+ * romap_train is given object_ids = NULL. */
+romap_status romap_set_object_active(romap_ctx* ctx, int32_t object_id, int32_t active);
+romap_status romap_get_object_info(romap_ctx* ctx, int32_t object_id, romap_object_info* info);
+
+/* Adds a posed keyframe (Sec. V-A "Data").  rgb: H*W*3 bytes; mask: H*W
+ * int32 instance ids, 0 = background; depth_z: H*W camera z of sparse depth,
+ * <= 0 or non-finite = none, may be NULL.  For every registered object seen
+ * in the mask the keyframe joins its set if it is the object's first, or if
+ * the angle of Eq. 5 to the object's last accepted keyframe exceeds
+ * alpha_deg.  *keyframe_id and *n_objects_accepted may be NULL. */
+romap_status romap_add_keyframe(romap_ctx* ctx, const romap_camera* cam, const uint8_t* rgb,
+                                const int32_t* mask, const float* depth_z, int32_t* keyframe_id,
+                                int32_t* n_objects_accepted);
+
+/* Runs n_steps training iterations (draw, render, loss, backward, Adam) on
+ * every listed object (NULL = every active object).  rays_per_object: rays
+ * per step for each listed object (NULL = config default).  stats may be
+ * NULL, in which case the call does not wait for the GPU.  Returns
+ * ROMAP_E_STATE if a listed object has no keyframe, ROMAP_E_NUMERIC (after
+ * the steps ran) if an object's loss is not finite. */
+romap_status romap_train(romap_ctx* ctx, const int32_t* object_ids, int32_t n_objects,
+                         int32_t n_steps, const int32_t* rays_per_object,
+                         romap_train_stats* stats);
+
+/* One step's loss and gradient without the Adam update or step advance: the
+ * gradient buffer is cleared, then holds dL/dparams (read it with kind
+ * ROMAP_GRAD).  losses (host, n_objects floats) may be NULL. */
+romap_status romap_loss_and_grad(romap_ctx* ctx, const int32_t* object_ids, int32_t n_objects,
+                                 const int32_t* rays_per_object, float* losses);
+
+/* Renders one object's model from a camera (composited on black):
+ * rgb H*W*3, depth H*W (ray distance), opacity H*W (1 - T_end); any output
+ * may be NULL.  out_on_device: outputs are device pointers (ordered on the
+ * context stream) rather than host buffers (the call then waits). */
+romap_status romap_render(romap_ctx* ctx, int32_t object_id, const romap_camera* cam, float* rgb,
+                          float* depth, float* opacity, int32_t out_on_device);
+
+/* Density at n object-frame points xyz (n*3), for meshing (Sec. III:
+ * marching cubes on the object's density).  Points outside the box are
+ * clamped to it.  on_device: xyz and sigma are device pointers. */
+romap_status romap_query_density(romap_ctx* ctx, int32_t object_id, const float* xyz, int64_t n,
+                                 float* sigma, int32_t on_device);
+
+/* Copies an object's parameters (kind ROMAP_PARAMS / ADAM_M / ADAM_V / GRAD)
+ * to or from a host buffer of n floats.  *n_required (may be NULL) receives
+ * the count; buf may be NULL to query it.  ROMAP_E_INVALID_ARG if n is
+ * smaller than the count. */
+romap_status romap_get_params(romap_ctx* ctx, int32_t object_id, int32_t kind, float* buf,
+                              int64_t n, int64_t* n_required);
+romap_status romap_set_params(romap_ctx* ctx, int32_t object_id, int32_t kind, const float* buf,
+                              int64_t n);
+
+/* Checkpoint of the whole context: config, objects (box, parameters, Adam
+ * state, step counters, keyframe sets) and keyframes.  A loaded context
+ * continues bit-identically because every random draw is a Philox counter
+ * keyed on (seed, object, step, ray).  load needs an empty context. */
+romap_status romap_save(romap_ctx* ctx, const char* path);
+romap_status romap_load(romap_ctx* ctx, const char* path);
+
+/* ---- inspection: the drawn rays of one step ------------------------------
+ * Draws object_id's rays for its current step exactly as romap_train does
+ * and copies them to host arrays (each may be NULL):
+ *   kf_uv     n_rays*3 int32: keyframe index within the object's set, u, v
+ *   cls       n_rays int32: 0 occluder, 1 object, 2 background (Sec. V-B);
+ *             -1 when the ray misses the box
+ *   ray_f     n_rays*16 floats: o[3], d[3], t_n, delta, target[3] (image colour,
+ *             or the random colour of a background ray), D, 0, 0, 0, has_depth
+ *   positions n_rays*N*3 floats: normalised sample positions in [0,1]^3    */
+romap_status romap_debug_rays(romap_ctx* ctx, int32_t object_id, int32_t n_rays, int32_t* kf_uv,
+                              int32_t* cls, float* ray_f, float* positions);
+/* Hash-grid encoding of n normalised positions p (n*3, [0,1]^3) with the
+ * object's current grid: idx n*L*8 uint32 corner indices within each level,
+ * feat n*L*2 floats.  Host buffers; either output may be NULL. */
+romap_status romap_debug_encode(romap_ctx* ctx, int32_t object_id, const float* p, int64_t n,
+                                uint32_t* idx, float* feat);
+
+/* ---- differentiable surface (for torch.autograd.Function) ----------------
+ * rays_dev: n_rays*8 floats per ray: origin[3], unit direction[3], t_near,
+ * t_far, in the object frame (t_far <= t_near = empty ray).  params_dev: the
+ * object's parameter vector in ROMAP_PARAMS order (NULL = the object's own).
+ * Forward writes rgb (n*3, on black), depth (n) and T_end (n); any may be
+ * NULL.  Backward recomputes every per-sample activation (nothing is stored
+ * between the calls) and writes dL/dparams into d_params_dev (overwritten),
+ * given dL/drgb, dL/ddepth, dL/dT_end (any may be NULL = zero).  All
+ * pointers are device pointers ordered on the context stream. */
+romap_status romap_field_forward(romap_ctx* ctx, int32_t object_id, const float* params_dev,
+                                 const float* rays_dev, int32_t n_rays, float* rgb_dev,
+                                 float* depth_dev, float* tend_dev);
+romap_status romap_field_backward(romap_ctx* ctx, int32_t object_id, const float* params_dev,
+                                  const float* rays_dev, int32_t n_rays, const float* d_rgb_dev,
+                                  const float* d_depth_dev, const float* d_tend_dev,
+                                  float* d_params_dev);
+
+/* Kernels of one training step, in launch order. */
+#define ROMAP_PHASE_RAYGEN 0     /* ray draw, classification, box clipping (Sec. V-B) */
+#define ROMAP_PHASE_ENCODE 1     /* hash-grid gather */
+#define ROMAP_PHASE_PACK 2       /* MLP weights -> MFMA operand images */
+#define ROMAP_PHASE_FIELD 3      /* MLP, volume rendering, loss, adjoint */
+#define ROMAP_PHASE_ENCODE_BWD 4 /* hash-grid gradient scatter */
+#define ROMAP_PHASE_REDUCE 5     /* per-object MLP gradient and loss */
+#define ROMAP_PHASE_ADAM 6       /* dense Adam */
+#define ROMAP_N_PHASES 7
+
+/* Average duration in ms of each kernel of a step over the steps of the last
+ * romap_train call made with profile_phases = 1 (measured with HIP events on
+ * the context stream).  avg_ms: ROMAP_N_PHASES floats.  *n_steps (may be
+ * NULL) receives the number of steps averaged (0 if none). */
+romap_status romap_get_phase_times(romap_ctx* ctx, float* avg_ms, int32_t* n_steps);
+
+/* Synchronises the context stream. */
+romap_status romap_sync(romap_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -93,14 +93,16 @@ def lib():
         _lib.or_draw_ray.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, C.c_int,
                                      C.POINTER(Keyframe), C.c_int, C.POINTER(Ray)]
         _lib.or_object_step.argtypes = [C.POINTER(Config), C.POINTER(Levels), C.c_int, C.c_int, P,
-                                        C.c_int, C.POINTER(Keyframe), C.c_int, C.c_int, P, P, P,
-                                        C.POINTER(Ray), C.c_int]
+                                        C.c_int, C.POINTER(Keyframe), C.c_int, C.c_int, P, P, P, P,
+                                        P, P, C.POINTER(Ray), C.c_int]
         _lib.or_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int, C.c_double, C.c_double,
                                  C.c_double, C.c_double]
         _lib.or_render.argtypes = [C.POINTER(Config), C.POINTER(Levels), P, C.POINTER(Keyframe), P,
                                    P, P, P, C.c_int]
         _lib.or_query_density.argtypes = [C.POINTER(Levels), P, P, C.c_int64, P, P]
         _lib.or_philox4x32_10.argtypes = [P, P, P]
+        _lib.or_field.argtypes = [C.POINTER(Config), C.POINTER(Levels), P, P, C.c_int, P, P, P, P,
+                                  P, P, P, P, P, P, C.c_int]
     return _lib
 
 
@@ -269,7 +271,7 @@ class OracleContext:
     def __init__(self, cfg: Config, alpha_deg: float = 25.0, nthreads: int | None = None):
         self.cfg = cfg
         self.alpha_deg = alpha_deg
-        self.nthreads = nthreads or os.cpu_count() or 1
+        self.nthreads = nthreads or min(16, os.cpu_count() or 1)
         self.objects: list[_Obj] = []
         self.keyframes: list[_Kf] = []
 
@@ -322,8 +324,18 @@ class OracleContext:
             k.x0, k.y0, k.w, k.h = rect
         return arr
 
-    def loss_and_grad(self, oid, step, B, rays=False, params=None, want_grad=True):
-        """Loss of one step and dL/dparams (no optimiser update)."""
+    def loss_and_grad(self, oid, step, B, rays=False, params=None, want_grad=True, mass=None,
+                      ambiguous=None, margin=None):
+        """Loss of one step and dL/dparams (no optimiser update).  mass: an array
+        of the parameter count that receives the magnitude of every gradient
+        entry, the same backward on absolute values, which bounds to first order
+        how far rounding (in any order of summation) can move the entry.
+        ambiguous: an array of the parameter count that receives, for samples
+        whose decisions (ReLU branch, density clamp, depth-error sign) lie within
+        1e-5 relative of a tie, the magnitude of their contributions with every
+        branch taken: how far another branch choice can move each entry.
+        margin: a 1-element array that receives the smallest relative distance
+        of a decision from its tie in the step."""
         o = self.objects[oid]
         if not o.kfs:
             raise RuntimeError("object has no keyframes")
@@ -334,8 +346,11 @@ class OracleContext:
         ray_buf = (Ray * B)() if rays else None
         rc = lib().or_object_step(C.byref(self.cfg), C.byref(o.lv), oid, o.instance, _p(o.half),
                                   len(o.kfs), kfa, int(step), int(B), _p(p),
-                                  _p(grad) if want_grad else None, _p(loss), ray_buf,
-                                  self.nthreads)
+                                  _p(grad) if want_grad else None,
+                                  _p(mass) if (want_grad and mass is not None) else None,
+                                  None if ambiguous is None else _p(ambiguous),
+                                  None if margin is None else _p(margin),
+                                  _p(loss), ray_buf, self.nthreads)
         if rc != 0:
             raise RuntimeError("oracle step failed")
         return float(loss[0]), grad, ray_buf
@@ -367,6 +382,26 @@ class OracleContext:
         lib().or_render(C.byref(self.cfg), C.byref(o.lv), _p(o.half), C.byref(kf), _p(o.params),
                         _p(rgb), _p(depth), _p(opac), self.nthreads)
         return rgb, depth, opac
+
+    def field(self, oid, rays, params=None, d_rgb=None, d_depth=None, d_tend=None, grad=False,
+              mass=None, ambiguous=None):
+        """rays: (n, 8) float32 object-frame rays (o, d, t_near, t_far).  Returns
+        rgb, depth, T_end and, with grad, d(sum d_rgb.C + d_depth D + d_tend T_end)/dparams."""
+        o = self.objects[oid]
+        rays = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+        n = rays.shape[0]
+        p = o.params if params is None else np.ascontiguousarray(params, np.float64)
+        rgb, depth, tend = np.zeros((n, 3)), np.zeros(n), np.zeros(n)
+        g = np.zeros(p.size) if grad else None
+        cv = lambda a: None if a is None else np.ascontiguousarray(a, np.float64)
+        dr, dd, dt = cv(d_rgb), cv(d_depth), cv(d_tend)
+        lib().or_field(C.byref(self.cfg), C.byref(o.lv), _p(o.half), _p(p), n, _p(rays), _p(rgb),
+                       _p(depth), _p(tend), None if dr is None else _p(dr),
+                       None if dd is None else _p(dd), None if dt is None else _p(dt),
+                       None if g is None else _p(g),
+                       None if (g is None or mass is None) else _p(mass),
+                       None if (g is None or ambiguous is None) else _p(ambiguous), self.nthreads)
+        return rgb, depth, tend, g
 
     def query_density(self, oid, xyz):
         o = self.objects[oid]

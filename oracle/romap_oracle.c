@@ -348,11 +348,12 @@ void or_draw_ray(const or_config* cfg, int obj, int step, int r, int nkf, const 
 /* ------------------------------------------------------------------------ */
 /* One training step of one object: draw, render, loss (Eq. 7-11), gradient
  * of the loss with respect to every parameter.  `grad` (may be NULL) is
- * overwritten with dL/dparams.  `rays` (may be NULL) receives the per-ray
+ * overwritten with dL/dparams; `grad_abs` (may be NULL) with the magnitude of
+ * the same gradient (see sample_backward_magnitude).  `rays` (may be NULL) receives the per-ray
  * record.  The loss is L = (1/B) sum_r l_r. */
 typedef struct {
   uint32_t* idx;
-  double *w, *e, *h1, *y, *h2, *sigma, *rgb, *dist, *wts, *dsig, *tnext;
+  double *w, *e, *h1, *y, *h2, *sigma, *rgb, *dist, *wts, *dsig, *dsig_m, *tnext;
   float *pos, *dist32;
 } or_scratch;
 
@@ -368,6 +369,7 @@ static void scratch_alloc(or_scratch* s, int N, int L) {
   s->dist = (double*)malloc(sizeof(double) * N);
   s->wts = (double*)malloc(sizeof(double) * N);
   s->dsig = (double*)malloc(sizeof(double) * N);
+  s->dsig_m = (double*)malloc(sizeof(double) * N);
   s->tnext = (double*)malloc(sizeof(double) * N);
   s->pos = (float*)malloc(sizeof(float) * N * 3);
   s->dist32 = (float*)malloc(sizeof(float) * N);
@@ -375,7 +377,7 @@ static void scratch_alloc(or_scratch* s, int N, int L) {
 
 static void scratch_free(or_scratch* s) {
   free(s->idx); free(s->w); free(s->e); free(s->h1); free(s->y); free(s->h2);
-  free(s->sigma); free(s->rgb); free(s->dist); free(s->wts); free(s->dsig); free(s->tnext);
+  free(s->sigma); free(s->rgb); free(s->dist); free(s->wts); free(s->dsig); free(s->dsig_m); free(s->tnext);
   free(s->pos); free(s->dist32);
 }
 
@@ -433,18 +435,225 @@ static void sample_backward(const or_levels* lv, int din, const double* mlp, con
     }
 }
 
+/* The same backward on magnitudes: every weight, activation and upstream
+ * adjoint replaced by its absolute value, so each sum becomes a sum of
+ * |terms|.  The result bounds, to first order, how far a gradient computed
+ * with rounding (in any summation order) can move: rounding error of each
+ * operation is relative to these magnitudes, not to the possibly cancelled
+ * value.  Test infrastructure for the per-entry tolerance. */
+static void sample_backward_magnitude(const or_levels* lv, int din, const double* mlp,
+                                      const uint32_t* idx, const double* w, const double* e,
+                                      const double* h1, const double* y, const double* h2,
+                                      double sigma, const double* rgb, double dsig_m,
+                                      const double* dc_m, int all_branches, double* mag) {
+  const double* W1 = mlp;
+  const double* W2 = W1 + OR_HIDDEN * din;
+  const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
+  const double* W4 = W3 + OR_HIDDEN * OR_GEO;
+  double* mG = mag;
+  double* mW1 = mag + or_grid_params(lv);
+  double* mW2 = mW1 + OR_HIDDEN * din;
+  double* mW3 = mW2 + OR_DOUT * OR_HIDDEN;
+  double* mW4 = mW3 + OR_HIDDEN * OR_GEO;
+  double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], dh1[OR_HIDDEN], de[2 * OR_MAX_LEVELS];
+  for (int k = 0; k < 3; ++k) dz4[k] = dc_m[k] * rgb[k] * (1.0 - rgb[k]);
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < OR_HIDDEN; ++j) mW4[k * OR_HIDDEN + j] += dz4[k] * h2[j];
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) s += fabs(W4[k * OR_HIDDEN + j]) * dz4[k];
+    dh2[j] = (h2[j] > 0.0 || all_branches) ? s : 0.0;
+  }
+  for (int j = 0; j < OR_HIDDEN; ++j)
+    for (int g = 0; g < OR_GEO; ++g) mW3[j * OR_GEO + g] += dh2[j] * fabs(y[1 + g]);
+  for (int g = 0; g < OR_GEO; ++g) {
+    double s = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) s += fabs(W3[j * OR_GEO + g]) * dh2[j];
+    dy[1 + g] = s;
+  }
+  dy[0] = (y[0] < 15.0 || all_branches) ? dsig_m * sigma : 0.0;
+  for (int i = 0; i < OR_DOUT; ++i)
+    for (int j = 0; j < OR_HIDDEN; ++j) mW2[i * OR_HIDDEN + j] += dy[i] * h1[j];
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < OR_DOUT; ++i) s += fabs(W2[i * OR_HIDDEN + j]) * dy[i];
+    dh1[j] = (h1[j] > 0.0 || all_branches) ? s : 0.0;
+  }
+  for (int j = 0; j < OR_HIDDEN; ++j)
+    for (int q = 0; q < din; ++q) mW1[j * din + q] += dh1[j] * fabs(e[q]);
+  for (int q = 0; q < din; ++q) {
+    double s = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) s += fabs(W1[j * din + q]) * dh1[j];
+    de[q] = s;
+  }
+  for (int l = 0; l < lv->L; ++l)
+    for (int b = 0; b < 8; ++b) {
+      int64_t at = lv->off[l] + 2 * (int64_t)idx[8 * l + b];
+      mG[at + 0] += w[8 * l + b] * de[2 * l + 0];
+      mG[at + 1] += w[8 * l + b] * de[2 * l + 1];
+    }
+}
+
+/* Forward of one ray with N uniform samples in [tn, tf]: positions, encoding,
+ * MLPs (kept in s for the backward), and Eq. 6 (plus T_end C_rand for a
+ * background ray). */
+static void ray_forward(const or_levels* lv, int N, const double* params, const float o[3],
+                        const float d[3], const float half[3], float tn, float tf, float* delta,
+                        or_scratch* s, int bg, const double crand[3], double C[3], double* D,
+                        double* Tend) {
+  const int L = lv->L, din = 2 * L;
+  const double* mlp = params + or_grid_params(lv);
+  or_sample_positions(o, d, half, tn, tf, N, delta, s->dist32, s->pos);
+  for (int i = 0; i < N; ++i) s->dist[i] = (double)s->dist32[i];
+  for (int i = 0; i < N; ++i) {
+    or_encode(lv, s->pos + 3 * i, params, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i);
+    or_mlp_forward(din, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * i, s->y + OR_DOUT * i,
+                   s->h2 + OR_HIDDEN * i, s->sigma + i, s->rgb + 3 * i);
+  }
+  or_composite(N, s->sigma, s->rgb, s->dist, (double)*delta, bg, crand, C, D, Tend, s->wts);
+}
+
+/* Backward of one ray given dl/dC (gC), dl/dD (gD), dl/dT_end (gT) and the
+ * per-sample density-loss weight dens (Eq. 10 term, background rays only).
+ * Adjoint of Eq. 6: dC/dtau_i = T_{i+1} c_i - sum_{j>i} w_j c_j, and every
+ * tau_i enters T_end = exp(-sum tau) (background rays composite T_end C_rand).
+ * Adds dl/dparams into grad and, if mag is not NULL, the magnitude of the same
+ * backward into mag. */
+static void ray_backward(const or_levels* lv, int N, const double* params, double delta,
+                         or_scratch* s, int bg, const double crand[3], double Tend,
+                         const double gC[3], double gD, double gT, double dens, double* grad,
+                         double* mag) {
+  const int L = lv->L, din = 2 * L;
+  const double* mlp = params + or_grid_params(lv);
+  double suf_c[3] = {0.0, 0.0, 0.0}, suf_d = 0.0;
+  double S_i = 0.0;
+  for (int i = 0; i < N; ++i) {
+    S_i += s->sigma[i] * delta;
+    s->tnext[i] = exp(-S_i);
+  }
+  const double* Tnext = s->tnext;
+  for (int i = N - 1; i >= 0; --i) {
+    double a = 0.0, am = 0.0;
+    for (int k = 0; k < 3; ++k) a += gC[k] * (Tnext[i] * s->rgb[3 * i + k] - suf_c[k]);
+    if (bg)
+      for (int k = 0; k < 3; ++k) a -= gC[k] * Tend * crand[k];
+    a += gD * (Tnext[i] * s->dist[i] - suf_d);
+    a -= gT * Tend;
+    s->dsig[i] = a * delta + dens;
+    /* magnitude of the same adjoint (for the tolerance of the tests) */
+    for (int k = 0; k < 3; ++k) am += fabs(gC[k]) * (Tnext[i] * s->rgb[3 * i + k] + suf_c[k]);
+    if (bg)
+      for (int k = 0; k < 3; ++k) am += fabs(gC[k]) * Tend * crand[k];
+    am += fabs(gD) * (Tnext[i] * s->dist[i] + suf_d) + fabs(gT) * Tend;
+    s->dsig_m[i] = am * delta + dens;
+    for (int k = 0; k < 3; ++k) suf_c[k] += s->wts[i] * s->rgb[3 * i + k];
+    suf_d += s->wts[i] * s->dist[i];
+  }
+  for (int i = 0; i < N; ++i) {
+    double dci[3];
+    for (int k = 0; k < 3; ++k) dci[k] = s->wts[i] * gC[k];
+    sample_backward(lv, din, mlp, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i,
+                    s->h1 + OR_HIDDEN * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i,
+                    s->sigma[i], s->rgb + 3 * i, s->dsig[i], dci, grad);
+    if (mag) {
+      for (int k = 0; k < 3; ++k) dci[k] = s->wts[i] * fabs(gC[k]);
+      sample_backward_magnitude(lv, din, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
+                                s->e + 2 * L * i, s->h1 + OR_HIDDEN * i, s->y + OR_DOUT * i,
+                                s->h2 + OR_HIDDEN * i, s->sigma[i], s->rgb + 3 * i,
+                                s->dsig_m[i], dci, 0, mag);
+    }
+  }
+}
+
+/* Test infrastructure.  A gradient entry is not unique when it depends on a
+ * discrete decision (a ReLU branch, the density clamp, the sign of the depth
+ * error) that a computation with rounding error could take the other way.
+ * The relative distance of a decision from its tie is |pre-activation| over
+ * the sum of |terms| that form it; sample_ties returns the smallest one over
+ * the sample's decisions. */
+static double sample_ties(int din, const double* mlp, const double* e, const double* h1,
+                          const double* y) {
+  const double* W1 = mlp;
+  const double* W2 = W1 + OR_HIDDEN * din;
+  const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
+  double m = INFINITY;
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double pre = 0.0, mag = 0.0;
+    for (int q = 0; q < din; ++q) {
+      pre += W1[j * din + q] * e[q];
+      mag += fabs(W1[j * din + q] * e[q]);
+    }
+    if (mag > 0.0) m = fmin(m, fabs(pre) / mag);
+  }
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double pre = 0.0, mag = 0.0;
+    for (int g = 0; g < OR_GEO; ++g) {
+      pre += W3[j * OR_GEO + g] * y[1 + g];
+      mag += fabs(W3[j * OR_GEO + g] * y[1 + g]);
+    }
+    if (mag > 0.0) m = fmin(m, fabs(pre) / mag);
+  }
+  double mag0 = 0.0;
+  for (int j = 0; j < OR_HIDDEN; ++j) mag0 += fabs(W2[j] * h1[j]);
+  if (mag0 > 0.0) m = fmin(m, fabs(y[0] - 15.0) / mag0);
+  return m;
+}
+
+/* Tests only.  Smallest distance of a ray's decisions from their ties
+ * (dtie: that of its depth-error sign), and into amb (may be NULL), for each
+ * sample with a decision closer than 1e-5: the magnitude of its gradient
+ * contributions with every branch taken, which bounds the change another
+ * branch choice can make (twice for every sample when the depth sign ties).
+ * Needs the forward of the ray and the magnitudes dsig_m of ray_backward. */
+static double tie_allowance(const or_levels* lv, int N, const double* params, or_scratch* s,
+                            const double gCabs[3], double dtie, double* amb) {
+  const double kTie = 1e-5;
+  const int L = lv->L;
+  const double* mlp = params + or_grid_params(lv);
+  double rm = dtie;
+  for (int i = 0; i < N; ++i) {
+    const double sm = sample_ties(2 * L, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * i,
+                                  s->y + OR_DOUT * i);
+    rm = fmin(rm, sm);
+    const int reps = dtie < kTie ? 2 : (sm < kTie ? 1 : 0);
+    if (amb && reps) {
+      double dcm[3];
+      for (int k = 0; k < 3; ++k) dcm[k] = s->wts[i] * gCabs[k];
+#pragma omp critical
+      for (int rep = 0; rep < reps; ++rep)
+        sample_backward_magnitude(lv, 2 * L, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
+                                  s->e + 2 * L * i, s->h1 + OR_HIDDEN * i, s->y + OR_DOUT * i,
+                                  s->h2 + OR_HIDDEN * i, s->sigma[i], s->rgb + 3 * i,
+                                  s->dsig_m[i], dcm, 1, amb);
+    }
+  }
+  return rm;
+}
+
+/* Sums per-thread buffers (P floats each) in thread order into out. */
+static void reduce_threads(const double* t, int nthreads, int64_t P, double* out) {
+  for (int64_t i = 0; i < P; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < nthreads; ++k) acc += t[(int64_t)k * P + i];
+    out[i] = acc;
+  }
+}
+
 int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int instance,
                    const float half[3], int nkf, const or_keyframe* kfs, int step, int B,
-                   const double* params, double* grad, double* loss, or_ray* rays, int nthreads) {
+                   const double* params, double* grad, double* grad_abs, double* ambiguous,
+                   double* min_margin, double* loss, or_ray* rays, int nthreads) {
   if (nkf < 1 || B < 1 || cfg->N < 1) return -1;
-  const int L = lv->L, N = cfg->N, din = 2 * L;
-  const int64_t Pg = or_grid_params(lv);
-  const int64_t P = Pg + or_mlp_params(din);
-  const double* mlp = params + Pg;
+  const int L = lv->L, N = cfg->N;
+  const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L);
   if (nthreads < 1) nthreads = 1;
   double* ray_loss = (double*)calloc((size_t)B, sizeof(double));
+  double* ray_margin = (double*)calloc((size_t)B, sizeof(double));
   double* tgrad = NULL;
+  double* tabs = NULL;
   if (grad) tgrad = (double*)calloc((size_t)P * nthreads, sizeof(double));
+  if (grad && grad_abs) tabs = (double*)calloc((size_t)P * nthreads, sizeof(double));
+  if (ambiguous) memset(ambiguous, 0, sizeof(double) * (size_t)P);
 
 #pragma omp parallel num_threads(nthreads)
   {
@@ -455,6 +664,7 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
     or_scratch s;
     scratch_alloc(&s, N, L);
     double* my_grad = grad ? tgrad + (int64_t)tid * P : NULL;
+    double* my_abs = tabs ? tabs + (int64_t)tid * P : NULL;
 #pragma omp for schedule(static)
     for (int r = 0; r < B; ++r) {
       or_ray ray;
@@ -465,17 +675,10 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
       ray.loss = 0.0;
       /* occluder rays carry no loss (Sec. V-B); rays missing the box have no samples */
       if (ray.cls != 0 && ray.hit) {
-        or_sample_positions(ray.o, ray.d, half, ray.tn, ray.tf, N, &ray.delta, s.dist32, s.pos);
-        for (int i = 0; i < N; ++i) s.dist[i] = (double)s.dist32[i];
-        for (int i = 0; i < N; ++i) {
-          or_encode(lv, s.pos + 3 * i, params, s.idx + 8 * L * i, s.w + 8 * L * i, s.e + 2 * L * i);
-          or_mlp_forward(din, mlp, s.e + 2 * L * i, s.h1 + OR_HIDDEN * i, s.y + OR_DOUT * i,
-                         s.h2 + OR_HIDDEN * i, s.sigma + i, s.rgb + 3 * i);
-        }
         double crand[3] = {ray.Crand[0], ray.Crand[1], ray.Crand[2]};
-        int bg = ray.cls == 2;
-        or_composite(N, s.sigma, s.rgb, s.dist, (double)ray.delta, bg, crand, ray.Chat, &ray.Dhat,
-                     &ray.Tend, s.wts);
+        const int bg = ray.cls == 2;
+        ray_forward(lv, N, params, ray.o, ray.d, half, ray.tn, ray.tf, &ray.delta, &s, bg, crand,
+                    ray.Chat, &ray.Dhat, &ray.Tend);
         /* Eq. 7-11: squared colour error against the image (object rays) or
          * the random colour (background rays); depth and density terms. */
         double target[3];
@@ -496,52 +699,90 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
             double diff = ray.Dhat - (double)ray.D;
             gD = cfg->lambda_depth * (diff > 0.0 ? 1.0 : (diff < 0.0 ? -1.0 : 0.0)) / (double)B;
           }
-          /* adjoint of Eq. 6: dC/dtau_i = T_{i+1} c_i - sum_{j>i} w_j c_j, and for
-           * background rays also - T_end C_rand (T_end = exp(-sum tau)). */
-          double suf_c[3] = {0.0, 0.0, 0.0}, suf_d = 0.0;
-          double S_i = 0.0;
-          for (int i = 0; i < N; ++i) {
-            S_i += s.sigma[i] * (double)ray.delta;
-            s.tnext[i] = exp(-S_i);
-          }
-          double* Tnext = s.tnext;
-          double Tend = ray.Tend;
-          for (int i = N - 1; i >= 0; --i) {
-            double a = 0.0;
-            for (int k = 0; k < 3; ++k) a += gC[k] * (Tnext[i] * s.rgb[3 * i + k] - suf_c[k]);
-            if (bg)
-              for (int k = 0; k < 3; ++k) a -= gC[k] * Tend * crand[k];
-            a += gD * (Tnext[i] * s.dist[i] - suf_d);
-            s.dsig[i] = a * (double)ray.delta + (bg ? cfg->lambda_density / (double)B : 0.0);
-            for (int k = 0; k < 3; ++k) suf_c[k] += s.wts[i] * s.rgb[3 * i + k];
-            suf_d += s.wts[i] * s.dist[i];
-          }
-          for (int i = 0; i < N; ++i) {
-            double dci[3];
-            for (int k = 0; k < 3; ++k) dci[k] = s.wts[i] * gC[k];
-            sample_backward(lv, din, mlp, s.idx + 8 * L * i, s.w + 8 * L * i, s.e + 2 * L * i,
-                            s.h1 + OR_HIDDEN * i, s.y + OR_DOUT * i, s.h2 + OR_HIDDEN * i,
-                            s.sigma[i], s.rgb + 3 * i, s.dsig[i], dci, my_grad);
-          }
+          ray_backward(lv, N, params, (double)ray.delta, &s, bg, crand, ray.Tend, gC, gD, 0.0,
+                       bg ? cfg->lambda_density / (double)B : 0.0, my_grad, my_abs);
         }
+        double dtie = INFINITY;
+        if (!bg && ray.has_depth)
+          dtie = fabs(ray.Dhat - (double)ray.D) / fmax(fabs((double)ray.D), 1e-30);
+        double gCa[3];
+        for (int k = 0; k < 3; ++k) gCa[k] = fabs(2.0 * (ray.Chat[k] - (bg ? crand[k] : (double)ray.C[k])) / (double)B);
+        const double rm = tie_allowance(lv, N, params, &s, gCa, dtie, my_grad ? ambiguous : NULL);
+        ray_margin[r] = rm;
+      } else {
+        ray_margin[r] = INFINITY;
       }
       ray_loss[r] = ray.loss;
       if (rays) rays[r] = ray;
     }
     scratch_free(&s);
   }
-  double total = 0.0;
-  for (int r = 0; r < B; ++r) total += ray_loss[r];
-  *loss = total;
-  if (grad) {
-    for (int64_t i = 0; i < P; ++i) {
-      double acc = 0.0;
-      for (int t = 0; t < nthreads; ++t) acc += tgrad[(int64_t)t * P + i];
-      grad[i] = acc;
-    }
-    free(tgrad);
+  double total = 0.0, mm = INFINITY;
+  for (int r = 0; r < B; ++r) {
+    total += ray_loss[r];
+    mm = fmin(mm, ray_margin[r]);
   }
+  *loss = total;
+  if (min_margin) *min_margin = mm;
+  if (grad) reduce_threads(tgrad, nthreads, P, grad);
+  if (tabs) reduce_threads(tabs, nthreads, P, grad_abs);
+  free(tgrad);
+  free(tabs);
   free(ray_loss);
+  free(ray_margin);
+  return 0;
+}
+
+/* The field as a differentiable function of the parameters: rays given in the
+ * object frame (n x 8 floats: origin, unit direction, t_near, t_far; an empty
+ * interval renders nothing), composited on black.  Forward writes rgb (n x 3),
+ * depth (n), T_end (n); with grad it also writes the gradient of
+ * sum_r (d_rgb_r . C_r + d_depth_r D_r + d_tend_r T_end_r). */
+int or_field(const or_config* cfg, const or_levels* lv, const float half[3], const double* params,
+             int n, const float* rays, double* rgb, double* depth, double* tend,
+             const double* d_rgb, const double* d_depth, const double* d_tend, double* grad,
+             double* grad_abs, double* ambiguous, int nthreads) {
+  const int L = lv->L, N = cfg->N;
+  const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L);
+  if (nthreads < 1) nthreads = 1;
+  double* tgrad = grad ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
+  double* tabs = (grad && grad_abs) ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
+  if (ambiguous) memset(ambiguous, 0, sizeof(double) * (size_t)P);
+#pragma omp parallel num_threads(nthreads)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    or_scratch s;
+    scratch_alloc(&s, N, L);
+#pragma omp for schedule(static)
+    for (int r = 0; r < n; ++r) {
+      const float* q = rays + 8 * (int64_t)r;
+      const double zero[3] = {0.0, 0.0, 0.0};
+      double C[3] = {0.0, 0.0, 0.0}, D = 0.0, Tend = 1.0;
+      float delta = 0.0f;
+      const int hit = q[7] > q[6];
+      if (hit) ray_forward(lv, N, params, q, q + 3, half, q[6], q[7], &delta, &s, 0, zero, C, &D, &Tend);
+      for (int k = 0; k < 3; ++k) rgb[3 * r + k] = C[k];
+      depth[r] = D;
+      tend[r] = Tend;
+      if (grad && hit) {
+        const double gC[3] = {d_rgb ? d_rgb[3 * r] : 0.0, d_rgb ? d_rgb[3 * r + 1] : 0.0,
+                              d_rgb ? d_rgb[3 * r + 2] : 0.0};
+        ray_backward(lv, N, params, (double)delta, &s, 0, zero, Tend, gC,
+                     d_depth ? d_depth[r] : 0.0, d_tend ? d_tend[r] : 0.0, 0.0,
+                     tgrad + (int64_t)tid * P, tabs ? tabs + (int64_t)tid * P : NULL);
+        const double gCa[3] = {fabs(gC[0]), fabs(gC[1]), fabs(gC[2])};
+        if (ambiguous) tie_allowance(lv, N, params, &s, gCa, INFINITY, ambiguous);
+      }
+    }
+    scratch_free(&s);
+  }
+  if (grad) reduce_threads(tgrad, nthreads, P, grad);
+  if (tabs) reduce_threads(tabs, nthreads, P, grad_abs);
+  free(tgrad);
+  free(tabs);
   return 0;
 }
 

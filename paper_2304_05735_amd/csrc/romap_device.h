@@ -1,0 +1,169 @@
+// romap_device.h -- data layouts shared by the gfx950 kernels and the host
+// runtime of libromap.  Internal to the library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RM_MAX_LEVELS 16
+#define RM_HIDDEN 64
+#define RM_GEO 15
+#define RM_DOUT 16
+#define RM_MLP_MAX (64 * 32 + 16 * 64 + 64 * 15 + 3 * 64) /* 4224 */
+#define RM_REC_STRIDE 4240 /* floats per work-item record: MLP grads, loss, pad */
+#define RM_REC_LOSS 4224
+#define RM_WPACK 10240      /* packed MLP weight image, elements (K1 <= 32) */
+#define RM_WG 256           /* threads of the fused field kernel (4 waves) */
+#define RM_ADAM_CHUNK 8192  /* floats per Adam work chunk */
+
+// Offsets of the eight packed GEMM operands inside a weight image.
+#define RM_OFF_F1 0     /* W1        64 x K1  */
+#define RM_OFF_F2 2048  /* W2        16 x 64  */
+#define RM_OFF_F3 3072  /* W3'       64 x 16  (column 0 = 0, k>=1 -> W3[.][k-1]) */
+#define RM_OFF_F4 4096  /* W4 padded 16 x 64  */
+#define RM_OFF_B4 5120  /* W4'^T     64 x 16  */
+#define RM_OFF_B3 6144  /* W3'^T     16 x 64  */
+#define RM_OFF_B2 7168  /* W2^T      64 x 16  */
+#define RM_OFF_B1 8192  /* W1^T      K1 x 64  */
+
+// ray classes (Sec. V-B) and flags
+#define RM_CLS_OCCLUDER 0
+#define RM_CLS_OBJECT 1
+#define RM_CLS_BACKGROUND 2
+#define RM_F_CLS 3u
+#define RM_F_HIT 4u
+#define RM_F_DEPTH 8u
+
+// kernel modes of the fused field kernel
+#define RM_MODE_TRAIN 0   /* loss of Eq. 7-11 against the ray targets, then adjoint */
+#define RM_MODE_FORWARD 1 /* colour, depth, T_end only */
+#define RM_MODE_ADJOINT 2 /* adjoint of caller-given output gradients */
+
+struct KfRef {          // one accepted keyframe of one object
+  int32_t kf;           // global keyframe slot
+  int32_t x0, y0, w, h; // candidate rectangle
+  float M[9];           // camera -> object rotation
+  float c[3];           // camera centre in the object frame
+  int32_t pad;
+  int64_t cand_begin;   // candidates of the object's earlier keyframes
+};
+
+struct KfDev {
+  const uint8_t* rgb;
+  const int32_t* mask;
+  const float* depth;   // may be null
+  int32_t W, H;
+  float fx, fy, cx, cy;
+};
+
+struct ObjStatic {      // written by the host
+  float* params;        // P_alloc floats: grid (P_grid) then MLP
+  float* grad;
+  float* m;
+  float* v;
+  int64_t P, P_grid, P_alloc;
+  int64_t off[RM_MAX_LEVELS + 1]; // level offsets in floats
+  uint32_t N_l[RM_MAX_LEVELS];
+  uint32_t T_l[RM_MAX_LEVELS];
+  uint32_t hashed_mask;
+  int32_t L, din, instance, id, n_kf;
+  float half[3];
+  int32_t pad;
+  const KfRef* kfs;
+  int64_t n_cand;
+};
+
+struct ObjState {       // written by the device
+  int32_t step;         // Adam steps taken
+  float bc1, bc2;       // 1 - beta^step of the current step
+  float loss_acc;       // sum of per-step losses since the host last read it
+  int32_t n_loss;
+  int32_t pad[3];
+};
+
+struct RayRec {         // 64 B
+  float o[3], d[3];
+  float tn, delta;
+  float tgt[3];         // image colour (object rays) or random colour (background)
+  float D;              // depth target (ray distance)
+  uint32_t flags;
+  int32_t obj;
+  int32_t pad0, pad1;
+};
+
+struct StepObj {        // one object of a launch
+  int32_t obj;
+  int32_t n_rays;       // B_o, the loss normaliser
+  int32_t ray_begin;
+  int32_t item_begin, item_end;
+  int32_t pad[3];
+};
+
+struct Item {           // one workgroup of the fused field kernel
+  int32_t so;
+  int32_t ray_begin;
+  int32_t n_rays;
+  int32_t pad;
+};
+
+struct Chunk {          // one workgroup of the Adam kernel
+  int32_t obj;
+  int32_t pad;
+  int64_t begin;
+};
+
+struct StepArgs {
+  const ObjStatic* objs;
+  ObjState* state;
+  const KfDev* kfs;
+  const StepObj* sobj;
+  int32_t n_sobj;
+  const Item* items;
+  int32_t n_items;
+  const Chunk* chunks;
+  int32_t n_chunks;
+  RayRec* rays;
+  int32_t n_rays;
+  float2* e;            // [L][S] encodings
+  float2* de;           // [L][S] their adjoints
+  int64_t S;            // samples = n_rays * N
+  float* partials;      // n_items * RM_REC_STRIDE
+  float* wpack32;       // n_sobj * RM_WPACK
+  uint16_t* wpack16;    // n_sobj * RM_WPACK
+  uint32_t seed_lo, seed_hi;
+  float lambda_depth, lambda_density;
+  float lr, beta1, beta2, eps;
+  int32_t mode;
+  int32_t advance;      // reduce kernel advances the Adam step counter
+  const float* params_override; // single-object launches only
+  float* grad_override;
+  const float* adj_rgb;
+  const float* adj_depth;
+  const float* adj_tend;
+  float* out_rgb;
+  float* out_depth;
+  float* out_tend;
+  int32_t* dbg_kfuv;    // raygen: kf, u, v per ray (may be null)
+  int32_t* dbg_cls;
+};
+
+// Launch helpers implemented in romap_kernels.hip.
+hipError_t rm_launch_raygen(const StepArgs& a, int NS, hipStream_t st);
+hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int L, int block, hipStream_t st);
+hipError_t rm_launch_encode_bwd(const StepArgs& a, int NS, int L, int block, hipStream_t st);
+hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st);
+hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStream_t st);
+hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st);
+hipError_t rm_launch_adam(const StepArgs& a, hipStream_t st);
+hipError_t rm_launch_camera_rays(const StepArgs& a, int NS, const float* M, const float* c,
+                                 float fx, float fy, float cx, float cy, int W, int pix0,
+                                 hipStream_t st);
+hipError_t rm_launch_user_rays(const StepArgs& a, int NS, const float* rays, hipStream_t st);
+hipError_t rm_launch_query_density(const ObjStatic* objs, int obj, const float* xyz, int64_t n,
+                                   float* sigma, hipStream_t st);
+hipError_t rm_launch_debug_encode(const ObjStatic* objs, int obj, const float* p, int64_t n,
+                                  uint32_t* idx, float* feat, hipStream_t st);
+hipError_t rm_launch_fill(float* x, int64_t n, float v, hipStream_t st);
+hipError_t rm_launch_init(float* params, int64_t P_grid, int din, uint32_t k0, uint32_t k1,
+                          hipStream_t st);
+hipError_t rm_launch_debug_positions(const StepArgs& a, int NS, float* pos, hipStream_t st);
+hipError_t rm_launch_reset_loss(const StepArgs& a, hipStream_t st);

@@ -1,0 +1,1160 @@
+// romap_kernels.hip -- gfx950 kernels of one training step of RO-MAP's
+// per-object radiance fields (arXiv 2304.05735, Sec. V).
+//
+// One step over every object of a launch:
+//   k_raygen       draw rays in each object's detection boxes, classify them by
+//                  the instance mask, back-project into the object frame, clip
+//                  to the 3D box (Sec. V-B)                        [FP32, exact]
+//   k_encode_fwd   multiresolution hash-grid gather, level-major so that one
+//                  level's table (<= 4 MiB) stays resident in each XCD's L2
+//   k_pack         MLP weights -> MFMA operand images (FP32 and BF16)
+//   k_field        fused per-ray MLP (MFMA) + volume rendering (Eq. 6) + loss
+//                  (Eq. 7-11) + adjoint, activations recomputed in the backward
+//                  half, wavefront prefix scans for transmittance
+//   k_encode_bwd   level-major scatter-add of the encoding adjoint (atomics)
+//   k_reduce       per-object MLP gradient and loss from the work-item records
+//   k_adam         dense Adam over every parameter of every object of the step
+//
+// Precision: the ray / sample-position / cell / hash path is IEEE FP32 with no
+// contraction (this file is built with -ffp-contract=off; FMAs are written
+// out where wanted), so positions and indices are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "romap_device.h"
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+// Philox4x32-10 (Salmon et al., SC'11): the counter-based generator behind
+// every random draw, so a draw depends only on (seed, object, step, ray).
+__device__ inline void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// FP32 -> BF16, round to nearest even.
+__device__ inline uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Orders this wave's LDS traffic: every lane's earlier LDS accesses are
+// complete before any lane's later ones (cross-lane exchange inside a wave).
+__device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+__device__ inline float wave_sum(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// exclusive suffix sum over the 64 lanes (sum over lanes > lane)
+__device__ inline float wave_excl_suffix(float x, int lane) {
+  float inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    float y = __shfl_down(inc, o, 64);
+    if (lane + o < 64) inc += y;
+  }
+  float nxt = __shfl_down(inc, 1, 64);
+  return lane < 63 ? nxt : 0.0f;
+}
+
+// exclusive prefix without the subtraction: shift the inclusive scan by one lane
+__device__ inline float wave_excl_prefix(float x, int lane) {
+  float inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    float y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  float prv = __shfl_up(inc, 1, 64);
+  return lane > 0 ? prv : 0.0f;
+}
+
+// Position of sample i of a ray in the unit cube of the object's box:
+// d_i = t_n + (i + 1/2) delta, x = o + d_i d, p = (x + a) / 2a, clamped.
+__device__ inline void sample_pos(const RayRec& R, int i, const float* half, float p[3]) {
+  const float di = R.tn + ((float)i + 0.5f) * R.delta;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float x = R.o[k] + di * R.d[k];
+    const float q = (x + half[k]) / (half[k] + half[k]);
+    p[k] = fminf(fmaxf(q, 0.0f), 1.0f);
+  }
+}
+
+struct Cell {
+  uint32_t c[3];
+  float f[3];
+};
+
+__device__ inline void make_cell(const float p[3], uint32_t N, Cell& cl) {
+  const float Nf = (float)N;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float g = p[k] * Nf;
+    int ci = (int)floorf(g);
+    ci = ci < 0 ? 0 : ci;
+    ci = ci > (int)N - 1 ? (int)N - 1 : ci;
+    cl.c[k] = (uint32_t)ci;
+    cl.f[k] = g - (float)ci;
+  }
+}
+
+// Index of corner b (bit0 x, bit1 y, bit2 z) of a cell within its level:
+// dense 1:1 when the level fits its table, else the spatial hash of the
+// multiresolution hash encoding (primes 1, 2654435761, 805459861) mod T.
+__device__ inline uint32_t corner_index(const Cell& cl, int b, uint32_t N, uint32_t T,
+                                        bool hashed) {
+  const uint32_t vx = cl.c[0] + (uint32_t)(b & 1);
+  const uint32_t vy = cl.c[1] + (uint32_t)((b >> 1) & 1);
+  const uint32_t vz = cl.c[2] + (uint32_t)((b >> 2) & 1);
+  if (hashed) return (vx ^ (vy * 2654435761u) ^ (vz * 805459861u)) & (T - 1u);
+  const uint32_t n1 = N + 1u;
+  return vx + vy * n1 + vz * n1 * n1;
+}
+
+__device__ inline float corner_weight(const Cell& cl, int b) {
+  const float wx = (b & 1) ? cl.f[0] : 1.0f - cl.f[0];
+  const float wy = (b & 2) ? cl.f[1] : 1.0f - cl.f[1];
+  const float wz = (b & 4) ? cl.f[2] : 1.0f - cl.f[2];
+  return (wx * wy) * wz;
+}
+
+__device__ inline int find_sobj(const StepObj* so, int n, int r) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (so[mid].ray_begin <= r) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Back-projection of pixel (u, v) and clipping to the box [-a, a]:
+// pinhole camera, pixel centres at +0.5, unit direction, slab test.
+__device__ inline void pixel_ray(const float* M, const float* c, float fx, float fy, float cx,
+                                 float cy, int u, int v, const float* half, RayRec& R, int NS) {
+  const float x = (((float)u + 0.5f) - cx) / fx;
+  const float y = (((float)v + 0.5f) - cy) / fy;
+  float dd[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) dd[k] = (M[3 * k + 0] * x + M[3 * k + 1] * y) + M[3 * k + 2];
+  const float n = sqrtf((dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]);
+  float tmin = -INFINITY, tmax = INFINITY;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    R.d[k] = dd[k] / n;
+    R.o[k] = c[k];
+    const float inv = 1.0f / R.d[k];
+    const float t0 = (-half[k] - R.o[k]) * inv;
+    const float t1 = (half[k] - R.o[k]) * inv;
+    tmin = fmaxf(tmin, fminf(t0, t1));
+    tmax = fminf(tmax, fmaxf(t0, t1));
+  }
+  const float tn = fmaxf(tmin, 0.0f);
+  const bool hit = tmax > tn;
+  R.tn = tn;
+  R.delta = hit ? (tmax - tn) / (float)NS : 0.0f;
+  R.flags = hit ? RM_F_HIT : 0u;
+}
+
+// ---------------------------------------------------------------------------
+// K1: ray draw, classification, back-projection, box clipping (Sec. V-B)
+template <int NS>
+__global__ __launch_bounds__(256) void k_raygen(StepArgs a) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n_rays) return;
+  const int si = find_sobj(a.sobj, a.n_sobj, r);
+  const StepObj so = a.sobj[si];
+  const ObjStatic& ob = a.objs[so.obj];
+  const int local = r - so.ray_begin;
+  const uint32_t step = (uint32_t)a.state[so.obj].step;
+  uint32_t x[4];
+  philox4x32_10(step, (uint32_t)local, 0u, 0u, a.seed_lo ^ (uint32_t)ob.id, a.seed_hi, x);
+  const int64_t q = (int64_t)(((uint64_t)x[0] * (uint64_t)ob.n_cand) >> 32);
+  int lo = 0, hi = ob.n_kf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ob.kfs[mid].cand_begin <= q) lo = mid; else hi = mid - 1;
+  }
+  const KfRef& kr = ob.kfs[lo];
+  const int64_t lq = q - kr.cand_begin;
+  const int u = kr.x0 + (int)(lq % kr.w);
+  const int v = kr.y0 + (int)(lq / kr.w);
+  const KfDev kf = a.kfs[kr.kf];
+  float crand[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) crand[j] = (float)(x[j + 1] >> 8) * (1.0f / 16777216.0f);
+  const int64_t pix = (int64_t)v * kf.W + u;
+  const int m = kf.mask[pix];
+  const uint32_t cls = (m == ob.instance) ? RM_CLS_OBJECT : (m == 0 ? RM_CLS_BACKGROUND : RM_CLS_OCCLUDER);
+  RayRec R;
+  pixel_ray(kr.M, kr.c, kf.fx, kf.fy, kf.cx, kf.cy, u, v, ob.half, R, NS);
+  R.flags |= cls;
+  R.D = 0.0f;
+  if (cls == RM_CLS_BACKGROUND) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) R.tgt[j] = crand[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) R.tgt[j] = (float)kf.rgb[3 * pix + j] / 255.0f;
+  }
+  if (cls == RM_CLS_OBJECT && kf.depth) {
+    const float z = kf.depth[pix];
+    if (z > 0.0f && isfinite(z)) {
+      // camera z -> distance along the ray, the quantity of Eq. 8
+      const float xn = (((float)u + 0.5f) - kf.cx) / kf.fx;
+      const float yn = (((float)v + 0.5f) - kf.cy) / kf.fy;
+      R.D = z * sqrtf((xn * xn + yn * yn) + 1.0f);
+      R.flags |= RM_F_DEPTH;
+    }
+  }
+  R.obj = so.obj;
+  R.pad0 = 0;
+  R.pad1 = 0;
+  a.rays[r] = R;
+  if (a.dbg_kfuv) {
+    a.dbg_kfuv[3 * r + 0] = lo;
+    a.dbg_kfuv[3 * r + 1] = u;
+    a.dbg_kfuv[3 * r + 2] = v;
+  }
+}
+
+// rays of every pixel of a camera, for rendering (class "object", no target)
+struct CamArgs {
+  float M[9], c[3];
+  float fx, fy, cx, cy;
+  int W, pix0;
+};
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_camera_rays(StepArgs a, CamArgs ca) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n_rays) return;
+  const int p = ca.pix0 + r;
+  const int obj = a.sobj[0].obj;
+  RayRec R;
+  pixel_ray(ca.M, ca.c, ca.fx, ca.fy, ca.cx, ca.cy, p % ca.W, p / ca.W, a.objs[obj].half, R, NS);
+  R.flags |= RM_CLS_OBJECT;
+  R.tgt[0] = R.tgt[1] = R.tgt[2] = 0.0f;
+  R.D = 0.0f;
+  R.obj = obj;
+  R.pad0 = R.pad1 = 0;
+  a.rays[r] = R;
+}
+
+// caller-given rays (o, d, t_near, t_far) in the object frame
+template <int NS>
+__global__ __launch_bounds__(256) void k_user_rays(StepArgs a, const float* rays) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n_rays) return;
+  const float* q = rays + 8 * (int64_t)r;
+  RayRec R;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    R.o[k] = q[k];
+    R.d[k] = q[3 + k];
+  }
+  const float tn = q[6], tf = q[7];
+  const bool hit = tf > tn;
+  R.tn = tn;
+  R.delta = hit ? (tf - tn) / (float)NS : 0.0f;
+  R.flags = (hit ? RM_F_HIT : 0u) | RM_CLS_OBJECT;
+  R.tgt[0] = R.tgt[1] = R.tgt[2] = 0.0f;
+  R.D = 0.0f;
+  R.obj = a.sobj[0].obj;
+  R.pad0 = R.pad1 = 0;
+  a.rays[r] = R;
+}
+
+__device__ inline bool ray_active(uint32_t flags) {
+  return (flags & RM_F_HIT) && (flags & RM_F_CLS) != RM_CLS_OCCLUDER;
+}
+
+// ---------------------------------------------------------------------------
+// K2: encoding forward.  Grid (ceil(S / block), L): level is the slow index,
+// so the chip sweeps one level's table at a time.  One thread per sample.
+template <int NS>
+__global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
+  const int l = blockIdx.y;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.S) return;
+  const int r = (int)(s / NS), i = (int)(s % NS);
+  const RayRec R = a.rays[r];
+  if (!ray_active(R.flags)) return;
+  const ObjStatic& ob = a.objs[R.obj];
+  float p[3];
+  sample_pos(R, i, ob.half, p);
+  const uint32_t N = ob.N_l[l], T = ob.T_l[l];
+  const bool hashed = (ob.hashed_mask >> l) & 1u;
+  Cell cl;
+  make_cell(p, N, cl);
+  const float* G = (a.params_override ? a.params_override : ob.params) + ob.off[l];
+  float ex = 0.0f, ey = 0.0f;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint32_t id = corner_index(cl, b, N, T, hashed);
+    const float2 g = *(const float2*)(G + 2 * (int64_t)id);
+    const float w = corner_weight(cl, b);
+    ex = fmaf(w, g.x, ex);
+    ey = fmaf(w, g.y, ey);
+  }
+  a.e[(int64_t)l * a.S + s] = make_float2(ex, ey);
+}
+
+// K6: encoding backward: grad[idx_b] += w_b * de for the 8 corners
+template <int NS>
+__global__ __launch_bounds__(512) void k_encode_bwd(StepArgs a) {
+  const int l = blockIdx.y;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.S) return;
+  const int r = (int)(s / NS), i = (int)(s % NS);
+  const RayRec R = a.rays[r];
+  if (!ray_active(R.flags)) return;
+  const ObjStatic& ob = a.objs[R.obj];
+  const float2 g = a.de[(int64_t)l * a.S + s];
+  if (g.x == 0.0f && g.y == 0.0f) return;
+  float p[3];
+  sample_pos(R, i, ob.half, p);
+  const uint32_t N = ob.N_l[l], T = ob.T_l[l];
+  const bool hashed = (ob.hashed_mask >> l) & 1u;
+  Cell cl;
+  make_cell(p, N, cl);
+  float* Gg = (a.grad_override ? a.grad_override : ob.grad) + ob.off[l];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint32_t id = corner_index(cl, b, N, T, hashed);
+    const float w = corner_weight(cl, b);
+    unsafeAtomicAdd(Gg + 2 * (int64_t)id, w * g.x);
+    unsafeAtomicAdd(Gg + 2 * (int64_t)id + 1, w * g.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K3: MLP weights -> MFMA operand images.  For a GEMM Out(M x 16 samples) =
+// A(M x K) X(K x 16), operand element (t, q, r, lane) is
+// A[16t + lane%16][16q + 4(lane/16) + r]; the FP32 image orders it
+// ((t Q + q) 4 + r) 64 + lane (one 16x16x4 operand per 64 contiguous values),
+// the BF16 image ((t Q + q) 64 + lane) 4 + r (one 16x16x16 operand per lane).
+__device__ inline float mlp_A(const float* W, int din, int K1, int gemm, int m, int k) {
+  const float* W1 = W;
+  const float* W2 = W1 + RM_HIDDEN * din;
+  const float* W3 = W2 + RM_DOUT * RM_HIDDEN;
+  const float* W4 = W3 + RM_HIDDEN * RM_GEO;
+  switch (gemm) {
+    case 0: return k < din ? W1[m * din + k] : 0.0f;                 // F1 64 x K1
+    case 1: return W2[m * RM_HIDDEN + k];                             // F2 16 x 64
+    case 2: return k >= 1 ? W3[m * RM_GEO + (k - 1)] : 0.0f;          // F3 64 x 16
+    case 3: return m < 3 ? W4[m * RM_HIDDEN + k] : 0.0f;              // F4 16 x 64
+    case 4: return k < 3 ? W4[k * RM_HIDDEN + m] : 0.0f;              // B4 64 x 16
+    case 5: return m >= 1 ? W3[k * RM_GEO + (m - 1)] : 0.0f;          // B3 16 x 64
+    case 6: return W2[k * RM_HIDDEN + m];                             // B2 64 x 16
+    default: return m < din ? W1[k * din + m] : 0.0f;                 // B1 K1 x 64
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pack(StepArgs a, int K1) {
+  const StepObj so = a.sobj[blockIdx.x];
+  const ObjStatic& ob = a.objs[so.obj];
+  const float* W = (a.params_override ? a.params_override : ob.params) + ob.P_grid;
+  const int din = ob.din;
+  const int Ms[8] = {64, 16, 64, 16, 64, 16, 64, K1};
+  const int Ks[8] = {K1, 64, 16, 64, 16, 64, 16, 64};
+  const int offs[8] = {RM_OFF_F1, RM_OFF_F2, RM_OFF_F3, RM_OFF_F4,
+                       RM_OFF_B4, RM_OFF_B3, RM_OFF_B2, RM_OFF_B1};
+  float* o32 = a.wpack32 + (int64_t)blockIdx.x * RM_WPACK;
+  uint16_t* o16 = a.wpack16 + (int64_t)blockIdx.x * RM_WPACK;
+  for (int gm = 0; gm < 8; ++gm) {
+    const int M = Ms[gm], K = Ks[gm], Q = K / 16;
+    for (int j = threadIdx.x; j < M * K; j += blockDim.x) {
+      {  // FP32 image
+        const int lane = j & 63, r = (j >> 6) & 3, tq = j >> 8;
+        const int q = tq % Q, t = tq / Q;
+        o32[offs[gm] + j] = mlp_A(W, din, K1, gm, 16 * t + (lane & 15), 16 * q + 4 * (lane >> 4) + r);
+      }
+      {  // BF16 image
+        const int r = j & 3, lane = (j >> 2) & 63, tq = j >> 8;
+        const int q = tq % Q, t = tq / Q;
+        o16[offs[gm] + j] =
+            f2bf(mlp_A(W, din, K1, gm, 16 * t + (lane & 15), 16 * q + 4 * (lane >> 4) + r));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K4: fused per-ray field kernel.
+//
+// A wave owns one ray at a time; its N samples are processed in blocks of 16.
+// Activations are kept transposed, [feature][sample], as 16x16 MFMA result
+// fragments (lane = sample column, 4 feature rows per lane), which are
+// directly the B operands of the next layer: every forward and input-adjoint
+// GEMM chains in registers.  Weight gradients contract over samples and need
+// the [feature][sample] tiles in LDS (per-wave staging).
+//
+// PREC 0: FP32 MFMA 16x16x4.  PREC 1: BF16 MFMA 16x16x16, FP32 accumulation.
+template <int PREC>
+struct Mma;
+
+template <>
+struct Mma<0> {
+  typedef float wtype;
+  static constexpr int STRIDE = 17;  // staging row stride (floats)
+  template <int M, int K>
+  __device__ static inline void gemm(const float* wA, const floatx4* X, floatx4* Out, int lane) {
+    constexpr int Q = K / 16;
+#pragma unroll
+    for (int t = 0; t < M / 16; ++t) {
+      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wA[((t * Q + q) * 4 + r) * 64 + lane],
+                                                    X[q][r], acc, 0, 0, 0);
+      }
+      Out[t] = acc;
+    }
+  }
+  __device__ static inline void stage(float* buf, const floatx4* F, int nf, int lane) {
+    const int g = lane >> 4, n = lane & 15;
+    for (int f = 0; f < nf; ++f) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[(16 * f + 4 * g + r) * STRIDE + n] = F[f][r];
+    }
+  }
+  // acc[t][u] += G^T(16t.., 16 samples) X(16 samples, 16u..)
+  template <int MG, int MX>
+  __device__ static inline void dw(const float* gb, const float* xb, floatx4* acc, int lane) {
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < MG / 16; ++t)
+#pragma unroll
+      for (int u = 0; u < MX / 16; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[t * (MX / 16) + u] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              gb[(16 * t + i) * STRIDE + 4 * c + g], xb[(16 * u + i) * STRIDE + 4 * c + g],
+              acc[t * (MX / 16) + u], 0, 0, 0);
+  }
+};
+
+__device__ inline shortx4 pack_bf16x4(floatx4 v) {
+  shortx4 s;
+  s[0] = (short)f2bf(v[0]);
+  s[1] = (short)f2bf(v[1]);
+  s[2] = (short)f2bf(v[2]);
+  s[3] = (short)f2bf(v[3]);
+  return s;
+}
+
+template <>
+struct Mma<1> {
+  typedef uint16_t wtype;
+  static constexpr int STRIDE = 20;  // staging row stride (bf16), keeps 8-byte alignment
+  template <int M, int K>
+  __device__ static inline void gemm(const uint16_t* wA, const floatx4* X, floatx4* Out,
+                                     int lane) {
+    constexpr int Q = K / 16;
+    shortx4 xb[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) xb[q] = pack_bf16x4(X[q]);
+#pragma unroll
+    for (int t = 0; t < M / 16; ++t) {
+      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const shortx4 av = *(const shortx4*)(wA + ((t * Q + q) * 64 + lane) * 4);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, xb[q], acc, 0, 0, 0);
+      }
+      Out[t] = acc;
+    }
+  }
+  __device__ static inline void stage(uint16_t* buf, const floatx4* F, int nf, int lane) {
+    const int g = lane >> 4, n = lane & 15;
+    for (int f = 0; f < nf; ++f) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[(16 * f + 4 * g + r) * STRIDE + n] = f2bf(F[f][r]);
+    }
+  }
+  template <int MG, int MX>
+  __device__ static inline void dw(const uint16_t* gb, const uint16_t* xb, floatx4* acc,
+                                   int lane) {
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < MG / 16; ++t) {
+      const shortx4 av = *(const shortx4*)(gb + (16 * t + i) * STRIDE + 4 * g);
+#pragma unroll
+      for (int u = 0; u < MX / 16; ++u) {
+        const shortx4 bv = *(const shortx4*)(xb + (16 * u + i) * STRIDE + 4 * g);
+        acc[t * (MX / 16) + u] =
+            __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t * (MX / 16) + u], 0, 0, 0);
+      }
+    }
+  }
+};
+
+__device__ inline void relu4(floatx4* F, int n) {
+  for (int f = 0; f < n; ++f) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) F[f][r] = F[f][r] > 0.0f ? F[f][r] : 0.0f;
+  }
+}
+
+__device__ inline float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// Loads the encoding of 16 samples (s0 .. s0+15) as K1/16 fragments:
+// fragment q, register r, lane (g, n) = feature 16q + 4g + r of sample s0 + n,
+// feature f = level f/2, component f%2 of the [L][S] float2 buffer.
+template <int K1>
+__device__ inline void load_e(const float2* e, int64_t S, int64_t s, int L, int g, floatx4* E) {
+#pragma unroll
+  for (int q = 0; q < K1 / 16; ++q) {
+    const int l0 = 8 * q + 2 * g, l1 = l0 + 1;
+    const float2 v0 = l0 < L ? e[(int64_t)l0 * S + s] : make_float2(0.0f, 0.0f);
+    const float2 v1 = l1 < L ? e[(int64_t)l1 * S + s] : make_float2(0.0f, 0.0f);
+    E[q][0] = v0.x;
+    E[q][1] = v0.y;
+    E[q][2] = v1.x;
+    E[q][3] = v1.y;
+  }
+}
+
+template <int PREC, int NS, int K1>
+__global__ __launch_bounds__(RM_WG) void k_field(StepArgs a) {
+  typedef Mma<PREC> MM;
+  typedef typename MM::wtype wt;
+  constexpr int NB = NS / 16;             // 16-sample blocks per ray
+  constexpr int SPL = NS > 64 ? NS / 64 : 1;  // samples per lane in the composite
+  constexpr int STG = 64 * MM::STRIDE;    // one staging tile (64 feature rows)
+  constexpr int KQ = K1 / 16;
+
+  __shared__ __align__(16) wt s_w[RM_WPACK];
+  __shared__ __align__(16) wt s_stage[4][2][STG];
+  __shared__ __align__(16) float s_rv[4][NS * 4];
+  __shared__ float s_rec[RM_REC_LOSS + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  const Item it = a.items[blockIdx.x];
+  const StepObj so = a.sobj[it.so];
+  const ObjStatic& ob = a.objs[so.obj];
+  const int L = ob.L, din = ob.din;
+  const int64_t S = a.S;
+  const float invB = 1.0f / (float)so.n_rays;
+  const int mode = a.mode;
+
+  {  // weights of this object into LDS (16-byte copies)
+    const uint4* src = (const uint4*)((PREC ? (const void*)(a.wpack16 + (int64_t)it.so * RM_WPACK)
+                                            : (const void*)(a.wpack32 + (int64_t)it.so * RM_WPACK)));
+    uint4* dst = (uint4*)s_w;
+    constexpr int NV = RM_WPACK * (int)sizeof(wt) / 16;
+    for (int j = tid; j < NV; j += RM_WG) dst[j] = src[j];
+    for (int j = tid; j < RM_REC_LOSS + 1; j += RM_WG) s_rec[j] = 0.0f;
+  }
+  __syncthreads();
+
+  const wt* wF1 = s_w + RM_OFF_F1;
+  const wt* wF2 = s_w + RM_OFF_F2;
+  const wt* wF3 = s_w + RM_OFF_F3;
+  const wt* wF4 = s_w + RM_OFF_F4;
+  const wt* wB4 = s_w + RM_OFF_B4;
+  const wt* wB3 = s_w + RM_OFF_B3;
+  const wt* wB2 = s_w + RM_OFF_B2;
+  const wt* wB1 = s_w + RM_OFF_B1;
+  wt* gbuf = s_stage[wave][0];
+  wt* xbuf = s_stage[wave][1];
+  float* rv = s_rv[wave];
+
+  floatx4 acc1[4 * KQ], acc2[4], acc3[4], acc4[4];
+#pragma unroll
+  for (int j = 0; j < 4 * KQ; ++j) acc1[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    acc2[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    acc3[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    acc4[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  float loss_w = 0.0f;
+
+  for (int rr = wave; rr < it.n_rays; rr += 4) {
+    const int ray = __builtin_amdgcn_readfirstlane(it.ray_begin + rr);
+    const RayRec R = a.rays[ray];
+    if (!ray_active(R.flags)) {
+      if (mode == RM_MODE_FORWARD && lane == 0) {
+        if (a.out_rgb) a.out_rgb[3 * ray] = a.out_rgb[3 * ray + 1] = a.out_rgb[3 * ray + 2] = 0.0f;
+        if (a.out_depth) a.out_depth[ray] = 0.0f;
+        if (a.out_tend) a.out_tend[ray] = 1.0f;
+      }
+      continue;
+    }
+    const int64_t sray = (int64_t)ray * NS;
+
+    // ---- forward: sigma, colour of every sample ----
+    for (int b = 0; b < NB; ++b) {
+      floatx4 E[KQ], H1[4], Y[1], H2[4], Z[1];
+      load_e<K1>(a.e, S, sray + 16 * b + n, L, g, E);
+      MM::template gemm<64, K1>(wF1, E, H1, lane);
+      relu4(H1, 4);
+      MM::template gemm<16, 64>(wF2, H1, Y, lane);
+      MM::template gemm<64, 16>(wF3, Y, H2, lane);
+      relu4(H2, 4);
+      MM::template gemm<16, 64>(wF4, H2, Z, lane);
+      if (g == 0) {
+        float* q = rv + (16 * b + n) * 4;
+        q[0] = Y[0][0];
+        q[1] = sigmoidf_(Z[0][0]);
+        q[2] = sigmoidf_(Z[0][1]);
+        q[3] = sigmoidf_(Z[0][2]);
+      }
+    }
+    wave_lds_sync();
+
+    // ---- volume rendering (Eq. 6) and its adjoint; lane = sample ----
+    {
+      const uint32_t cls = R.flags & RM_F_CLS;
+      const bool bg = (mode == RM_MODE_TRAIN) && cls == RM_CLS_BACKGROUND;
+      const bool valid = lane * SPL < NS;
+      float y0[SPL], c[SPL][3], sig[SPL], tau[SPL], dist[SPL], w[SPL], Sx[SPL];
+      float lane_tau = 0.0f, lane_sig = 0.0f;
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        const int i = lane * SPL + j;
+        if (valid) {
+          const float* q = rv + i * 4;
+          y0[j] = q[0];
+          c[j][0] = q[1];
+          c[j][1] = q[2];
+          c[j][2] = q[3];
+          sig[j] = expf(fminf(y0[j], 15.0f));
+          tau[j] = sig[j] * R.delta;
+          dist[j] = R.tn + ((float)i + 0.5f) * R.delta;
+        } else {
+          y0[j] = 0.0f;
+          c[j][0] = c[j][1] = c[j][2] = 0.0f;
+          sig[j] = tau[j] = dist[j] = 0.0f;
+        }
+        lane_tau += tau[j];
+        lane_sig += sig[j];
+      }
+      const float P = wave_excl_prefix(lane_tau, lane);
+      float run = P;
+      float lc[3] = {0.0f, 0.0f, 0.0f}, ld = 0.0f;
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        Sx[j] = run;
+        const float T = expf(-run);
+        const float alpha = -expm1f(-tau[j]);
+        w[j] = valid ? T * alpha : 0.0f;
+        run += tau[j];
+        lc[0] = fmaf(w[j], c[j][0], lc[0]);
+        lc[1] = fmaf(w[j], c[j][1], lc[1]);
+        lc[2] = fmaf(w[j], c[j][2], lc[2]);
+        ld = fmaf(w[j], dist[j], ld);
+      }
+      float Ch[3];
+      Ch[0] = wave_sum(lc[0]);
+      Ch[1] = wave_sum(lc[1]);
+      Ch[2] = wave_sum(lc[2]);
+      const float Dh = wave_sum(ld);
+      const float Stot = wave_sum(lane_tau);
+      const float Tend = expf(-Stot);
+
+      if (mode == RM_MODE_FORWARD) {
+        if (lane == 0) {
+          if (a.out_rgb) {
+            a.out_rgb[3 * ray] = Ch[0];
+            a.out_rgb[3 * ray + 1] = Ch[1];
+            a.out_rgb[3 * ray + 2] = Ch[2];
+          }
+          if (a.out_depth) a.out_depth[ray] = Dh;
+          if (a.out_tend) a.out_tend[ray] = Tend;
+        }
+        continue;
+      }
+
+      float gC[3], gD = 0.0f, gT = 0.0f, dens = 0.0f;
+      if (mode == RM_MODE_TRAIN) {
+        // Eq. 7-11: squared colour error against the image (object rays) or
+        // against the random colour with residual transmittance (background
+        // rays), L1 depth term, density term on every background sample.
+        float Co[3], l = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          Co[k] = bg ? fmaf(Tend, R.tgt[k], Ch[k]) : Ch[k];
+          const float df = Co[k] - R.tgt[k];
+          l = fmaf(df, df, l);
+          gC[k] = 2.0f * df * invB;
+        }
+        if (!bg && (R.flags & RM_F_DEPTH)) {
+          const float dd = Dh - R.D;
+          l += a.lambda_depth * fabsf(dd);
+          gD = a.lambda_depth * (dd > 0.0f ? 1.0f : (dd < 0.0f ? -1.0f : 0.0f)) * invB;
+        }
+        if (bg) {
+          l += a.lambda_density * wave_sum(lane_sig);
+          dens = a.lambda_density * invB;
+        }
+        loss_w += l * invB;
+      } else {  // RM_MODE_ADJOINT
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gC[k] = a.adj_rgb ? a.adj_rgb[3 * ray + k] : 0.0f;
+        gD = a.adj_depth ? a.adj_depth[ray] : 0.0f;
+        gT = a.adj_tend ? a.adj_tend[ray] : 0.0f;
+      }
+      // suffix sums  sum_{j > i} w_j c_j  and  sum_{j > i} w_j d_j
+      const float Qc0 = wave_excl_suffix(lc[0], lane);
+      const float Qc1 = wave_excl_suffix(lc[1], lane);
+      const float Qc2 = wave_excl_suffix(lc[2], lane);
+      const float Qd = wave_excl_suffix(ld, lane);
+      float sc[3] = {Qc0, Qc1, Qc2}, sd = Qd;
+      float bgterm = 0.0f;
+      if (bg) bgterm = Tend * (gC[0] * R.tgt[0] + gC[1] * R.tgt[1] + gC[2] * R.tgt[2]);
+#pragma unroll
+      for (int j = SPL - 1; j >= 0; --j) {
+        const int i = lane * SPL + j;
+        const float Tn = expf(-(Sx[j] + tau[j]));
+        float dtau = gC[0] * (Tn * c[j][0] - sc[0]) + gC[1] * (Tn * c[j][1] - sc[1]) +
+                     gC[2] * (Tn * c[j][2] - sc[2]) + gD * (Tn * dist[j] - sd) - bgterm -
+                     gT * Tend;
+        const float dsig = dtau * R.delta + dens;
+        sc[0] = fmaf(w[j], c[j][0], sc[0]);
+        sc[1] = fmaf(w[j], c[j][1], sc[1]);
+        sc[2] = fmaf(w[j], c[j][2], sc[2]);
+        sd = fmaf(w[j], dist[j], sd);
+        if (valid) {
+          float* q = rv + i * 4;
+          q[0] = y0[j] < 15.0f ? dsig * sig[j] : 0.0f;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) q[1 + k] = w[j] * gC[k] * c[j][k] * (1.0f - c[j][k]);
+        }
+      }
+    }
+    wave_lds_sync();
+
+    // ---- backward: recompute activations per block, adjoints, dW ----
+    for (int b = 0; b < NB; ++b) {
+      const int64_t s = sray + 16 * b + n;
+      floatx4 E[KQ], H1[4], Y[1], H2[4];
+      load_e<K1>(a.e, S, s, L, g, E);
+      MM::template gemm<64, K1>(wF1, E, H1, lane);
+      relu4(H1, 4);
+      MM::template gemm<16, 64>(wF2, H1, Y, lane);
+      MM::template gemm<64, 16>(wF3, Y, H2, lane);
+      relu4(H2, 4);
+      floatx4 dZ[1], dH2[4], dY[1], dH1[4], dE[KQ];
+      float dy0 = 0.0f;
+      if (g == 0) {
+        const float* q = rv + (16 * b + n) * 4;
+        dy0 = q[0];
+        dZ[0] = floatx4{q[1], q[2], q[3], 0.0f};
+      } else {
+        dZ[0] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+      // colour head: dW4 += dZ^T H2, dH2 = W4^T dZ masked by ReLU
+      MM::stage(gbuf, dZ, 1, lane);
+      MM::stage(xbuf, H2, 4, lane);
+      wave_lds_sync();
+      MM::template dw<16, 64>(gbuf, xbuf, acc4, lane);
+      wave_lds_sync();
+      MM::template gemm<64, 16>(wB4, dZ, dH2, lane);
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dH2[f][r] = H2[f][r] > 0.0f ? dH2[f][r] : 0.0f;
+      // dW3 += dH2^T Y, dY = W3^T dH2 (+ density adjoint in row 0)
+      MM::stage(gbuf, dH2, 4, lane);
+      MM::stage(xbuf, Y, 1, lane);
+      wave_lds_sync();
+      MM::template dw<64, 16>(gbuf, xbuf, acc3, lane);
+      wave_lds_sync();
+      MM::template gemm<16, 64>(wB3, dH2, dY, lane);
+      if (g == 0) dY[0][0] += dy0;
+      // dW2 += dY^T H1, dH1 = W2^T dY masked
+      MM::stage(gbuf, dY, 1, lane);
+      MM::stage(xbuf, H1, 4, lane);
+      wave_lds_sync();
+      MM::template dw<16, 64>(gbuf, xbuf, acc2, lane);
+      wave_lds_sync();
+      MM::template gemm<64, 16>(wB2, dY, dH1, lane);
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dH1[f][r] = H1[f][r] > 0.0f ? dH1[f][r] : 0.0f;
+      // dW1 += dH1^T E, dE = W1^T dH1
+      MM::stage(gbuf, dH1, 4, lane);
+      MM::stage(xbuf, E, KQ, lane);
+      wave_lds_sync();
+      MM::template dw<64, K1>(gbuf, xbuf, acc1, lane);
+      wave_lds_sync();
+      MM::template gemm<K1, 64>(wB1, dH1, dE, lane);
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        const int l0 = 8 * q + 2 * g, l1 = l0 + 1;
+        if (l0 < L) a.de[(int64_t)l0 * S + s] = make_float2(dE[q][0], dE[q][1]);
+        if (l1 < L) a.de[(int64_t)l1 * S + s] = make_float2(dE[q][2], dE[q][3]);
+      }
+    }
+  }
+
+  // ---- work-item record: weight gradients in parameter order, and loss ----
+  if (mode != RM_MODE_FORWARD) {
+    const int o2 = RM_HIDDEN * din, o3 = o2 + RM_DOUT * RM_HIDDEN, o4 = o3 + RM_HIDDEN * RM_GEO;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * g + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < KQ; ++u) {
+          const int m = 16 * t + row, k = 16 * u + n;
+          if (k < din) atomicAdd(&s_rec[m * din + k], acc1[t * KQ + u][r]);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) atomicAdd(&s_rec[o2 + row * RM_HIDDEN + 16 * u + n], acc2[u][r]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (n >= 1) atomicAdd(&s_rec[o3 + (16 * t + row) * RM_GEO + (n - 1)], acc3[t][r]);
+      if (row < 3)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) atomicAdd(&s_rec[o4 + row * RM_HIDDEN + 16 * u + n], acc4[u][r]);
+    }
+    if (lane == 0) atomicAdd(&s_rec[RM_REC_LOSS], loss_w);
+    __syncthreads();
+    float* rec = a.partials + (int64_t)blockIdx.x * RM_REC_STRIDE;
+    for (int j = tid; j < RM_REC_LOSS + 1; j += RM_WG) rec[j] = s_rec[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K5: per-object MLP gradient (sum of the work-item records in item order,
+// deterministic) and loss; advances the Adam step counter.
+__global__ __launch_bounds__(256) void k_reduce(StepArgs a) {
+  const StepObj so = a.sobj[blockIdx.y];
+  const ObjStatic& ob = a.objs[so.obj];
+  const int nm = (int)(ob.P - ob.P_grid);
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  float* gdst = a.grad_override ? a.grad_override : ob.grad;
+  if (j < nm) {
+    float s = 0.0f;
+    for (int it = so.item_begin; it < so.item_end; ++it)
+      s += a.partials[(int64_t)it * RM_REC_STRIDE + j];
+    gdst[ob.P_grid + j] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.mode == RM_MODE_TRAIN) {
+    float l = 0.0f;
+    for (int it = so.item_begin; it < so.item_end; ++it)
+      l += a.partials[(int64_t)it * RM_REC_STRIDE + RM_REC_LOSS];
+    ObjState* st = a.state + so.obj;
+    st->loss_acc += l;
+    st->n_loss += 1;
+    if (a.advance) {
+      const int k = st->step + 1;
+      st->step = k;
+      st->bc1 = (float)(1.0 - pow((double)a.beta1, (double)k));
+      st->bc2 = (float)(1.0 - pow((double)a.beta2, (double)k));
+    }
+  }
+}
+
+// K7: dense Adam over every parameter of the step's objects; zeroes the
+// gradient for the next step.
+__global__ __launch_bounds__(256) void k_adam(StepArgs a) {
+  const Chunk ch = a.chunks[blockIdx.x];
+  const ObjStatic& ob = a.objs[ch.obj];
+  const float bc1 = a.state[ch.obj].bc1, bc2 = a.state[ch.obj].bc2;
+  const float b1 = a.beta1, b2 = a.beta2, lr = a.lr, eps = a.eps;
+  const float ob1 = 1.0f - b1, ob2 = 1.0f - b2;
+  int64_t end = ch.begin + RM_ADAM_CHUNK;
+  if (end > ob.P_alloc) end = ob.P_alloc;
+  for (int64_t i = ch.begin + 4 * (int64_t)threadIdx.x; i < end; i += 4 * (int64_t)blockDim.x) {
+    float4 p = *(const float4*)(ob.params + i);
+    float4 gr = *(const float4*)(ob.grad + i);
+    float4 m = *(const float4*)(ob.m + i);
+    float4 v = *(const float4*)(ob.v + i);
+    float* pp = &p.x;
+    float* gg = &gr.x;
+    float* mm = &m.x;
+    float* vv = &v.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      mm[k] = b1 * mm[k] + ob1 * gg[k];
+      vv[k] = b2 * vv[k] + ob2 * (gg[k] * gg[k]);
+      pp[k] -= lr * (mm[k] / bc1) / (sqrtf(vv[k] / bc2) + eps);
+    }
+    *(float4*)(ob.params + i) = p;
+    *(float4*)(ob.m + i) = m;
+    *(float4*)(ob.v + i) = v;
+    *(float4*)(ob.grad + i) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// density at object-frame points (meshing): encode + density head on VALU
+__global__ __launch_bounds__(256) void k_query_density(const ObjStatic* objs, int obj,
+                                                       const float* xyz, int64_t n, float* sigma) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const ObjStatic& ob = objs[obj];
+  float p[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float q = (xyz[3 * t + k] + ob.half[k]) / (ob.half[k] + ob.half[k]);
+    p[k] = fminf(fmaxf(q, 0.0f), 1.0f);
+  }
+  float e[2 * RM_MAX_LEVELS];
+  for (int l = 0; l < ob.L; ++l) {
+    Cell cl;
+    make_cell(p, ob.N_l[l], cl);
+    const bool hashed = (ob.hashed_mask >> l) & 1u;
+    const float* G = ob.params + ob.off[l];
+    float ex = 0.0f, ey = 0.0f;
+    for (int b = 0; b < 8; ++b) {
+      const uint32_t id = corner_index(cl, b, ob.N_l[l], ob.T_l[l], hashed);
+      const float w = corner_weight(cl, b);
+      ex = fmaf(w, G[2 * (int64_t)id], ex);
+      ey = fmaf(w, G[2 * (int64_t)id + 1], ey);
+    }
+    e[2 * l] = ex;
+    e[2 * l + 1] = ey;
+  }
+  const float* W1 = ob.params + ob.P_grid;
+  const float* W2 = W1 + RM_HIDDEN * ob.din;
+  float y0 = 0.0f;
+  for (int h = 0; h < RM_HIDDEN; ++h) {
+    float s = 0.0f;
+    for (int k = 0; k < ob.din; ++k) s = fmaf(W1[h * ob.din + k], e[k], s);
+    y0 = fmaf(W2[h], s > 0.0f ? s : 0.0f, y0);
+  }
+  sigma[t] = expf(fminf(y0, 15.0f));
+}
+
+__global__ __launch_bounds__(256) void k_debug_encode(const ObjStatic* objs, int obj,
+                                                      const float* pts, int64_t n, uint32_t* idx,
+                                                      float* feat) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const ObjStatic& ob = objs[obj];
+  const float p[3] = {pts[3 * t], pts[3 * t + 1], pts[3 * t + 2]};
+  for (int l = 0; l < ob.L; ++l) {
+    Cell cl;
+    make_cell(p, ob.N_l[l], cl);
+    const bool hashed = (ob.hashed_mask >> l) & 1u;
+    const float* G = ob.params + ob.off[l];
+    float ex = 0.0f, ey = 0.0f;
+    for (int b = 0; b < 8; ++b) {
+      const uint32_t id = corner_index(cl, b, ob.N_l[l], ob.T_l[l], hashed);
+      const float w = corner_weight(cl, b);
+      if (idx) idx[(t * ob.L + l) * 8 + b] = id;
+      ex = fmaf(w, G[2 * (int64_t)id], ex);
+      ey = fmaf(w, G[2 * (int64_t)id + 1], ey);
+    }
+    if (feat) {
+      feat[(t * ob.L + l) * 2] = ex;
+      feat[(t * ob.L + l) * 2 + 1] = ey;
+    }
+  }
+}
+
+// parameter initialisation: grid U(-1e-4, 1e-4), MLP Glorot-uniform, each
+// value drawn from Philox with counter (index, kind, 0xFFFFFFFF, 0)
+__global__ __launch_bounds__(256) void k_init_params(float* params, int64_t P_grid, int din,
+                                                     uint32_t k0, uint32_t k1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n1 = (int64_t)RM_HIDDEN * din, n2 = n1 + RM_DOUT * RM_HIDDEN;
+  const int64_t n3 = n2 + RM_HIDDEN * RM_GEO, n4 = n3 + 3 * RM_HIDDEN;
+  if (i >= P_grid + n4) return;
+  uint32_t kind;
+  float lim;
+  if (i < P_grid) {
+    kind = 0u;
+    lim = 1e-4f;
+  } else {
+    const int64_t j = i - P_grid;
+    if (j < n1) { kind = 1u; lim = sqrtf(6.0f / (float)(RM_HIDDEN + din)); }
+    else if (j < n2) { kind = 2u; lim = sqrtf(6.0f / (float)(RM_DOUT + RM_HIDDEN)); }
+    else if (j < n3) { kind = 3u; lim = sqrtf(6.0f / (float)(RM_HIDDEN + RM_GEO)); }
+    else { kind = 4u; lim = sqrtf(6.0f / (float)(3 + RM_HIDDEN)); }
+  }
+  uint32_t x[4];
+  philox4x32_10((uint32_t)i, kind, 0xFFFFFFFFu, 0u, k0, k1, x);
+  const float u = (float)(x[0] >> 8) * (1.0f / 16777216.0f);
+  params[i] = (2.0f * u - 1.0f) * lim;
+}
+
+// sample positions of a launch's rays (inspection)
+template <int NS>
+__global__ __launch_bounds__(256) void k_debug_positions(StepArgs a, float* pos) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.S) return;
+  const RayRec R = a.rays[s / NS];
+  float p[3] = {0.0f, 0.0f, 0.0f};
+  if (R.flags & RM_F_HIT) sample_pos(R, (int)(s % NS), a.objs[R.obj].half, p);
+  pos[3 * s] = p[0];
+  pos[3 * s + 1] = p[1];
+  pos[3 * s + 2] = p[2];
+}
+
+// clears the per-object loss accumulators of a launch's objects
+__global__ void k_reset_loss(StepArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_sobj) return;
+  ObjState* st = a.state + a.sobj[i].obj;
+  st->loss_acc = 0.0f;
+  st->n_loss = 0;
+}
+
+__global__ void k_fill(float* x, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+#define RM_NS_SWITCH(NS, CALL)              \
+  switch (NS) {                             \
+    case 32: { constexpr int NSC = 32; CALL; break; }   \
+    case 64: { constexpr int NSC = 64; CALL; break; }   \
+    case 128: { constexpr int NSC = 128; CALL; break; } \
+    default: return hipErrorInvalidValue;   \
+  }
+
+hipError_t rm_launch_raygen(const StepArgs& a, int NS, hipStream_t st) {
+  if (a.n_rays <= 0) return hipSuccess;
+  RM_NS_SWITCH(NS, (k_raygen<NSC><<<cdiv(a.n_rays, 256), 256, 0, st>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int L, int block, hipStream_t st) {
+  if (a.S <= 0) return hipSuccess;
+  dim3 grid(cdiv(a.S, block), L);
+  RM_NS_SWITCH(NS, (k_encode_fwd<NSC><<<grid, block, 0, st>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_encode_bwd(const StepArgs& a, int NS, int L, int block, hipStream_t st) {
+  if (a.S <= 0) return hipSuccess;
+  dim3 grid(cdiv(a.S, block), L);
+  RM_NS_SWITCH(NS, (k_encode_bwd<NSC><<<grid, block, 0, st>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st) {
+  if (a.n_sobj <= 0) return hipSuccess;
+  k_pack<<<a.n_sobj, 256, 0, st>>>(a, K1);
+  return hipGetLastError();
+}
+
+template <int PREC, int K1>
+static hipError_t launch_field_k(const StepArgs& a, int NS, hipStream_t st) {
+  RM_NS_SWITCH(NS, (k_field<PREC, NSC, K1><<<a.n_items, RM_WG, 0, st>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStream_t st) {
+  if (a.n_items <= 0) return hipSuccess;
+  if (K1 == 16) return prec ? launch_field_k<1, 16>(a, NS, st) : launch_field_k<0, 16>(a, NS, st);
+  if (K1 == 32) return prec ? launch_field_k<1, 32>(a, NS, st) : launch_field_k<0, 32>(a, NS, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st) {
+  if (a.n_sobj <= 0) return hipSuccess;
+  dim3 grid(cdiv(n_mlp_max, 256), a.n_sobj);
+  k_reduce<<<grid, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_adam(const StepArgs& a, hipStream_t st) {
+  if (a.n_chunks <= 0) return hipSuccess;
+  k_adam<<<a.n_chunks, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_camera_rays(const StepArgs& a, int NS, const float* M, const float* c,
+                                 float fx, float fy, float cx, float cy, int W, int pix0,
+                                 hipStream_t st) {
+  if (a.n_rays <= 0) return hipSuccess;
+  CamArgs ca;
+  for (int k = 0; k < 9; ++k) ca.M[k] = M[k];
+  for (int k = 0; k < 3; ++k) ca.c[k] = c[k];
+  ca.fx = fx;
+  ca.fy = fy;
+  ca.cx = cx;
+  ca.cy = cy;
+  ca.W = W;
+  ca.pix0 = pix0;
+  RM_NS_SWITCH(NS, (k_camera_rays<NSC><<<cdiv(a.n_rays, 256), 256, 0, st>>>(a, ca)));
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_user_rays(const StepArgs& a, int NS, const float* rays, hipStream_t st) {
+  if (a.n_rays <= 0) return hipSuccess;
+  RM_NS_SWITCH(NS, (k_user_rays<NSC><<<cdiv(a.n_rays, 256), 256, 0, st>>>(a, rays)));
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_query_density(const ObjStatic* objs, int obj, const float* xyz, int64_t n,
+                                   float* sigma, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_query_density<<<cdiv(n, 256), 256, 0, st>>>(objs, obj, xyz, n, sigma);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_debug_encode(const ObjStatic* objs, int obj, const float* p, int64_t n,
+                                  uint32_t* idx, float* feat, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_debug_encode<<<cdiv(n, 256), 256, 0, st>>>(objs, obj, p, n, idx, feat);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_init(float* params, int64_t P_grid, int din, uint32_t k0, uint32_t k1,
+                          hipStream_t st) {
+  const int64_t n = P_grid + (int64_t)RM_HIDDEN * din + RM_DOUT * RM_HIDDEN + RM_HIDDEN * RM_GEO +
+                    3 * RM_HIDDEN;
+  k_init_params<<<cdiv(n, 256), 256, 0, st>>>(params, P_grid, din, k0, k1);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_debug_positions(const StepArgs& a, int NS, float* pos, hipStream_t st) {
+  if (a.S <= 0) return hipSuccess;
+  RM_NS_SWITCH(NS, (k_debug_positions<NSC><<<cdiv(a.S, 256), 256, 0, st>>>(a, pos)));
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_reset_loss(const StepArgs& a, hipStream_t st) {
+  if (a.n_sobj <= 0) return hipSuccess;
+  k_reset_loss<<<cdiv(a.n_sobj, 64), 64, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_fill(float* x, int64_t n, float v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill<<<cdiv(n, 256), 256, 0, st>>>(x, n, v);
+  return hipGetLastError();
+}

@@ -1,0 +1,1484 @@
+// romap_runtime.hip -- host side of libromap: the C ABI of include/romap.h.
+//
+// Owns the context: object registry (one hash-grid + MLP model per object
+// instance, Sec. V), keyframe store with the view-angle rule of Eq. 5
+// (Sec. V-A "Data"), per-step work lists covering every object of a step,
+// hipGraph capture/replay of a step, the tile autotuner, and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/romap.h"
+#include "romap_device.h"
+
+namespace {
+
+std::string g_create_error;
+
+struct HostKf {
+  romap_camera cam;
+  uint8_t* d_rgb = nullptr;
+  int32_t* d_mask = nullptr;
+  float* d_depth = nullptr;
+  std::vector<int32_t> h_mask;  // candidate rectangles of later-registered objects are not
+                                // computed (keyframes join only objects registered before them)
+};
+
+struct HostObj {
+  int id = 0, instance = 0, log2T = 0, active = 1;
+  romap_box box{};
+  int L = 0, din = 0;
+  int64_t P = 0, P_grid = 0, P_alloc = 0;
+  int64_t off[RM_MAX_LEVELS + 1]{};
+  uint32_t N_l[RM_MAX_LEVELS]{}, T_l[RM_MAX_LEVELS]{};
+  uint32_t hashed_mask = 0;
+  float* d_block = nullptr;  // params | grad | m | v, P_alloc floats each
+  std::vector<KfRef> kfs;
+  KfRef* d_kfs = nullptr;
+  size_t d_kfs_cap = 0;
+  int64_t n_cand = 0;
+  bool has_last = false;
+  double last_centre[3]{};
+};
+
+struct Plan {                 // one launch: its objects, rays and work lists
+  std::vector<StepObj> sobj;
+  std::vector<Item> items;
+  std::vector<Chunk> chunks;
+  int n_rays = 0;
+  int64_t S = 0;
+  int rays_per_item = 8;
+  int enc_block = 256;
+  size_t off_sobj = 0, off_items = 0, off_chunks = 0;  // in the device table arena (bytes)
+};
+
+template <class T>
+hipError_t grow(T** p, size_t* cap, size_t need) {
+  if (need <= *cap && *p) return hipSuccess;
+  size_t n = std::max(need, *cap * 2);
+  if (n == 0) n = 1;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    if (e != hipSuccess) return e;
+    *p = nullptr;
+  }
+  *cap = 0;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e == hipSuccess) *cap = n;
+  return e;
+}
+
+}  // namespace
+
+struct romap_ctx {
+  romap_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<HostObj> objs;
+  std::vector<HostKf> kfs;
+  ObjStatic* d_objs = nullptr;
+  size_t cap_objs = 0;
+  ObjState* d_state = nullptr;
+  size_t cap_state = 0;
+  KfDev* d_kfdev = nullptr;
+  size_t cap_kfdev = 0;
+  // scratch of a step
+  RayRec* d_rays = nullptr;
+  size_t cap_rays = 0;
+  float2* d_e = nullptr;
+  float2* d_de = nullptr;
+  size_t cap_e = 0, cap_de = 0;
+  float* d_partials = nullptr;
+  size_t cap_partials = 0;
+  float* d_wpack32 = nullptr;
+  uint16_t* d_wpack16 = nullptr;
+  size_t cap_w32 = 0, cap_w16 = 0;
+  char* d_tables = nullptr;
+  size_t cap_tables = 0;
+  // graph of the last batched step
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> gsig;
+  // autotuner results keyed by the work signature
+  std::map<std::vector<int64_t>, std::pair<int, int>> tuned;
+  // per-kernel timing of the last profiled train call
+  hipEvent_t pev[ROMAP_N_PHASES + 1] = {};
+  double phase_ms[ROMAP_N_PHASES] = {};
+  int phase_steps = 0;
+  std::string err;
+};
+
+namespace {
+
+romap_status fail(romap_ctx* c, romap_status code, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, ROMAP_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define HIPALLOC(ctx, expr)                                                                \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation)                      \
+      return fail(ctx, ROMAP_E_OUT_OF_MEMORY, std::string(#expr) + ": out of memory");     \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, ROMAP_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+bool is_fin(float x) { return std::isfinite(x); }
+
+// Level table of the hash encoding: N_l = floor(N_min b^l + 1e-6) with
+// b = exp((ln N_max - ln N_min)/(L - 1)); dense 1:1 when (N_l+1)^3 <= T.
+void make_levels(const romap_config& cfg, int log2T, HostObj& o) {
+  const int L = cfg.n_levels;
+  double b = 1.0;
+  if (L > 1) b = std::exp((std::log((double)cfg.max_res) - std::log((double)cfg.base_res)) / (double)(L - 1));
+  const int64_t T = (int64_t)1 << log2T;
+  int64_t off = 0;
+  o.hashed_mask = 0;
+  for (int l = 0; l < L; ++l) {
+    const int N = L > 1 ? (int)std::floor((double)cfg.base_res * std::pow(b, (double)l) + 1e-6) : cfg.base_res;
+    const int64_t dense = (int64_t)(N + 1) * (N + 1) * (N + 1);
+    const bool hashed = dense > T;
+    o.N_l[l] = (uint32_t)N;
+    o.T_l[l] = (uint32_t)(hashed ? T : dense);
+    if (hashed) o.hashed_mask |= 1u << l;
+    o.off[l] = off;
+    off += 2 * (int64_t)o.T_l[l];
+  }
+  o.off[L] = off;
+  o.L = L;
+  o.din = 2 * L;
+  o.P_grid = off;
+  o.P = off + (int64_t)RM_HIDDEN * o.din + RM_DOUT * RM_HIDDEN + RM_HIDDEN * RM_GEO + 3 * RM_HIDDEN;
+  o.P_alloc = (o.P + 63) / 64 * 64;
+}
+
+// Camera -> object frame: with R = Rz(yaw), M = R^T R_wc, c = R^T (t_wc - t),
+// computed in FP64 and rounded once.
+void object_frame(const float* Twc, const romap_box& bx, float* M, float* c) {
+  const double ct = std::cos((double)bx.yaw), st = std::sin((double)bx.yaw);
+  for (int j = 0; j < 3; ++j) {
+    const double r0 = (double)Twc[j], r1 = (double)Twc[4 + j], r2 = (double)Twc[8 + j];
+    M[j] = (float)(ct * r0 + st * r1);
+    M[3 + j] = (float)(-st * r0 + ct * r1);
+    M[6 + j] = (float)r2;
+  }
+  const double dx = (double)Twc[3] - (double)bx.t[0];
+  const double dy = (double)Twc[7] - (double)bx.t[1];
+  const double dz = (double)Twc[11] - (double)bx.t[2];
+  c[0] = (float)(ct * dx + st * dy);
+  c[1] = (float)(-st * dx + ct * dy);
+  c[2] = (float)dz;
+}
+
+// Detection box of an instance: bounding box of its mask pixels widened by
+// margin_pct percent of its size per side (integer ceiling), clamped.
+bool candidate_rect(const int32_t* mask, int W, int H, int instance, int margin_pct, int r[4]) {
+  int xmin = W, xmax = -1, ymin = H, ymax = -1;
+  for (int y = 0; y < H; ++y) {
+    const int32_t* row = mask + (int64_t)y * W;
+    for (int x = 0; x < W; ++x)
+      if (row[x] == instance) {
+        xmin = std::min(xmin, x);
+        xmax = std::max(xmax, x);
+        ymin = std::min(ymin, y);
+        ymax = std::max(ymax, y);
+      }
+  }
+  if (xmax < 0) return false;
+  const int w0 = xmax - xmin + 1, h0 = ymax - ymin + 1;
+  const int mx = (w0 * margin_pct + 99) / 100, my = (h0 * margin_pct + 99) / 100;
+  const int x0 = std::max(0, xmin - mx), y0 = std::max(0, ymin - my);
+  const int x1 = std::min(W - 1, xmax + mx), y1 = std::min(H - 1, ymax + my);
+  r[0] = x0;
+  r[1] = y0;
+  r[2] = x1 - x0 + 1;
+  r[3] = y1 - y0 + 1;
+  return true;
+}
+
+ObjStatic to_static(const HostObj& o) {
+  ObjStatic s{};
+  s.params = o.d_block;
+  s.grad = o.d_block + o.P_alloc;
+  s.m = o.d_block + 2 * o.P_alloc;
+  s.v = o.d_block + 3 * o.P_alloc;
+  s.P = o.P;
+  s.P_grid = o.P_grid;
+  s.P_alloc = o.P_alloc;
+  for (int l = 0; l <= RM_MAX_LEVELS; ++l) s.off[l] = o.off[l];
+  for (int l = 0; l < RM_MAX_LEVELS; ++l) {
+    s.N_l[l] = o.N_l[l];
+    s.T_l[l] = o.T_l[l];
+  }
+  s.hashed_mask = o.hashed_mask;
+  s.L = o.L;
+  s.din = o.din;
+  s.instance = o.instance;
+  s.id = o.id;
+  s.n_kf = (int)o.kfs.size();
+  for (int k = 0; k < 3; ++k) s.half[k] = o.box.half[k];
+  s.kfs = o.d_kfs;
+  s.n_cand = o.n_cand;
+  return s;
+}
+
+romap_status upload_object(romap_ctx* c, int id) {
+  HostObj& o = c->objs[id];
+  if (!o.kfs.empty()) {
+    if (o.kfs.size() > o.d_kfs_cap) {
+      size_t cap = o.d_kfs_cap;
+      HIPALLOC(c, grow(&o.d_kfs, &cap, o.kfs.size()));
+      o.d_kfs_cap = cap;
+    }
+    HIPCHK(c, hipMemcpyAsync(o.d_kfs, o.kfs.data(), o.kfs.size() * sizeof(KfRef),
+                             hipMemcpyHostToDevice, c->stream));
+  }
+  ObjStatic s = to_static(o);
+  HIPCHK(c, hipMemcpyAsync(c->d_objs + id, &s, sizeof(s), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ROMAP_OK;
+}
+
+int K1_of(const romap_config& cfg) { return 2 * cfg.n_levels <= 16 ? 16 : 32; }
+
+StepArgs base_args(romap_ctx* c) {
+  StepArgs a{};
+  a.objs = c->d_objs;
+  a.state = c->d_state;
+  a.kfs = c->d_kfdev;
+  a.rays = c->d_rays;
+  a.e = c->d_e;
+  a.de = c->d_de;
+  a.partials = c->d_partials;
+  a.wpack32 = c->d_wpack32;
+  a.wpack16 = c->d_wpack16;
+  a.seed_lo = (uint32_t)c->cfg.seed;
+  a.seed_hi = (uint32_t)(c->cfg.seed >> 32);
+  a.lambda_depth = c->cfg.lambda_depth;
+  a.lambda_density = c->cfg.lambda_density;
+  a.lr = c->cfg.lr;
+  a.beta1 = c->cfg.beta1;
+  a.beta2 = c->cfg.beta2;
+  a.eps = c->cfg.eps;
+  a.mode = RM_MODE_TRAIN;
+  a.advance = 1;
+  return a;
+}
+
+void build_items(Plan& p) {
+  p.items.clear();
+  for (size_t i = 0; i < p.sobj.size(); ++i) {
+    StepObj& so = p.sobj[i];
+    so.item_begin = (int)p.items.size();
+    for (int r = 0; r < so.n_rays; r += p.rays_per_item) {
+      Item it{};
+      it.so = (int)i;
+      it.ray_begin = so.ray_begin + r;
+      it.n_rays = std::min(p.rays_per_item, so.n_rays - r);
+      p.items.push_back(it);
+    }
+    so.item_end = (int)p.items.size();
+  }
+}
+
+// Builds the work lists of a launch over (object, rays) pairs.
+void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int rays_per_item,
+                int enc_block, Plan& p) {
+  p = Plan();
+  p.rays_per_item = rays_per_item;
+  p.enc_block = enc_block;
+  int ray = 0;
+  for (auto& pr : list) {
+    StepObj so{};
+    so.obj = pr.first;
+    so.n_rays = pr.second;
+    so.ray_begin = ray;
+    ray += pr.second;
+    p.sobj.push_back(so);
+    const HostObj& o = c->objs[pr.first];
+    for (int64_t b = 0; b < o.P_alloc; b += RM_ADAM_CHUNK) {
+      Chunk ch{};
+      ch.obj = pr.first;
+      ch.begin = b;
+      p.chunks.push_back(ch);
+    }
+  }
+  p.n_rays = ray;
+  p.S = (int64_t)ray * c->cfg.samples_per_ray;
+  build_items(p);
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Makes sure the scratch buffers fit a set of plans, then uploads their
+// work tables into the table arena.
+romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
+  size_t max_rays = 0, max_items = 0, max_sobj = 0, tab = 0;
+  int64_t max_S = 0;
+  for (Plan* p : plans) {
+    max_rays = std::max(max_rays, (size_t)p->n_rays);
+    max_items = std::max(max_items, p->items.size());
+    max_sobj = std::max(max_sobj, p->sobj.size());
+    max_S = std::max(max_S, p->S);
+    p->off_sobj = tab;
+    tab += align256(p->sobj.size() * sizeof(StepObj));
+    p->off_items = tab;
+    tab += align256(p->items.size() * sizeof(Item));
+    p->off_chunks = tab;
+    tab += align256(p->chunks.size() * sizeof(Chunk));
+  }
+  const size_t L = (size_t)c->cfg.n_levels;
+  auto regrow = [&](auto** ptr, size_t* cap, size_t need) -> hipError_t {
+    if (need <= *cap) return hipSuccess;
+    // a reallocation invalidates the captured graph
+    if (c->gexec) {
+      hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+      c->gsig.clear();
+    }
+    return grow(ptr, cap, need);
+  };
+  HIPALLOC(c, regrow(&c->d_rays, &c->cap_rays, std::max<size_t>(max_rays, 1)));
+  HIPALLOC(c, regrow(&c->d_e, &c->cap_e, std::max<size_t>(L * (size_t)max_S, 1)));
+  HIPALLOC(c, regrow(&c->d_de, &c->cap_de, std::max<size_t>(L * (size_t)max_S, 1)));
+  HIPALLOC(c, regrow(&c->d_partials, &c->cap_partials, std::max<size_t>(max_items * RM_REC_STRIDE, 1)));
+  HIPALLOC(c, regrow(&c->d_wpack32, &c->cap_w32, std::max<size_t>(max_sobj * RM_WPACK, 1)));
+  HIPALLOC(c, regrow(&c->d_wpack16, &c->cap_w16, std::max<size_t>(max_sobj * RM_WPACK, 1)));
+  HIPALLOC(c, regrow(&c->d_tables, &c->cap_tables, std::max<size_t>(tab, 256)));
+  std::vector<char> h(tab);
+  for (Plan* p : plans) {
+    if (!p->sobj.empty()) std::memcpy(h.data() + p->off_sobj, p->sobj.data(), p->sobj.size() * sizeof(StepObj));
+    if (!p->items.empty()) std::memcpy(h.data() + p->off_items, p->items.data(), p->items.size() * sizeof(Item));
+    if (!p->chunks.empty()) std::memcpy(h.data() + p->off_chunks, p->chunks.data(), p->chunks.size() * sizeof(Chunk));
+  }
+  if (tab) HIPCHK(c, hipMemcpyAsync(c->d_tables, h.data(), tab, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ROMAP_OK;
+}
+
+StepArgs plan_args(romap_ctx* c, const Plan& p) {
+  StepArgs a = base_args(c);
+  a.sobj = (const StepObj*)(c->d_tables + p.off_sobj);
+  a.n_sobj = (int)p.sobj.size();
+  a.items = (const Item*)(c->d_tables + p.off_items);
+  a.n_items = (int)p.items.size();
+  a.chunks = (const Chunk*)(c->d_tables + p.off_chunks);
+  a.n_chunks = (int)p.chunks.size();
+  a.n_rays = p.n_rays;
+  a.S = p.S;
+  return a;
+}
+
+// One training step of every object of a plan (the hot path).  ev: null, or
+// ROMAP_N_PHASES + 1 events recorded between the kernels.
+hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a, bool adam,
+                        hipEvent_t* ev = nullptr) {
+  const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels, K1 = K1_of(c->cfg);
+  hipError_t e;
+#define RM_MARK(i) \
+  if (ev && (e = hipEventRecord(ev[i], c->stream)) != hipSuccess) return e;
+  RM_MARK(0);
+  if ((e = rm_launch_raygen(a, NS, c->stream)) != hipSuccess) return e;
+  RM_MARK(1);
+  if ((e = rm_launch_encode_fwd(a, NS, L, p.enc_block, c->stream)) != hipSuccess) return e;
+  RM_MARK(2);
+  if ((e = rm_launch_pack(a, K1, c->stream)) != hipSuccess) return e;
+  RM_MARK(3);
+  if ((e = rm_launch_field(a, NS, K1, c->cfg.precision, c->stream)) != hipSuccess) return e;
+  RM_MARK(4);
+  if ((e = rm_launch_encode_bwd(a, NS, L, p.enc_block, c->stream)) != hipSuccess) return e;
+  RM_MARK(5);
+  if ((e = rm_launch_reduce(a, RM_MLP_MAX, c->stream)) != hipSuccess) return e;
+  RM_MARK(6);
+  if (adam && (e = rm_launch_adam(a, c->stream)) != hipSuccess) return e;
+  RM_MARK(7);
+#undef RM_MARK
+  return hipSuccess;
+}
+
+// Adds the phase durations of the step whose events were just recorded.
+hipError_t accumulate_phases(romap_ctx* c) {
+  hipError_t e = hipEventSynchronize(c->pev[ROMAP_N_PHASES]);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < ROMAP_N_PHASES; ++i) {
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, c->pev[i], c->pev[i + 1])) != hipSuccess) return e;
+    c->phase_ms[i] += ms;
+  }
+  return hipSuccess;
+}
+
+std::vector<int64_t> signature(romap_ctx* c, const std::vector<std::pair<int, int>>& list) {
+  std::vector<int64_t> s = {c->cfg.samples_per_ray, c->cfg.n_levels, c->cfg.precision};
+  for (auto& pr : list) {
+    s.push_back(pr.first);
+    s.push_back(pr.second);
+  }
+  return s;
+}
+
+// Tile autotuner: times the fused field kernel for each ray-tile size and the
+// encoding gather for each block size on the real work list, keeps the
+// fastest.  Only scratch buffers are written (rays, encodings, records).
+romap_status autotune(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int* rpi,
+                      int* blk) {
+  auto key = signature(c, list);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) {
+    *rpi = it->second.first;
+    *blk = it->second.second;
+    return ROMAP_OK;
+  }
+  const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels, K1 = K1_of(c->cfg);
+  const int cands[] = {4, 8, 16, 32};
+  const int blocks[] = {128, 256, 512};
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_rpi = 8, best_blk = 256;
+  for (int cand : cands) {
+    Plan p;
+    build_plan(c, list, cand, 256, p);
+    romap_status st = stage_plans(c, {&p});
+    if (st != ROMAP_OK) return st;
+    StepArgs a = plan_args(c, p);
+    HIPCHK(c, rm_launch_raygen(a, NS, c->stream));
+    HIPCHK(c, rm_launch_encode_fwd(a, NS, L, 256, c->stream));
+    HIPCHK(c, rm_launch_pack(a, K1, c->stream));
+    HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < 3; ++r) HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_rpi = cand;
+    }
+    if (cand == cands[0]) {
+      float bb = 1e30f;
+      for (int blk_c : blocks) {
+        HIPCHK(c, rm_launch_encode_fwd(a, NS, L, blk_c, c->stream));
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < 3; ++r) HIPCHK(c, rm_launch_encode_fwd(a, NS, L, blk_c, c->stream));
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < bb) {
+          bb = ms;
+          best_blk = blk_c;
+        }
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->tuned[key] = {best_rpi, best_blk};
+  *rpi = best_rpi;
+  *blk = best_blk;
+  return ROMAP_OK;
+}
+
+romap_status check_object(romap_ctx* c, int32_t id) {
+  if (id < 0 || id >= (int32_t)c->objs.size())
+    return fail(c, ROMAP_E_NOT_FOUND, "unknown object id " + std::to_string(id));
+  return ROMAP_OK;
+}
+
+romap_status validate_camera(romap_ctx* c, const romap_camera* cam) {
+  if (!cam) return fail(c, ROMAP_E_INVALID_ARG, "camera is NULL");
+  if (cam->width <= 0 || cam->height <= 0 || (int64_t)cam->width * cam->height > (1 << 26))
+    return fail(c, ROMAP_E_INVALID_ARG, "bad image size");
+  if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f) || !is_fin(cam->fx) || !is_fin(cam->fy) ||
+      !is_fin(cam->cx) || !is_fin(cam->cy))
+    return fail(c, ROMAP_E_INVALID_ARG, "bad intrinsics");
+  for (int k = 0; k < 12; ++k)
+    if (!is_fin(cam->T_wc[k])) return fail(c, ROMAP_E_INVALID_ARG, "non-finite pose");
+  return ROMAP_OK;
+}
+
+romap_status read_losses(romap_ctx* c, const Plan& p, std::vector<float>* per_obj, int* n_nan) {
+  std::vector<ObjState> st(c->objs.size());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(st.data(), c->d_state, st.size() * sizeof(ObjState), hipMemcpyDeviceToHost));
+  per_obj->clear();
+  *n_nan = 0;
+  for (auto& so : p.sobj) {
+    const ObjState& s = st[so.obj];
+    const float l = s.n_loss ? s.loss_acc / (float)s.n_loss : 0.0f;
+    if (!std::isfinite(l)) ++*n_nan;
+    per_obj->push_back(l);
+  }
+  return ROMAP_OK;
+}
+
+romap_status resolve_list(romap_ctx* c, const int32_t* ids, int32_t n, const int32_t* rays,
+                          std::vector<std::pair<int, int>>& list) {
+  list.clear();
+  if (ids) {
+    if (n < 0) return fail(c, ROMAP_E_INVALID_ARG, "negative object count");
+    for (int i = 0; i < n; ++i) {
+      romap_status s = check_object(c, ids[i]);
+      if (s != ROMAP_OK) return s;
+      for (int j = 0; j < i; ++j)
+        if (ids[j] == ids[i]) return fail(c, ROMAP_E_INVALID_ARG, "object listed twice");
+      const int b = rays ? rays[i] : c->cfg.rays_per_step;
+      if (b <= 0 || b > (1 << 22)) return fail(c, ROMAP_E_INVALID_ARG, "bad ray count");
+      list.push_back({ids[i], b});
+    }
+  } else {
+    int k = 0;
+    for (auto& o : c->objs) {
+      if (!o.active) continue;
+      const int b = rays ? rays[k] : c->cfg.rays_per_step;
+      if (b <= 0 || b > (1 << 22)) return fail(c, ROMAP_E_INVALID_ARG, "bad ray count");
+      list.push_back({o.id, b});
+      ++k;
+    }
+  }
+  for (auto& pr : list)
+    if (c->objs[pr.first].kfs.empty())
+      return fail(c, ROMAP_E_STATE, "object " + std::to_string(pr.first) + " has no keyframe");
+  return ROMAP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+romap_status romap_default_config(romap_config* cfg) {
+  if (!cfg) return ROMAP_E_INVALID_ARG;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->n_levels = 16;
+  cfg->base_res = 16;
+  cfg->max_res = 1024;
+  cfg->log2_table_size = 19;
+  cfg->samples_per_ray = 64;
+  cfg->rays_per_step = 4096;
+  cfg->lr = 1e-2f;
+  cfg->beta1 = 0.9f;
+  cfg->beta2 = 0.99f;
+  cfg->eps = 1e-15f;
+  cfg->lambda_depth = 0.5f;
+  cfg->lambda_density = 0.01f;
+  cfg->alpha_deg = 25.0f;
+  cfg->bbox_margin_pct = 10;
+  cfg->precision = ROMAP_PREC_FP32;
+  cfg->batch_mode = ROMAP_BATCH_ALL;
+  cfg->use_graph = 1;
+  cfg->autotune = 1;
+  cfg->profile_phases = 0;
+  cfg->seed = 0;
+  return ROMAP_OK;
+}
+
+const char* romap_last_error(const romap_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+romap_status romap_create(const romap_config* cfg, void* hip_stream, romap_ctx** out) {
+  if (!cfg || !out) return fail(nullptr, ROMAP_E_INVALID_ARG, "NULL argument");
+  const romap_config& k = *cfg;
+  if (k.n_levels < 1 || k.n_levels > 16) return fail(nullptr, ROMAP_E_INVALID_ARG, "n_levels must be 1..16");
+  if (k.base_res < 1 || k.max_res < k.base_res || k.max_res > (1 << 16))
+    return fail(nullptr, ROMAP_E_INVALID_ARG, "bad resolutions");
+  if (k.log2_table_size < 8 || k.log2_table_size > 24)
+    return fail(nullptr, ROMAP_E_INVALID_ARG, "log2_table_size must be 8..24");
+  if (k.samples_per_ray != 32 && k.samples_per_ray != 64 && k.samples_per_ray != 128)
+    return fail(nullptr, ROMAP_E_INVALID_ARG, "samples_per_ray must be 32, 64 or 128");
+  if (k.rays_per_step <= 0 || k.rays_per_step > (1 << 22))
+    return fail(nullptr, ROMAP_E_INVALID_ARG, "bad rays_per_step");
+  if (!(k.lr > 0.0f) || !(k.beta1 >= 0.0f && k.beta1 < 1.0f) || !(k.beta2 >= 0.0f && k.beta2 < 1.0f) ||
+      !(k.eps >= 0.0f) || !is_fin(k.lr))
+    return fail(nullptr, ROMAP_E_INVALID_ARG, "bad Adam hyperparameters");
+  if (!(k.lambda_depth >= 0.0f) || !(k.lambda_density >= 0.0f) || !is_fin(k.lambda_depth) ||
+      !is_fin(k.lambda_density))
+    return fail(nullptr, ROMAP_E_INVALID_ARG, "bad loss weights");
+  if (!(k.alpha_deg >= 0.0f && k.alpha_deg <= 180.0f)) return fail(nullptr, ROMAP_E_INVALID_ARG, "bad alpha_deg");
+  if (k.bbox_margin_pct < 0 || k.bbox_margin_pct > 100) return fail(nullptr, ROMAP_E_INVALID_ARG, "bad margin");
+  if (k.precision != ROMAP_PREC_FP32 && k.precision != ROMAP_PREC_BF16)
+    return fail(nullptr, ROMAP_E_INVALID_ARG, "bad precision");
+  if (k.batch_mode != ROMAP_BATCH_ALL && k.batch_mode != ROMAP_BATCH_PER_OBJECT)
+    return fail(nullptr, ROMAP_E_INVALID_ARG, "bad batch_mode");
+  romap_ctx* c = new romap_ctx();
+  c->cfg = k;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(nullptr, ROMAP_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return ROMAP_OK;
+}
+
+romap_status romap_destroy(romap_ctx* c) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  hipStreamSynchronize(c->stream);
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  for (int i = 0; i <= ROMAP_N_PHASES; ++i)
+    if (c->pev[i]) hipEventDestroy(c->pev[i]);
+  for (auto& o : c->objs) {
+    hipFree(o.d_block);
+    hipFree(o.d_kfs);
+  }
+  for (auto& k : c->kfs) {
+    hipFree(k.d_rgb);
+    hipFree(k.d_mask);
+    hipFree(k.d_depth);
+  }
+  hipFree(c->d_objs);
+  hipFree(c->d_state);
+  hipFree(c->d_kfdev);
+  hipFree(c->d_rays);
+  hipFree(c->d_e);
+  hipFree(c->d_de);
+  hipFree(c->d_partials);
+  hipFree(c->d_wpack32);
+  hipFree(c->d_wpack16);
+  hipFree(c->d_tables);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+  return ROMAP_OK;
+}
+
+romap_status romap_get_phase_times(romap_ctx* c, float* avg_ms, int32_t* n_steps) {
+  if (!c || !avg_ms) return ROMAP_E_INVALID_ARG;
+  for (int i = 0; i < ROMAP_N_PHASES; ++i)
+    avg_ms[i] = c->phase_steps ? (float)(c->phase_ms[i] / c->phase_steps) : 0.0f;
+  if (n_steps) *n_steps = c->phase_steps;
+  return ROMAP_OK;
+}
+
+romap_status romap_sync(romap_ctx* c) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ROMAP_OK;
+}
+
+romap_status romap_add_object(romap_ctx* c, int32_t instance_id, const romap_box* box,
+                              int32_t log2_table_size, int32_t* object_id) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  if (!box) return fail(c, ROMAP_E_INVALID_ARG, "box is NULL");
+  if (instance_id < 1) return fail(c, ROMAP_E_INVALID_ARG, "instance ids start at 1 (0 = background)");
+  for (int k = 0; k < 3; ++k)
+    if (!(box->half[k] > 0.0f) || !is_fin(box->half[k]) || !is_fin(box->t[k]))
+      return fail(c, ROMAP_E_INVALID_ARG, "box centre must be finite and half extents > 0");
+  if (!is_fin(box->yaw)) return fail(c, ROMAP_E_INVALID_ARG, "non-finite yaw");
+  const int lt = log2_table_size == 0 ? c->cfg.log2_table_size : log2_table_size;
+  if (lt < 8 || lt > 24) return fail(c, ROMAP_E_INVALID_ARG, "log2_table_size must be 8..24");
+  for (auto& o : c->objs)
+    if (o.instance == instance_id) return fail(c, ROMAP_E_INVALID_ARG, "instance already registered");
+  HostObj o;
+  o.id = (int)c->objs.size();
+  o.instance = instance_id;
+  o.log2T = lt;
+  o.box = *box;
+  make_levels(c->cfg, lt, o);
+  // device tables first, so that a failure leaves no half-registered object
+  {
+    size_t cap = c->cap_objs;
+    if (c->objs.size() + 1 > cap) {
+      ObjStatic* nd = nullptr;
+      const size_t ncap = std::max<size_t>(16, 2 * cap);
+      HIPALLOC(c, hipMalloc((void**)&nd, ncap * sizeof(ObjStatic)));
+      ObjState* ns = nullptr;
+      hipError_t e = hipMalloc((void**)&ns, ncap * sizeof(ObjState));
+      if (e != hipSuccess) {
+        hipFree(nd);
+        return fail(c, ROMAP_E_OUT_OF_MEMORY, "object table: out of memory");
+      }
+      HIPCHK(c, hipMemsetAsync(ns, 0, ncap * sizeof(ObjState), c->stream));
+      if (c->d_objs) {
+        HIPCHK(c, hipMemcpyAsync(nd, c->d_objs, c->objs.size() * sizeof(ObjStatic), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(ns, c->d_state, c->objs.size() * sizeof(ObjState), hipMemcpyDeviceToDevice, c->stream));
+      }
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      hipFree(c->d_objs);
+      hipFree(c->d_state);
+      c->d_objs = nd;
+      c->d_state = ns;
+      c->cap_objs = c->cap_state = ncap;
+      if (c->gexec) {
+        hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+        c->gsig.clear();
+      }
+    }
+  }
+  HIPALLOC(c, hipMalloc((void**)&o.d_block, 4 * (size_t)o.P_alloc * sizeof(float)));
+  hipError_t e = hipMemsetAsync(o.d_block, 0, 4 * (size_t)o.P_alloc * sizeof(float), c->stream);
+  if (e == hipSuccess)
+    e = rm_launch_init(o.d_block, o.P_grid, o.din, (uint32_t)c->cfg.seed ^ (uint32_t)o.id,
+                       (uint32_t)(c->cfg.seed >> 32), c->stream);
+  ObjState st0{};
+  st0.bc1 = 1.0f;
+  st0.bc2 = 1.0f;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->d_state + o.id, &st0, sizeof(st0), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    hipFree(o.d_block);
+    return fail(c, ROMAP_E_HIP, std::string("object init: ") + hipGetErrorString(e));
+  }
+  c->objs.push_back(o);
+  romap_status s = upload_object(c, o.id);
+  if (s != ROMAP_OK) return s;
+  if (object_id) *object_id = o.id;
+  return ROMAP_OK;
+}
+
+romap_status romap_set_object_active(romap_ctx* c, int32_t id, int32_t active) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  c->objs[id].active = active ? 1 : 0;
+  return ROMAP_OK;
+}
+
+romap_status romap_get_object_info(romap_ctx* c, int32_t id, romap_object_info* info) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  if (!info) return fail(c, ROMAP_E_INVALID_ARG, "info is NULL");
+  const HostObj& o = c->objs[id];
+  ObjState st{};
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(&st, c->d_state + id, sizeof(st), hipMemcpyDeviceToHost));
+  std::memset(info, 0, sizeof(*info));
+  info->instance_id = o.instance;
+  info->log2_table_size = o.log2T;
+  info->n_grid_params = o.P_grid;
+  info->n_mlp_params = o.P - o.P_grid;
+  info->n_keyframes = (int)o.kfs.size();
+  info->step = st.step;
+  info->n_candidates = o.n_cand;
+  info->active = o.active;
+  for (int l = 0; l < o.L; ++l) {
+    info->level_res[l] = (int)o.N_l[l];
+    info->level_hashed[l] = (o.hashed_mask >> l) & 1;
+  }
+  return ROMAP_OK;
+}
+
+romap_status romap_add_keyframe(romap_ctx* c, const romap_camera* cam, const uint8_t* rgb,
+                                const int32_t* mask, const float* depth_z, int32_t* keyframe_id,
+                                int32_t* n_objects_accepted) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = validate_camera(c, cam);
+  if (s != ROMAP_OK) return s;
+  if (!rgb || !mask) return fail(c, ROMAP_E_INVALID_ARG, "rgb and mask are required");
+  const int W = cam->width, H = cam->height;
+  const size_t npix = (size_t)W * H;
+  // which objects accept this keyframe (Eq. 5), decided before any side effect
+  struct Acc {
+    int obj;
+    int rect[4];
+  };
+  std::vector<Acc> acc;
+  const double tI[3] = {cam->T_wc[3], cam->T_wc[7], cam->T_wc[11]};
+  for (auto& o : c->objs) {
+    Acc a;
+    if (!candidate_rect(mask, W, H, o.instance, c->cfg.bbox_margin_pct, a.rect)) continue;
+    if (o.has_last) {
+      double va[3], vb[3], dot = 0, na = 0, nb = 0;
+      for (int k = 0; k < 3; ++k) {
+        va[k] = o.last_centre[k] - (double)o.box.t[k];
+        vb[k] = tI[k] - (double)o.box.t[k];
+        dot += va[k] * vb[k];
+        na += va[k] * va[k];
+        nb += vb[k] * vb[k];
+      }
+      double cs = dot / (std::sqrt(na) * std::sqrt(nb));
+      cs = std::max(-1.0, std::min(1.0, cs));
+      const double alpha = std::acos(cs) * 180.0 / M_PI;
+      if (!(alpha > (double)c->cfg.alpha_deg)) continue;
+    }
+    a.obj = o.id;
+    acc.push_back(a);
+  }
+  HostKf kf;
+  kf.cam = *cam;
+  HIPALLOC(c, hipMalloc((void**)&kf.d_rgb, npix * 3));
+  hipError_t e = hipMalloc((void**)&kf.d_mask, npix * sizeof(int32_t));
+  if (e == hipSuccess && depth_z) e = hipMalloc((void**)&kf.d_depth, npix * sizeof(float));
+  if (e == hipSuccess && c->kfs.size() + 1 > c->cap_kfdev) {
+    KfDev* nd = nullptr;
+    const size_t ncap = std::max<size_t>(64, 2 * c->cap_kfdev);
+    e = hipMalloc((void**)&nd, ncap * sizeof(KfDev));
+    if (e == hipSuccess && c->d_kfdev)
+      e = hipMemcpy(nd, c->d_kfdev, c->kfs.size() * sizeof(KfDev), hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) {
+      hipStreamSynchronize(c->stream);
+      hipFree(c->d_kfdev);
+      c->d_kfdev = nd;
+      c->cap_kfdev = ncap;
+      if (c->gexec) {
+        hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+        c->gsig.clear();
+      }
+    } else if (nd) {
+      hipFree(nd);
+    }
+  }
+  if (e != hipSuccess) {
+    hipFree(kf.d_rgb);
+    hipFree(kf.d_mask);
+    hipFree(kf.d_depth);
+    return fail(c, e == hipErrorOutOfMemory ? ROMAP_E_OUT_OF_MEMORY : ROMAP_E_HIP,
+                std::string("keyframe allocation: ") + hipGetErrorString(e));
+  }
+  HIPCHK(c, hipMemcpyAsync(kf.d_rgb, rgb, npix * 3, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(kf.d_mask, mask, npix * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  if (depth_z)
+    HIPCHK(c, hipMemcpyAsync(kf.d_depth, depth_z, npix * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  KfDev kd{};
+  kd.rgb = kf.d_rgb;
+  kd.mask = kf.d_mask;
+  kd.depth = kf.d_depth;
+  kd.W = W;
+  kd.H = H;
+  kd.fx = cam->fx;
+  kd.fy = cam->fy;
+  kd.cx = cam->cx;
+  kd.cy = cam->cy;
+  const int kid = (int)c->kfs.size();
+  HIPCHK(c, hipMemcpyAsync(c->d_kfdev + kid, &kd, sizeof(kd), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->kfs.push_back(kf);
+  for (auto& a : acc) {
+    HostObj& o = c->objs[a.obj];
+    KfRef r{};
+    r.kf = kid;
+    r.x0 = a.rect[0];
+    r.y0 = a.rect[1];
+    r.w = a.rect[2];
+    r.h = a.rect[3];
+    object_frame(cam->T_wc, o.box, r.M, r.c);
+    r.cand_begin = o.n_cand;
+    o.kfs.push_back(r);
+    o.n_cand += (int64_t)r.w * r.h;
+    o.has_last = true;
+    for (int k = 0; k < 3; ++k) o.last_centre[k] = tI[k];
+    s = upload_object(c, o.id);
+    if (s != ROMAP_OK) return s;
+  }
+  if (keyframe_id) *keyframe_id = kid;
+  if (n_objects_accepted) *n_objects_accepted = (int)acc.size();
+  return ROMAP_OK;
+}
+
+romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_steps,
+                         const int32_t* rays, romap_train_stats* stats) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  if (n_steps < 0) return fail(c, ROMAP_E_INVALID_ARG, "negative step count");
+  std::vector<std::pair<int, int>> list;
+  romap_status s = resolve_list(c, ids, n, rays, list);
+  if (s != ROMAP_OK) return s;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (list.empty() || n_steps == 0) return ROMAP_OK;
+  int rpi = 8, blk = 256;
+  if (c->cfg.autotune) {
+    s = autotune(c, list, &rpi, &blk);
+    if (s != ROMAP_OK) return s;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (stats) {
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+  }
+  int64_t rays_total = 0;
+  for (auto& pr : list) rays_total += pr.second;
+  std::vector<float> losses;
+  int n_nan = 0;
+  Plan all;
+  build_plan(c, list, rpi, blk, all);
+  const bool prof = c->cfg.profile_phases != 0;
+  if (prof) {
+    for (int i = 0; i <= ROMAP_N_PHASES; ++i)
+      if (!c->pev[i]) HIPCHK(c, hipEventCreate(&c->pev[i]));
+    for (int i = 0; i < ROMAP_N_PHASES; ++i) c->phase_ms[i] = 0.0;
+    c->phase_steps = 0;
+  }
+  if (c->cfg.batch_mode == ROMAP_BATCH_ALL) {
+    s = stage_plans(c, {&all});
+    if (s != ROMAP_OK) return s;
+    StepArgs a = plan_args(c, all);
+    if (stats) {
+      HIPCHK(c, rm_launch_reset_loss(a, c->stream));
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    if (prof) {
+      for (int i = 0; i < n_steps; ++i) {
+        HIPCHK(c, enqueue_step(c, all, a, true, c->pev));
+        HIPCHK(c, accumulate_phases(c));
+        ++c->phase_steps;
+      }
+    } else if (c->cfg.use_graph) {
+      std::vector<int64_t> sig = signature(c, list);
+      sig.push_back(rpi);
+      sig.push_back(blk);
+      sig.push_back((int64_t)(uintptr_t)c->d_tables);
+      if (!c->gexec || sig != c->gsig) {
+        if (c->gexec) {
+          hipGraphExecDestroy(c->gexec);
+          c->gexec = nullptr;
+        }
+        hipGraph_t graph;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = enqueue_step(c, all, a, true);
+        hipError_t ce = hipStreamEndCapture(c->stream, &graph);
+        if (le != hipSuccess) return fail(c, ROMAP_E_HIP, std::string("capture: ") + hipGetErrorString(le));
+        if (ce != hipSuccess) return fail(c, ROMAP_E_HIP, std::string("end capture: ") + hipGetErrorString(ce));
+        hipError_t ie = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+          c->gexec = nullptr;
+          return fail(c, ROMAP_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        }
+        c->gsig = sig;
+      }
+      for (int i = 0; i < n_steps; ++i) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    } else {
+      for (int i = 0; i < n_steps; ++i) HIPCHK(c, enqueue_step(c, all, a, true));
+    }
+    if (stats) {
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      s = read_losses(c, all, &losses, &n_nan);
+      if (s != ROMAP_OK) return s;
+    }
+  } else {
+    // one launch per object per phase (the plain path)
+    std::vector<Plan> plans(list.size());
+    std::vector<Plan*> pp;
+    for (size_t i = 0; i < list.size(); ++i) {
+      build_plan(c, {list[i]}, rpi, blk, plans[i]);
+      pp.push_back(&plans[i]);
+    }
+    s = stage_plans(c, pp);
+    if (s != ROMAP_OK) return s;
+    std::vector<StepArgs> args;
+    for (auto& p : plans) args.push_back(plan_args(c, p));
+    if (stats) {
+      for (auto& a : args) HIPCHK(c, rm_launch_reset_loss(a, c->stream));
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    for (int i = 0; i < n_steps; ++i) {
+      for (size_t k = 0; k < plans.size(); ++k) {
+        HIPCHK(c, enqueue_step(c, plans[k], args[k], true, prof ? c->pev : nullptr));
+        if (prof) HIPCHK(c, accumulate_phases(c));
+      }
+      if (prof) ++c->phase_steps;
+    }
+    if (stats) {
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      losses.clear();
+      for (auto& p : plans) {
+        std::vector<float> l1;
+        int nn = 0;
+        s = read_losses(c, p, &l1, &nn);
+        if (s != ROMAP_OK) return s;
+        losses.insert(losses.end(), l1.begin(), l1.end());
+        n_nan += nn;
+      }
+    }
+  }
+  if (stats) {
+    float ms = 0.0f;
+    HIPCHK(c, hipEventSynchronize(e1));
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    double sum = 0.0;
+    for (float l : losses) sum += l;
+    stats->loss_mean = losses.empty() ? 0.0f : (float)(sum / losses.size());
+    stats->rays_trained = rays_total * n_steps;
+    stats->seconds = ms * 1e-3f;
+    stats->n_objects_nan = n_nan;
+    if (n_nan) return fail(c, ROMAP_E_NUMERIC, std::to_string(n_nan) + " object(s) with non-finite loss");
+  }
+  return ROMAP_OK;
+}
+
+romap_status romap_loss_and_grad(romap_ctx* c, const int32_t* ids, int32_t n, const int32_t* rays,
+                                 float* losses) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  std::vector<std::pair<int, int>> list;
+  romap_status s = resolve_list(c, ids, n, rays, list);
+  if (s != ROMAP_OK) return s;
+  if (list.empty()) return ROMAP_OK;
+  Plan p;
+  build_plan(c, list, 8, 256, p);
+  s = stage_plans(c, {&p});
+  if (s != ROMAP_OK) return s;
+  for (auto& pr : list) {
+    const HostObj& o = c->objs[pr.first];
+    HIPCHK(c, rm_launch_fill(o.d_block + o.P_alloc, o.P_alloc, 0.0f, c->stream));
+  }
+  StepArgs a = plan_args(c, p);
+  a.advance = 0;
+  HIPCHK(c, rm_launch_reset_loss(a, c->stream));
+  HIPCHK(c, enqueue_step(c, p, a, false));
+  std::vector<float> l;
+  int nn = 0;
+  s = read_losses(c, p, &l, &nn);
+  if (s != ROMAP_OK) return s;
+  if (losses)
+    for (size_t i = 0; i < l.size(); ++i) losses[i] = l[i];
+  return ROMAP_OK;
+}
+
+romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, float* rgb,
+                          float* depth, float* opacity, int32_t on_device) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  s = validate_camera(c, cam);
+  if (s != ROMAP_OK) return s;
+  const HostObj& o = c->objs[id];
+  const int W = cam->width, H = cam->height;
+  const int64_t npix = (int64_t)W * H;
+  float M[9], cc[3];
+  object_frame(cam->T_wc, o.box, M, cc);
+  float *d_rgb = nullptr, *d_depth = nullptr, *d_tend = nullptr;
+  if (on_device) {
+    d_rgb = rgb;
+    d_depth = depth;
+  } else {
+    if (rgb) HIPALLOC(c, hipMalloc((void**)&d_rgb, npix * 3 * sizeof(float)));
+    if (depth) HIPALLOC(c, hipMalloc((void**)&d_depth, npix * sizeof(float)));
+  }
+  if (opacity) HIPALLOC(c, hipMalloc((void**)&d_tend, npix * sizeof(float)));
+  const int chunk = 32768;
+  const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels, K1 = K1_of(c->cfg);
+  for (int64_t p0 = 0; p0 < npix; p0 += chunk) {
+    const int nr = (int)std::min<int64_t>(chunk, npix - p0);
+    Plan p;
+    build_plan(c, {{id, nr}}, 8, 256, p);
+    p.chunks.clear();
+    s = stage_plans(c, {&p});
+    if (s != ROMAP_OK) return s;
+    StepArgs a = plan_args(c, p);
+    a.mode = RM_MODE_FORWARD;
+    a.out_rgb = d_rgb ? d_rgb + 3 * p0 : nullptr;
+    a.out_depth = d_depth ? d_depth + p0 : nullptr;
+    a.out_tend = d_tend ? d_tend + p0 : nullptr;
+    HIPCHK(c, rm_launch_camera_rays(a, NS, M, cc, cam->fx, cam->fy, cam->cx, cam->cy, W, (int)p0, c->stream));
+    HIPCHK(c, rm_launch_encode_fwd(a, NS, L, 256, c->stream));
+    HIPCHK(c, rm_launch_pack(a, K1, c->stream));
+    HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  if (!on_device) {
+    if (rgb) HIPCHK(c, hipMemcpy(rgb, d_rgb, npix * 3 * sizeof(float), hipMemcpyDeviceToHost));
+    if (depth) HIPCHK(c, hipMemcpy(depth, d_depth, npix * sizeof(float), hipMemcpyDeviceToHost));
+    hipFree(d_rgb);
+    hipFree(d_depth);
+  }
+  if (opacity) {
+    std::vector<float> t(npix);
+    HIPCHK(c, hipMemcpy(t.data(), d_tend, npix * sizeof(float), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < npix; ++i) t[i] = 1.0f - t[i];
+    if (on_device)
+      HIPCHK(c, hipMemcpy(opacity, t.data(), npix * sizeof(float), hipMemcpyHostToDevice));
+    else
+      std::memcpy(opacity, t.data(), npix * sizeof(float));
+    hipFree(d_tend);
+  }
+  return ROMAP_OK;
+}
+
+romap_status romap_query_density(romap_ctx* c, int32_t id, const float* xyz, int64_t n,
+                                 float* sigma, int32_t on_device) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  if (n < 0 || (n > 0 && (!xyz || !sigma))) return fail(c, ROMAP_E_INVALID_ARG, "bad buffers");
+  if (n == 0) return ROMAP_OK;
+  if (on_device) {
+    HIPCHK(c, rm_launch_query_density(c->d_objs, id, xyz, n, sigma, c->stream));
+    return ROMAP_OK;
+  }
+  float *dx = nullptr, *ds = nullptr;
+  HIPALLOC(c, hipMalloc((void**)&dx, n * 3 * sizeof(float)));
+  hipError_t e = hipMalloc((void**)&ds, n * sizeof(float));
+  if (e != hipSuccess) {
+    hipFree(dx);
+    return fail(c, ROMAP_E_OUT_OF_MEMORY, "query buffers: out of memory");
+  }
+  HIPCHK(c, hipMemcpyAsync(dx, xyz, n * 3 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, rm_launch_query_density(c->d_objs, id, dx, n, ds, c->stream));
+  HIPCHK(c, hipMemcpyAsync(sigma, ds, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  hipFree(dx);
+  hipFree(ds);
+  return ROMAP_OK;
+}
+
+static float* kind_ptr(const HostObj& o, int kind) {
+  switch (kind) {
+    case ROMAP_PARAMS: return o.d_block;
+    case ROMAP_GRAD: return o.d_block + o.P_alloc;
+    case ROMAP_ADAM_M: return o.d_block + 2 * o.P_alloc;
+    case ROMAP_ADAM_V: return o.d_block + 3 * o.P_alloc;
+    default: return nullptr;
+  }
+}
+
+romap_status romap_get_params(romap_ctx* c, int32_t id, int32_t kind, float* buf, int64_t n,
+                              int64_t* n_required) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  const HostObj& o = c->objs[id];
+  float* src = kind_ptr(o, kind);
+  if (!src) return fail(c, ROMAP_E_INVALID_ARG, "bad parameter kind");
+  if (n_required) *n_required = o.P;
+  if (!buf) return ROMAP_OK;
+  if (n < o.P) return fail(c, ROMAP_E_INVALID_ARG, "buffer too small");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(buf, src, o.P * sizeof(float), hipMemcpyDeviceToHost));
+  return ROMAP_OK;
+}
+
+romap_status romap_set_params(romap_ctx* c, int32_t id, int32_t kind, const float* buf, int64_t n) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  const HostObj& o = c->objs[id];
+  float* dst = kind_ptr(o, kind);
+  if (!dst) return fail(c, ROMAP_E_INVALID_ARG, "bad parameter kind");
+  if (!buf || n != o.P) return fail(c, ROMAP_E_INVALID_ARG, "buffer must hold exactly the object's parameter count");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(dst, buf, o.P * sizeof(float), hipMemcpyHostToDevice));
+  return ROMAP_OK;
+}
+
+romap_status romap_debug_rays(romap_ctx* c, int32_t id, int32_t n_rays, int32_t* kf_uv,
+                              int32_t* cls, float* ray_f, float* positions) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  if (n_rays <= 0 || n_rays > (1 << 22)) return fail(c, ROMAP_E_INVALID_ARG, "bad ray count");
+  if (c->objs[id].kfs.empty()) return fail(c, ROMAP_E_STATE, "object has no keyframe");
+  Plan p;
+  build_plan(c, {{id, n_rays}}, 8, 256, p);
+  s = stage_plans(c, {&p});
+  if (s != ROMAP_OK) return s;
+  StepArgs a = plan_args(c, p);
+  int32_t* d_kfuv = nullptr;
+  float* d_pos = nullptr;
+  HIPALLOC(c, hipMalloc((void**)&d_kfuv, (size_t)n_rays * 3 * sizeof(int32_t)));
+  a.dbg_kfuv = d_kfuv;
+  const int NS = c->cfg.samples_per_ray;
+  HIPCHK(c, rm_launch_raygen(a, NS, c->stream));
+  if (positions) {
+    HIPALLOC(c, hipMalloc((void**)&d_pos, (size_t)p.S * 3 * sizeof(float)));
+    HIPCHK(c, rm_launch_debug_positions(a, NS, d_pos, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<RayRec> rr(n_rays);
+  HIPCHK(c, hipMemcpy(rr.data(), c->d_rays, n_rays * sizeof(RayRec), hipMemcpyDeviceToHost));
+  if (kf_uv) HIPCHK(c, hipMemcpy(kf_uv, d_kfuv, (size_t)n_rays * 3 * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (positions) HIPCHK(c, hipMemcpy(positions, d_pos, (size_t)p.S * 3 * sizeof(float), hipMemcpyDeviceToHost));
+  hipFree(d_kfuv);
+  hipFree(d_pos);
+  for (int r = 0; r < n_rays; ++r) {
+    const RayRec& R = rr[r];
+    if (cls) cls[r] = (R.flags & RM_F_HIT) ? (int)(R.flags & RM_F_CLS) : -1;
+    if (ray_f) {
+      float* q = ray_f + 16 * (int64_t)r;
+      for (int k = 0; k < 3; ++k) {
+        q[k] = R.o[k];
+        q[3 + k] = R.d[k];
+        q[8 + k] = R.tgt[k];
+      }
+      q[6] = R.tn;
+      q[7] = R.delta;
+      q[11] = R.D;
+      q[12] = q[13] = q[14] = 0.0f;
+      q[15] = (R.flags & RM_F_DEPTH) ? 1.0f : 0.0f;
+    }
+  }
+  return ROMAP_OK;
+}
+
+romap_status romap_debug_encode(romap_ctx* c, int32_t id, const float* p, int64_t n, uint32_t* idx,
+                                float* feat) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  if (n <= 0 || !p) return fail(c, ROMAP_E_INVALID_ARG, "bad points");
+  const int L = c->objs[id].L;
+  float *dp = nullptr, *df = nullptr;
+  uint32_t* di = nullptr;
+  HIPALLOC(c, hipMalloc((void**)&dp, n * 3 * sizeof(float)));
+  HIPALLOC(c, hipMalloc((void**)&df, n * L * 2 * sizeof(float)));
+  HIPALLOC(c, hipMalloc((void**)&di, n * L * 8 * sizeof(uint32_t)));
+  HIPCHK(c, hipMemcpyAsync(dp, p, n * 3 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, rm_launch_debug_encode(c->d_objs, id, dp, n, di, df, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (idx) HIPCHK(c, hipMemcpy(idx, di, n * L * 8 * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if (feat) HIPCHK(c, hipMemcpy(feat, df, n * L * 2 * sizeof(float), hipMemcpyDeviceToHost));
+  hipFree(dp);
+  hipFree(df);
+  hipFree(di);
+  return ROMAP_OK;
+}
+
+static romap_status field_common(romap_ctx* c, int32_t id, const float* params_dev,
+                                 const float* rays_dev, int32_t n_rays, Plan& p, StepArgs& a) {
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  if (n_rays <= 0 || !rays_dev) return fail(c, ROMAP_E_INVALID_ARG, "bad rays");
+  build_plan(c, {{id, n_rays}}, 8, 256, p);
+  p.chunks.clear();
+  s = stage_plans(c, {&p});
+  if (s != ROMAP_OK) return s;
+  a = plan_args(c, p);
+  a.params_override = params_dev;
+  const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels, K1 = K1_of(c->cfg);
+  HIPCHK(c, rm_launch_user_rays(a, NS, rays_dev, c->stream));
+  HIPCHK(c, rm_launch_encode_fwd(a, NS, L, 256, c->stream));
+  HIPCHK(c, rm_launch_pack(a, K1, c->stream));
+  return ROMAP_OK;
+}
+
+romap_status romap_field_forward(romap_ctx* c, int32_t id, const float* params_dev,
+                                 const float* rays_dev, int32_t n_rays, float* rgb_dev,
+                                 float* depth_dev, float* tend_dev) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  Plan p;
+  StepArgs a;
+  romap_status s = field_common(c, id, params_dev, rays_dev, n_rays, p, a);
+  if (s != ROMAP_OK) return s;
+  a.mode = RM_MODE_FORWARD;
+  a.out_rgb = rgb_dev;
+  a.out_depth = depth_dev;
+  a.out_tend = tend_dev;
+  HIPCHK(c, rm_launch_field(a, c->cfg.samples_per_ray, K1_of(c->cfg), c->cfg.precision, c->stream));
+  return ROMAP_OK;
+}
+
+romap_status romap_field_backward(romap_ctx* c, int32_t id, const float* params_dev,
+                                  const float* rays_dev, int32_t n_rays, const float* d_rgb_dev,
+                                  const float* d_depth_dev, const float* d_tend_dev,
+                                  float* d_params_dev) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  if (!d_params_dev) return fail(c, ROMAP_E_INVALID_ARG, "d_params is NULL");
+  Plan p;
+  StepArgs a;
+  romap_status s = field_common(c, id, params_dev, rays_dev, n_rays, p, a);
+  if (s != ROMAP_OK) return s;
+  const HostObj& o = c->objs[id];
+  a.mode = RM_MODE_ADJOINT;
+  a.adj_rgb = d_rgb_dev;
+  a.adj_depth = d_depth_dev;
+  a.adj_tend = d_tend_dev;
+  a.grad_override = d_params_dev;
+  a.advance = 0;
+  const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels;
+  HIPCHK(c, rm_launch_fill(d_params_dev, o.P, 0.0f, c->stream));
+  HIPCHK(c, rm_launch_field(a, NS, K1_of(c->cfg), c->cfg.precision, c->stream));
+  HIPCHK(c, rm_launch_encode_bwd(a, NS, L, 256, c->stream));
+  HIPCHK(c, rm_launch_reduce(a, RM_MLP_MAX, c->stream));
+  return ROMAP_OK;
+}
+
+// ---- checkpoint -------------------------------------------------------------
+static const char kMagic[8] = {'R', 'O', 'M', 'A', 'P', 'C', 'K', '1'};
+
+romap_status romap_save(romap_ctx* c, const char* path) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  if (!path) return fail(c, ROMAP_E_INVALID_ARG, "path is NULL");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(c, ROMAP_E_INVALID_ARG, std::string("cannot open ") + path);
+  bool ok = true;
+  auto W = [&](const void* p, size_t n) { ok = ok && std::fwrite(p, 1, n, f) == n; };
+  W(kMagic, 8);
+  W(&c->cfg, sizeof(c->cfg));
+  const int32_t nk = (int32_t)c->kfs.size(), no = (int32_t)c->objs.size();
+  W(&nk, 4);
+  for (auto& k : c->kfs) {
+    W(&k.cam, sizeof(k.cam));
+    const size_t npix = (size_t)k.cam.width * k.cam.height;
+    std::vector<uint8_t> rgb(npix * 3);
+    std::vector<int32_t> mask(npix);
+    hipMemcpy(rgb.data(), k.d_rgb, npix * 3, hipMemcpyDeviceToHost);
+    hipMemcpy(mask.data(), k.d_mask, npix * 4, hipMemcpyDeviceToHost);
+    const int32_t hd = k.d_depth ? 1 : 0;
+    W(&hd, 4);
+    W(rgb.data(), rgb.size());
+    W(mask.data(), mask.size() * 4);
+    if (hd) {
+      std::vector<float> d(npix);
+      hipMemcpy(d.data(), k.d_depth, npix * 4, hipMemcpyDeviceToHost);
+      W(d.data(), npix * 4);
+    }
+  }
+  W(&no, 4);
+  std::vector<ObjState> st(c->objs.size());
+  if (no) hipMemcpy(st.data(), c->d_state, no * sizeof(ObjState), hipMemcpyDeviceToHost);
+  for (int i = 0; i < no; ++i) {
+    const HostObj& o = c->objs[i];
+    W(&o.instance, 4);
+    W(&o.log2T, 4);
+    W(&o.active, 4);
+    W(&o.box, sizeof(o.box));
+    W(&st[i].step, 4);
+    const int32_t hl = o.has_last;
+    W(&hl, 4);
+    W(o.last_centre, sizeof(o.last_centre));
+    const int32_t nref = (int32_t)o.kfs.size();
+    W(&nref, 4);
+    for (auto& r : o.kfs) {
+      const int32_t v[5] = {r.kf, r.x0, r.y0, r.w, r.h};
+      W(v, sizeof(v));
+    }
+    std::vector<float> buf(3 * o.P_alloc);
+    hipMemcpy(buf.data(), o.d_block, o.P_alloc * 4, hipMemcpyDeviceToHost);
+    hipMemcpy(buf.data() + o.P_alloc, o.d_block + 2 * o.P_alloc, 2 * o.P_alloc * 4, hipMemcpyDeviceToHost);
+    W(buf.data(), buf.size() * 4);
+  }
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(c, ROMAP_E_INVALID_ARG, std::string("write failed: ") + path);
+  return ROMAP_OK;
+}
+
+romap_status romap_load(romap_ctx* c, const char* path) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  if (!path) return fail(c, ROMAP_E_INVALID_ARG, "path is NULL");
+  if (!c->objs.empty() || !c->kfs.empty()) return fail(c, ROMAP_E_STATE, "load needs an empty context");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(c, ROMAP_E_INVALID_ARG, std::string("cannot open ") + path);
+  bool ok = true;
+  auto R = [&](void* p, size_t n) { ok = ok && std::fread(p, 1, n, f) == n; };
+  char magic[8];
+  R(magic, 8);
+  romap_config cfg;
+  R(&cfg, sizeof(cfg));
+  if (!ok || std::memcmp(magic, kMagic, 8) != 0) {
+    std::fclose(f);
+    return fail(c, ROMAP_E_INVALID_ARG, "not a checkpoint");
+  }
+  if (cfg.n_levels != c->cfg.n_levels || cfg.base_res != c->cfg.base_res || cfg.max_res != c->cfg.max_res ||
+      cfg.samples_per_ray != c->cfg.samples_per_ray) {
+    std::fclose(f);
+    return fail(c, ROMAP_E_INVALID_ARG, "checkpoint model config differs from the context");
+  }
+  c->cfg.seed = cfg.seed;
+  int32_t nk = 0;
+  R(&nk, 4);
+  std::vector<romap_camera> cams(std::max(nk, 0));
+  romap_status s = ROMAP_OK;
+  // keyframes: re-added without the acceptance rule; object sets are restored below
+  std::vector<int> saved_active;
+  for (int i = 0; i < nk && ok; ++i) {
+    romap_camera cam;
+    R(&cam, sizeof(cam));
+    int32_t hd = 0;
+    R(&hd, 4);
+    const size_t npix = (size_t)cam.width * cam.height;
+    std::vector<uint8_t> rgb(npix * 3);
+    std::vector<int32_t> mask(npix);
+    std::vector<float> depth;
+    R(rgb.data(), rgb.size());
+    R(mask.data(), npix * 4);
+    if (hd) {
+      depth.resize(npix);
+      R(depth.data(), npix * 4);
+    }
+    if (!ok) break;
+    s = romap_add_keyframe(c, &cam, rgb.data(), mask.data(), hd ? depth.data() : nullptr, nullptr, nullptr);
+    if (s != ROMAP_OK) {
+      std::fclose(f);
+      return s;
+    }
+  }
+  int32_t no = 0;
+  R(&no, 4);
+  for (int i = 0; i < no && ok; ++i) {
+    int32_t inst, lt, act, step, hl, nref;
+    romap_box box;
+    double lc[3];
+    R(&inst, 4);
+    R(&lt, 4);
+    R(&act, 4);
+    R(&box, sizeof(box));
+    R(&step, 4);
+    R(&hl, 4);
+    R(lc, sizeof(lc));
+    R(&nref, 4);
+    if (!ok) break;
+    int32_t id = -1;
+    s = romap_add_object(c, inst, &box, lt, &id);
+    if (s != ROMAP_OK) {
+      std::fclose(f);
+      return s;
+    }
+    HostObj& o = c->objs[id];
+    o.active = act;
+    o.has_last = hl;
+    std::memcpy(o.last_centre, lc, sizeof(lc));
+    for (int k = 0; k < nref && ok; ++k) {
+      int32_t v[5];
+      R(v, sizeof(v));
+      if (!ok || v[0] < 0 || v[0] >= (int)c->kfs.size()) {
+        ok = false;
+        break;
+      }
+      KfRef r{};
+      r.kf = v[0];
+      r.x0 = v[1];
+      r.y0 = v[2];
+      r.w = v[3];
+      r.h = v[4];
+      object_frame(c->kfs[v[0]].cam.T_wc, o.box, r.M, r.c);
+      r.cand_begin = o.n_cand;
+      o.kfs.push_back(r);
+      o.n_cand += (int64_t)r.w * r.h;
+    }
+    std::vector<float> buf(3 * o.P_alloc);
+    R(buf.data(), buf.size() * 4);
+    if (!ok) break;
+    HIPCHK(c, hipMemcpy(o.d_block, buf.data(), o.P_alloc * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(o.d_block + 2 * o.P_alloc, buf.data() + o.P_alloc, 2 * o.P_alloc * 4, hipMemcpyHostToDevice));
+    ObjState st{};
+    st.step = step;
+    st.bc1 = step ? (float)(1.0 - std::pow((double)c->cfg.beta1, (double)step)) : 1.0f;
+    st.bc2 = step ? (float)(1.0 - std::pow((double)c->cfg.beta2, (double)step)) : 1.0f;
+    HIPCHK(c, hipMemcpy(c->d_state + id, &st, sizeof(st), hipMemcpyHostToDevice));
+    s = upload_object(c, id);
+    if (s != ROMAP_OK) {
+      std::fclose(f);
+      return s;
+    }
+  }
+  std::fclose(f);
+  if (!ok) return fail(c, ROMAP_E_INVALID_ARG, "truncated checkpoint");
+  return ROMAP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+"""C-ABI library checks that need no GPU: it loads and exports every symbol
+that include/romap.h declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2304_05735_amd", "libromap.so")
+HEADER = os.path.join(ROOT, "include", "romap.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:romap_status|const char\*)\s+(romap_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for verb in ("romap_create", "romap_add_object", "romap_add_keyframe", "romap_train",
+                 "romap_render", "romap_query_density", "romap_field_forward",
+                 "romap_field_backward"):
+        assert verb in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libromap.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libromap.so not built")
+def test_binding_names_match_header():
+    import paper_2304_05735_amd as pk
+    assert sorted(pk.EXPORTS) == declared_symbols()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libromap.so not built")
+def test_default_config_and_create_validation_without_gpu():
+    """Host-only calls: defaults, and argument checks that fail before any HIP call."""
+    import paper_2304_05735_amd as pk
+    cfg = pk.default_config()
+    assert (cfg.n_levels, cfg.base_res, cfg.max_res, cfg.log2_table_size) == (16, 16, 1024, 19)
+    assert cfg.samples_per_ray == 64 and cfg.rays_per_step == 4096
+    assert abs(cfg.lambda_depth - 0.5) < 1e-7 and abs(cfg.lambda_density - 0.01) < 1e-9
+    assert abs(cfg.alpha_deg - 25.0) < 1e-6
+    L = pk.lib()
+    h = ctypes.c_void_p()
+    for field, bad in [("n_levels", 17), ("samples_per_ray", 48), ("log2_table_size", 30),
+                       ("precision", 5), ("rays_per_step", 0)]:
+        c = pk.default_config(**{field: bad})
+        assert L.romap_create(ctypes.byref(c), None, ctypes.byref(h)) == pk.ROMAP_E_INVALID_ARG
+        assert L.romap_last_error(None)

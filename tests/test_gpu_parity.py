@@ -1,0 +1,310 @@
+"""GPU path vs the CPU oracle, element by element, on the same seeded inputs.
+
+Integer work (ray draws, classes, hash indices) and the FP32 position path are
+compared bit for bit; FP32 forward outputs to 1e-5 relative; gradients to
+1e-4.  Every test calls the library through the C ABI.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2304_05735_amd as pk
+import scenes
+from tests.gpu_common import assert_fwd_close, assert_grad_close, make_pair, oracle_grad
+from tests.tiny import random_params, tiny_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return tiny_scene(W=32, H=24, n_views=3)
+
+
+def _set_same_params(g, o, gid, seed=0, grid_scale=0.5):
+    ob = o.objects[gid]
+    p = random_params(oracle.grid_params(ob.lv), 2 * ob.lv.L, seed=seed, grid_scale=grid_scale)
+    p32 = p.astype(np.float32)
+    g.set_params(gid, p32)
+    ob.params[:] = p32.astype(np.float64)
+    return p32
+
+
+# ------------------------------------------------------------------ encoding
+@pytest.mark.parametrize("lt", [19, 12, 8])
+def test_hash_indices_bit_exact_and_features(tiny, lt):
+    _say("encode parity log2T", lt)
+    frames, box = tiny
+    g, o, gid = make_pair(16, 16, 1024, lt, 64, 256, frames, box)
+    p32 = _set_same_params(g, o, gid, seed=lt, grid_scale=1.0)
+    rng = np.random.default_rng(lt)
+    pts = rng.random((3000, 3)).astype(np.float32)
+    pts[:100] = np.round(pts[:100] * 16) / 16  # exact vertices of the coarse levels
+    pts[100:120] = 0.0
+    pts[120:140] = 1.0
+    idx, feat = g.debug_encode(gid, pts)
+    ob = o.objects[gid]
+    for i in range(pts.shape[0]):
+        oi, _, oe = oracle.encode(ob.lv, pts[i], ob.params)
+        assert np.array_equal(idx[i], oi), i
+        assert_fwd_close(feat[i].reshape(-1), oe, rtol=1e-5, atol=1e-6, what=f"feat {i}")
+
+
+# ------------------------------------------------------------------ rays
+@pytest.mark.parametrize("N", [32, 64, 128])
+def test_ray_draws_and_sample_positions_bit_exact(tiny, N):
+    _say("ray parity N", N)
+    frames, box = tiny
+    B = 1500
+    g, o, gid = make_pair(2, 16, 32, 8, N, B, frames, box)
+    kfuv, cls, rf, pos = g.debug_rays(gid, B)
+    _, _, rays = o.loss_and_grad(gid, 0, B, rays=True, want_grad=False)
+    ob = o.objects[gid]
+    seen = set()
+    for r in range(B):
+        ra = rays[r]
+        assert (kfuv[r, 0], kfuv[r, 1], kfuv[r, 2]) == (ra.kf, ra.u, ra.v), r
+        want_cls = ra.cls if ra.hit else -1
+        assert cls[r] == want_cls, r
+        seen.add(int(cls[r]))
+        if not ra.hit:
+            continue
+        assert np.array_equal(rf[r, 0:3], np.array(ra.o, np.float32))
+        assert np.array_equal(rf[r, 3:6], np.array(ra.d, np.float32))
+        assert rf[r, 6] == np.float32(ra.tn)
+        _, dist, opos = oracle.sample_positions(ra.o, ra.d, ob.half, ra.tn, ra.tf, N)
+        delta, _, _ = oracle.sample_positions(ra.o, ra.d, ob.half, ra.tn, ra.tf, N)
+        assert rf[r, 7] == np.float32(delta)
+        tgt = np.array(ra.Crand if ra.cls == 2 else ra.C, np.float32)
+        assert np.array_equal(rf[r, 8:11], tgt)
+        if ra.has_depth:
+            assert rf[r, 15] == 1.0 and rf[r, 11] == np.float32(ra.D)
+        assert np.array_equal(pos[r], opos), r
+    assert {0, 1, 2} <= seen
+
+
+# ------------------------------------------------------------------ one step
+@pytest.mark.parametrize("prec_case", ["L2_T8_N32", "L8_T12_N32", "L16_T19_N64", "L16_T15_N128"])
+def test_step_loss_and_gradient_parity(tiny, prec_case):
+    _say("step parity", prec_case)
+    frames, box = tiny
+    L, lt, N = {"L2_T8_N32": (2, 8, 32), "L8_T12_N32": (8, 12, 32), "L16_T19_N64": (16, 19, 64),
+                "L16_T15_N128": (16, 15, 128)}[prec_case]
+    nmax = {2: 32, 8: 128, 16: 1024}[L]
+    B = 192
+    g, o, gid = make_pair(L, 16, nmax, lt, N, B, frames, box)
+    _set_same_params(g, o, gid, seed=L + lt)
+    gl = g.loss_and_grad([gid])[0]
+    gg = g.get_params(gid, pk.GRAD)
+    ol, og, mass, allow, rays = oracle_grad(o, gid, 0, B, rays=True)
+    assert sum(1 for r in rays if r.hit and r.cls == 1) > 10
+    assert sum(1 for r in rays if r.hit and r.cls == 2) > 10
+    assert_fwd_close([gl], [ol], rtol=1e-5, what="loss")
+    Pg = oracle.grid_params(o.objects[gid].lv)
+    e_grid = assert_grad_close(gg[:Pg], og[:Pg], mass[:Pg], allow[:Pg], what="grid grad")
+    e_mlp = assert_grad_close(gg[Pg:], og[Pg:], mass[Pg:], allow[Pg:], what="mlp grad")
+    _say(f"  loss {gl:.6g} vs {ol:.6g}; grad rel err grid {e_grid:.2e} mlp {e_mlp:.2e}")
+
+
+def test_loss_and_grad_leaves_state_untouched(tiny):
+    frames, box = tiny
+    g, o, gid = make_pair(2, 16, 32, 8, 32, 128, frames, box)
+    _set_same_params(g, o, gid)
+    a = g.loss_and_grad([gid])[0]
+    b = g.loss_and_grad([gid])[0]
+    assert g.object_info(gid).step == 0
+    assert abs(a - b) <= 1e-6 * abs(a)
+
+
+# ------------------------------------------------------------------ Adam
+def test_dense_adam_matches_oracle(tiny):
+    """All rays miss the (displaced) box, so the step's gradient is zero and
+    only the gradient written into the buffer drives Adam; three steps check
+    the recurrence and the dense update of zero-gradient parameters."""
+    _say("adam parity")
+    frames, box = tiny
+    far = dict(box, t=np.array([30.0, 30.0, 30.0], np.float32))
+    g, o, gid = make_pair(2, 16, 32, 8, 32, 64, frames, far)
+    p0 = _set_same_params(g, o, gid)
+    P = p0.size
+    rng = np.random.default_rng(5)
+    g0 = rng.standard_normal(P).astype(np.float32) * 1e-2
+    g0[::7] = 0.0
+    Pg = oracle.grid_params(o.objects[gid].lv)
+    g.set_params(gid, g0, kind=pk.GRAD)
+    p = p0.astype(np.float64)
+    m = np.zeros(P)
+    v = np.zeros(P)
+    for k in (1, 2, 3):
+        g.train(1, [gid])
+        gk = np.zeros(P)
+        if k == 1:
+            gk[:Pg] = g0[:Pg]  # the MLP part is recomputed by the (empty) step: zero
+        oracle.adam(p, gk, m, v, k, 1e-2, 0.9, 0.99, 1e-15)
+        gp = g.get_params(gid)
+        assert_fwd_close(gp, p, rtol=2e-6, atol=2e-8, what=f"params after step {k}")
+        assert_fwd_close(g.get_params(gid, pk.ADAM_M), m, rtol=1e-5, atol=1e-10, what="m")
+        assert_fwd_close(g.get_params(gid, pk.ADAM_V), v, rtol=1e-5, atol=1e-14, what="v")
+    assert g.object_info(gid).step == 3
+    assert np.abs(g.get_params(gid, pk.GRAD)).max() == 0.0
+
+
+# ------------------------------------------------------------------ training steps
+def test_training_steps_track_oracle(tiny):
+    _say("train parity")
+    frames, box = tiny
+    B = 256
+    g, o, gid = make_pair(8, 16, 128, 12, 32, B, frames, box)
+    _set_same_params(g, o, gid, grid_scale=0.1)
+    gl = []
+    for _ in range(4):
+        st = g.train(1, [gid])
+        gl.append(st.loss_mean)
+    ol = o.train(gid, 4, B)
+    # the first loss is evaluated at identical parameters
+    assert_fwd_close([gl[0]], [ol[0]], rtol=1e-5, what="loss step 0")
+    # later steps differ only by FP32 rounding carried through Adam
+    assert_fwd_close(gl, ol, rtol=2e-2, what="loss curve")
+
+
+# ------------------------------------------------------------------ render / query
+def test_render_and_density_parity(tiny):
+    _say("render parity")
+    frames, box = tiny
+    g, o, gid = make_pair(8, 16, 128, 12, 64, 64, frames, box)
+    _set_same_params(g, o, gid, seed=3)
+    cam = scenes.camera(scenes.look_at((1.3, -0.9, 0.7), (0, 0, 0)), 40, 30, 36.0)
+    rgb, depth, opac = g.render(gid, cam)
+    orgb, odepth, oopac = o.render(gid, cam, 40, 30)
+    assert (oopac > 0.05).sum() > 100
+    assert_fwd_close(rgb, orgb, what="rgb")
+    assert_fwd_close(depth, odepth, what="depth")
+    assert_fwd_close(opac, oopac, rtol=1e-5, atol=2e-7, what="opacity")
+    rng = np.random.default_rng(9)
+    xyz = (rng.uniform(-1.1, 1.1, (4000, 3)) * box["half"]).astype(np.float32)
+    assert_fwd_close(g.query_density(gid, xyz), o.query_density(gid, xyz), what="sigma")
+
+
+# ------------------------------------------------------------------ many objects, one launch
+def test_batched_objects_match_per_object_oracle():
+    """Three objects with uneven tables and ray counts in one launch per phase."""
+    _say("batched parity")
+    wl = scenes.config3(n_obj=3, n_views=8, W=160, H=120, seed=1, room=4.0)
+    cfg = pk.default_config(samples_per_ray=32, autotune=0)
+    g = pk.Context(cfg)
+    ocfg = oracle.make_config(N=32)
+    o = oracle.OracleContext(ocfg)
+    rays = [300, 77, 1024]
+    lts = [15, 19, 16]
+    ids = []
+    for ob, lt in zip(wl.objects, lts):
+        ids.append(g.add_object(ob.instance, ob.t, ob.yaw, ob.half, lt))
+        o.add_object(ob.instance, ob.t, ob.yaw, ob.half, lt)
+    for cam, rgb, mask, depth in wl.frames:
+        g.add_keyframe(cam, rgb, mask, depth)
+        o.add_keyframe(cam, rgb, mask, depth)
+    for i in ids:
+        assert o.objects[i].kfs, "object never seen"
+        _set_same_params(g, o, i, seed=10 + i)
+    gl = g.loss_and_grad(ids, rays)
+    for k, i in enumerate(ids):
+        ol, og, mass, allow, _ = oracle_grad(o, i, 0, rays[k])
+        assert_fwd_close([gl[k]], [ol], what=f"loss obj {i}")
+        assert_grad_close(g.get_params(i, pk.GRAD), og, mass, allow, what=f"grad obj {i}")
+
+
+# ------------------------------------------------------------------ full size of the workload
+def test_full_size_workload_sampled():
+    """16 levels x 2^19, 4096 rays x 64 samples: every position bit-exact on a
+    sample of rays, the loss and the full gradient against the oracle."""
+    _say("full-size parity")
+    wl = scenes.config2(n_views=6)
+    ob = wl.objects[0]
+    B = 4096
+    frames = wl.frames
+    box = dict(instance=ob.instance, t=ob.t, yaw=ob.yaw, half=ob.half)
+    g, o, gid = make_pair(16, 16, 1024, 19, 64, B, frames, box)
+    # trained-like parameters: the library's own initialisation
+    p = g.get_params(gid)
+    o.objects[gid].params[:] = p.astype(np.float64)
+    kfuv, cls, rf, pos = g.debug_rays(gid, B)
+    _, _, rays = o.loss_and_grad(gid, 0, B, rays=True, want_grad=False)
+    for r in range(0, B, 37):
+        ra = rays[r]
+        assert (kfuv[r, 1], kfuv[r, 2]) == (ra.u, ra.v)
+        if ra.hit:
+            _, _, opos = oracle.sample_positions(ra.o, ra.d, ob.half, ra.tn, ra.tf, 64)
+            assert np.array_equal(pos[r], opos), r
+    gl = g.loss_and_grad([gid])[0]
+    gg = g.get_params(gid, pk.GRAD)
+    ol, og, mass, allow, _ = oracle_grad(o, gid, 0, B)
+    assert_fwd_close([gl], [ol], what="loss")
+    assert_grad_close(gg, og, mass, allow, what="grad")
+
+
+# ------------------------------------------------------------------ ABI contract
+def test_abi_errors_and_no_partial_state(tiny):
+    frames, box = tiny
+    g = pk.Context(pk.default_config(n_levels=2, base_res=16, max_res=32, log2_table_size=8,
+                                     samples_per_ray=32))
+    with pytest.raises(pk.RomapError) as e:
+        g.add_object(1, box["t"], box["yaw"], [0.3, -1.0, 0.3])
+    assert e.value.code == pk.ROMAP_E_INVALID_ARG
+    with pytest.raises(pk.RomapError) as e:
+        g.add_object(1, box["t"], box["yaw"], box["half"], log2T=30)
+    assert e.value.code == pk.ROMAP_E_INVALID_ARG
+    gid = g.add_object(1, box["t"], box["yaw"], box["half"])
+    with pytest.raises(pk.RomapError) as e:
+        g.add_object(1, box["t"], box["yaw"], box["half"])
+    assert e.value.code == pk.ROMAP_E_INVALID_ARG
+    with pytest.raises(pk.RomapError) as e:
+        g.train(1, [gid])
+    assert e.value.code == pk.ROMAP_E_STATE
+    with pytest.raises(pk.RomapError) as e:
+        g.train(1, [5])
+    assert e.value.code == pk.ROMAP_E_NOT_FOUND
+    cam, rgb, mask, depth = frames[0]
+    bad = dict(cam, fx=-1.0)
+    with pytest.raises(pk.RomapError):
+        g.add_keyframe(bad, rgb, mask, depth)
+    assert g.object_info(gid).n_keyframes == 0
+    g.add_keyframe(cam, rgb, mask, depth)
+    assert g.object_info(gid).n_keyframes == 1
+    with pytest.raises(pk.RomapError):
+        g.set_params(gid, np.zeros(3, np.float32))
+    st = g.train(2, [gid])
+    assert math.isfinite(st.loss_mean) and st.rays_trained == 2 * 4096
+    assert g.object_info(gid).step == 2
+
+
+def test_checkpoint_roundtrip_continues_identically(tiny, tmp_path):
+    frames, box = tiny
+    cfg = dict(n_levels=8, base_res=16, max_res=128, log2_table_size=12, samples_per_ray=32,
+               rays_per_step=256, autotune=0)
+    a = pk.Context(pk.default_config(**cfg))
+    gid = a.add_object(1, box["t"], box["yaw"], box["half"])
+    for cam, rgb, mask, depth in frames:
+        a.add_keyframe(cam, rgb, mask, depth)
+    a.train(3, [gid])
+    path = tmp_path / "ck.bin"
+    a.save(path)
+    b = pk.Context(pk.default_config(**cfg))
+    b.load(path)
+    assert np.array_equal(a.get_params(gid), b.get_params(0))
+    assert np.array_equal(a.get_params(gid, pk.ADAM_V), b.get_params(0, pk.ADAM_V))
+    assert b.object_info(0).step == 3 and b.object_info(0).n_keyframes == len(frames)
+    # the next draw is the same: identical rays, positions
+    ka, ca, ra, pa = a.debug_rays(gid, 256)
+    kb, cb, rb, pb = b.debug_rays(0, 256)
+    assert np.array_equal(ka, kb) and np.array_equal(pa, pb)
+    la = a.loss_and_grad([gid])[0]
+    lb = b.loss_and_grad([0])[0]
+    assert abs(la - lb) <= 1e-6 * abs(la)

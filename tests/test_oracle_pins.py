@@ -505,3 +505,73 @@ def test_config1_training_raises_psnr():
     after = mean_psnr()
     assert after > before + 3.0, (before, after)
     assert np.mean(losses[-10:]) < np.mean(losses[:10])
+
+
+def test_gradient_mass_bounds_gradient():
+    """The magnitude (backward on absolute values) bounds |gradient| entry by
+    entry; no magnitude, no gradient."""
+    ctx, oid, _ = _tiny_ctx(N=8)
+    o = ctx.objects[oid]
+    p = random_params(oracle.grid_params(o.lv), 4, seed=21, grid_scale=1.0)
+    mass = np.zeros(p.size)
+    _, g, _ = ctx.loss_and_grad(oid, 0, 32, params=p, mass=mass)
+    _, g2, _ = ctx.loss_and_grad(oid, 0, 32, params=p)
+    assert np.array_equal(g, g2)
+    assert (mass >= np.abs(g) * (1 - 1e-12)).all()
+    assert (g[mass == 0] == 0).all() and (mass > 0).sum() > 100
+
+
+def _pixel_rays(o, cam, half, pixels):
+    M, c = oracle.object_frame(cam["T_wc"], o.t, o.yaw)
+    rays = []
+    for (u, v) in pixels:
+        ro, rd = oracle.pixel_ray(M, c, cam["fx"], cam["fy"], cam["cx"], cam["cy"], u, v)
+        hit, tn, tf = oracle.slab(ro, rd, half)
+        rays.append(list(ro) + list(rd) + ([tn, tf] if hit else [0.0, 0.0]))
+    return np.array(rays, np.float32)
+
+
+def test_field_forward_equals_render_on_pixel_rays():
+    cfg = oracle.make_config(L=8, nmin=16, nmax=128, log2T=12, N=32)
+    ctx = oracle.OracleContext(cfg, nthreads=2)
+    half = np.array([0.4, 0.5, 0.3], np.float32)
+    oid = ctx.add_object(1, np.zeros(3, np.float32), 0.3, half)
+    o = ctx.objects[oid]
+    o.params[:] = random_params(oracle.grid_params(o.lv), 16, seed=31)
+    cam = scenes.camera(scenes.look_at((1.4, 0.9, 0.5), (0, 0, 0)), 20, 16, 18.0)
+    rgb, depth, opac = ctx.render(oid, cam, 20, 16)
+    pix = [(u, v) for v in range(16) for u in range(20)]
+    frgb, fdepth, ftend, _ = ctx.field(oid, _pixel_rays(o, cam, half, pix))
+    assert np.array_equal(frgb, rgb.reshape(-1, 3))
+    assert np.array_equal(fdepth, depth.reshape(-1))
+    assert np.allclose(1 - ftend, opac.reshape(-1), rtol=0, atol=1e-15)
+
+
+def test_field_gradient_matches_finite_differences():
+    """Gradient of sum(a.C + b D + c T_end) over every parameter of a small model."""
+    cfg = oracle.make_config(L=2, nmin=16, nmax=32, log2T=8, N=8)
+    ctx = oracle.OracleContext(cfg, nthreads=1)
+    half = np.array([0.4, 0.5, 0.3], np.float32)
+    oid = ctx.add_object(1, np.zeros(3, np.float32), 0.3, half)
+    o = ctx.objects[oid]
+    p = random_params(oracle.grid_params(o.lv), 4, seed=32, grid_scale=1.0)
+    cam = scenes.camera(scenes.look_at((1.4, 0.9, 0.5), (0, 0, 0)), 10, 8, 9.0)
+    rays = _pixel_rays(o, cam, half, [(u, v) for v in range(8) for u in range(10)])
+    rng = np.random.default_rng(33)
+    a, b, c = rng.standard_normal((80, 3)), rng.standard_normal(80), rng.standard_normal(80)
+
+    def obj(pp):
+        rgb, d, t, _ = ctx.field(oid, rays, params=pp)
+        return float(np.sum(a * rgb) + b @ d + c @ t)
+
+    _, _, _, g = ctx.field(oid, rays, params=p, d_rgb=a, d_depth=b, d_tend=c, grad=True)
+    fd = np.zeros(p.size)
+    for i in range(p.size):
+        h = 1e-6 * max(1.0, abs(p[i]))
+        pp = p.copy()
+        pp[i] += h
+        fp = obj(pp)
+        pp[i] -= 2 * h
+        fd[i] = (fp - obj(pp)) / (2 * h)
+    scale = np.abs(g).max()
+    assert np.all(np.abs(fd - g) <= 1e-6 * scale + 1e-5 * np.abs(g))
