@@ -324,31 +324,108 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
   a.e[(int64_t)l * a.S + s] = make_float2(ex, ey);
 }
 
-// K6: encoding backward: grad[idx_b] += w_b * de for the 8 corners
+// K6: encoding backward: grad[idx_b] += w_b * de for the 8 corners.
+//
+// Float atomics cost per cache line an instruction touches, not per float, so
+// the scatter is arranged to put several floats of one line into one
+// instruction.  One block covers 256 consecutive samples of one level:
+//  1. each lane forms its sample's 8 corner contributions (w_b * de);
+//  2. samples of a wave that fall in the same cell (consecutive along a ray,
+//     frequent on coarse levels) are merged by a segmented suffix sum, so the
+//     first sample of each run carries the run's total;
+//  3. the merged (index, value) pairs go through LDS and are issued with 16
+//     lanes per sample: lanes 4p..4p+3 hold corners 2p and 2p+1 (the x pair)
+//     and both features, i.e. two neighbouring table entries -- adjacent in a
+//     dense level, and in a hashed level as well, since x enters the hash with
+//     factor 1 -- so one instruction writes 16 contiguous bytes per pair.
 template <int NS>
-__global__ __launch_bounds__(512) void k_encode_bwd(StepArgs a) {
+__global__ __launch_bounds__(256) void k_encode_bwd(StepArgs a) {
+  __shared__ uint32_t s_idx[4][64 * 8];
+  __shared__ float2 s_val[4][64 * 8];
+  __shared__ float* s_ptr[4][64];
   const int l = blockIdx.y;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.S) return;
-  const int r = (int)(s / NS), i = (int)(s % NS);
-  const RayRec R = a.rays[r];
-  if (!ray_active(R.flags)) return;
-  const ObjStatic& ob = a.objs[R.obj];
-  const float2 g = a.de[(int64_t)l * a.S + s];
-  if (g.x == 0.0f && g.y == 0.0f) return;
-  float p[3];
-  sample_pos(R, i, ob.half, p);
-  const uint32_t N = ob.N_l[l], T = ob.T_l[l];
-  const bool hashed = (ob.hashed_mask >> l) & 1u;
-  Cell cl;
-  make_cell(p, N, cl);
-  float* Gg = (a.grad_override ? a.grad_override : ob.grad) + ob.off[l];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool act = s < a.S;
+  RayRec R;
+  float2 g = make_float2(0.0f, 0.0f);
+  if (act) {
+    R = a.rays[s / NS];
+    act = ray_active(R.flags);
+  }
+  if (act) {
+    g = a.de[(int64_t)l * a.S + s];
+    act = !(g.x == 0.0f && g.y == 0.0f);
+  }
+  uint64_t key = ~0ull - (uint64_t)lane;  // distinct keys for idle lanes
+  uint32_t idx[8];
+  float2 v[8];
+  float* gbase = nullptr;
+  if (act) {
+    const ObjStatic& ob = a.objs[R.obj];
+    float p[3];
+    sample_pos(R, (int)(s % NS), ob.half, p);
+    const uint32_t N = ob.N_l[l], T = ob.T_l[l];
+    const bool hashed = (ob.hashed_mask >> l) & 1u;
+    Cell cl;
+    make_cell(p, N, cl);
+    key = (uint64_t)cl.c[0] | ((uint64_t)cl.c[1] << 16) | ((uint64_t)cl.c[2] << 32) |
+          ((uint64_t)(uint32_t)R.obj << 48);
+    gbase = (a.grad_override ? a.grad_override : ob.grad) + ob.off[l];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      idx[b] = corner_index(cl, b, N, T, hashed);
+      const float w = corner_weight(cl, b);
+      v[b] = make_float2(w * g.x, w * g.y);
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      idx[b] = 0xFFFFFFFFu;
+      v[b] = make_float2(0.0f, 0.0f);
+    }
+  }
+  // runs of equal cells: lane e is the last lane of this lane's run
+  const uint64_t knext = __shfl_down(key, 1, 64);
+  const bool tail = (lane == 63) || (knext != key);
+  const uint64_t tails = __ballot(tail);
+  const uint64_t kprev = __shfl_up(key, 1, 64);
+  const bool head = (lane == 0) || (kprev != key);
+  if (tails != ~0ull) {  // some run is longer than one sample
+    const int e = lane + __builtin_ctzll(tails >> lane);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const float yx = __shfl_down(v[b].x, o, 64);
+        const float yy = __shfl_down(v[b].y, o, 64);
+        if (lane + o <= e) {
+          v[b].x += yx;
+          v[b].y += yy;
+        }
+      }
+    }
+  }
+  const bool emit = act && head;
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    const uint32_t id = corner_index(cl, b, N, T, hashed);
-    const float w = corner_weight(cl, b);
-    unsafeAtomicAdd(Gg + 2 * (int64_t)id, w * g.x);
-    unsafeAtomicAdd(Gg + 2 * (int64_t)id + 1, w * g.y);
+    s_idx[wave][lane * 8 + b] = emit ? idx[b] : 0xFFFFFFFFu;
+    s_val[wave][lane * 8 + b] = v[b];
+  }
+  s_ptr[wave][lane] = gbase;
+  wave_lds_sync();
+  const int k = lane & 15;
+  const int b = ((k >> 2) << 1) | ((k >> 1) & 1);
+  const int f = k & 1;
+#pragma unroll 4
+  for (int it = 0; it < 16; ++it) {
+    const int smp = it * 4 + (lane >> 4);
+    const uint32_t id = s_idx[wave][smp * 8 + b];
+    if (id != 0xFFFFFFFFu) {
+      const float2 val = s_val[wave][smp * 8 + b];
+      const float x = f ? val.y : val.x;
+      if (x != 0.0f) unsafeAtomicAdd(s_ptr[wave][smp] + 2 * (int64_t)id + f, x);
+    }
   }
 }
 
@@ -849,20 +926,26 @@ __global__ __launch_bounds__(RM_WG) void k_field(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// K5: per-object MLP gradient (sum of the work-item records in item order,
-// deterministic) and loss; advances the Adam step counter.
+// K5: per-object MLP gradient (sum of the work-item records, in a fixed
+// order: deterministic) and loss; advances the Adam step counter.  A block
+// owns 64 gradient entries; its 4 waves sum interleaved quarters of the
+// items, then combine in LDS.
 __global__ __launch_bounds__(256) void k_reduce(StepArgs a) {
+  __shared__ float s_part[4][64];
   const StepObj so = a.sobj[blockIdx.y];
   const ObjStatic& ob = a.objs[so.obj];
   const int nm = (int)(ob.P - ob.P_grid);
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
   float* gdst = a.grad_override ? a.grad_override : ob.grad;
-  if (j < nm) {
-    float s = 0.0f;
-    for (int it = so.item_begin; it < so.item_end; ++it)
-      s += a.partials[(int64_t)it * RM_REC_STRIDE + j];
-    gdst[ob.P_grid + j] = s;
-  }
+  float acc = 0.0f;
+  if (j < nm)
+    for (int it = so.item_begin + wave; it < so.item_end; it += 4)
+      acc += a.partials[(int64_t)it * RM_REC_STRIDE + j];
+  s_part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && j < nm)
+    gdst[ob.P_grid + j] = (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
   if (blockIdx.x == 0 && threadIdx.x == 0 && a.mode == RM_MODE_TRAIN) {
     float l = 0.0f;
     for (int it = so.item_begin; it < so.item_end; ++it)
@@ -871,10 +954,10 @@ __global__ __launch_bounds__(256) void k_reduce(StepArgs a) {
     st->loss_acc += l;
     st->n_loss += 1;
     if (a.advance) {
-      const int k = st->step + 1;
-      st->step = k;
-      st->bc1 = (float)(1.0 - pow((double)a.beta1, (double)k));
-      st->bc2 = (float)(1.0 - pow((double)a.beta2, (double)k));
+      const int kk = st->step + 1;
+      st->step = kk;
+      st->bc1 = (float)(1.0 - pow((double)a.beta1, (double)kk));
+      st->bc2 = (float)(1.0 - pow((double)a.beta2, (double)kk));
     }
   }
 }
@@ -1058,9 +1141,10 @@ hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int L, int block, hip
 }
 
 hipError_t rm_launch_encode_bwd(const StepArgs& a, int NS, int L, int block, hipStream_t st) {
+  (void)block;  // fixed 256-thread blocks (the LDS staging is sized for 4 waves)
   if (a.S <= 0) return hipSuccess;
-  dim3 grid(cdiv(a.S, block), L);
-  RM_NS_SWITCH(NS, (k_encode_bwd<NSC><<<grid, block, 0, st>>>(a)));
+  dim3 grid(cdiv(a.S, 256), L);
+  RM_NS_SWITCH(NS, (k_encode_bwd<NSC><<<grid, 256, 0, st>>>(a)));
   return hipGetLastError();
 }
 
@@ -1085,7 +1169,7 @@ hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStrea
 
 hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
-  dim3 grid(cdiv(n_mlp_max, 256), a.n_sobj);
+  dim3 grid(cdiv(n_mlp_max, 64), a.n_sobj);
   k_reduce<<<grid, 256, 0, st>>>(a);
   return hipGetLastError();
 }

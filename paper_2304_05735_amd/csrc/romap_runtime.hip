@@ -430,9 +430,10 @@ std::vector<int64_t> signature(romap_ctx* c, const std::vector<std::pair<int, in
   return s;
 }
 
-// Tile autotuner: times the fused field kernel for each ray-tile size and the
-// encoding gather for each block size on the real work list, keeps the
-// fastest.  Only scratch buffers are written (rays, encodings, records).
+// Tile autotuner: times the fused field kernel plus the record reduction for
+// each ray-tile size, and the encoding gather for each block size, on the
+// real work list; keeps the fastest.  Only scratch buffers and the gradient
+// buffer's MLP part (rewritten by every step) are written.
 romap_status autotune(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int* rpi,
                       int* blk) {
   auto key = signature(c, list);
@@ -459,9 +460,15 @@ romap_status autotune(romap_ctx* c, const std::vector<std::pair<int, int>>& list
     HIPCHK(c, rm_launch_raygen(a, NS, c->stream));
     HIPCHK(c, rm_launch_encode_fwd(a, NS, L, 256, c->stream));
     HIPCHK(c, rm_launch_pack(a, K1, c->stream));
+    StepArgs ar = a;  // the reduce only reads the records here: no step advance, no loss
+    ar.mode = RM_MODE_ADJOINT;
+    ar.advance = 0;
     HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
     HIPCHK(c, hipEventRecord(e0, c->stream));
-    for (int r = 0; r < 3; ++r) HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
+    for (int r = 0; r < 3; ++r) {
+      HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
+      HIPCHK(c, rm_launch_reduce(ar, RM_MLP_MAX, c->stream));
+    }
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));
     float ms = 0.0f;

@@ -53,9 +53,9 @@ def test_autograd_field_matches_oracle(L, lt, N):
     rgb, depth, tend = field(rays)
     orgb, odepth, otend, _ = o.field(oid, rays_np)
     torch.cuda.synchronize()
-    assert_fwd_close(rgb.cpu().numpy(), orgb, what="rgb")
-    assert_fwd_close(depth.cpu().numpy(), odepth, what="depth")
-    assert_fwd_close(tend.cpu().numpy(), otend, what="tend")
+    assert_fwd_close(rgb.detach().cpu().numpy(), orgb, what="rgb")
+    assert_fwd_close(depth.detach().cpu().numpy(), odepth, what="depth")
+    assert_fwd_close(tend.detach().cpu().numpy(), otend, what="tend")
     rng = np.random.default_rng(42)
     a = rng.standard_normal((rays_np.shape[0], 3)).astype(np.float32)
     b = rng.standard_normal(rays_np.shape[0]).astype(np.float32)
