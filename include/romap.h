@@ -148,6 +148,20 @@ romap_status romap_add_object(romap_ctx* ctx, int32_t instance_id, const romap_b
 romap_status romap_set_object_active(romap_ctx* ctx, int32_t object_id, int32_t active);
 romap_status romap_get_object_info(romap_ctx* ctx, int32_t object_id, romap_object_info* info);
 
+/* Occupancy skip for long ray budgets (not in the paper; used by the
+ * incremental mapping stream): a 64^3 bitfield over the object's box, bit
+ * x + 64 y + 4096 z (least significant bit first in each byte) for the cell
+ * floor(64 p) of a sample at normalised position p (clamped to 0..63).  A
+ * sample in a clear cell has density 0: it skips the encoding, adds nothing
+ * to rendering, the density loss or the gradient.  Applies to training,
+ * rendering and the differentiable surface; not to romap_query_density.
+ *   set:    bits = 32768 host bytes, or NULL to switch skipping off
+ *   update: bits = (density at the cell centre > threshold), switches it on
+ *   get:    copies the bits out (ROMAP_E_STATE if skipping is off) */
+romap_status romap_set_occupancy(romap_ctx* ctx, int32_t object_id, const uint8_t* bits);
+romap_status romap_update_occupancy(romap_ctx* ctx, int32_t object_id, float threshold);
+romap_status romap_get_occupancy(romap_ctx* ctx, int32_t object_id, uint8_t* bits);
+
 /* Adds a posed keyframe (Sec. V-A "Data").  rgb: H*W*3 bytes; mask: H*W
  * int32 instance ids, 0 = background; depth_z: H*W camera z of sparse depth,
  * <= 0 or non-finite = none, may be NULL.  For every registered object seen

@@ -94,11 +94,11 @@ def lib():
                                      C.POINTER(Keyframe), C.c_int, C.POINTER(Ray)]
         _lib.or_object_step.argtypes = [C.POINTER(Config), C.POINTER(Levels), C.c_int, C.c_int, P,
                                         C.c_int, C.POINTER(Keyframe), C.c_int, C.c_int, P, P, P, P,
-                                        P, P, C.POINTER(Ray), C.c_int]
+                                        P, P, P, C.POINTER(Ray), C.c_int]
         _lib.or_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int, C.c_double, C.c_double,
                                  C.c_double, C.c_double]
         _lib.or_render.argtypes = [C.POINTER(Config), C.POINTER(Levels), P, C.POINTER(Keyframe), P,
-                                   P, P, P, C.c_int]
+                                   P, P, P, P, C.c_int]
         _lib.or_query_density.argtypes = [C.POINTER(Levels), P, P, C.c_int64, P, P]
         _lib.or_philox4x32_10.argtypes = [P, P, P]
         _lib.or_field.argtypes = [C.POINTER(Config), C.POINTER(Levels), P, P, C.c_int, P, P, P, P,
@@ -262,6 +262,7 @@ class _Obj:
         self.grad = np.zeros_like(params)
         self.k = 0
         self.kfs: list[tuple[_Kf, tuple]] = []  # (keyframe, candidate rect)
+        self.occ = None  # 64^3 occupancy bits (32768 bytes) or None
         self.last_centre = None
 
 
@@ -346,6 +347,7 @@ class OracleContext:
         ray_buf = (Ray * B)() if rays else None
         rc = lib().or_object_step(C.byref(self.cfg), C.byref(o.lv), oid, o.instance, _p(o.half),
                                   len(o.kfs), kfa, int(step), int(B), _p(p),
+                                  None if o.occ is None else _p(o.occ),
                                   _p(grad) if want_grad else None,
                                   _p(mass) if (want_grad and mass is not None) else None,
                                   None if ambiguous is None else _p(ambiguous),
@@ -380,7 +382,8 @@ class OracleContext:
         depth = np.zeros((H, W))
         opac = np.zeros((H, W))
         lib().or_render(C.byref(self.cfg), C.byref(o.lv), _p(o.half), C.byref(kf), _p(o.params),
-                        _p(rgb), _p(depth), _p(opac), self.nthreads)
+                        None if o.occ is None else _p(o.occ), _p(rgb), _p(depth), _p(opac),
+                        self.nthreads)
         return rgb, depth, opac
 
     def field(self, oid, rays, params=None, d_rgb=None, d_depth=None, d_tend=None, grad=False,
@@ -402,6 +405,20 @@ class OracleContext:
                        None if (g is None or mass is None) else _p(mass),
                        None if (g is None or ambiguous is None) else _p(ambiguous), self.nthreads)
         return rgb, depth, tend, g
+
+    def set_occupancy(self, oid, bits):
+        """64^3 occupancy bitfield (32768 bytes, bit x + 64 y + 4096 z) or None."""
+        self.objects[oid].occ = None if bits is None else np.ascontiguousarray(bits, np.uint8)
+
+    def occupancy_from_density(self, oid, threshold):
+        """Bits of the cells whose centre density exceeds threshold."""
+        o = self.objects[oid]
+        g = (np.arange(64, dtype=np.float64) + 0.5) / 64.0
+        z, y, x = np.meshgrid(g, g, g, indexing="ij")
+        p = np.stack([x, y, z], -1).reshape(-1, 3)
+        xyz = (p * (2.0 * o.half) - o.half).astype(np.float32)
+        sig = self.query_density(oid, xyz)
+        return np.packbits(sig > threshold, bitorder="little")
 
     def query_density(self, oid, xyz):
         o = self.objects[oid]

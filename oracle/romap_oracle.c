@@ -355,6 +355,7 @@ typedef struct {
   uint32_t* idx;
   double *w, *e, *h1, *y, *h2, *sigma, *rgb, *dist, *wts, *dsig, *dsig_m, *tnext;
   float *pos, *dist32;
+  int* live; /* sample not skipped by the occupancy bitfield */
 } or_scratch;
 
 static void scratch_alloc(or_scratch* s, int N, int L) {
@@ -373,12 +374,13 @@ static void scratch_alloc(or_scratch* s, int N, int L) {
   s->tnext = (double*)malloc(sizeof(double) * N);
   s->pos = (float*)malloc(sizeof(float) * N * 3);
   s->dist32 = (float*)malloc(sizeof(float) * N);
+  s->live = (int*)malloc(sizeof(int) * N);
 }
 
 static void scratch_free(or_scratch* s) {
   free(s->idx); free(s->w); free(s->e); free(s->h1); free(s->y); free(s->h2);
   free(s->sigma); free(s->rgb); free(s->dist); free(s->wts); free(s->dsig); free(s->dsig_m); free(s->tnext);
-  free(s->pos); free(s->dist32);
+  free(s->pos); free(s->dist32); free(s->live);
 }
 
 /* Backward of one sample through the MLPs and the encoding.  dsig, dc are
@@ -494,21 +496,39 @@ static void sample_backward_magnitude(const or_levels* lv, int din, const double
     }
 }
 
+/* Occupancy skip (an addition to the paper's method for long ray budgets): a
+ * 64^3 bitfield over the object's unit cube, bit x + 64 y + 4096 z of cell
+ * (floor(64 p), clamped), least significant bit first in each byte.  A sample
+ * in a cell whose bit is 0 has density 0: it adds nothing to the rendering,
+ * the density loss or the gradient. */
+int or_occupied(const uint8_t* occ, const float p[3]) {
+  if (!occ) return 1;
+  int c[3];
+  for (int k = 0; k < 3; ++k) {
+    int ci = (int)floorf(p[k] * 64.0f);
+    c[k] = ci < 0 ? 0 : (ci > 63 ? 63 : ci);
+  }
+  const int bit = c[0] + 64 * c[1] + 4096 * c[2];
+  return (occ[bit >> 3] >> (bit & 7)) & 1;
+}
+
 /* Forward of one ray with N uniform samples in [tn, tf]: positions, encoding,
  * MLPs (kept in s for the backward), and Eq. 6 (plus T_end C_rand for a
  * background ray). */
 static void ray_forward(const or_levels* lv, int N, const double* params, const float o[3],
                         const float d[3], const float half[3], float tn, float tf, float* delta,
                         or_scratch* s, int bg, const double crand[3], double C[3], double* D,
-                        double* Tend) {
+                        double* Tend, const uint8_t* occ) {
   const int L = lv->L, din = 2 * L;
   const double* mlp = params + or_grid_params(lv);
   or_sample_positions(o, d, half, tn, tf, N, delta, s->dist32, s->pos);
   for (int i = 0; i < N; ++i) s->dist[i] = (double)s->dist32[i];
   for (int i = 0; i < N; ++i) {
+    s->live[i] = or_occupied(occ, s->pos + 3 * i);
     or_encode(lv, s->pos + 3 * i, params, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i);
     or_mlp_forward(din, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * i, s->y + OR_DOUT * i,
                    s->h2 + OR_HIDDEN * i, s->sigma + i, s->rgb + 3 * i);
+    if (!s->live[i]) s->sigma[i] = 0.0;
   }
   or_composite(N, s->sigma, s->rgb, s->dist, (double)*delta, bg, crand, C, D, Tend, s->wts);
 }
@@ -539,17 +559,18 @@ static void ray_backward(const or_levels* lv, int N, const double* params, doubl
       for (int k = 0; k < 3; ++k) a -= gC[k] * Tend * crand[k];
     a += gD * (Tnext[i] * s->dist[i] - suf_d);
     a -= gT * Tend;
-    s->dsig[i] = a * delta + dens;
+    s->dsig[i] = s->live[i] ? a * delta + dens : 0.0;
     /* magnitude of the same adjoint (for the tolerance of the tests) */
     for (int k = 0; k < 3; ++k) am += fabs(gC[k]) * (Tnext[i] * s->rgb[3 * i + k] + suf_c[k]);
     if (bg)
       for (int k = 0; k < 3; ++k) am += fabs(gC[k]) * Tend * crand[k];
     am += fabs(gD) * (Tnext[i] * s->dist[i] + suf_d) + fabs(gT) * Tend;
-    s->dsig_m[i] = am * delta + dens;
+    s->dsig_m[i] = s->live[i] ? am * delta + dens : 0.0;
     for (int k = 0; k < 3; ++k) suf_c[k] += s->wts[i] * s->rgb[3 * i + k];
     suf_d += s->wts[i] * s->dist[i];
   }
   for (int i = 0; i < N; ++i) {
+    if (!s->live[i]) continue; /* density 0 by construction: no dependence on parameters */
     double dci[3];
     for (int k = 0; k < 3; ++k) dci[k] = s->wts[i] * gC[k];
     sample_backward(lv, din, mlp, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i,
@@ -612,6 +633,7 @@ static double tie_allowance(const or_levels* lv, int N, const double* params, or
   const double* mlp = params + or_grid_params(lv);
   double rm = dtie;
   for (int i = 0; i < N; ++i) {
+    if (!s->live[i]) continue;
     const double sm = sample_ties(2 * L, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * i,
                                   s->y + OR_DOUT * i);
     rm = fmin(rm, sm);
@@ -641,8 +663,9 @@ static void reduce_threads(const double* t, int nthreads, int64_t P, double* out
 
 int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int instance,
                    const float half[3], int nkf, const or_keyframe* kfs, int step, int B,
-                   const double* params, double* grad, double* grad_abs, double* ambiguous,
-                   double* min_margin, double* loss, or_ray* rays, int nthreads) {
+                   const double* params, const uint8_t* occ, double* grad, double* grad_abs,
+                   double* ambiguous, double* min_margin, double* loss, or_ray* rays,
+                   int nthreads) {
   if (nkf < 1 || B < 1 || cfg->N < 1) return -1;
   const int L = lv->L, N = cfg->N;
   const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L);
@@ -678,7 +701,7 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
         double crand[3] = {ray.Crand[0], ray.Crand[1], ray.Crand[2]};
         const int bg = ray.cls == 2;
         ray_forward(lv, N, params, ray.o, ray.d, half, ray.tn, ray.tf, &ray.delta, &s, bg, crand,
-                    ray.Chat, &ray.Dhat, &ray.Tend);
+                    ray.Chat, &ray.Dhat, &ray.Tend, occ);
         /* Eq. 7-11: squared colour error against the image (object rays) or
          * the random colour (background rays); depth and density terms. */
         double target[3];
@@ -763,7 +786,9 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
       double C[3] = {0.0, 0.0, 0.0}, D = 0.0, Tend = 1.0;
       float delta = 0.0f;
       const int hit = q[7] > q[6];
-      if (hit) ray_forward(lv, N, params, q, q + 3, half, q[6], q[7], &delta, &s, 0, zero, C, &D, &Tend);
+      if (hit)
+        ray_forward(lv, N, params, q, q + 3, half, q[6], q[7], &delta, &s, 0, zero, C, &D, &Tend,
+                    NULL);
       for (int k = 0; k < 3; ++k) rgb[3 * r + k] = C[k];
       depth[r] = D;
       tend[r] = Tend;
@@ -803,8 +828,8 @@ void or_adam(int64_t P, double* p, double* g, double* m, double* v, int k, doubl
 /* Render every pixel of a camera through the object's box (evaluation and
  * meshing); composited on black, opacity = 1 - T_end.  Misses give 0. */
 int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
-              const or_keyframe* cam, const double* params, double* rgb, double* depth,
-              double* opacity, int nthreads) {
+              const or_keyframe* cam, const double* params, const uint8_t* occ, double* rgb,
+              double* depth, double* opacity, int nthreads) {
   const int L = lv->L, N = cfg->N, din = 2 * L;
   const double* mlp = params + or_grid_params(lv);
   const int64_t npix = (int64_t)cam->W * cam->H;
@@ -825,6 +850,7 @@ int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
           s.dist[i] = (double)s.dist32[i];
           or_encode(lv, s.pos + 3 * i, params, s.idx, s.w, s.e);
           or_mlp_forward(din, mlp, s.e, s.h1, s.y, s.h2, s.sigma + i, s.rgb + 3 * i);
+          if (!or_occupied(occ, s.pos + 3 * i)) s.sigma[i] = 0.0;
         }
         double zero[3] = {0.0, 0.0, 0.0};
         or_composite(N, s.sigma, s.rgb, s.dist, (double)dl, 0, zero, C, &D, &Tend, s.wts);

@@ -75,8 +75,9 @@ void or_draw_ray(const or_config* cfg, int obj, int step, int r, int nkf, const 
                  int instance, or_ray* out);
 int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int instance,
                    const float half[3], int nkf, const or_keyframe* kfs, int step, int B,
-                   const double* params, double* grad, double* grad_abs, double* ambiguous,
-                   double* min_margin, double* loss, or_ray* rays, int nthreads);
+                   const double* params, const uint8_t* occ, double* grad, double* grad_abs,
+                   double* ambiguous, double* min_margin, double* loss, or_ray* rays,
+                   int nthreads);
 int or_field(const or_config* cfg, const or_levels* lv, const float half[3], const double* params,
              int n, const float* rays, double* rgb, double* depth, double* tend,
              const double* d_rgb, const double* d_depth, const double* d_tend, double* grad,
@@ -84,8 +85,9 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
 void or_adam(int64_t P, double* p, double* g, double* m, double* v, int k, double lr, double b1,
              double b2, double eps);
 int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
-              const or_keyframe* cam, const double* params, double* rgb, double* depth,
-              double* opacity, int nthreads);
+              const or_keyframe* cam, const double* params, const uint8_t* occ, double* rgb,
+              double* depth, double* opacity, int nthreads);
+int or_occupied(const uint8_t* occ, const float p[3]);
 void or_query_density(const or_levels* lv, const float half[3], const double* params, int64_t n,
                       const float* xyz, double* sigma);
 

@@ -76,7 +76,8 @@ EXPORTS = ["romap_default_config", "romap_create", "romap_destroy", "romap_last_
            "romap_add_keyframe", "romap_train", "romap_loss_and_grad", "romap_render",
            "romap_query_density", "romap_get_params", "romap_set_params", "romap_save",
            "romap_load", "romap_debug_rays", "romap_debug_encode", "romap_field_forward",
-           "romap_field_backward", "romap_get_phase_times", "romap_sync"]
+           "romap_field_backward", "romap_get_phase_times", "romap_sync", "romap_set_occupancy",
+           "romap_update_occupancy", "romap_get_occupancy"]
 
 
 def lib():
@@ -112,6 +113,9 @@ def lib():
             "romap_field_backward": [P, i32, P, P, i32, P, P, P, P],
             "romap_get_phase_times": [P, P, C.POINTER(i32)],
             "romap_sync": [P],
+            "romap_set_occupancy": [P, i32, P],
+            "romap_update_occupancy": [P, i32, C.c_float],
+            "romap_get_occupancy": [P, i32, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -301,6 +305,19 @@ class Context:
                                                _ptr(d_rgb), _ptr(d_depth), _ptr(d_tend),
                                                _ptr(out)))
         return out
+
+    def set_occupancy(self, oid, bits):
+        b = None if bits is None else np.ascontiguousarray(bits, np.uint8)
+        assert b is None or b.size == 32768
+        self._check(lib().romap_set_occupancy(self.h, int(oid), _ptr(b)))
+
+    def update_occupancy(self, oid, threshold):
+        self._check(lib().romap_update_occupancy(self.h, int(oid), float(threshold)))
+
+    def get_occupancy(self, oid):
+        b = np.zeros(32768, np.uint8)
+        self._check(lib().romap_get_occupancy(self.h, int(oid), _ptr(b)))
+        return b
 
     def phase_times(self):
         """Average ms per kernel over the steps of the last profiled train call."""

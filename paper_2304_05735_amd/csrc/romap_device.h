@@ -14,6 +14,10 @@
 #define RM_WPACK 10240      /* packed MLP weight image, elements (K1 <= 32) */
 #define RM_WG 256           /* threads of the fused field kernel (4 waves) */
 #define RM_ADAM_CHUNK 8192  /* floats per Adam work chunk */
+#define RM_RB_BITS 13       /* binned scatter: table entries per region = 8192 (64 KiB) */
+#define RM_RB (1 << RM_RB_BITS)
+#define RM_BIN_MIN_T 65536  /* hashed levels with at least this many entries are binned */
+#define RM_MAX_REGIONS 2048 /* 2^24 / 2^13 */
 
 // Offsets of the eight packed GEMM operands inside a weight image.
 #define RM_OFF_F1 0     /* W1        64 x K1  */
@@ -65,11 +69,13 @@ struct ObjStatic {      // written by the host
   uint32_t N_l[RM_MAX_LEVELS];
   uint32_t T_l[RM_MAX_LEVELS];
   uint32_t hashed_mask;
+  uint32_t binned_mask; // levels whose gradient goes through the binned scatter
   int32_t L, din, instance, id, n_kf;
   float half[3];
   int32_t pad;
   const KfRef* kfs;
   int64_t n_cand;
+  const uint32_t* occ;  // 64^3 occupancy bits, or null (no skipping)
 };
 
 struct ObjState {       // written by the device
@@ -111,6 +117,26 @@ struct Chunk {          // one workgroup of the Adam kernel
   int64_t begin;
 };
 
+struct BinPair {        // one (object of the launch, binned level)
+  int32_t so, l;
+  int32_t nb;           // sample blocks of 256 of the object
+  int32_t R;            // regions of the level's table
+  int64_t cm_base;      // count matrix [R][nb] of this pair
+  int64_t rec_base;     // first record slot of this pair
+  int32_t bin_base;     // first bin (region) of this pair
+  int32_t cap;          // record slots per bin
+  int64_t s_begin;      // first sample of the object
+  int64_t n_samples;
+};
+
+struct BinBlock {       // one block of 256 samples of one binned pair
+  int32_t pair, blk;
+};
+
+struct Bin {            // one region of one binned pair
+  int32_t pair, region;
+};
+
 struct StepArgs {
   const ObjStatic* objs;
   ObjState* state;
@@ -144,12 +170,24 @@ struct StepArgs {
   float* out_tend;
   int32_t* dbg_kfuv;    // raygen: kf, u, v per ray (may be null)
   int32_t* dbg_cls;
+  // binned scatter of the hashed levels
+  const BinPair* bpairs;
+  int32_t n_bpairs;
+  const BinBlock* bblocks;
+  int32_t n_bblocks;
+  const Bin* bins;
+  int32_t n_bins;
+  int32_t* cm;          // counts, then offsets, [R][nb] per pair
+  int32_t* bin_count;   // records per bin
+  uint32_t* rec_idx;    // entry index within the region
+  float2* rec_val;
 };
 
 // Launch helpers implemented in romap_kernels.hip.
 hipError_t rm_launch_raygen(const StepArgs& a, int NS, hipStream_t st);
 hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int L, int block, hipStream_t st);
 hipError_t rm_launch_encode_bwd(const StepArgs& a, int NS, int L, int block, hipStream_t st);
+hipError_t rm_launch_binned_bwd(const StepArgs& a, int NS, hipStream_t st);
 hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st);
 hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStream_t st);
 hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st);
@@ -163,6 +201,8 @@ hipError_t rm_launch_query_density(const ObjStatic* objs, int obj, const float* 
 hipError_t rm_launch_debug_encode(const ObjStatic* objs, int obj, const float* p, int64_t n,
                                   uint32_t* idx, float* feat, hipStream_t st);
 hipError_t rm_launch_fill(float* x, int64_t n, float v, hipStream_t st);
+hipError_t rm_launch_occ_update(const ObjStatic* objs, int obj, uint32_t* bits, float threshold,
+                                hipStream_t st);
 hipError_t rm_launch_init(float* params, int64_t P_grid, int din, uint32_t k0, uint32_t k1,
                           hipStream_t st);
 hipError_t rm_launch_debug_positions(const StepArgs& a, int NS, float* pos, hipStream_t st);

@@ -105,6 +105,20 @@ __device__ inline void sample_pos(const RayRec& R, int i, const float* half, flo
   }
 }
 
+// Occupancy skip: 64^3 bits over the unit cube, bit x + 64 y + 4096 z of cell
+// floor(64 p) (clamped).  A sample in a clear cell has density 0.
+__device__ inline bool occupied(const uint32_t* occ, const float p[3]) {
+  if (!occ) return true;
+  int c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int ci = (int)floorf(p[k] * 64.0f);
+    c[k] = ci < 0 ? 0 : (ci > 63 ? 63 : ci);
+  }
+  const int bit = c[0] + 64 * c[1] + 4096 * c[2];
+  return (occ[bit >> 5] >> (bit & 31)) & 1u;
+}
+
 struct Cell {
   uint32_t c[3];
   float f[3];
@@ -307,6 +321,10 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
   const ObjStatic& ob = a.objs[R.obj];
   float p[3];
   sample_pos(R, i, ob.half, p);
+  if (!occupied(ob.occ, p)) {  // skipped sample: no gather, zero encoding
+    a.e[(int64_t)l * a.S + s] = make_float2(0.0f, 0.0f);
+    return;
+  }
   const uint32_t N = ob.N_l[l], T = ob.T_l[l];
   const bool hashed = (ob.hashed_mask >> l) & 1u;
   Cell cl;
@@ -353,6 +371,7 @@ __global__ __launch_bounds__(256) void k_encode_bwd(StepArgs a) {
     R = a.rays[s / NS];
     act = ray_active(R.flags);
   }
+  if (act) act = !((a.objs[R.obj].binned_mask >> l) & 1u);  // handled by the binned scatter
   if (act) {
     g = a.de[(int64_t)l * a.S + s];
     act = !(g.x == 0.0f && g.y == 0.0f);
@@ -426,6 +445,144 @@ __global__ __launch_bounds__(256) void k_encode_bwd(StepArgs a) {
       const float x = f ? val.y : val.x;
       if (x != 0.0f) unsafeAtomicAdd(s_ptr[wave][smp] + 2 * (int64_t)id + f, x);
     }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Binned scatter of the hashed levels (tables of >= 2^16 entries).  A hashed
+// level spreads a sample's corners uniformly over its table and no two
+// samples of a ray share a cell, so run merging finds nothing there and every
+// float atomic touches its own cache line.  Instead the (entry, value)
+// records are sorted into regions of 2^13 entries (64 KiB), and one
+// workgroup per region sums them in LDS and updates the region of the
+// gradient with coalesced loads and stores:
+//   k_bin_count    per block of 256 samples: records per region
+//   k_bin_scan     per region: each block's offset inside the region's bin
+//   k_bin_scatter  write the records (a full bin falls back to atomics)
+//   k_bin_acc      per region: LDS sum, then gradient += region image
+
+// The 8 corner records of sample s at the pair's level; false if none.
+template <int NS>
+__device__ inline bool bin_records(const StepArgs& a, const BinPair& bp, int64_t s,
+                                   uint32_t idx[8], float2 v[8]) {
+  const RayRec R = a.rays[s / NS];
+  if (!ray_active(R.flags)) return false;
+  const int l = bp.l;
+  const float2 g = a.de[(int64_t)l * a.S + s];
+  if (g.x == 0.0f && g.y == 0.0f) return false;
+  const ObjStatic& ob = a.objs[R.obj];
+  float p[3];
+  sample_pos(R, (int)(s % NS), ob.half, p);
+  Cell cl;
+  make_cell(p, ob.N_l[l], cl);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    idx[b] = corner_index(cl, b, ob.N_l[l], ob.T_l[l], true);
+    const float w = corner_weight(cl, b);
+    v[b] = make_float2(w * g.x, w * g.y);
+  }
+  return true;
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_bin_count(StepArgs a) {
+  __shared__ int hist[RM_MAX_REGIONS];
+  const BinBlock bb = a.bblocks[blockIdx.x];
+  const BinPair bp = a.bpairs[bb.pair];
+  for (int r = threadIdx.x; r < bp.R; r += 256) hist[r] = 0;
+  __syncthreads();
+  const int64_t k = (int64_t)bb.blk * 256 + threadIdx.x;
+  uint32_t idx[8];
+  float2 v[8];
+  if (k < bp.n_samples && bin_records<NS>(a, bp, bp.s_begin + k, idx, v)) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) atomicAdd(&hist[idx[b] >> RM_RB_BITS], 1);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < bp.R; r += 256)
+    a.cm[bp.cm_base + (int64_t)r * bp.nb + bb.blk] = hist[r];
+}
+
+// one wave per bin: exclusive scan of the blocks' counts, total of the bin
+__global__ __launch_bounds__(64) void k_bin_scan(StepArgs a) {
+  const Bin bn = a.bins[blockIdx.x];
+  const BinPair bp = a.bpairs[bn.pair];
+  int32_t* row = a.cm + bp.cm_base + (int64_t)bn.region * bp.nb;
+  const int lane = threadIdx.x;
+  int carry = 0;
+  for (int c0 = 0; c0 < bp.nb; c0 += 64) {
+    const int c = c0 + lane;
+    const int x = c < bp.nb ? row[c] : 0;
+    int inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
+    }
+    if (c < bp.nb) row[c] = carry + inc - x;
+    carry += __shfl(inc, 63, 64);
+  }
+  if (lane == 0) a.bin_count[bp.bin_base + bn.region] = carry;
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_bin_scatter(StepArgs a) {
+  __shared__ int rank[RM_MAX_REGIONS];
+  const BinBlock bb = a.bblocks[blockIdx.x];
+  const BinPair bp = a.bpairs[bb.pair];
+  for (int r = threadIdx.x; r < bp.R; r += 256) rank[r] = 0;
+  __syncthreads();
+  const int64_t k = (int64_t)bb.blk * 256 + threadIdx.x;
+  uint32_t idx[8];
+  float2 v[8];
+  if (k < bp.n_samples && bin_records<NS>(a, bp, bp.s_begin + k, idx, v)) {
+    const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
+    float* gl = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int r = (int)(idx[b] >> RM_RB_BITS);
+      const int pos = a.cm[bp.cm_base + (int64_t)r * bp.nb + bb.blk] + atomicAdd(&rank[r], 1);
+      if (pos < bp.cap) {
+        const int64_t slot = bp.rec_base + (int64_t)r * bp.cap + pos;
+        a.rec_idx[slot] = idx[b] & (RM_RB - 1);
+        a.rec_val[slot] = v[b];
+      } else {  // bin full: direct atomics (correct, only slower)
+        unsafeAtomicAdd(gl + 2 * (int64_t)idx[b], v[b].x);
+        unsafeAtomicAdd(gl + 2 * (int64_t)idx[b] + 1, v[b].y);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bin_acc(StepArgs a) {
+  __shared__ float2 img[RM_RB];
+  const Bin bn = a.bins[blockIdx.x];
+  const BinPair bp = a.bpairs[bn.pair];
+  for (int e = threadIdx.x; e < RM_RB; e += 256) img[e] = make_float2(0.0f, 0.0f);
+  __syncthreads();
+  int n = a.bin_count[bp.bin_base + bn.region];
+  n = n < bp.cap ? n : bp.cap;
+  const int64_t base = bp.rec_base + (int64_t)bn.region * bp.cap;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const uint32_t e = a.rec_idx[base + i];
+    const float2 v = a.rec_val[base + i];
+    atomicAdd(&img[e].x, v.x);
+    atomicAdd(&img[e].y, v.y);
+  }
+  __syncthreads();
+  const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
+  float4* gr = (float4*)((a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l] +
+                         2 * (int64_t)bn.region * RM_RB);
+  const float4* im = (const float4*)img;
+  for (int q = threadIdx.x; q < RM_RB / 2; q += 256) {
+    float4 g = gr[q];
+    const float4 d = im[q];
+    g.x += d.x;
+    g.y += d.y;
+    g.z += d.z;
+    g.w += d.w;
+    gr[q] = g;
   }
 }
 
@@ -725,7 +882,14 @@ __global__ __launch_bounds__(RM_WG) void k_field(StepArgs a) {
           c[j][0] = q[1];
           c[j][1] = q[2];
           c[j][2] = q[3];
-          sig[j] = expf(fminf(y0[j], 15.0f));
+          bool live = true;
+          if (ob.occ) {
+            float p[3];
+            sample_pos(R, i, ob.half, p);
+            live = occupied(ob.occ, p);
+          }
+          sig[j] = live ? expf(fminf(y0[j], 15.0f)) : 0.0f;
+          if (!live) y0[j] = 16.0f;  // no density adjoint either
           tau[j] = sig[j] * R.delta;
           dist[j] = R.tn + ((float)i + 0.5f) * R.delta;
         } else {
@@ -926,10 +1090,10 @@ __global__ __launch_bounds__(RM_WG) void k_field(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// K5: per-object MLP gradient (sum of the work-item records, in a fixed
-// order: deterministic) and loss; advances the Adam step counter.  A block
-// owns 64 gradient entries; its 4 waves sum interleaved quarters of the
-// items, then combine in LDS.
+// K5: per-object MLP gradient and loss from the work-item records, summed in
+// a fixed order (deterministic); advances the Adam step counter.  A block owns
+// 64 record columns (column RM_REC_LOSS is the loss); its 4 waves sum
+// interleaved quarters of the items, then combine in LDS.
 __global__ __launch_bounds__(256) void k_reduce(StepArgs a) {
   __shared__ float s_part[4][64];
   const StepObj so = a.sobj[blockIdx.y];
@@ -937,21 +1101,21 @@ __global__ __launch_bounds__(256) void k_reduce(StepArgs a) {
   const int nm = (int)(ob.P - ob.P_grid);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
-  float* gdst = a.grad_override ? a.grad_override : ob.grad;
+  const bool used = j < nm || j == RM_REC_LOSS;
   float acc = 0.0f;
-  if (j < nm)
+  if (used)
     for (int it = so.item_begin + wave; it < so.item_end; it += 4)
       acc += a.partials[(int64_t)it * RM_REC_STRIDE + j];
   s_part[wave][lane] = acc;
   __syncthreads();
-  if (wave == 0 && j < nm)
-    gdst[ob.P_grid + j] = (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.mode == RM_MODE_TRAIN) {
-    float l = 0.0f;
-    for (int it = so.item_begin; it < so.item_end; ++it)
-      l += a.partials[(int64_t)it * RM_REC_STRIDE + RM_REC_LOSS];
+  if (wave != 0 || !used) return;
+  const float tot = (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
+  if (j < nm) {
+    float* gdst = a.grad_override ? a.grad_override : ob.grad;
+    gdst[ob.P_grid + j] = tot;
+  } else if (a.mode == RM_MODE_TRAIN) {
     ObjState* st = a.state + so.obj;
-    st->loss_acc += l;
+    st->loss_acc += tot;
     st->n_loss += 1;
     if (a.advance) {
       const int kk = st->step + 1;
@@ -1109,6 +1273,45 @@ __global__ void k_reset_loss(StepArgs a) {
   st->n_loss = 0;
 }
 
+// occupancy refresh: bit = density at the cell centre > threshold; a wave
+// covers 64 consecutive cells and stores its two words from a ballot
+__global__ __launch_bounds__(256) void k_occ_update(const ObjStatic* objs, int obj,
+                                                   uint32_t* bits, float threshold) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;  // < 64^3, grid exact
+  const ObjStatic& ob = objs[obj];
+  const float p[3] = {((float)(cell & 63) + 0.5f) / 64.0f,
+                      ((float)((cell >> 6) & 63) + 0.5f) / 64.0f,
+                      ((float)(cell >> 12) + 0.5f) / 64.0f};
+  float e[2 * RM_MAX_LEVELS];
+  for (int l = 0; l < ob.L; ++l) {
+    Cell cl;
+    make_cell(p, ob.N_l[l], cl);
+    const bool hashed = (ob.hashed_mask >> l) & 1u;
+    const float* G = ob.params + ob.off[l];
+    float ex = 0.0f, ey = 0.0f;
+    for (int b = 0; b < 8; ++b) {
+      const uint32_t id = corner_index(cl, b, ob.N_l[l], ob.T_l[l], hashed);
+      const float w = corner_weight(cl, b);
+      ex = fmaf(w, G[2 * (int64_t)id], ex);
+      ey = fmaf(w, G[2 * (int64_t)id + 1], ey);
+    }
+    e[2 * l] = ex;
+    e[2 * l + 1] = ey;
+  }
+  const float* W1 = ob.params + ob.P_grid;
+  const float* W2 = W1 + RM_HIDDEN * ob.din;
+  float y0 = 0.0f;
+  for (int h = 0; h < RM_HIDDEN; ++h) {
+    float sacc = 0.0f;
+    for (int k = 0; k < ob.din; ++k) sacc = fmaf(W1[h * ob.din + k], e[k], sacc);
+    y0 = fmaf(W2[h], sacc > 0.0f ? sacc : 0.0f, y0);
+  }
+  const bool on = expf(fminf(y0, 15.0f)) > threshold;
+  const uint64_t m = __ballot(on);
+  const int lane = threadIdx.x & 63;
+  if (lane < 2) bits[(cell >> 5) + lane] = (uint32_t)(m >> (32 * lane));
+}
+
 __global__ void k_fill(float* x, int64_t n, float v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -1148,6 +1351,19 @@ hipError_t rm_launch_encode_bwd(const StepArgs& a, int NS, int L, int block, hip
   return hipGetLastError();
 }
 
+hipError_t rm_launch_binned_bwd(const StepArgs& a, int NS, hipStream_t st) {
+  if (a.n_bblocks <= 0) return hipSuccess;
+  RM_NS_SWITCH(NS, (k_bin_count<NSC><<<a.n_bblocks, 256, 0, st>>>(a)));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_bin_scan<<<a.n_bins, 64, 0, st>>>(a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  RM_NS_SWITCH(NS, (k_bin_scatter<NSC><<<a.n_bblocks, 256, 0, st>>>(a)));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_bin_acc<<<a.n_bins, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
 hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
   k_pack<<<a.n_sobj, 256, 0, st>>>(a, K1);
@@ -1169,7 +1385,8 @@ hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStrea
 
 hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
-  dim3 grid(cdiv(n_mlp_max, 64), a.n_sobj);
+  (void)n_mlp_max;
+  dim3 grid(cdiv(RM_REC_LOSS + 1, 64), a.n_sobj);
   k_reduce<<<grid, 256, 0, st>>>(a);
   return hipGetLastError();
 }
@@ -1234,6 +1451,12 @@ hipError_t rm_launch_debug_positions(const StepArgs& a, int NS, float* pos, hipS
 hipError_t rm_launch_reset_loss(const StepArgs& a, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
   k_reset_loss<<<cdiv(a.n_sobj, 64), 64, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_occ_update(const ObjStatic* objs, int obj, uint32_t* bits, float threshold,
+                                hipStream_t st) {
+  k_occ_update<<<(64 * 64 * 64) / 256, 256, 0, st>>>(objs, obj, bits, threshold);
   return hipGetLastError();
 }
 

@@ -45,17 +45,24 @@ struct HostObj {
   int64_t n_cand = 0;
   bool has_last = false;
   double last_centre[3]{};
+  uint32_t* d_occ = nullptr;  // 64^3 occupancy bits
+  bool occ_on = false;
 };
 
 struct Plan {                 // one launch: its objects, rays and work lists
   std::vector<StepObj> sobj;
   std::vector<Item> items;
   std::vector<Chunk> chunks;
+  std::vector<BinPair> bpairs;
+  std::vector<BinBlock> bblocks;
+  std::vector<Bin> bins;
+  int64_t cm_size = 0, rec_size = 0;
   int n_rays = 0;
   int64_t S = 0;
   int rays_per_item = 8;
   int enc_block = 256;
   size_t off_sobj = 0, off_items = 0, off_chunks = 0;  // in the device table arena (bytes)
+  size_t off_bpairs = 0, off_bblocks = 0, off_bins = 0;
 };
 
 template <class T>
@@ -101,6 +108,14 @@ struct romap_ctx {
   size_t cap_w32 = 0, cap_w16 = 0;
   char* d_tables = nullptr;
   size_t cap_tables = 0;
+  int32_t* d_cm = nullptr;
+  size_t cap_cm = 0;
+  int32_t* d_bin_count = nullptr;
+  size_t cap_bin_count = 0;
+  uint32_t* d_rec_idx = nullptr;
+  size_t cap_rec_idx = 0;
+  float2* d_rec_val = nullptr;
+  size_t cap_rec_val = 0;
   // graph of the last batched step
   hipGraphExec_t gexec = nullptr;
   std::vector<int64_t> gsig;
@@ -224,6 +239,9 @@ ObjStatic to_static(const HostObj& o) {
     s.T_l[l] = o.T_l[l];
   }
   s.hashed_mask = o.hashed_mask;
+  s.binned_mask = 0;
+  for (int l = 0; l < o.L; ++l)
+    if (((o.hashed_mask >> l) & 1u) && o.T_l[l] >= RM_BIN_MIN_T) s.binned_mask |= 1u << l;
   s.L = o.L;
   s.din = o.din;
   s.instance = o.instance;
@@ -232,6 +250,7 @@ ObjStatic to_static(const HostObj& o) {
   for (int k = 0; k < 3; ++k) s.half[k] = o.box.half[k];
   s.kfs = o.d_kfs;
   s.n_cand = o.n_cand;
+  s.occ = o.occ_on ? o.d_occ : nullptr;
   return s;
 }
 
@@ -261,6 +280,10 @@ StepArgs base_args(romap_ctx* c) {
   a.kfs = c->d_kfdev;
   a.rays = c->d_rays;
   a.e = c->d_e;
+  a.cm = c->d_cm;
+  a.bin_count = c->d_bin_count;
+  a.rec_idx = c->d_rec_idx;
+  a.rec_val = c->d_rec_val;
   a.de = c->d_de;
   a.partials = c->d_partials;
   a.wpack32 = c->d_wpack32;
@@ -319,6 +342,35 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
   p.n_rays = ray;
   p.S = (int64_t)ray * c->cfg.samples_per_ray;
   build_items(p);
+  // binned scatter of the large hashed levels
+  const int NS = c->cfg.samples_per_ray;
+  for (size_t i = 0; i < p.sobj.size(); ++i) {
+    const HostObj& o = c->objs[p.sobj[i].obj];
+    const int64_t So = (int64_t)p.sobj[i].n_rays * NS;
+    for (int l = 0; l < o.L; ++l) {
+      if (!(((o.hashed_mask >> l) & 1u) && o.T_l[l] >= RM_BIN_MIN_T)) continue;
+      BinPair bp{};
+      bp.so = (int)i;
+      bp.l = l;
+      bp.nb = (int)((So + 255) / 256);
+      bp.R = (int)(o.T_l[l] >> RM_RB_BITS);
+      // records per region: 8 So / R on average (uniform hash); twice that
+      // plus a margin, a full bin falls back to atomics
+      const int64_t expect = (8 * So + bp.R - 1) / bp.R;
+      bp.cap = (int)std::min<int64_t>(2 * expect + 1024, 8 * So);
+      bp.cm_base = p.cm_size;
+      p.cm_size += (int64_t)bp.R * bp.nb;
+      bp.rec_base = p.rec_size;
+      p.rec_size += (int64_t)bp.R * bp.cap;
+      bp.bin_base = (int)p.bins.size();
+      bp.s_begin = (int64_t)p.sobj[i].ray_begin * NS;
+      bp.n_samples = So;
+      const int pi = (int)p.bpairs.size();
+      p.bpairs.push_back(bp);
+      for (int b = 0; b < bp.nb; ++b) p.bblocks.push_back(BinBlock{pi, b});
+      for (int r = 0; r < bp.R; ++r) p.bins.push_back(Bin{pi, r});
+    }
+  }
 }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -326,7 +378,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Makes sure the scratch buffers fit a set of plans, then uploads their
 // work tables into the table arena.
 romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
-  size_t max_rays = 0, max_items = 0, max_sobj = 0, tab = 0;
+  size_t max_rays = 0, max_items = 0, max_sobj = 0, tab = 0, max_cm = 0, max_rec = 0, max_bins = 0;
   int64_t max_S = 0;
   for (Plan* p : plans) {
     max_rays = std::max(max_rays, (size_t)p->n_rays);
@@ -339,6 +391,15 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
     tab += align256(p->items.size() * sizeof(Item));
     p->off_chunks = tab;
     tab += align256(p->chunks.size() * sizeof(Chunk));
+    p->off_bpairs = tab;
+    tab += align256(p->bpairs.size() * sizeof(BinPair));
+    p->off_bblocks = tab;
+    tab += align256(p->bblocks.size() * sizeof(BinBlock));
+    p->off_bins = tab;
+    tab += align256(p->bins.size() * sizeof(Bin));
+    max_cm = std::max(max_cm, (size_t)p->cm_size);
+    max_rec = std::max(max_rec, (size_t)p->rec_size);
+    max_bins = std::max(max_bins, p->bins.size());
   }
   const size_t L = (size_t)c->cfg.n_levels;
   auto regrow = [&](auto** ptr, size_t* cap, size_t need) -> hipError_t {
@@ -358,11 +419,18 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
   HIPALLOC(c, regrow(&c->d_wpack32, &c->cap_w32, std::max<size_t>(max_sobj * RM_WPACK, 1)));
   HIPALLOC(c, regrow(&c->d_wpack16, &c->cap_w16, std::max<size_t>(max_sobj * RM_WPACK, 1)));
   HIPALLOC(c, regrow(&c->d_tables, &c->cap_tables, std::max<size_t>(tab, 256)));
+  HIPALLOC(c, regrow(&c->d_cm, &c->cap_cm, std::max<size_t>(max_cm, 1)));
+  HIPALLOC(c, regrow(&c->d_bin_count, &c->cap_bin_count, std::max<size_t>(max_bins, 1)));
+  HIPALLOC(c, regrow(&c->d_rec_idx, &c->cap_rec_idx, std::max<size_t>(max_rec, 1)));
+  HIPALLOC(c, regrow(&c->d_rec_val, &c->cap_rec_val, std::max<size_t>(max_rec, 1)));
   std::vector<char> h(tab);
   for (Plan* p : plans) {
     if (!p->sobj.empty()) std::memcpy(h.data() + p->off_sobj, p->sobj.data(), p->sobj.size() * sizeof(StepObj));
     if (!p->items.empty()) std::memcpy(h.data() + p->off_items, p->items.data(), p->items.size() * sizeof(Item));
     if (!p->chunks.empty()) std::memcpy(h.data() + p->off_chunks, p->chunks.data(), p->chunks.size() * sizeof(Chunk));
+    if (!p->bpairs.empty()) std::memcpy(h.data() + p->off_bpairs, p->bpairs.data(), p->bpairs.size() * sizeof(BinPair));
+    if (!p->bblocks.empty()) std::memcpy(h.data() + p->off_bblocks, p->bblocks.data(), p->bblocks.size() * sizeof(BinBlock));
+    if (!p->bins.empty()) std::memcpy(h.data() + p->off_bins, p->bins.data(), p->bins.size() * sizeof(Bin));
   }
   if (tab) HIPCHK(c, hipMemcpyAsync(c->d_tables, h.data(), tab, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -379,6 +447,16 @@ StepArgs plan_args(romap_ctx* c, const Plan& p) {
   a.n_chunks = (int)p.chunks.size();
   a.n_rays = p.n_rays;
   a.S = p.S;
+  a.bpairs = (const BinPair*)(c->d_tables + p.off_bpairs);
+  a.n_bpairs = (int)p.bpairs.size();
+  a.bblocks = (const BinBlock*)(c->d_tables + p.off_bblocks);
+  a.n_bblocks = (int)p.bblocks.size();
+  a.bins = (const Bin*)(c->d_tables + p.off_bins);
+  a.n_bins = (int)p.bins.size();
+  a.cm = c->d_cm;
+  a.bin_count = c->d_bin_count;
+  a.rec_idx = c->d_rec_idx;
+  a.rec_val = c->d_rec_val;
   return a;
 }
 
@@ -400,6 +478,7 @@ hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a, bool ada
   if ((e = rm_launch_field(a, NS, K1, c->cfg.precision, c->stream)) != hipSuccess) return e;
   RM_MARK(4);
   if ((e = rm_launch_encode_bwd(a, NS, L, p.enc_block, c->stream)) != hipSuccess) return e;
+  if ((e = rm_launch_binned_bwd(a, NS, c->stream)) != hipSuccess) return e;
   RM_MARK(5);
   if ((e = rm_launch_reduce(a, RM_MLP_MAX, c->stream)) != hipSuccess) return e;
   RM_MARK(6);
@@ -648,6 +727,7 @@ romap_status romap_destroy(romap_ctx* c) {
   for (auto& o : c->objs) {
     hipFree(o.d_block);
     hipFree(o.d_kfs);
+    hipFree(o.d_occ);
   }
   for (auto& k : c->kfs) {
     hipFree(k.d_rgb);
@@ -664,6 +744,10 @@ romap_status romap_destroy(romap_ctx* c) {
   hipFree(c->d_wpack32);
   hipFree(c->d_wpack16);
   hipFree(c->d_tables);
+  hipFree(c->d_cm);
+  hipFree(c->d_bin_count);
+  hipFree(c->d_rec_idx);
+  hipFree(c->d_rec_val);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
   return ROMAP_OK;
@@ -760,6 +844,47 @@ romap_status romap_set_object_active(romap_ctx* c, int32_t id, int32_t active) {
   romap_status s = check_object(c, id);
   if (s != ROMAP_OK) return s;
   c->objs[id].active = active ? 1 : 0;
+  return ROMAP_OK;
+}
+
+static const size_t kOccBytes = 64 * 64 * 64 / 8;
+
+romap_status romap_set_occupancy(romap_ctx* c, int32_t id, const uint8_t* bits) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  HostObj& o = c->objs[id];
+  if (!bits) {
+    o.occ_on = false;
+    return upload_object(c, id);
+  }
+  if (!o.d_occ) HIPALLOC(c, hipMalloc((void**)&o.d_occ, kOccBytes));
+  HIPCHK(c, hipMemcpyAsync(o.d_occ, bits, kOccBytes, hipMemcpyHostToDevice, c->stream));
+  o.occ_on = true;
+  return upload_object(c, id);
+}
+
+romap_status romap_update_occupancy(romap_ctx* c, int32_t id, float threshold) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  if (!std::isfinite(threshold)) return fail(c, ROMAP_E_INVALID_ARG, "non-finite threshold");
+  HostObj& o = c->objs[id];
+  if (!o.d_occ) HIPALLOC(c, hipMalloc((void**)&o.d_occ, kOccBytes));
+  HIPCHK(c, rm_launch_occ_update(c->d_objs, id, o.d_occ, threshold, c->stream));
+  o.occ_on = true;
+  return upload_object(c, id);
+}
+
+romap_status romap_get_occupancy(romap_ctx* c, int32_t id, uint8_t* bits) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  if (!bits) return fail(c, ROMAP_E_INVALID_ARG, "bits is NULL");
+  const HostObj& o = c->objs[id];
+  if (!o.occ_on) return fail(c, ROMAP_E_STATE, "occupancy skipping is off for this object");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(bits, o.d_occ, kOccBytes, hipMemcpyDeviceToHost));
   return ROMAP_OK;
 }
 
@@ -1083,7 +1208,11 @@ romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, flo
     const int nr = (int)std::min<int64_t>(chunk, npix - p0);
     Plan p;
     build_plan(c, {{id, nr}}, 8, 256, p);
-    p.chunks.clear();
+    p.chunks.clear();  // forward only: no Adam, no gradient scatter
+    p.bpairs.clear();
+    p.bblocks.clear();
+    p.bins.clear();
+    p.cm_size = p.rec_size = 0;
     s = stage_plans(c, {&p});
     if (s != ROMAP_OK) return s;
     StepArgs a = plan_args(c, p);
@@ -1309,6 +1438,7 @@ romap_status romap_field_backward(romap_ctx* c, int32_t id, const float* params_
   HIPCHK(c, rm_launch_fill(d_params_dev, o.P, 0.0f, c->stream));
   HIPCHK(c, rm_launch_field(a, NS, K1_of(c->cfg), c->cfg.precision, c->stream));
   HIPCHK(c, rm_launch_encode_bwd(a, NS, L, 256, c->stream));
+  HIPCHK(c, rm_launch_binned_bwd(a, NS, c->stream));
   HIPCHK(c, rm_launch_reduce(a, RM_MLP_MAX, c->stream));
   return ROMAP_OK;
 }

@@ -308,3 +308,40 @@ def test_checkpoint_roundtrip_continues_identically(tiny, tmp_path):
     la = a.loss_and_grad([gid])[0]
     lb = b.loss_and_grad([0])[0]
     assert abs(la - lb) <= 1e-6 * abs(la)
+
+
+# ------------------------------------------------------------------ occupancy skip
+def test_occupancy_skip_parity(tiny):
+    _say("occupancy parity")
+    frames, box = tiny
+    B = 256
+    g, o, gid = make_pair(8, 16, 128, 12, 64, B, frames, box)
+    _set_same_params(g, o, gid, seed=7, grid_scale=1.0)
+    ob = o.objects[gid]
+    cells = (np.arange(64) + 0.5) / 64.0
+    z, y, x = np.meshgrid(cells, cells, cells, indexing="ij")
+    xyz = (np.stack([x, y, z], -1).reshape(-1, 3) * (2.0 * ob.half) - ob.half).astype(np.float32)
+    dens = o.query_density(gid, xyz)
+    thr = float(np.median(dens))
+    bits = np.packbits(dens > thr, bitorder="little")
+    g.set_occupancy(gid, bits)
+    o.set_occupancy(gid, bits)
+    assert np.array_equal(g.get_occupancy(gid), bits)
+    gl = g.loss_and_grad([gid])[0]
+    gg = g.get_params(gid, pk.GRAD)
+    ol, og, mass, allow, _ = oracle_grad(o, gid, 0, B)
+    assert_fwd_close([gl], [ol], what="loss with occupancy")
+    assert_grad_close(gg, og, mass, allow, what="grad with occupancy")
+    cam = scenes.camera(scenes.look_at((1.3, -0.9, 0.7), (0, 0, 0)), 40, 30, 36.0)
+    rgb, _, opac = g.render(gid, cam)
+    orgb, _, oopac = o.render(gid, cam, 40, 30)
+    assert_fwd_close(rgb, orgb, what="rgb with occupancy")
+    assert_fwd_close(opac, oopac, rtol=1e-5, atol=2e-7, what="opacity with occupancy")
+    # refresh rule: bit = density at the cell centre > threshold
+    g.update_occupancy(gid, thr)
+    gb = np.unpackbits(g.get_occupancy(gid), bitorder="little").astype(bool)
+    sure = np.abs(dens - thr) > 1e-4 * thr
+    assert np.array_equal(gb[sure], (dens > thr)[sure])
+    g.set_occupancy(gid, None)
+    with pytest.raises(pk.RomapError):
+        g.get_occupancy(gid)

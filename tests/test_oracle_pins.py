@@ -575,3 +575,44 @@ def test_field_gradient_matches_finite_differences():
         fd[i] = (fp - obj(pp)) / (2 * h)
     scale = np.abs(g).max()
     assert np.all(np.abs(fd - g) <= 1e-6 * scale + 1e-5 * np.abs(g))
+
+
+# ---------------------------------------------------------------- occupancy skip
+def test_occupancy_all_set_changes_nothing_and_all_clear_kills_density():
+    ctx, oid, _ = _tiny_ctx(N=16, L=8, nmax=128, log2T=12)
+    o = ctx.objects[oid]
+    p = random_params(oracle.grid_params(o.lv), 16, seed=61, grid_scale=1.0)
+    B = 200
+    l0, g0, rays = ctx.loss_and_grad(oid, 0, B, params=p, rays=True)
+    ctx.set_occupancy(oid, np.full(32768, 255, np.uint8))
+    l1, g1, _ = ctx.loss_and_grad(oid, 0, B, params=p)
+    assert l1 == l0 and np.array_equal(g1, g0)
+    ctx.set_occupancy(oid, np.zeros(32768, np.uint8))
+    l2, g2, _ = ctx.loss_and_grad(oid, 0, B, params=p)
+    # density 0 everywhere: object rays render black at depth 0, background
+    # rays render their random colour exactly, no density term; nothing
+    # depends on the parameters
+    want = sum(sum(float(c) ** 2 for c in r.C) + (0.5 * r.D if r.has_depth else 0.0)
+               for r in rays if r.hit and r.cls == 1) / B
+    assert math.isclose(l2, want, rel_tol=1e-12)
+    assert not g2.any()
+
+
+def test_occupancy_bit_layout():
+    bits = np.zeros(32768, np.uint8)
+    lib = oracle.lib()
+    lib.or_occupied.argtypes = [oracle.C.c_void_p, oracle.C.c_void_p]
+    def occ(p):
+        pp = np.asarray(p, np.float32)
+        return lib.or_occupied(bits.ctypes.data_as(oracle.C.c_void_p), pp.ctypes.data_as(oracle.C.c_void_p))
+    for cell in [(0, 0, 0), (63, 0, 0), (5, 17, 40), (63, 63, 63)]:
+        bits[:] = 0
+        b = cell[0] + 64 * cell[1] + 4096 * cell[2]
+        bits[b >> 3] = 1 << (b & 7)
+        centre = [(c + 0.5) / 64 for c in cell]
+        assert occ(centre) == 1
+        other = [(c + 1.5) / 64 if c < 63 else (c - 0.5) / 64 for c in cell]
+        assert occ(other) == 0
+    bits[:] = 0
+    bits[-1] = 0x80  # cell (63, 63, 63): p = 1 clamps into it
+    assert occ([1.0, 1.0, 1.0]) == 1
