@@ -34,13 +34,85 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def build_workload(name):
+def build_workload(name, frames=300):
     import scenes
     if name == "config2":
         return scenes.config2()
     if name in ("config3", "config4"):
         return scenes.config3(n_obj=24)
+    if name == "config5":
+        return scenes.config5(n_frames=frames)
     raise SystemExit(f"unknown workload {name}")
+
+
+def run_stream(wl, args):
+    """Incremental mapping stream: keyframes arrive one by one (25 Hz in the
+    scene's timeline); an object is registered on the first frame where its
+    mask has >= 200 pixels; objects seen in the last 50 frames are active;
+    each frame trains every active object for 4 steps of 2^16 rays in total,
+    split in proportion to the mask pixels seen so far (at least 64 each), with
+    the BF16 MLP and 128 samples per ray; the occupancy bitfield of an object
+    is refreshed every 25 frames once it has trained for 25 frames."""
+    import numpy as np
+    import paper_2304_05735_amd as pk
+    import scenes
+    cfg = pk.default_config(samples_per_ray=128, precision=pk.PREC_BF16, batch_mode=pk.BATCH_ALL,
+                            use_graph=1, autotune=0)
+    ctx = pk.Context(cfg)
+    spec = {o.instance: o for o in wl.objects}
+    oid_of, first, last_seen, pix, has_kf = {}, {}, {}, {}, {}
+    budget, steps_per_frame = 1 << 16, 4
+    frame_ms, train_ms, psnr_log = [], [], []
+    rays_trained = 0
+    for f, (cam, rgb, mask, depth) in enumerate(wl.frames):
+        ids, counts = np.unique(mask, return_counts=True)
+        if f % 50 == 49 and oid_of:  # PSNR on this frame before it is used (novel view)
+            vis = sorted(((c, int(i)) for i, c in zip(ids, counts) if int(i) in oid_of), reverse=True)[:6]
+            vals = []
+            for c, inst in vis:
+                pred, _, _ = ctx.render(oid_of[inst], cam)
+                vals.append(scenes.psnr(pred, rgb / 255.0, mask == inst))
+            psnr_log.append((f, round(float(np.mean(vals)), 3) if vals else None, len(vals)))
+        ctx.sync()
+        t0 = time.perf_counter()
+        for inst, cnt in zip(ids, counts):
+            inst = int(inst)
+            if inst == 0 or inst not in spec:
+                continue
+            if inst not in oid_of and cnt >= 200:
+                ob = spec[inst]
+                oid_of[inst] = ctx.add_object(inst, ob.t, ob.yaw, ob.half, ob.log2T)
+                first[inst], pix[inst], has_kf[inst] = f, 0, False
+            if inst in oid_of:
+                last_seen[inst] = f
+                pix[inst] += int(cnt)
+                has_kf[inst] = True
+        ctx.add_keyframe(cam, rgb, mask, depth)
+        active = [i for i in oid_of if f - last_seen[i] <= 50 and has_kf[i]]
+        if active:
+            w = np.array([pix[i] for i in active], np.float64)
+            r = np.maximum(64, np.floor(budget * w / w.sum())).astype(np.int32)
+            t1 = time.perf_counter()
+            ctx.train(steps_per_frame, [oid_of[i] for i in active], r, stats=False)
+            rays_trained += int(r.sum()) * steps_per_frame
+            for i in active:
+                if f - first[i] >= 25 and (f - first[i]) % 25 == 0:
+                    ctx.update_occupancy(oid_of[i], 0.05)
+            ctx.sync()
+            train_ms.append((time.perf_counter() - t1) * 1e3)
+        frame_ms.append((time.perf_counter() - t0) * 1e3)
+        if f % 25 == 0:
+            log(f"frame {f}: {len(oid_of)} objects, {len(active)} active, "
+                f"{frame_ms[-1]:.2f} ms")
+    fm = np.array(frame_ms)
+    tm = np.array(train_ms)
+    return dict(frames=len(frame_ms), objects_registered=len(oid_of),
+                ms_per_frame_mean=round(float(fm.mean()), 3),
+                ms_per_frame_p50=round(float(np.percentile(fm, 50)), 3),
+                ms_per_frame_p95=round(float(np.percentile(fm, 95)), 3),
+                frames_over_40ms=int((fm > 40.0).sum()),
+                train_rays_per_s=round(rays_trained / (tm.sum() * 1e-3), 1) if tm.size else None,
+                psnr_over_time=psnr_log)
 
 
 def make_ctx(wl, precision, batch_mode, use_graph, autotune=1, profile=0):
@@ -183,6 +255,9 @@ def main():
     ap.add_argument("--psnr-chunk", type=int, default=250)
     ap.add_argument("--only-headline", action="store_true",
                     help="time the batched path only (for profiler runs)")
+    ap.add_argument("--frames", type=int, default=300, help="frames of the config5 stream")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 512 MiB three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the path is the "
@@ -193,11 +268,28 @@ def main():
     import torch
     import paper_2304_05735_amd as pk
     assert torch.cuda.is_available(), "no GPU visible"
+    if args.copy_probe:
+        src = torch.ones(128 << 20, device="cuda")  # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x 512 MiB copied")
+        del src, dst
     log("workload", args.workload)
     t = time.perf_counter()
-    wl = build_workload(args.workload)
+    wl = build_workload(args.workload, args.frames)
     log(f"scene ready in {time.perf_counter() - t:.1f}s: {len(wl.objects)} objects, "
         f"{len(wl.frames)} frames")
+    if args.workload == "config5":
+        st = run_stream(wl, args)
+        log("stream", json.dumps(st))
+        out = {"metric": METRIC, "value": st["train_rays_per_s"], "unit": "rays/s", "n_gpus": 1,
+               "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mfma/fp32",
+               "data": "synthetic", "config": {"workload": wl.name}, "stream": st}
+        print(json.dumps(out), flush=True)
+        return
     prec = pk.PREC_BF16 if args.workload == "config4" else pk.PREC_FP32
     # ---- headline: batched path, one hipGraph per step
     ctx, ids, rays = make_ctx(wl, prec, pk.BATCH_ALL, 1)

@@ -16,7 +16,9 @@
 #define RM_ADAM_CHUNK 8192  /* floats per Adam work chunk */
 #define RM_RB_BITS 13       /* binned scatter: table entries per region = 8192 (64 KiB) */
 #define RM_RB (1 << RM_RB_BITS)
-#define RM_BIN_MIN_T 65536  /* hashed levels with at least this many entries are binned */
+#define RM_BIN_MIN_T 65536  /* levels with at least this many entries are binned */
+#define RM_ACC_WG 512       /* threads of the region accumulation kernel */
+#define RM_ACC_CHUNK 16384  /* records per accumulation workgroup (about) */
 #define RM_MAX_REGIONS 2048 /* 2^24 / 2^13 */
 
 // Offsets of the eight packed GEMM operands inside a weight image.
@@ -124,7 +126,9 @@ struct BinPair {        // one (object of the launch, binned level)
   int64_t cm_base;      // count matrix [R][nb] of this pair
   int64_t rec_base;     // first record slot of this pair
   int32_t bin_base;     // first bin (region) of this pair
-  int32_t cap;          // record slots per bin
+  int32_t cap;          // record slots per bin (multiple of 4)
+  int32_t K;            // accumulation workgroups per bin
+  int32_t pad2;
   int64_t s_begin;      // first sample of the object
   int64_t n_samples;
 };
@@ -133,8 +137,8 @@ struct BinBlock {       // one block of 256 samples of one binned pair
   int32_t pair, blk;
 };
 
-struct Bin {            // one region of one binned pair
-  int32_t pair, region;
+struct Bin {            // one accumulation workgroup: chunk k of K of one region
+  int32_t pair, region, k, pad;
 };
 
 struct StepArgs {

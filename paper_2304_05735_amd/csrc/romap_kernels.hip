@@ -450,17 +450,19 @@ __global__ __launch_bounds__(256) void k_encode_bwd(StepArgs a) {
 
 
 // ---------------------------------------------------------------------------
-// Binned scatter of the hashed levels (tables of >= 2^16 entries).  A hashed
-// level spreads a sample's corners uniformly over its table and no two
-// samples of a ray share a cell, so run merging finds nothing there and every
+// Binned scatter of the large levels (tables of >= 2^16 entries).  There no
+// two samples of a ray share a cell, so run merging finds little and every
 // float atomic touches its own cache line.  Instead the (entry, value)
-// records are sorted into regions of 2^13 entries (64 KiB), and one
-// workgroup per region sums them in LDS and updates the region of the
-// gradient with coalesced loads and stores:
+// records are sorted into regions of 2^13 entries (64 KiB), and workgroups
+// per region sum them in LDS and update the region of the gradient with
+// coalesced memory operations:
 //   k_bin_count    per block of 256 samples: records per region
 //   k_bin_scan     per region: each block's offset inside the region's bin
-//   k_bin_scatter  write the records (a full bin falls back to atomics)
-//   k_bin_acc      per region: LDS sum, then gradient += region image
+//   k_bin_scatter  sort the block's records by region in LDS, write them out
+//                  coalesced (a full bin falls back to atomics)
+//   k_bin_acc      K workgroups per region: LDS sums, then the gradient
+//                  region is updated (plain read-modify-write when K = 1,
+//                  coalesced atomics otherwise)
 
 // The 8 corner records of sample s at the pair's level; false if none.
 template <int NS>
@@ -476,9 +478,10 @@ __device__ inline bool bin_records(const StepArgs& a, const BinPair& bp, int64_t
   sample_pos(R, (int)(s % NS), ob.half, p);
   Cell cl;
   make_cell(p, ob.N_l[l], cl);
+  const bool hashed = (ob.hashed_mask >> l) & 1u;
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    idx[b] = corner_index(cl, b, ob.N_l[l], ob.T_l[l], true);
+    idx[b] = corner_index(cl, b, ob.N_l[l], ob.T_l[l], hashed);
     const float w = corner_weight(cl, b);
     v[b] = make_float2(w * g.x, w * g.y);
   }
@@ -504,9 +507,10 @@ __global__ __launch_bounds__(256) void k_bin_count(StepArgs a) {
     a.cm[bp.cm_base + (int64_t)r * bp.nb + bb.blk] = hist[r];
 }
 
-// one wave per bin: exclusive scan of the blocks' counts, total of the bin
+// one wave per region: exclusive scan of the blocks' counts, total of the bin
 __global__ __launch_bounds__(64) void k_bin_scan(StepArgs a) {
   const Bin bn = a.bins[blockIdx.x];
+  if (bn.k != 0) return;  // one wave per region
   const BinPair bp = a.bpairs[bn.pair];
   int32_t* row = a.cm + bp.cm_base + (int64_t)bn.region * bp.nb;
   const int lane = threadIdx.x;
@@ -528,43 +532,102 @@ __global__ __launch_bounds__(64) void k_bin_scan(StepArgs a) {
 
 template <int NS>
 __global__ __launch_bounds__(256) void k_bin_scatter(StepArgs a) {
-  __shared__ int rank[RM_MAX_REGIONS];
+  __shared__ int lbase[RM_MAX_REGIONS];   // block-local offset of each region
+  __shared__ int lcur[RM_MAX_REGIONS];
+  __shared__ uint32_t s_idx[256 * 8];     // the block's records, sorted by region
+  __shared__ float2 s_val[256 * 8];
+  __shared__ int s_tot;
   const BinBlock bb = a.bblocks[blockIdx.x];
   const BinPair bp = a.bpairs[bb.pair];
-  for (int r = threadIdx.x; r < bp.R; r += 256) rank[r] = 0;
+  const int tid = threadIdx.x;
+  for (int r = tid; r < bp.R; r += 256) lcur[r] = 0;
   __syncthreads();
-  const int64_t k = (int64_t)bb.blk * 256 + threadIdx.x;
+  const int64_t k = (int64_t)bb.blk * 256 + tid;
   uint32_t idx[8];
   float2 v[8];
-  if (k < bp.n_samples && bin_records<NS>(a, bp, bp.s_begin + k, idx, v)) {
-    const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
-    float* gl = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l];
+  const bool has = k < bp.n_samples && bin_records<NS>(a, bp, bp.s_begin + k, idx, v);
+  if (has) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) atomicAdd(&lcur[idx[b] >> RM_RB_BITS], 1);
+  }
+  __syncthreads();
+  if (tid < 64) {  // exclusive scan of the region counts (one wave)
+    int carry = 0;
+    for (int c0 = 0; c0 < bp.R; c0 += 64) {
+      const int c = c0 + tid;
+      const int x = c < bp.R ? lcur[c] : 0;
+      int inc = x;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (tid >= o) inc += y;
+      }
+      if (c < bp.R) lbase[c] = carry + inc - x;
+      carry += __shfl(inc, 63, 64);
+    }
+    if (tid == 0) s_tot = carry;
+  }
+  __syncthreads();
+  for (int r = tid; r < bp.R; r += 256) lcur[r] = lbase[r];
+  __syncthreads();
+  if (has) {
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const int r = (int)(idx[b] >> RM_RB_BITS);
-      const int pos = a.cm[bp.cm_base + (int64_t)r * bp.nb + bb.blk] + atomicAdd(&rank[r], 1);
-      if (pos < bp.cap) {
-        const int64_t slot = bp.rec_base + (int64_t)r * bp.cap + pos;
-        a.rec_idx[slot] = idx[b] & (RM_RB - 1);
-        a.rec_val[slot] = v[b];
-      } else {  // bin full: direct atomics (correct, only slower)
-        unsafeAtomicAdd(gl + 2 * (int64_t)idx[b], v[b].x);
-        unsafeAtomicAdd(gl + 2 * (int64_t)idx[b] + 1, v[b].y);
-      }
+      const int j = atomicAdd(&lcur[idx[b] >> RM_RB_BITS], 1);
+      s_idx[j] = idx[b];
+      s_val[j] = v[b];
+    }
+  }
+  __syncthreads();
+  const int n = s_tot;
+  const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
+  float* gl = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l];
+  for (int j = tid; j < n; j += 256) {  // consecutive lanes: consecutive slots of one bin
+    const uint32_t id = s_idx[j];
+    const int r = (int)(id >> RM_RB_BITS);
+    const int pos = a.cm[bp.cm_base + (int64_t)r * bp.nb + bb.blk] + (j - lbase[r]);
+    const float2 val = s_val[j];
+    if (pos < bp.cap) {
+      const int64_t slot = bp.rec_base + (int64_t)r * bp.cap + pos;
+      a.rec_idx[slot] = id & (RM_RB - 1);
+      a.rec_val[slot] = val;
+    } else {  // bin full: direct atomics (correct, only slower)
+      unsafeAtomicAdd(gl + 2 * (int64_t)id, val.x);
+      unsafeAtomicAdd(gl + 2 * (int64_t)id + 1, val.y);
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_bin_acc(StepArgs a) {
+__global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
   __shared__ float2 img[RM_RB];
   const Bin bn = a.bins[blockIdx.x];
   const BinPair bp = a.bpairs[bn.pair];
-  for (int e = threadIdx.x; e < RM_RB; e += 256) img[e] = make_float2(0.0f, 0.0f);
-  __syncthreads();
   int n = a.bin_count[bp.bin_base + bn.region];
   n = n < bp.cap ? n : bp.cap;
-  const int64_t base = bp.rec_base + (int64_t)bn.region * bp.cap;
-  for (int i = threadIdx.x; i < n; i += 256) {
+  // this workgroup's share of the bin: [i0, i1), multiples of 4 but the end
+  const int per = ((n + bp.K - 1) / bp.K + 3) & ~3;
+  const int i0 = bn.k * per;
+  const int i1 = (i0 + per < n) ? i0 + per : n;
+  if (i0 >= i1) return;  // empty share: nothing to add
+  for (int e = threadIdx.x; e < RM_RB; e += RM_ACC_WG) img[e] = make_float2(0.0f, 0.0f);
+  __syncthreads();
+  const int64_t base = bp.rec_base + (int64_t)bn.region * bp.cap;  // multiple of 4
+  const uint4* ri = (const uint4*)(a.rec_idx + base);
+  const float4* rv = (const float4*)(a.rec_val + base);
+  const int q1 = i1 >> 2;
+  for (int q = (i0 >> 2) + threadIdx.x; q < q1; q += RM_ACC_WG) {  // 4 records per lane
+    const uint4 e4 = ri[q];
+    const float4 va = rv[2 * q], vb = rv[2 * q + 1];
+    atomicAdd(&img[e4.x].x, va.x);
+    atomicAdd(&img[e4.x].y, va.y);
+    atomicAdd(&img[e4.y].x, va.z);
+    atomicAdd(&img[e4.y].y, va.w);
+    atomicAdd(&img[e4.z].x, vb.x);
+    atomicAdd(&img[e4.z].y, vb.y);
+    atomicAdd(&img[e4.w].x, vb.z);
+    atomicAdd(&img[e4.w].y, vb.w);
+  }
+  for (int i = (q1 << 2) + threadIdx.x; i < i1; i += RM_ACC_WG) {  // tail
     const uint32_t e = a.rec_idx[base + i];
     const float2 v = a.rec_val[base + i];
     atomicAdd(&img[e].x, v.x);
@@ -572,17 +635,26 @@ __global__ __launch_bounds__(256) void k_bin_acc(StepArgs a) {
   }
   __syncthreads();
   const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
-  float4* gr = (float4*)((a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l] +
-                         2 * (int64_t)bn.region * RM_RB);
-  const float4* im = (const float4*)img;
-  for (int q = threadIdx.x; q < RM_RB / 2; q += 256) {
-    float4 g = gr[q];
-    const float4 d = im[q];
-    g.x += d.x;
-    g.y += d.y;
-    g.z += d.z;
-    g.w += d.w;
-    gr[q] = g;
+  // entries of this region (a dense level's last region is partial)
+  const int64_t e0 = (int64_t)bn.region * RM_RB;
+  const int64_t rem = (int64_t)ob.T_l[bp.l] - e0;
+  const int ne = rem < RM_RB ? (int)rem : RM_RB;
+  float* g = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l] + 2 * e0;
+  if (bp.K == 1) {  // sole owner of the region: coalesced read-modify-write
+    float2* gr = (float2*)g;
+    for (int e = threadIdx.x; e < ne; e += RM_ACC_WG) {
+      float2 x = gr[e];
+      const float2 d = img[e];
+      x.x += d.x;
+      x.y += d.y;
+      gr[e] = x;
+    }
+  } else {  // shared region: coalesced atomics (64 consecutive floats per wave)
+    const float* im = (const float*)img;
+    for (int f = threadIdx.x; f < 2 * ne; f += RM_ACC_WG) {
+      const float d = im[f];
+      if (d != 0.0f) unsafeAtomicAdd(g + f, d);
+    }
   }
 }
 
@@ -1360,7 +1432,7 @@ hipError_t rm_launch_binned_bwd(const StepArgs& a, int NS, hipStream_t st) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   RM_NS_SWITCH(NS, (k_bin_scatter<NSC><<<a.n_bblocks, 256, 0, st>>>(a)));
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_bin_acc<<<a.n_bins, 256, 0, st>>>(a);
+  k_bin_acc<<<a.n_bins, RM_ACC_WG, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ struct Plan {                 // one launch: its objects, rays and work lists
   std::vector<BinBlock> bblocks;
   std::vector<Bin> bins;
   int64_t cm_size = 0, rec_size = 0;
+  int64_t bin_regions = 0;  // regions over all pairs (bin_count entries)
   int n_rays = 0;
   int64_t S = 0;
   int rays_per_item = 8;
@@ -198,32 +199,6 @@ void object_frame(const float* Twc, const romap_box& bx, float* M, float* c) {
   c[2] = (float)dz;
 }
 
-// Detection box of an instance: bounding box of its mask pixels widened by
-// margin_pct percent of its size per side (integer ceiling), clamped.
-bool candidate_rect(const int32_t* mask, int W, int H, int instance, int margin_pct, int r[4]) {
-  int xmin = W, xmax = -1, ymin = H, ymax = -1;
-  for (int y = 0; y < H; ++y) {
-    const int32_t* row = mask + (int64_t)y * W;
-    for (int x = 0; x < W; ++x)
-      if (row[x] == instance) {
-        xmin = std::min(xmin, x);
-        xmax = std::max(xmax, x);
-        ymin = std::min(ymin, y);
-        ymax = std::max(ymax, y);
-      }
-  }
-  if (xmax < 0) return false;
-  const int w0 = xmax - xmin + 1, h0 = ymax - ymin + 1;
-  const int mx = (w0 * margin_pct + 99) / 100, my = (h0 * margin_pct + 99) / 100;
-  const int x0 = std::max(0, xmin - mx), y0 = std::max(0, ymin - my);
-  const int x1 = std::min(W - 1, xmax + mx), y1 = std::min(H - 1, ymax + my);
-  r[0] = x0;
-  r[1] = y0;
-  r[2] = x1 - x0 + 1;
-  r[3] = y1 - y0 + 1;
-  return true;
-}
-
 ObjStatic to_static(const HostObj& o) {
   ObjStatic s{};
   s.params = o.d_block;
@@ -241,7 +216,7 @@ ObjStatic to_static(const HostObj& o) {
   s.hashed_mask = o.hashed_mask;
   s.binned_mask = 0;
   for (int l = 0; l < o.L; ++l)
-    if (((o.hashed_mask >> l) & 1u) && o.T_l[l] >= RM_BIN_MIN_T) s.binned_mask |= 1u << l;
+    if (o.T_l[l] >= RM_BIN_MIN_T) s.binned_mask |= 1u << l;
   s.L = o.L;
   s.din = o.din;
   s.instance = o.instance;
@@ -342,33 +317,36 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
   p.n_rays = ray;
   p.S = (int64_t)ray * c->cfg.samples_per_ray;
   build_items(p);
-  // binned scatter of the large hashed levels
+  // binned scatter of the large levels
   const int NS = c->cfg.samples_per_ray;
   for (size_t i = 0; i < p.sobj.size(); ++i) {
     const HostObj& o = c->objs[p.sobj[i].obj];
     const int64_t So = (int64_t)p.sobj[i].n_rays * NS;
     for (int l = 0; l < o.L; ++l) {
-      if (!(((o.hashed_mask >> l) & 1u) && o.T_l[l] >= RM_BIN_MIN_T)) continue;
+      if (o.T_l[l] < RM_BIN_MIN_T) continue;
       BinPair bp{};
       bp.so = (int)i;
       bp.l = l;
       bp.nb = (int)((So + 255) / 256);
-      bp.R = (int)(o.T_l[l] >> RM_RB_BITS);
-      // records per region: 8 So / R on average (uniform hash); twice that
-      // plus a margin, a full bin falls back to atomics
+      bp.R = (int)((o.T_l[l] + RM_RB - 1) >> RM_RB_BITS);
+      // records per region: 8 So / R on average (uniform hash, z-slabs of a
+      // dense level); twice that plus a margin, a full bin falls back to atomics
       const int64_t expect = (8 * So + bp.R - 1) / bp.R;
-      bp.cap = (int)std::min<int64_t>(2 * expect + 1024, 8 * So);
+      bp.cap = (int)((std::min<int64_t>(2 * expect + 1024, 8 * So) + 3) & ~(int64_t)3);
+      bp.K = (int)std::max<int64_t>(1, std::min<int64_t>(16, expect / RM_ACC_CHUNK));
       bp.cm_base = p.cm_size;
       p.cm_size += (int64_t)bp.R * bp.nb;
       bp.rec_base = p.rec_size;
       p.rec_size += (int64_t)bp.R * bp.cap;
-      bp.bin_base = (int)p.bins.size();
+      bp.bin_base = (int)p.bin_regions;
+      p.bin_regions += bp.R;
       bp.s_begin = (int64_t)p.sobj[i].ray_begin * NS;
       bp.n_samples = So;
       const int pi = (int)p.bpairs.size();
       p.bpairs.push_back(bp);
       for (int b = 0; b < bp.nb; ++b) p.bblocks.push_back(BinBlock{pi, b});
-      for (int r = 0; r < bp.R; ++r) p.bins.push_back(Bin{pi, r});
+      for (int r = 0; r < bp.R; ++r)
+        for (int k = 0; k < bp.K; ++k) p.bins.push_back(Bin{pi, r, k, 0});
     }
   }
 }
@@ -399,7 +377,7 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
     tab += align256(p->bins.size() * sizeof(Bin));
     max_cm = std::max(max_cm, (size_t)p->cm_size);
     max_rec = std::max(max_rec, (size_t)p->rec_size);
-    max_bins = std::max(max_bins, p->bins.size());
+    max_bins = std::max(max_bins, (size_t)p->bin_regions);
   }
   const size_t L = (size_t)c->cfg.n_levels;
   auto regrow = [&](auto** ptr, size_t* cap, size_t need) -> hipError_t {
@@ -929,9 +907,46 @@ romap_status romap_add_keyframe(romap_ctx* c, const romap_camera* cam, const uin
   };
   std::vector<Acc> acc;
   const double tI[3] = {cam->T_wc[3], cam->T_wc[7], cam->T_wc[11]};
+  // bounding boxes of every registered instance in one pass over the mask
+  std::map<int32_t, int> slot;
+  for (auto& o : c->objs) slot[o.instance] = o.id;
+  std::vector<int> bx0(c->objs.size(), W), bx1(c->objs.size(), -1), by0(c->objs.size(), H),
+      by1(c->objs.size(), -1);
+  {
+    int32_t last_inst = 0;
+    int last_slot = -1;
+    for (int y = 0; y < H; ++y) {
+      const int32_t* row = mask + (int64_t)y * W;
+      for (int x = 0; x < W; ++x) {
+        const int32_t m = row[x];
+        if (m == 0) continue;
+        if (m != last_inst) {
+          auto it = slot.find(m);
+          last_inst = m;
+          last_slot = it == slot.end() ? -1 : it->second;
+        }
+        if (last_slot < 0) continue;
+        bx0[last_slot] = std::min(bx0[last_slot], x);
+        bx1[last_slot] = std::max(bx1[last_slot], x);
+        by0[last_slot] = std::min(by0[last_slot], y);
+        by1[last_slot] = std::max(by1[last_slot], y);
+      }
+    }
+  }
   for (auto& o : c->objs) {
     Acc a;
-    if (!candidate_rect(mask, W, H, o.instance, c->cfg.bbox_margin_pct, a.rect)) continue;
+    if (bx1[o.id] < 0) continue;  // the object is not observed in this image
+    {  // detection box: mask bounding box widened by margin_pct percent per side
+      const int w0 = bx1[o.id] - bx0[o.id] + 1, h0 = by1[o.id] - by0[o.id] + 1;
+      const int mx = (w0 * c->cfg.bbox_margin_pct + 99) / 100;
+      const int my = (h0 * c->cfg.bbox_margin_pct + 99) / 100;
+      const int x0 = std::max(0, bx0[o.id] - mx), y0 = std::max(0, by0[o.id] - my);
+      const int x1 = std::min(W - 1, bx1[o.id] + mx), y1 = std::min(H - 1, by1[o.id] + my);
+      a.rect[0] = x0;
+      a.rect[1] = y0;
+      a.rect[2] = x1 - x0 + 1;
+      a.rect[3] = y1 - y0 + 1;
+    }
     if (o.has_last) {
       double va[3], vb[3], dot = 0, na = 0, nb = 0;
       for (int k = 0; k < 3; ++k) {
@@ -1213,6 +1228,7 @@ romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, flo
     p.bblocks.clear();
     p.bins.clear();
     p.cm_size = p.rec_size = 0;
+    p.bin_regions = 0;
     s = stage_plans(c, {&p});
     if (s != ROMAP_OK) return s;
     StepArgs a = plan_args(c, p);

@@ -193,14 +193,36 @@ class Scene:
         d = dc @ T[:, :3].T
         npix = d.shape[0]
         o_all = np.broadcast_to(T[:, 3], d.shape)
-        # bounding-sphere cull: only pixels whose ray meets some primitive's sphere
+        Rcw = T[:, :3].T
+        # per primitive: pixels inside the projection of its bounding cube
+        # (all pixels if the cube reaches behind the camera), then the exact
+        # bounding-sphere test on those pixels only
         cands = []
         for p in self.prims:
-            oc = o_all - p.center
-            b = d @ (T[:, 3] - p.center)
-            disc = b * b - (float(np.sum((T[:, 3] - p.center) ** 2)) - p.bound_radius() ** 2)
-            cands.append((disc > 0) & (-b + np.sqrt(np.maximum(disc, 0)) > 0))
-        active = np.nonzero(np.logical_or.reduce(cands))[0] if cands else np.zeros(0, np.int64)
+            rad = p.bound_radius()
+            corners = p.center + rad * np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1)
+                                                  for sz in (-1, 1)], np.float64)
+            pc = (corners - T[:, 3]) @ Rcw.T
+            if (pc[:, 2] <= 1e-3).any():
+                sel = np.arange(npix)
+            else:
+                uu = pc[:, 0] / pc[:, 2] * cam["fx"] + cam["cx"]
+                vv = pc[:, 1] / pc[:, 2] * cam["fy"] + cam["cy"]
+                u0, u1 = max(int(np.floor(uu.min())) - 1, 0), min(int(np.ceil(uu.max())) + 1, W - 1)
+                v0, v1 = max(int(np.floor(vv.min())) - 1, 0), min(int(np.ceil(vv.max())) + 1, H - 1)
+                if u1 < u0 or v1 < v0:
+                    cands.append(np.zeros(0, np.int64))
+                    continue
+                ug, vg = np.meshgrid(np.arange(u0, u1 + 1), np.arange(v0, v1 + 1))
+                sel = (vg * W + ug).reshape(-1)
+            oc = T[:, 3] - p.center
+            b = d[sel] @ oc
+            disc = b * b - (float(oc @ oc) - rad ** 2)
+            ok = (disc > 0) & (-b + np.sqrt(np.maximum(disc, 0)) > 0)
+            cands.append(sel[ok])
+        active = (np.unique(np.concatenate(cands)) if cands else np.zeros(0, np.int64))
+        pos_in_active = np.full(npix, -1, np.int64)
+        pos_in_active[active] = np.arange(active.size)
         rgb_full = np.zeros((npix, 3))
         mask_full = np.zeros(npix, np.int32)
         depth_full = np.zeros(npix, np.float32)
@@ -210,7 +232,7 @@ class Scene:
         n = active.size
         segs_in, segs_out, segs_p = [], [], []
         for pi, p in enumerate(self.prims):
-            cand = np.nonzero(cands[pi][active])[0]
+            cand = pos_in_active[cands[pi]]
             if cand.size == 0:
                 continue
             ti, to = p.segments(o[cand], d[cand])
@@ -304,7 +326,10 @@ def _fibonacci_cameras(n, radius, W, H, f):
 
 def _render_one(args):
     scene, cam = args
-    return scene.render(cam)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):  # one BLAS thread per worker process
+        rgb, mask, depth = scene.render(cam)
+    return to_u8(rgb), mask, depth
 
 
 def _render_frames(wl: Workload, depth_frac=0.0, seed=0, workers=None):
@@ -322,13 +347,15 @@ def _render_frames(wl: Workload, depth_frac=0.0, seed=0, workers=None):
         depth = None
         if depth_frac > 0:
             depth = np.zeros_like(dz)
-            ids = [o.instance for o in wl.objects]
-            for inst in ids:
+            wanted = {o.instance for o in wl.objects}
+            for inst in np.unique(mask):
+                if int(inst) not in wanted:
+                    continue
                 pix = np.flatnonzero(mask.reshape(-1) == inst)
                 if pix.size:
                     take = rng.choice(pix, max(1, int(round(depth_frac * pix.size))), replace=False)
                     depth.reshape(-1)[take] = dz.reshape(-1)[take]
-        wl.frames.append((cam, to_u8(rgb), mask, depth))
+        wl.frames.append((cam, rgb, mask, depth))
     return wl
 
 
@@ -422,6 +449,49 @@ def config3(n_obj=24, n_views=60, W=640, H=480, seed=0, room=8.0) -> Workload:
     mx = max(max(counts.values()), 1)
     wl.rays = {k: int(min(8192, max(256, round(8192 * v / mx)))) for k, v in counts.items()}
     wl.eval_views = list(range(0, n_views, n_views // 5))
+    return wl
+
+
+def config5(n_obj=128, n_frames=300, W=640, H=480, seed=5, room=14.0) -> Workload:
+    """Incremental mapping stream: n_obj primitives in a room, a camera moving
+    on a loop through the room at 25 frames per second, looking ahead and
+    slightly inward.  Objects are meant to be registered when first seen."""
+    rng = np.random.default_rng(seed)
+    kinds = ["sphere", "box", "torus"]
+    prims, placed = [], []
+    half_room = room / 2
+    for i in range(n_obj):
+        kind = kinds[i % 3]
+        edge = math.exp(rng.uniform(math.log(0.15), math.log(1.0)))
+        yaw = float(rng.uniform(0, 2 * math.pi))
+        if kind == "sphere":
+            size = np.array([edge / 2])
+        elif kind == "box":
+            size = np.array([edge / 2, edge / 2 * rng.uniform(0.5, 1.0), edge / 2 * rng.uniform(0.5, 1.0)])
+        else:
+            size = np.array([edge * 0.35, edge * 0.12])
+        p = Primitive(kind, np.zeros(3), size, yaw, i + 1, rng.uniform(0, 2 * math.pi, 3))
+        rad = p.bound_radius()
+        for _ in range(4000):
+            xy = rng.uniform(-half_room + rad, half_room - rad, 2)
+            if 3.0 < np.linalg.norm(xy) and all(np.linalg.norm(xy - q[0]) > rad + q[1] + 0.1
+                                                for q in placed):
+                break
+        placed.append((xy, rad))
+        p.center = np.array([xy[0], xy[1], p.bound_half()[2]])
+        prims.append(p)
+    f = (W / 2) / math.tan(math.radians(35))
+    cams = []
+    for k in range(n_frames):
+        ang = 2 * math.pi * k / n_frames
+        eye = np.array([2.2 * math.cos(ang), 2.2 * math.sin(ang), 1.4])
+        look = eye + np.array([-math.sin(ang + 0.5), math.cos(ang + 0.5), -0.35])
+        cams.append(camera(look_at(eye, look), W, H, f))
+    objs = [ObjectSpec(p.instance, p.center.astype(np.float32), float(np.float32(p.yaw)),
+                       (p.bound_half() * 1.1).astype(np.float32), 19) for p in prims]
+    wl = Workload(f"config5: {n_obj}-object stream, {n_frames} frames at 25 Hz, L16 T2^19, "
+                  f"N 128, 64^3 occupancy, {W}x{H}", Scene(prims), cams, objs)
+    _render_frames(wl, depth_frac=0.005, seed=seed)
     return wl
 
 
