@@ -7,7 +7,18 @@ dominant kernel, the plain path (FP32, one launch per object per phase, no
 graph) beside it, PSNR of both after training, and the CPU oracle timed on a
 bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config4|config2|config3|config5]
+
+The default workload is the 24-object batched BF16 one (the metric's).  HBM
+traffic per launch comes from rocprofv3 counter runs of this script, turned
+into a committed summary by
+
+    python bench.py --pmc-summary <rocprofv3 output dir> --workload <name>
+
+(`<dir>/fetch` holds a FETCH_SIZE run, `<dir>/write` a WRITE_SIZE run, both
+with --copy-probe so that a plain 512 MiB copy calibrates the counters).  The
+summary records a hash of the kernel source: once the kernels change, the
+traffic is reported as null until the counters are taken again.
 
 Inputs are seeded synthetic scenes (the paper's datasets are not available).
 Only one GPU is used; --gpus above 1 exits with a message.
@@ -28,6 +39,15 @@ METRIC = "trained rays/s (fwd+bwd+Adam) all objects, batched BF16 vs plain FP32 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 BF16_PEAK_TFLOPS = 2500.0  # dense
 FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_2304_05735_amd", "csrc", "romap_kernels.hip")
+# kernels of each timed phase (the phase's duration covers all of them)
+PHASE_KERNELS = {
+    "raygen": ["k_raygen"], "encode_fwd": ["k_encode_fwd"], "pack": ["k_pack"],
+    "field": ["k_field"], "reduce": ["k_reduce"], "adam": ["k_adam"],
+    "encode_bwd": ["k_encode_bwd", "k_bin_count", "k_bin_scan", "k_bin_scatter", "k_bin_acc"],
+}
 
 
 def log(*a):
@@ -221,6 +241,85 @@ def field_flops(ctx, rays):
     return S * 4224 * 2 * 4
 
 
+def kernel_src_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+
+
+def _kernel_key(name):
+    """'void k_field<0, 64, 32>(StepArgs)' -> 'k_field'"""
+    n = name.replace("void ", "").strip()
+    for sep in ("<", "("):
+        n = n.split(sep)[0]
+    return n.strip()
+
+
+def pmc_summary(d, workload, steps):
+    """Writes the per-launch HBM traffic of each kernel from a FETCH_SIZE and a
+    WRITE_SIZE rocprofv3 run (KiB per dispatch), each counter scaled by what it
+    reads for the 512 MiB copies of --copy-probe."""
+    import csv
+    import statistics
+    per = {}
+    factor = {}
+    for cname, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        rows = list(csv.DictReader(open(os.path.join(d, sub, "run_counter_collection.csv"))))
+        copies = [float(r["Counter_Value"]) for r in rows
+                  if r["Counter_Name"] == cname and "copyBuffer" in r["Kernel_Name"]
+                  and float(r["Counter_Value"]) > 100000]
+        if not copies:
+            raise SystemExit(f"no 512 MiB copy dispatch in {sub}: run with --copy-probe")
+        factor[cname] = 524288.0 / statistics.median(copies)
+        for r in rows:
+            if r["Counter_Name"] != cname or not r["Kernel_Name"].lstrip("void ").startswith("k_"):
+                continue
+            k = _kernel_key(r["Kernel_Name"])
+            per.setdefault(k, {}).setdefault(cname, []).append(float(r["Counter_Value"]))
+    out = [f"# HBM traffic per dispatch, workload {workload}",
+           f"# rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir>/fetch (write) -o run -f csv "
+           f"-- python3 bench.py --steps {steps} --warmup 5 --only-headline --copy-probe "
+           f"--workload {workload}",
+           f"# then: python bench.py --pmc-summary <dir> --workload {workload}",
+           f"# calibration (512 MiB copy): FETCH_SIZE x {factor['FETCH_SIZE']:.4f}, "
+           f"WRITE_SIZE x {factor['WRITE_SIZE']:.4f}",
+           f"kernel_source_sha256_16 {kernel_src_hash()}",
+           "# kernel dispatches fetch_KiB_raw write_KiB_raw hbm_bytes_calibrated"]
+    for k in sorted(per):
+        f = per[k].get("FETCH_SIZE", [0.0])
+        w = per[k].get("WRITE_SIZE", [0.0])
+        fm, wm = sum(f) / len(f), sum(w) / len(w)
+        byt = (fm * factor["FETCH_SIZE"] + wm * factor["WRITE_SIZE"]) * 1024.0
+        out.append(f"{k} {len(f)} {fm:.1f} {wm:.1f} {byt:.0f}")
+    path = traffic_file(workload)
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+    log("wrote", path)
+
+
+def traffic_of(workload, kernels):
+    """Calibrated HBM bytes per step of the given kernels from the committed
+    counter summary, or None if it is missing or the kernels changed since."""
+    path = traffic_file(workload)
+    if not os.path.exists(path):
+        return None
+    tab, src = {}, None
+    for line in open(path):
+        if line.startswith("kernel_source_sha256_16"):
+            src = line.split()[1]
+        elif line.strip() and not line.startswith("#"):
+            k, _, _, _, b = line.split()
+            tab[k] = float(b)
+    if src != kernel_src_hash():
+        return None
+    return sum(tab.get(k, 0.0) for k in kernels)
+
+
 def cpu_baseline(wl, seconds_target=15.0):
     """The oracle as it stands on the host cores, on a bounded sample: as many
     full 4096-ray steps of the first object as fit in ~seconds_target."""
@@ -248,7 +347,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="config4")
     ap.add_argument("--psnr-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
@@ -258,7 +357,12 @@ def main():
     ap.add_argument("--frames", type=int, default=300, help="frames of the config5 stream")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 512 MiB three times (calibrates the HBM byte counters)")
+    ap.add_argument("--pmc-summary", metavar="DIR",
+                    help="write the HBM traffic summary from rocprofv3 counter runs and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.workload, args.steps)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the path is the "
               "single-GPU share of the workload; sharding across GPUs is not built.",
@@ -309,11 +413,13 @@ def main():
     phases, nph = pctx.phase_times()
     log("phase ms:", json.dumps({k: round(v, 5) for k, v in phases.items()}))
     dominant = max(phases, key=phases.get)
-    if dominant in ("encode_fwd", "encode_bwd", "adam") or True:
-        byt = algorithmic_bytes(pctx, ids, rays, dominant)
+    byt = algorithmic_bytes(pctx, ids, rays, dominant)
     achieved = byt / (phases[dominant] * 1e-3) / 1e9 if phases[dominant] > 0 else 0.0
-    roofline = dict(bound="hbm", kernel=dominant, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+    traffic = traffic_of(args.workload, PHASE_KERNELS[dominant])
+    roofline = dict(bound="hbm", kernel=dominant, kernels=PHASE_KERNELS[dominant],
+                    achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else int(traffic),
                     avg_ms=round(phases[dominant], 5), algorithmic_bytes=int(byt),
                     phase_ms={k: round(v, 5) for k, v in phases.items()})
     fl = field_flops(pctx, rays)

@@ -14,12 +14,17 @@
 #define RM_WPACK 10240      /* packed MLP weight image, elements (K1 <= 32) */
 #define RM_WG 256           /* threads of the fused field kernel (4 waves) */
 #define RM_ADAM_CHUNK 8192  /* floats per Adam work chunk */
-#define RM_RB_BITS 13       /* binned scatter: table entries per region = 8192 (64 KiB) */
+#define RM_RB_BITS 12       /* binned scatter: table entries per region = 4096 */
 #define RM_RB (1 << RM_RB_BITS)
+#ifndef RM_BIN_MIN_T
 #define RM_BIN_MIN_T 65536  /* levels with at least this many entries are binned */
+#endif
 #define RM_ACC_WG 512       /* threads of the region accumulation kernel */
+#define RM_SCAT_WG 512      /* samples (threads) per block of the binning kernel */
 #define RM_ACC_CHUNK 16384  /* records per accumulation workgroup (about) */
-#define RM_MAX_REGIONS 2048 /* 2^24 / 2^13 */
+#define RM_ACC_MAXK 256     /* accumulation workgroups per region, at most */
+#define RM_FX_BITS 38       /* fixed-point fraction bits of the region sums */
+#define RM_MAX_REGIONS 4096 /* 2^24 / 2^12 */
 
 // Offsets of the eight packed GEMM operands inside a weight image.
 #define RM_OFF_F1 0     /* W1        64 x K1  */
@@ -121,9 +126,8 @@ struct Chunk {          // one workgroup of the Adam kernel
 
 struct BinPair {        // one (object of the launch, binned level)
   int32_t so, l;
-  int32_t nb;           // sample blocks of 256 of the object
+  int32_t nb;           // sample blocks of RM_SCAT_WG of the object
   int32_t R;            // regions of the level's table
-  int64_t cm_base;      // count matrix [R][nb] of this pair
   int64_t rec_base;     // first record slot of this pair
   int32_t bin_base;     // first bin (region) of this pair
   int32_t cap;          // record slots per bin (multiple of 4)
@@ -133,7 +137,7 @@ struct BinPair {        // one (object of the launch, binned level)
   int64_t n_samples;
 };
 
-struct BinBlock {       // one block of 256 samples of one binned pair
+struct BinBlock {       // one block of RM_SCAT_WG samples of one binned pair
   int32_t pair, blk;
 };
 
@@ -174,16 +178,18 @@ struct StepArgs {
   float* out_tend;
   int32_t* dbg_kfuv;    // raygen: kf, u, v per ray (may be null)
   int32_t* dbg_cls;
-  // binned scatter of the hashed levels
+  int32_t n_lev_atomic; // levels 0 .. n_lev_atomic-1 may take the atomic scatter
+  // binned scatter of the large levels
   const BinPair* bpairs;
   int32_t n_bpairs;
   const BinBlock* bblocks;
   int32_t n_bblocks;
   const Bin* bins;
   int32_t n_bins;
-  int32_t* cm;          // counts, then offsets, [R][nb] per pair
-  int32_t* bin_count;   // records per bin
-  uint32_t* rec_idx;    // entry index within the region
+  int32_t n_regions;    // bins over all pairs
+  int32_t bin_max_R;    // most regions of one pair
+  int32_t* bin_count;   // records per bin (zeroed by the gather kernel)
+  uint16_t* rec_idx;    // entry index within the region
   float2* rec_val;
 };
 

@@ -314,6 +314,8 @@ template <int NS>
 __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
   const int l = blockIdx.y;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l == 0)  // fresh fill counters for the binned scatter of this pass
+    for (int64_t j = s; j < a.n_regions; j += (int64_t)gridDim.x * blockDim.x) a.bin_count[j] = 0;
   if (s >= a.S) return;
   const int r = (int)(s / NS), i = (int)(s % NS);
   const RayRec R = a.rays[r];
@@ -453,16 +455,16 @@ __global__ __launch_bounds__(256) void k_encode_bwd(StepArgs a) {
 // Binned scatter of the large levels (tables of >= 2^16 entries).  There no
 // two samples of a ray share a cell, so run merging finds little and every
 // float atomic touches its own cache line.  Instead the (entry, value)
-// records are sorted into regions of 2^13 entries (64 KiB), and workgroups
-// per region sum them in LDS and update the region of the gradient with
+// records are sorted into regions of RM_RB entries, and workgroups per
+// region sum them in LDS and update the region of the gradient with
 // coalesced memory operations:
-//   k_bin_count    per block of 256 samples: records per region
-//   k_bin_scan     per region: each block's offset inside the region's bin
-//   k_bin_scatter  sort the block's records by region in LDS, write them out
-//                  coalesced (a full bin falls back to atomics)
+//   k_bin_scatter  per block of samples: rank the records per region, reserve
+//                  space in the regions' bins, write them out sorted by region
+//                  (a full bin falls back to atomics)
 //   k_bin_acc      K workgroups per region: LDS sums, then the gradient
 //                  region is updated (plain read-modify-write when K = 1,
-//                  coalesced atomics otherwise)
+//                  atomics on consecutive entries otherwise)
+// The bins' fill counters are zeroed by the gather kernel of the same pass.
 
 // The 8 corner records of sample s at the pair's level; false if none.
 template <int NS>
@@ -488,108 +490,94 @@ __device__ inline bool bin_records(const StepArgs& a, const BinPair& bp, int64_t
   return true;
 }
 
-template <int NS>
-__global__ __launch_bounds__(256) void k_bin_count(StepArgs a) {
-  __shared__ int hist[RM_MAX_REGIONS];
-  const BinBlock bb = a.bblocks[blockIdx.x];
-  const BinPair bp = a.bpairs[bb.pair];
-  for (int r = threadIdx.x; r < bp.R; r += 256) hist[r] = 0;
-  __syncthreads();
-  const int64_t k = (int64_t)bb.blk * 256 + threadIdx.x;
-  uint32_t idx[8];
-  float2 v[8];
-  if (k < bp.n_samples && bin_records<NS>(a, bp, bp.s_begin + k, idx, v)) {
+// Exclusive scan of cnt[0..n) into base[0..n) by a whole block of WG
+// threads (n <= 8 * WG); returns the total to every thread.
+template <int WG>
+__device__ inline int block_exclusive_scan(const int* cnt, int* base, int n, int* s_wsum) {
+  constexpr int NW = WG / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (n + WG - 1) / WG;  // contiguous entries per thread
+  const int j0 = tid * per;
+  int mine = 0;
+  for (int j = j0; j < j0 + per && j < n; ++j) mine += cnt[j];
+  int inc = mine;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) atomicAdd(&hist[idx[b] >> RM_RB_BITS], 1);
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) s_wsum[wave] = inc;
+  __syncthreads();
+  int woff = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    woff += w < wave ? s_wsum[w] : 0;
+    tot += s_wsum[w];
+  }
+  int run = woff + inc - mine;
+  for (int j = j0; j < j0 + per && j < n; ++j) {
+    base[j] = run;
+    run += cnt[j];
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < bp.R; r += 256)
-    a.cm[bp.cm_base + (int64_t)r * bp.nb + bb.blk] = hist[r];
+  return tot;
 }
 
-// one wave per region: exclusive scan of the blocks' counts, total of the bin
-__global__ __launch_bounds__(64) void k_bin_scan(StepArgs a) {
-  const Bin bn = a.bins[blockIdx.x];
-  if (bn.k != 0) return;  // one wave per region
-  const BinPair bp = a.bpairs[bn.pair];
-  int32_t* row = a.cm + bp.cm_base + (int64_t)bn.region * bp.nb;
-  const int lane = threadIdx.x;
-  int carry = 0;
-  for (int c0 = 0; c0 < bp.nb; c0 += 64) {
-    const int c = c0 + lane;
-    const int x = c < bp.nb ? row[c] : 0;
-    int inc = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += y;
-    }
-    if (c < bp.nb) row[c] = carry + inc - x;
-    carry += __shfl(inc, 63, 64);
-  }
-  if (lane == 0) a.bin_count[bp.bin_base + bn.region] = carry;
-}
-
+// One block: RM_SCAT_WG samples of one (object, level) pair, up to 8 records
+// each.  The records are ranked per region in LDS, each region's share of
+// the block is reserved in its bin with one global atomic, and the records,
+// sorted by region through LDS, are written out with consecutive lanes on
+// consecutive slots.  Slots beyond a bin's capacity go to the gradient
+// directly (atomics).  The order of records inside a bin depends on timing;
+// the fixed-point region sums do not.
 template <int NS>
-__global__ __launch_bounds__(256) void k_bin_scatter(StepArgs a) {
-  __shared__ int lbase[RM_MAX_REGIONS];   // block-local offset of each region
-  __shared__ int lcur[RM_MAX_REGIONS];
-  __shared__ uint32_t s_idx[256 * 8];     // the block's records, sorted by region
-  __shared__ float2 s_val[256 * 8];
-  __shared__ int s_tot;
+__global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
+  // dynamic LDS: staging of the sorted records, then three per-region arrays
+  // of a.bin_max_R entries
+  extern __shared__ __align__(16) char dyn[];
+  float2* s_val = (float2*)dyn;                          // RM_SCAT_WG * 8
+  uint32_t* s_id = (uint32_t*)(s_val + RM_SCAT_WG * 8);  // RM_SCAT_WG * 8
+  int* lcnt = (int*)(s_id + RM_SCAT_WG * 8);   // records of the block per region
+  int* lbase = lcnt + a.bin_max_R;             // their first position in the staging
+  int* gpos = lbase + a.bin_max_R;             // first slot reserved in the region's bin
+  __shared__ int s_wsum[RM_SCAT_WG / 64];
   const BinBlock bb = a.bblocks[blockIdx.x];
   const BinPair bp = a.bpairs[bb.pair];
   const int tid = threadIdx.x;
-  for (int r = tid; r < bp.R; r += 256) lcur[r] = 0;
+  for (int r = tid; r < bp.R; r += RM_SCAT_WG) lcnt[r] = 0;
   __syncthreads();
-  const int64_t k = (int64_t)bb.blk * 256 + tid;
+  const int64_t k = (int64_t)bb.blk * RM_SCAT_WG + tid;
   uint32_t idx[8];
   float2 v[8];
+  int rank[8];
   const bool has = k < bp.n_samples && bin_records<NS>(a, bp, bp.s_begin + k, idx, v);
   if (has) {
 #pragma unroll
-    for (int b = 0; b < 8; ++b) atomicAdd(&lcur[idx[b] >> RM_RB_BITS], 1);
+    for (int b = 0; b < 8; ++b) rank[b] = atomicAdd(&lcnt[idx[b] >> RM_RB_BITS], 1);
   }
   __syncthreads();
-  if (tid < 64) {  // exclusive scan of the region counts (one wave)
-    int carry = 0;
-    for (int c0 = 0; c0 < bp.R; c0 += 64) {
-      const int c = c0 + tid;
-      const int x = c < bp.R ? lcur[c] : 0;
-      int inc = x;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(inc, o, 64);
-        if (tid >= o) inc += y;
-      }
-      if (c < bp.R) lbase[c] = carry + inc - x;
-      carry += __shfl(inc, 63, 64);
-    }
-    if (tid == 0) s_tot = carry;
-  }
-  __syncthreads();
-  for (int r = tid; r < bp.R; r += 256) lcur[r] = lbase[r];
-  __syncthreads();
+  const int n = block_exclusive_scan<RM_SCAT_WG>(lcnt, lbase, bp.R, s_wsum);
+  for (int r = tid; r < bp.R; r += RM_SCAT_WG)
+    gpos[r] = lcnt[r] ? atomicAdd(&a.bin_count[bp.bin_base + r], lcnt[r]) : 0;
   if (has) {
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const int j = atomicAdd(&lcur[idx[b] >> RM_RB_BITS], 1);
-      s_idx[j] = idx[b];
+      const int j = lbase[idx[b] >> RM_RB_BITS] + rank[b];
+      s_id[j] = idx[b];
       s_val[j] = v[b];
     }
   }
   __syncthreads();
-  const int n = s_tot;
   const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
   float* gl = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l];
-  for (int j = tid; j < n; j += 256) {  // consecutive lanes: consecutive slots of one bin
-    const uint32_t id = s_idx[j];
+  for (int j = tid; j < n; j += RM_SCAT_WG) {
+    const uint32_t id = s_id[j];
     const int r = (int)(id >> RM_RB_BITS);
-    const int pos = a.cm[bp.cm_base + (int64_t)r * bp.nb + bb.blk] + (j - lbase[r]);
+    const int pos = gpos[r] + (j - lbase[r]);
     const float2 val = s_val[j];
     if (pos < bp.cap) {
       const int64_t slot = bp.rec_base + (int64_t)r * bp.cap + pos;
-      a.rec_idx[slot] = id & (RM_RB - 1);
+      a.rec_idx[slot] = (uint16_t)(id & (RM_RB - 1));
       a.rec_val[slot] = val;
     } else {  // bin full: direct atomics (correct, only slower)
       unsafeAtomicAdd(gl + 2 * (int64_t)id, val.x);
@@ -598,8 +586,32 @@ __global__ __launch_bounds__(256) void k_bin_scatter(StepArgs a) {
   }
 }
 
+// Region sums are taken in LDS as 64-bit fixed point: float atomics in LDS
+// run about 24 times slower than integer ones on this chip.  A first pass
+// takes, per entry, the largest binary exponent of its records (an integer
+// max); the second adds every record scaled by 2^(RM_FX_BITS - that
+// exponent), rounded to an integer (|term| < 2^(RM_FX_BITS + 1)), so each
+// term is kept to 2^-RM_FX_BITS of the entry's largest one -- finer than an
+// FP32 rounding of the sum -- and the sum is exact and independent of order.
+// Up to 2^(62 - RM_FX_BITS) records per entry and workgroup fit.
+
+// biased FP32 exponent field of |v| (0 for zero and subnormals)
+__device__ inline uint32_t exp_field(float v) { return (__float_as_uint(v) >> 23) & 0xffu; }
+
+// 2^k as a double, k within the normal range
+__device__ inline double pow2d(int k) { return __longlong_as_double((long long)(k + 1023) << 52); }
+
+__device__ inline void fx_add(unsigned long long* acc, const uint32_t* emax, uint32_t e, float vx,
+                              float vy) {
+  const uint32_t eb = emax[e] > 1u ? emax[e] : 1u;
+  const double sc = pow2d(RM_FX_BITS + 127 - (int)eb);  // |v| < 2^(eb - 126)
+  atomicAdd(&acc[2 * e], (unsigned long long)__double2ll_rn((double)vx * sc));
+  atomicAdd(&acc[2 * e + 1], (unsigned long long)__double2ll_rn((double)vy * sc));
+}
+
 __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
-  __shared__ float2 img[RM_RB];
+  __shared__ uint32_t emax[RM_RB];
+  __shared__ unsigned long long acc[2 * RM_RB];
   const Bin bn = a.bins[blockIdx.x];
   const BinPair bp = a.bpairs[bn.pair];
   int n = a.bin_count[bp.bin_base + bn.region];
@@ -609,29 +621,44 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
   const int i0 = bn.k * per;
   const int i1 = (i0 + per < n) ? i0 + per : n;
   if (i0 >= i1) return;  // empty share: nothing to add
-  for (int e = threadIdx.x; e < RM_RB; e += RM_ACC_WG) img[e] = make_float2(0.0f, 0.0f);
+  for (int e = threadIdx.x; e < RM_RB; e += RM_ACC_WG) {
+    emax[e] = 0u;
+    acc[2 * e] = 0ull;
+    acc[2 * e + 1] = 0ull;
+  }
   __syncthreads();
   const int64_t base = bp.rec_base + (int64_t)bn.region * bp.cap;  // multiple of 4
-  const uint4* ri = (const uint4*)(a.rec_idx + base);
+  const ushort4* ri = (const ushort4*)(a.rec_idx + base);
   const float4* rv = (const float4*)(a.rec_val + base);
-  const int q1 = i1 >> 2;
-  for (int q = (i0 >> 2) + threadIdx.x; q < q1; q += RM_ACC_WG) {  // 4 records per lane
-    const uint4 e4 = ri[q];
+  const int q0 = i0 >> 2, q1 = i1 >> 2;
+  // pass 1: largest exponent per entry
+  for (int q = q0 + threadIdx.x; q < q1; q += RM_ACC_WG) {  // 4 records per lane
+    const ushort4 e4 = ri[q];
     const float4 va = rv[2 * q], vb = rv[2 * q + 1];
-    atomicAdd(&img[e4.x].x, va.x);
-    atomicAdd(&img[e4.x].y, va.y);
-    atomicAdd(&img[e4.y].x, va.z);
-    atomicAdd(&img[e4.y].y, va.w);
-    atomicAdd(&img[e4.z].x, vb.x);
-    atomicAdd(&img[e4.z].y, vb.y);
-    atomicAdd(&img[e4.w].x, vb.z);
-    atomicAdd(&img[e4.w].y, vb.w);
+    atomicMax(&emax[e4.x], max(exp_field(va.x), exp_field(va.y)));
+    atomicMax(&emax[e4.y], max(exp_field(va.z), exp_field(va.w)));
+    atomicMax(&emax[e4.z], max(exp_field(vb.x), exp_field(vb.y)));
+    atomicMax(&emax[e4.w], max(exp_field(vb.z), exp_field(vb.w)));
   }
   for (int i = (q1 << 2) + threadIdx.x; i < i1; i += RM_ACC_WG) {  // tail
     const uint32_t e = a.rec_idx[base + i];
     const float2 v = a.rec_val[base + i];
-    atomicAdd(&img[e].x, v.x);
-    atomicAdd(&img[e].y, v.y);
+    atomicMax(&emax[e], max(exp_field(v.x), exp_field(v.y)));
+  }
+  __syncthreads();
+  // pass 2: fixed-point sums
+  for (int q = q0 + threadIdx.x; q < q1; q += RM_ACC_WG) {
+    const ushort4 e4 = ri[q];
+    const float4 va = rv[2 * q], vb = rv[2 * q + 1];
+    fx_add(acc, emax, e4.x, va.x, va.y);
+    fx_add(acc, emax, e4.y, va.z, va.w);
+    fx_add(acc, emax, e4.z, vb.x, vb.y);
+    fx_add(acc, emax, e4.w, vb.z, vb.w);
+  }
+  for (int i = (q1 << 2) + threadIdx.x; i < i1; i += RM_ACC_WG) {
+    const uint32_t e = a.rec_idx[base + i];
+    const float2 v = a.rec_val[base + i];
+    fx_add(acc, emax, e, v.x, v.y);
   }
   __syncthreads();
   const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
@@ -639,21 +666,27 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
   const int64_t e0 = (int64_t)bn.region * RM_RB;
   const int64_t rem = (int64_t)ob.T_l[bp.l] - e0;
   const int ne = rem < RM_RB ? (int)rem : RM_RB;
-  float* g = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l] + 2 * e0;
-  if (bp.K == 1) {  // sole owner of the region: coalesced read-modify-write
-    float2* gr = (float2*)g;
-    for (int e = threadIdx.x; e < ne; e += RM_ACC_WG) {
-      float2 x = gr[e];
-      const float2 d = img[e];
-      x.x += d.x;
-      x.y += d.y;
-      gr[e] = x;
+  float2* g = (float2*)((a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l] + 2 * e0);
+  for (int e = threadIdx.x; e < ne; e += RM_ACC_WG) {
+    const uint32_t em = emax[e];
+    const long long sx = (long long)acc[2 * e], sy = (long long)acc[2 * e + 1];
+    if (em == 0u && sx == 0 && sy == 0) continue;  // untouched (or only zeros)
+    float dx, dy;
+    if (em == 0xffu) {  // an Inf or NaN among the records
+      dx = dy = __int_as_float(0x7fc00000);
+    } else {
+      const double isc = pow2d((int)(em > 1u ? em : 1u) - 127 - RM_FX_BITS);
+      dx = (float)((double)sx * isc);
+      dy = (float)((double)sy * isc);
     }
-  } else {  // shared region: coalesced atomics (64 consecutive floats per wave)
-    const float* im = (const float*)img;
-    for (int f = threadIdx.x; f < 2 * ne; f += RM_ACC_WG) {
-      const float d = im[f];
-      if (d != 0.0f) unsafeAtomicAdd(g + f, d);
+    if (bp.K == 1) {  // sole owner of the region: coalesced read-modify-write
+      float2 x = g[e];
+      x.x += dx;
+      x.y += dy;
+      g[e] = x;
+    } else {  // shared region: atomics on consecutive entries
+      unsafeAtomicAdd(&g[e].x, dx);
+      unsafeAtomicAdd(&g[e].y, dy);
     }
   }
 }
@@ -878,7 +911,6 @@ __global__ __launch_bounds__(RM_WG) void k_field(StepArgs a) {
     uint4* dst = (uint4*)s_w;
     constexpr int NV = RM_WPACK * (int)sizeof(wt) / 16;
     for (int j = tid; j < NV; j += RM_WG) dst[j] = src[j];
-    for (int j = tid; j < RM_REC_LOSS + 1; j += RM_WG) s_rec[j] = 0.0f;
   }
   __syncthreads();
 
@@ -1133,29 +1165,50 @@ __global__ __launch_bounds__(RM_WG) void k_field(StepArgs a) {
   }
 
   // ---- work-item record: weight gradients in parameter order, and loss ----
+  // The waves' partial sums are combined in turn (wave 0 stores, waves 1..3
+  // add), with plain LDS accesses: each wave covers every record entry once,
+  // and float atomics in LDS are slow.  The order is fixed, so the record is
+  // deterministic.
   if (mode != RM_MODE_FORWARD) {
     const int o2 = RM_HIDDEN * din, o3 = o2 + RM_DOUT * RM_HIDDEN, o4 = o3 + RM_HIDDEN * RM_GEO;
+    for (int turn = 0; turn < RM_WG / 64; ++turn) {
+      if (wave == turn) {
+        const bool first = turn == 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 4 * g + r;
+        for (int r = 0; r < 4; ++r) {
+          const int row = 4 * g + r;
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+          for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int u = 0; u < KQ; ++u) {
-          const int m = 16 * t + row, k = 16 * u + n;
-          if (k < din) atomicAdd(&s_rec[m * din + k], acc1[t * KQ + u][r]);
+            for (int u = 0; u < KQ; ++u) {
+              const int m = 16 * t + row, k = 16 * u + n;
+              if (k < din) {
+                float* d = &s_rec[m * din + k];
+                *d = first ? acc1[t * KQ + u][r] : *d + acc1[t * KQ + u][r];
+              }
+            }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            float* d = &s_rec[o2 + row * RM_HIDDEN + 16 * u + n];
+            *d = first ? acc2[u][r] : *d + acc2[u][r];
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (n >= 1) {
+              float* d = &s_rec[o3 + (16 * t + row) * RM_GEO + (n - 1)];
+              *d = first ? acc3[t][r] : *d + acc3[t][r];
+            }
+          if (row < 3)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              float* d = &s_rec[o4 + row * RM_HIDDEN + 16 * u + n];
+              *d = first ? acc4[u][r] : *d + acc4[u][r];
+            }
         }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) atomicAdd(&s_rec[o2 + row * RM_HIDDEN + 16 * u + n], acc2[u][r]);
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (n >= 1) atomicAdd(&s_rec[o3 + (16 * t + row) * RM_GEO + (n - 1)], acc3[t][r]);
-      if (row < 3)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) atomicAdd(&s_rec[o4 + row * RM_HIDDEN + 16 * u + n], acc4[u][r]);
+        if (lane == 0) s_rec[RM_REC_LOSS] = first ? loss_w : s_rec[RM_REC_LOSS] + loss_w;
+      }
+      __syncthreads();
     }
-    if (lane == 0) atomicAdd(&s_rec[RM_REC_LOSS], loss_w);
-    __syncthreads();
     float* rec = a.partials + (int64_t)blockIdx.x * RM_REC_STRIDE;
     for (int j = tid; j < RM_REC_LOSS + 1; j += RM_WG) rec[j] = s_rec[j];
   }
@@ -1417,21 +1470,26 @@ hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int L, int block, hip
 
 hipError_t rm_launch_encode_bwd(const StepArgs& a, int NS, int L, int block, hipStream_t st) {
   (void)block;  // fixed 256-thread blocks (the LDS staging is sized for 4 waves)
-  if (a.S <= 0) return hipSuccess;
-  dim3 grid(cdiv(a.S, 256), L);
+  const int nl = a.n_lev_atomic < L ? a.n_lev_atomic : L;  // larger levels are binned
+  if (a.S <= 0 || nl <= 0) return hipSuccess;
+  dim3 grid(cdiv(a.S, 256), nl);
   RM_NS_SWITCH(NS, (k_encode_bwd<NSC><<<grid, 256, 0, st>>>(a)));
   return hipGetLastError();
 }
 
 hipError_t rm_launch_binned_bwd(const StepArgs& a, int NS, hipStream_t st) {
   if (a.n_bblocks <= 0) return hipSuccess;
-  RM_NS_SWITCH(NS, (k_bin_count<NSC><<<a.n_bblocks, 256, 0, st>>>(a)));
+  const size_t lds = (size_t)RM_SCAT_WG * 8 * 12 + (size_t)a.bin_max_R * 3 * sizeof(int);
+  if (lds > 65536) {  // beyond the default dynamic LDS limit (tables of 2^22+ entries)
+    hipError_t e0 = hipSuccess;
+    RM_NS_SWITCH(NS, (e0 = hipFuncSetAttribute((const void*)k_bin_scatter<NSC>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds)));
+    if (e0 != hipSuccess) return e0;
+  }
+  RM_NS_SWITCH(NS, (k_bin_scatter<NSC><<<a.n_bblocks, RM_SCAT_WG, lds, st>>>(a)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_bin_scan<<<a.n_bins, 64, 0, st>>>(a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  RM_NS_SWITCH(NS, (k_bin_scatter<NSC><<<a.n_bblocks, 256, 0, st>>>(a)));
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   k_bin_acc<<<a.n_bins, RM_ACC_WG, 0, st>>>(a);
   return hipGetLastError();
 }

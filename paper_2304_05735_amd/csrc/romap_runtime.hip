@@ -56,8 +56,9 @@ struct Plan {                 // one launch: its objects, rays and work lists
   std::vector<BinPair> bpairs;
   std::vector<BinBlock> bblocks;
   std::vector<Bin> bins;
-  int64_t cm_size = 0, rec_size = 0;
+  int64_t rec_size = 0;
   int64_t bin_regions = 0;  // regions over all pairs (bin_count entries)
+  int n_lev_atomic = 0;     // levels below the binning size, most over the objects
   int n_rays = 0;
   int64_t S = 0;
   int rays_per_item = 8;
@@ -109,11 +110,9 @@ struct romap_ctx {
   size_t cap_w32 = 0, cap_w16 = 0;
   char* d_tables = nullptr;
   size_t cap_tables = 0;
-  int32_t* d_cm = nullptr;
-  size_t cap_cm = 0;
   int32_t* d_bin_count = nullptr;
   size_t cap_bin_count = 0;
-  uint32_t* d_rec_idx = nullptr;
+  uint16_t* d_rec_idx = nullptr;
   size_t cap_rec_idx = 0;
   float2* d_rec_val = nullptr;
   size_t cap_rec_val = 0;
@@ -255,7 +254,6 @@ StepArgs base_args(romap_ctx* c) {
   a.kfs = c->d_kfdev;
   a.rays = c->d_rays;
   a.e = c->d_e;
-  a.cm = c->d_cm;
   a.bin_count = c->d_bin_count;
   a.rec_idx = c->d_rec_idx;
   a.rec_val = c->d_rec_val;
@@ -323,19 +321,24 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
     const HostObj& o = c->objs[p.sobj[i].obj];
     const int64_t So = (int64_t)p.sobj[i].n_rays * NS;
     for (int l = 0; l < o.L; ++l) {
-      if (o.T_l[l] < RM_BIN_MIN_T) continue;
+      if (o.T_l[l] < RM_BIN_MIN_T) {  // table sizes grow with l: a prefix of the levels
+        p.n_lev_atomic = std::max(p.n_lev_atomic, l + 1);
+        continue;
+      }
       BinPair bp{};
       bp.so = (int)i;
       bp.l = l;
-      bp.nb = (int)((So + 255) / 256);
+      bp.nb = (int)((So + RM_SCAT_WG - 1) / RM_SCAT_WG);
       bp.R = (int)((o.T_l[l] + RM_RB - 1) >> RM_RB_BITS);
       // records per region: 8 So / R on average (uniform hash, z-slabs of a
       // dense level); twice that plus a margin, a full bin falls back to atomics
       const int64_t expect = (8 * So + bp.R - 1) / bp.R;
       bp.cap = (int)((std::min<int64_t>(2 * expect + 1024, 8 * So) + 3) & ~(int64_t)3);
-      bp.K = (int)std::max<int64_t>(1, std::min<int64_t>(16, expect / RM_ACC_CHUNK));
-      bp.cm_base = p.cm_size;
-      p.cm_size += (int64_t)bp.R * bp.nb;
+      // workgroups per region: about RM_ACC_CHUNK records each, and at most
+      // 2^(62 - RM_FX_BITS) / 2 per workgroup so no fixed-point sum can overflow
+      const int64_t kmin = (bp.cap + ((int64_t)1 << (61 - RM_FX_BITS)) - 1) >> (61 - RM_FX_BITS);
+      bp.K = (int)std::max<int64_t>(kmin, std::min<int64_t>(RM_ACC_MAXK, expect / RM_ACC_CHUNK));
+      bp.K = std::max(bp.K, 1);
       bp.rec_base = p.rec_size;
       p.rec_size += (int64_t)bp.R * bp.cap;
       bp.bin_base = (int)p.bin_regions;
@@ -356,7 +359,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Makes sure the scratch buffers fit a set of plans, then uploads their
 // work tables into the table arena.
 romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
-  size_t max_rays = 0, max_items = 0, max_sobj = 0, tab = 0, max_cm = 0, max_rec = 0, max_bins = 0;
+  size_t max_rays = 0, max_items = 0, max_sobj = 0, tab = 0, max_rec = 0, max_bins = 0;
   int64_t max_S = 0;
   for (Plan* p : plans) {
     max_rays = std::max(max_rays, (size_t)p->n_rays);
@@ -375,7 +378,6 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
     tab += align256(p->bblocks.size() * sizeof(BinBlock));
     p->off_bins = tab;
     tab += align256(p->bins.size() * sizeof(Bin));
-    max_cm = std::max(max_cm, (size_t)p->cm_size);
     max_rec = std::max(max_rec, (size_t)p->rec_size);
     max_bins = std::max(max_bins, (size_t)p->bin_regions);
   }
@@ -397,7 +399,6 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
   HIPALLOC(c, regrow(&c->d_wpack32, &c->cap_w32, std::max<size_t>(max_sobj * RM_WPACK, 1)));
   HIPALLOC(c, regrow(&c->d_wpack16, &c->cap_w16, std::max<size_t>(max_sobj * RM_WPACK, 1)));
   HIPALLOC(c, regrow(&c->d_tables, &c->cap_tables, std::max<size_t>(tab, 256)));
-  HIPALLOC(c, regrow(&c->d_cm, &c->cap_cm, std::max<size_t>(max_cm, 1)));
   HIPALLOC(c, regrow(&c->d_bin_count, &c->cap_bin_count, std::max<size_t>(max_bins, 1)));
   HIPALLOC(c, regrow(&c->d_rec_idx, &c->cap_rec_idx, std::max<size_t>(max_rec, 1)));
   HIPALLOC(c, regrow(&c->d_rec_val, &c->cap_rec_val, std::max<size_t>(max_rec, 1)));
@@ -431,10 +432,13 @@ StepArgs plan_args(romap_ctx* c, const Plan& p) {
   a.n_bblocks = (int)p.bblocks.size();
   a.bins = (const Bin*)(c->d_tables + p.off_bins);
   a.n_bins = (int)p.bins.size();
-  a.cm = c->d_cm;
   a.bin_count = c->d_bin_count;
   a.rec_idx = c->d_rec_idx;
   a.rec_val = c->d_rec_val;
+  a.n_regions = (int)p.bin_regions;
+  a.bin_max_R = 0;
+  for (const BinPair& bp : p.bpairs) a.bin_max_R = std::max(a.bin_max_R, bp.R);
+  a.n_lev_atomic = p.n_lev_atomic;
   return a;
 }
 
@@ -722,7 +726,6 @@ romap_status romap_destroy(romap_ctx* c) {
   hipFree(c->d_wpack32);
   hipFree(c->d_wpack16);
   hipFree(c->d_tables);
-  hipFree(c->d_cm);
   hipFree(c->d_bin_count);
   hipFree(c->d_rec_idx);
   hipFree(c->d_rec_val);
@@ -1227,7 +1230,7 @@ romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, flo
     p.bpairs.clear();
     p.bblocks.clear();
     p.bins.clear();
-    p.cm_size = p.rec_size = 0;
+    p.rec_size = 0;
     p.bin_regions = 0;
     s = stage_plans(c, {&p});
     if (s != ROMAP_OK) return s;
