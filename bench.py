@@ -45,8 +45,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2304_05735_amd", "csrc", "romap_kernels.h
 # kernels of each timed phase (the phase's duration covers all of them)
 PHASE_KERNELS = {
     "raygen": ["k_raygen"], "encode_fwd": ["k_encode_fwd"], "pack": ["k_pack"],
-    "field": ["k_field"], "reduce": ["k_reduce"], "adam": ["k_adam"],
-    "encode_bwd": ["k_encode_bwd", "k_bin_count", "k_bin_scan", "k_bin_scatter", "k_bin_acc"],
+    "field": ["k_field"], "bin_scatter": ["k_bin_scatter"], "bin_acc": ["k_bin_acc"],
+    "reduce": ["k_reduce"], "adam": ["k_adam"],
 }
 
 
@@ -219,13 +219,16 @@ def equal_psnr(wl, ids, rays, prec, steps, chunk, ms_batched, ms_plain):
 
 
 def algorithmic_bytes(ctx, ids, rays, phase):
-    """Algorithmic bytes of one launch of a kernel over the whole step."""
+    """Algorithmic bytes of one step of a kernel (all its launches)."""
     L, N = ctx.cfg.n_levels, ctx.cfg.samples_per_ray
     S = sum(rays) * N
+    grid = sum(ctx.object_info(i).n_grid_params for i in ids)
     if phase == "encode_fwd":   # 8 corners x 8 B gathered + 8 B written, per sample and level
         return S * L * (64 + 8)
-    if phase == "encode_bwd":   # 8 B adjoint read + 8 corners x 8 B scattered
-        return S * L * (8 + 64)
+    if phase == "bin_scatter":  # 8 B adjoint read + 8 records x 10 B written
+        return S * L * (8 + 80)
+    if phase == "bin_acc":      # 8 records x 10 B read; every grid gradient entry written once
+        return S * L * 80 + 4 * grid
     if phase == "adam":         # p, g, m, v read; p, m, v, g written
         return sum(32 * (ctx.object_info(i).n_grid_params + ctx.object_info(i).n_mlp_params)
                    for i in ids)

@@ -252,18 +252,19 @@ romap_status romap_field_backward(romap_ctx* ctx, int32_t object_id, const float
                                   float* d_params_dev);
 
 /* Kernels of one training step, in launch order. */
-#define ROMAP_PHASE_RAYGEN 0     /* ray draw, classification, box clipping (Sec. V-B) */
-#define ROMAP_PHASE_ENCODE 1     /* hash-grid gather */
-#define ROMAP_PHASE_PACK 2       /* MLP weights -> MFMA operand images */
-#define ROMAP_PHASE_FIELD 3      /* MLP, volume rendering, loss, adjoint */
-#define ROMAP_PHASE_ENCODE_BWD 4 /* hash-grid gradient scatter */
-#define ROMAP_PHASE_REDUCE 5     /* per-object MLP gradient and loss */
-#define ROMAP_PHASE_ADAM 6       /* dense Adam */
-#define ROMAP_N_PHASES 7
+#define ROMAP_PHASE_RAYGEN 0      /* ray draw, classification, box clipping (Sec. V-B) */
+#define ROMAP_PHASE_ENCODE 1      /* hash-grid gather */
+#define ROMAP_PHASE_PACK 2        /* MLP weights -> MFMA operand images */
+#define ROMAP_PHASE_FIELD 3       /* MLP, volume rendering, loss, adjoint */
+#define ROMAP_PHASE_BIN_SCATTER 4 /* hash-grid gradient: records sorted into bins */
+#define ROMAP_PHASE_BIN_ACC 5     /* hash-grid gradient: bin sums into the gradient */
+#define ROMAP_PHASE_REDUCE 6      /* per-object MLP gradient and loss */
+#define ROMAP_PHASE_ADAM 7        /* dense Adam */
+#define ROMAP_N_PHASES 8
 
-/* Average duration in ms of each kernel of a step over the steps of the last
- * romap_train call made with profile_phases = 1 (measured with HIP events on
- * the context stream).  avg_ms: ROMAP_N_PHASES floats.  *n_steps (may be
+/* Average duration in ms of each kernel of a step (summed over its launches
+ * within the step) over the steps of the last romap_train call made with
+ * profile_phases = 1 (measured with HIP events on the context stream).  avg_ms: ROMAP_N_PHASES floats.  *n_steps (may be
  * NULL) receives the number of steps averaged (0 if none). */
 romap_status romap_get_phase_times(romap_ctx* ctx, float* avg_ms, int32_t* n_steps);
 

@@ -16,13 +16,11 @@
 #define RM_ADAM_CHUNK 8192  /* floats per Adam work chunk */
 #define RM_RB_BITS 12       /* binned scatter: table entries per region = 4096 */
 #define RM_RB (1 << RM_RB_BITS)
-#ifndef RM_BIN_MIN_T
-#define RM_BIN_MIN_T 65536  /* levels with at least this many entries are binned */
-#endif
 #define RM_ACC_WG 512       /* threads of the region accumulation kernel */
 #define RM_SCAT_WG 512      /* samples (threads) per block of the binning kernel */
 #define RM_ACC_CHUNK 16384  /* records per accumulation workgroup (about) */
 #define RM_ACC_MAXK 256     /* accumulation workgroups per region, at most */
+#define RM_GROUP_RECORDS (1ll << 28) /* record slots of one bin group (2.5 GiB) */
 #define RM_FX_BITS 38       /* fixed-point fraction bits of the region sums */
 #define RM_MAX_REGIONS 4096 /* 2^24 / 2^12 */
 
@@ -76,7 +74,6 @@ struct ObjStatic {      // written by the host
   uint32_t N_l[RM_MAX_LEVELS];
   uint32_t T_l[RM_MAX_LEVELS];
   uint32_t hashed_mask;
-  uint32_t binned_mask; // levels whose gradient goes through the binned scatter
   int32_t L, din, instance, id, n_kf;
   float half[3];
   int32_t pad;
@@ -145,6 +142,16 @@ struct Bin {            // one accumulation workgroup: chunk k of K of one regio
   int32_t pair, region, k, pad;
 };
 
+// Pairs are binned and accumulated in groups of at most RM_GROUP_RECORDS
+// record slots, reused from group to group, which bounds the record memory
+// of very large launches.  (Groups small enough to keep the records in the
+// last-level cache were measured slower: each launch then ends in a partial
+// wave of workgroups.)
+struct BinGroup {
+  int32_t bb_begin, bb_end;    // binning blocks of the group
+  int32_t bin_begin, bin_end;  // accumulation workgroups of the group
+};
+
 struct StepArgs {
   const ObjStatic* objs;
   ObjState* state;
@@ -178,7 +185,6 @@ struct StepArgs {
   float* out_tend;
   int32_t* dbg_kfuv;    // raygen: kf, u, v per ray (may be null)
   int32_t* dbg_cls;
-  int32_t n_lev_atomic; // levels 0 .. n_lev_atomic-1 may take the atomic scatter
   // binned scatter of the large levels
   const BinPair* bpairs;
   int32_t n_bpairs;
@@ -186,6 +192,8 @@ struct StepArgs {
   int32_t n_bblocks;
   const Bin* bins;
   int32_t n_bins;
+  int32_t bb_begin;     // this launch's first binning block / accumulation workgroup
+  int32_t bin_begin;
   int32_t n_regions;    // bins over all pairs
   int32_t bin_max_R;    // most regions of one pair
   int32_t* bin_count;   // records per bin (zeroed by the gather kernel)
@@ -196,8 +204,8 @@ struct StepArgs {
 // Launch helpers implemented in romap_kernels.hip.
 hipError_t rm_launch_raygen(const StepArgs& a, int NS, hipStream_t st);
 hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int L, int block, hipStream_t st);
-hipError_t rm_launch_encode_bwd(const StepArgs& a, int NS, int L, int block, hipStream_t st);
-hipError_t rm_launch_binned_bwd(const StepArgs& a, int NS, hipStream_t st);
+hipError_t rm_launch_bin_scatter(const StepArgs& a, const BinGroup& g, int NS, hipStream_t st);
+hipError_t rm_launch_bin_acc(const StepArgs& a, const BinGroup& g, hipStream_t st);
 hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st);
 hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStream_t st);
 hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st);

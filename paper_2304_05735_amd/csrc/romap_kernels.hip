@@ -344,126 +344,21 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
   a.e[(int64_t)l * a.S + s] = make_float2(ex, ey);
 }
 
-// K6: encoding backward: grad[idx_b] += w_b * de for the 8 corners.
-//
-// Float atomics cost per cache line an instruction touches, not per float, so
-// the scatter is arranged to put several floats of one line into one
-// instruction.  One block covers 256 consecutive samples of one level:
-//  1. each lane forms its sample's 8 corner contributions (w_b * de);
-//  2. samples of a wave that fall in the same cell (consecutive along a ray,
-//     frequent on coarse levels) are merged by a segmented suffix sum, so the
-//     first sample of each run carries the run's total;
-//  3. the merged (index, value) pairs go through LDS and are issued with 16
-//     lanes per sample: lanes 4p..4p+3 hold corners 2p and 2p+1 (the x pair)
-//     and both features, i.e. two neighbouring table entries -- adjacent in a
-//     dense level, and in a hashed level as well, since x enters the hash with
-//     factor 1 -- so one instruction writes 16 contiguous bytes per pair.
-template <int NS>
-__global__ __launch_bounds__(256) void k_encode_bwd(StepArgs a) {
-  __shared__ uint32_t s_idx[4][64 * 8];
-  __shared__ float2 s_val[4][64 * 8];
-  __shared__ float* s_ptr[4][64];
-  const int l = blockIdx.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  bool act = s < a.S;
-  RayRec R;
-  float2 g = make_float2(0.0f, 0.0f);
-  if (act) {
-    R = a.rays[s / NS];
-    act = ray_active(R.flags);
-  }
-  if (act) act = !((a.objs[R.obj].binned_mask >> l) & 1u);  // handled by the binned scatter
-  if (act) {
-    g = a.de[(int64_t)l * a.S + s];
-    act = !(g.x == 0.0f && g.y == 0.0f);
-  }
-  uint64_t key = ~0ull - (uint64_t)lane;  // distinct keys for idle lanes
-  uint32_t idx[8];
-  float2 v[8];
-  float* gbase = nullptr;
-  if (act) {
-    const ObjStatic& ob = a.objs[R.obj];
-    float p[3];
-    sample_pos(R, (int)(s % NS), ob.half, p);
-    const uint32_t N = ob.N_l[l], T = ob.T_l[l];
-    const bool hashed = (ob.hashed_mask >> l) & 1u;
-    Cell cl;
-    make_cell(p, N, cl);
-    key = (uint64_t)cl.c[0] | ((uint64_t)cl.c[1] << 16) | ((uint64_t)cl.c[2] << 32) |
-          ((uint64_t)(uint32_t)R.obj << 48);
-    gbase = (a.grad_override ? a.grad_override : ob.grad) + ob.off[l];
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      idx[b] = corner_index(cl, b, N, T, hashed);
-      const float w = corner_weight(cl, b);
-      v[b] = make_float2(w * g.x, w * g.y);
-    }
-  } else {
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      idx[b] = 0xFFFFFFFFu;
-      v[b] = make_float2(0.0f, 0.0f);
-    }
-  }
-  // runs of equal cells: lane e is the last lane of this lane's run
-  const uint64_t knext = __shfl_down(key, 1, 64);
-  const bool tail = (lane == 63) || (knext != key);
-  const uint64_t tails = __ballot(tail);
-  const uint64_t kprev = __shfl_up(key, 1, 64);
-  const bool head = (lane == 0) || (kprev != key);
-  if (tails != ~0ull) {  // some run is longer than one sample
-    const int e = lane + __builtin_ctzll(tails >> lane);
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const float yx = __shfl_down(v[b].x, o, 64);
-        const float yy = __shfl_down(v[b].y, o, 64);
-        if (lane + o <= e) {
-          v[b].x += yx;
-          v[b].y += yy;
-        }
-      }
-    }
-  }
-  const bool emit = act && head;
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    s_idx[wave][lane * 8 + b] = emit ? idx[b] : 0xFFFFFFFFu;
-    s_val[wave][lane * 8 + b] = v[b];
-  }
-  s_ptr[wave][lane] = gbase;
-  wave_lds_sync();
-  const int k = lane & 15;
-  const int b = ((k >> 2) << 1) | ((k >> 1) & 1);
-  const int f = k & 1;
-#pragma unroll 4
-  for (int it = 0; it < 16; ++it) {
-    const int smp = it * 4 + (lane >> 4);
-    const uint32_t id = s_idx[wave][smp * 8 + b];
-    if (id != 0xFFFFFFFFu) {
-      const float2 val = s_val[wave][smp * 8 + b];
-      const float x = f ? val.y : val.x;
-      if (x != 0.0f) unsafeAtomicAdd(s_ptr[wave][smp] + 2 * (int64_t)id + f, x);
-    }
-  }
-}
-
-
 // ---------------------------------------------------------------------------
-// Binned scatter of the large levels (tables of >= 2^16 entries).  There no
-// two samples of a ray share a cell, so run merging finds little and every
-// float atomic touches its own cache line.  Instead the (entry, value)
-// records are sorted into regions of RM_RB entries, and workgroups per
-// region sum them in LDS and update the region of the gradient with
-// coalesced memory operations:
+// K6: encoding backward, grad[idx_b] += w_b * de for the 8 corners of every
+// sample, as a binned scatter.  Float atomics on a table cost per cache line
+// an instruction touches, and on the fine levels no two samples of a ray
+// share a cell, so direct atomics are bound by one line per corner.  Instead
+// the (entry, value) records are sorted into regions of RM_RB entries, and
+// workgroups per region sum them in LDS and update the region of the
+// gradient with coalesced memory operations:
 //   k_bin_scatter  per block of samples: rank the records per region, reserve
 //                  space in the regions' bins, write them out sorted by region
 //                  (a full bin falls back to atomics)
 //   k_bin_acc      K workgroups per region: LDS sums, then the gradient
-//                  region is updated (plain read-modify-write when K = 1,
-//                  atomics on consecutive entries otherwise)
+//                  region is updated (plain stores when K = 1 -- the gradient
+//                  is zero on entry -- atomics on consecutive entries
+//                  otherwise, and read-modify-write if the bin overflowed)
 // The bins' fill counters are zeroed by the gather kernel of the same pass.
 
 // The 8 corner records of sample s at the pair's level; false if none.
@@ -541,7 +436,7 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
   int* lbase = lcnt + a.bin_max_R;             // their first position in the staging
   int* gpos = lbase + a.bin_max_R;             // first slot reserved in the region's bin
   __shared__ int s_wsum[RM_SCAT_WG / 64];
-  const BinBlock bb = a.bblocks[blockIdx.x];
+  const BinBlock bb = a.bblocks[a.bb_begin + blockIdx.x];
   const BinPair bp = a.bpairs[bb.pair];
   const int tid = threadIdx.x;
   for (int r = tid; r < bp.R; r += RM_SCAT_WG) lcnt[r] = 0;
@@ -557,8 +452,14 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
   }
   __syncthreads();
   const int n = block_exclusive_scan<RM_SCAT_WG>(lcnt, lbase, bp.R, s_wsum);
-  for (int r = tid; r < bp.R; r += RM_SCAT_WG)
-    gpos[r] = lcnt[r] ? atomicAdd(&a.bin_count[bp.bin_base + r], lcnt[r]) : 0;
+  // reserve the block's share of each bin; with at most one region per
+  // thread the reservation is in flight while the records are staged
+  int mine = 0;
+  const bool one = bp.R <= RM_SCAT_WG;
+  if (one && tid < bp.R && lcnt[tid]) mine = atomicAdd(&a.bin_count[bp.bin_base + tid], lcnt[tid]);
+  if (!one)
+    for (int r = tid; r < bp.R; r += RM_SCAT_WG)
+      gpos[r] = lcnt[r] ? atomicAdd(&a.bin_count[bp.bin_base + r], lcnt[r]) : 0;
   if (has) {
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -567,6 +468,7 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
       s_val[j] = v[b];
     }
   }
+  if (one && tid < bp.R) gpos[tid] = mine;
   __syncthreads();
   const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
   float* gl = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l];
@@ -612,10 +514,11 @@ __device__ inline void fx_add(unsigned long long* acc, const uint32_t* emax, uin
 __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
   __shared__ uint32_t emax[RM_RB];
   __shared__ unsigned long long acc[2 * RM_RB];
-  const Bin bn = a.bins[blockIdx.x];
+  const Bin bn = a.bins[a.bin_begin + blockIdx.x];
   const BinPair bp = a.bpairs[bn.pair];
   int n = a.bin_count[bp.bin_base + bn.region];
-  n = n < bp.cap ? n : bp.cap;
+  const bool spilled = n > bp.cap;  // some records went to the gradient directly
+  n = spilled ? bp.cap : n;
   // this workgroup's share of the bin: [i0, i1), multiples of 4 but the end
   const int per = ((n + bp.K - 1) / bp.K + 3) & ~3;
   const int i0 = bn.k * per;
@@ -646,7 +549,7 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
     atomicMax(&emax[e], max(exp_field(v.x), exp_field(v.y)));
   }
   __syncthreads();
-  // pass 2: fixed-point sums
+  // pass 2: fixed-point sums (the records are read again, mostly from cache)
   for (int q = q0 + threadIdx.x; q < q1; q += RM_ACC_WG) {
     const ushort4 e4 = ri[q];
     const float4 va = rv[2 * q], vb = rv[2 * q + 1];
@@ -679,7 +582,9 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
       dx = (float)((double)sx * isc);
       dy = (float)((double)sy * isc);
     }
-    if (bp.K == 1) {  // sole owner of the region: coalesced read-modify-write
+    if (bp.K == 1 && !spilled) {  // sole writer of a zero region: plain stores
+      g[e] = make_float2(dx, dy);
+    } else if (bp.K == 1) {  // the scatter's overflow atomics are in the region too
       float2 x = g[e];
       x.x += dx;
       x.y += dy;
@@ -725,7 +630,8 @@ __global__ __launch_bounds__(256) void k_pack(StepArgs a, int K1) {
                        RM_OFF_B4, RM_OFF_B3, RM_OFF_B2, RM_OFF_B1};
   float* o32 = a.wpack32 + (int64_t)blockIdx.x * RM_WPACK;
   uint16_t* o16 = a.wpack16 + (int64_t)blockIdx.x * RM_WPACK;
-  for (int gm = 0; gm < 8; ++gm) {
+  {  // one operand per block
+    const int gm = blockIdx.y;
     const int M = Ms[gm], K = Ks[gm], Q = K / 16;
     for (int j = threadIdx.x; j < M * K; j += blockDim.x) {
       {  // FP32 image
@@ -1217,69 +1123,114 @@ __global__ __launch_bounds__(RM_WG) void k_field(StepArgs a) {
 // ---------------------------------------------------------------------------
 // K5: per-object MLP gradient and loss from the work-item records, summed in
 // a fixed order (deterministic); advances the Adam step counter.  A block owns
-// 64 record columns (column RM_REC_LOSS is the loss); its 4 waves sum
-// interleaved quarters of the items, then combine in LDS.
-__global__ __launch_bounds__(256) void k_reduce(StepArgs a) {
-  __shared__ float s_part[4][64];
+// 256 record columns, 4 per lane (column RM_REC_LOSS is the loss); its 16
+// waves sum interleaved sixteenths of the items, then combine in LDS.
+__global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
+  __shared__ float4 s_part[16][64];
   const StepObj so = a.sobj[blockIdx.y];
   const ObjStatic& ob = a.objs[so.obj];
   const int nm = (int)(ob.P - ob.P_grid);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int j = blockIdx.x * 64 + lane;
-  const bool used = j < nm || j == RM_REC_LOSS;
-  float acc = 0.0f;
-  if (used)
-    for (int it = so.item_begin + wave; it < so.item_end; it += 4)
-      acc += a.partials[(int64_t)it * RM_REC_STRIDE + j];
-  s_part[wave][lane] = acc;
+  const int j0 = blockIdx.x * 256 + 4 * lane;  // 4 columns per lane (the stride is a multiple of 4)
+  float4 s0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), s1 = s0;
+  if (j0 < RM_REC_STRIDE) {
+    const float* col = a.partials + j0;
+    int it = so.item_begin + wave;
+    for (; it + 16 < so.item_end; it += 32) {  // two items per lane in flight
+      const float4 x = *(const float4*)(col + (int64_t)it * RM_REC_STRIDE);
+      const float4 y = *(const float4*)(col + (int64_t)(it + 16) * RM_REC_STRIDE);
+      s0.x += x.x; s0.y += x.y; s0.z += x.z; s0.w += x.w;
+      s1.x += y.x; s1.y += y.y; s1.z += y.z; s1.w += y.w;
+    }
+    if (it < so.item_end) {
+      const float4 x = *(const float4*)(col + (int64_t)it * RM_REC_STRIDE);
+      s0.x += x.x; s0.y += x.y; s0.z += x.z; s0.w += x.w;
+    }
+  }
+  s_part[wave][lane] = make_float4(s0.x + s1.x, s0.y + s1.y, s0.z + s1.z, s0.w + s1.w);
   __syncthreads();
-  if (wave != 0 || !used) return;
-  const float tot = (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
-  if (j < nm) {
-    float* gdst = a.grad_override ? a.grad_override : ob.grad;
-    gdst[ob.P_grid + j] = tot;
-  } else if (a.mode == RM_MODE_TRAIN) {
-    ObjState* st = a.state + so.obj;
-    st->loss_acc += tot;
-    st->n_loss += 1;
-    if (a.advance) {
-      const int kk = st->step + 1;
-      st->step = kk;
-      st->bc1 = (float)(1.0 - pow((double)a.beta1, (double)kk));
-      st->bc2 = (float)(1.0 - pow((double)a.beta2, (double)kk));
+  if (wave != 0 || j0 >= RM_REC_STRIDE) return;
+  float4 t = s_part[0][lane];
+#pragma unroll
+  for (int w = 1; w < 16; ++w) {  // fixed order: deterministic
+    const float4 u = s_part[w][lane];
+    t.x += u.x; t.y += u.y; t.z += u.z; t.w += u.w;
+  }
+  const float tv[4] = {t.x, t.y, t.z, t.w};
+  float* gdst = a.grad_override ? a.grad_override : ob.grad;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int j = j0 + c;
+    if (j < nm) {
+      gdst[ob.P_grid + j] = tv[c];
+    } else if (j == RM_REC_LOSS && a.mode == RM_MODE_TRAIN) {
+      ObjState* st = a.state + so.obj;
+      st->loss_acc += tv[c];
+      st->n_loss += 1;
+      if (a.advance) {
+        const int kk = st->step + 1;
+        st->step = kk;
+        st->bc1 = (float)(1.0 - pow((double)a.beta1, (double)kk));
+        st->bc2 = (float)(1.0 - pow((double)a.beta2, (double)kk));
+      }
     }
   }
 }
 
 // K7: dense Adam over every parameter of the step's objects; zeroes the
 // gradient for the next step.
+__device__ inline void adam4(float4& p, const float4& g, float4& m, float4& v, float b1, float b2,
+                             float ob1, float ob2, float lr, float bc1, float bc2, float eps) {
+  float* pp = &p.x;
+  const float* gg = &g.x;
+  float* mm = &m.x;
+  float* vv = &v.x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    mm[k] = b1 * mm[k] + ob1 * gg[k];
+    vv[k] = b2 * vv[k] + ob2 * (gg[k] * gg[k]);
+    pp[k] -= lr * (mm[k] / bc1) / (sqrtf(vv[k] / bc2) + eps);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_adam(StepArgs a) {
   const Chunk ch = a.chunks[blockIdx.x];
   const ObjStatic& ob = a.objs[ch.obj];
   const float bc1 = a.state[ch.obj].bc1, bc2 = a.state[ch.obj].bc2;
   const float b1 = a.beta1, b2 = a.beta2, lr = a.lr, eps = a.eps;
   const float ob1 = 1.0f - b1, ob2 = 1.0f - b2;
+  float* __restrict__ P = ob.params;
+  float* __restrict__ G = ob.grad;
+  float* __restrict__ M = ob.m;
+  float* __restrict__ V = ob.v;
   int64_t end = ch.begin + RM_ADAM_CHUNK;
   if (end > ob.P_alloc) end = ob.P_alloc;
-  for (int64_t i = ch.begin + 4 * (int64_t)threadIdx.x; i < end; i += 4 * (int64_t)blockDim.x) {
-    float4 p = *(const float4*)(ob.params + i);
-    float4 gr = *(const float4*)(ob.grad + i);
-    float4 m = *(const float4*)(ob.m + i);
-    float4 v = *(const float4*)(ob.v + i);
-    float* pp = &p.x;
-    float* gg = &gr.x;
-    float* mm = &m.x;
-    float* vv = &v.x;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      mm[k] = b1 * mm[k] + ob1 * gg[k];
-      vv[k] = b2 * vv[k] + ob2 * (gg[k] * gg[k]);
-      pp[k] -= lr * (mm[k] / bc1) / (sqrtf(vv[k] / bc2) + eps);
+  const int64_t step = 4 * (int64_t)blockDim.x;
+  // two float4 of each array per lane in flight (P_alloc is a multiple of 64)
+  for (int64_t i = ch.begin + 4 * (int64_t)threadIdx.x; i < end; i += 2 * step) {
+    const int64_t i2 = i + step;
+    const bool two = i2 < end;
+    float4 p0 = *(const float4*)(P + i), g0 = *(const float4*)(G + i);
+    float4 m0 = *(const float4*)(M + i), v0 = *(const float4*)(V + i);
+    float4 p1, g1, m1, v1;
+    if (two) {
+      p1 = *(const float4*)(P + i2);
+      g1 = *(const float4*)(G + i2);
+      m1 = *(const float4*)(M + i2);
+      v1 = *(const float4*)(V + i2);
     }
-    *(float4*)(ob.params + i) = p;
-    *(float4*)(ob.m + i) = m;
-    *(float4*)(ob.v + i) = v;
-    *(float4*)(ob.grad + i) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    adam4(p0, g0, m0, v0, b1, b2, ob1, ob2, lr, bc1, bc2, eps);
+    *(float4*)(P + i) = p0;
+    *(float4*)(M + i) = m0;
+    *(float4*)(V + i) = v0;
+    *(float4*)(G + i) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (two) {
+      adam4(p1, g1, m1, v1, b1, b2, ob1, ob2, lr, bc1, bc2, eps);
+      *(float4*)(P + i2) = p1;
+      *(float4*)(M + i2) = m1;
+      *(float4*)(V + i2) = v1;
+      *(float4*)(G + i2) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
   }
 }
 
@@ -1468,17 +1419,8 @@ hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int L, int block, hip
   return hipGetLastError();
 }
 
-hipError_t rm_launch_encode_bwd(const StepArgs& a, int NS, int L, int block, hipStream_t st) {
-  (void)block;  // fixed 256-thread blocks (the LDS staging is sized for 4 waves)
-  const int nl = a.n_lev_atomic < L ? a.n_lev_atomic : L;  // larger levels are binned
-  if (a.S <= 0 || nl <= 0) return hipSuccess;
-  dim3 grid(cdiv(a.S, 256), nl);
-  RM_NS_SWITCH(NS, (k_encode_bwd<NSC><<<grid, 256, 0, st>>>(a)));
-  return hipGetLastError();
-}
-
-hipError_t rm_launch_binned_bwd(const StepArgs& a, int NS, hipStream_t st) {
-  if (a.n_bblocks <= 0) return hipSuccess;
+hipError_t rm_launch_bin_scatter(const StepArgs& a, const BinGroup& g, int NS, hipStream_t st) {
+  if (g.bb_end <= g.bb_begin) return hipSuccess;
   const size_t lds = (size_t)RM_SCAT_WG * 8 * 12 + (size_t)a.bin_max_R * 3 * sizeof(int);
   if (lds > 65536) {  // beyond the default dynamic LDS limit (tables of 2^22+ entries)
     hipError_t e0 = hipSuccess;
@@ -1487,16 +1429,23 @@ hipError_t rm_launch_binned_bwd(const StepArgs& a, int NS, hipStream_t st) {
                                                (int)lds)));
     if (e0 != hipSuccess) return e0;
   }
-  RM_NS_SWITCH(NS, (k_bin_scatter<NSC><<<a.n_bblocks, RM_SCAT_WG, lds, st>>>(a)));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_bin_acc<<<a.n_bins, RM_ACC_WG, 0, st>>>(a);
+  StepArgs b = a;
+  b.bb_begin = g.bb_begin;
+  RM_NS_SWITCH(NS, (k_bin_scatter<NSC><<<g.bb_end - g.bb_begin, RM_SCAT_WG, lds, st>>>(b)));
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_bin_acc(const StepArgs& a, const BinGroup& g, hipStream_t st) {
+  if (g.bin_end <= g.bin_begin) return hipSuccess;
+  StepArgs b = a;
+  b.bin_begin = g.bin_begin;
+  k_bin_acc<<<g.bin_end - g.bin_begin, RM_ACC_WG, 0, st>>>(b);
   return hipGetLastError();
 }
 
 hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
-  k_pack<<<a.n_sobj, 256, 0, st>>>(a, K1);
+  k_pack<<<dim3(a.n_sobj, 8), 256, 0, st>>>(a, K1);
   return hipGetLastError();
 }
 
@@ -1516,8 +1465,8 @@ hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStrea
 hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
   (void)n_mlp_max;
-  dim3 grid(cdiv(RM_REC_LOSS + 1, 64), a.n_sobj);
-  k_reduce<<<grid, 256, 0, st>>>(a);
+  dim3 grid(cdiv(RM_REC_LOSS + 1, 256), a.n_sobj);
+  k_reduce<<<grid, 1024, 0, st>>>(a);
   return hipGetLastError();
 }
 

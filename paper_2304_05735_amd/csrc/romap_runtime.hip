@@ -56,9 +56,9 @@ struct Plan {                 // one launch: its objects, rays and work lists
   std::vector<BinPair> bpairs;
   std::vector<BinBlock> bblocks;
   std::vector<Bin> bins;
-  int64_t rec_size = 0;
+  std::vector<BinGroup> bgroups;
+  int64_t rec_size = 0;      // record slots of the largest group
   int64_t bin_regions = 0;  // regions over all pairs (bin_count entries)
-  int n_lev_atomic = 0;     // levels below the binning size, most over the objects
   int n_rays = 0;
   int64_t S = 0;
   int rays_per_item = 8;
@@ -122,7 +122,9 @@ struct romap_ctx {
   // autotuner results keyed by the work signature
   std::map<std::vector<int64_t>, std::pair<int, int>> tuned;
   // per-kernel timing of the last profiled train call
-  hipEvent_t pev[ROMAP_N_PHASES + 1] = {};
+  std::vector<hipEvent_t> pev;  // event pool of the kernel timing (profile_phases)
+  std::vector<int> pev_phase;    // phase that ends at each recorded event (-1: start)
+  int pev_n = 0;                 // events recorded in the current step
   double phase_ms[ROMAP_N_PHASES] = {};
   int phase_steps = 0;
   std::string err;
@@ -213,9 +215,6 @@ ObjStatic to_static(const HostObj& o) {
     s.T_l[l] = o.T_l[l];
   }
   s.hashed_mask = o.hashed_mask;
-  s.binned_mask = 0;
-  for (int l = 0; l < o.L; ++l)
-    if (o.T_l[l] >= RM_BIN_MIN_T) s.binned_mask |= 1u << l;
   s.L = o.L;
   s.din = o.din;
   s.instance = o.instance;
@@ -315,16 +314,13 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
   p.n_rays = ray;
   p.S = (int64_t)ray * c->cfg.samples_per_ray;
   build_items(p);
-  // binned scatter of the large levels
+  // binned gradient scatter: every (object, level) pair
   const int NS = c->cfg.samples_per_ray;
+  int64_t grp_rec = 0;  // record slots of the open group
   for (size_t i = 0; i < p.sobj.size(); ++i) {
     const HostObj& o = c->objs[p.sobj[i].obj];
     const int64_t So = (int64_t)p.sobj[i].n_rays * NS;
     for (int l = 0; l < o.L; ++l) {
-      if (o.T_l[l] < RM_BIN_MIN_T) {  // table sizes grow with l: a prefix of the levels
-        p.n_lev_atomic = std::max(p.n_lev_atomic, l + 1);
-        continue;
-      }
       BinPair bp{};
       bp.so = (int)i;
       bp.l = l;
@@ -333,14 +329,27 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
       // records per region: 8 So / R on average (uniform hash, z-slabs of a
       // dense level); twice that plus a margin, a full bin falls back to atomics
       const int64_t expect = (8 * So + bp.R - 1) / bp.R;
-      bp.cap = (int)((std::min<int64_t>(2 * expect + 1024, 8 * So) + 3) & ~(int64_t)3);
+      // hashed: near-uniform counts, the mean plus 8 standard deviations;
+      // dense: regions are z-slabs, twice the mean (a full bin falls back to
+      // atomics)
+      const bool hashed = (o.hashed_mask >> l) & 1u;
+      const int64_t want = hashed ? expect + 8 * (int64_t)std::ceil(std::sqrt((double)expect)) + 256
+                                  : 2 * expect + 1024;
+      bp.cap = (int)((std::min<int64_t>(want, 8 * So) + 3) & ~(int64_t)3);
       // workgroups per region: about RM_ACC_CHUNK records each, and at most
       // 2^(62 - RM_FX_BITS) / 2 per workgroup so no fixed-point sum can overflow
       const int64_t kmin = (bp.cap + ((int64_t)1 << (61 - RM_FX_BITS)) - 1) >> (61 - RM_FX_BITS);
       bp.K = (int)std::max<int64_t>(kmin, std::min<int64_t>(RM_ACC_MAXK, expect / RM_ACC_CHUNK));
       bp.K = std::max(bp.K, 1);
-      bp.rec_base = p.rec_size;
-      p.rec_size += (int64_t)bp.R * bp.cap;
+      const int64_t slots = (int64_t)bp.R * bp.cap;
+      if (p.bgroups.empty() || (grp_rec > 0 && grp_rec + slots > RM_GROUP_RECORDS)) {
+        const int nbb = (int)p.bblocks.size(), nbin = (int)p.bins.size();
+        p.bgroups.push_back(BinGroup{nbb, nbb, nbin, nbin});
+        grp_rec = 0;
+      }
+      bp.rec_base = grp_rec;  // record slots are reused from group to group
+      grp_rec += slots;
+      p.rec_size = std::max(p.rec_size, grp_rec);
       bp.bin_base = (int)p.bin_regions;
       p.bin_regions += bp.R;
       bp.s_begin = (int64_t)p.sobj[i].ray_begin * NS;
@@ -350,6 +359,8 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
       for (int b = 0; b < bp.nb; ++b) p.bblocks.push_back(BinBlock{pi, b});
       for (int r = 0; r < bp.R; ++r)
         for (int k = 0; k < bp.K; ++k) p.bins.push_back(Bin{pi, r, k, 0});
+      p.bgroups.back().bb_end = (int)p.bblocks.size();
+      p.bgroups.back().bin_end = (int)p.bins.size();
     }
   }
 }
@@ -438,47 +449,66 @@ StepArgs plan_args(romap_ctx* c, const Plan& p) {
   a.n_regions = (int)p.bin_regions;
   a.bin_max_R = 0;
   for (const BinPair& bp : p.bpairs) a.bin_max_R = std::max(a.bin_max_R, bp.R);
-  a.n_lev_atomic = p.n_lev_atomic;
   return a;
 }
 
 // One training step of every object of a plan (the hot path).  ev: null, or
 // ROMAP_N_PHASES + 1 events recorded between the kernels.
+// Records a timing event on the context stream; ph is the phase of the
+// kernel launched just before it (-1 at the start of a step).
+hipError_t mark_phase(romap_ctx* c, int ph) {
+  if (c->pev_n == (int)c->pev.size()) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    c->pev.push_back(ev);
+    c->pev_phase.push_back(-1);
+  }
+  c->pev_phase[c->pev_n] = ph;
+  return hipEventRecord(c->pev[c->pev_n++], c->stream);
+}
+
 hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a, bool adam,
-                        hipEvent_t* ev = nullptr) {
+                        bool prof = false) {
   const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels, K1 = K1_of(c->cfg);
   hipError_t e;
-#define RM_MARK(i) \
-  if (ev && (e = hipEventRecord(ev[i], c->stream)) != hipSuccess) return e;
-  RM_MARK(0);
+#define RM_MARK(ph) \
+  if (prof && (e = mark_phase(c, ph)) != hipSuccess) return e;
+  RM_MARK(-1);
   if ((e = rm_launch_raygen(a, NS, c->stream)) != hipSuccess) return e;
-  RM_MARK(1);
+  RM_MARK(ROMAP_PHASE_RAYGEN);
   if ((e = rm_launch_encode_fwd(a, NS, L, p.enc_block, c->stream)) != hipSuccess) return e;
-  RM_MARK(2);
+  RM_MARK(ROMAP_PHASE_ENCODE);
   if ((e = rm_launch_pack(a, K1, c->stream)) != hipSuccess) return e;
-  RM_MARK(3);
+  RM_MARK(ROMAP_PHASE_PACK);
   if ((e = rm_launch_field(a, NS, K1, c->cfg.precision, c->stream)) != hipSuccess) return e;
-  RM_MARK(4);
-  if ((e = rm_launch_encode_bwd(a, NS, L, p.enc_block, c->stream)) != hipSuccess) return e;
-  if ((e = rm_launch_binned_bwd(a, NS, c->stream)) != hipSuccess) return e;
-  RM_MARK(5);
+  RM_MARK(ROMAP_PHASE_FIELD);
+  for (const BinGroup& g : p.bgroups) {
+    if ((e = rm_launch_bin_scatter(a, g, NS, c->stream)) != hipSuccess) return e;
+    RM_MARK(ROMAP_PHASE_BIN_SCATTER);
+    if ((e = rm_launch_bin_acc(a, g, c->stream)) != hipSuccess) return e;
+    RM_MARK(ROMAP_PHASE_BIN_ACC);
+  }
   if ((e = rm_launch_reduce(a, RM_MLP_MAX, c->stream)) != hipSuccess) return e;
-  RM_MARK(6);
+  RM_MARK(ROMAP_PHASE_REDUCE);
   if (adam && (e = rm_launch_adam(a, c->stream)) != hipSuccess) return e;
-  RM_MARK(7);
+  RM_MARK(ROMAP_PHASE_ADAM);
 #undef RM_MARK
   return hipSuccess;
 }
 
-// Adds the phase durations of the step whose events were just recorded.
+// Adds the kernel durations of the step whose events were just recorded:
+// the time between two consecutive events belongs to the phase of the later.
 hipError_t accumulate_phases(romap_ctx* c) {
-  hipError_t e = hipEventSynchronize(c->pev[ROMAP_N_PHASES]);
+  if (c->pev_n == 0) return hipSuccess;
+  hipError_t e = hipEventSynchronize(c->pev[c->pev_n - 1]);
   if (e != hipSuccess) return e;
-  for (int i = 0; i < ROMAP_N_PHASES; ++i) {
+  for (int i = 1; i < c->pev_n; ++i) {
     float ms = 0.0f;
-    if ((e = hipEventElapsedTime(&ms, c->pev[i], c->pev[i + 1])) != hipSuccess) return e;
-    c->phase_ms[i] += ms;
+    if ((e = hipEventElapsedTime(&ms, c->pev[i - 1], c->pev[i])) != hipSuccess) return e;
+    c->phase_ms[c->pev_phase[i]] += ms;
   }
+  c->pev_n = 0;
   return hipSuccess;
 }
 
@@ -704,8 +734,7 @@ romap_status romap_destroy(romap_ctx* c) {
   if (!c) return ROMAP_E_INVALID_ARG;
   hipStreamSynchronize(c->stream);
   if (c->gexec) hipGraphExecDestroy(c->gexec);
-  for (int i = 0; i <= ROMAP_N_PHASES; ++i)
-    if (c->pev[i]) hipEventDestroy(c->pev[i]);
+  for (hipEvent_t ev : c->pev) hipEventDestroy(ev);
   for (auto& o : c->objs) {
     hipFree(o.d_block);
     hipFree(o.d_kfs);
@@ -1066,8 +1095,7 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
   build_plan(c, list, rpi, blk, all);
   const bool prof = c->cfg.profile_phases != 0;
   if (prof) {
-    for (int i = 0; i <= ROMAP_N_PHASES; ++i)
-      if (!c->pev[i]) HIPCHK(c, hipEventCreate(&c->pev[i]));
+    c->pev_n = 0;
     for (int i = 0; i < ROMAP_N_PHASES; ++i) c->phase_ms[i] = 0.0;
     c->phase_steps = 0;
   }
@@ -1081,7 +1109,7 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
     }
     if (prof) {
       for (int i = 0; i < n_steps; ++i) {
-        HIPCHK(c, enqueue_step(c, all, a, true, c->pev));
+        HIPCHK(c, enqueue_step(c, all, a, true, true));
         HIPCHK(c, accumulate_phases(c));
         ++c->phase_steps;
       }
@@ -1136,7 +1164,7 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
     }
     for (int i = 0; i < n_steps; ++i) {
       for (size_t k = 0; k < plans.size(); ++k) {
-        HIPCHK(c, enqueue_step(c, plans[k], args[k], true, prof ? c->pev : nullptr));
+        HIPCHK(c, enqueue_step(c, plans[k], args[k], true, prof));
         if (prof) HIPCHK(c, accumulate_phases(c));
       }
       if (prof) ++c->phase_steps;
@@ -1230,6 +1258,7 @@ romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, flo
     p.bpairs.clear();
     p.bblocks.clear();
     p.bins.clear();
+    p.bgroups.clear();
     p.rec_size = 0;
     p.bin_regions = 0;
     s = stage_plans(c, {&p});
@@ -1456,8 +1485,10 @@ romap_status romap_field_backward(romap_ctx* c, int32_t id, const float* params_
   const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels;
   HIPCHK(c, rm_launch_fill(d_params_dev, o.P, 0.0f, c->stream));
   HIPCHK(c, rm_launch_field(a, NS, K1_of(c->cfg), c->cfg.precision, c->stream));
-  HIPCHK(c, rm_launch_encode_bwd(a, NS, L, 256, c->stream));
-  HIPCHK(c, rm_launch_binned_bwd(a, NS, c->stream));
+  for (const BinGroup& g : p.bgroups) {
+    HIPCHK(c, rm_launch_bin_scatter(a, g, NS, c->stream));
+    HIPCHK(c, rm_launch_bin_acc(a, g, c->stream));
+  }
   HIPCHK(c, rm_launch_reduce(a, RM_MLP_MAX, c->stream));
   return ROMAP_OK;
 }
