@@ -20,7 +20,7 @@
 #define RM_SCAT_WG 512      /* samples (threads) per block of the binning kernel */
 #define RM_ACC_CHUNK 16384  /* records per accumulation workgroup (about) */
 #define RM_ACC_MAXK 256     /* accumulation workgroups per region, at most */
-#define RM_GROUP_RECORDS (1ll << 28) /* record slots of one bin group (2.5 GiB) */
+#define RM_GROUP_RECORDS (1ll << 29) /* record slots of one bin group (5 GiB) */
 #define RM_FX_BITS 38       /* fixed-point fraction bits of the region sums */
 #define RM_MAX_REGIONS 4096 /* 2^24 / 2^12 */
 
@@ -203,7 +203,7 @@ struct StepArgs {
 
 // Launch helpers implemented in romap_kernels.hip.
 hipError_t rm_launch_raygen(const StepArgs& a, int NS, hipStream_t st);
-hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int L, int block, hipStream_t st);
+hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int block, hipStream_t st);
 hipError_t rm_launch_bin_scatter(const StepArgs& a, const BinGroup& g, int NS, hipStream_t st);
 hipError_t rm_launch_bin_acc(const StepArgs& a, const BinGroup& g, hipStream_t st);
 hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st);

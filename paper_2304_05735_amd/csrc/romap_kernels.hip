@@ -157,6 +157,45 @@ __device__ inline float corner_weight(const Cell& cl, int b) {
   return (wx * wy) * wz;
 }
 
+// All 8 corner indices of a cell, with the products shared between corners:
+// (c + 1) * P = c * P + P mod 2^32 for the hash, and the dense index of
+// corner b is the cell's index plus b's offsets.  Same values as corner_index.
+__device__ inline void cell_corners(const Cell& cl, uint32_t N, uint32_t T, bool hashed,
+                                    uint32_t idx[8]) {
+  if (hashed) {
+    const uint32_t x0 = cl.c[0], x1 = x0 + 1u;
+    const uint32_t y0 = cl.c[1] * 2654435761u, y1 = y0 + 2654435761u;
+    const uint32_t z0 = cl.c[2] * 805459861u, z1 = z0 + 805459861u;
+    const uint32_t m = T - 1u;
+    idx[0] = (x0 ^ y0 ^ z0) & m;
+    idx[1] = (x1 ^ y0 ^ z0) & m;
+    idx[2] = (x0 ^ y1 ^ z0) & m;
+    idx[3] = (x1 ^ y1 ^ z0) & m;
+    idx[4] = (x0 ^ y0 ^ z1) & m;
+    idx[5] = (x1 ^ y0 ^ z1) & m;
+    idx[6] = (x0 ^ y1 ^ z1) & m;
+    idx[7] = (x1 ^ y1 ^ z1) & m;
+  } else {
+    const uint32_t n1 = N + 1u, n2 = n1 * n1;
+    const uint32_t b0 = cl.c[0] + cl.c[1] * n1 + cl.c[2] * n2;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+      idx[b] = b0 + (uint32_t)(b & 1) + ((b >> 1) & 1) * n1 + ((b >> 2) & 1) * n2;
+  }
+}
+
+// All 8 trilinear weights, (wx * wy) * wz as corner_weight, sharing wx * wy.
+__device__ inline void cell_weights(const Cell& cl, float w[8]) {
+  const float wx[2] = {1.0f - cl.f[0], cl.f[0]};
+  const float wy[2] = {1.0f - cl.f[1], cl.f[1]};
+  const float wz[2] = {1.0f - cl.f[2], cl.f[2]};
+  float wxy[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wxy[q] = wx[q & 1] * wy[q >> 1];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) w[b] = wxy[b & 3] * wz[b >> 2];
+}
+
 __device__ inline int find_sobj(const StepObj* so, int n, int r) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -308,40 +347,51 @@ __device__ inline bool ray_active(uint32_t flags) {
 }
 
 // ---------------------------------------------------------------------------
-// K2: encoding forward.  Grid (ceil(S / block), L): level is the slow index,
-// so the chip sweeps one level's table at a time.  One thread per sample.
+// K2: encoding forward.  One block per RM_SCAT_WG samples of one (object,
+// level) pair, blocks ordered object by object and level by level within an
+// object, so the chip sweeps one table at a time; the object and level are
+// uniform in a block.  blockDim threads cover the block's samples.
 template <int NS>
 __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
-  const int l = blockIdx.y;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l == 0)  // fresh fill counters for the binned scatter of this pass
-    for (int64_t j = s; j < a.n_regions; j += (int64_t)gridDim.x * blockDim.x) a.bin_count[j] = 0;
-  if (s >= a.S) return;
-  const int r = (int)(s / NS), i = (int)(s % NS);
-  const RayRec R = a.rays[r];
-  if (!ray_active(R.flags)) return;
-  const ObjStatic& ob = a.objs[R.obj];
-  float p[3];
-  sample_pos(R, i, ob.half, p);
-  if (!occupied(ob.occ, p)) {  // skipped sample: no gather, zero encoding
-    a.e[(int64_t)l * a.S + s] = make_float2(0.0f, 0.0f);
-    return;
-  }
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t j = gtid; j < a.n_regions; j += (int64_t)gridDim.x * blockDim.x)
+    a.bin_count[j] = 0;  // fresh fill counters for the binned scatter of this pass
+  const BinBlock bb = a.bblocks[blockIdx.x];
+  const BinPair bp = a.bpairs[bb.pair];
+  const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
+  const int l = bp.l;
   const uint32_t N = ob.N_l[l], T = ob.T_l[l];
   const bool hashed = (ob.hashed_mask >> l) & 1u;
-  Cell cl;
-  make_cell(p, N, cl);
   const float* G = (a.params_override ? a.params_override : ob.params) + ob.off[l];
-  float ex = 0.0f, ey = 0.0f;
+  for (int k = threadIdx.x; k < RM_SCAT_WG; k += blockDim.x) {
+    const int64_t ks = (int64_t)bb.blk * RM_SCAT_WG + k;
+    if (ks >= bp.n_samples) break;
+    const int64_t s = bp.s_begin + ks;
+    const RayRec R = a.rays[s / NS];
+    if (!ray_active(R.flags)) continue;
+    float p[3];
+    sample_pos(R, (int)(s % NS), ob.half, p);
+    if (!occupied(ob.occ, p)) {  // skipped sample: no gather, zero encoding
+      a.e[(int64_t)l * a.S + s] = make_float2(0.0f, 0.0f);
+      continue;
+    }
+    Cell cl;
+    make_cell(p, N, cl);
+    uint32_t idx[8];
+    float w[8];
+    cell_corners(cl, N, T, hashed, idx);
+    cell_weights(cl, w);
+    float2 g[8];
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const uint32_t id = corner_index(cl, b, N, T, hashed);
-    const float2 g = *(const float2*)(G + 2 * (int64_t)id);
-    const float w = corner_weight(cl, b);
-    ex = fmaf(w, g.x, ex);
-    ey = fmaf(w, g.y, ey);
+    for (int b = 0; b < 8; ++b) g[b] = *(const float2*)(G + 2 * (int64_t)idx[b]);
+    float ex = 0.0f, ey = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      ex = fmaf(w[b], g[b].x, ex);
+      ey = fmaf(w[b], g[b].y, ey);
+    }
+    a.e[(int64_t)l * a.S + s] = make_float2(ex, ey);
   }
-  a.e[(int64_t)l * a.S + s] = make_float2(ex, ey);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,27 +411,24 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
 //                  otherwise, and read-modify-write if the bin overflowed)
 // The bins' fill counters are zeroed by the gather kernel of the same pass.
 
-// The 8 corner records of sample s at the pair's level; false if none.
+// The 8 corner records of sample s at level l of object ob; false if none.
 template <int NS>
-__device__ inline bool bin_records(const StepArgs& a, const BinPair& bp, int64_t s,
-                                   uint32_t idx[8], float2 v[8]) {
+__device__ inline bool bin_records(const StepArgs& a, const ObjStatic& ob, int l, uint32_t N,
+                                   uint32_t T, bool hashed, int64_t s, uint32_t idx[8],
+                                   float2 v[8]) {
   const RayRec R = a.rays[s / NS];
   if (!ray_active(R.flags)) return false;
-  const int l = bp.l;
   const float2 g = a.de[(int64_t)l * a.S + s];
   if (g.x == 0.0f && g.y == 0.0f) return false;
-  const ObjStatic& ob = a.objs[R.obj];
   float p[3];
   sample_pos(R, (int)(s % NS), ob.half, p);
   Cell cl;
-  make_cell(p, ob.N_l[l], cl);
-  const bool hashed = (ob.hashed_mask >> l) & 1u;
+  make_cell(p, N, cl);
+  cell_corners(cl, N, T, hashed, idx);
+  float w[8];
+  cell_weights(cl, w);
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    idx[b] = corner_index(cl, b, ob.N_l[l], ob.T_l[l], hashed);
-    const float w = corner_weight(cl, b);
-    v[b] = make_float2(w * g.x, w * g.y);
-  }
+  for (int b = 0; b < 8; ++b) v[b] = make_float2(w[b] * g.x, w[b] * g.y);
   return true;
 }
 
@@ -445,7 +492,11 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
   uint32_t idx[8];
   float2 v[8];
   int rank[8];
-  const bool has = k < bp.n_samples && bin_records<NS>(a, bp, bp.s_begin + k, idx, v);
+  const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];  // uniform in the block
+  const uint32_t NL = ob.N_l[bp.l], TL = ob.T_l[bp.l];
+  const bool hashed = (ob.hashed_mask >> bp.l) & 1u;
+  const bool has =
+      k < bp.n_samples && bin_records<NS>(a, ob, bp.l, NL, TL, hashed, bp.s_begin + k, idx, v);
   if (has) {
 #pragma unroll
     for (int b = 0; b < 8; ++b) rank[b] = atomicAdd(&lcnt[idx[b] >> RM_RB_BITS], 1);
@@ -470,17 +521,28 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
   }
   if (one && tid < bp.R) gpos[tid] = mine;
   __syncthreads();
-  const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
+  // per region: slot of staging position j is dst[r] + j (relative to the
+  // pair's records) as long as it stays below the bin's end lim[r]
+  int* dst = lbase;  // reused: lbase is read once per region here
+  int* lim = gpos;
+  for (int r = tid; r < bp.R; r += RM_SCAT_WG) {
+    const int b0 = r * bp.cap;
+    const int d = b0 + gpos[r] - lbase[r];
+    dst[r] = d;
+    lim[r] = b0 + bp.cap;
+  }
+  __syncthreads();
   float* gl = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l];
+  uint16_t* ridx = a.rec_idx + bp.rec_base;
+  float2* rval = a.rec_val + bp.rec_base;
   for (int j = tid; j < n; j += RM_SCAT_WG) {
     const uint32_t id = s_id[j];
     const int r = (int)(id >> RM_RB_BITS);
-    const int pos = gpos[r] + (j - lbase[r]);
+    const int slot = dst[r] + j;
     const float2 val = s_val[j];
-    if (pos < bp.cap) {
-      const int64_t slot = bp.rec_base + (int64_t)r * bp.cap + pos;
-      a.rec_idx[slot] = (uint16_t)(id & (RM_RB - 1));
-      a.rec_val[slot] = val;
+    if (slot < lim[r]) {
+      ridx[slot] = (uint16_t)(id & (RM_RB - 1));
+      rval[slot] = val;
     } else {  // bin full: direct atomics (correct, only slower)
       unsafeAtomicAdd(gl + 2 * (int64_t)id, val.x);
       unsafeAtomicAdd(gl + 2 * (int64_t)id + 1, val.y);
@@ -1412,10 +1474,9 @@ hipError_t rm_launch_raygen(const StepArgs& a, int NS, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int L, int block, hipStream_t st) {
-  if (a.S <= 0) return hipSuccess;
-  dim3 grid(cdiv(a.S, block), L);
-  RM_NS_SWITCH(NS, (k_encode_fwd<NSC><<<grid, block, 0, st>>>(a)));
+hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int block, hipStream_t st) {
+  if (a.n_bblocks <= 0) return hipSuccess;
+  RM_NS_SWITCH(NS, (k_encode_fwd<NSC><<<a.n_bblocks, block, 0, st>>>(a)));
   return hipGetLastError();
 }
 

@@ -477,7 +477,7 @@ hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a, bool ada
   RM_MARK(-1);
   if ((e = rm_launch_raygen(a, NS, c->stream)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_RAYGEN);
-  if ((e = rm_launch_encode_fwd(a, NS, L, p.enc_block, c->stream)) != hipSuccess) return e;
+  if ((e = rm_launch_encode_fwd(a, NS, p.enc_block, c->stream)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_ENCODE);
   if ((e = rm_launch_pack(a, K1, c->stream)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_PACK);
@@ -549,7 +549,7 @@ romap_status autotune(romap_ctx* c, const std::vector<std::pair<int, int>>& list
     if (st != ROMAP_OK) return st;
     StepArgs a = plan_args(c, p);
     HIPCHK(c, rm_launch_raygen(a, NS, c->stream));
-    HIPCHK(c, rm_launch_encode_fwd(a, NS, L, 256, c->stream));
+    HIPCHK(c, rm_launch_encode_fwd(a, NS, 256, c->stream));
     HIPCHK(c, rm_launch_pack(a, K1, c->stream));
     StepArgs ar = a;  // the reduce only reads the records here: no step advance, no loss
     ar.mode = RM_MODE_ADJOINT;
@@ -571,9 +571,9 @@ romap_status autotune(romap_ctx* c, const std::vector<std::pair<int, int>>& list
     if (cand == cands[0]) {
       float bb = 1e30f;
       for (int blk_c : blocks) {
-        HIPCHK(c, rm_launch_encode_fwd(a, NS, L, blk_c, c->stream));
+        HIPCHK(c, rm_launch_encode_fwd(a, NS, blk_c, c->stream));
         HIPCHK(c, hipEventRecord(e0, c->stream));
-        for (int r = 0; r < 3; ++r) HIPCHK(c, rm_launch_encode_fwd(a, NS, L, blk_c, c->stream));
+        for (int r = 0; r < 3; ++r) HIPCHK(c, rm_launch_encode_fwd(a, NS, blk_c, c->stream));
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipEventSynchronize(e1));
         HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
@@ -1254,10 +1254,8 @@ romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, flo
     const int nr = (int)std::min<int64_t>(chunk, npix - p0);
     Plan p;
     build_plan(c, {{id, nr}}, 8, 256, p);
-    p.chunks.clear();  // forward only: no Adam, no gradient scatter
-    p.bpairs.clear();
-    p.bblocks.clear();
-    p.bins.clear();
+    p.chunks.clear();  // forward only: no Adam, no gradient scatter (the
+    p.bins.clear();    // sample blocks stay: the gather runs over them)
     p.bgroups.clear();
     p.rec_size = 0;
     p.bin_regions = 0;
@@ -1269,7 +1267,7 @@ romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, flo
     a.out_depth = d_depth ? d_depth + p0 : nullptr;
     a.out_tend = d_tend ? d_tend + p0 : nullptr;
     HIPCHK(c, rm_launch_camera_rays(a, NS, M, cc, cam->fx, cam->fy, cam->cx, cam->cy, W, (int)p0, c->stream));
-    HIPCHK(c, rm_launch_encode_fwd(a, NS, L, 256, c->stream));
+    HIPCHK(c, rm_launch_encode_fwd(a, NS, 256, c->stream));
     HIPCHK(c, rm_launch_pack(a, K1, c->stream));
     HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1444,7 +1442,7 @@ static romap_status field_common(romap_ctx* c, int32_t id, const float* params_d
   a.params_override = params_dev;
   const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels, K1 = K1_of(c->cfg);
   HIPCHK(c, rm_launch_user_rays(a, NS, rays_dev, c->stream));
-  HIPCHK(c, rm_launch_encode_fwd(a, NS, L, 256, c->stream));
+  HIPCHK(c, rm_launch_encode_fwd(a, NS, 256, c->stream));
   HIPCHK(c, rm_launch_pack(a, K1, c->stream));
   return ROMAP_OK;
 }
