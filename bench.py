@@ -45,8 +45,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2304_05735_amd", "csrc", "romap_kernels.h
 # kernels of each timed phase (the phase's duration covers all of them)
 PHASE_KERNELS = {
     "raygen": ["k_raygen"], "encode_fwd": ["k_encode_fwd"], "pack": ["k_pack"],
-    "field": ["k_field"], "bin_scatter": ["k_bin_scatter"], "bin_acc": ["k_bin_acc"],
-    "reduce": ["k_reduce"], "adam": ["k_adam"],
+    "field": ["k_field"], "reduce": ["k_reduce"], "bin_scatter": ["k_bin_scatter"],
+    "bin_acc": ["k_bin_acc"], "bin_finish": ["k_bin_finish"],
 }
 
 
@@ -227,11 +227,8 @@ def algorithmic_bytes(ctx, ids, rays, phase):
         return S * L * (64 + 8)
     if phase == "bin_scatter":  # 8 B adjoint read + 8 records x 10 B written
         return S * L * (8 + 80)
-    if phase == "bin_acc":      # 8 records x 10 B read; every grid gradient entry written once
-        return S * L * 80 + 4 * grid
-    if phase == "adam":         # p, g, m, v read; p, m, v, g written
-        return sum(32 * (ctx.object_info(i).n_grid_params + ctx.object_info(i).n_mlp_params)
-                   for i in ids)
+    if phase == "bin_acc":      # 8 records x 10 B read; Adam on the table: p, m, v read and written
+        return S * L * 80 + 24 * grid
     if phase == "field":        # encodings read twice (forward, recompute), adjoints written
         return S * L * 8 * 3
     return 0

@@ -119,7 +119,9 @@ typedef struct {
 #define ROMAP_PARAMS 0 /* grid then MLP */
 #define ROMAP_ADAM_M 1
 #define ROMAP_ADAM_V 2
-#define ROMAP_GRAD 3   /* gradient buffer (left in place by romap_loss_and_grad) */
+#define ROMAP_GRAD 3   /* gradient buffer: dL/dparams after romap_loss_and_grad; zero
+                        * after romap_train, whose Adam update is applied where each
+                        * gradient is complete (the buffer is not written) */
 
 /* Fills *cfg with the defaults: L 16, N_min 16, N_max 1024, T 2^19, N 64,
  * 4096 rays, Adam lr 1e-2 b1 0.9 b2 0.99 eps 1e-15, lambda_1 0.5,
@@ -254,12 +256,12 @@ romap_status romap_field_backward(romap_ctx* ctx, int32_t object_id, const float
 /* Kernels of one training step, in launch order. */
 #define ROMAP_PHASE_RAYGEN 0      /* ray draw, classification, box clipping (Sec. V-B) */
 #define ROMAP_PHASE_ENCODE 1      /* hash-grid gather */
-#define ROMAP_PHASE_PACK 2        /* MLP weights -> MFMA operand images */
+#define ROMAP_PHASE_PACK 2        /* MLP weights -> MFMA operand images, step advance */
 #define ROMAP_PHASE_FIELD 3       /* MLP, volume rendering, loss, adjoint */
-#define ROMAP_PHASE_BIN_SCATTER 4 /* hash-grid gradient: records sorted into bins */
-#define ROMAP_PHASE_BIN_ACC 5     /* hash-grid gradient: bin sums into the gradient */
-#define ROMAP_PHASE_REDUCE 6      /* per-object MLP gradient and loss */
-#define ROMAP_PHASE_ADAM 7        /* dense Adam */
+#define ROMAP_PHASE_REDUCE 4      /* per-object MLP gradient and loss; Adam on the MLP */
+#define ROMAP_PHASE_BIN_SCATTER 5 /* hash-grid gradient: records sorted into bins */
+#define ROMAP_PHASE_BIN_ACC 6     /* hash-grid gradient: bin sums; Adam on the table */
+#define ROMAP_PHASE_BIN_FINISH 7  /* Adam on table regions summed by several groups */
 #define ROMAP_N_PHASES 8
 
 /* Average duration in ms of each kernel of a step (summed over its launches

@@ -28,7 +28,8 @@ ROMAP_E_STATE = -6
 PREC_FP32, PREC_BF16 = 0, 1
 BATCH_ALL, BATCH_PER_OBJECT = 0, 1
 PARAMS, ADAM_M, ADAM_V, GRAD = 0, 1, 2, 3
-PHASES = ("raygen", "encode_fwd", "pack", "field", "bin_scatter", "bin_acc", "reduce", "adam")
+PHASES = ("raygen", "encode_fwd", "pack", "field", "reduce", "bin_scatter", "bin_acc",
+          "bin_finish")
 
 
 class romap_config(C.Structure):

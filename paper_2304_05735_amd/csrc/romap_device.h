@@ -13,7 +13,7 @@
 #define RM_REC_LOSS 4224
 #define RM_WPACK 10240      /* packed MLP weight image, elements (K1 <= 32) */
 #define RM_WG 256           /* threads of the fused field kernel (4 waves) */
-#define RM_ADAM_CHUNK 8192  /* floats per Adam work chunk */
+#define RM_FIN_WG 512       /* entries per workgroup of the finishing kernel */
 #define RM_RB_BITS 12       /* binned scatter: table entries per region = 4096 */
 #define RM_RB (1 << RM_RB_BITS)
 #define RM_ACC_WG 512       /* threads of the region accumulation kernel */
@@ -115,10 +115,9 @@ struct Item {           // one workgroup of the fused field kernel
   int32_t pad;
 };
 
-struct Chunk {          // one workgroup of the Adam kernel
-  int32_t obj;
-  int32_t pad;
-  int64_t begin;
+struct Fin {            // one workgroup of the finishing kernel: RM_FIN_WG
+  int32_t pair, region; // entries of a region that several workgroups summed
+  int32_t sub, pad;
 };
 
 struct BinPair {        // one (object of the launch, binned level)
@@ -160,8 +159,8 @@ struct StepArgs {
   int32_t n_sobj;
   const Item* items;
   int32_t n_items;
-  const Chunk* chunks;
-  int32_t n_chunks;
+  const Fin* fins;
+  int32_t n_fins;
   RayRec* rays;
   int32_t n_rays;
   float2* e;            // [L][S] encodings
@@ -174,7 +173,7 @@ struct StepArgs {
   float lambda_depth, lambda_density;
   float lr, beta1, beta2, eps;
   int32_t mode;
-  int32_t advance;      // reduce kernel advances the Adam step counter
+  int32_t fuse_adam;    // training step: Adam applied where each gradient is complete
   const float* params_override; // single-object launches only
   float* grad_override;
   const float* adj_rgb;
@@ -209,7 +208,7 @@ hipError_t rm_launch_bin_acc(const StepArgs& a, const BinGroup& g, hipStream_t s
 hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st);
 hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStream_t st);
 hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st);
-hipError_t rm_launch_adam(const StepArgs& a, hipStream_t st);
+hipError_t rm_launch_bin_finish(const StepArgs& a, hipStream_t st);
 hipError_t rm_launch_camera_rays(const StepArgs& a, int NS, const float* M, const float* c,
                                  float fx, float fy, float cx, float cy, int W, int pix0,
                                  hipStream_t st);

@@ -5,15 +5,23 @@
 //   k_raygen       draw rays in each object's detection boxes, classify them by
 //                  the instance mask, back-project into the object frame, clip
 //                  to the 3D box (Sec. V-B)                        [FP32, exact]
-//   k_encode_fwd   multiresolution hash-grid gather, level-major so that one
-//                  level's table (<= 4 MiB) stays resident in each XCD's L2
-//   k_pack         MLP weights -> MFMA operand images (FP32 and BF16)
+//   k_encode_fwd   multiresolution hash-grid gather, one (object, level) table
+//                  at a time
+//   k_pack         MLP weights -> MFMA operand images (FP32 and BF16); advances
+//                  the Adam step
 //   k_field        fused per-ray MLP (MFMA) + volume rendering (Eq. 6) + loss
 //                  (Eq. 7-11) + adjoint, activations recomputed in the backward
 //                  half, wavefront prefix scans for transmittance
-//   k_encode_bwd   level-major scatter-add of the encoding adjoint (atomics)
-//   k_reduce       per-object MLP gradient and loss from the work-item records
-//   k_adam         dense Adam over every parameter of every object of the step
+//   k_reduce       per-object MLP gradient and loss from the work-item records;
+//                  Adam on the MLP weights
+//   k_bin_scatter  encoding adjoint -> (entry, value) records sorted into bins
+//                  of table regions
+//   k_bin_acc      region sums in LDS; Adam on the region's table entries
+//   k_bin_finish   Adam on regions summed by several workgroups
+//
+// Adam is dense: every parameter of every object of the step is updated each
+// step, each where its gradient is complete, so the gradient itself is never
+// written in a training step.
 //
 // Precision: the ray / sample-position / cell / hash path is IEEE FP32 with no
 // contraction (this file is built with -ffp-contract=off; FMAs are written
@@ -394,6 +402,27 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
   }
 }
 
+// One Adam update of parameter p with gradient g (moments m, v; bias
+// corrections bc1, bc2 of the step).
+__device__ inline void adam1(float& p, float& m, float& v, float g, const StepArgs& a, float bc1,
+                             float bc2) {
+  m = a.beta1 * m + (1.0f - a.beta1) * g;
+  v = a.beta2 * v + (1.0f - a.beta2) * (g * g);
+  p -= a.lr * (m / bc1) / (sqrtf(v / bc2) + a.eps);
+}
+
+// Adam on the two features of the table entry at float offset off, with
+// gradient (gx, gy); the object's step has been advanced by the pack kernel.
+__device__ inline void adam_entry(const ObjStatic& ob, int64_t off, float gx, float gy,
+                                  const StepArgs& a, float bc1, float bc2) {
+  float2 p = *(float2*)(ob.params + off), m = *(float2*)(ob.m + off), v = *(float2*)(ob.v + off);
+  adam1(p.x, m.x, v.x, gx, a, bc1, bc2);
+  adam1(p.y, m.y, v.y, gy, a, bc1, bc2);
+  *(float2*)(ob.params + off) = p;
+  *(float2*)(ob.m + off) = m;
+  *(float2*)(ob.v + off) = v;
+}
+
 // ---------------------------------------------------------------------------
 // K6: encoding backward, grad[idx_b] += w_b * de for the 8 corners of every
 // sample, as a binned scatter.  Float atomics on a table cost per cache line
@@ -585,7 +614,11 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
   const int per = ((n + bp.K - 1) / bp.K + 3) & ~3;
   const int i0 = bn.k * per;
   const int i1 = (i0 + per < n) ? i0 + per : n;
-  if (i0 >= i1) return;  // empty share: nothing to add
+  // The sole workgroup of a region (K = 1) applies a training step's Adam
+  // update to all of the region's entries, even with no records; shared
+  // regions are finished by k_bin_finish.
+  const bool adam_here = a.fuse_adam && bp.K == 1;
+  if (i0 >= i1 && !adam_here) return;  // empty share: nothing to add
   for (int e = threadIdx.x; e < RM_RB; e += RM_ACC_WG) {
     emax[e] = 0u;
     acc[2 * e] = 0ull;
@@ -626,24 +659,37 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
     fx_add(acc, emax, e, v.x, v.y);
   }
   __syncthreads();
-  const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
+  const int oi = a.sobj[bp.so].obj;
+  const ObjStatic& ob = a.objs[oi];
   // entries of this region (a dense level's last region is partial)
   const int64_t e0 = (int64_t)bn.region * RM_RB;
   const int64_t rem = (int64_t)ob.T_l[bp.l] - e0;
   const int ne = rem < RM_RB ? (int)rem : RM_RB;
-  float2* g = (float2*)((a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l] + 2 * e0);
+  const int64_t off0 = ob.off[bp.l] + 2 * e0;  // float offset of the region
+  float2* g = (float2*)((a.grad_override ? a.grad_override : ob.grad) + off0);
+  const float bc1 = a.state[oi].bc1, bc2 = a.state[oi].bc2;
   for (int e = threadIdx.x; e < ne; e += RM_ACC_WG) {
     const uint32_t em = emax[e];
     const long long sx = (long long)acc[2 * e], sy = (long long)acc[2 * e + 1];
-    if (em == 0u && sx == 0 && sy == 0) continue;  // untouched (or only zeros)
-    float dx, dy;
+    float dx = 0.0f, dy = 0.0f;
     if (em == 0xffu) {  // an Inf or NaN among the records
       dx = dy = __int_as_float(0x7fc00000);
-    } else {
+    } else if (sx != 0 || sy != 0) {
       const double isc = pow2d((int)(em > 1u ? em : 1u) - 127 - RM_FX_BITS);
       dx = (float)((double)sx * isc);
       dy = (float)((double)sy * isc);
     }
+    if (adam_here) {  // the entry's gradient is complete: update, keep g zero
+      if (spilled) {
+        const float2 x = g[e];
+        dx += x.x;
+        dy += x.y;
+        g[e] = make_float2(0.0f, 0.0f);
+      }
+      adam_entry(ob, off0 + 2 * e, dx, dy, a, bc1, bc2);
+      continue;
+    }
+    if (em == 0u && sx == 0 && sy == 0) continue;  // untouched (or only zeros)
     if (bp.K == 1 && !spilled) {  // sole writer of a zero region: plain stores
       g[e] = make_float2(dx, dy);
     } else if (bp.K == 1) {  // the scatter's overflow atomics are in the region too
@@ -656,6 +702,25 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
       unsafeAtomicAdd(&g[e].y, dy);
     }
   }
+}
+
+// Training steps: Adam on the entries of regions that several workgroups
+// summed into the gradient (and leaves it zero for the next step).
+__global__ __launch_bounds__(RM_FIN_WG) void k_bin_finish(StepArgs a) {
+  const Fin f = a.fins[blockIdx.x];
+  const BinPair bp = a.bpairs[f.pair];
+  const int oi = a.sobj[bp.so].obj;
+  const ObjStatic& ob = a.objs[oi];
+  const int64_t e0 = (int64_t)f.region * RM_RB;
+  const int64_t rem = (int64_t)ob.T_l[bp.l] - e0;
+  const int ne = rem < RM_RB ? (int)rem : RM_RB;
+  const int e = f.sub * RM_FIN_WG + threadIdx.x;
+  if (e >= ne) return;
+  const int64_t off = ob.off[bp.l] + 2 * (e0 + e);
+  float2* g = (float2*)(ob.grad + off);
+  const float2 x = *g;
+  *g = make_float2(0.0f, 0.0f);
+  adam_entry(ob, off, x.x, x.y, a, a.state[oi].bc1, a.state[oi].bc2);
 }
 
 // ---------------------------------------------------------------------------
@@ -681,9 +746,18 @@ __device__ inline float mlp_A(const float* W, int din, int K1, int gemm, int m, 
   }
 }
 
+// Also advances each object's Adam step (training steps only): after the ray
+// draw, which uses the step as its counter, and before any Adam update.
 __global__ __launch_bounds__(256) void k_pack(StepArgs a, int K1) {
   const StepObj so = a.sobj[blockIdx.x];
   const ObjStatic& ob = a.objs[so.obj];
+  if (a.fuse_adam && blockIdx.y == 0 && threadIdx.x == 0) {
+    ObjState* st = a.state + so.obj;
+    const int kk = st->step + 1;
+    st->step = kk;
+    st->bc1 = (float)(1.0 - pow((double)a.beta1, (double)kk));
+    st->bc2 = (float)(1.0 - pow((double)a.beta2, (double)kk));
+  }
   const float* W = (a.params_override ? a.params_override : ob.params) + ob.P_grid;
   const int din = ob.din;
   const int Ms[8] = {64, 16, 64, 16, 64, 16, 64, K1};
@@ -1184,7 +1258,8 @@ __global__ __launch_bounds__(RM_WG) void k_field(StepArgs a) {
 
 // ---------------------------------------------------------------------------
 // K5: per-object MLP gradient and loss from the work-item records, summed in
-// a fixed order (deterministic); advances the Adam step counter.  A block owns
+// a fixed order (deterministic); in a training step the MLP's Adam update is
+// applied here, else the gradient is written.  A block owns
 // 256 record columns, 4 per lane (column RM_REC_LOSS is the loss); its 16
 // waves sum interleaved sixteenths of the items, then combine in LDS.
 __global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
@@ -1220,81 +1295,25 @@ __global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
   }
   const float tv[4] = {t.x, t.y, t.z, t.w};
   float* gdst = a.grad_override ? a.grad_override : ob.grad;
+  const float bc1 = a.state[so.obj].bc1, bc2 = a.state[so.obj].bc2;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int j = j0 + c;
     if (j < nm) {
-      gdst[ob.P_grid + j] = tv[c];
+      const int64_t o = ob.P_grid + j;
+      if (a.fuse_adam) {  // training step: the MLP gradient is complete here
+        adam1(ob.params[o], ob.m[o], ob.v[o], tv[c], a, bc1, bc2);
+      } else {
+        gdst[o] = tv[c];
+      }
     } else if (j == RM_REC_LOSS && a.mode == RM_MODE_TRAIN) {
       ObjState* st = a.state + so.obj;
       st->loss_acc += tv[c];
       st->n_loss += 1;
-      if (a.advance) {
-        const int kk = st->step + 1;
-        st->step = kk;
-        st->bc1 = (float)(1.0 - pow((double)a.beta1, (double)kk));
-        st->bc2 = (float)(1.0 - pow((double)a.beta2, (double)kk));
-      }
     }
   }
 }
 
-// K7: dense Adam over every parameter of the step's objects; zeroes the
-// gradient for the next step.
-__device__ inline void adam4(float4& p, const float4& g, float4& m, float4& v, float b1, float b2,
-                             float ob1, float ob2, float lr, float bc1, float bc2, float eps) {
-  float* pp = &p.x;
-  const float* gg = &g.x;
-  float* mm = &m.x;
-  float* vv = &v.x;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    mm[k] = b1 * mm[k] + ob1 * gg[k];
-    vv[k] = b2 * vv[k] + ob2 * (gg[k] * gg[k]);
-    pp[k] -= lr * (mm[k] / bc1) / (sqrtf(vv[k] / bc2) + eps);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_adam(StepArgs a) {
-  const Chunk ch = a.chunks[blockIdx.x];
-  const ObjStatic& ob = a.objs[ch.obj];
-  const float bc1 = a.state[ch.obj].bc1, bc2 = a.state[ch.obj].bc2;
-  const float b1 = a.beta1, b2 = a.beta2, lr = a.lr, eps = a.eps;
-  const float ob1 = 1.0f - b1, ob2 = 1.0f - b2;
-  float* __restrict__ P = ob.params;
-  float* __restrict__ G = ob.grad;
-  float* __restrict__ M = ob.m;
-  float* __restrict__ V = ob.v;
-  int64_t end = ch.begin + RM_ADAM_CHUNK;
-  if (end > ob.P_alloc) end = ob.P_alloc;
-  const int64_t step = 4 * (int64_t)blockDim.x;
-  // two float4 of each array per lane in flight (P_alloc is a multiple of 64)
-  for (int64_t i = ch.begin + 4 * (int64_t)threadIdx.x; i < end; i += 2 * step) {
-    const int64_t i2 = i + step;
-    const bool two = i2 < end;
-    float4 p0 = *(const float4*)(P + i), g0 = *(const float4*)(G + i);
-    float4 m0 = *(const float4*)(M + i), v0 = *(const float4*)(V + i);
-    float4 p1, g1, m1, v1;
-    if (two) {
-      p1 = *(const float4*)(P + i2);
-      g1 = *(const float4*)(G + i2);
-      m1 = *(const float4*)(M + i2);
-      v1 = *(const float4*)(V + i2);
-    }
-    adam4(p0, g0, m0, v0, b1, b2, ob1, ob2, lr, bc1, bc2, eps);
-    *(float4*)(P + i) = p0;
-    *(float4*)(M + i) = m0;
-    *(float4*)(V + i) = v0;
-    *(float4*)(G + i) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (two) {
-      adam4(p1, g1, m1, v1, b1, b2, ob1, ob2, lr, bc1, bc2, eps);
-      *(float4*)(P + i2) = p1;
-      *(float4*)(M + i2) = m1;
-      *(float4*)(V + i2) = v1;
-      *(float4*)(G + i2) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // density at object-frame points (meshing): encode + density head on VALU
@@ -1531,9 +1550,9 @@ hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t rm_launch_adam(const StepArgs& a, hipStream_t st) {
-  if (a.n_chunks <= 0) return hipSuccess;
-  k_adam<<<a.n_chunks, 256, 0, st>>>(a);
+hipError_t rm_launch_bin_finish(const StepArgs& a, hipStream_t st) {
+  if (a.n_fins <= 0 || !a.fuse_adam) return hipSuccess;
+  k_bin_finish<<<a.n_fins, RM_FIN_WG, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -47,12 +47,16 @@ struct HostObj {
   double last_centre[3]{};
   uint32_t* d_occ = nullptr;  // 64^3 occupancy bits
   bool occ_on = false;
+  // the gradient buffer holds values (a training step needs it zero: its
+  // Adam update is fused and only overflow or shared-region sums pass
+  // through the buffer)
+  bool grad_dirty = false;
 };
 
 struct Plan {                 // one launch: its objects, rays and work lists
   std::vector<StepObj> sobj;
   std::vector<Item> items;
-  std::vector<Chunk> chunks;
+  std::vector<Fin> fins;         // Adam work of regions summed by several workgroups
   std::vector<BinPair> bpairs;
   std::vector<BinBlock> bblocks;
   std::vector<Bin> bins;
@@ -63,7 +67,7 @@ struct Plan {                 // one launch: its objects, rays and work lists
   int64_t S = 0;
   int rays_per_item = 8;
   int enc_block = 256;
-  size_t off_sobj = 0, off_items = 0, off_chunks = 0;  // in the device table arena (bytes)
+  size_t off_sobj = 0, off_items = 0, off_fins = 0;  // in the device table arena (bytes)
   size_t off_bpairs = 0, off_bblocks = 0, off_bins = 0;
 };
 
@@ -269,7 +273,6 @@ StepArgs base_args(romap_ctx* c) {
   a.beta2 = c->cfg.beta2;
   a.eps = c->cfg.eps;
   a.mode = RM_MODE_TRAIN;
-  a.advance = 1;
   return a;
 }
 
@@ -303,13 +306,6 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
     so.ray_begin = ray;
     ray += pr.second;
     p.sobj.push_back(so);
-    const HostObj& o = c->objs[pr.first];
-    for (int64_t b = 0; b < o.P_alloc; b += RM_ADAM_CHUNK) {
-      Chunk ch{};
-      ch.obj = pr.first;
-      ch.begin = b;
-      p.chunks.push_back(ch);
-    }
   }
   p.n_rays = ray;
   p.S = (int64_t)ray * c->cfg.samples_per_ray;
@@ -359,6 +355,11 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
       for (int b = 0; b < bp.nb; ++b) p.bblocks.push_back(BinBlock{pi, b});
       for (int r = 0; r < bp.R; ++r)
         for (int k = 0; k < bp.K; ++k) p.bins.push_back(Bin{pi, r, k, 0});
+      if (bp.K > 1)
+        for (int r = 0; r < bp.R; ++r) {
+          const int64_t ne = std::min<int64_t>(RM_RB, (int64_t)o.T_l[l] - (int64_t)r * RM_RB);
+          for (int sub = 0; sub * RM_FIN_WG < ne; ++sub) p.fins.push_back(Fin{pi, r, sub, 0});
+        }
       p.bgroups.back().bb_end = (int)p.bblocks.size();
       p.bgroups.back().bin_end = (int)p.bins.size();
     }
@@ -381,8 +382,8 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
     tab += align256(p->sobj.size() * sizeof(StepObj));
     p->off_items = tab;
     tab += align256(p->items.size() * sizeof(Item));
-    p->off_chunks = tab;
-    tab += align256(p->chunks.size() * sizeof(Chunk));
+    p->off_fins = tab;
+    tab += align256(p->fins.size() * sizeof(Fin));
     p->off_bpairs = tab;
     tab += align256(p->bpairs.size() * sizeof(BinPair));
     p->off_bblocks = tab;
@@ -417,7 +418,7 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
   for (Plan* p : plans) {
     if (!p->sobj.empty()) std::memcpy(h.data() + p->off_sobj, p->sobj.data(), p->sobj.size() * sizeof(StepObj));
     if (!p->items.empty()) std::memcpy(h.data() + p->off_items, p->items.data(), p->items.size() * sizeof(Item));
-    if (!p->chunks.empty()) std::memcpy(h.data() + p->off_chunks, p->chunks.data(), p->chunks.size() * sizeof(Chunk));
+    if (!p->fins.empty()) std::memcpy(h.data() + p->off_fins, p->fins.data(), p->fins.size() * sizeof(Fin));
     if (!p->bpairs.empty()) std::memcpy(h.data() + p->off_bpairs, p->bpairs.data(), p->bpairs.size() * sizeof(BinPair));
     if (!p->bblocks.empty()) std::memcpy(h.data() + p->off_bblocks, p->bblocks.data(), p->bblocks.size() * sizeof(BinBlock));
     if (!p->bins.empty()) std::memcpy(h.data() + p->off_bins, p->bins.data(), p->bins.size() * sizeof(Bin));
@@ -433,8 +434,8 @@ StepArgs plan_args(romap_ctx* c, const Plan& p) {
   a.n_sobj = (int)p.sobj.size();
   a.items = (const Item*)(c->d_tables + p.off_items);
   a.n_items = (int)p.items.size();
-  a.chunks = (const Chunk*)(c->d_tables + p.off_chunks);
-  a.n_chunks = (int)p.chunks.size();
+  a.fins = (const Fin*)(c->d_tables + p.off_fins);
+  a.n_fins = (int)p.fins.size();
   a.n_rays = p.n_rays;
   a.S = p.S;
   a.bpairs = (const BinPair*)(c->d_tables + p.off_bpairs);
@@ -468,9 +469,11 @@ hipError_t mark_phase(romap_ctx* c, int ph) {
   return hipEventRecord(c->pev[c->pev_n++], c->stream);
 }
 
-hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a, bool adam,
+hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a0, bool adam,
                         bool prof = false) {
-  const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels, K1 = K1_of(c->cfg);
+  const int NS = c->cfg.samples_per_ray, K1 = K1_of(c->cfg);
+  StepArgs a = a0;
+  a.fuse_adam = adam ? 1 : 0;
   hipError_t e;
 #define RM_MARK(ph) \
   if (prof && (e = mark_phase(c, ph)) != hipSuccess) return e;
@@ -483,16 +486,16 @@ hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a, bool ada
   RM_MARK(ROMAP_PHASE_PACK);
   if ((e = rm_launch_field(a, NS, K1, c->cfg.precision, c->stream)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_FIELD);
+  if ((e = rm_launch_reduce(a, RM_MLP_MAX, c->stream)) != hipSuccess) return e;
+  RM_MARK(ROMAP_PHASE_REDUCE);
   for (const BinGroup& g : p.bgroups) {
     if ((e = rm_launch_bin_scatter(a, g, NS, c->stream)) != hipSuccess) return e;
     RM_MARK(ROMAP_PHASE_BIN_SCATTER);
     if ((e = rm_launch_bin_acc(a, g, c->stream)) != hipSuccess) return e;
     RM_MARK(ROMAP_PHASE_BIN_ACC);
   }
-  if ((e = rm_launch_reduce(a, RM_MLP_MAX, c->stream)) != hipSuccess) return e;
-  RM_MARK(ROMAP_PHASE_REDUCE);
-  if (adam && (e = rm_launch_adam(a, c->stream)) != hipSuccess) return e;
-  RM_MARK(ROMAP_PHASE_ADAM);
+  if ((e = rm_launch_bin_finish(a, c->stream)) != hipSuccess) return e;
+  RM_MARK(ROMAP_PHASE_BIN_FINISH);
 #undef RM_MARK
   return hipSuccess;
 }
@@ -551,9 +554,8 @@ romap_status autotune(romap_ctx* c, const std::vector<std::pair<int, int>>& list
     HIPCHK(c, rm_launch_raygen(a, NS, c->stream));
     HIPCHK(c, rm_launch_encode_fwd(a, NS, 256, c->stream));
     HIPCHK(c, rm_launch_pack(a, K1, c->stream));
-    StepArgs ar = a;  // the reduce only reads the records here: no step advance, no loss
+    StepArgs ar = a;  // the reduce only sums the records here: no loss, no Adam
     ar.mode = RM_MODE_ADJOINT;
-    ar.advance = 0;
     HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
     HIPCHK(c, hipEventRecord(e0, c->stream));
     for (int r = 0; r < 3; ++r) {
@@ -586,6 +588,7 @@ romap_status autotune(romap_ctx* c, const std::vector<std::pair<int, int>>& list
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  for (auto& pr : list) c->objs[pr.first].grad_dirty = true;  // the reduce wrote MLP gradients
   c->tuned[key] = {best_rpi, best_blk};
   *rpi = best_rpi;
   *blk = best_blk;
@@ -1082,6 +1085,15 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
     s = autotune(c, list, &rpi, &blk);
     if (s != ROMAP_OK) return s;
   }
+  // a training step keeps the gradient buffer at zero; clear it where
+  // romap_loss_and_grad, romap_set_params or the autotuner left values
+  for (auto& pr : list) {
+    HostObj& o = c->objs[pr.first];
+    if (o.grad_dirty) {
+      HIPCHK(c, rm_launch_fill(o.d_block + o.P_alloc, o.P_alloc, 0.0f, c->stream));
+      o.grad_dirty = false;
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (stats) {
     HIPCHK(c, hipEventCreate(&e0));
@@ -1215,9 +1227,9 @@ romap_status romap_loss_and_grad(romap_ctx* c, const int32_t* ids, int32_t n, co
     HIPCHK(c, rm_launch_fill(o.d_block + o.P_alloc, o.P_alloc, 0.0f, c->stream));
   }
   StepArgs a = plan_args(c, p);
-  a.advance = 0;
   HIPCHK(c, rm_launch_reset_loss(a, c->stream));
   HIPCHK(c, enqueue_step(c, p, a, false));
+  for (auto& pr : list) c->objs[pr.first].grad_dirty = true;
   std::vector<float> l;
   int nn = 0;
   s = read_losses(c, p, &l, &nn);
@@ -1254,8 +1266,8 @@ romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, flo
     const int nr = (int)std::min<int64_t>(chunk, npix - p0);
     Plan p;
     build_plan(c, {{id, nr}}, 8, 256, p);
-    p.chunks.clear();  // forward only: no Adam, no gradient scatter (the
-    p.bins.clear();    // sample blocks stay: the gather runs over them)
+    p.fins.clear();  // forward only: no Adam, no gradient scatter (the
+    p.bins.clear();  // sample blocks stay: the gather runs over them)
     p.bgroups.clear();
     p.rec_size = 0;
     p.bin_regions = 0;
@@ -1354,6 +1366,7 @@ romap_status romap_set_params(romap_ctx* c, int32_t id, int32_t kind, const floa
   if (!buf || n != o.P) return fail(c, ROMAP_E_INVALID_ARG, "buffer must hold exactly the object's parameter count");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(dst, buf, o.P * sizeof(float), hipMemcpyHostToDevice));
+  if (kind == ROMAP_GRAD) c->objs[id].grad_dirty = true;
   return ROMAP_OK;
 }
 
@@ -1435,7 +1448,7 @@ static romap_status field_common(romap_ctx* c, int32_t id, const float* params_d
   if (s != ROMAP_OK) return s;
   if (n_rays <= 0 || !rays_dev) return fail(c, ROMAP_E_INVALID_ARG, "bad rays");
   build_plan(c, {{id, n_rays}}, 8, 256, p);
-  p.chunks.clear();
+  p.fins.clear();
   s = stage_plans(c, {&p});
   if (s != ROMAP_OK) return s;
   a = plan_args(c, p);
@@ -1479,7 +1492,6 @@ romap_status romap_field_backward(romap_ctx* c, int32_t id, const float* params_
   a.adj_depth = d_depth_dev;
   a.adj_tend = d_tend_dev;
   a.grad_override = d_params_dev;
-  a.advance = 0;
   const int NS = c->cfg.samples_per_ray, L = c->cfg.n_levels;
   HIPCHK(c, rm_launch_fill(d_params_dev, o.P, 0.0f, c->stream));
   HIPCHK(c, rm_launch_field(a, NS, K1_of(c->cfg), c->cfg.precision, c->stream));
