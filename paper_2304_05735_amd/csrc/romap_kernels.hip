@@ -924,7 +924,7 @@ __device__ inline void load_e(const float2* e, int64_t S, int64_t s, int L, int 
 }
 
 template <int PREC, int NS, int K1>
-__global__ __launch_bounds__(RM_WG) void k_field(StepArgs a) {
+__global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void k_field(StepArgs a) {
   typedef Mma<PREC> MM;
   typedef typename MM::wtype wt;
   constexpr int NB = NS / 16;             // 16-sample blocks per ray
