@@ -619,6 +619,31 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
   // regions are finished by k_bin_finish.
   const bool adam_here = a.fuse_adam && bp.K == 1;
   if (i0 >= i1 && !adam_here) return;  // empty share: nothing to add
+  const int oi = a.sobj[bp.so].obj;
+  const ObjStatic& ob = a.objs[oi];
+  // entries of this region (a dense level's last region is partial)
+  const int64_t e0 = (int64_t)bn.region * RM_RB;
+  const int64_t rem = (int64_t)ob.T_l[bp.l] - e0;
+  const int ne = rem < RM_RB ? (int)rem : RM_RB;
+  const int64_t off0 = ob.off[bp.l] + 2 * e0;  // float offset of the region
+  // Adam operands of this thread's entries, loaded now so that they arrive
+  // while the records are summed
+  constexpr int EPT = RM_RB / RM_ACC_WG;
+  float2* __restrict__ Pp = (float2*)(ob.params + off0);
+  float2* __restrict__ Pm = (float2*)(ob.m + off0);
+  float2* __restrict__ Pv = (float2*)(ob.v + off0);
+  float2 ap[EPT], am[EPT], av[EPT];
+  if (adam_here) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = threadIdx.x + k * RM_ACC_WG;
+      if (e < ne) {
+        ap[k] = Pp[e];
+        am[k] = Pm[e];
+        av[k] = Pv[e];
+      }
+    }
+  }
   for (int e = threadIdx.x; e < RM_RB; e += RM_ACC_WG) {
     emax[e] = 0u;
     acc[2 * e] = 0ull;
@@ -659,16 +684,12 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
     fx_add(acc, emax, e, v.x, v.y);
   }
   __syncthreads();
-  const int oi = a.sobj[bp.so].obj;
-  const ObjStatic& ob = a.objs[oi];
-  // entries of this region (a dense level's last region is partial)
-  const int64_t e0 = (int64_t)bn.region * RM_RB;
-  const int64_t rem = (int64_t)ob.T_l[bp.l] - e0;
-  const int ne = rem < RM_RB ? (int)rem : RM_RB;
-  const int64_t off0 = ob.off[bp.l] + 2 * e0;  // float offset of the region
   float2* g = (float2*)((a.grad_override ? a.grad_override : ob.grad) + off0);
   const float bc1 = a.state[oi].bc1, bc2 = a.state[oi].bc2;
-  for (int e = threadIdx.x; e < ne; e += RM_ACC_WG) {
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = threadIdx.x + k * RM_ACC_WG;
+    if (e >= ne) break;
     const uint32_t em = emax[e];
     const long long sx = (long long)acc[2 * e], sy = (long long)acc[2 * e + 1];
     float dx = 0.0f, dy = 0.0f;
@@ -686,7 +707,11 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
         dy += x.y;
         g[e] = make_float2(0.0f, 0.0f);
       }
-      adam_entry(ob, off0 + 2 * e, dx, dy, a, bc1, bc2);
+      adam1(ap[k].x, am[k].x, av[k].x, dx, a, bc1, bc2);
+      adam1(ap[k].y, am[k].y, av[k].y, dy, a, bc1, bc2);
+      Pp[e] = ap[k];
+      Pm[e] = am[k];
+      Pv[e] = av[k];
       continue;
     }
     if (em == 0u && sx == 0 && sy == 0) continue;  // untouched (or only zeros)
