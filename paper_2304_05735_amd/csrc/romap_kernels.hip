@@ -389,9 +389,25 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
     float w[8];
     cell_corners(cl, N, T, hashed, idx);
     cell_weights(cl, w);
+    // The two corners of an x-pair are neighbouring entries on dense levels
+    // (index + 1) and, when the cell's x is even, on hashed ones (x enters
+    // the hash with factor 1: index ^ 1): then one 16-byte load brings both,
+    // halving the cache requests of the pair.
     float2 g[8];
+    const bool adj = !hashed || (cl.c[0] & 1u) == 0u;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) g[b] = *(const float2*)(G + 2 * (int64_t)idx[b]);
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t i0 = idx[2 * q], i1 = idx[2 * q + 1];
+      if (adj) {
+        const uint32_t lo = i0 < i1 ? i0 : i1;
+        const float4 v = *(const float4*)(G + 2 * (int64_t)lo);
+        g[2 * q] = i0 == lo ? make_float2(v.x, v.y) : make_float2(v.z, v.w);
+        g[2 * q + 1] = i1 == lo ? make_float2(v.x, v.y) : make_float2(v.z, v.w);
+      } else {
+        g[2 * q] = *(const float2*)(G + 2 * (int64_t)i0);
+        g[2 * q + 1] = *(const float2*)(G + 2 * (int64_t)i1);
+      }
+    }
     float ex = 0.0f, ey = 0.0f;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
