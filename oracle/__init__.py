@@ -101,6 +101,10 @@ def lib():
                                    P, P, P, P, C.c_int]
         _lib.or_query_density.argtypes = [C.POINTER(Levels), P, P, C.c_int64, P, P]
         _lib.or_philox4x32_10.argtypes = [P, P, P]
+        _lib.or_mc_case.argtypes = [C.c_int, P]
+        _lib.or_mc_case.restype = C.c_int
+        _lib.or_marching_cubes.argtypes = [P, C.c_int, C.c_float, P, P, P, C.c_int64]
+        _lib.or_marching_cubes.restype = C.c_int64
         _lib.or_field.argtypes = [C.POINTER(Config), C.POINTER(Levels), P, P, C.c_int, P, P, P, P,
                                   P, P, P, P, P, P, C.c_int]
     return _lib
@@ -108,6 +112,36 @@ def lib():
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def mc_case(m: int):
+    """Triangles of marching-cubes case m: (n, 3) edge numbers."""
+    t = np.zeros(16, np.int8)
+    n = lib().or_mc_case(int(m), _p(t))
+    return t[:3 * n].reshape(n, 3).astype(np.int64)
+
+
+def grid_points(res, lo, hi):
+    """Corner positions of a res^3 cell grid, x fastest, as the mesher forms
+    them: lo + (hi - lo) * (i / res) in FP32."""
+    lo = np.asarray(lo, np.float32)
+    hi = np.asarray(hi, np.float32)
+    f = (np.arange(res + 1, dtype=np.float32) / np.float32(res)).astype(np.float32)
+    ax = [(lo[a] + (hi[a] - lo[a]) * f).astype(np.float32) for a in range(3)]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.stack([x, y, z], -1).reshape(-1, 3)
+
+
+def marching_cubes(grid, res, iso, lo, hi):
+    """Marching cubes on a (res+1)^3 grid (x fastest): (n, 3, 3) triangles."""
+    grid = np.ascontiguousarray(grid, np.float32).reshape(-1)
+    assert grid.size == (res + 1) ** 3
+    lo = np.asarray(lo, np.float32)
+    hi = np.asarray(hi, np.float32)
+    n = lib().or_marching_cubes(_p(grid), int(res), float(np.float32(iso)), _p(lo), _p(hi), None, 0)
+    out = np.zeros((max(n, 1), 9), np.float32)
+    lib().or_marching_cubes(_p(grid), int(res), float(np.float32(iso)), _p(lo), _p(hi), _p(out), n)
+    return out[:n].reshape(n, 3, 3)
 
 
 # --------------------------------------------------------------------------
@@ -419,6 +453,21 @@ class OracleContext:
         xyz = (p * (2.0 * o.half) - o.half).astype(np.float32)
         sig = self.query_density(oid, xyz)
         return np.packbits(sig > threshold, bitorder="little")
+
+    def extract_mesh(self, oid, res=64, iso=10.0):
+        """Density on the (res+1)^3 corners of the object's box (FP64 model,
+        rounded to FP32), marching cubes in the object frame, then the box
+        pose: world = Rz(yaw) x + t (FP64).  Returns (world, object-frame)
+        triangle arrays."""
+        o = self.objects[oid]
+        half = np.asarray(o.half, np.float32)
+        pts = grid_points(res, -half, half)
+        sig = self.query_density(oid, pts).astype(np.float32)
+        tri = marching_cubes(sig, res, iso, -half, half)
+        c, s = np.cos(float(o.yaw)), np.sin(float(o.yaw))
+        R = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+        world = tri.astype(np.float64) @ R.T + np.asarray(o.t, np.float64)
+        return world, tri
 
     def query_density(self, oid, xyz):
         o = self.objects[oid]

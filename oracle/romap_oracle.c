@@ -882,3 +882,222 @@ void or_query_density(const or_levels* lv, const float half[3], const double* pa
     or_mlp_forward(din, mlp, e, h1, y, h2, sigma + i, rgb);
   }
 }
+
+/* ------------------------------------------------------------------------
+ * Marching cubes (Lorensen & Cline 1987), the mesh extraction of Sec. III
+ * (64^3 per object in Sec. VI; meshes placed in the world by the object pose).
+ *
+ * Cell corners are numbered by their offsets, corner c = (c&1, c>>1&1, c>>2&1).
+ * Edges: 0..3 along x from corners 0,2,4,6; 4..7 along y from corners
+ * 0,1,4,5; 8..11 along z from corners 0,1,2,3.  A corner is inside when its
+ * value is > iso.  The triangles of a case are derived, not tabulated from
+ * elsewhere: the crossing points (one per edge whose ends differ) are joined
+ * into closed loops face by face -- on a face with two crossings the two are
+ * joined; on a face with four (the ambiguous pattern) each inside corner of
+ * the face is cut off by joining its two edges -- and every loop becomes a
+ * triangle fan.  Canonical form of a loop: oriented so that its normal
+ * (Newell's method over the edge midpoints) points from the inside end of
+ * its first edge to the outside end, then rotated to start at its smallest
+ * edge number; loops are emitted by increasing smallest edge number, each as
+ * a fan from its first vertex (in that order) whose fan has no triangle
+ * lying in a cube face: (v_a, v_a+i, v_a+i+1), i = 1 .. len-2.
+ * ---------------------------------------------------------------------- */
+
+static const int or_mc_edge_end[12][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3},
+                                          {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
+/* the 6 faces as corner cycles */
+static const int or_mc_face[6][4] = {{0, 2, 6, 4}, {1, 3, 7, 5}, {0, 1, 5, 4},
+                                     {2, 3, 7, 6}, {0, 1, 3, 2}, {4, 5, 7, 6}};
+
+static int or_mc_edge_of(int a, int b) {
+  for (int e = 0; e < 12; ++e)
+    if ((or_mc_edge_end[e][0] == a && or_mc_edge_end[e][1] == b) ||
+        (or_mc_edge_end[e][0] == b && or_mc_edge_end[e][1] == a))
+      return e;
+  return -1;
+}
+
+static int or_mc_edge_on_face(int e, int f) {
+  int hits = 0;
+  for (int i = 0; i < 4; ++i)
+    hits += (or_mc_face[f][i] == or_mc_edge_end[e][0]) + (or_mc_face[f][i] == or_mc_edge_end[e][1]);
+  return hits == 2;
+}
+
+static int8_t or_mc_tris[256][16]; /* edge triples, -1 terminated */
+static int or_mc_ntri[256];
+static int or_mc_built = 0;
+
+static void or_mc_build(void) {
+  for (int m = 0; m < 256; ++m) {
+    int nb[12][2], nn[12];
+    for (int e = 0; e < 12; ++e) nn[e] = 0;
+    for (int f = 0; f < 6; ++f) {
+      const int* cyc = or_mc_face[f];
+      int ce[4], in[4], k = 0;
+      for (int i = 0; i < 4; ++i) in[i] = (m >> cyc[i]) & 1;
+      int side[4];
+      for (int i = 0; i < 4; ++i) {
+        side[i] = or_mc_edge_of(cyc[i], cyc[(i + 1) & 3]); /* edge between cyc[i], cyc[i+1] */
+        if (in[i] != in[(i + 1) & 3]) ce[k++] = side[i];
+      }
+      int pa[2][2], np = 0;
+      if (k == 2) {
+        pa[0][0] = ce[0];
+        pa[0][1] = ce[1];
+        np = 1;
+      } else if (k == 4) { /* inside corners cut off by their two edges */
+        if (in[0]) {
+          pa[0][0] = side[3]; pa[0][1] = side[0];
+          pa[1][0] = side[1]; pa[1][1] = side[2];
+        } else {
+          pa[0][0] = side[0]; pa[0][1] = side[1];
+          pa[1][0] = side[2]; pa[1][1] = side[3];
+        }
+        np = 2;
+      }
+      for (int j = 0; j < np; ++j) {
+        const int a = pa[j][0], b = pa[j][1];
+        nb[a][nn[a]++] = b;
+        nb[b][nn[b]++] = a;
+      }
+    }
+    int used[12] = {0}, nt = 0;
+    int loops[12][12], llen[12], nl = 0;
+    for (int e0 = 0; e0 < 12; ++e0) {
+      if (nn[e0] == 0 || used[e0]) continue;
+      int len = 0, prev = -1, cur = e0;
+      /* walk from e0 towards its smaller-numbered neighbour first */
+      int first = nb[e0][0] < nb[e0][1] ? nb[e0][0] : nb[e0][1];
+      loops[nl][len++] = e0;
+      used[e0] = 1;
+      prev = e0;
+      cur = first;
+      while (cur != e0) {
+        loops[nl][len++] = cur;
+        used[cur] = 1;
+        const int nx = nb[cur][0] == prev ? nb[cur][1] : nb[cur][0];
+        prev = cur;
+        cur = nx;
+      }
+      llen[nl++] = len;
+    }
+    for (int L = 0; L < nl; ++L) {
+      int* lp = loops[L];
+      const int len = llen[L];
+      /* Newell normal over the edge midpoints */
+      double nrm[3] = {0, 0, 0};
+      for (int i = 0; i < len; ++i) {
+        double p[3], q[3];
+        for (int k = 0; k < 3; ++k) {
+          const int a0 = or_mc_edge_end[lp[i]][0], a1 = or_mc_edge_end[lp[i]][1];
+          const int b0 = or_mc_edge_end[lp[(i + 1) % len]][0],
+                    b1 = or_mc_edge_end[lp[(i + 1) % len]][1];
+          p[k] = 0.5 * (((a0 >> k) & 1) + ((a1 >> k) & 1));
+          q[k] = 0.5 * (((b0 >> k) & 1) + ((b1 >> k) & 1));
+        }
+        nrm[0] += (p[1] - q[1]) * (p[2] + q[2]);
+        nrm[1] += (p[2] - q[2]) * (p[0] + q[0]);
+        nrm[2] += (p[0] - q[0]) * (p[1] + q[1]);
+      }
+      const int c0 = or_mc_edge_end[lp[0]][0], c1 = or_mc_edge_end[lp[0]][1];
+      const int cin = ((m >> c0) & 1) ? c0 : c1, cout = cin == c0 ? c1 : c0;
+      double dot = 0;
+      for (int k = 0; k < 3; ++k) dot += nrm[k] * (double)(((cout >> k) & 1) - ((cin >> k) & 1));
+      if (dot < 0) { /* reverse */
+        for (int i = 0; i < len / 2; ++i) {
+          const int t = lp[i];
+          lp[i] = lp[len - 1 - i];
+          lp[len - 1 - i] = t;
+        }
+      }
+      int s = 0;
+      for (int i = 1; i < len; ++i)
+        if (lp[i] < lp[s]) s = i;
+      int rot[12];
+      for (int i = 0; i < len; ++i) rot[i] = lp[(s + i) % len];
+      for (int i = 0; i < len; ++i) lp[i] = rot[i];
+    }
+    /* loops by increasing first (smallest) edge */
+    for (int a = 0; a < nl; ++a)
+      for (int b = a + 1; b < nl; ++b)
+        if (loops[b][0] < loops[a][0]) {
+          int tmp[12], tl = llen[a];
+          for (int i = 0; i < 12; ++i) tmp[i] = loops[a][i];
+          for (int i = 0; i < 12; ++i) loops[a][i] = loops[b][i];
+          llen[a] = llen[b];
+          for (int i = 0; i < 12; ++i) loops[b][i] = tmp[i];
+          llen[b] = tl;
+        }
+    for (int L = 0; L < nl; ++L) {
+      /* fan apex: the first loop vertex from which no fan triangle lies in a
+       * cube face (a face holding two segments of the loop would otherwise
+       * get a flat triangle, duplicated by the neighbouring cell) */
+      const int len = llen[L];
+      int apex = 0;
+      for (int s0 = 0; s0 < len; ++s0) {
+        int flat = 0;
+        for (int i = 1; i + 1 < len && !flat; ++i)
+          for (int f = 0; f < 6; ++f)
+            if (or_mc_edge_on_face(loops[L][s0], f) &&
+                or_mc_edge_on_face(loops[L][(s0 + i) % len], f) &&
+                or_mc_edge_on_face(loops[L][(s0 + i + 1) % len], f))
+              flat = 1;
+        if (!flat) {
+          apex = s0;
+          break;
+        }
+      }
+      for (int i = 1; i + 1 < len; ++i) {
+        or_mc_tris[m][3 * nt] = (int8_t)loops[L][apex];
+        or_mc_tris[m][3 * nt + 1] = (int8_t)loops[L][(apex + i) % len];
+        or_mc_tris[m][3 * nt + 2] = (int8_t)loops[L][(apex + i + 1) % len];
+        ++nt;
+      }
+    }
+    for (int i = 3 * nt; i < 16; ++i) or_mc_tris[m][i] = -1;
+    or_mc_ntri[m] = nt;
+  }
+  or_mc_built = 1;
+}
+
+int or_mc_case(int m, int8_t tris[16]) {
+  if (!or_mc_built) or_mc_build();
+  for (int i = 0; i < 16; ++i) tris[i] = or_mc_tris[m & 255][i];
+  return or_mc_ntri[m & 255];
+}
+
+/* grid: (res+1)^3 values, x fastest, corner (i,j,k) at lo + (hi - lo) * (i,j,k)/res
+ * (FP32, that expression order).  Writes up to max_tris triangles (9 floats:
+ * three vertices) in cell order (x fastest), returns the total count.  Vertex
+ * on an edge from corner a to corner b: t = (iso - v_a) / (v_b - v_a),
+ * x = x_a + t * (x_b - x_a), FP32, no contraction. */
+int64_t or_marching_cubes(const float* grid, int res, float iso, const float lo[3],
+                          const float hi[3], float* out, int64_t max_tris) {
+  if (!or_mc_built) or_mc_build();
+  const int64_t n1 = res + 1;
+  int64_t total = 0;
+  for (int k = 0; k < res; ++k)
+    for (int j = 0; j < res; ++j)
+      for (int i = 0; i < res; ++i) {
+        float v[8], x[8][3];
+        int m = 0;
+        for (int c = 0; c < 8; ++c) {
+          const int ci = i + (c & 1), cj = j + ((c >> 1) & 1), ck = k + ((c >> 2) & 1);
+          v[c] = grid[(int64_t)ci + n1 * ((int64_t)cj + n1 * ck)];
+          const int g[3] = {ci, cj, ck};
+          for (int a = 0; a < 3; ++a) x[c][a] = lo[a] + (hi[a] - lo[a]) * ((float)g[a] / (float)res);
+          if (v[c] > iso) m |= 1 << c;
+        }
+        for (int t = 0; t < or_mc_ntri[m]; ++t, ++total) {
+          if (!out || total >= max_tris) continue;
+          for (int q = 0; q < 3; ++q) {
+            const int e = or_mc_tris[m][3 * t + q];
+            const int a = or_mc_edge_end[e][0], b = or_mc_edge_end[e][1];
+            const float s = (iso - v[a]) / (v[b] - v[a]);
+            for (int d = 0; d < 3; ++d) out[9 * total + 3 * q + d] = x[a][d] + s * (x[b][d] - x[a][d]);
+          }
+        }
+      }
+  return total;
+}

@@ -90,5 +90,8 @@ int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
 int or_occupied(const uint8_t* occ, const float p[3]);
 void or_query_density(const or_levels* lv, const float half[3], const double* params, int64_t n,
                       const float* xyz, double* sigma);
+int or_mc_case(int m, int8_t tris[16]);
+int64_t or_marching_cubes(const float* grid, int res, float iso, const float lo[3],
+                          const float hi[3], float* out, int64_t max_tris);
 
 #endif
