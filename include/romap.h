@@ -203,6 +203,40 @@ romap_status romap_render(romap_ctx* ctx, int32_t object_id, const romap_camera*
 romap_status romap_query_density(romap_ctx* ctx, int32_t object_id, const float* xyz, int64_t n,
                                  float* sigma, int32_t on_device);
 
+/* Marching cubes (Sec. III: the object meshes; 64^3 per object in Sec. VI)
+ * on a density grid of (res+1)^3 corner values, x fastest, corner (i, j, k)
+ * at lo + (hi - lo) * (i, j, k) / res (FP32, that order).  A corner is
+ * inside when its value is > iso; the vertex on an edge from corner a to b
+ * is x_a + t (x_b - x_a), t = (iso - v_a) / (v_b - v_a).  Triangles come in
+ * cell order (x fastest), each cell's as its case lists them (romap_mc_case),
+ * oriented with normals pointing from inside to outside.  tris: up to
+ * max_tris triangles of 9 floats (three vertices) are written; *n_tris
+ * receives the total count (so tris = NULL, max_tris = 0 counts).  grid and
+ * tris are device pointers when on_device (the call still waits for the
+ * count).  res in 1..160, else ROMAP_E_INVALID_ARG. */
+romap_status romap_marching_cubes(romap_ctx* ctx, const float* grid, int32_t res, float iso,
+                                  const float lo[3], const float hi[3], float* tris,
+                                  int64_t max_tris, int64_t* n_tris, int32_t on_device);
+
+/* An object's mesh: its density (as romap_query_density) on the (res+1)^3
+ * corners of its box [-a, a], then romap_marching_cubes at iso; in the
+ * object frame, or with world_frame = 1 placed by the box pose,
+ * x_w = Rz(yaw) x + t (Sec. III: meshes transformed to the global frame by
+ * the object poses).  Buffers and errors as romap_marching_cubes. */
+romap_status romap_extract_mesh(romap_ctx* ctx, int32_t object_id, int32_t res, float iso,
+                                int32_t world_frame, float* tris, int64_t max_tris,
+                                int64_t* n_tris, int32_t on_device);
+
+/* The marching-cubes case table (host only, no device needed): the edge
+ * triples of case m (bit c set = corner c inside; corner c at (c&1, c>>1&1,
+ * c>>2&1); edges 0-3 along x from corners 0,2,4,6, 4-7 along y from 0,1,4,5,
+ * 8-11 along z from 0,1,2,3) into tris[16] (-1 after the last), returns the
+ * triangle count.  Built from the cube's faces: on a face with four crossing
+ * edges each inside corner is cut off by its two edges; loops oriented by
+ * their Newell normal from inside to outside, started at their smallest
+ * edge, fanned from the first vertex whose fan has no triangle in a face. */
+int32_t romap_mc_case(int32_t m, int8_t tris[16]);
+
 /* Copies an object's parameters (kind ROMAP_PARAMS / ADAM_M / ADAM_V / GRAD)
  * to or from a host buffer of n floats.  *n_required (may be NULL) receives
  * the count; buf may be NULL to query it.  ROMAP_E_INVALID_ARG if n is

@@ -78,7 +78,8 @@ EXPORTS = ["romap_default_config", "romap_create", "romap_destroy", "romap_last_
            "romap_query_density", "romap_get_params", "romap_set_params", "romap_save",
            "romap_load", "romap_debug_rays", "romap_debug_encode", "romap_field_forward",
            "romap_field_backward", "romap_get_phase_times", "romap_sync", "romap_set_occupancy",
-           "romap_update_occupancy", "romap_get_occupancy"]
+           "romap_update_occupancy", "romap_get_occupancy", "romap_marching_cubes",
+           "romap_extract_mesh", "romap_mc_case"]
 
 
 def lib():
@@ -117,6 +118,9 @@ def lib():
             "romap_set_occupancy": [P, i32, P],
             "romap_update_occupancy": [P, i32, C.c_float],
             "romap_get_occupancy": [P, i32, P],
+            "romap_marching_cubes": [P, P, i32, C.c_float, P, P, P, i64, C.POINTER(i64), i32],
+            "romap_extract_mesh": [P, i32, i32, C.c_float, i32, P, i64, C.POINTER(i64), i32],
+            "romap_mc_case": [i32, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -152,6 +156,13 @@ def make_camera(cam: dict) -> romap_camera:
     c.fx, c.fy, c.cx, c.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
     c.width, c.height = int(cam["W"]), int(cam["H"])
     return c
+
+
+def mc_case(m: int):
+    """The library's marching-cubes case m: (n, 3) edge triples (host only)."""
+    t = np.zeros(16, np.int8)
+    n = lib().romap_mc_case(int(m), _ptr(t))
+    return t[:3 * n].reshape(n, 3).astype(np.int64)
 
 
 class Context:
@@ -235,6 +246,40 @@ class Context:
         self._check(lib().romap_render(self.h, int(oid), C.byref(c), _ptr(rgb), _ptr(depth),
                                        _ptr(opac), 0))
         return rgb, depth, opac
+
+    def marching_cubes(self, grid, res, iso, lo, hi):
+        """Marching cubes on a (res+1)^3 grid (x fastest; numpy or a device
+        tensor): (n, 3, 3) triangles (numpy, or a tensor on the grid's device)."""
+        lo = np.ascontiguousarray(lo, np.float32)
+        hi = np.ascontiguousarray(hi, np.float32)
+        n = C.c_int64(0)
+        if isinstance(grid, torch.Tensor):
+            g = grid.contiguous().float()
+            self._check(lib().romap_marching_cubes(self.h, _ptr(g), int(res), float(iso), _ptr(lo),
+                                                   _ptr(hi), None, 0, C.byref(n), 1))
+            out = torch.empty((max(n.value, 1), 3, 3), dtype=torch.float32, device=g.device)
+            self._check(lib().romap_marching_cubes(self.h, _ptr(g), int(res), float(iso), _ptr(lo),
+                                                   _ptr(hi), _ptr(out), n.value, C.byref(n), 1))
+            return out[:n.value]
+        g = np.ascontiguousarray(grid, np.float32).reshape(-1)
+        self._check(lib().romap_marching_cubes(self.h, _ptr(g), int(res), float(iso), _ptr(lo),
+                                               _ptr(hi), None, 0, C.byref(n), 0))
+        out = np.zeros((max(n.value, 1), 3, 3), np.float32)
+        self._check(lib().romap_marching_cubes(self.h, _ptr(g), int(res), float(iso), _ptr(lo),
+                                               _ptr(hi), _ptr(out), n.value, C.byref(n), 0))
+        return out[:n.value]
+
+    def extract_mesh(self, oid, res=64, iso=10.0, world=True, max_tris=None):
+        """An object's mesh: (n, 3, 3) triangles, world frame by default."""
+        n = C.c_int64(0)
+        if max_tris is None:
+            self._check(lib().romap_extract_mesh(self.h, int(oid), int(res), float(iso), int(world),
+                                                 None, 0, C.byref(n), 0))
+            max_tris = n.value
+        out = np.zeros((max(max_tris, 1), 3, 3), np.float32)
+        self._check(lib().romap_extract_mesh(self.h, int(oid), int(res), float(iso), int(world),
+                                             _ptr(out), int(max_tris), C.byref(n), 0))
+        return out[:min(n.value, max_tris)]
 
     def query_density(self, oid, xyz):
         if isinstance(xyz, torch.Tensor):

@@ -213,6 +213,29 @@ hipError_t rm_launch_camera_rays(const StepArgs& a, int NS, const float* M, cons
                                  float fx, float fy, float cx, float cy, int W, int pix0,
                                  hipStream_t st);
 hipError_t rm_launch_user_rays(const StepArgs& a, int NS, const float* rays, hipStream_t st);
+// marching cubes over a (res+1)^3 corner grid (x fastest)
+#define RM_MC_SCAN 1024      /* cells per block of the count scan */
+#define RM_MC_MAX_RES 160    /* res^3 <= 4096 scan blocks of RM_MC_SCAN */
+struct MeshArgs {
+  const float* grid;
+  int res;
+  float iso;
+  float lo[3], hi[3];
+  const int8_t* tris;       // [256][16] edge triples of each case
+  const uint8_t* ntri;      // [256] triangles of each case
+  const uint8_t* edge_a;    // [12] corners of each edge
+  const uint8_t* edge_b;
+  int* cnt;                 // res^3: triangles per cell, then in-block exclusive prefix
+  int* bsum;                // per scan block: exclusive prefix of block totals; [nb] = total
+  float* out;               // max_tris * 9
+  int64_t max_tris;
+  int world;                // apply x_w = R x + t
+  float R[9], t[3];
+};
+hipError_t rm_launch_density_grid(const ObjStatic* objs, int obj, int res, float* grid,
+                                  hipStream_t st);
+hipError_t rm_launch_mc_count(const MeshArgs& m, hipStream_t st);
+hipError_t rm_launch_mc_emit(const MeshArgs& m, hipStream_t st);
 hipError_t rm_launch_query_density(const ObjStatic* objs, int obj, const float* xyz, int64_t n,
                                    float* sigma, hipStream_t st);
 hipError_t rm_launch_debug_encode(const ObjStatic* objs, int obj, const float* p, int64_t n,

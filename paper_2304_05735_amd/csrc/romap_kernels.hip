@@ -1358,15 +1358,11 @@ __global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
 
 // ---------------------------------------------------------------------------
 // density at object-frame points (meshing): encode + density head on VALU
-__global__ __launch_bounds__(256) void k_query_density(const ObjStatic* objs, int obj,
-                                                       const float* xyz, int64_t n, float* sigma) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const ObjStatic& ob = objs[obj];
+__device__ inline float density_at(const ObjStatic& ob, const float x[3]) {
   float p[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const float q = (xyz[3 * t + k] + ob.half[k]) / (ob.half[k] + ob.half[k]);
+    const float q = (x[k] + ob.half[k]) / (ob.half[k] + ob.half[k]);
     p[k] = fminf(fmaxf(q, 0.0f), 1.0f);
   }
   float e[2 * RM_MAX_LEVELS];
@@ -1393,7 +1389,158 @@ __global__ __launch_bounds__(256) void k_query_density(const ObjStatic* objs, in
     for (int k = 0; k < ob.din; ++k) s = fmaf(W1[h * ob.din + k], e[k], s);
     y0 = fmaf(W2[h], s > 0.0f ? s : 0.0f, y0);
   }
-  sigma[t] = expf(fminf(y0, 15.0f));
+  return expf(fminf(y0, 15.0f));
+}
+
+__global__ __launch_bounds__(256) void k_query_density(const ObjStatic* objs, int obj,
+                                                       const float* xyz, int64_t n, float* sigma) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float x[3] = {xyz[3 * t], xyz[3 * t + 1], xyz[3 * t + 2]};
+  sigma[t] = density_at(objs[obj], x);
+}
+
+// ---------------------------------------------------------------------------
+// Meshing: marching cubes (Lorensen & Cline) over a (res+1)^3 corner grid,
+// x fastest, corner (i, j, k) at lo + (hi - lo) * (i, j, k) / res.
+
+__device__ inline float grid_coord(float lo, float hi, int g, int res) {
+  return lo + (hi - lo) * ((float)g / (float)res);
+}
+
+// density of an object at the corners of a grid over its box
+__global__ __launch_bounds__(256) void k_density_grid(const ObjStatic* objs, int obj, int res,
+                                                      float* grid) {
+  const int64_t n1 = res + 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n1 * n1 * n1) return;
+  const ObjStatic& ob = objs[obj];
+  const int g[3] = {(int)(t % n1), (int)((t / n1) % n1), (int)(t / (n1 * n1))};
+  float x[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x[a] = grid_coord(-ob.half[a], ob.half[a], g[a], res);
+  grid[t] = density_at(ob, x);
+}
+
+// case of cell c and its 8 corner values
+__device__ inline int mc_cell(const MeshArgs& m, int64_t c, float v[8], int g0[3]) {
+  const int64_t n1 = m.res + 1;
+  g0[0] = (int)(c % m.res);
+  g0[1] = (int)((c / m.res) % m.res);
+  g0[2] = (int)(c / ((int64_t)m.res * m.res));
+  int mask = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int64_t gi = (g0[0] + (k & 1)) + n1 * ((g0[1] + ((k >> 1) & 1)) + n1 * (g0[2] + (k >> 2)));
+    v[k] = m.grid[gi];
+    mask |= (v[k] > m.iso ? 1 : 0) << k;
+  }
+  return mask;
+}
+
+__global__ __launch_bounds__(256) void k_mc_count(MeshArgs m) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)m.res * m.res * m.res) return;
+  float v[8];
+  int g0[3];
+  m.cnt[c] = m.ntri[mc_cell(m, c, v, g0)];
+}
+
+// exclusive scan of cnt[0 .. n) in blocks of RM_MC_SCAN (in place); block totals to bsum
+__global__ __launch_bounds__(256) void k_mc_scan_blocks(int* cnt, int64_t n, int* bsum) {
+  __shared__ int s_w[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t b0 = (int64_t)blockIdx.x * RM_MC_SCAN + 4 * tid;  // 4 consecutive per thread
+  int x[4], mine = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    x[k] = b0 + k < n ? cnt[b0 + k] : 0;
+    mine += x[k];
+  }
+  int inc = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wave; ++w) off += s_w[w];
+  int run = off + inc - mine;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (b0 + k < n) cnt[b0 + k] = run;
+    run += x[k];
+  }
+  if (tid == 255) bsum[blockIdx.x] = off + inc;
+}
+
+// exclusive scan of the block totals (nb <= 4 * 1024) in one block; total to bsum[nb]
+__global__ __launch_bounds__(1024) void k_mc_scan_totals(int* bsum, int nb) {
+  __shared__ int s_w[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int x[4], mine = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    x[k] = 4 * tid + k < nb ? bsum[4 * tid + k] : 0;
+    mine += x[k];
+  }
+  int inc = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) off += s_w[w];
+    tot += s_w[w];
+  }
+  int run = off + inc - mine;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (4 * tid + k < nb) bsum[4 * tid + k] = run;
+    run += x[k];
+  }
+  if (tid == 0) bsum[nb] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_mc_emit(MeshArgs m) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)m.res * m.res * m.res) return;
+  float v[8];
+  int g0[3];
+  const int mask = mc_cell(m, c, v, g0);
+  const int nt = m.ntri[mask];
+  if (nt == 0) return;
+  const int64_t base = (int64_t)m.cnt[c] + m.bsum[c / RM_MC_SCAN];
+  for (int t = 0; t < nt; ++t) {
+    if (base + t >= m.max_tris) return;
+    float* o = m.out + 9 * (base + t);
+    for (int q = 0; q < 3; ++q) {
+      const int e = m.tris[16 * mask + 3 * t + q];
+      const int ca = m.edge_a[e], cb = m.edge_b[e];
+      const float s = (m.iso - v[ca]) / (v[cb] - v[ca]);
+      float x[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float xa = grid_coord(m.lo[a], m.hi[a], g0[a] + ((ca >> a) & 1), m.res);
+        const float xb = grid_coord(m.lo[a], m.hi[a], g0[a] + ((cb >> a) & 1), m.res);
+        x[a] = xa + s * (xb - xa);
+      }
+      if (m.world) {  // box pose: x_w = R x + t
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          o[3 * q + a] = ((m.R[3 * a] * x[0] + m.R[3 * a + 1] * x[1]) + m.R[3 * a + 2] * x[2]) + m.t[a];
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[3 * q + a] = x[a];
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_debug_encode(const ObjStatic* objs, int obj,
@@ -1624,6 +1771,31 @@ hipError_t rm_launch_query_density(const ObjStatic* objs, int obj, const float* 
                                    float* sigma, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   k_query_density<<<cdiv(n, 256), 256, 0, st>>>(objs, obj, xyz, n, sigma);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_density_grid(const ObjStatic* objs, int obj, int res, float* grid,
+                                  hipStream_t st) {
+  const int64_t n1 = res + 1;
+  k_density_grid<<<cdiv(n1 * n1 * n1, 256), 256, 0, st>>>(objs, obj, res, grid);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_mc_count(const MeshArgs& m, hipStream_t st) {
+  const int64_t nc = (int64_t)m.res * m.res * m.res;
+  k_mc_count<<<cdiv(nc, 256), 256, 0, st>>>(m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nb = (int)cdiv(nc, RM_MC_SCAN);
+  k_mc_scan_blocks<<<nb, 256, 0, st>>>(m.cnt, nc, m.bsum);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_mc_scan_totals<<<1, 1024, 0, st>>>(m.bsum, nb);
+  return hipGetLastError();
+}
+
+hipError_t rm_launch_mc_emit(const MeshArgs& m, hipStream_t st) {
+  const int64_t nc = (int64_t)m.res * m.res * m.res;
+  k_mc_emit<<<cdiv(nc, 256), 256, 0, st>>>(m);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -93,6 +94,15 @@ struct romap_ctx {
   romap_config cfg{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // meshing: case tables (device) and scratch
+  uint8_t* d_mc = nullptr;   // tris [256*16] int8 | ntri [256] | edge_a [12] | edge_b [12]
+  float* d_mgrid = nullptr;
+  size_t cap_mgrid = 0;
+  int* d_mcnt = nullptr;
+  size_t cap_mcnt = 0;
+  int* d_mbsum = nullptr;
+  float* d_mtris = nullptr;
+  size_t cap_mtris = 0;
   std::vector<HostObj> objs;
   std::vector<HostKf> kfs;
   ObjStatic* d_objs = nullptr;
@@ -759,6 +769,11 @@ romap_status romap_destroy(romap_ctx* c) {
   hipFree(c->d_wpack16);
   hipFree(c->d_tables);
   hipFree(c->d_bin_count);
+  hipFree(c->d_mc);
+  hipFree(c->d_mgrid);
+  hipFree(c->d_mcnt);
+  hipFree(c->d_mbsum);
+  hipFree(c->d_mtris);
   hipFree(c->d_rec_idx);
   hipFree(c->d_rec_val);
   if (c->own_stream) hipStreamDestroy(c->stream);
@@ -1301,6 +1316,256 @@ romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, flo
     hipFree(d_tend);
   }
   return ROMAP_OK;
+}
+
+// ---- meshing (marching cubes) ------------------------------------------------
+
+// Case table of marching cubes, derived from the cube's faces.  Corner c sits
+// at (c&1, c>>1&1, c>>2&1); edges 0-3 run along x from corners 0,2,4,6, edges
+// 4-7 along y from 0,1,4,5, edges 8-11 along z from 0,1,2,3; a corner is
+// inside when its value exceeds iso.  Per case: the crossing edges of each
+// face are joined in pairs (two crossings: the pair; four: each inside corner
+// of the face cut off by its two edges), which closes them into loops; a
+// loop is oriented so that its Newell normal over the edge midpoints points
+// from the inside to the outside end of its first edge, rotated to start at
+// its smallest edge, loops ordered by that edge, and each becomes a fan from
+// its first vertex whose fan puts no triangle inside a cube face.
+struct McTable {
+  int8_t tris[256][16];
+  uint8_t ntri[256];
+  uint8_t ea[12], eb[12];
+};
+
+static void build_mc_table(McTable& T) {
+  for (int e = 0; e < 12; ++e) {
+    const int axis = e / 4, j = e % 4;
+    // the corners with the axis bit clear, in increasing order
+    int lows[4], n = 0;
+    for (int c = 0; c < 8; ++c)
+      if (!((c >> axis) & 1)) lows[n++] = c;
+    T.ea[e] = (uint8_t)lows[j];
+    T.eb[e] = (uint8_t)(lows[j] | (1 << axis));
+  }
+  auto edge_between = [&](int a, int b) {
+    for (int e = 0; e < 12; ++e)
+      if ((T.ea[e] == a && T.eb[e] == b) || (T.ea[e] == b && T.eb[e] == a)) return e;
+    return -1;
+  };
+  // faces as corner cycles: fixed axis bit, cycle through the other two
+  std::vector<std::array<int, 4>> faces;
+  for (int axis = 0; axis < 3; ++axis)
+    for (int side = 0; side < 2; ++side) {
+      const int u = (axis + 1) % 3, w = (axis + 2) % 3;
+      const int lo = std::min(u, w), hi = std::max(u, w);
+      const int base = side << axis;
+      faces.push_back({base, base | (1 << lo), base | (1 << lo) | (1 << hi), base | (1 << hi)});
+    }
+  auto on_face = [&](int e, const std::array<int, 4>& f) {
+    int k = 0;
+    for (int c : f) k += (c == T.ea[e]) + (c == T.eb[e]);
+    return k == 2;
+  };
+  for (int m = 0; m < 256; ++m) {
+    auto in = [&](int c) { return (m >> c) & 1; };
+    std::vector<std::vector<int>> link(12);
+    for (const auto& f : faces) {
+      int side[4];
+      std::vector<int> cross;
+      for (int i = 0; i < 4; ++i) {
+        side[i] = edge_between(f[i], f[(i + 1) % 4]);
+        if (in(f[i]) != in(f[(i + 1) % 4])) cross.push_back(side[i]);
+      }
+      std::vector<std::pair<int, int>> pairs;
+      if (cross.size() == 2) {
+        pairs.push_back({cross[0], cross[1]});
+      } else if (cross.size() == 4) {
+        const int k0 = in(f[0]) ? 0 : 1;  // the face's inside corners: f[k0], f[k0 + 2]
+        for (int k = k0; k < 4; k += 2) pairs.push_back({side[(k + 3) % 4], side[k]});
+      }
+      for (auto& pr : pairs) {
+        link[pr.first].push_back(pr.second);
+        link[pr.second].push_back(pr.first);
+      }
+    }
+    std::vector<std::vector<int>> loops;
+    std::vector<bool> seen(12, false);
+    for (int e0 = 0; e0 < 12; ++e0) {
+      if (link[e0].empty() || seen[e0]) continue;
+      std::vector<int> lp{e0};
+      seen[e0] = true;
+      int prev = e0, cur = std::min(link[e0][0], link[e0][1]);
+      while (cur != e0) {
+        lp.push_back(cur);
+        seen[cur] = true;
+        const int nx = link[cur][0] == prev ? link[cur][1] : link[cur][0];
+        prev = cur;
+        cur = nx;
+      }
+      // orientation: Newell normal vs inside -> outside of the first edge
+      double nrm[3] = {0, 0, 0};
+      auto mid = [&](int e, int a) { return 0.5 * (((T.ea[e] >> a) & 1) + ((T.eb[e] >> a) & 1)); };
+      const size_t L = lp.size();
+      for (size_t i = 0; i < L; ++i) {
+        const int p = lp[i], q = lp[(i + 1) % L];
+        nrm[0] += (mid(p, 1) - mid(q, 1)) * (mid(p, 2) + mid(q, 2));
+        nrm[1] += (mid(p, 2) - mid(q, 2)) * (mid(p, 0) + mid(q, 0));
+        nrm[2] += (mid(p, 0) - mid(q, 0)) * (mid(p, 1) + mid(q, 1));
+      }
+      const int ci = in(T.ea[lp[0]]) ? T.ea[lp[0]] : T.eb[lp[0]];
+      const int co = ci == T.ea[lp[0]] ? T.eb[lp[0]] : T.ea[lp[0]];
+      double d = 0;
+      for (int a = 0; a < 3; ++a) d += nrm[a] * (double)(((co >> a) & 1) - ((ci >> a) & 1));
+      if (d < 0) std::reverse(lp.begin(), lp.end());
+      std::rotate(lp.begin(), std::min_element(lp.begin(), lp.end()), lp.end());
+      loops.push_back(lp);
+    }
+    std::sort(loops.begin(), loops.end(),
+              [](const std::vector<int>& x, const std::vector<int>& y) { return x[0] < y[0]; });
+    int nt = 0;
+    for (const auto& lp : loops) {
+      const int L = (int)lp.size();
+      int apex = 0;
+      for (int a0 = 0; a0 < L; ++a0) {
+        bool flat = false;
+        for (int i = 1; i + 1 < L && !flat; ++i)
+          for (const auto& f : faces)
+            if (on_face(lp[a0], f) && on_face(lp[(a0 + i) % L], f) && on_face(lp[(a0 + i + 1) % L], f))
+              flat = true;
+        if (!flat) {
+          apex = a0;
+          break;
+        }
+      }
+      for (int i = 1; i + 1 < L; ++i, ++nt) {
+        T.tris[m][3 * nt] = (int8_t)lp[apex];
+        T.tris[m][3 * nt + 1] = (int8_t)lp[(apex + i) % L];
+        T.tris[m][3 * nt + 2] = (int8_t)lp[(apex + i + 1) % L];
+      }
+    }
+    for (int i = 3 * nt; i < 16; ++i) T.tris[m][i] = -1;
+    T.ntri[m] = (uint8_t)nt;
+  }
+}
+
+int32_t romap_mc_case(int32_t m, int8_t tris[16]) {
+  static McTable T;
+  static bool built = false;
+  if (!built) {
+    build_mc_table(T);
+    built = true;
+  }
+  for (int i = 0; i < 16; ++i) tris[i] = T.tris[m & 255][i];
+  return T.ntri[m & 255];
+}
+
+static romap_status mc_setup(romap_ctx* c, int res) {
+  if (!c->d_mc) {
+    McTable T;
+    build_mc_table(T);
+    std::vector<uint8_t> h(256 * 16 + 256 + 24);
+    std::memcpy(h.data(), T.tris, 256 * 16);
+    std::memcpy(h.data() + 4096, T.ntri, 256);
+    std::memcpy(h.data() + 4352, T.ea, 12);
+    std::memcpy(h.data() + 4364, T.eb, 12);
+    HIPALLOC(c, hipMalloc((void**)&c->d_mc, h.size()));
+    HIPALLOC(c, hipMalloc((void**)&c->d_mbsum, (RM_MC_MAX_RES * RM_MC_MAX_RES * RM_MC_MAX_RES /
+                                                    RM_MC_SCAN + 2) * sizeof(int)));
+    HIPCHK(c, hipMemcpy(c->d_mc, h.data(), h.size(), hipMemcpyHostToDevice));
+  }
+  const size_t n1 = (size_t)res + 1;
+  HIPALLOC(c, grow(&c->d_mgrid, &c->cap_mgrid, n1 * n1 * n1));
+  HIPALLOC(c, grow(&c->d_mcnt, &c->cap_mcnt, (size_t)res * res * res));
+  return ROMAP_OK;
+}
+
+// Counts the triangles of m.grid and, if tris is given, writes up to max_tris
+// of them (host or device buffer).
+static romap_status mc_run(romap_ctx* c, MeshArgs& m, float* tris, int64_t max_tris,
+                           int64_t* n_tris, int on_device) {
+  m.tris = (const int8_t*)c->d_mc;
+  m.ntri = c->d_mc + 4096;
+  m.edge_a = c->d_mc + 4352;
+  m.edge_b = c->d_mc + 4364;
+  m.cnt = c->d_mcnt;
+  m.bsum = c->d_mbsum;
+  HIPCHK(c, rm_launch_mc_count(m, c->stream));
+  const int64_t nc = (int64_t)m.res * m.res * m.res;
+  const int nb = (int)((nc + RM_MC_SCAN - 1) / RM_MC_SCAN);
+  int total = 0;
+  HIPCHK(c, hipMemcpyAsync(&total, c->d_mbsum + nb, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (n_tris) *n_tris = total;
+  const int64_t nw = std::min<int64_t>(total, max_tris);
+  if (!tris || nw <= 0) return ROMAP_OK;
+  m.max_tris = nw;
+  if (on_device) {
+    m.out = tris;
+    HIPCHK(c, rm_launch_mc_emit(m, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ROMAP_OK;
+  }
+  HIPALLOC(c, grow(&c->d_mtris, &c->cap_mtris, (size_t)nw * 9));
+  m.out = c->d_mtris;
+  HIPCHK(c, rm_launch_mc_emit(m, c->stream));
+  HIPCHK(c, hipMemcpyAsync(tris, c->d_mtris, (size_t)nw * 9 * sizeof(float), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ROMAP_OK;
+}
+
+romap_status romap_marching_cubes(romap_ctx* c, const float* grid, int32_t res, float iso,
+                                  const float lo[3], const float hi[3], float* tris,
+                                  int64_t max_tris, int64_t* n_tris, int32_t on_device) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  if (res < 1 || res > RM_MC_MAX_RES) return fail(c, ROMAP_E_INVALID_ARG, "res must be 1..160");
+  if (!grid || !lo || !hi || max_tris < 0) return fail(c, ROMAP_E_INVALID_ARG, "bad buffers");
+  romap_status s = mc_setup(c, res);
+  if (s != ROMAP_OK) return s;
+  const size_t ng = (size_t)(res + 1) * (res + 1) * (res + 1);
+  MeshArgs m{};
+  if (on_device) {
+    m.grid = grid;
+  } else {
+    HIPCHK(c, hipMemcpyAsync(c->d_mgrid, grid, ng * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    m.grid = c->d_mgrid;
+  }
+  m.res = res;
+  m.iso = iso;
+  for (int a = 0; a < 3; ++a) {
+    m.lo[a] = lo[a];
+    m.hi[a] = hi[a];
+  }
+  return mc_run(c, m, tris, max_tris, n_tris, on_device);
+}
+
+romap_status romap_extract_mesh(romap_ctx* c, int32_t id, int32_t res, float iso,
+                                int32_t world_frame, float* tris, int64_t max_tris,
+                                int64_t* n_tris, int32_t on_device) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  if (res < 1 || res > RM_MC_MAX_RES) return fail(c, ROMAP_E_INVALID_ARG, "res must be 1..160");
+  if (max_tris < 0) return fail(c, ROMAP_E_INVALID_ARG, "bad buffers");
+  s = mc_setup(c, res);
+  if (s != ROMAP_OK) return s;
+  const HostObj& o = c->objs[id];
+  HIPCHK(c, rm_launch_density_grid(c->d_objs, id, res, c->d_mgrid, c->stream));
+  MeshArgs m{};
+  m.grid = c->d_mgrid;
+  m.res = res;
+  m.iso = iso;
+  for (int a = 0; a < 3; ++a) {
+    m.lo[a] = -o.box.half[a];
+    m.hi[a] = o.box.half[a];
+  }
+  if (world_frame) {  // box pose: R = Rz(yaw) in FP64, rounded once
+    const double cy = std::cos((double)o.box.yaw), sy = std::sin((double)o.box.yaw);
+    const double R[9] = {cy, -sy, 0.0, sy, cy, 0.0, 0.0, 0.0, 1.0};
+    m.world = 1;
+    for (int k = 0; k < 9; ++k) m.R[k] = (float)R[k];
+    for (int a = 0; a < 3; ++a) m.t[a] = o.box.t[a];
+  }
+  return mc_run(c, m, tris, max_tris, n_tris, on_device);
 }
 
 romap_status romap_query_density(romap_ctx* c, int32_t id, const float* xyz, int64_t n,
