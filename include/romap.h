@@ -203,6 +203,18 @@ romap_status romap_render(romap_ctx* ctx, int32_t object_id, const romap_camera*
 romap_status romap_query_density(romap_ctx* ctx, int32_t object_id, const float* xyz, int64_t n,
                                  float* sigma, int32_t on_device);
 
+/* An object's box from its sparse world point cloud (Sec. IV-B, pose and
+ * size estimation; host computation in FP64, no device needed): t = the
+ * midpoint of the per-axis extremes of the points (Eq. 1); yaw = the
+ * direction of the dominant principal axis of the points projected on the
+ * horizontal plane (PCA of their 2x2 second moments about the mean), folded
+ * into [-pi/2, pi/2); half = half the per-axis extent of the points in the
+ * object frame, R(yaw)^T (x - t) (Eq. 4).  Roll and pitch are zero.  The
+ * paper's refinement of the yaw by image line features (Eq. 2-3) is not
+ * computed.  xyz: n*3 floats (host); ROMAP_E_INVALID_ARG if n < 1 or a
+ * pointer is NULL.  The result feeds romap_add_object. */
+romap_status romap_box_from_points(const float* xyz, int64_t n, romap_box* box);
+
 /* Marching cubes (Sec. III: the object meshes; 64^3 per object in Sec. VI)
  * on a density grid of (res+1)^3 corner values, x fastest, corner (i, j, k)
  * at lo + (hi - lo) * (i, j, k) / res (FP32, that order).  A corner is

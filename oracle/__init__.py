@@ -101,6 +101,8 @@ def lib():
                                    P, P, P, P, C.c_int]
         _lib.or_query_density.argtypes = [C.POINTER(Levels), P, P, C.c_int64, P, P]
         _lib.or_philox4x32_10.argtypes = [P, P, P]
+        _lib.or_box_from_points.argtypes = [P, C.c_int64, P, P, P]
+        _lib.or_box_from_points.restype = C.c_int
         _lib.or_mc_case.argtypes = [C.c_int, P]
         _lib.or_mc_case.restype = C.c_int
         _lib.or_marching_cubes.argtypes = [P, C.c_int, C.c_float, P, P, P, C.c_int64]
@@ -112,6 +114,17 @@ def lib():
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def box_from_points(xyz):
+    """Box (t, yaw, half) of a world point cloud: Eq. 1, PCA yaw, Eq. 4."""
+    xyz = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+    t = np.zeros(3)
+    yaw = np.zeros(1)
+    half = np.zeros(3)
+    if lib().or_box_from_points(_p(xyz), xyz.shape[0], _p(t), _p(yaw), _p(half)) != 0:
+        raise ValueError("empty point cloud")
+    return t, float(yaw[0]), half
 
 
 def mc_case(m: int):

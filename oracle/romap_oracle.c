@@ -1101,3 +1101,61 @@ int64_t or_marching_cubes(const float* grid, int res, float iso, const float lo[
       }
   return total;
 }
+
+/* ------------------------------------------------------------------------
+ * Object box from its sparse point cloud (Sec. IV-B, pose and size
+ * estimation): translation = midpoint of the per-axis extremes of the world
+ * points (Eq. 1); yaw = direction of the dominant principal axis of the
+ * points projected on the horizontal plane (PCA), folded into [-pi/2, pi/2)
+ * (a cuboid's axis has no sign); size = half the per-axis extent of the
+ * points in the object frame rotated by that yaw (Eq. 4).  Roll and pitch
+ * are zero (objects on a support).  FP64 throughout.  The line-feature
+ * refinement of the yaw (Eq. 2-3) needs image line segments and is not
+ * computed here.
+ * ---------------------------------------------------------------------- */
+int or_box_from_points(const double* xyz, int64_t n, double t[3], double* yaw, double half[3]) {
+  if (n < 1) return -1;
+  double mn[3], mx[3];
+  for (int k = 0; k < 3; ++k) mn[k] = mx[k] = xyz[k];
+  for (int64_t i = 1; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      const double v = xyz[3 * i + k];
+      if (v < mn[k]) mn[k] = v;
+      if (v > mx[k]) mx[k] = v;
+    }
+  for (int k = 0; k < 3; ++k) t[k] = 0.5 * (mx[k] + mn[k]); /* Eq. 1 */
+  /* PCA of the horizontal projection: 2x2 covariance about the mean */
+  double mxy[2] = {0, 0};
+  for (int64_t i = 0; i < n; ++i) {
+    mxy[0] += xyz[3 * i];
+    mxy[1] += xyz[3 * i + 1];
+  }
+  mxy[0] /= (double)n;
+  mxy[1] /= (double)n;
+  double sxx = 0, syy = 0, sxy = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double dx = xyz[3 * i] - mxy[0], dy = xyz[3 * i + 1] - mxy[1];
+    sxx += dx * dx;
+    syy += dy * dy;
+    sxy += dx * dy;
+  }
+  /* eigenvector of the larger eigenvalue of [[sxx, sxy], [sxy, syy]] is at
+   * angle 0.5 * atan2(2 sxy, sxx - syy) */
+  double th = 0.5 * atan2(2.0 * sxy, sxx - syy);
+  const double pi = 3.14159265358979323846;
+  if (th >= 0.5 * pi) th -= pi;
+  if (th < -0.5 * pi) th += pi;
+  *yaw = th;
+  const double c = cos(th), s = sin(th);
+  double lo[3], hi[3];
+  for (int64_t i = 0; i < n; ++i) {
+    const double dx = xyz[3 * i] - t[0], dy = xyz[3 * i + 1] - t[1], dz = xyz[3 * i + 2] - t[2];
+    const double o[3] = {c * dx + s * dy, -s * dx + c * dy, dz}; /* R(yaw)^T (x - t) */
+    for (int k = 0; k < 3; ++k) {
+      if (i == 0 || o[k] < lo[k]) lo[k] = o[k];
+      if (i == 0 || o[k] > hi[k]) hi[k] = o[k];
+    }
+  }
+  for (int k = 0; k < 3; ++k) half[k] = 0.5 * (hi[k] - lo[k]); /* Eq. 4 */
+  return 0;
+}

@@ -93,5 +93,6 @@ void or_query_density(const or_levels* lv, const float half[3], const double* pa
 int or_mc_case(int m, int8_t tris[16]);
 int64_t or_marching_cubes(const float* grid, int res, float iso, const float lo[3],
                           const float hi[3], float* out, int64_t max_tris);
+int or_box_from_points(const double* xyz, int64_t n, double t[3], double* yaw, double half[3]);
 
 #endif

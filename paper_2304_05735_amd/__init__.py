@@ -79,7 +79,7 @@ EXPORTS = ["romap_default_config", "romap_create", "romap_destroy", "romap_last_
            "romap_load", "romap_debug_rays", "romap_debug_encode", "romap_field_forward",
            "romap_field_backward", "romap_get_phase_times", "romap_sync", "romap_set_occupancy",
            "romap_update_occupancy", "romap_get_occupancy", "romap_marching_cubes",
-           "romap_extract_mesh", "romap_mc_case"]
+           "romap_extract_mesh", "romap_mc_case", "romap_box_from_points"]
 
 
 def lib():
@@ -121,6 +121,7 @@ def lib():
             "romap_marching_cubes": [P, P, i32, C.c_float, P, P, P, i64, C.POINTER(i64), i32],
             "romap_extract_mesh": [P, i32, i32, C.c_float, i32, P, i64, C.POINTER(i64), i32],
             "romap_mc_case": [i32, P],
+            "romap_box_from_points": [P, i64, C.POINTER(romap_box)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -156,6 +157,16 @@ def make_camera(cam: dict) -> romap_camera:
     c.fx, c.fy, c.cx, c.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
     c.width, c.height = int(cam["W"]), int(cam["H"])
     return c
+
+
+def box_from_points(xyz):
+    """Box of a world point cloud (Eq. 1, PCA yaw, Eq. 4): (t, yaw, half)."""
+    xyz = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+    b = romap_box()
+    rc = lib().romap_box_from_points(_ptr(xyz), xyz.shape[0], C.byref(b))
+    if rc != 0:
+        raise RomapError(rc, "box_from_points: empty or NULL input")
+    return (np.array(b.t[:], np.float32), float(b.yaw), np.array(b.half[:], np.float32))
 
 
 def mc_case(m: int):

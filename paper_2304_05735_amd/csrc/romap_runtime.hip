@@ -1318,6 +1318,56 @@ romap_status romap_render(romap_ctx* c, int32_t id, const romap_camera* cam, flo
   return ROMAP_OK;
 }
 
+// ---- object box from its point cloud (Sec. IV-B) --------------------------------
+
+romap_status romap_box_from_points(const float* xyz, int64_t n, romap_box* box) {
+  if (!xyz || n < 1 || !box) return ROMAP_E_INVALID_ARG;
+  // Eq. 1: centre of the world-axis extremes
+  double lo[3] = {xyz[0], xyz[1], xyz[2]}, hi[3] = {xyz[0], xyz[1], xyz[2]};
+  double sx = 0, sy = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], (double)xyz[3 * i + k]);
+      hi[k] = std::max(hi[k], (double)xyz[3 * i + k]);
+    }
+    sx += xyz[3 * i];
+    sy += xyz[3 * i + 1];
+  }
+  double t[3];
+  for (int k = 0; k < 3; ++k) t[k] = (lo[k] + hi[k]) / 2;
+  // yaw: principal axis of the horizontal projection (second moments about
+  // the mean), an axis without sign, folded into [-pi/2, pi/2)
+  const double mx = sx / (double)n, my = sy / (double)n;
+  double cxx = 0, cyy = 0, cxy = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double u = xyz[3 * i] - mx, w = xyz[3 * i + 1] - my;
+    cxx += u * u;
+    cyy += w * w;
+    cxy += u * w;
+  }
+  const double PI = 3.14159265358979323846;
+  double yaw = std::atan2(2 * cxy, cxx - cyy) / 2;
+  if (yaw < -PI / 2) yaw += PI;
+  if (yaw >= PI / 2) yaw -= PI;
+  // Eq. 4: half the extent of the points in the object frame
+  const double c = std::cos(yaw), s = std::sin(yaw);
+  double olo[3] = {0, 0, 0}, ohi[3] = {0, 0, 0};
+  for (int64_t i = 0; i < n; ++i) {
+    const double d[3] = {xyz[3 * i] - t[0], xyz[3 * i + 1] - t[1], xyz[3 * i + 2] - t[2]};
+    const double q[3] = {c * d[0] + s * d[1], c * d[1] - s * d[0], d[2]};
+    for (int k = 0; k < 3; ++k) {
+      olo[k] = i ? std::min(olo[k], q[k]) : q[k];
+      ohi[k] = i ? std::max(ohi[k], q[k]) : q[k];
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    box->t[k] = (float)t[k];
+    box->half[k] = (float)((ohi[k] - olo[k]) / 2);
+  }
+  box->yaw = (float)yaw;
+  return ROMAP_OK;
+}
+
 // ---- meshing (marching cubes) ------------------------------------------------
 
 // Case table of marching cubes, derived from the cube's faces.  Corner c sits

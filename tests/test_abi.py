@@ -65,3 +65,27 @@ def test_library_mc_table_equals_oracle_table():
     import paper_2304_05735_amd as pk
     for m in range(256):
         assert np.array_equal(pk.mc_case(m), oracle.mc_case(m)), m
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libromap.so not built")
+def test_box_from_points_matches_oracle():
+    """The library's box producer (host code) against the oracle's on yawed,
+    noisy, uneven point clouds (the float32 input rounded once on both sides)."""
+    import math
+    import oracle
+    import paper_2304_05735_amd as pk
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        half = rng.uniform(0.1, 1.0, 3)
+        yaw = rng.uniform(-1.5, 1.5)
+        t = rng.uniform(-3, 3, 3)
+        loc = rng.uniform(-1, 1, (rng.integers(5, 400), 3)) * half
+        c, s = math.cos(yaw), math.sin(yaw)
+        pts = (loc @ np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]]).T + t).astype(np.float32)
+        gt, gy, gh = pk.box_from_points(pts)
+        ot, oy, oh = oracle.box_from_points(pts.astype(np.float64))
+        assert np.allclose(gt, ot, rtol=1e-6, atol=1e-6)
+        assert abs(gy - oy) < 1e-6
+        assert np.allclose(gh, oh, rtol=1e-5, atol=1e-6)
+    with pytest.raises(pk.RomapError):
+        pk.box_from_points(np.zeros((0, 3), np.float32))

@@ -139,3 +139,46 @@ def test_object_mesh_in_world_frame():
     assert np.allclose(world[..., 0], c * x - s * y + 1.0)
     assert np.allclose(world[..., 1], s * x + c * y - 2.0)
     assert np.all(np.abs(local) <= ob.half + 1e-7)
+
+
+# ------------------------------------------------------------------ box from points (Eq. 1, PCA, Eq. 4)
+def _box_cloud(t0, yaw0, half0, n, seed):
+    """Points filling a yawed box: its 8 corners and random interior points,
+    mirrored through the box axes (a centrally and axially symmetric cloud)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-1, 1, (n, 3))
+    s = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], float)
+    local = np.concatenate([s] + [u * f for f in s]) * half0
+    c, sn = math.cos(yaw0), math.sin(yaw0)
+    R = np.array([[c, -sn, 0], [sn, c, 0], [0, 0, 1]])
+    return local @ R.T + t0
+
+
+@pytest.mark.parametrize("yaw0", [-0.7, -0.2, 0.0, 0.4, 0.75])
+def test_box_from_symmetric_cloud_is_exact(yaw0):
+    t0 = np.array([1.5, -0.4, 0.35])
+    half0 = np.array([0.6, 0.25, 0.35])  # long axis along the box x
+    t, yaw, half = oracle.box_from_points(_box_cloud(t0, yaw0, half0, 300, 7))
+    assert np.allclose(t, t0, atol=1e-12)       # Eq. 1: midpoint of the world extremes
+    assert abs(yaw - yaw0) < 1e-9                # PCA axis of a symmetric box cloud
+    assert np.allclose(half, half0, atol=1e-9)   # Eq. 4 with the corners present
+
+
+def test_box_yaw_is_folded_and_axis_swaps():
+    t0 = np.zeros(3)
+    half0 = np.array([0.6, 0.25, 0.35])
+    _, y1, h1 = oracle.box_from_points(_box_cloud(t0, 0.3 + math.pi, half0, 200, 1))
+    assert abs(y1 - 0.3) < 1e-9 and np.allclose(h1, half0, atol=1e-9)
+    # long axis along y: the principal axis is the box y axis, so yaw turns by pi/2
+    # and the extents swap
+    half1 = np.array([0.25, 0.6, 0.35])
+    _, y2, h2 = oracle.box_from_points(_box_cloud(t0, 0.2, half1, 200, 2))
+    assert abs(y2 - (0.2 - math.pi / 2)) < 1e-9
+    assert np.allclose(h2, [0.6, 0.25, 0.35], atol=1e-9)
+
+
+def test_box_from_one_point():
+    t, yaw, half = oracle.box_from_points(np.array([[0.3, 0.2, 0.1]]))
+    assert np.allclose(t, [0.3, 0.2, 0.1]) and yaw == 0.0 and np.allclose(half, 0.0)
+    with pytest.raises(ValueError):
+        oracle.box_from_points(np.zeros((0, 3)))
