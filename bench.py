@@ -236,6 +236,32 @@ def mesh_timing(ctx, ids, res=64, iso=10.0, reps=3):
                 paper_ms_per_object_rtx4090=2.84)
 
 
+def table_sweep(steps=200, warmup=20):
+    """Table 4's sweep of the hash-table size on one object: time per step
+    (graph, FP32 and BF16) of 4096 rays x 32 samples (the paper's N) and of
+    4096 x 64, for T = 2^14 .. 2^20, on the single-object scene."""
+    import paper_2304_05735_amd as pk
+    import scenes
+    wl = scenes.config2()
+    ob = wl.objects[0]
+    rows = []
+    for N in (32, 64):
+        for prec in (pk.PREC_FP32, pk.PREC_BF16):
+            for lt in (14, 16, 18, 20):
+                cfg = pk.default_config(samples_per_ray=N, precision=prec, use_graph=1, autotune=1)
+                ctx = pk.Context(cfg)
+                i = ctx.add_object(ob.instance, ob.t, ob.yaw, ob.half, lt)
+                for cam, rgb, mask, depth in wl.frames:
+                    ctx.add_keyframe(cam, rgb, mask, depth)
+                dt = timed_steps(ctx, [i], [4096], warmup, steps)
+                rows.append(dict(N=N, precision="bf16" if prec else "fp32", log2T=lt,
+                                 ms_per_step=round(dt / steps * 1e3, 4)))
+                log("table sweep", rows[-1])
+                del ctx
+    return dict(rows=rows, paper_rtx4090_ms={"2^14": 0.658, "2^16": 0.706, "2^18": 0.921,
+                                              "2^20": 1.495})
+
+
 def density_ablation(wl, ids, rays, prec, steps):
     """The loss ablation of the paper's Fig. 8 on this workload: training with
     and without the density term of the background rays (lambda_2 = 0.01 vs
@@ -400,6 +426,8 @@ def main():
     ap.add_argument("--psnr-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
+    ap.add_argument("--table-sweep", action="store_true",
+                    help="time one object for T = 2^14..2^20 (the paper's Table 4 sweep) and exit")
     ap.add_argument("--ablation-density", action="store_true",
                     help="also train with lambda_2 = 0 and report PSNR and empty-space opacity")
     ap.add_argument("--psnr-chunk", type=int, default=250)
@@ -431,6 +459,9 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 3 x 512 MiB copied")
         del src, dst
+    if args.table_sweep:
+        print(json.dumps({"table_sweep": table_sweep()}), flush=True)
+        return
     log("workload", args.workload)
     t = time.perf_counter()
     wl = build_workload(args.workload, args.frames)
