@@ -14,7 +14,7 @@
 #define RM_WPACK 10240      /* packed MLP weight image, elements (K1 <= 32) */
 #define RM_WG 256           /* threads of the fused field kernel (4 waves) */
 #define RM_FIN_WG 512       /* entries per workgroup of the finishing kernel */
-#define RM_RB_BITS 12       /* binned scatter: table entries per region = 4096 */
+#define RM_RB_BITS 11       /* binned scatter: table entries per region = 2048 */
 #define RM_RB (1 << RM_RB_BITS)
 #define RM_ACC_WG 512       /* threads of the region accumulation kernel */
 #define RM_SCAT_WG 512      /* samples (threads) per block of the binning kernel */
@@ -22,7 +22,7 @@
 #define RM_ACC_MAXK 256     /* accumulation workgroups per region, at most */
 #define RM_GROUP_RECORDS (1ll << 29) /* record slots of one bin group (5 GiB) */
 #define RM_FX_BITS 38       /* fixed-point fraction bits of the region sums */
-#define RM_MAX_REGIONS 4096 /* 2^24 / 2^12 */
+#define RM_MAX_REGIONS 8192 /* 2^24 / 2^11 */
 
 // Offsets of the eight packed GEMM operands inside a weight image.
 #define RM_OFF_F1 0     /* W1        64 x K1  */
