@@ -281,6 +281,13 @@ romap_status romap_debug_rays(romap_ctx* ctx, int32_t object_id, int32_t n_rays,
  * feat n*L*2 floats.  Host buffers; either output may be NULL. */
 romap_status romap_debug_encode(romap_ctx* ctx, int32_t object_id, const float* p, int64_t n,
                                 uint32_t* idx, float* feat);
+/* For tests of the overflow path of the gradient binning: caps every bin
+ * (the records of one 2048-entry table region) at `slots` record slots,
+ * rounded up to a multiple of 4 (0 restores the sized capacity).  Records
+ * beyond a bin's capacity go to the gradient with atomics and are merged by
+ * the region's accumulation: results are the same up to rounding order, the
+ * step only slower.  ROMAP_E_INVALID_ARG if slots < 0. */
+romap_status romap_debug_bin_capacity(romap_ctx* ctx, int32_t slots);
 
 /* ---- differentiable surface (for torch.autograd.Function) ----------------
  * rays_dev: n_rays*8 floats per ray: origin[3], unit direction[3], t_near,

@@ -79,7 +79,8 @@ EXPORTS = ["romap_default_config", "romap_create", "romap_destroy", "romap_last_
            "romap_load", "romap_debug_rays", "romap_debug_encode", "romap_field_forward",
            "romap_field_backward", "romap_get_phase_times", "romap_sync", "romap_set_occupancy",
            "romap_update_occupancy", "romap_get_occupancy", "romap_marching_cubes",
-           "romap_extract_mesh", "romap_mc_case", "romap_box_from_points"]
+           "romap_extract_mesh", "romap_mc_case", "romap_box_from_points",
+           "romap_debug_bin_capacity"]
 
 
 def lib():
@@ -121,6 +122,7 @@ def lib():
             "romap_marching_cubes": [P, P, i32, C.c_float, P, P, P, i64, C.POINTER(i64), i32],
             "romap_extract_mesh": [P, i32, i32, C.c_float, i32, P, i64, C.POINTER(i64), i32],
             "romap_mc_case": [i32, P],
+            "romap_debug_bin_capacity": [P, i32],
             "romap_box_from_points": [P, i64, C.POINTER(romap_box)],
         }
         for name, args in sig.items():
@@ -257,6 +259,10 @@ class Context:
         self._check(lib().romap_render(self.h, int(oid), C.byref(c), _ptr(rgb), _ptr(depth),
                                        _ptr(opac), 0))
         return rgb, depth, opac
+
+    def debug_bin_capacity(self, slots: int):
+        """Cap every gradient bin at `slots` records (0 = sized capacity)."""
+        self._check(lib().romap_debug_bin_capacity(self.h, int(slots)))
 
     def marching_cubes(self, grid, res, iso, lo, hi):
         """Marching cubes on a (res+1)^3 grid (x fastest; numpy or a device

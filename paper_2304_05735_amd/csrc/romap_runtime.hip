@@ -92,6 +92,7 @@ hipError_t grow(T** p, size_t* cap, size_t need) {
 
 struct romap_ctx {
   romap_config cfg{};
+  int debug_bin_cap = 0;  // romap_debug_bin_capacity (0: sized capacity)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // meshing: case tables (device) and scratch
@@ -342,6 +343,7 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
       const int64_t want = hashed ? expect + 8 * (int64_t)std::ceil(std::sqrt((double)expect)) + 256
                                   : 2 * expect + 1024;
       bp.cap = (int)((std::min<int64_t>(want, 8 * So) + 3) & ~(int64_t)3);
+      if (c->debug_bin_cap > 0) bp.cap = std::min(bp.cap, (c->debug_bin_cap + 3) & ~3);
       // workgroups per region: about RM_ACC_CHUNK records each, and at most
       // 2^(62 - RM_FX_BITS) / 2 per workgroup so no fixed-point sum can overflow
       const int64_t kmin = (bp.cap + ((int64_t)1 << (61 - RM_FX_BITS)) - 1) >> (61 - RM_FX_BITS);
@@ -1731,6 +1733,13 @@ romap_status romap_debug_rays(romap_ctx* c, int32_t id, int32_t n_rays, int32_t*
       q[15] = (R.flags & RM_F_DEPTH) ? 1.0f : 0.0f;
     }
   }
+  return ROMAP_OK;
+}
+
+romap_status romap_debug_bin_capacity(romap_ctx* c, int32_t slots) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  if (slots < 0) return fail(c, ROMAP_E_INVALID_ARG, "slots must be >= 0");
+  c->debug_bin_cap = slots;
   return ROMAP_OK;
 }
 

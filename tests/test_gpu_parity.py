@@ -344,3 +344,31 @@ def test_occupancy_skip_parity(tiny):
     g.set_occupancy(gid, None)
     with pytest.raises(pk.RomapError):
         g.get_occupancy(gid)
+
+
+# ------------------------------------------------------------------ gradient bins that overflow
+@pytest.mark.parametrize("B", [48, 512])
+def test_bin_overflow_path_matches_oracle(tiny, B):
+    """Bins capped at 64 records: nearly every record takes the overflow path
+    (atomics into the gradient, merged by the region's accumulation; with
+    B = 48 the region has one accumulation workgroup, with B = 512 several).
+    The gradient still matches the oracle, and a training step still applies
+    Adam with that gradient."""
+    _say("bin overflow", B)
+    frames, box = tiny
+    g, o, gid = make_pair(2, 16, 32, 8, 32, B, frames, box)
+    _set_same_params(g, o, gid, seed=9)
+    g.debug_bin_capacity(64)
+    gl = g.loss_and_grad([gid])[0]
+    gg = g.get_params(gid, pk.GRAD)
+    ol, og, mass, allow, _ = oracle_grad(o, gid, 0, B)
+    assert_fwd_close([gl], [ol], what="loss")
+    assert_grad_close(gg, og, mass, allow, what="grad (overflow)")
+    p0 = g.get_params(gid).astype(np.float64)
+    P = p0.size
+    m, v = np.zeros(P), np.zeros(P)
+    g.train(1, [gid])
+    oracle.adam(p0, gg.astype(np.float64), m, v, 1, 1e-2, 0.9, 0.99, 1e-15)
+    assert_fwd_close(g.get_params(gid), p0, rtol=2e-6, atol=2e-8, what="params after step")
+    assert np.abs(g.get_params(gid, pk.GRAD)).max() == 0.0
+    g.debug_bin_capacity(0)
