@@ -76,7 +76,9 @@ typedef struct {
   int32_t bbox_margin_pct;                 /* detection-box margin, % per side */
   int32_t precision;                       /* ROMAP_PREC_* */
   int32_t batch_mode;                      /* ROMAP_BATCH_* */
-  int32_t use_graph;                       /* replay each step as one hipGraph */
+  int32_t use_graph;                       /* replay each step as one hipGraph (captured
+                                            * when the call has >= 8 steps or the
+                                            * graph of its shapes exists) */
   int32_t autotune;                        /* pick tile shapes by timing */
   int32_t profile_phases;                  /* time each kernel of a step with HIP
                                               events (launches without a graph and

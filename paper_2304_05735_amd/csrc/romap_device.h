@@ -14,6 +14,7 @@
 #define RM_WPACK 10240      /* packed MLP weight image, elements (K1 <= 32) */
 #define RM_WG 256           /* threads of the fused field kernel (4 waves) */
 #define RM_FIN_WG 512       /* entries per workgroup of the finishing kernel */
+#define RM_GRAPH_MIN_STEPS 8 /* steps of a romap_train call that repay a graph capture */
 #define RM_RB_BITS 11       /* binned scatter: table entries per region = 2048 */
 #define RM_RB (1 << RM_RB_BITS)
 #define RM_ACC_WG 512       /* threads of the region accumulation kernel */

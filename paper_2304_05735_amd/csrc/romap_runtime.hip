@@ -1088,6 +1088,26 @@ romap_status romap_add_keyframe(romap_ctx* c, const romap_camera* cam, const uin
   return ROMAP_OK;
 }
 
+// The captured step graph is keyed by the objects, their ray counts, the
+// tile choice and the work-table arena.
+static std::vector<int64_t> graph_sig(romap_ctx* c, const std::vector<std::pair<int, int>>& list,
+                                      int rpi, int blk) {
+  std::vector<int64_t> sig = signature(c, list);
+  sig.push_back(rpi);
+  sig.push_back(blk);
+  sig.push_back((int64_t)(uintptr_t)c->d_tables);
+  return sig;
+}
+
+// A graph is used when it exists for this step already, or when the call
+// replays it often enough to repay a capture (a few milliseconds); short
+// calls with new shapes (a mapping stream's per-frame steps) run eagerly.
+static bool graph_pays(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int rpi,
+                       int blk, int n_steps) {
+  if (n_steps >= RM_GRAPH_MIN_STEPS) return true;
+  return c->gexec && graph_sig(c, list, rpi, blk) == c->gsig;
+}
+
 romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_steps,
                          const int32_t* rays, romap_train_stats* stats) {
   if (!c) return ROMAP_E_INVALID_ARG;
@@ -1142,11 +1162,8 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
         HIPCHK(c, accumulate_phases(c));
         ++c->phase_steps;
       }
-    } else if (c->cfg.use_graph) {
-      std::vector<int64_t> sig = signature(c, list);
-      sig.push_back(rpi);
-      sig.push_back(blk);
-      sig.push_back((int64_t)(uintptr_t)c->d_tables);
+    } else if (c->cfg.use_graph && graph_pays(c, list, rpi, blk, n_steps)) {
+      std::vector<int64_t> sig = graph_sig(c, list, rpi, blk);
       if (!c->gexec || sig != c->gsig) {
         if (c->gexec) {
           hipGraphExecDestroy(c->gexec);

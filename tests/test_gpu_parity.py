@@ -372,3 +372,25 @@ def test_bin_overflow_path_matches_oracle(tiny, B):
     assert_fwd_close(g.get_params(gid), p0, rtol=2e-6, atol=2e-8, what="params after step")
     assert np.abs(g.get_params(gid, pk.GRAD)).max() == 0.0
     g.debug_bin_capacity(0)
+
+
+# ------------------------------------------------------------------ graph replay
+def test_graph_replay_equals_eager_steps(tiny):
+    """The captured step graph (used for calls of >= 8 steps, and replayed by
+    later calls of the same shapes) advances exactly like eager launches: with
+    one accumulation workgroup per region every sum is order-independent, so
+    parameters and Adam moments agree bit for bit after 10 + 10 steps."""
+    _say("graph replay")
+    frames, box = tiny
+    ctxs = []
+    for graph in (1, 0):
+        g, o, gid = make_pair(2, 16, 32, 8, 32, 64, frames, box, use_graph=graph)
+        _set_same_params(g, o, gid, seed=21)
+        st1 = g.train(10, [gid])
+        st2 = g.train(10, [gid])
+        ctxs.append((g, gid, st1.loss_mean, st2.loss_mean))
+    (ga, ia, la1, la2), (gb, ib, lb1, lb2) = ctxs
+    assert ga.object_info(ia).step == gb.object_info(ib).step == 20
+    for kind in (pk.PARAMS, pk.ADAM_M, pk.ADAM_V):
+        assert np.array_equal(ga.get_params(ia, kind), gb.get_params(ib, kind)), kind
+    assert la1 == lb1 and la2 == lb2
