@@ -540,8 +540,36 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
   const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];  // uniform in the block
   const uint32_t NL = ob.N_l[bp.l], TL = ob.T_l[bp.l];
   const bool hashed = (ob.hashed_mask >> bp.l) & 1u;
-  const bool has =
+  bool has =
       k < bp.n_samples && bin_records<NS>(a, ob, bp.l, NL, TL, hashed, bp.s_begin + k, idx, v);
+  if (bp.merge) {
+    // Coarse dense level: consecutive samples of a ray (consecutive lanes)
+    // often share a cell and so all 8 entries.  Sums over runs of equal cells
+    // (key: the cell's first corner index, which is unique on a dense level,
+    // and the ray's parity within the wave); a lane gathers its run's next 3
+    // samples, so the run's head and every 4th sample after it carry the
+    // records of the run.
+    const int lane = tid & 63;
+    const uint32_t key = has ? (idx[0] | (((uint32_t)((bp.s_begin + k) / NS) & 1u) << 31))
+                             : 0xFFFFFFFFu - (uint32_t)lane;
+#pragma unroll
+    for (int o = 1; o < 4; o <<= 1) {
+      const uint32_t kn = __shfl_down(key, o, 64);
+      const bool same = lane + o < 64 && kn == key;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const float yx = __shfl_down(v[b].x, o, 64), yy = __shfl_down(v[b].y, o, 64);
+        if (same) {
+          v[b].x += yx;
+          v[b].y += yy;
+        }
+      }
+    }
+    const uint32_t kp = __shfl_up(key, 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || kp != key);
+    const int start = 63 - __clzll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)));
+    has = has && ((lane - start) & 3) == 0;
+  }
   if (has) {
 #pragma unroll
     for (int b = 0; b < 8; ++b) rank[b] = atomicAdd(&lcnt[idx[b] >> RM_RB_BITS], 1);
