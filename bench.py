@@ -294,16 +294,19 @@ def density_ablation(wl, ids, rays, prec, steps):
 
 
 def algorithmic_bytes(ctx, ids, rays, phase):
-    """Algorithmic bytes of one step of a kernel (all its launches)."""
+    """Algorithmic bytes of one step of a kernel (all its launches).  The
+    binning kernels' records are the counted ones (fewer than 8 per sample
+    and level where runs of samples in one cell are merged)."""
     L, N = ctx.cfg.n_levels, ctx.cfg.samples_per_ray
     S = sum(rays) * N
     grid = sum(ctx.object_info(i).n_grid_params for i in ids)
+    rec = ctx.step_records()
     if phase == "encode_fwd":   # 8 corners x 8 B gathered + 8 B written, per sample and level
         return S * L * (64 + 8)
-    if phase == "bin_scatter":  # 8 B adjoint read + 8 records x 10 B written
-        return S * L * (8 + 80)
-    if phase == "bin_acc":      # 8 records x 10 B read; Adam on the table: p, m, v read and written
-        return S * L * 80 + 24 * grid
+    if phase == "bin_scatter":  # 8 B adjoint read per sample and level + 10 B per record written
+        return S * L * 8 + 10 * rec
+    if phase == "bin_acc":      # 10 B per record read; Adam on the table: p, m, v read and written
+        return 10 * rec + 24 * grid
     if phase == "field":        # encodings read twice (forward, recompute), adjoints written
         return S * L * 8 * 3
     return 0

@@ -324,6 +324,11 @@ romap_status romap_field_backward(romap_ctx* ctx, int32_t object_id, const float
  * profile_phases = 1 (measured with HIP events on the context stream).  avg_ms: ROMAP_N_PHASES floats.  *n_steps (may be
  * NULL) receives the number of steps averaged (0 if none). */
 romap_status romap_get_phase_times(romap_ctx* ctx, float* avg_ms, int32_t* n_steps);
+/* Gradient records per step (written by the binning kernel, read by the
+ * accumulation; 10 B each) averaged over the same profiled steps: the work
+ * measure of the two binning kernels (fewer than 8 per sample and level
+ * where runs of samples in one cell are merged). */
+romap_status romap_get_step_records(romap_ctx* ctx, double* avg_records);
 
 /* Synchronises the context stream. */
 romap_status romap_sync(romap_ctx* ctx);

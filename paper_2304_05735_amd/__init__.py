@@ -80,7 +80,7 @@ EXPORTS = ["romap_default_config", "romap_create", "romap_destroy", "romap_last_
            "romap_field_backward", "romap_get_phase_times", "romap_sync", "romap_set_occupancy",
            "romap_update_occupancy", "romap_get_occupancy", "romap_marching_cubes",
            "romap_extract_mesh", "romap_mc_case", "romap_box_from_points",
-           "romap_debug_bin_capacity"]
+           "romap_debug_bin_capacity", "romap_get_step_records"]
 
 
 def lib():
@@ -123,6 +123,7 @@ def lib():
             "romap_extract_mesh": [P, i32, i32, C.c_float, i32, P, i64, C.POINTER(i64), i32],
             "romap_mc_case": [i32, P],
             "romap_debug_bin_capacity": [P, i32],
+            "romap_get_step_records": [P, C.POINTER(C.c_double)],
             "romap_box_from_points": [P, i64, C.POINTER(romap_box)],
         }
         for name, args in sig.items():
@@ -381,6 +382,12 @@ class Context:
         b = np.zeros(32768, np.uint8)
         self._check(lib().romap_get_occupancy(self.h, int(oid), _ptr(b)))
         return b
+
+    def step_records(self) -> float:
+        """Gradient records per step over the last profiled romap_train."""
+        x = C.c_double(0.0)
+        self._check(lib().romap_get_step_records(self.h, C.byref(x)))
+        return x.value
 
     def phase_times(self):
         """Average ms per kernel over the steps of the last profiled train call."""

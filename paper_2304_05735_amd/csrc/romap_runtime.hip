@@ -141,6 +141,7 @@ struct romap_ctx {
   std::vector<int> pev_phase;    // phase that ends at each recorded event (-1: start)
   int pev_n = 0;                 // events recorded in the current step
   double phase_ms[ROMAP_N_PHASES] = {};
+  double records_sum = 0;        // gradient records of the profiled steps
   int phase_steps = 0;
   std::string err;
 };
@@ -515,6 +516,19 @@ hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a0, bool ad
   return hipSuccess;
 }
 
+// Adds the gradient records the step just run wrote into its bins (the
+// binning kernel's fill counters, clamped at each bin's capacity).
+romap_status count_records(romap_ctx* c, const Plan& p) {
+  if (p.bin_regions == 0) return ROMAP_OK;
+  std::vector<int32_t> cnt((size_t)p.bin_regions);
+  HIPCHK(c, hipMemcpyAsync(cnt.data(), c->d_bin_count, cnt.size() * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (const BinPair& bp : p.bpairs)
+    for (int r = 0; r < bp.R; ++r) c->records_sum += std::min(cnt[bp.bin_base + r], bp.cap);
+  return ROMAP_OK;
+}
+
 // Adds the kernel durations of the step whose events were just recorded:
 // the time between two consecutive events belongs to the phase of the later.
 hipError_t accumulate_phases(romap_ctx* c) {
@@ -791,6 +805,12 @@ romap_status romap_get_phase_times(romap_ctx* c, float* avg_ms, int32_t* n_steps
   for (int i = 0; i < ROMAP_N_PHASES; ++i)
     avg_ms[i] = c->phase_steps ? (float)(c->phase_ms[i] / c->phase_steps) : 0.0f;
   if (n_steps) *n_steps = c->phase_steps;
+  return ROMAP_OK;
+}
+
+romap_status romap_get_step_records(romap_ctx* c, double* avg_records) {
+  if (!c || !avg_records) return ROMAP_E_INVALID_ARG;
+  *avg_records = c->phase_steps ? c->records_sum / c->phase_steps : 0.0;
   return ROMAP_OK;
 }
 
@@ -1148,6 +1168,7 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
   const bool prof = c->cfg.profile_phases != 0;
   if (prof) {
     c->pev_n = 0;
+    c->records_sum = 0;
     for (int i = 0; i < ROMAP_N_PHASES; ++i) c->phase_ms[i] = 0.0;
     c->phase_steps = 0;
   }
@@ -1163,6 +1184,8 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
       for (int i = 0; i < n_steps; ++i) {
         HIPCHK(c, enqueue_step(c, all, a, true, true));
         HIPCHK(c, accumulate_phases(c));
+        s = count_records(c, all);
+        if (s != ROMAP_OK) return s;
         ++c->phase_steps;
       }
     } else if (c->cfg.use_graph && graph_pays(c, list, rpi, blk, n_steps)) {
@@ -1214,7 +1237,11 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
     for (int i = 0; i < n_steps; ++i) {
       for (size_t k = 0; k < plans.size(); ++k) {
         HIPCHK(c, enqueue_step(c, plans[k], args[k], true, prof));
-        if (prof) HIPCHK(c, accumulate_phases(c));
+        if (prof) {
+          HIPCHK(c, accumulate_phases(c));
+          s = count_records(c, plans[k]);
+          if (s != ROMAP_OK) return s;
+        }
       }
       if (prof) ++c->phase_steps;
     }

@@ -394,3 +394,27 @@ def test_graph_replay_equals_eager_steps(tiny):
     for kind in (pk.PARAMS, pk.ADAM_M, pk.ADAM_V):
         assert np.array_equal(ga.get_params(ia, kind), gb.get_params(ib, kind)), kind
     assert la1 == lb1 and la2 == lb2
+
+
+def test_profiled_steps_match_and_count_records(tiny):
+    """Profiled steps (one event pair per phase, records counted) advance the
+    state exactly as unprofiled ones, and the counted gradient records stay
+    within 8 per sample and level; on a coarse dense level, where runs of
+    samples in one cell are merged, there are fewer."""
+    _say("profiled steps")
+    frames, box = tiny
+    B, N, L = 64, 32, 2
+    res = {}
+    for nmin, nmax, log2T in ((16, 32, 8), (4, 8, 12)):
+        for prof in (1, 0):
+            g, o, gid = make_pair(L, nmin, nmax, log2T, N, B, frames, box,
+                                  profile_phases=prof, use_graph=0)
+            _set_same_params(g, o, gid, seed=5)
+            g.train(3, [gid])
+            res[(nmin, prof)] = (g.get_params(gid, pk.PARAMS), g.get_params(gid, pk.ADAM_V),
+                                 g.step_records() if prof else None)
+        for k in (0, 1):
+            assert np.array_equal(res[(nmin, 1)][k], res[(nmin, 0)][k])
+    hashed, merged = res[(16, 1)][2], res[(4, 1)][2]
+    assert 0 < hashed <= 8 * B * N * L
+    assert 0 < merged < 8 * B * N * L
