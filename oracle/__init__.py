@@ -49,7 +49,8 @@ class Config(C.Structure):
 
 class Levels(C.Structure):
     _fields_ = [("L", C.c_int32), ("N", C.c_int32 * MAX_LEVELS), ("T", C.c_int64 * MAX_LEVELS),
-                ("hashed", C.c_int32 * MAX_LEVELS), ("off", C.c_int64 * (MAX_LEVELS + 1))]
+                ("hashed", C.c_int32 * MAX_LEVELS), ("off", C.c_int64 * (MAX_LEVELS + 1)),
+                ("mlp_layers", C.c_int32)]
 
 
 class Keyframe(C.Structure):
@@ -80,6 +81,7 @@ def lib():
         P = C.c_void_p
         _lib.or_grid_params.restype = C.c_int64
         _lib.or_mlp_params.restype = C.c_int64
+        _lib.or_mlp_params.argtypes = [C.c_int, C.c_int]
         _lib.or_make_levels.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Levels)]
         _lib.or_slab.argtypes = [P, P, P, P, P]
         _lib.or_sample_positions.argtypes = [P, P, P, C.c_float, C.c_float, C.c_int, P, P, P]
@@ -87,7 +89,7 @@ def lib():
                                       C.c_int, C.c_int, P, P]
         _lib.or_object_frame.argtypes = [P, P, C.c_float, P, P]
         _lib.or_encode.argtypes = [C.POINTER(Levels), P, P, P, P, P]
-        _lib.or_mlp_forward.argtypes = [C.c_int, P, P, P, P, P, P, P]
+        _lib.or_mlp_forward.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P, P]
         _lib.or_composite.argtypes = [C.c_int, P, P, P, C.c_double, C.c_int, P, P, P, P, P]
         _lib.or_candidate_rect.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P]
         _lib.or_draw_ray.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, C.c_int,
@@ -168,10 +170,15 @@ def philox(ctr, key) -> np.ndarray:
     return out
 
 
-def levels(L, nmin, nmax, log2T) -> Levels:
+def levels(L, nmin, nmax, log2T, mlp_layers=1) -> Levels:
+    """Level table of an object's grid; mlp_layers = hidden layers of its
+    density MLP (1, 2 or 3)."""
+    if mlp_layers not in (1, 2, 3):
+        raise ValueError("mlp_layers must be 1, 2 or 3")
     lv = Levels()
     if lib().or_make_levels(L, nmin, nmax, log2T, C.byref(lv)) != 0:
         raise ValueError("bad level parameters")
+    lv.mlp_layers = mlp_layers
     return lv
 
 
@@ -179,8 +186,8 @@ def grid_params(lv: Levels) -> int:
     return int(lv.off[lv.L])
 
 
-def mlp_params(din: int) -> int:
-    return int(lib().or_mlp_params(din))
+def mlp_params(din: int, layers: int = 1) -> int:
+    return int(lib().or_mlp_params(din, layers))
 
 
 def object_frame(Twc, t, yaw):
@@ -233,15 +240,17 @@ def encode(lv: Levels, p, grid):
     return idx.reshape(L, 8), w.reshape(L, 8), e
 
 
-def mlp_forward(din, mlp, e):
+def mlp_forward(din, mlp, e, layers=1):
+    """h1: the density MLP's hidden activations, 64 per layer."""
     mlp = np.ascontiguousarray(mlp, np.float64)
     e = np.ascontiguousarray(e, np.float64)
-    h1 = np.zeros(HIDDEN)
+    assert mlp.size >= mlp_params(din, layers)
+    h1 = np.zeros(HIDDEN * layers)
     y = np.zeros(DOUT)
     h2 = np.zeros(HIDDEN)
     sigma = np.zeros(1)
     rgb = np.zeros(3)
-    lib().or_mlp_forward(din, _p(mlp), _p(e), _p(h1), _p(y), _p(h2), _p(sigma), _p(rgb))
+    lib().or_mlp_forward(din, layers, _p(mlp), _p(e), _p(h1), _p(y), _p(h2), _p(sigma), _p(rgb))
     return dict(h1=h1, y=y, h2=h2, sigma=float(sigma[0]), rgb=rgb)
 
 
@@ -316,8 +325,10 @@ class _Obj:
 class OracleContext:
     """Plain CPU counterpart of the GPU library's context (same verbs)."""
 
-    def __init__(self, cfg: Config, alpha_deg: float = 25.0, nthreads: int | None = None):
+    def __init__(self, cfg: Config, alpha_deg: float = 25.0, nthreads: int | None = None,
+                 mlp_layers: int = 1):
         self.cfg = cfg
+        self.mlp_layers = mlp_layers
         self.alpha_deg = alpha_deg
         self.nthreads = nthreads or min(16, os.cpu_count() or 1)
         self.objects: list[_Obj] = []
@@ -326,8 +337,8 @@ class OracleContext:
     # register object with box and table size (Sec. V: a new model per new instance)
     def add_object(self, instance, t, yaw, half, log2T=None, params=None) -> int:
         log2T = self.cfg.log2T if log2T is None else log2T
-        lv = levels(self.cfg.L, self.cfg.nmin, self.cfg.nmax, log2T)
-        P = grid_params(lv) + mlp_params(2 * self.cfg.L)
+        lv = levels(self.cfg.L, self.cfg.nmin, self.cfg.nmax, log2T, self.mlp_layers)
+        P = grid_params(lv) + mlp_params(2 * self.cfg.L, self.mlp_layers)
         p = np.zeros(P) if params is None else np.array(params, np.float64)
         assert p.size == P
         self.objects.append(_Obj(instance, t, yaw, half, log2T, lv, p))

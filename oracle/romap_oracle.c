@@ -89,14 +89,18 @@ int or_make_levels(int L, int nmin, int nmax, int log2T, or_levels* out) {
     off += out->T[l] * 2;
   }
   out->off[L] = off;
+  out->mlp_layers = 1;
   return 0;
 }
 
 int64_t or_grid_params(const or_levels* lv) { return lv->off[lv->L]; }
 
-/* W1 (64 x din), W2 (16 x 64), W3 (64 x 15), W4 (3 x 64), row-major, no biases */
-int64_t or_mlp_params(int din) {
-  return (int64_t)OR_HIDDEN * din + OR_DOUT * OR_HIDDEN + OR_HIDDEN * OR_GEO + 3 * OR_HIDDEN;
+/* W1 (64 x din), then layers - 1 hidden-to-hidden matrices Wh (64 x 64) of
+ * the density MLP, W2 (16 x 64), W3 (64 x 15), W4 (3 x 64); row-major (row =
+ * output), no biases */
+int64_t or_mlp_params(int din, int layers) {
+  return (int64_t)OR_HIDDEN * din + (int64_t)(layers - 1) * OR_HIDDEN * OR_HIDDEN +
+         OR_DOUT * OR_HIDDEN + OR_HIDDEN * OR_GEO + 3 * OR_HIDDEN;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -216,12 +220,16 @@ void or_encode(const or_levels* lv, const float p[3], const double* grid, uint32
 }
 
 /* Density / colour MLP (Sec. V: a single hidden layer of 64 per head; position
- * only, no view direction, Sec. V-B).  h1 = ReLU(W1 e), y = W2 h1,
- * sigma = exp(min(y0, 15)), h2 = ReLU(W3 y[1..15]), rgb = sigmoid(W4 h2). */
-void or_mlp_forward(int din, const double* mlp, const double* e, double* h1, double* y,
+ * only, no view direction, Sec. V-B; the model-size study of Table 4 also
+ * trains density MLPs of 2 and 3 hidden layers).  h_0 = ReLU(W1 e),
+ * h_k = ReLU(Wh_k h_{k-1}) for k < layers, y = W2 h_{layers-1},
+ * sigma = exp(min(y0, 15)), h2 = ReLU(W3 y[1..15]), rgb = sigmoid(W4 h2).
+ * h1 receives the layers hidden activations, 64 each. */
+void or_mlp_forward(int din, int layers, const double* mlp, const double* e, double* h1, double* y,
                     double* h2, double* sigma, double* rgb) {
   const double* W1 = mlp;
-  const double* W2 = W1 + OR_HIDDEN * din;
+  const double* Wh = W1 + OR_HIDDEN * din;
+  const double* W2 = Wh + (layers - 1) * OR_HIDDEN * OR_HIDDEN;
   const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
   const double* W4 = W3 + OR_HIDDEN * OR_GEO;
   for (int i = 0; i < OR_HIDDEN; ++i) {
@@ -229,9 +237,20 @@ void or_mlp_forward(int din, const double* mlp, const double* e, double* h1, dou
     for (int j = 0; j < din; ++j) s += W1[i * din + j] * e[j];
     h1[i] = s > 0.0 ? s : 0.0;
   }
+  for (int k = 1; k < layers; ++k) {
+    const double* W = Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    const double* hp = h1 + (k - 1) * OR_HIDDEN;
+    double* hn = h1 + k * OR_HIDDEN;
+    for (int i = 0; i < OR_HIDDEN; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < OR_HIDDEN; ++j) s += W[i * OR_HIDDEN + j] * hp[j];
+      hn[i] = s > 0.0 ? s : 0.0;
+    }
+  }
+  const double* hl = h1 + (layers - 1) * OR_HIDDEN;
   for (int i = 0; i < OR_DOUT; ++i) {
     double s = 0.0;
-    for (int j = 0; j < OR_HIDDEN; ++j) s += W2[i * OR_HIDDEN + j] * h1[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) s += W2[i * OR_HIDDEN + j] * hl[j];
     y[i] = s;
   }
   *sigma = exp(fmin(y[0], 15.0));
@@ -358,11 +377,11 @@ typedef struct {
   int* live; /* sample not skipped by the occupancy bitfield */
 } or_scratch;
 
-static void scratch_alloc(or_scratch* s, int N, int L) {
+static void scratch_alloc(or_scratch* s, int N, int L, int layers) {
   s->idx = (uint32_t*)malloc(sizeof(uint32_t) * N * L * 8);
   s->w = (double*)malloc(sizeof(double) * N * L * 8);
   s->e = (double*)malloc(sizeof(double) * N * L * 2);
-  s->h1 = (double*)malloc(sizeof(double) * N * OR_HIDDEN);
+  s->h1 = (double*)malloc(sizeof(double) * N * OR_HIDDEN * layers);
   s->y = (double*)malloc(sizeof(double) * N * OR_DOUT);
   s->h2 = (double*)malloc(sizeof(double) * N * OR_HIDDEN);
   s->sigma = (double*)malloc(sizeof(double) * N);
@@ -384,21 +403,26 @@ static void scratch_free(or_scratch* s) {
 }
 
 /* Backward of one sample through the MLPs and the encoding.  dsig, dc are
- * dl/dsigma and dl/dc of this sample; adds into grad (grid, then MLP). */
+ * dl/dsigma and dl/dc of this sample; adds into grad (grid, then MLP).  h1
+ * holds the hidden activations of the density MLP's lv->mlp_layers layers. */
 static void sample_backward(const or_levels* lv, int din, const double* mlp, const uint32_t* idx,
                             const double* w, const double* e, const double* h1, const double* y,
                             const double* h2, double sigma, const double* rgb, double dsig,
                             const double* dc, double* grad) {
+  const int nh = lv->mlp_layers;
   const double* W1 = mlp;
-  const double* W2 = W1 + OR_HIDDEN * din;
+  const double* Wh = W1 + OR_HIDDEN * din;
+  const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
   const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
   const double* W4 = W3 + OR_HIDDEN * OR_GEO;
   double* gG = grad;
   double* gW1 = grad + or_grid_params(lv);
-  double* gW2 = gW1 + OR_HIDDEN * din;
+  double* gWh = gW1 + OR_HIDDEN * din;
+  double* gW2 = gWh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
   double* gW3 = gW2 + OR_DOUT * OR_HIDDEN;
   double* gW4 = gW3 + OR_HIDDEN * OR_GEO;
-  double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], dh1[OR_HIDDEN], de[2 * OR_MAX_LEVELS];
+  double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], dh[OR_HIDDEN], dp[OR_HIDDEN],
+      de[2 * OR_MAX_LEVELS];
   for (int k = 0; k < 3; ++k) dz4[k] = dc[k] * rgb[k] * (1.0 - rgb[k]);
   for (int k = 0; k < 3; ++k)
     for (int j = 0; j < OR_HIDDEN; ++j) gW4[k * OR_HIDDEN + j] += dz4[k] * h2[j];
@@ -415,18 +439,34 @@ static void sample_backward(const or_levels* lv, int din, const double* mlp, con
     dy[1 + g] = s;
   }
   dy[0] = y[0] < 15.0 ? dsig * sigma : 0.0;
+  /* last hidden layer */
+  const double* hl = h1 + (nh - 1) * OR_HIDDEN;
   for (int i = 0; i < OR_DOUT; ++i)
-    for (int j = 0; j < OR_HIDDEN; ++j) gW2[i * OR_HIDDEN + j] += dy[i] * h1[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) gW2[i * OR_HIDDEN + j] += dy[i] * hl[j];
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double s = 0.0;
     for (int i = 0; i < OR_DOUT; ++i) s += W2[i * OR_HIDDEN + j] * dy[i];
-    dh1[j] = h1[j] > 0.0 ? s : 0.0;
+    dh[j] = hl[j] > 0.0 ? s : 0.0;
+  }
+  /* hidden-to-hidden layers, last to first: dh is the adjoint of h_k */
+  for (int k = nh - 1; k >= 1; --k) {
+    const double* W = Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    double* gW = gWh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    const double* hp = h1 + (k - 1) * OR_HIDDEN;
+    for (int i = 0; i < OR_HIDDEN; ++i)
+      for (int j = 0; j < OR_HIDDEN; ++j) gW[i * OR_HIDDEN + j] += dh[i] * hp[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < OR_HIDDEN; ++i) s += W[i * OR_HIDDEN + j] * dh[i];
+      dp[j] = hp[j] > 0.0 ? s : 0.0;
+    }
+    memcpy(dh, dp, sizeof(dh));
   }
   for (int j = 0; j < OR_HIDDEN; ++j)
-    for (int q = 0; q < din; ++q) gW1[j * din + q] += dh1[j] * e[q];
+    for (int q = 0; q < din; ++q) gW1[j * din + q] += dh[j] * e[q];
   for (int q = 0; q < din; ++q) {
     double s = 0.0;
-    for (int j = 0; j < OR_HIDDEN; ++j) s += W1[j * din + q] * dh1[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) s += W1[j * din + q] * dh[j];
     de[q] = s;
   }
   for (int l = 0; l < lv->L; ++l)
@@ -448,16 +488,20 @@ static void sample_backward_magnitude(const or_levels* lv, int din, const double
                                       const double* h1, const double* y, const double* h2,
                                       double sigma, const double* rgb, double dsig_m,
                                       const double* dc_m, int all_branches, double* mag) {
+  const int nh = lv->mlp_layers;
   const double* W1 = mlp;
-  const double* W2 = W1 + OR_HIDDEN * din;
+  const double* Wh = W1 + OR_HIDDEN * din;
+  const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
   const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
   const double* W4 = W3 + OR_HIDDEN * OR_GEO;
   double* mG = mag;
   double* mW1 = mag + or_grid_params(lv);
-  double* mW2 = mW1 + OR_HIDDEN * din;
+  double* mWh = mW1 + OR_HIDDEN * din;
+  double* mW2 = mWh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
   double* mW3 = mW2 + OR_DOUT * OR_HIDDEN;
   double* mW4 = mW3 + OR_HIDDEN * OR_GEO;
-  double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], dh1[OR_HIDDEN], de[2 * OR_MAX_LEVELS];
+  double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], dh[OR_HIDDEN], dp[OR_HIDDEN],
+      de[2 * OR_MAX_LEVELS];
   for (int k = 0; k < 3; ++k) dz4[k] = dc_m[k] * rgb[k] * (1.0 - rgb[k]);
   for (int k = 0; k < 3; ++k)
     for (int j = 0; j < OR_HIDDEN; ++j) mW4[k * OR_HIDDEN + j] += dz4[k] * h2[j];
@@ -474,18 +518,32 @@ static void sample_backward_magnitude(const or_levels* lv, int din, const double
     dy[1 + g] = s;
   }
   dy[0] = (y[0] < 15.0 || all_branches) ? dsig_m * sigma : 0.0;
+  const double* hl = h1 + (nh - 1) * OR_HIDDEN;
   for (int i = 0; i < OR_DOUT; ++i)
-    for (int j = 0; j < OR_HIDDEN; ++j) mW2[i * OR_HIDDEN + j] += dy[i] * h1[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) mW2[i * OR_HIDDEN + j] += dy[i] * hl[j];
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double s = 0.0;
     for (int i = 0; i < OR_DOUT; ++i) s += fabs(W2[i * OR_HIDDEN + j]) * dy[i];
-    dh1[j] = (h1[j] > 0.0 || all_branches) ? s : 0.0;
+    dh[j] = (hl[j] > 0.0 || all_branches) ? s : 0.0;
+  }
+  for (int k = nh - 1; k >= 1; --k) {
+    const double* W = Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    double* mW = mWh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    const double* hp = h1 + (k - 1) * OR_HIDDEN;
+    for (int i = 0; i < OR_HIDDEN; ++i)
+      for (int j = 0; j < OR_HIDDEN; ++j) mW[i * OR_HIDDEN + j] += dh[i] * hp[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < OR_HIDDEN; ++i) s += fabs(W[i * OR_HIDDEN + j]) * dh[i];
+      dp[j] = (hp[j] > 0.0 || all_branches) ? s : 0.0;
+    }
+    memcpy(dh, dp, sizeof(dh));
   }
   for (int j = 0; j < OR_HIDDEN; ++j)
-    for (int q = 0; q < din; ++q) mW1[j * din + q] += dh1[j] * fabs(e[q]);
+    for (int q = 0; q < din; ++q) mW1[j * din + q] += dh[j] * fabs(e[q]);
   for (int q = 0; q < din; ++q) {
     double s = 0.0;
-    for (int j = 0; j < OR_HIDDEN; ++j) s += fabs(W1[j * din + q]) * dh1[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) s += fabs(W1[j * din + q]) * dh[j];
     de[q] = s;
   }
   for (int l = 0; l < lv->L; ++l)
@@ -519,15 +577,15 @@ static void ray_forward(const or_levels* lv, int N, const double* params, const 
                         const float d[3], const float half[3], float tn, float tf, float* delta,
                         or_scratch* s, int bg, const double crand[3], double C[3], double* D,
                         double* Tend, const uint8_t* occ) {
-  const int L = lv->L, din = 2 * L;
+  const int L = lv->L, din = 2 * L, nh = lv->mlp_layers;
   const double* mlp = params + or_grid_params(lv);
   or_sample_positions(o, d, half, tn, tf, N, delta, s->dist32, s->pos);
   for (int i = 0; i < N; ++i) s->dist[i] = (double)s->dist32[i];
   for (int i = 0; i < N; ++i) {
     s->live[i] = or_occupied(occ, s->pos + 3 * i);
     or_encode(lv, s->pos + 3 * i, params, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i);
-    or_mlp_forward(din, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * i, s->y + OR_DOUT * i,
-                   s->h2 + OR_HIDDEN * i, s->sigma + i, s->rgb + 3 * i);
+    or_mlp_forward(din, nh, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
+                   s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma + i, s->rgb + 3 * i);
     if (!s->live[i]) s->sigma[i] = 0.0;
   }
   or_composite(N, s->sigma, s->rgb, s->dist, (double)*delta, bg, crand, C, D, Tend, s->wts);
@@ -543,7 +601,7 @@ static void ray_backward(const or_levels* lv, int N, const double* params, doubl
                          or_scratch* s, int bg, const double crand[3], double Tend,
                          const double gC[3], double gD, double gT, double dens, double* grad,
                          double* mag) {
-  const int L = lv->L, din = 2 * L;
+  const int L = lv->L, din = 2 * L, nh = lv->mlp_layers;
   const double* mlp = params + or_grid_params(lv);
   double suf_c[3] = {0.0, 0.0, 0.0}, suf_d = 0.0;
   double S_i = 0.0;
@@ -574,14 +632,14 @@ static void ray_backward(const or_levels* lv, int N, const double* params, doubl
     double dci[3];
     for (int k = 0; k < 3; ++k) dci[k] = s->wts[i] * gC[k];
     sample_backward(lv, din, mlp, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i,
-                    s->h1 + OR_HIDDEN * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i,
+                    s->h1 + OR_HIDDEN * nh * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i,
                     s->sigma[i], s->rgb + 3 * i, s->dsig[i], dci, grad);
     if (mag) {
       for (int k = 0; k < 3; ++k) dci[k] = s->wts[i] * fabs(gC[k]);
       sample_backward_magnitude(lv, din, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
-                                s->e + 2 * L * i, s->h1 + OR_HIDDEN * i, s->y + OR_DOUT * i,
-                                s->h2 + OR_HIDDEN * i, s->sigma[i], s->rgb + 3 * i,
-                                s->dsig_m[i], dci, 0, mag);
+                                s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
+                                s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma[i],
+                                s->rgb + 3 * i, s->dsig_m[i], dci, 0, mag);
     }
   }
 }
@@ -592,10 +650,11 @@ static void ray_backward(const or_levels* lv, int N, const double* params, doubl
  * The relative distance of a decision from its tie is |pre-activation| over
  * the sum of |terms| that form it; sample_ties returns the smallest one over
  * the sample's decisions. */
-static double sample_ties(int din, const double* mlp, const double* e, const double* h1,
+static double sample_ties(int din, int nh, const double* mlp, const double* e, const double* h1,
                           const double* y) {
   const double* W1 = mlp;
-  const double* W2 = W1 + OR_HIDDEN * din;
+  const double* Wh = W1 + OR_HIDDEN * din;
+  const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
   const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
   double m = INFINITY;
   for (int j = 0; j < OR_HIDDEN; ++j) {
@@ -606,6 +665,18 @@ static double sample_ties(int din, const double* mlp, const double* e, const dou
     }
     if (mag > 0.0) m = fmin(m, fabs(pre) / mag);
   }
+  for (int k = 1; k < nh; ++k) {
+    const double* W = Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    const double* hp = h1 + (k - 1) * OR_HIDDEN;
+    for (int i = 0; i < OR_HIDDEN; ++i) {
+      double pre = 0.0, mag = 0.0;
+      for (int j = 0; j < OR_HIDDEN; ++j) {
+        pre += W[i * OR_HIDDEN + j] * hp[j];
+        mag += fabs(W[i * OR_HIDDEN + j] * hp[j]);
+      }
+      if (mag > 0.0) m = fmin(m, fabs(pre) / mag);
+    }
+  }
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double pre = 0.0, mag = 0.0;
     for (int g = 0; g < OR_GEO; ++g) {
@@ -614,8 +685,9 @@ static double sample_ties(int din, const double* mlp, const double* e, const dou
     }
     if (mag > 0.0) m = fmin(m, fabs(pre) / mag);
   }
+  const double* hl = h1 + (nh - 1) * OR_HIDDEN;
   double mag0 = 0.0;
-  for (int j = 0; j < OR_HIDDEN; ++j) mag0 += fabs(W2[j] * h1[j]);
+  for (int j = 0; j < OR_HIDDEN; ++j) mag0 += fabs(W2[j] * hl[j]);
   if (mag0 > 0.0) m = fmin(m, fabs(y[0] - 15.0) / mag0);
   return m;
 }
@@ -629,12 +701,12 @@ static double sample_ties(int din, const double* mlp, const double* e, const dou
 static double tie_allowance(const or_levels* lv, int N, const double* params, or_scratch* s,
                             const double gCabs[3], double dtie, double* amb) {
   const double kTie = 1e-5;
-  const int L = lv->L;
+  const int L = lv->L, nh = lv->mlp_layers;
   const double* mlp = params + or_grid_params(lv);
   double rm = dtie;
   for (int i = 0; i < N; ++i) {
     if (!s->live[i]) continue;
-    const double sm = sample_ties(2 * L, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * i,
+    const double sm = sample_ties(2 * L, nh, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
                                   s->y + OR_DOUT * i);
     rm = fmin(rm, sm);
     const int reps = dtie < kTie ? 2 : (sm < kTie ? 1 : 0);
@@ -644,9 +716,9 @@ static double tie_allowance(const or_levels* lv, int N, const double* params, or
 #pragma omp critical
       for (int rep = 0; rep < reps; ++rep)
         sample_backward_magnitude(lv, 2 * L, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
-                                  s->e + 2 * L * i, s->h1 + OR_HIDDEN * i, s->y + OR_DOUT * i,
-                                  s->h2 + OR_HIDDEN * i, s->sigma[i], s->rgb + 3 * i,
-                                  s->dsig_m[i], dcm, 1, amb);
+                                  s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
+                                  s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma[i],
+                                  s->rgb + 3 * i, s->dsig_m[i], dcm, 1, amb);
     }
   }
   return rm;
@@ -668,7 +740,7 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
                    int nthreads) {
   if (nkf < 1 || B < 1 || cfg->N < 1) return -1;
   const int L = lv->L, N = cfg->N;
-  const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L);
+  const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L, lv->mlp_layers);
   if (nthreads < 1) nthreads = 1;
   double* ray_loss = (double*)calloc((size_t)B, sizeof(double));
   double* ray_margin = (double*)calloc((size_t)B, sizeof(double));
@@ -685,7 +757,7 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
     tid = omp_get_thread_num();
 #endif
     or_scratch s;
-    scratch_alloc(&s, N, L);
+    scratch_alloc(&s, N, L, lv->mlp_layers);
     double* my_grad = grad ? tgrad + (int64_t)tid * P : NULL;
     double* my_abs = tabs ? tabs + (int64_t)tid * P : NULL;
 #pragma omp for schedule(static)
@@ -766,7 +838,7 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
              const double* d_rgb, const double* d_depth, const double* d_tend, double* grad,
              double* grad_abs, double* ambiguous, int nthreads) {
   const int L = lv->L, N = cfg->N;
-  const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L);
+  const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L, lv->mlp_layers);
   if (nthreads < 1) nthreads = 1;
   double* tgrad = grad ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
   double* tabs = (grad && grad_abs) ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
@@ -778,7 +850,7 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
     tid = omp_get_thread_num();
 #endif
     or_scratch s;
-    scratch_alloc(&s, N, L);
+    scratch_alloc(&s, N, L, lv->mlp_layers);
 #pragma omp for schedule(static)
     for (int r = 0; r < n; ++r) {
       const float* q = rays + 8 * (int64_t)r;
@@ -837,7 +909,7 @@ int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
 #pragma omp parallel num_threads(nthreads)
   {
     or_scratch s;
-    scratch_alloc(&s, N, L);
+    scratch_alloc(&s, N, L, lv->mlp_layers);
 #pragma omp for schedule(static)
     for (int64_t px = 0; px < npix; ++px) {
       int u = (int)(px % cam->W), v = (int)(px / cam->W);
@@ -849,7 +921,8 @@ int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
         for (int i = 0; i < N; ++i) {
           s.dist[i] = (double)s.dist32[i];
           or_encode(lv, s.pos + 3 * i, params, s.idx, s.w, s.e);
-          or_mlp_forward(din, mlp, s.e, s.h1, s.y, s.h2, s.sigma + i, s.rgb + 3 * i);
+          or_mlp_forward(din, lv->mlp_layers, mlp, s.e, s.h1, s.y, s.h2, s.sigma + i,
+                         s.rgb + 3 * i);
           if (!or_occupied(occ, s.pos + 3 * i)) s.sigma[i] = 0.0;
         }
         double zero[3] = {0.0, 0.0, 0.0};
@@ -870,8 +943,8 @@ void or_query_density(const or_levels* lv, const float half[3], const double* pa
   const int din = 2 * lv->L;
   const double* mlp = params + or_grid_params(lv);
   uint32_t idx[8 * OR_MAX_LEVELS];
-  double w[8 * OR_MAX_LEVELS], e[2 * OR_MAX_LEVELS], h1[OR_HIDDEN], y[OR_DOUT], h2[OR_HIDDEN],
-      rgb[3];
+  double w[8 * OR_MAX_LEVELS], e[2 * OR_MAX_LEVELS], h1[OR_HIDDEN * OR_MAX_MLP_LAYERS], y[OR_DOUT],
+      h2[OR_HIDDEN], rgb[3];
   for (int64_t i = 0; i < n; ++i) {
     float p[3];
     for (int k = 0; k < 3; ++k) {
@@ -879,7 +952,7 @@ void or_query_density(const or_levels* lv, const float half[3], const double* pa
       p[k] = fminf(fmaxf(q, 0.0f), 1.0f);
     }
     or_encode(lv, p, params, idx, w, e);
-    or_mlp_forward(din, mlp, e, h1, y, h2, sigma + i, rgb);
+    or_mlp_forward(din, lv->mlp_layers, mlp, e, h1, y, h2, sigma + i, rgb);
   }
 }
 

@@ -18,6 +18,7 @@
 #define OR_HIDDEN 64
 #define OR_GEO 15
 #define OR_DOUT 16 /* 1 density logit + 15 geometry features */
+#define OR_MAX_MLP_LAYERS 3 /* hidden layers of the density MLP (Table 4: 1, 2, 3) */
 
 typedef struct {
   int32_t L, nmin, nmax, log2T, N; /* levels, coarsest/finest res, log2 table, samples per ray */
@@ -33,6 +34,8 @@ typedef struct {
   int64_t T[OR_MAX_LEVELS];      /* entries of each level */
   int32_t hashed[OR_MAX_LEVELS]; /* 1 = spatial hash, 0 = dense 1:1 */
   int64_t off[OR_MAX_LEVELS + 1];/* offset of each level in floats (F = 2) */
+  int32_t mlp_layers;            /* hidden layers of the density MLP, 1..3 (1 from
+                                    or_make_levels; the caller may raise it) */
 } or_levels;
 
 typedef struct {
@@ -55,7 +58,7 @@ typedef struct {
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 int or_make_levels(int L, int nmin, int nmax, int log2T, or_levels* out);
 int64_t or_grid_params(const or_levels* lv);
-int64_t or_mlp_params(int din);
+int64_t or_mlp_params(int din, int layers);
 void or_object_frame(const float Twc[12], const float t[3], float yaw, float M[9], float c[3]);
 void or_pixel_ray(const float M[9], const float c[3], float fx, float fy, float cx, float cy,
                   int u, int v, float o[3], float d[3]);
@@ -64,8 +67,8 @@ void or_sample_positions(const float o[3], const float d[3], const float half[3]
                          float tf, int N, float* delta, float* dist, float* pos);
 void or_encode(const or_levels* lv, const float p[3], const double* grid, uint32_t* idx,
                double* w, double* e);
-void or_mlp_forward(int din, const double* mlp, const double* e, double* h1, double* y,
-                    double* h2, double* sigma, double* rgb);
+void or_mlp_forward(int din, int layers, const double* mlp, const double* e, double* h1,
+                    double* y, double* h2, double* sigma, double* rgb);
 void or_composite(int N, const double* sigma, const double* rgb, const double* dist, double delta,
                   int background, const double crand[3], double C[3], double* D, double* Tend,
                   double* w);

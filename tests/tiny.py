@@ -35,13 +35,13 @@ def tiny_scene(W=24, H=20, n_views=3, seed=0):
     return frames, box
 
 
-def random_params(n_grid, din, seed=0, grid_scale=0.5):
-    """Grid U(-s, s); MLP Glorot-uniform.  Layout: grid, W1 (64 x din), W2 (16 x 64),
-    W3 (64 x 15), W4 (3 x 64)."""
+def random_params(n_grid, din, seed=0, grid_scale=0.5, layers=1):
+    """Grid U(-s, s); MLP Glorot-uniform.  Layout: grid, W1 (64 x din), layers - 1
+    matrices 64 x 64 (density MLP), W2 (16 x 64), W3 (64 x 15), W4 (3 x 64)."""
     rng = np.random.default_rng(seed)
     grid = rng.uniform(-grid_scale, grid_scale, n_grid)
     mats = []
-    for (o, i) in [(64, din), (16, 64), (64, 15), (3, 64)]:
+    for (o, i) in [(64, din)] + [(64, 64)] * (layers - 1) + [(16, 64), (64, 15), (3, 64)]:
         lim = math.sqrt(6.0 / (o + i))
         mats.append(rng.uniform(-lim, lim, o * i))
     return np.concatenate([grid] + mats)
