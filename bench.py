@@ -237,29 +237,33 @@ def mesh_timing(ctx, ids, res=64, iso=10.0, reps=3):
 
 
 def table_sweep(steps=200, warmup=20):
-    """Table 4's sweep of the hash-table size on one object: time per step
-    (graph, FP32 and BF16) of 4096 rays x 32 samples (the paper's N) and of
-    4096 x 64, for T = 2^14 .. 2^20, on the single-object scene."""
+    """Table 4's model-size study on one object: time per step (graph, FP32
+    and BF16) of 4096 rays x 32 samples (the paper's N) and of 4096 x 64, for
+    T = 2^14 .. 2^20 with the one-hidden-layer density MLP, and for T = 2^16
+    with density MLPs of 2 and 3 hidden layers, on the single-object scene."""
     import paper_2304_05735_amd as pk
     import scenes
     wl = scenes.config2()
     ob = wl.objects[0]
     rows = []
+    models = [(lt, 1) for lt in (14, 16, 18, 20)] + [(16, 2), (16, 3)]
     for N in (32, 64):
         for prec in (pk.PREC_FP32, pk.PREC_BF16):
-            for lt in (14, 16, 18, 20):
-                cfg = pk.default_config(samples_per_ray=N, precision=prec, use_graph=1, autotune=1)
+            for lt, layers in models:
+                cfg = pk.default_config(samples_per_ray=N, precision=prec, use_graph=1, autotune=1,
+                                        mlp_layers=layers)
                 ctx = pk.Context(cfg)
                 i = ctx.add_object(ob.instance, ob.t, ob.yaw, ob.half, lt)
                 for cam, rgb, mask, depth in wl.frames:
                     ctx.add_keyframe(cam, rgb, mask, depth)
                 dt = timed_steps(ctx, [i], [4096], warmup, steps)
                 rows.append(dict(N=N, precision="bf16" if prec else "fp32", log2T=lt,
-                                 ms_per_step=round(dt / steps * 1e3, 4)))
+                                 mlp_layers=layers, ms_per_step=round(dt / steps * 1e3, 4)))
                 log("table sweep", rows[-1])
                 del ctx
     return dict(rows=rows, paper_rtx4090_ms={"2^14": 0.658, "2^16": 0.706, "2^18": 0.921,
-                                              "2^20": 1.495})
+                                              "2^20": 1.495, "2^16, 2 layers": 0.862,
+                                              "2^16, 3 layers": 1.052})
 
 
 def density_ablation(wl, ids, rays, prec, steps):
@@ -430,7 +434,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
     ap.add_argument("--table-sweep", action="store_true",
-                    help="time one object for T = 2^14..2^20 (the paper's Table 4 sweep) and exit")
+                    help="time one object for T = 2^14..2^20 and for 2- and 3-layer density MLPs "
+                         "(the paper's Table 4 study) and exit")
     ap.add_argument("--ablation-density", action="store_true",
                     help="also train with lambda_2 = 0 and report PSNR and empty-space opacity")
     ap.add_argument("--psnr-chunk", type=int, default=250)

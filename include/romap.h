@@ -34,7 +34,8 @@
  *  - Parameter order of an object (get/set_params): the grid level-major,
  *    [level][entry][feature] with F = 2 features and level l holding
  *    T_l = min(T, (N_l + 1)^3) entries; then the MLP weights W1 (64 x 2L),
- *    W2 (16 x 64), W3 (64 x 15), W4 (3 x 64), row-major, no biases.
+ *    mlp_layers - 1 matrices 64 x 64 of a deeper density MLP, W2 (16 x 64),
+ *    W3 (64 x 15), W4 (3 x 64), row-major (row = output), no biases.
  */
 #ifndef ROMAP_H
 #define ROMAP_H
@@ -83,6 +84,10 @@ typedef struct {
   int32_t profile_phases;                  /* time each kernel of a step with HIP
                                               events (launches without a graph and
                                               waits after every step) */
+  int32_t mlp_layers;                      /* hidden layers (64 wide) of the density
+                                              MLP: 1 (Sec. V), 2 or 3 (the model-size
+                                              study of Table 4).  The extra 64 x 64
+                                              matrices follow W1 in the parameters */
   uint64_t seed;
 } romap_config;
 

@@ -12,6 +12,16 @@
 #define RM_REC_STRIDE 4240 /* floats per work-item record: MLP grads, loss, pad */
 #define RM_REC_LOSS 4224
 #define RM_WPACK 10240      /* packed MLP weight image, elements (K1 <= 32) */
+#define RM_MAX_MLP_LAYERS 3 /* hidden layers of the density MLP: 1 (Sec. V), 2, 3 (Table 4) */
+// with nh hidden layers: nh - 1 more 64 x 64 matrices in the parameters,
+// their gradients in the work-item records and two operand images each
+#define RM_HH (RM_HIDDEN * RM_HIDDEN)
+#define RM_MLP_NH(nh) (RM_MLP_MAX + ((nh) - 1) * RM_HH)      /* MLP floats, K1 = 32 */
+#define RM_REC_LOSS_NH(nh) RM_MLP_NH(nh)
+#define RM_REC_STRIDE_NH(nh) (RM_REC_LOSS_NH(nh) + 16)
+#define RM_WPACK_NH(nh) (RM_WPACK + ((nh) - 1) * 2 * RM_HH)
+#define RM_OFF_HF(k) (RM_WPACK + ((k) - 1) * 2 * RM_HH)     /* Wh_k   64 x 64 */
+#define RM_OFF_HB(k) (RM_OFF_HF(k) + RM_HH)                 /* Wh_k^T 64 x 64 */
 #define RM_WG 256           /* threads of the fused field kernel (4 waves) */
 #define RM_FIN_WG 512       /* entries per workgroup of the finishing kernel */
 #define RM_GRAPH_MIN_STEPS 8 /* steps of a romap_train call that repay a graph capture */
@@ -81,7 +91,7 @@ struct ObjStatic {      // written by the host
   uint32_t hashed_mask;
   int32_t L, din, instance, id, n_kf;
   float half[3];
-  int32_t pad;
+  int32_t mlp_layers;   // hidden layers of the density MLP
   const KfRef* kfs;
   int64_t n_cand;
   const uint32_t* occ;  // 64^3 occupancy bits, or null (no skipping)
@@ -179,6 +189,7 @@ struct StepArgs {
   float lr, beta1, beta2, eps;
   int32_t mode;
   int32_t fuse_adam;    // training step: Adam applied where each gradient is complete
+  int32_t mlp_layers;   // hidden layers of the density MLP (1..RM_MAX_MLP_LAYERS)
   const float* params_override; // single-object launches only
   float* grad_override;
   const float* adj_rgb;
@@ -248,7 +259,7 @@ hipError_t rm_launch_debug_encode(const ObjStatic* objs, int obj, const float* p
 hipError_t rm_launch_fill(float* x, int64_t n, float v, hipStream_t st);
 hipError_t rm_launch_occ_update(const ObjStatic* objs, int obj, uint32_t* bits, float threshold,
                                 hipStream_t st);
-hipError_t rm_launch_init(float* params, int64_t P_grid, int din, uint32_t k0, uint32_t k1,
-                          hipStream_t st);
+hipError_t rm_launch_init(float* params, int64_t P_grid, int din, int nh, uint32_t k0,
+                          uint32_t k1, hipStream_t st);
 hipError_t rm_launch_debug_positions(const StepArgs& a, int NS, float* pos, hipStream_t st);
 hipError_t rm_launch_reset_loss(const StepArgs& a, hipStream_t st);

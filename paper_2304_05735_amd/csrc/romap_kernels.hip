@@ -798,9 +798,12 @@ __global__ __launch_bounds__(RM_FIN_WG) void k_bin_finish(StepArgs a) {
 // A[16t + lane%16][16q + 4(lane/16) + r]; the FP32 image orders it
 // ((t Q + q) 4 + r) 64 + lane (one 16x16x4 operand per 64 contiguous values),
 // the BF16 image ((t Q + q) 64 + lane) 4 + r (one 16x16x16 operand per lane).
-__device__ inline float mlp_A(const float* W, int din, int K1, int gemm, int m, int k) {
+// Operands 8 + 2(k-1) and 9 + 2(k-1) are the k-th hidden-to-hidden matrix of
+// a deeper density MLP (nh hidden layers) and its transpose.
+__device__ inline float mlp_A(const float* W, int din, int nh, int gemm, int m, int k) {
   const float* W1 = W;
-  const float* W2 = W1 + RM_HIDDEN * din;
+  const float* Wh = W1 + RM_HIDDEN * din;
+  const float* W2 = Wh + (nh - 1) * RM_HH;
   const float* W3 = W2 + RM_DOUT * RM_HIDDEN;
   const float* W4 = W3 + RM_HIDDEN * RM_GEO;
   switch (gemm) {
@@ -811,7 +814,11 @@ __device__ inline float mlp_A(const float* W, int din, int K1, int gemm, int m, 
     case 4: return k < 3 ? W4[k * RM_HIDDEN + m] : 0.0f;              // B4 64 x 16
     case 5: return m >= 1 ? W3[k * RM_GEO + (m - 1)] : 0.0f;          // B3 16 x 64
     case 6: return W2[k * RM_HIDDEN + m];                             // B2 64 x 16
-    default: return m < din ? W1[k * din + m] : 0.0f;                 // B1 K1 x 64
+    case 7: return m < din ? W1[k * din + m] : 0.0f;                  // B1 K1 x 64
+    default: {
+      const float* H = Wh + ((gemm - 8) >> 1) * RM_HH;
+      return (gemm & 1) ? H[k * RM_HIDDEN + m] : H[m * RM_HIDDEN + k];  // Wh_k^T, Wh_k
+    }
   }
 }
 
@@ -828,27 +835,29 @@ __global__ __launch_bounds__(256) void k_pack(StepArgs a, int K1) {
     st->bc2 = (float)(1.0 - pow((double)a.beta2, (double)kk));
   }
   const float* W = (a.params_override ? a.params_override : ob.params) + ob.P_grid;
-  const int din = ob.din;
+  const int din = ob.din, nh = a.mlp_layers;
   const int Ms[8] = {64, 16, 64, 16, 64, 16, 64, K1};
   const int Ks[8] = {K1, 64, 16, 64, 16, 64, 16, 64};
   const int offs[8] = {RM_OFF_F1, RM_OFF_F2, RM_OFF_F3, RM_OFF_F4,
                        RM_OFF_B4, RM_OFF_B3, RM_OFF_B2, RM_OFF_B1};
-  float* o32 = a.wpack32 + (int64_t)blockIdx.x * RM_WPACK;
-  uint16_t* o16 = a.wpack16 + (int64_t)blockIdx.x * RM_WPACK;
+  const int64_t stride = RM_WPACK_NH(nh);
+  float* o32 = a.wpack32 + (int64_t)blockIdx.x * stride;
+  uint16_t* o16 = a.wpack16 + (int64_t)blockIdx.x * stride;
   {  // one operand per block
     const int gm = blockIdx.y;
-    const int M = Ms[gm], K = Ks[gm], Q = K / 16;
+    const int M = gm < 8 ? Ms[gm] : RM_HIDDEN, K = gm < 8 ? Ks[gm] : RM_HIDDEN, Q = K / 16;
+    const int off = gm < 8 ? offs[gm] : RM_OFF_HF(1) + (gm - 8) * RM_HH;
     for (int j = threadIdx.x; j < M * K; j += blockDim.x) {
       {  // FP32 image
         const int lane = j & 63, r = (j >> 6) & 3, tq = j >> 8;
         const int q = tq % Q, t = tq / Q;
-        o32[offs[gm] + j] = mlp_A(W, din, K1, gm, 16 * t + (lane & 15), 16 * q + 4 * (lane >> 4) + r);
+        o32[off + j] = mlp_A(W, din, nh, gm, 16 * t + (lane & 15), 16 * q + 4 * (lane >> 4) + r);
       }
       {  // BF16 image
         const int r = j & 3, lane = (j >> 2) & 63, tq = j >> 8;
         const int q = tq % Q, t = tq / Q;
-        o16[offs[gm] + j] =
-            f2bf(mlp_A(W, din, K1, gm, 16 * t + (lane & 15), 16 * q + 4 * (lane >> 4) + r));
+        o16[off + j] =
+            f2bf(mlp_A(W, din, nh, gm, 16 * t + (lane & 15), 16 * q + 4 * (lane >> 4) + r));
       }
     }
   }
@@ -992,19 +1001,29 @@ __device__ inline void load_e(const float2* e, int64_t S, int64_t s, int L, int 
   }
 }
 
-template <int PREC, int NS, int K1>
-__global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void k_field(StepArgs a) {
+// NH: hidden layers of the density MLP (1, or 2 and 3 for the model-size
+// study); the deeper variants run one wave per SIMD (their 64 x 64 weight
+// gradients are accumulated in registers), and their work-item record shares
+// LDS with the weights, which are no longer read when it is written.
+template <int PREC, int NS, int K1, int NH>
+__global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 1 : 2))) void k_field(StepArgs a) {
   typedef Mma<PREC> MM;
   typedef typename MM::wtype wt;
   constexpr int NB = NS / 16;             // 16-sample blocks per ray
   constexpr int SPL = NS > 64 ? NS / 64 : 1;  // samples per lane in the composite
   constexpr int STG = 64 * MM::STRIDE;    // one staging tile (64 feature rows)
   constexpr int KQ = K1 / 16;
+  constexpr int WP = RM_WPACK_NH(NH);
+  constexpr int RL = RM_REC_LOSS_NH(NH);
+  constexpr int WBYTES = WP * (int)sizeof(wt), RBYTES = (RL + 1) * 4;
+  constexpr bool ALIAS = NH > 1;
 
-  __shared__ __align__(16) wt s_w[RM_WPACK];
+  __shared__ __align__(16) char s_wraw[ALIAS && RBYTES > WBYTES ? RBYTES : WBYTES];
   __shared__ __align__(16) wt s_stage[4][2][STG];
   __shared__ __align__(16) float s_rv[4][NS * 4];
-  __shared__ float s_rec[RM_REC_LOSS + 1];
+  __shared__ float s_rec_own[ALIAS ? 1 : RL + 1];
+  wt* s_w = (wt*)s_wraw;
+  float* s_rec = ALIAS ? (float*)s_wraw : s_rec_own;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, n = lane & 15;
@@ -1017,10 +1036,10 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void
   const int mode = a.mode;
 
   {  // weights of this object into LDS (16-byte copies)
-    const uint4* src = (const uint4*)((PREC ? (const void*)(a.wpack16 + (int64_t)it.so * RM_WPACK)
-                                            : (const void*)(a.wpack32 + (int64_t)it.so * RM_WPACK)));
+    const uint4* src = (const uint4*)((PREC ? (const void*)(a.wpack16 + (int64_t)it.so * WP)
+                                            : (const void*)(a.wpack32 + (int64_t)it.so * WP)));
     uint4* dst = (uint4*)s_w;
-    constexpr int NV = RM_WPACK * (int)sizeof(wt) / 16;
+    constexpr int NV = WP * (int)sizeof(wt) / 16;
     for (int j = tid; j < NV; j += RM_WG) dst[j] = src[j];
   }
   __syncthreads();
@@ -1038,8 +1057,13 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void
   float* rv = s_rv[wave];
 
   floatx4 acc1[4 * KQ], acc2[4], acc3[4], acc4[4];
+  floatx4 accH[NH > 1 ? NH - 1 : 1][16];  // hidden-to-hidden weight gradients
 #pragma unroll
   for (int j = 0; j < 4 * KQ; ++j) acc1[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < (NH > 1 ? NH - 1 : 1); ++k)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) accH[k][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     acc2[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -1067,6 +1091,14 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void
       load_e<K1>(a.e, S, sray + 16 * b + n, L, g, E);
       MM::template gemm<64, K1>(wF1, E, H1, lane);
       relu4(H1, 4);
+#pragma unroll
+      for (int k = 1; k < NH; ++k) {  // deeper density MLP: H1 <- ReLU(Wh_k H1)
+        floatx4 Hn[4];
+        MM::template gemm<64, 64>(s_w + RM_OFF_HF(k), H1, Hn, lane);
+        relu4(Hn, 4);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) H1[f] = Hn[f];
+      }
       MM::template gemm<16, 64>(wF2, H1, Y, lane);
       MM::template gemm<64, 16>(wF3, Y, H2, lane);
       relu4(H2, 4);
@@ -1213,10 +1245,16 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void
     // ---- backward: recompute activations per block, adjoints, dW ----
     for (int b = 0; b < NB; ++b) {
       const int64_t s = sray + 16 * b + n;
-      floatx4 E[KQ], H1[4], Y[1], H2[4];
+      floatx4 E[KQ], HH[NH][4], Y[1], H2[4];
+      floatx4* H1 = HH[NH - 1];  // the last hidden layer of the density MLP
       load_e<K1>(a.e, S, s, L, g, E);
-      MM::template gemm<64, K1>(wF1, E, H1, lane);
-      relu4(H1, 4);
+      MM::template gemm<64, K1>(wF1, E, HH[0], lane);
+      relu4(HH[0], 4);
+#pragma unroll
+      for (int k = 1; k < NH; ++k) {
+        MM::template gemm<64, 64>(s_w + RM_OFF_HF(k), HH[k - 1], HH[k], lane);
+        relu4(HH[k], 4);
+      }
       MM::template gemm<16, 64>(wF2, H1, Y, lane);
       MM::template gemm<64, 16>(wF3, Y, H2, lane);
       relu4(H2, 4);
@@ -1259,7 +1297,23 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void
       for (int f = 0; f < 4; ++f)
 #pragma unroll
         for (int r = 0; r < 4; ++r) dH1[f][r] = H1[f][r] > 0.0f ? dH1[f][r] : 0.0f;
-      // dW1 += dH1^T E, dE = W1^T dH1
+      // deeper density MLP, last layer first: dWh_k += dH^T H_{k-1},
+      // dH <- Wh_k^T dH masked by ReLU
+#pragma unroll
+      for (int k = NH - 1; k >= 1; --k) {
+        MM::stage(gbuf, dH1, 4, lane);
+        MM::stage(xbuf, HH[k - 1], 4, lane);
+        wave_lds_sync();
+        MM::template dw<64, 64>(gbuf, xbuf, accH[k - 1], lane);
+        wave_lds_sync();
+        floatx4 dP[4];
+        MM::template gemm<64, 64>(s_w + RM_OFF_HB(k), dH1, dP, lane);
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dH1[f][r] = HH[k - 1][f][r] > 0.0f ? dP[f][r] : 0.0f;
+      }
+      // dW1 += dH^T E, dE = W1^T dH  (dH of the first hidden layer)
       MM::stage(gbuf, dH1, 4, lane);
       MM::stage(xbuf, E, KQ, lane);
       wave_lds_sync();
@@ -1281,7 +1335,9 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void
   // and float atomics in LDS are slow.  The order is fixed, so the record is
   // deterministic.
   if (mode != RM_MODE_FORWARD) {
-    const int o2 = RM_HIDDEN * din, o3 = o2 + RM_DOUT * RM_HIDDEN, o4 = o3 + RM_HIDDEN * RM_GEO;
+    const int oh = RM_HIDDEN * din, o2 = oh + (NH - 1) * RM_HH, o3 = o2 + RM_DOUT * RM_HIDDEN,
+              o4 = o3 + RM_HIDDEN * RM_GEO;
+    if (ALIAS) __syncthreads();  // the record overwrites the weights: every wave is done
     for (int turn = 0; turn < RM_WG / 64; ++turn) {
       if (wave == turn) {
         const bool first = turn == 0;
@@ -1315,13 +1371,22 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void
               float* d = &s_rec[o4 + row * RM_HIDDEN + 16 * u + n];
               *d = first ? acc4[u][r] : *d + acc4[u][r];
             }
+#pragma unroll
+          for (int k = 0; k < NH - 1; ++k)
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                float* d = &s_rec[oh + k * RM_HH + (16 * tt + row) * RM_HIDDEN + 16 * u + n];
+                *d = first ? accH[k][tt * 4 + u][r] : *d + accH[k][tt * 4 + u][r];
+              }
         }
-        if (lane == 0) s_rec[RM_REC_LOSS] = first ? loss_w : s_rec[RM_REC_LOSS] + loss_w;
+        if (lane == 0) s_rec[RL] = first ? loss_w : s_rec[RL] + loss_w;
       }
       __syncthreads();
     }
-    float* rec = a.partials + (int64_t)blockIdx.x * RM_REC_STRIDE;
-    for (int j = tid; j < RM_REC_LOSS + 1; j += RM_WG) rec[j] = s_rec[j];
+    float* rec = a.partials + (int64_t)blockIdx.x * RM_REC_STRIDE_NH(NH);
+    for (int j = tid; j < RL + 1; j += RM_WG) rec[j] = s_rec[j];
   }
 }
 
@@ -1329,7 +1394,7 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(2))) void
 // K5: per-object MLP gradient and loss from the work-item records, summed in
 // a fixed order (deterministic); in a training step the MLP's Adam update is
 // applied here, else the gradient is written.  A block owns
-// 256 record columns, 4 per lane (column RM_REC_LOSS is the loss); its 16
+// 256 record columns, 4 per lane (column RM_REC_LOSS_NH is the loss); its 16
 // waves sum interleaved sixteenths of the items, then combine in LDS.
 __global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
   __shared__ float4 s_part[16][64];
@@ -1339,23 +1404,24 @@ __global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j0 = blockIdx.x * 256 + 4 * lane;  // 4 columns per lane (the stride is a multiple of 4)
   float4 s0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), s1 = s0;
-  if (j0 < RM_REC_STRIDE) {
+  const int stride = RM_REC_STRIDE_NH(a.mlp_layers), rloss = RM_REC_LOSS_NH(a.mlp_layers);
+  if (j0 < stride) {
     const float* col = a.partials + j0;
     int it = so.item_begin + wave;
     for (; it + 16 < so.item_end; it += 32) {  // two items per lane in flight
-      const float4 x = *(const float4*)(col + (int64_t)it * RM_REC_STRIDE);
-      const float4 y = *(const float4*)(col + (int64_t)(it + 16) * RM_REC_STRIDE);
+      const float4 x = *(const float4*)(col + (int64_t)it * stride);
+      const float4 y = *(const float4*)(col + (int64_t)(it + 16) * stride);
       s0.x += x.x; s0.y += x.y; s0.z += x.z; s0.w += x.w;
       s1.x += y.x; s1.y += y.y; s1.z += y.z; s1.w += y.w;
     }
     if (it < so.item_end) {
-      const float4 x = *(const float4*)(col + (int64_t)it * RM_REC_STRIDE);
+      const float4 x = *(const float4*)(col + (int64_t)it * stride);
       s0.x += x.x; s0.y += x.y; s0.z += x.z; s0.w += x.w;
     }
   }
   s_part[wave][lane] = make_float4(s0.x + s1.x, s0.y + s1.y, s0.z + s1.z, s0.w + s1.w);
   __syncthreads();
-  if (wave != 0 || j0 >= RM_REC_STRIDE) return;
+  if (wave != 0 || j0 >= stride) return;
   float4 t = s_part[0][lane];
 #pragma unroll
   for (int w = 1; w < 16; ++w) {  // fixed order: deterministic
@@ -1375,7 +1441,7 @@ __global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
       } else {
         gdst[o] = tv[c];
       }
-    } else if (j == RM_REC_LOSS && a.mode == RM_MODE_TRAIN) {
+    } else if (j == rloss && a.mode == RM_MODE_TRAIN) {
       ObjState* st = a.state + so.obj;
       st->loss_acc += tv[c];
       st->n_loss += 1;
@@ -1410,12 +1476,32 @@ __device__ inline float density_at(const ObjStatic& ob, const float x[3]) {
     e[2 * l + 1] = ey;
   }
   const float* W1 = ob.params + ob.P_grid;
-  const float* W2 = W1 + RM_HIDDEN * ob.din;
+  const float* Wh = W1 + RM_HIDDEN * ob.din;
+  const float* W2 = Wh + (ob.mlp_layers - 1) * RM_HH;
   float y0 = 0.0f;
-  for (int h = 0; h < RM_HIDDEN; ++h) {
-    float s = 0.0f;
-    for (int k = 0; k < ob.din; ++k) s = fmaf(W1[h * ob.din + k], e[k], s);
-    y0 = fmaf(W2[h], s > 0.0f ? s : 0.0f, y0);
+  if (ob.mlp_layers == 1) {
+    for (int h = 0; h < RM_HIDDEN; ++h) {
+      float s = 0.0f;
+      for (int k = 0; k < ob.din; ++k) s = fmaf(W1[h * ob.din + k], e[k], s);
+      y0 = fmaf(W2[h], s > 0.0f ? s : 0.0f, y0);
+    }
+  } else {  // deeper density MLP: hidden activations in registers
+    float ha[RM_HIDDEN], hb[RM_HIDDEN];
+    for (int h = 0; h < RM_HIDDEN; ++h) {
+      float s = 0.0f;
+      for (int k = 0; k < ob.din; ++k) s = fmaf(W1[h * ob.din + k], e[k], s);
+      ha[h] = s > 0.0f ? s : 0.0f;
+    }
+    for (int k = 1; k < ob.mlp_layers; ++k) {
+      const float* H = Wh + (k - 1) * RM_HH;
+      for (int h = 0; h < RM_HIDDEN; ++h) {
+        float s = 0.0f;
+        for (int j = 0; j < RM_HIDDEN; ++j) s = fmaf(H[h * RM_HIDDEN + j], ha[j], s);
+        hb[h] = s > 0.0f ? s : 0.0f;
+      }
+      for (int h = 0; h < RM_HIDDEN; ++h) ha[h] = hb[h];
+    }
+    for (int h = 0; h < RM_HIDDEN; ++h) y0 = fmaf(W2[h], ha[h], y0);
   }
   return expf(fminf(y0, 15.0f));
 }
@@ -1601,9 +1687,10 @@ __global__ __launch_bounds__(256) void k_debug_encode(const ObjStatic* objs, int
 // parameter initialisation: grid U(-1e-4, 1e-4), MLP Glorot-uniform, each
 // value drawn from Philox with counter (index, kind, 0xFFFFFFFF, 0)
 __global__ __launch_bounds__(256) void k_init_params(float* params, int64_t P_grid, int din,
-                                                     uint32_t k0, uint32_t k1) {
+                                                     int nh, uint32_t k0, uint32_t k1) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n1 = (int64_t)RM_HIDDEN * din, n2 = n1 + RM_DOUT * RM_HIDDEN;
+  const int64_t n1 = (int64_t)RM_HIDDEN * din, nhh = n1 + (int64_t)(nh - 1) * RM_HH;
+  const int64_t n2 = nhh + RM_DOUT * RM_HIDDEN;
   const int64_t n3 = n2 + RM_HIDDEN * RM_GEO, n4 = n3 + 3 * RM_HIDDEN;
   if (i >= P_grid + n4) return;
   uint32_t kind;
@@ -1614,6 +1701,7 @@ __global__ __launch_bounds__(256) void k_init_params(float* params, int64_t P_gr
   } else {
     const int64_t j = i - P_grid;
     if (j < n1) { kind = 1u; lim = sqrtf(6.0f / (float)(RM_HIDDEN + din)); }
+    else if (j < nhh) { kind = 5u; lim = sqrtf(6.0f / (float)(2 * RM_HIDDEN)); }
     else if (j < n2) { kind = 2u; lim = sqrtf(6.0f / (float)(RM_DOUT + RM_HIDDEN)); }
     else if (j < n3) { kind = 3u; lim = sqrtf(6.0f / (float)(RM_HIDDEN + RM_GEO)); }
     else { kind = 4u; lim = sqrtf(6.0f / (float)(3 + RM_HIDDEN)); }
@@ -1741,27 +1829,40 @@ hipError_t rm_launch_bin_acc(const StepArgs& a, const BinGroup& g, hipStream_t s
 
 hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
-  k_pack<<<dim3(a.n_sobj, 8), 256, 0, st>>>(a, K1);
+  if (a.mlp_layers < 1 || a.mlp_layers > RM_MAX_MLP_LAYERS) return hipErrorInvalidValue;
+  k_pack<<<dim3(a.n_sobj, 8 + 2 * (a.mlp_layers - 1)), 256, 0, st>>>(a, K1);
   return hipGetLastError();
 }
 
-template <int PREC, int K1>
+template <int PREC, int K1, int NH>
 static hipError_t launch_field_k(const StepArgs& a, int NS, hipStream_t st) {
-  RM_NS_SWITCH(NS, (k_field<PREC, NSC, K1><<<a.n_items, RM_WG, 0, st>>>(a)));
+  RM_NS_SWITCH(NS, (k_field<PREC, NSC, K1, NH><<<a.n_items, RM_WG, 0, st>>>(a)));
   return hipGetLastError();
+}
+
+template <int NH>
+static hipError_t launch_field_nh(const StepArgs& a, int NS, int K1, int prec, hipStream_t st) {
+  if (K1 == 16)
+    return prec ? launch_field_k<1, 16, NH>(a, NS, st) : launch_field_k<0, 16, NH>(a, NS, st);
+  if (K1 == 32)
+    return prec ? launch_field_k<1, 32, NH>(a, NS, st) : launch_field_k<0, 32, NH>(a, NS, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStream_t st) {
   if (a.n_items <= 0) return hipSuccess;
-  if (K1 == 16) return prec ? launch_field_k<1, 16>(a, NS, st) : launch_field_k<0, 16>(a, NS, st);
-  if (K1 == 32) return prec ? launch_field_k<1, 32>(a, NS, st) : launch_field_k<0, 32>(a, NS, st);
-  return hipErrorInvalidValue;
+  switch (a.mlp_layers) {
+    case 1: return launch_field_nh<1>(a, NS, K1, prec, st);
+    case 2: return launch_field_nh<2>(a, NS, K1, prec, st);
+    case 3: return launch_field_nh<3>(a, NS, K1, prec, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
   (void)n_mlp_max;
-  dim3 grid(cdiv(RM_REC_LOSS + 1, 256), a.n_sobj);
+  dim3 grid(cdiv(RM_REC_LOSS_NH(a.mlp_layers) + 1, 256), a.n_sobj);
   k_reduce<<<grid, 1024, 0, st>>>(a);
   return hipGetLastError();
 }
@@ -1834,11 +1935,11 @@ hipError_t rm_launch_debug_encode(const ObjStatic* objs, int obj, const float* p
   return hipGetLastError();
 }
 
-hipError_t rm_launch_init(float* params, int64_t P_grid, int din, uint32_t k0, uint32_t k1,
-                          hipStream_t st) {
-  const int64_t n = P_grid + (int64_t)RM_HIDDEN * din + RM_DOUT * RM_HIDDEN + RM_HIDDEN * RM_GEO +
-                    3 * RM_HIDDEN;
-  k_init_params<<<cdiv(n, 256), 256, 0, st>>>(params, P_grid, din, k0, k1);
+hipError_t rm_launch_init(float* params, int64_t P_grid, int din, int nh, uint32_t k0,
+                          uint32_t k1, hipStream_t st) {
+  const int64_t n = P_grid + (int64_t)RM_HIDDEN * din + (int64_t)(nh - 1) * RM_HH +
+                    RM_DOUT * RM_HIDDEN + RM_HIDDEN * RM_GEO + 3 * RM_HIDDEN;
+  k_init_params<<<cdiv(n, 256), 256, 0, st>>>(params, P_grid, din, nh, k0, k1);
   return hipGetLastError();
 }
 

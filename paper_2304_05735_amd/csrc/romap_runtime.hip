@@ -34,7 +34,7 @@ struct HostKf {
 struct HostObj {
   int id = 0, instance = 0, log2T = 0, active = 1;
   romap_box box{};
-  int L = 0, din = 0;
+  int L = 0, din = 0, mlp_layers = 1;
   int64_t P = 0, P_grid = 0, P_alloc = 0;
   int64_t off[RM_MAX_LEVELS + 1]{};
   uint32_t N_l[RM_MAX_LEVELS]{}, T_l[RM_MAX_LEVELS]{};
@@ -194,7 +194,9 @@ void make_levels(const romap_config& cfg, int log2T, HostObj& o) {
   o.L = L;
   o.din = 2 * L;
   o.P_grid = off;
-  o.P = off + (int64_t)RM_HIDDEN * o.din + RM_DOUT * RM_HIDDEN + RM_HIDDEN * RM_GEO + 3 * RM_HIDDEN;
+  o.mlp_layers = cfg.mlp_layers;
+  o.P = off + (int64_t)RM_HIDDEN * o.din + (int64_t)(o.mlp_layers - 1) * RM_HH +
+        RM_DOUT * RM_HIDDEN + RM_HIDDEN * RM_GEO + 3 * RM_HIDDEN;
   o.P_alloc = (o.P + 63) / 64 * 64;
 }
 
@@ -233,6 +235,7 @@ ObjStatic to_static(const HostObj& o) {
   s.hashed_mask = o.hashed_mask;
   s.L = o.L;
   s.din = o.din;
+  s.mlp_layers = o.mlp_layers;
   s.instance = o.instance;
   s.id = o.id;
   s.n_kf = (int)o.kfs.size();
@@ -285,6 +288,7 @@ StepArgs base_args(romap_ctx* c) {
   a.beta2 = c->cfg.beta2;
   a.eps = c->cfg.eps;
   a.mode = RM_MODE_TRAIN;
+  a.mlp_layers = c->cfg.mlp_layers;
   return a;
 }
 
@@ -423,9 +427,11 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
   HIPALLOC(c, regrow(&c->d_rays, &c->cap_rays, std::max<size_t>(max_rays, 1)));
   HIPALLOC(c, regrow(&c->d_e, &c->cap_e, std::max<size_t>(L * (size_t)max_S, 1)));
   HIPALLOC(c, regrow(&c->d_de, &c->cap_de, std::max<size_t>(L * (size_t)max_S, 1)));
-  HIPALLOC(c, regrow(&c->d_partials, &c->cap_partials, std::max<size_t>(max_items * RM_REC_STRIDE, 1)));
-  HIPALLOC(c, regrow(&c->d_wpack32, &c->cap_w32, std::max<size_t>(max_sobj * RM_WPACK, 1)));
-  HIPALLOC(c, regrow(&c->d_wpack16, &c->cap_w16, std::max<size_t>(max_sobj * RM_WPACK, 1)));
+  const size_t nh = (size_t)c->cfg.mlp_layers;
+  HIPALLOC(c, regrow(&c->d_partials, &c->cap_partials,
+                     std::max<size_t>(max_items * RM_REC_STRIDE_NH(nh), 1)));
+  HIPALLOC(c, regrow(&c->d_wpack32, &c->cap_w32, std::max<size_t>(max_sobj * RM_WPACK_NH(nh), 1)));
+  HIPALLOC(c, regrow(&c->d_wpack16, &c->cap_w16, std::max<size_t>(max_sobj * RM_WPACK_NH(nh), 1)));
   HIPALLOC(c, regrow(&c->d_tables, &c->cap_tables, std::max<size_t>(tab, 256)));
   HIPALLOC(c, regrow(&c->d_bin_count, &c->cap_bin_count, std::max<size_t>(max_bins, 1)));
   HIPALLOC(c, regrow(&c->d_rec_idx, &c->cap_rec_idx, std::max<size_t>(max_rec, 1)));
@@ -714,6 +720,7 @@ romap_status romap_default_config(romap_config* cfg) {
   cfg->use_graph = 1;
   cfg->autotune = 1;
   cfg->profile_phases = 0;
+  cfg->mlp_layers = 1;
   cfg->seed = 0;
   return ROMAP_OK;
 }
@@ -732,6 +739,8 @@ romap_status romap_create(const romap_config* cfg, void* hip_stream, romap_ctx**
     return fail(nullptr, ROMAP_E_INVALID_ARG, "log2_table_size must be 8..24");
   if (k.samples_per_ray != 32 && k.samples_per_ray != 64 && k.samples_per_ray != 128)
     return fail(nullptr, ROMAP_E_INVALID_ARG, "samples_per_ray must be 32, 64 or 128");
+  if (k.mlp_layers < 1 || k.mlp_layers > RM_MAX_MLP_LAYERS)
+    return fail(nullptr, ROMAP_E_INVALID_ARG, "mlp_layers must be 1..3");
   if (k.rays_per_step <= 0 || k.rays_per_step > (1 << 22))
     return fail(nullptr, ROMAP_E_INVALID_ARG, "bad rays_per_step");
   if (!(k.lr > 0.0f) || !(k.beta1 >= 0.0f && k.beta1 < 1.0f) || !(k.beta2 >= 0.0f && k.beta2 < 1.0f) ||
@@ -873,7 +882,8 @@ romap_status romap_add_object(romap_ctx* c, int32_t instance_id, const romap_box
   HIPALLOC(c, hipMalloc((void**)&o.d_block, 4 * (size_t)o.P_alloc * sizeof(float)));
   hipError_t e = hipMemsetAsync(o.d_block, 0, 4 * (size_t)o.P_alloc * sizeof(float), c->stream);
   if (e == hipSuccess)
-    e = rm_launch_init(o.d_block, o.P_grid, o.din, (uint32_t)c->cfg.seed ^ (uint32_t)o.id,
+    e = rm_launch_init(o.d_block, o.P_grid, o.din, o.mlp_layers,
+                       (uint32_t)c->cfg.seed ^ (uint32_t)o.id,
                        (uint32_t)(c->cfg.seed >> 32), c->stream);
   ObjState st0{};
   st0.bc1 = 1.0f;
@@ -1875,7 +1885,7 @@ romap_status romap_field_backward(romap_ctx* c, int32_t id, const float* params_
 }
 
 // ---- checkpoint -------------------------------------------------------------
-static const char kMagic[8] = {'R', 'O', 'M', 'A', 'P', 'C', 'K', '1'};
+static const char kMagic[8] = {'R', 'O', 'M', 'A', 'P', 'C', 'K', '2'};
 
 romap_status romap_save(romap_ctx* c, const char* path) {
   if (!c) return ROMAP_E_INVALID_ARG;
@@ -1952,7 +1962,7 @@ romap_status romap_load(romap_ctx* c, const char* path) {
     return fail(c, ROMAP_E_INVALID_ARG, "not a checkpoint");
   }
   if (cfg.n_levels != c->cfg.n_levels || cfg.base_res != c->cfg.base_res || cfg.max_res != c->cfg.max_res ||
-      cfg.samples_per_ray != c->cfg.samples_per_ray) {
+      cfg.samples_per_ray != c->cfg.samples_per_ray || cfg.mlp_layers != c->cfg.mlp_layers) {
     std::fclose(f);
     return fail(c, ROMAP_E_INVALID_ARG, "checkpoint model config differs from the context");
   }

@@ -12,7 +12,8 @@ depends on a discrete decision (ReLU branch, density clamp, depth-error sign)
 that lies within 1e-5 relative of its tie, FP32 and FP64 may both be right
 and disagree: such entries may further differ by the oracle's allowance (the
 tie samples' contributions with every branch taken); everything else must
-match to the bound above.
+match to the bound above, and the norm-wise bound is taken over the entries
+that no such decision reaches.
 """
 import numpy as np
 
@@ -36,23 +37,28 @@ def assert_grad_close(gpu, ref, mass, allow=None, rtol=1e-4, mtol=1e-4, what="")
     allow = np.zeros_like(ref) if allow is None else np.asarray(allow, np.float64)
     d = gpu - ref
     nr = np.linalg.norm(ref)
-    assert np.linalg.norm(d) <= rtol * nr + 1e-30, (what, np.linalg.norm(d) / max(nr, 1e-30))
+    # norm-wise over the entries no tied decision reaches (those are bounded
+    # one by one below, by their allowance)
+    clean = allow == 0
+    assert np.linalg.norm(d[clean]) <= rtol * nr + 1e-30, (
+        what, np.linalg.norm(d[clean]) / max(nr, 1e-30))
     bad = np.abs(d) > rtol * np.abs(ref) + mtol * mass + allow
     assert not bad.any(), (what, int(bad.sum()), float(np.abs(d).max()), np.flatnonzero(bad)[:5])
     return float(np.linalg.norm(d) / max(nr, 1e-30))
 
 
-def make_pair(L, nmin, nmax, log2T, N, B, frames, box, precision=pk.PREC_FP32, **kw):
+def make_pair(L, nmin, nmax, log2T, N, B, frames, box, precision=pk.PREC_FP32, mlp_layers=1,
+              **kw):
     """A GPU context and an oracle context holding the same object and keyframes."""
     cfg = pk.default_config(n_levels=L, base_res=nmin, max_res=nmax, log2_table_size=log2T,
                             samples_per_ray=N, rays_per_step=B, autotune=0,
-                            precision=precision, **kw)
+                            precision=precision, mlp_layers=mlp_layers, **kw)
     g = pk.Context(cfg)
     ocfg = oracle.make_config(L=L, nmin=nmin, nmax=nmax, log2T=log2T, N=N,
                               lambda_depth=float(cfg.lambda_depth),
                               lambda_density=float(cfg.lambda_density), lr=float(cfg.lr),
                               beta1=float(cfg.beta1), beta2=float(cfg.beta2), eps=float(cfg.eps))
-    o = oracle.OracleContext(ocfg)
+    o = oracle.OracleContext(ocfg, mlp_layers=mlp_layers)
     gid = g.add_object(box["instance"], box["t"], box["yaw"], box["half"])
     oid = o.add_object(box["instance"], box["t"], box["yaw"], box["half"])
     assert gid == oid
