@@ -384,6 +384,27 @@ def pmc_summary(d, workload, steps):
     log("wrote", path)
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (GB/s, bytes read + written) of a plain
+    tensor copy: the achievable HBM bandwidth the roofline is also quoted
+    against (besides the datasheet peak)."""
+    import torch
+    src = torch.ones(nbytes // 4, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def traffic_of(workload, kernels):
     """Calibrated HBM bytes per step of the given kernels from the committed
     counter summary, or None if it is missing or the kernels changed since."""
@@ -510,9 +531,12 @@ def main():
     byt = algorithmic_bytes(pctx, ids, rays, dominant)
     achieved = byt / (phases[dominant] * 1e-3) / 1e9 if phases[dominant] > 0 else 0.0
     traffic = traffic_of(args.workload, PHASE_KERNELS[dominant])
+    copy_gbs = copy_bandwidth()
+    log(f"copy bandwidth {copy_gbs:.0f} GB/s")
     roofline = dict(bound="hbm", kernel=dominant, kernels=PHASE_KERNELS[dominant],
                     achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    copy_gbs=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4),
                     traffic=None if traffic is None else int(traffic),
                     avg_ms=round(phases[dominant], 5), algorithmic_bytes=int(byt),
                     phase_ms={k: round(v, 5) for k, v in phases.items()})
