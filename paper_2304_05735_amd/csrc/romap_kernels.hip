@@ -355,23 +355,26 @@ __device__ inline bool ray_active(uint32_t flags) {
 }
 
 // ---------------------------------------------------------------------------
-// K2: encoding forward.  One block per RM_SCAT_WG samples of one (object,
-// level) pair, blocks ordered object by object and level by level within an
-// object, so the chip sweeps one table at a time; the object and level are
-// uniform in a block.  blockDim threads cover the block's samples.
+// K2: encoding forward.  RM_ENC_SPLIT workgroups per block of RM_SCAT_WG
+// samples of one (object, level) pair, blocks ordered object by object and
+// level by level within an object, so the chip sweeps one table at a time;
+// the object and level are uniform in a workgroup.  blockDim threads cover
+// the workgroup's samples.
 template <int NS>
 __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t j = gtid; j < a.n_regions; j += (int64_t)gridDim.x * blockDim.x)
     a.bin_count[j] = 0;  // fresh fill counters for the binned scatter of this pass
-  const BinBlock bb = a.bblocks[blockIdx.x];
+  const BinBlock bb = a.bblocks[blockIdx.x / RM_ENC_SPLIT];
+  constexpr int SPAN = RM_SCAT_WG / RM_ENC_SPLIT;  // samples of this workgroup
+  const int k0 = (int)(blockIdx.x % RM_ENC_SPLIT) * SPAN;
   const BinPair bp = a.bpairs[bb.pair];
   const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
   const int l = bp.l;
   const uint32_t N = ob.N_l[l], T = ob.T_l[l];
   const bool hashed = (ob.hashed_mask >> l) & 1u;
   const float* G = (a.params_override ? a.params_override : ob.params) + ob.off[l];
-  for (int k = threadIdx.x; k < RM_SCAT_WG; k += blockDim.x) {
+  for (int k = k0 + threadIdx.x; k < k0 + SPAN; k += blockDim.x) {
     const int64_t ks = (int64_t)bb.blk * RM_SCAT_WG + k;
     if (ks >= bp.n_samples) break;
     const int64_t s = bp.s_begin + ks;
@@ -1807,7 +1810,7 @@ hipError_t rm_launch_raygen(const StepArgs& a, int NS, hipStream_t st) {
 
 hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int block, hipStream_t st) {
   if (a.n_bblocks <= 0) return hipSuccess;
-  RM_NS_SWITCH(NS, (k_encode_fwd<NSC><<<a.n_bblocks, block, 0, st>>>(a)));
+  RM_NS_SWITCH(NS, (k_encode_fwd<NSC><<<a.n_bblocks * RM_ENC_SPLIT, block, 0, st>>>(a)));
   return hipGetLastError();
 }
 
