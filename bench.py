@@ -69,8 +69,9 @@ def run_stream(wl, args):
     """Incremental mapping stream: keyframes arrive one by one (25 Hz in the
     scene's timeline); an object is registered on the first frame where its
     mask has >= 200 pixels; objects seen in the last 50 frames are active;
-    each frame trains every active object for 3 steps of 2^16 rays in total,
-    split in proportion to the mask pixels seen so far (at least 64 each), with
+    each frame trains every active object for 4 steps of 2^16 rays in total
+    (2^18 rays per frame), split in proportion to the mask pixels seen so far
+    (at least 64 each), with
     the BF16 MLP and 128 samples per ray; the occupancy bitfield of an object
     is refreshed every 25 frames once it has trained for 25 frames."""
     import numpy as np
@@ -81,7 +82,7 @@ def run_stream(wl, args):
     ctx = pk.Context(cfg)
     spec = {o.instance: o for o in wl.objects}
     oid_of, first, last_seen, pix, has_kf = {}, {}, {}, {}, {}
-    budget, steps_per_frame = 1 << 16, 3
+    budget, steps_per_frame = 1 << 16, 4
     frame_ms, train_ms, psnr_log = [], [], []
     rays_trained = 0
     for f, (cam, rgb, mask, depth) in enumerate(wl.frames):
