@@ -1024,6 +1024,10 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
   constexpr int SPL = NS > 64 ? NS / 64 : 1;  // samples per lane in the composite
   constexpr int STG = 64 * MM::STRIDE;    // one staging tile (64 feature rows)
   constexpr int KQ = K1 / 16;
+  // a ray's encodings stay in registers from the forward to the backward
+  // pass when they fit (NS <= 64), else the backward reads them again
+  constexpr bool KEEP_E = NB * KQ <= 8;
+  constexpr int NBK = KEEP_E ? NB : 1;
   constexpr int WP = RM_WPACK_NH(NH);
   constexpr int RL = RM_REC_LOSS_NH(NH);
   constexpr int WBYTES = WP * (int)sizeof(wt), RBYTES = (RL + 1) * 4;
@@ -1097,9 +1101,15 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
     const int64_t sray = (int64_t)ray * NS;
 
     // ---- forward: sigma, colour of every sample ----
+    floatx4 EK[NBK][KQ];
+#pragma unroll
     for (int b = 0; b < NB; ++b) {
       floatx4 E[KQ], H1[4], Y[1], H2[4], Z[1];
       load_e<K1>(a.e, S, sray + 16 * b + n, L, g, E);
+      if (KEEP_E) {
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) EK[KEEP_E ? b : 0][q] = E[q];
+      }
       MM::template gemm<64, K1>(wF1, E, H1, lane);
       relu4(H1, 4);
 #pragma unroll
@@ -1254,11 +1264,17 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
     wave_lds_sync();
 
     // ---- backward: recompute activations per block, adjoints, dW ----
+#pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int64_t s = sray + 16 * b + n;
       floatx4 E[KQ], HH[NH][4], Y[1], H2[4];
       floatx4* H1 = HH[NH - 1];  // the last hidden layer of the density MLP
-      load_e<K1>(a.e, S, s, L, g, E);
+      if (KEEP_E) {
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) E[q] = EK[KEEP_E ? b : 0][q];
+      } else {
+        load_e<K1>(a.e, S, s, L, g, E);
+      }
       MM::template gemm<64, K1>(wF1, E, HH[0], lane);
       relu4(HH[0], 4);
 #pragma unroll
