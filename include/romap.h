@@ -88,6 +88,13 @@ typedef struct {
                                               MLP: 1 (Sec. V), 2 or 3 (the model-size
                                               study of Table 4).  The extra 64 x 64
                                               matrices follow W1 in the parameters */
+  int32_t streams;                         /* 2 (default): a batched training step of
+                                              two or more objects runs as two groups of
+                                              objects (about 3/4 and 1/4 of the work)
+                                              on two streams (the context stream and
+                                              one of the library's, joined back after
+                                              every step), so that their phases
+                                              overlap; 1: one stream */
   uint64_t seed;
 } romap_config;
 

@@ -40,7 +40,8 @@ class romap_config(C.Structure):
                 ("lambda_density", C.c_float), ("alpha_deg", C.c_float),
                 ("bbox_margin_pct", C.c_int32), ("precision", C.c_int32),
                 ("batch_mode", C.c_int32), ("use_graph", C.c_int32), ("autotune", C.c_int32),
-                ("profile_phases", C.c_int32), ("mlp_layers", C.c_int32), ("seed", C.c_uint64)]
+                ("profile_phases", C.c_int32), ("mlp_layers", C.c_int32), ("streams", C.c_int32),
+                ("seed", C.c_uint64)]
 
 
 class romap_box(C.Structure):

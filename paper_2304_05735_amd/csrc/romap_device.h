@@ -25,6 +25,13 @@
 #define RM_WG 256           /* threads of the fused field kernel (4 waves) */
 #define RM_FIN_WG 512       /* entries per workgroup of the finishing kernel */
 #define RM_GRAPH_MIN_STEPS 8 /* steps of a romap_train call that repay a graph capture */
+// Work share of the first half of a two-stream step.  Uneven halves overlap
+// different phases of the two (gathers of one with the MLP of the other);
+// measured on 24 objects, ms per step: 0.5 2.203, 0.6 2.193, 0.7 2.180,
+// 0.75 2.175, 0.8 2.193, 0.85 2.186 (one stream: 2.233).
+#ifndef RM_SPLIT_SHARE
+#define RM_SPLIT_SHARE 0.75
+#endif
 #ifndef RM_MERGE_NUM         /* merge same-cell sample runs where N_l <= NUM/DEN * samples */
 #define RM_MERGE_NUM 1       /* 1/2, 3/4, 1: 2.37, 2.33, 2.33 ms per step, 24 objects x 64 samples */
 #define RM_MERGE_DEN 1
@@ -224,7 +231,7 @@ hipError_t rm_launch_bin_scatter(const StepArgs& a, const BinGroup& g, int NS, h
 hipError_t rm_launch_bin_acc(const StepArgs& a, const BinGroup& g, hipStream_t st);
 hipError_t rm_launch_pack(const StepArgs& a, int K1, hipStream_t st);
 hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStream_t st);
-hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st);
+hipError_t rm_launch_reduce(const StepArgs& a, hipStream_t st);
 hipError_t rm_launch_bin_finish(const StepArgs& a, hipStream_t st);
 hipError_t rm_launch_camera_rays(const StepArgs& a, int NS, const float* M, const float* c,
                                  float fx, float fy, float cx, float cy, int W, int pix0,

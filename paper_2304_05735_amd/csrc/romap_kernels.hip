@@ -1887,9 +1887,8 @@ hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStrea
   }
 }
 
-hipError_t rm_launch_reduce(const StepArgs& a, int n_mlp_max, hipStream_t st) {
+hipError_t rm_launch_reduce(const StepArgs& a, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
-  (void)n_mlp_max;
   dim3 grid(cdiv(RM_REC_LOSS_NH(a.mlp_layers) + 1, 256), a.n_sobj);
   k_reduce<<<grid, 1024, 0, st>>>(a);
   return hipGetLastError();

@@ -70,6 +70,9 @@ struct Plan {                 // one launch: its objects, rays and work lists
   int enc_block = 256;
   size_t off_sobj = 0, off_items = 0, off_fins = 0;  // in the device table arena (bytes)
   size_t off_bpairs = 0, off_bblocks = 0, off_bins = 0;
+  // start of the plan's share of each scratch buffer (elements); nonzero for
+  // the second of two plans whose steps run at the same time
+  size_t so_rays = 0, so_e = 0, so_partials = 0, so_wpack = 0, so_bins = 0, so_rec = 0;
 };
 
 template <class T>
@@ -95,6 +98,8 @@ struct romap_ctx {
   int debug_bin_cap = 0;  // romap_debug_bin_capacity (0: sized capacity)
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t stream2 = nullptr;   // second half of a split batched step
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // meshing: case tables (device) and scratch
   uint8_t* d_mc = nullptr;   // tris [256*16] int8 | ntri [256] | edge_a [12] | edge_b [12]
   float* d_mgrid = nullptr;
@@ -389,15 +394,36 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Makes sure the scratch buffers fit a set of plans, then uploads their
-// work tables into the table arena.
-romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
+// work tables into the table arena.  Plans that run one after another share
+// the scratch buffers; concurrent plans each get their own share of them.
+romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans, bool concurrent = false) {
   size_t max_rays = 0, max_items = 0, max_sobj = 0, tab = 0, max_rec = 0, max_bins = 0;
   int64_t max_S = 0;
+  const size_t L = (size_t)c->cfg.n_levels;
+  const size_t nh = (size_t)c->cfg.mlp_layers;
   for (Plan* p : plans) {
-    max_rays = std::max(max_rays, (size_t)p->n_rays);
-    max_items = std::max(max_items, p->items.size());
-    max_sobj = std::max(max_sobj, p->sobj.size());
-    max_S = std::max(max_S, p->S);
+    if (concurrent) {
+      p->so_rays = max_rays;
+      p->so_e = L * (size_t)max_S;
+      p->so_partials = max_items * RM_REC_STRIDE_NH(nh);
+      p->so_wpack = max_sobj * RM_WPACK_NH(nh);
+      p->so_bins = max_bins;
+      p->so_rec = max_rec;  // a multiple of 4: the bins' vector loads stay aligned
+      max_rays += (size_t)p->n_rays;
+      max_items += p->items.size();
+      max_sobj += p->sobj.size();
+      max_S += p->S;
+      max_rec += (size_t)p->rec_size;
+      max_bins += (size_t)p->bin_regions;
+    } else {
+      p->so_rays = p->so_e = p->so_partials = p->so_wpack = p->so_bins = p->so_rec = 0;
+      max_rays = std::max(max_rays, (size_t)p->n_rays);
+      max_items = std::max(max_items, p->items.size());
+      max_sobj = std::max(max_sobj, p->sobj.size());
+      max_S = std::max(max_S, p->S);
+      max_rec = std::max(max_rec, (size_t)p->rec_size);
+      max_bins = std::max(max_bins, (size_t)p->bin_regions);
+    }
     p->off_sobj = tab;
     tab += align256(p->sobj.size() * sizeof(StepObj));
     p->off_items = tab;
@@ -410,10 +436,7 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
     tab += align256(p->bblocks.size() * sizeof(BinBlock));
     p->off_bins = tab;
     tab += align256(p->bins.size() * sizeof(Bin));
-    max_rec = std::max(max_rec, (size_t)p->rec_size);
-    max_bins = std::max(max_bins, (size_t)p->bin_regions);
   }
-  const size_t L = (size_t)c->cfg.n_levels;
   auto regrow = [&](auto** ptr, size_t* cap, size_t need) -> hipError_t {
     if (need <= *cap) return hipSuccess;
     // a reallocation invalidates the captured graph
@@ -427,7 +450,6 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans) {
   HIPALLOC(c, regrow(&c->d_rays, &c->cap_rays, std::max<size_t>(max_rays, 1)));
   HIPALLOC(c, regrow(&c->d_e, &c->cap_e, std::max<size_t>(L * (size_t)max_S, 1)));
   HIPALLOC(c, regrow(&c->d_de, &c->cap_de, std::max<size_t>(L * (size_t)max_S, 1)));
-  const size_t nh = (size_t)c->cfg.mlp_layers;
   HIPALLOC(c, regrow(&c->d_partials, &c->cap_partials,
                      std::max<size_t>(max_items * RM_REC_STRIDE_NH(nh), 1)));
   HIPALLOC(c, regrow(&c->d_wpack32, &c->cap_w32, std::max<size_t>(max_sobj * RM_WPACK_NH(nh), 1)));
@@ -466,9 +488,15 @@ StepArgs plan_args(romap_ctx* c, const Plan& p) {
   a.n_bblocks = (int)p.bblocks.size();
   a.bins = (const Bin*)(c->d_tables + p.off_bins);
   a.n_bins = (int)p.bins.size();
-  a.bin_count = c->d_bin_count;
-  a.rec_idx = c->d_rec_idx;
-  a.rec_val = c->d_rec_val;
+  a.rays = c->d_rays + p.so_rays;
+  a.e = c->d_e + p.so_e;
+  a.de = c->d_de + p.so_e;
+  a.partials = c->d_partials + p.so_partials;
+  a.wpack32 = c->d_wpack32 + p.so_wpack;
+  a.wpack16 = c->d_wpack16 + p.so_wpack;
+  a.bin_count = c->d_bin_count + p.so_bins;
+  a.rec_idx = c->d_rec_idx + p.so_rec;
+  a.rec_val = c->d_rec_val + p.so_rec;
   a.n_regions = (int)p.bin_regions;
   a.bin_max_R = 0;
   for (const BinPair& bp : p.bpairs) a.bin_max_R = std::max(a.bin_max_R, bp.R);
@@ -492,34 +520,78 @@ hipError_t mark_phase(romap_ctx* c, int ph) {
 }
 
 hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a0, bool adam,
-                        bool prof = false) {
+                        bool prof = false, hipStream_t st = nullptr) {
   const int NS = c->cfg.samples_per_ray, K1 = K1_of(c->cfg);
+  if (!st) st = c->stream;
   StepArgs a = a0;
   a.fuse_adam = adam ? 1 : 0;
   hipError_t e;
 #define RM_MARK(ph) \
   if (prof && (e = mark_phase(c, ph)) != hipSuccess) return e;
   RM_MARK(-1);
-  if ((e = rm_launch_raygen(a, NS, c->stream)) != hipSuccess) return e;
+  if ((e = rm_launch_raygen(a, NS, st)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_RAYGEN);
-  if ((e = rm_launch_encode_fwd(a, NS, p.enc_block, c->stream)) != hipSuccess) return e;
+  if ((e = rm_launch_encode_fwd(a, NS, p.enc_block, st)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_ENCODE);
-  if ((e = rm_launch_pack(a, K1, c->stream)) != hipSuccess) return e;
+  if ((e = rm_launch_pack(a, K1, st)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_PACK);
-  if ((e = rm_launch_field(a, NS, K1, c->cfg.precision, c->stream)) != hipSuccess) return e;
+  if ((e = rm_launch_field(a, NS, K1, c->cfg.precision, st)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_FIELD);
-  if ((e = rm_launch_reduce(a, RM_MLP_MAX, c->stream)) != hipSuccess) return e;
+  if ((e = rm_launch_reduce(a, st)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_REDUCE);
   for (const BinGroup& g : p.bgroups) {
-    if ((e = rm_launch_bin_scatter(a, g, NS, c->stream)) != hipSuccess) return e;
+    if ((e = rm_launch_bin_scatter(a, g, NS, st)) != hipSuccess) return e;
     RM_MARK(ROMAP_PHASE_BIN_SCATTER);
-    if ((e = rm_launch_bin_acc(a, g, c->stream)) != hipSuccess) return e;
+    if ((e = rm_launch_bin_acc(a, g, st)) != hipSuccess) return e;
     RM_MARK(ROMAP_PHASE_BIN_ACC);
   }
-  if ((e = rm_launch_bin_finish(a, c->stream)) != hipSuccess) return e;
+  if ((e = rm_launch_bin_finish(a, st)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_BIN_FINISH);
 #undef RM_MARK
   return hipSuccess;
+}
+
+// One step of two plans at the same time: the second on the context's second
+// stream, forked from and joined back into the context stream (also under
+// graph capture).  Their objects differ and each has its own scratch, so the
+// two only share the device (bandwidth-bound phases of one overlap
+// latency-bound phases of the other).
+hipError_t enqueue_pair(romap_ctx* c, const Plan* p, const StepArgs* a) {
+  hipError_t e;
+  if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(c->stream2, c->ev_fork, 0)) != hipSuccess) return e;
+  if ((e = enqueue_step(c, p[1], a[1], true, false, c->stream2)) != hipSuccess) return e;
+  if ((e = enqueue_step(c, p[0], a[0], true, false, c->stream)) != hipSuccess) return e;
+  if ((e = hipEventRecord(c->ev_join, c->stream2)) != hipSuccess) return e;
+  return hipStreamWaitEvent(c->stream, c->ev_join, 0);
+}
+
+// Splits a batched step's objects in two groups whose work (rays x samples x
+// levels of gathers, records and MLP, plus the table's Adam bytes) is about
+// RM_SPLIT_SHARE and the rest; each group keeps the list order.
+void split_list(romap_ctx* c, const std::vector<std::pair<int, int>>& list,
+                std::vector<std::pair<int, int>> half[2]) {
+  const double per_sample = 200.0 * c->cfg.n_levels;  // bytes moved per sample (about)
+  std::vector<std::pair<double, size_t>> cost;
+  for (size_t i = 0; i < list.size(); ++i) {
+    const HostObj& o = c->objs[list[i].first];
+    cost.push_back({(double)list[i].second * c->cfg.samples_per_ray * per_sample +
+                        24.0 * (double)o.P_grid, i});
+  }
+  std::sort(cost.begin(), cost.end(), [](const auto& x, const auto& y) {
+    return x.first > y.first || (x.first == y.first && x.second < y.second);
+  });
+  std::vector<int> side(list.size(), 0);
+  double w[2] = {0.0, 0.0};
+  const double share[2] = {RM_SPLIT_SHARE, 1.0 - RM_SPLIT_SHARE};
+  for (auto& cs : cost) {
+    const int h = w[1] / share[1] < w[0] / share[0] ? 1 : 0;
+    side[cs.second] = h;
+    w[h] += cs.first;
+  }
+  half[0].clear();
+  half[1].clear();
+  for (size_t i = 0; i < list.size(); ++i) half[side[i]].push_back(list[i]);
 }
 
 // Adds the gradient records the step just run wrote into its bins (the
@@ -527,7 +599,7 @@ hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a0, bool ad
 romap_status count_records(romap_ctx* c, const Plan& p) {
   if (p.bin_regions == 0) return ROMAP_OK;
   std::vector<int32_t> cnt((size_t)p.bin_regions);
-  HIPCHK(c, hipMemcpyAsync(cnt.data(), c->d_bin_count, cnt.size() * sizeof(int32_t),
+  HIPCHK(c, hipMemcpyAsync(cnt.data(), c->d_bin_count + p.so_bins, cnt.size() * sizeof(int32_t),
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (const BinPair& bp : p.bpairs)
@@ -595,7 +667,7 @@ romap_status autotune(romap_ctx* c, const std::vector<std::pair<int, int>>& list
     HIPCHK(c, hipEventRecord(e0, c->stream));
     for (int r = 0; r < 3; ++r) {
       HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
-      HIPCHK(c, rm_launch_reduce(ar, RM_MLP_MAX, c->stream));
+      HIPCHK(c, rm_launch_reduce(ar, c->stream));
     }
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));
@@ -721,6 +793,7 @@ romap_status romap_default_config(romap_config* cfg) {
   cfg->autotune = 1;
   cfg->profile_phases = 0;
   cfg->mlp_layers = 1;
+  cfg->streams = 2;
   cfg->seed = 0;
   return ROMAP_OK;
 }
@@ -741,6 +814,7 @@ romap_status romap_create(const romap_config* cfg, void* hip_stream, romap_ctx**
     return fail(nullptr, ROMAP_E_INVALID_ARG, "samples_per_ray must be 32, 64 or 128");
   if (k.mlp_layers < 1 || k.mlp_layers > RM_MAX_MLP_LAYERS)
     return fail(nullptr, ROMAP_E_INVALID_ARG, "mlp_layers must be 1..3");
+  if (k.streams != 1 && k.streams != 2) return fail(nullptr, ROMAP_E_INVALID_ARG, "streams must be 1 or 2");
   if (k.rays_per_step <= 0 || k.rays_per_step > (1 << 22))
     return fail(nullptr, ROMAP_E_INVALID_ARG, "bad rays_per_step");
   if (!(k.lr > 0.0f) || !(k.beta1 >= 0.0f && k.beta1 < 1.0f) || !(k.beta2 >= 0.0f && k.beta2 < 1.0f) ||
@@ -775,6 +849,12 @@ romap_status romap_destroy(romap_ctx* c) {
   if (!c) return ROMAP_E_INVALID_ARG;
   hipStreamSynchronize(c->stream);
   if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->stream2) {
+    hipStreamSynchronize(c->stream2);
+    hipStreamDestroy(c->stream2);
+    hipEventDestroy(c->ev_fork);
+    hipEventDestroy(c->ev_join);
+  }
   for (hipEvent_t ev : c->pev) hipEventDestroy(ev);
   for (auto& o : c->objs) {
     hipFree(o.d_block);
@@ -1129,6 +1209,7 @@ static std::vector<int64_t> graph_sig(romap_ctx* c, const std::vector<std::pair<
   sig.push_back(rpi);
   sig.push_back(blk);
   sig.push_back((int64_t)(uintptr_t)c->d_tables);
+  sig.push_back(c->cfg.streams);
   return sig;
 }
 
@@ -1176,6 +1257,21 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
   Plan all;
   build_plan(c, list, rpi, blk, all);
   const bool prof = c->cfg.profile_phases != 0;
+  // a batched step of two or more objects runs as two concurrent halves
+  const bool split = c->cfg.batch_mode == ROMAP_BATCH_ALL && c->cfg.streams == 2 && !prof &&
+                     list.size() >= 2;
+  Plan half[2];
+  if (split) {
+    std::vector<std::pair<int, int>> hl[2];
+    split_list(c, list, hl);
+    build_plan(c, hl[0], rpi, blk, half[0]);
+    build_plan(c, hl[1], rpi, blk, half[1]);
+    if (!c->stream2) {
+      HIPCHK(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+      HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+      HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+  }
   if (prof) {
     c->pev_n = 0;
     c->records_sum = 0;
@@ -1183,11 +1279,24 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
     c->phase_steps = 0;
   }
   if (c->cfg.batch_mode == ROMAP_BATCH_ALL) {
-    s = stage_plans(c, {&all});
+    s = split ? stage_plans(c, {&half[0], &half[1]}, true) : stage_plans(c, {&all});
     if (s != ROMAP_OK) return s;
-    StepArgs a = plan_args(c, all);
+    StepArgs a = split ? StepArgs{} : plan_args(c, all);
+    StepArgs ah[2];
+    if (split) {
+      ah[0] = plan_args(c, half[0]);
+      ah[1] = plan_args(c, half[1]);
+    }
+    auto one_step = [&]() -> hipError_t {
+      return split ? enqueue_pair(c, half, ah) : enqueue_step(c, all, a, true);
+    };
     if (stats) {
-      HIPCHK(c, rm_launch_reset_loss(a, c->stream));
+      if (split) {
+        HIPCHK(c, rm_launch_reset_loss(ah[0], c->stream));
+        HIPCHK(c, rm_launch_reset_loss(ah[1], c->stream));
+      } else {
+        HIPCHK(c, rm_launch_reset_loss(a, c->stream));
+      }
       HIPCHK(c, hipEventRecord(e0, c->stream));
     }
     if (prof) {
@@ -1207,7 +1316,7 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
         }
         hipGraph_t graph;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t le = enqueue_step(c, all, a, true);
+        hipError_t le = one_step();
         hipError_t ce = hipStreamEndCapture(c->stream, &graph);
         if (le != hipSuccess) return fail(c, ROMAP_E_HIP, std::string("capture: ") + hipGetErrorString(le));
         if (ce != hipSuccess) return fail(c, ROMAP_E_HIP, std::string("end capture: ") + hipGetErrorString(ce));
@@ -1221,11 +1330,11 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
       }
       for (int i = 0; i < n_steps; ++i) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
     } else {
-      for (int i = 0; i < n_steps; ++i) HIPCHK(c, enqueue_step(c, all, a, true));
+      for (int i = 0; i < n_steps; ++i) HIPCHK(c, one_step());
     }
     if (stats) {
       HIPCHK(c, hipEventRecord(e1, c->stream));
-      s = read_losses(c, all, &losses, &n_nan);
+      s = read_losses(c, all, &losses, &n_nan);  // per object, in list order
       if (s != ROMAP_OK) return s;
     }
   } else {
@@ -1880,7 +1989,7 @@ romap_status romap_field_backward(romap_ctx* c, int32_t id, const float* params_
     HIPCHK(c, rm_launch_bin_scatter(a, g, NS, c->stream));
     HIPCHK(c, rm_launch_bin_acc(a, g, c->stream));
   }
-  HIPCHK(c, rm_launch_reduce(a, RM_MLP_MAX, c->stream));
+  HIPCHK(c, rm_launch_reduce(a, c->stream));
   return ROMAP_OK;
 }
 

@@ -418,3 +418,31 @@ def test_profiled_steps_match_and_count_records(tiny):
     hashed, merged = res[(16, 1)][2], res[(4, 1)][2]
     assert 0 < hashed <= 8 * B * N * L
     assert 0 < merged < 8 * B * N * L
+
+
+def test_two_stream_step_equals_one_stream():
+    """A batched step split in two halves on two streams (graph replay and
+    eager) advances every object exactly as the one-stream step: the halves
+    share no object and no scratch, and with one accumulation workgroup per
+    table region every sum is order-independent."""
+    _say("two streams")
+    wl = scenes.config3(n_obj=3, n_views=8, W=160, H=120, seed=1, room=4.0)
+    rays = [300, 77, 256]
+    lts = [15, 19, 16]
+    res = []
+    for streams in (2, 1):
+        g = pk.Context(pk.default_config(samples_per_ray=32, autotune=0, streams=streams))
+        ids = [g.add_object(ob.instance, ob.t, ob.yaw, ob.half, lt)
+               for ob, lt in zip(wl.objects, lts)]
+        for cam, rgb, mask, depth in wl.frames:
+            g.add_keyframe(cam, rgb, mask, depth)
+        st1 = g.train(10, ids, rays)  # captured step graph
+        st2 = g.train(3, ids, rays)   # its replay
+        st3 = g.train(2, ids, rays[::-1][:2] + [rays[2]])  # new shapes: eager
+        res.append((g, ids, [st1.loss_mean, st2.loss_mean, st3.loss_mean]))
+    (ga, ia, la), (gb, ib, lb) = res
+    assert la == lb
+    for i, j in zip(ia, ib):
+        assert ga.object_info(i).step == gb.object_info(j).step == 15
+        for kind in (pk.PARAMS, pk.ADAM_M, pk.ADAM_V):
+            assert np.array_equal(ga.get_params(i, kind), gb.get_params(j, kind)), (i, kind)
