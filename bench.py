@@ -136,9 +136,13 @@ def run_stream(wl, args):
                 psnr_over_time=psnr_log)
 
 
+STREAMS = 2  # --streams: 1 for profiler runs (one launch per kernel and phase)
+
+
 def make_ctx(wl, precision, batch_mode, use_graph, autotune=1, profile=0, **kw):
     import paper_2304_05735_amd as pk
     N = 64
+    kw.setdefault("streams", STREAMS)
     cfg = pk.default_config(samples_per_ray=N, precision=precision, batch_mode=batch_mode,
                             use_graph=use_graph, autotune=autotune, profile_phases=profile, **kw)
     ctx = pk.Context(cfg)
@@ -366,7 +370,7 @@ def pmc_summary(d, workload, steps):
     out = [f"# HBM traffic per dispatch, workload {workload}",
            f"# rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir>/fetch (write) -o run -f csv "
            f"-- python3 bench.py --steps {steps} --warmup 5 --only-headline --copy-probe "
-           f"--workload {workload}",
+           f"--streams 1 --workload {workload}",
            f"# then: python bench.py --pmc-summary <dir> --workload {workload}",
            f"# calibration (512 MiB copy): FETCH_SIZE x {factor['FETCH_SIZE']:.4f}, "
            f"WRITE_SIZE x {factor['WRITE_SIZE']:.4f}",
@@ -464,11 +468,16 @@ def main():
     ap.add_argument("--only-headline", action="store_true",
                     help="time the batched path only (for profiler runs)")
     ap.add_argument("--frames", type=int, default=300, help="frames of the config5 stream")
+    ap.add_argument("--streams", type=int, default=2, choices=(1, 2),
+                    help="streams of a batched step (1 for profiler runs: kernel traces and "
+                         "counters then describe one launch per kernel and phase)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 512 MiB three times (calibrates the HBM byte counters)")
     ap.add_argument("--pmc-summary", metavar="DIR",
                     help="write the HBM traffic summary from rocprofv3 counter runs and exit")
     args = ap.parse_args()
+    global STREAMS
+    STREAMS = args.streams
     if args.pmc_summary:
         pmc_summary(args.pmc_summary, args.workload, args.steps)
         return
