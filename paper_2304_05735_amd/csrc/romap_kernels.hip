@@ -1025,8 +1025,9 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
   constexpr int STG = 64 * MM::STRIDE;    // one staging tile (64 feature rows)
   constexpr int KQ = K1 / 16;
   // a ray's encodings stay in registers from the forward to the backward
-  // pass when they fit (NS <= 64), else the backward reads them again
-  constexpr bool KEEP_E = NB * KQ <= 8;
+  // pass when they fit (NS <= 64, one hidden layer), else the backward reads
+  // them again
+  constexpr bool KEEP_E = NH == 1 && NB * KQ <= 8;
   constexpr int NBK = KEEP_E ? NB : 1;
   constexpr int WP = RM_WPACK_NH(NH);
   constexpr int RL = RM_REC_LOSS_NH(NH);
@@ -1102,7 +1103,7 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
 
     // ---- forward: sigma, colour of every sample ----
     floatx4 EK[NBK][KQ];
-#pragma unroll
+#pragma unroll(KEEP_E ? NB : 1)
     for (int b = 0; b < NB; ++b) {
       floatx4 E[KQ], H1[4], Y[1], H2[4], Z[1];
       load_e<K1>(a.e, S, sray + 16 * b + n, L, g, E);
@@ -1264,7 +1265,7 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
     wave_lds_sync();
 
     // ---- backward: recompute activations per block, adjoints, dW ----
-#pragma unroll
+#pragma unroll(KEEP_E ? NB : 1)
     for (int b = 0; b < NB; ++b) {
       const int64_t s = sray + 16 * b + n;
       floatx4 E[KQ], HH[NH][4], Y[1], H2[4];
