@@ -256,17 +256,17 @@ struct MeshArgs {
   int world;                // apply x_w = R x + t
   float R[9], t[3];
 };
-hipError_t rm_launch_density_grid(const ObjStatic* objs, int obj, int res, float* grid,
+hipError_t rm_launch_density_grid(const ObjStatic* objs, int obj, int nh, int res, float* grid,
                                   hipStream_t st);
 hipError_t rm_launch_mc_count(const MeshArgs& m, hipStream_t st);
 hipError_t rm_launch_mc_emit(const MeshArgs& m, hipStream_t st);
-hipError_t rm_launch_query_density(const ObjStatic* objs, int obj, const float* xyz, int64_t n,
-                                   float* sigma, hipStream_t st);
+hipError_t rm_launch_query_density(const ObjStatic* objs, int obj, int nh, const float* xyz,
+                                   int64_t n, float* sigma, hipStream_t st);
 hipError_t rm_launch_debug_encode(const ObjStatic* objs, int obj, const float* p, int64_t n,
                                   uint32_t* idx, float* feat, hipStream_t st);
 hipError_t rm_launch_fill(float* x, int64_t n, float v, hipStream_t st);
-hipError_t rm_launch_occ_update(const ObjStatic* objs, int obj, uint32_t* bits, float threshold,
-                                hipStream_t st);
+hipError_t rm_launch_occ_update(const ObjStatic* objs, int obj, int nh, uint32_t* bits,
+                                float threshold, hipStream_t st);
 hipError_t rm_launch_init(float* params, int64_t P_grid, int din, int nh, uint32_t k0,
                           uint32_t k1, hipStream_t st);
 hipError_t rm_launch_debug_positions(const StepArgs& a, int NS, float* pos, hipStream_t st);

@@ -1479,14 +1479,11 @@ __global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
 
 
 // ---------------------------------------------------------------------------
-// density at object-frame points (meshing): encode + density head on VALU
-__device__ inline float density_at(const ObjStatic& ob, const float x[3]) {
-  float p[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const float q = (x[k] + ob.half[k]) / (ob.half[k] + ob.half[k]);
-    p[k] = fminf(fmaxf(q, 0.0f), 1.0f);
-  }
+// Density of an object's field at a normalised position p in [0,1]^3:
+// encoding + density head on VALU.  DEEP: the density MLP has hidden-to-hidden
+// layers (compiled apart, so the one-layer kernels keep their registers).
+template <bool DEEP>
+__device__ inline float density_p(const ObjStatic& ob, const float p[3]) {
   float e[2 * RM_MAX_LEVELS];
   for (int l = 0; l < ob.L; ++l) {
     Cell cl;
@@ -1507,13 +1504,13 @@ __device__ inline float density_at(const ObjStatic& ob, const float x[3]) {
   const float* Wh = W1 + RM_HIDDEN * ob.din;
   const float* W2 = Wh + (ob.mlp_layers - 1) * RM_HH;
   float y0 = 0.0f;
-  if (ob.mlp_layers == 1) {
+  if (!DEEP) {
     for (int h = 0; h < RM_HIDDEN; ++h) {
       float s = 0.0f;
       for (int k = 0; k < ob.din; ++k) s = fmaf(W1[h * ob.din + k], e[k], s);
       y0 = fmaf(W2[h], s > 0.0f ? s : 0.0f, y0);
     }
-  } else {  // deeper density MLP: hidden activations in registers
+  } else {
     float ha[RM_HIDDEN], hb[RM_HIDDEN];
     for (int h = 0; h < RM_HIDDEN; ++h) {
       float s = 0.0f;
@@ -1534,12 +1531,25 @@ __device__ inline float density_at(const ObjStatic& ob, const float x[3]) {
   return expf(fminf(y0, 15.0f));
 }
 
+// density at an object-frame point (meshing, queries)
+template <bool DEEP>
+__device__ inline float density_at(const ObjStatic& ob, const float x[3]) {
+  float p[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float q = (x[k] + ob.half[k]) / (ob.half[k] + ob.half[k]);
+    p[k] = fminf(fmaxf(q, 0.0f), 1.0f);
+  }
+  return density_p<DEEP>(ob, p);
+}
+
+template <bool DEEP>
 __global__ __launch_bounds__(256) void k_query_density(const ObjStatic* objs, int obj,
                                                        const float* xyz, int64_t n, float* sigma) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const float x[3] = {xyz[3 * t], xyz[3 * t + 1], xyz[3 * t + 2]};
-  sigma[t] = density_at(objs[obj], x);
+  sigma[t] = density_at<DEEP>(objs[obj], x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1551,6 +1561,7 @@ __device__ inline float grid_coord(float lo, float hi, int g, int res) {
 }
 
 // density of an object at the corners of a grid over its box
+template <bool DEEP>
 __global__ __launch_bounds__(256) void k_density_grid(const ObjStatic* objs, int obj, int res,
                                                       float* grid) {
   const int64_t n1 = res + 1;
@@ -1561,7 +1572,7 @@ __global__ __launch_bounds__(256) void k_density_grid(const ObjStatic* objs, int
   float x[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) x[a] = grid_coord(-ob.half[a], ob.half[a], g[a], res);
-  grid[t] = density_at(ob, x);
+  grid[t] = density_at<DEEP>(ob, x);
 }
 
 // case of cell c and its 8 corner values
@@ -1764,6 +1775,7 @@ __global__ void k_reset_loss(StepArgs a) {
 
 // occupancy refresh: bit = density at the cell centre > threshold; a wave
 // covers 64 consecutive cells and stores its two words from a ballot
+template <bool DEEP>
 __global__ __launch_bounds__(256) void k_occ_update(const ObjStatic* objs, int obj,
                                                    uint32_t* bits, float threshold) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;  // < 64^3, grid exact
@@ -1771,31 +1783,7 @@ __global__ __launch_bounds__(256) void k_occ_update(const ObjStatic* objs, int o
   const float p[3] = {((float)(cell & 63) + 0.5f) / 64.0f,
                       ((float)((cell >> 6) & 63) + 0.5f) / 64.0f,
                       ((float)(cell >> 12) + 0.5f) / 64.0f};
-  float e[2 * RM_MAX_LEVELS];
-  for (int l = 0; l < ob.L; ++l) {
-    Cell cl;
-    make_cell(p, ob.N_l[l], cl);
-    const bool hashed = (ob.hashed_mask >> l) & 1u;
-    const float* G = ob.params + ob.off[l];
-    float ex = 0.0f, ey = 0.0f;
-    for (int b = 0; b < 8; ++b) {
-      const uint32_t id = corner_index(cl, b, ob.N_l[l], ob.T_l[l], hashed);
-      const float w = corner_weight(cl, b);
-      ex = fmaf(w, G[2 * (int64_t)id], ex);
-      ey = fmaf(w, G[2 * (int64_t)id + 1], ey);
-    }
-    e[2 * l] = ex;
-    e[2 * l + 1] = ey;
-  }
-  const float* W1 = ob.params + ob.P_grid;
-  const float* W2 = W1 + RM_HIDDEN * ob.din;
-  float y0 = 0.0f;
-  for (int h = 0; h < RM_HIDDEN; ++h) {
-    float sacc = 0.0f;
-    for (int k = 0; k < ob.din; ++k) sacc = fmaf(W1[h * ob.din + k], e[k], sacc);
-    y0 = fmaf(W2[h], sacc > 0.0f ? sacc : 0.0f, y0);
-  }
-  const bool on = expf(fminf(y0, 15.0f)) > threshold;
+  const bool on = density_p<DEEP>(ob, p) > threshold;
   const uint64_t m = __ballot(on);
   const int lane = threadIdx.x & 63;
   if (lane < 2) bits[(cell >> 5) + lane] = (uint32_t)(m >> (32 * lane));
@@ -1924,17 +1912,19 @@ hipError_t rm_launch_user_rays(const StepArgs& a, int NS, const float* rays, hip
   return hipGetLastError();
 }
 
-hipError_t rm_launch_query_density(const ObjStatic* objs, int obj, const float* xyz, int64_t n,
-                                   float* sigma, hipStream_t st) {
+hipError_t rm_launch_query_density(const ObjStatic* objs, int obj, int nh, const float* xyz,
+                                   int64_t n, float* sigma, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  k_query_density<<<cdiv(n, 256), 256, 0, st>>>(objs, obj, xyz, n, sigma);
+  if (nh > 1) k_query_density<true><<<cdiv(n, 256), 256, 0, st>>>(objs, obj, xyz, n, sigma);
+  else k_query_density<false><<<cdiv(n, 256), 256, 0, st>>>(objs, obj, xyz, n, sigma);
   return hipGetLastError();
 }
 
-hipError_t rm_launch_density_grid(const ObjStatic* objs, int obj, int res, float* grid,
+hipError_t rm_launch_density_grid(const ObjStatic* objs, int obj, int nh, int res, float* grid,
                                   hipStream_t st) {
   const int64_t n1 = res + 1;
-  k_density_grid<<<cdiv(n1 * n1 * n1, 256), 256, 0, st>>>(objs, obj, res, grid);
+  if (nh > 1) k_density_grid<true><<<cdiv(n1 * n1 * n1, 256), 256, 0, st>>>(objs, obj, res, grid);
+  else k_density_grid<false><<<cdiv(n1 * n1 * n1, 256), 256, 0, st>>>(objs, obj, res, grid);
   return hipGetLastError();
 }
 
@@ -1983,9 +1973,10 @@ hipError_t rm_launch_reset_loss(const StepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t rm_launch_occ_update(const ObjStatic* objs, int obj, uint32_t* bits, float threshold,
-                                hipStream_t st) {
-  k_occ_update<<<(64 * 64 * 64) / 256, 256, 0, st>>>(objs, obj, bits, threshold);
+hipError_t rm_launch_occ_update(const ObjStatic* objs, int obj, int nh, uint32_t* bits,
+                                float threshold, hipStream_t st) {
+  if (nh > 1) k_occ_update<true><<<(64 * 64 * 64) / 256, 256, 0, st>>>(objs, obj, bits, threshold);
+  else k_occ_update<false><<<(64 * 64 * 64) / 256, 256, 0, st>>>(objs, obj, bits, threshold);
   return hipGetLastError();
 }
 

@@ -1014,7 +1014,7 @@ romap_status romap_update_occupancy(romap_ctx* c, int32_t id, float threshold) {
   if (!std::isfinite(threshold)) return fail(c, ROMAP_E_INVALID_ARG, "non-finite threshold");
   HostObj& o = c->objs[id];
   if (!o.d_occ) HIPALLOC(c, hipMalloc((void**)&o.d_occ, kOccBytes));
-  HIPCHK(c, rm_launch_occ_update(c->d_objs, id, o.d_occ, threshold, c->stream));
+  HIPCHK(c, rm_launch_occ_update(c->d_objs, id, c->cfg.mlp_layers, o.d_occ, threshold, c->stream));
   o.occ_on = true;
   return upload_object(c, id);
 }
@@ -1767,7 +1767,7 @@ romap_status romap_extract_mesh(romap_ctx* c, int32_t id, int32_t res, float iso
   s = mc_setup(c, res);
   if (s != ROMAP_OK) return s;
   const HostObj& o = c->objs[id];
-  HIPCHK(c, rm_launch_density_grid(c->d_objs, id, res, c->d_mgrid, c->stream));
+  HIPCHK(c, rm_launch_density_grid(c->d_objs, id, c->cfg.mlp_layers, res, c->d_mgrid, c->stream));
   MeshArgs m{};
   m.grid = c->d_mgrid;
   m.res = res;
@@ -1794,7 +1794,7 @@ romap_status romap_query_density(romap_ctx* c, int32_t id, const float* xyz, int
   if (n < 0 || (n > 0 && (!xyz || !sigma))) return fail(c, ROMAP_E_INVALID_ARG, "bad buffers");
   if (n == 0) return ROMAP_OK;
   if (on_device) {
-    HIPCHK(c, rm_launch_query_density(c->d_objs, id, xyz, n, sigma, c->stream));
+    HIPCHK(c, rm_launch_query_density(c->d_objs, id, c->cfg.mlp_layers, xyz, n, sigma, c->stream));
     return ROMAP_OK;
   }
   float *dx = nullptr, *ds = nullptr;
@@ -1805,7 +1805,7 @@ romap_status romap_query_density(romap_ctx* c, int32_t id, const float* xyz, int
     return fail(c, ROMAP_E_OUT_OF_MEMORY, "query buffers: out of memory");
   }
   HIPCHK(c, hipMemcpyAsync(dx, xyz, n * 3 * sizeof(float), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, rm_launch_query_density(c->d_objs, id, dx, n, ds, c->stream));
+  HIPCHK(c, rm_launch_query_density(c->d_objs, id, c->cfg.mlp_layers, dx, n, ds, c->stream));
   HIPCHK(c, hipMemcpyAsync(sigma, ds, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   hipFree(dx);

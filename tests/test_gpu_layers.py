@@ -146,3 +146,24 @@ def test_mlp_layers_out_of_range_is_rejected():
     for bad in (0, 4):
         with pytest.raises(pk.RomapError):
             pk.Context(pk.default_config(mlp_layers=bad))
+
+
+def test_deep_mlp_occupancy_refresh_follows_density(tiny):
+    """The occupancy refresh thresholds the density of the deeper MLP at the
+    cell centres (bits match the oracle's density wherever it is not within
+    1e-4 of the threshold)."""
+    _say("deep mlp occupancy")
+    frames, box = tiny
+    g, o, gid = make_pair(8, 16, 128, 12, 64, 64, frames, box, mlp_layers=2)
+    _same_params(g, o, gid, 2, seed=17)
+    ob = o.objects[gid]
+    cells = (np.arange(64) + 0.5) / 64.0
+    z, y, x = np.meshgrid(cells, cells, cells, indexing="ij")
+    xyz = (np.stack([x, y, z], -1).reshape(-1, 3) * (2.0 * ob.half) - ob.half).astype(np.float32)
+    dens = o.query_density(gid, xyz)
+    thr = float(np.median(dens))
+    g.update_occupancy(gid, thr)
+    gb = np.unpackbits(g.get_occupancy(gid), bitorder="little").astype(bool)
+    sure = np.abs(dens - thr) > 1e-4 * thr
+    assert sure.sum() > 200000
+    assert np.array_equal(gb[sure], (dens > thr)[sure])
