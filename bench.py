@@ -78,7 +78,7 @@ def run_stream(wl, args):
     import paper_2304_05735_amd as pk
     import scenes
     cfg = pk.default_config(samples_per_ray=128, precision=pk.PREC_BF16, batch_mode=pk.BATCH_ALL,
-                            use_graph=1, autotune=0)
+                            use_graph=1, autotune=0, streams=STREAMS)
     ctx = pk.Context(cfg)
     spec = {o.instance: o for o in wl.objects}
     oid_of, first, last_seen, pix, has_kf = {}, {}, {}, {}, {}

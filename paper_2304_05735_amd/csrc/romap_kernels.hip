@@ -1484,18 +1484,23 @@ __global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
 // layers (compiled apart, so the one-layer kernels keep their registers).
 template <bool DEEP>
 __device__ inline float density_p(const ObjStatic& ob, const float p[3]) {
+  // loops over the largest level count with guards: constant indices keep
+  // the encoding in registers
   float e[2 * RM_MAX_LEVELS];
-  for (int l = 0; l < ob.L; ++l) {
-    Cell cl;
-    make_cell(p, ob.N_l[l], cl);
-    const bool hashed = (ob.hashed_mask >> l) & 1u;
-    const float* G = ob.params + ob.off[l];
+#pragma unroll
+  for (int l = 0; l < RM_MAX_LEVELS; ++l) {
     float ex = 0.0f, ey = 0.0f;
-    for (int b = 0; b < 8; ++b) {
-      const uint32_t id = corner_index(cl, b, ob.N_l[l], ob.T_l[l], hashed);
-      const float w = corner_weight(cl, b);
-      ex = fmaf(w, G[2 * (int64_t)id], ex);
-      ey = fmaf(w, G[2 * (int64_t)id + 1], ey);
+    if (l < ob.L) {
+      Cell cl;
+      make_cell(p, ob.N_l[l], cl);
+      const bool hashed = (ob.hashed_mask >> l) & 1u;
+      const float* G = ob.params + ob.off[l];
+      for (int b = 0; b < 8; ++b) {
+        const uint32_t id = corner_index(cl, b, ob.N_l[l], ob.T_l[l], hashed);
+        const float w = corner_weight(cl, b);
+        ex = fmaf(w, G[2 * (int64_t)id], ex);
+        ey = fmaf(w, G[2 * (int64_t)id + 1], ey);
+      }
     }
     e[2 * l] = ex;
     e[2 * l + 1] = ey;
@@ -1507,7 +1512,9 @@ __device__ inline float density_p(const ObjStatic& ob, const float p[3]) {
   if (!DEEP) {
     for (int h = 0; h < RM_HIDDEN; ++h) {
       float s = 0.0f;
-      for (int k = 0; k < ob.din; ++k) s = fmaf(W1[h * ob.din + k], e[k], s);
+#pragma unroll
+      for (int k = 0; k < 2 * RM_MAX_LEVELS; ++k)
+        if (k < ob.din) s = fmaf(W1[h * ob.din + k], e[k], s);
       y0 = fmaf(W2[h], s > 0.0f ? s : 0.0f, y0);
     }
   } else {
