@@ -60,7 +60,8 @@ typedef struct romap_ctx romap_ctx;
 #define ROMAP_PREC_FP32 0 /* MLP contractions on FP32 MFMA */
 #define ROMAP_PREC_BF16 1 /* MLP contractions on BF16 MFMA, FP32 accumulate */
 
-#define ROMAP_BATCH_ALL 0        /* every object of a step in one launch per phase */
+#define ROMAP_BATCH_ALL 0        /* every object of a step in one launch per phase (two
+                                    object groups on two streams with streams = 2) */
 #define ROMAP_BATCH_PER_OBJECT 1 /* one launch per object per phase */
 
 /* Model and training hyperparameters.  Defaults: romap_default_config(). */

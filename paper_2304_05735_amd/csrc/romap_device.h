@@ -9,16 +9,14 @@
 #define RM_GEO 15
 #define RM_DOUT 16
 #define RM_MLP_MAX (64 * 32 + 16 * 64 + 64 * 15 + 3 * 64) /* 4224 */
-#define RM_REC_STRIDE 4240 /* floats per work-item record: MLP grads, loss, pad */
-#define RM_REC_LOSS 4224
 #define RM_WPACK 10240      /* packed MLP weight image, elements (K1 <= 32) */
 #define RM_MAX_MLP_LAYERS 3 /* hidden layers of the density MLP: 1 (Sec. V), 2, 3 (Table 4) */
 // with nh hidden layers: nh - 1 more 64 x 64 matrices in the parameters,
 // their gradients in the work-item records and two operand images each
 #define RM_HH (RM_HIDDEN * RM_HIDDEN)
 #define RM_MLP_NH(nh) (RM_MLP_MAX + ((nh) - 1) * RM_HH)      /* MLP floats, K1 = 32 */
-#define RM_REC_LOSS_NH(nh) RM_MLP_NH(nh)
-#define RM_REC_STRIDE_NH(nh) (RM_REC_LOSS_NH(nh) + 16)
+#define RM_REC_LOSS_NH(nh) RM_MLP_NH(nh)   /* work-item record: MLP gradients, then the loss */
+#define RM_REC_STRIDE_NH(nh) (RM_REC_LOSS_NH(nh) + 16)  /* floats per record, padded */
 #define RM_WPACK_NH(nh) (RM_WPACK + ((nh) - 1) * 2 * RM_HH)
 #define RM_OFF_HF(k) (RM_WPACK + ((k) - 1) * 2 * RM_HH)     /* Wh_k   64 x 64 */
 #define RM_OFF_HB(k) (RM_OFF_HF(k) + RM_HH)                 /* Wh_k^T 64 x 64 */
@@ -189,7 +187,7 @@ struct StepArgs {
   float2* e;            // [L][S] encodings
   float2* de;           // [L][S] their adjoints
   int64_t S;            // samples = n_rays * N
-  float* partials;      // n_items * RM_REC_STRIDE
+  float* partials;      // n_items * RM_REC_STRIDE_NH(mlp_layers)
   float* wpack32;       // n_sobj * RM_WPACK
   uint16_t* wpack16;    // n_sobj * RM_WPACK
   uint32_t seed_lo, seed_hi;
