@@ -582,8 +582,18 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
     has = has && ((lane - start) & 3) == 0;
   }
   if (has) {
+    // an x-pair of corners in one region takes both ranks with one atomic
 #pragma unroll
-    for (int b = 0; b < 8; ++b) rank[b] = atomicAdd(&lcnt[idx[b] >> RM_RB_BITS], 1);
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t r0 = idx[2 * q] >> RM_RB_BITS, r1 = idx[2 * q + 1] >> RM_RB_BITS;
+      if (r0 == r1) {
+        rank[2 * q] = atomicAdd(&lcnt[r0], 2);
+        rank[2 * q + 1] = rank[2 * q] + 1;
+      } else {
+        rank[2 * q] = atomicAdd(&lcnt[r0], 1);
+        rank[2 * q + 1] = atomicAdd(&lcnt[r1], 1);
+      }
+    }
   }
   __syncthreads();
   const int n = block_exclusive_scan<RM_SCAT_WG>(lcnt, lbase, bp.R, s_wsum);
