@@ -47,10 +47,12 @@ def test_default_config_and_create_validation_without_gpu():
     assert cfg.samples_per_ray == 64 and cfg.rays_per_step == 4096
     assert abs(cfg.lambda_depth - 0.5) < 1e-7 and abs(cfg.lambda_density - 0.01) < 1e-9
     assert abs(cfg.alpha_deg - 25.0) < 1e-6
+    assert cfg.mlp_layers == 1 and cfg.streams == 2
     L = pk.lib()
     h = ctypes.c_void_p()
     for field, bad in [("n_levels", 17), ("samples_per_ray", 48), ("log2_table_size", 30),
-                       ("precision", 5), ("rays_per_step", 0)]:
+                       ("precision", 5), ("rays_per_step", 0), ("mlp_layers", 0),
+                       ("mlp_layers", 4), ("streams", 0), ("streams", 3)]:
         c = pk.default_config(**{field: bad})
         assert L.romap_create(ctypes.byref(c), None, ctypes.byref(h)) == pk.ROMAP_E_INVALID_ARG
         assert L.romap_last_error(None)
