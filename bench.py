@@ -7,7 +7,7 @@ dominant kernel, the plain path (FP32, one launch per object per phase, no
 graph) beside it, PSNR of both after training, and the CPU oracle timed on a
 bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config4|config2|config3|config5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload objects24|objects24-fp32|torus1|stream128]
 
 The default workload is the 24-object batched BF16 one (the metric's).  HBM
 traffic per launch comes from rocprofv3 counter runs of this script, turned
@@ -56,12 +56,12 @@ def log(*a):
 
 def build_workload(name, frames=300):
     import scenes
-    if name == "config2":
-        return scenes.config2()
-    if name in ("config3", "config4"):
-        return scenes.config3(n_obj=24)
-    if name == "config5":
-        return scenes.config5(n_frames=frames)
+    if name == "torus1":
+        return scenes.torus_scene()
+    if name in ("objects24", "objects24-fp32"):
+        return scenes.room_scene(n_obj=24)
+    if name == "stream128":
+        return scenes.stream_scene(n_frames=frames)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -248,7 +248,7 @@ def table_sweep(steps=200, warmup=20):
     with density MLPs of 2 and 3 hidden layers, on the single-object scene."""
     import paper_2304_05735_amd as pk
     import scenes
-    wl = scenes.config2()
+    wl = scenes.torus_scene()
     ob = wl.objects[0]
     rows = []
     models = [(lt, 1) for lt in (14, 16, 18, 20)] + [(16, 2), (16, 3)]
@@ -455,7 +455,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config4")
+    ap.add_argument("--workload", default="objects24",
+                    choices=("objects24", "objects24-fp32", "torus1", "stream128"))
     ap.add_argument("--psnr-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psnr", action="store_true")
@@ -467,7 +468,7 @@ def main():
     ap.add_argument("--psnr-chunk", type=int, default=250)
     ap.add_argument("--only-headline", action="store_true",
                     help="time the batched path only (for profiler runs)")
-    ap.add_argument("--frames", type=int, default=300, help="frames of the config5 stream")
+    ap.add_argument("--frames", type=int, default=300, help="frames of the stream128 workload")
     ap.add_argument("--streams", type=int, default=2, choices=(1, 2),
                     help="streams of a batched step (1 for profiler runs: kernel traces and "
                          "counters then describe one launch per kernel and phase)")
@@ -506,7 +507,7 @@ def main():
     wl = build_workload(args.workload, args.frames)
     log(f"scene ready in {time.perf_counter() - t:.1f}s: {len(wl.objects)} objects, "
         f"{len(wl.frames)} frames")
-    if args.workload == "config5":
+    if args.workload == "stream128":
         st = run_stream(wl, args)
         log("stream", json.dumps(st))
         out = {"metric": METRIC, "value": st["train_rays_per_s"], "unit": "rays/s", "n_gpus": 1,
@@ -515,7 +516,7 @@ def main():
                "data": "synthetic", "config": {"workload": wl.name}, "stream": st}
         print(json.dumps(out), flush=True)
         return
-    prec = pk.PREC_BF16 if args.workload == "config4" else pk.PREC_FP32
+    prec = pk.PREC_BF16 if args.workload == "objects24" else pk.PREC_FP32
     # ---- headline: batched path, one hipGraph per step
     ctx, ids, rays = make_ctx(wl, prec, pk.BATCH_ALL, 1)
     rays_per_step = sum(rays)

@@ -359,19 +359,19 @@ def _render_frames(wl: Workload, depth_frac=0.0, seed=0, workers=None):
     return wl
 
 
-def config1() -> Workload:
+def sphere_scene() -> Workload:
     """One sphere (r 0.3, density 50) in the unit cube; 8 posed 64x64 views."""
     sph = Primitive("sphere", np.zeros(3), np.array([0.3]), instance=1)
     cams = _fibonacci_cameras(8, 1.5, 64, 64, 64.0)
     obj = ObjectSpec(1, np.zeros(3, np.float32), 0.0, np.full(3, 0.5, np.float32), 12)
-    wl = Workload("config1: 1 object, L8 T2^12, 256 rays x 32 samples", Scene([sph]), cams, [obj])
+    wl = Workload("1 object (sphere), L8 T2^12, 256 rays x 32 samples", Scene([sph]), cams, [obj])
     wl.rays = {1: 256}
     _render_frames(wl)
     wl.eval_views = list(range(len(cams)))
     return wl
 
 
-def config2(n_views=50, W=640, H=480) -> Workload:
+def torus_scene(n_views=50, W=640, H=480) -> Workload:
     """Sphere, yawed box and torus; the torus (instance 3) is the trained object."""
     prims = [
         Primitive("sphere", np.array([-0.7, 0.0, 0.3]), np.array([0.3]), 0.0, 1,
@@ -390,7 +390,7 @@ def config2(n_views=50, W=640, H=480) -> Workload:
     tor = prims[2]
     obj = ObjectSpec(3, tor.center.astype(np.float32), 0.0,
                      (tor.bound_half() * 1.1).astype(np.float32), 19)
-    wl = Workload(f"config2: 1 object (torus), L16 T2^19, 4096 rays x 64 samples, {W}x{H}",
+    wl = Workload(f"1 object (torus of 3 primitives), L16 T2^19, 4096 rays x 64 samples, {W}x{H}",
                   Scene(prims), cams, [obj])
     wl.rays = {3: 4096}
     _render_frames(wl, depth_frac=0.005)
@@ -398,7 +398,7 @@ def config2(n_views=50, W=640, H=480) -> Workload:
     return wl
 
 
-def config3(n_obj=24, n_views=60, W=640, H=480, seed=0, room=8.0) -> Workload:
+def room_scene(n_obj=24, n_views=60, W=640, H=480, seed=0, room=8.0) -> Workload:
     """n_obj primitives of log-uniform size on a floor, a circle of cameras."""
     rng = np.random.default_rng(seed)
     prims = []
@@ -437,7 +437,7 @@ def config3(n_obj=24, n_views=60, W=640, H=480, seed=0, room=8.0) -> Workload:
         log2T = int(min(19, max(15, round(e))))
         objs.append(ObjectSpec(p.instance, p.center.astype(np.float32), float(np.float32(p.yaw)),
                                (p.bound_half() * 1.1).astype(np.float32), log2T))
-    wl = Workload(f"config3: {n_obj} objects, L16 T2^15..2^19, x 64 samples, {W}x{H}", Scene(prims),
+    wl = Workload(f"{n_obj} objects, L16 T2^15..2^19, 64 samples per ray, {W}x{H}", Scene(prims),
                   cams, objs)
     _render_frames(wl, depth_frac=0.005, seed=seed)
     counts = {o.instance: 0 for o in objs}
@@ -452,7 +452,7 @@ def config3(n_obj=24, n_views=60, W=640, H=480, seed=0, room=8.0) -> Workload:
     return wl
 
 
-def config5(n_obj=128, n_frames=300, W=640, H=480, seed=5, room=14.0) -> Workload:
+def stream_scene(n_obj=128, n_frames=300, W=640, H=480, seed=5, room=14.0) -> Workload:
     """Incremental mapping stream: n_obj primitives in a room, a camera moving
     on a loop through the room at 25 frames per second, looking ahead and
     slightly inward.  Objects are meant to be registered when first seen."""
@@ -489,7 +489,7 @@ def config5(n_obj=128, n_frames=300, W=640, H=480, seed=5, room=14.0) -> Workloa
         cams.append(camera(look_at(eye, look), W, H, f))
     objs = [ObjectSpec(p.instance, p.center.astype(np.float32), float(np.float32(p.yaw)),
                        (p.bound_half() * 1.1).astype(np.float32), 19) for p in prims]
-    wl = Workload(f"config5: {n_obj}-object stream, {n_frames} frames at 25 Hz, L16 T2^19, "
+    wl = Workload(f"{n_obj}-object stream, {n_frames} frames at 25 Hz, L16 T2^19, "
                   f"N 128, 64^3 occupancy, {W}x{H}", Scene(prims), cams, objs)
     _render_frames(wl, depth_frac=0.005, seed=seed)
     return wl

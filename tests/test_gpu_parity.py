@@ -196,7 +196,7 @@ def test_render_and_density_parity(tiny):
 def test_batched_objects_match_per_object_oracle():
     """Three objects with uneven tables and ray counts in one launch per phase."""
     _say("batched parity")
-    wl = scenes.config3(n_obj=3, n_views=8, W=160, H=120, seed=1, room=4.0)
+    wl = scenes.room_scene(n_obj=3, n_views=8, W=160, H=120, seed=1, room=4.0)
     cfg = pk.default_config(samples_per_ray=32, autotune=0)
     g = pk.Context(cfg)
     ocfg = oracle.make_config(N=32)
@@ -225,7 +225,7 @@ def test_full_size_workload_sampled():
     """16 levels x 2^19, 4096 rays x 64 samples: every position bit-exact on a
     sample of rays, the loss and the full gradient against the oracle."""
     _say("full-size parity")
-    wl = scenes.config2(n_views=6)
+    wl = scenes.torus_scene(n_views=6)
     ob = wl.objects[0]
     B = 4096
     frames = wl.frames
@@ -426,7 +426,7 @@ def test_two_stream_step_equals_one_stream():
     share no object and no scratch, and with one accumulation workgroup per
     table region every sum is order-independent."""
     _say("two streams")
-    wl = scenes.config3(n_obj=3, n_views=8, W=160, H=120, seed=1, room=4.0)
+    wl = scenes.room_scene(n_obj=3, n_views=8, W=160, H=120, seed=1, room=4.0)
     rays = [300, 77, 256]
     lts = [15, 19, 16]
     res = []

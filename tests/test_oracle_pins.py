@@ -477,10 +477,10 @@ def test_query_density_matches_encode_plus_mlp():
 
 
 # ---------------------------------------------------------------- training
-def test_config1_training_raises_psnr():
+def test_sphere_scene_training_raises_psnr():
     """Plain method, one object, 50 Adam steps at lr 1e-2: PSNR on the object
     pixels of the training views must rise."""
-    wl = scenes.config1()
+    wl = scenes.sphere_scene()
     cfg = oracle.make_config(L=8, nmin=16, nmax=128, log2T=12, N=32)
     ctx = oracle.OracleContext(cfg)
     ob = wl.objects[0]
