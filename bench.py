@@ -241,14 +241,12 @@ def mesh_timing(ctx, ids, res=64, iso=10.0, reps=3):
                 paper_ms_per_object_rtx4090=2.84)
 
 
-def table_sweep(steps=200, warmup=20):
+def table_sweep(wl, steps=200, warmup=20):
     """Table 4's model-size study on one object: time per step (graph, FP32
     and BF16) of 4096 rays x 32 samples (the paper's N) and of 4096 x 64, for
     T = 2^14 .. 2^20 with the one-hidden-layer density MLP, and for T = 2^16
     with density MLPs of 2 and 3 hidden layers, on the single-object scene."""
     import paper_2304_05735_amd as pk
-    import scenes
-    wl = scenes.torus_scene()
     ob = wl.objects[0]
     rows = []
     models = [(lt, 1) for lt in (14, 16, 18, 20)] + [(16, 2), (16, 3)]
@@ -490,6 +488,13 @@ def main():
 
     import torch
     import paper_2304_05735_amd as pk
+    # the scene renders in forked worker processes: build it before this
+    # process opens the GPU (afterwards it would render serially)
+    log("workload", "torus1 (table sweep)" if args.table_sweep else args.workload)
+    t = time.perf_counter()
+    wl = build_workload("torus1" if args.table_sweep else args.workload, args.frames)
+    log(f"scene ready in {time.perf_counter() - t:.1f}s: {len(wl.objects)} objects, "
+        f"{len(wl.frames)} frames")
     assert torch.cuda.is_available(), "no GPU visible"
     if args.copy_probe:
         src = torch.ones(128 << 20, device="cuda")  # 512 MiB
@@ -500,13 +505,8 @@ def main():
         log("copy probe: 3 x 512 MiB copied")
         del src, dst
     if args.table_sweep:
-        print(json.dumps({"table_sweep": table_sweep()}), flush=True)
+        print(json.dumps({"table_sweep": table_sweep(wl)}), flush=True)
         return
-    log("workload", args.workload)
-    t = time.perf_counter()
-    wl = build_workload(args.workload, args.frames)
-    log(f"scene ready in {time.perf_counter() - t:.1f}s: {len(wl.objects)} objects, "
-        f"{len(wl.frames)} frames")
     if args.workload == "stream128":
         st = run_stream(wl, args)
         log("stream", json.dumps(st))

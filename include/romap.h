@@ -191,7 +191,9 @@ romap_status romap_add_keyframe(romap_ctx* ctx, const romap_camera* cam, const u
 
 /* Runs n_steps training iterations (draw, render, loss, backward, Adam) on
  * every listed object (NULL = every active object).  rays_per_object: rays
- * per step for each listed object (NULL = config default).  stats may be
+ * per step for each listed object, each in [1, 2^22] (NULL = config
+ * default); any other count is ROMAP_E_INVALID_ARG.  An empty list
+ * (n_objects = 0) or n_steps = 0 does nothing and succeeds.  stats may be
  * NULL, in which case the call does not wait for the GPU.  Returns
  * ROMAP_E_STATE if a listed object has no keyframe, ROMAP_E_NUMERIC (after
  * the steps ran) if an object's loss is not finite. */
@@ -201,7 +203,8 @@ romap_status romap_train(romap_ctx* ctx, const int32_t* object_ids, int32_t n_ob
 
 /* One step's loss and gradient without the Adam update or step advance: the
  * gradient buffer is cleared, then holds dL/dparams (read it with kind
- * ROMAP_GRAD).  losses (host, n_objects floats) may be NULL. */
+ * ROMAP_GRAD).  Objects and ray counts as for romap_train.  losses (host,
+ * n_objects floats) may be NULL. */
 romap_status romap_loss_and_grad(romap_ctx* ctx, const int32_t* object_ids, int32_t n_objects,
                                  const int32_t* rays_per_object, float* losses);
 

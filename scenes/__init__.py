@@ -332,12 +332,29 @@ def _render_one(args):
     return to_u8(rgb), mask, depth
 
 
+def _gpu_open() -> bool:
+    """True once this process holds the GPU driver open (/dev/kfd among its
+    file descriptors): the GPU runtime then has threads of its own, and a
+    forked child can inherit a lock one of them held and crash or hang."""
+    try:
+        fds = os.listdir("/proc/self/fd")
+    except OSError:
+        return False
+    for fd in fds:
+        try:
+            if os.readlink(f"/proc/self/fd/{fd}") == "/dev/kfd":
+                return True
+        except OSError:
+            pass
+    return False
+
+
 def _render_frames(wl: Workload, depth_frac=0.0, seed=0, workers=None):
     rng = np.random.default_rng(seed)
     wl.frames = []
     jobs = [(wl.scene, cam) for cam in wl.cameras]
     workers = workers or min(16, os.cpu_count() or 1)
-    if workers > 1 and len(jobs) > 2:
+    if workers > 1 and len(jobs) > 2 and not _gpu_open():
         ctx = mp.get_context("fork")
         with ctx.Pool(workers) as pool:
             outs = pool.map(_render_one, jobs)

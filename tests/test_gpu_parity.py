@@ -220,6 +220,53 @@ def test_batched_objects_match_per_object_oracle():
         assert_grad_close(g.get_params(i, pk.GRAD), og, mass, allow, what=f"grad obj {i}")
 
 
+@pytest.mark.parametrize("streams", [1, 2])
+def test_degenerate_batches(streams):
+    """Ray counts of 1, 2 and 65 (a single ray, a ragged tail of one
+    workgroup) batched with each other: loss and gradient match the oracle,
+    and a training step of that batch (split over two streams when asked)
+    applies Adam with exactly that gradient.  An empty object list and zero
+    steps do nothing; ray counts outside [1, 2^22] are rejected."""
+    _say("degenerate batches", streams)
+    wl = scenes.room_scene(n_obj=3, n_views=8, W=160, H=120, seed=1, room=4.0)
+    g = pk.Context(pk.default_config(samples_per_ray=32, autotune=0, streams=streams))
+    assert scenes._gpu_open()  # later scene builds in this process render serially
+    o = oracle.OracleContext(oracle.make_config(N=32))
+    ids = []
+    for ob, lt in zip(wl.objects, (12, 14, 13)):
+        ids.append(g.add_object(ob.instance, ob.t, ob.yaw, ob.half, lt))
+        o.add_object(ob.instance, ob.t, ob.yaw, ob.half, lt)
+    for cam, rgb, mask, depth in wl.frames:
+        g.add_keyframe(cam, rgb, mask, depth)
+        o.add_keyframe(cam, rgb, mask, depth)
+    p0 = [_set_same_params(g, o, i, seed=30 + i).astype(np.float64) for i in ids]
+    rays = [1, 2, 65]
+    for bad in ([0, 2, 65], [1, -3, 65], [1, 2, (1 << 22) + 1]):
+        with pytest.raises(pk.RomapError) as e:
+            g.train(1, ids, rays=bad)
+        assert e.value.code == pk.ROMAP_E_INVALID_ARG
+    st = g.train(1, [])
+    assert st.rays_trained == 0
+    g.train(0, ids, rays=rays)
+    assert all(g.object_info(i).step == 0 for i in ids)
+    gl = g.loss_and_grad(ids, rays)
+    grads = []
+    for k, i in enumerate(ids):
+        ol, og, mass, allow, _ = oracle_grad(o, i, 0, rays[k])
+        assert_fwd_close([gl[k]], [ol], what=f"loss obj {i} ({rays[k]} rays)")
+        gg = g.get_params(i, pk.GRAD)
+        assert_grad_close(gg, og, mass, allow, what=f"grad obj {i} ({rays[k]} rays)")
+        grads.append(gg.astype(np.float64))
+    st = g.train(1, ids, rays=rays)
+    assert st.rays_trained == sum(rays) and math.isfinite(st.loss_mean)
+    for k, i in enumerate(ids):
+        assert g.object_info(i).step == 1
+        p = p0[k]
+        m, v = np.zeros(p.size), np.zeros(p.size)
+        oracle.adam(p, grads[k], m, v, 1, 1e-2, 0.9, 0.99, 1e-15)
+        assert_fwd_close(g.get_params(i), p, rtol=2e-6, atol=2e-8, what=f"params obj {i}")
+
+
 # ------------------------------------------------------------------ full size of the workload
 def test_full_size_workload_sampled():
     """16 levels x 2^19, 4096 rays x 64 samples: every position bit-exact on a
