@@ -83,7 +83,7 @@ def run_stream(wl, args):
     spec = {o.instance: o for o in wl.objects}
     oid_of, first, last_seen, pix, has_kf = {}, {}, {}, {}, {}
     budget, steps_per_frame = 1 << 16, 4
-    frame_ms, train_ms, psnr_log = [], [], []
+    frame_ms, train_ms, kf_ms, psnr_log = [], [], [], []
     rays_trained = 0
     for f, (cam, rgb, mask, depth) in enumerate(wl.frames):
         ids, counts = np.unique(mask, return_counts=True)
@@ -108,7 +108,10 @@ def run_stream(wl, args):
                 last_seen[inst] = f
                 pix[inst] += int(cnt)
                 has_kf[inst] = True
+        tk = time.perf_counter()
         ctx.add_keyframe(cam, rgb, mask, depth)
+        ctx.sync()
+        kf_ms.append((time.perf_counter() - tk) * 1e3)
         active = [i for i in oid_of if f - last_seen[i] <= 50 and has_kf[i]]
         if active:
             w = np.array([pix[i] for i in active], np.float64)
@@ -132,6 +135,7 @@ def run_stream(wl, args):
                 ms_per_frame_p50=round(float(np.percentile(fm, 50)), 3),
                 ms_per_frame_p95=round(float(np.percentile(fm, 95)), 3),
                 frames_over_40ms=int((fm > 40.0).sum()),
+                keyframe_ms_mean=round(float(np.mean(kf_ms)), 3),
                 train_rays_per_s=round(rays_trained / (tm.sum() * 1e-3), 1) if tm.size else None,
                 psnr_over_time=psnr_log)
 
@@ -149,8 +153,12 @@ def make_ctx(wl, precision, batch_mode, use_graph, autotune=1, profile=0, **kw):
     ids = []
     for ob in wl.objects:
         ids.append(ctx.add_object(ob.instance, ob.t, ob.yaw, ob.half, ob.log2T))
+    ctx.sync()
+    t0 = time.perf_counter()
     for cam, rgb, mask, depth in wl.frames:
         ctx.add_keyframe(cam, rgb, mask, depth)
+    ctx.sync()
+    ctx.keyframe_seconds = time.perf_counter() - t0  # host buffers -> HBM, all frames
     keep, rays = [], []
     for i, ob in zip(ids, wl.objects):
         if ctx.object_info(i).n_keyframes > 0:
@@ -520,6 +528,13 @@ def main():
     # ---- headline: batched path, one hipGraph per step
     ctx, ids, rays = make_ctx(wl, prec, pk.BATCH_ALL, 1)
     rays_per_step = sum(rays)
+    # RGB8, int32 mask, float depth where given
+    kf_bytes = sum(rgb.shape[0] * rgb.shape[1] * (3 + 4 + (4 if depth is not None else 0))
+                   for _, rgb, _, depth in wl.frames)
+    keyframes = {"frames": len(wl.frames), "ms": round(ctx.keyframe_seconds * 1e3, 3),
+                 "MB": round(kf_bytes / 1e6, 1),
+                 "GB_per_s": round(kf_bytes / ctx.keyframe_seconds / 1e9, 2)}
+    log("keyframes", json.dumps(keyframes))
     log(f"{len(ids)} trained objects, {rays_per_step} rays/step")
     dt = timed_steps(ctx, ids, rays, args.warmup, args.steps)
     value = rays_per_step * args.steps / dt
@@ -592,6 +607,7 @@ def main():
         "ablation_density": ablation,
         "mesh": mesh,
         "cpu_baseline": cpu,
+        "keyframe_upload": keyframes,
     }
     print(json.dumps(out), flush=True)
 
