@@ -296,6 +296,38 @@ def test_full_size_workload_sampled():
     assert_grad_close(gg, og, mass, allow, what="grad")
 
 
+def test_largest_table_and_resolution(tiny):
+    """The largest accepted table (2^24 entries) and finest resolution
+    (2^16 cells per axis) on two levels, one dense (16^3 cells) and one
+    hashed: every corner index bit for bit, loss and gradient against the
+    oracle, and one fused Adam step over all of its 2^25 grid parameters."""
+    _say("largest table")
+    frames, box = tiny
+    B = 256
+    g, o, gid = make_pair(2, 16, 1 << 16, 24, 32, B, frames, box)
+    p0 = _set_same_params(g, o, gid, seed=24, grid_scale=1.0).astype(np.float64)
+    ob = o.objects[gid]
+    assert ob.lv.L == 2 and oracle.grid_params(ob.lv) > (1 << 24)
+    rng = np.random.default_rng(24)
+    pts = rng.random((2000, 3)).astype(np.float32)
+    pts[:20] = 1.0
+    idx, feat = g.debug_encode(gid, pts)
+    for i in range(pts.shape[0]):
+        oi, _, oe = oracle.encode(ob.lv, pts[i], ob.params)
+        assert np.array_equal(idx[i], oi), i
+        assert_fwd_close(feat[i].reshape(-1), oe, rtol=1e-5, atol=1e-6, what=f"feat {i}")
+    assert idx.max() >= (1 << 23)
+    gl = g.loss_and_grad([gid])[0]
+    gg = g.get_params(gid, pk.GRAD)
+    ol, og, mass, allow, _ = oracle_grad(o, gid, 0, B)
+    assert_fwd_close([gl], [ol], what="loss")
+    assert_grad_close(gg, og, mass, allow, what="grad")
+    g.train(1, [gid])
+    m, v = np.zeros(p0.size), np.zeros(p0.size)
+    oracle.adam(p0, gg.astype(np.float64), m, v, 1, 1e-2, 0.9, 0.99, 1e-15)
+    assert_fwd_close(g.get_params(gid), p0, rtol=2e-6, atol=2e-8, what="params after step")
+
+
 # ------------------------------------------------------------------ ABI contract
 def test_abi_errors_and_no_partial_state(tiny):
     frames, box = tiny
