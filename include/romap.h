@@ -71,7 +71,8 @@ typedef struct {
   int32_t max_res;         /* N_max */
   int32_t log2_table_size; /* default log2 T for objects registered with 0 */
   int32_t samples_per_ray; /* N: 32, 64 or 128 (uniform samples, Sec. V-B) */
-  int32_t rays_per_step;   /* default rays per object per step (4096 in Sec. VI) */
+  int32_t rays_per_step;   /* default rays per object per step (4096 in Sec. VI);
+                              1..2^22 and rays x samples_per_ray <= 2^27 */
   float lr, beta1, beta2, eps;             /* Adam */
   float lambda_depth, lambda_density;      /* lambda_1, lambda_2 of Eq. 11 */
   float alpha_deg;                         /* keyframe rule threshold of Eq. 5 */
@@ -191,7 +192,8 @@ romap_status romap_add_keyframe(romap_ctx* ctx, const romap_camera* cam, const u
 
 /* Runs n_steps training iterations (draw, render, loss, backward, Adam) on
  * every listed object (NULL = every active object).  rays_per_object: rays
- * per step for each listed object, each in [1, 2^22] (NULL = config
+ * per step for each listed object, each in [1, 2^22] with rays x
+ * samples_per_ray <= 2^27, at most 2^30 over the list (NULL = config
  * default); any other count is ROMAP_E_INVALID_ARG.  An empty list
  * (n_objects = 0) or n_steps = 0 does nothing and succeeds.  stats may be
  * NULL, in which case the call does not wait for the GPU.  Returns
@@ -315,7 +317,9 @@ romap_status romap_debug_bin_capacity(romap_ctx* ctx, int32_t slots);
  * NULL.  Backward recomputes every per-sample activation (nothing is stored
  * between the calls) and writes dL/dparams into d_params_dev (overwritten),
  * given dL/drgb, dL/ddepth, dL/dT_end (any may be NULL = zero).  All
- * pointers are device pointers ordered on the context stream. */
+ * pointers are device pointers ordered on the context stream.  n_rays as
+ * for romap_train (1..2^22, n_rays x samples_per_ray <= 2^27), else
+ * ROMAP_E_INVALID_ARG. */
 romap_status romap_field_forward(romap_ctx* ctx, int32_t object_id, const float* params_dev,
                                  const float* rays_dev, int32_t n_rays, float* rgb_dev,
                                  float* depth_dev, float* tend_dev);

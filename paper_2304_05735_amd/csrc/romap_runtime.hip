@@ -22,6 +22,20 @@ namespace {
 
 std::string g_create_error;
 
+// Ray-count limits.  One object's step writes at most 8 gradient records per
+// sample and level, all of them possibly into one region of a small dense
+// level: rays x samples <= 2^27 keeps that count, the region's bin counter
+// and its capacity within int32.  Ray indices of a step are int32: at most
+// 2^30 rays over the objects of one call.
+constexpr int kMaxRaysPerObject = 1 << 22;
+constexpr int64_t kMaxSamplesPerObject = int64_t(1) << 27;
+constexpr int64_t kMaxRaysPerCall = int64_t(1) << 30;
+
+bool ray_count_ok(int rays, int samples_per_ray) {
+  return rays > 0 && rays <= kMaxRaysPerObject &&
+         (int64_t)rays * samples_per_ray <= kMaxSamplesPerObject;
+}
+
 struct HostKf {
   romap_camera cam;
   uint8_t* d_rgb = nullptr;
@@ -746,7 +760,8 @@ romap_status resolve_list(romap_ctx* c, const int32_t* ids, int32_t n, const int
       for (int j = 0; j < i; ++j)
         if (ids[j] == ids[i]) return fail(c, ROMAP_E_INVALID_ARG, "object listed twice");
       const int b = rays ? rays[i] : c->cfg.rays_per_step;
-      if (b <= 0 || b > (1 << 22)) return fail(c, ROMAP_E_INVALID_ARG, "bad ray count");
+      if (!ray_count_ok(b, c->cfg.samples_per_ray))
+        return fail(c, ROMAP_E_INVALID_ARG, "bad ray count");
       list.push_back({ids[i], b});
     }
   } else {
@@ -754,11 +769,15 @@ romap_status resolve_list(romap_ctx* c, const int32_t* ids, int32_t n, const int
     for (auto& o : c->objs) {
       if (!o.active) continue;
       const int b = rays ? rays[k] : c->cfg.rays_per_step;
-      if (b <= 0 || b > (1 << 22)) return fail(c, ROMAP_E_INVALID_ARG, "bad ray count");
+      if (!ray_count_ok(b, c->cfg.samples_per_ray))
+        return fail(c, ROMAP_E_INVALID_ARG, "bad ray count");
       list.push_back({o.id, b});
       ++k;
     }
   }
+  int64_t total = 0;
+  for (auto& pr : list) total += pr.second;
+  if (total > kMaxRaysPerCall) return fail(c, ROMAP_E_INVALID_ARG, "too many rays in one call");
   for (auto& pr : list)
     if (c->objs[pr.first].kfs.empty())
       return fail(c, ROMAP_E_STATE, "object " + std::to_string(pr.first) + " has no keyframe");
@@ -815,7 +834,7 @@ romap_status romap_create(const romap_config* cfg, void* hip_stream, romap_ctx**
   if (k.mlp_layers < 1 || k.mlp_layers > RM_MAX_MLP_LAYERS)
     return fail(nullptr, ROMAP_E_INVALID_ARG, "mlp_layers must be 1..3");
   if (k.streams != 1 && k.streams != 2) return fail(nullptr, ROMAP_E_INVALID_ARG, "streams must be 1 or 2");
-  if (k.rays_per_step <= 0 || k.rays_per_step > (1 << 22))
+  if (!ray_count_ok(k.rays_per_step, k.samples_per_ray))
     return fail(nullptr, ROMAP_E_INVALID_ARG, "bad rays_per_step");
   if (!(k.lr > 0.0f) || !(k.beta1 >= 0.0f && k.beta1 < 1.0f) || !(k.beta2 >= 0.0f && k.beta2 < 1.0f) ||
       !(k.eps >= 0.0f) || !is_fin(k.lr))
@@ -1936,7 +1955,8 @@ static romap_status field_common(romap_ctx* c, int32_t id, const float* params_d
                                  const float* rays_dev, int32_t n_rays, Plan& p, StepArgs& a) {
   romap_status s = check_object(c, id);
   if (s != ROMAP_OK) return s;
-  if (n_rays <= 0 || !rays_dev) return fail(c, ROMAP_E_INVALID_ARG, "bad rays");
+  if (!rays_dev || !ray_count_ok(n_rays, c->cfg.samples_per_ray))
+    return fail(c, ROMAP_E_INVALID_ARG, "bad rays");
   build_plan(c, {{id, n_rays}}, 8, 256, p);
   p.fins.clear();
   s = stage_plans(c, {&p});

@@ -56,6 +56,10 @@ def test_default_config_and_create_validation_without_gpu():
         c = pk.default_config(**{field: bad})
         assert L.romap_create(ctypes.byref(c), None, ctypes.byref(h)) == pk.ROMAP_E_INVALID_ARG
         assert L.romap_last_error(None)
+    # rays x samples of one object at most 2^27 (int32 record counts per region)
+    for N, rays in [(32, (1 << 22) + 1), (64, (1 << 21) + 1), (128, (1 << 20) + 1)]:
+        c = pk.default_config(samples_per_ray=N, rays_per_step=rays)
+        assert L.romap_create(ctypes.byref(c), None, ctypes.byref(h)) == pk.ROMAP_E_INVALID_ARG
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libromap.so not built")

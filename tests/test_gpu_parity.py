@@ -358,6 +358,18 @@ def test_abi_errors_and_no_partial_state(tiny):
     assert g.object_info(gid).n_keyframes == 1
     with pytest.raises(pk.RomapError):
         g.set_params(gid, np.zeros(3, np.float32))
+    with pytest.raises(pk.RomapError) as e:  # 2^22 rays x 32 samples is the largest step
+        g.train(1, [gid], rays=[(1 << 22) + 1])
+    assert e.value.code == pk.ROMAP_E_INVALID_ARG
+    g128 = pk.Context(pk.default_config(n_levels=2, base_res=16, max_res=32, log2_table_size=8,
+                                        samples_per_ray=128, rays_per_step=64))
+    g128.add_object(1, box["t"], box["yaw"], box["half"])
+    with pytest.raises(pk.RomapError) as e:  # 2^20 + 1 rays x 128 samples > 2^27
+        g128.train(1, [0], rays=[(1 << 20) + 1])
+    assert e.value.code == pk.ROMAP_E_INVALID_ARG
+    with pytest.raises(pk.RomapError) as e:  # 2^20 x 128 is accepted (then: no keyframe)
+        g128.train(1, [0], rays=[1 << 20])
+    assert e.value.code == pk.ROMAP_E_STATE
     st = g.train(2, [gid])
     assert math.isfinite(st.loss_mean) and st.rays_trained == 2 * 4096
     assert g.object_info(gid).step == 2
