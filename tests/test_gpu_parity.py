@@ -328,6 +328,33 @@ def test_largest_table_and_resolution(tiny):
     assert_fwd_close(g.get_params(gid), p0, rtol=2e-6, atol=2e-8, what="params after step")
 
 
+def test_largest_object():
+    """Sixteen hashed levels of 2^24 entries (256 to 2^16 cells per axis):
+    2^29 grid parameters, so the object's gradient and Adam moments start at
+    byte offsets of 2^31 and beyond.  Corner indices bit for bit at sampled
+    points, loss and full gradient of a small batch against the oracle."""
+    _say("largest object")
+    frames, box = tiny_scene(W=32, H=24, n_views=3)
+    B = 64
+    g, o, gid = make_pair(16, 256, 1 << 16, 24, 32, B, frames, box)
+    ob = o.objects[gid]
+    Pg = oracle.grid_params(ob.lv)
+    assert Pg == 1 << 29
+    _set_same_params(g, o, gid, seed=29, grid_scale=1.0)
+    pts = np.random.default_rng(29).random((300, 3)).astype(np.float32)
+    idx, feat = g.debug_encode(gid, pts)
+    for i in range(pts.shape[0]):
+        oi, _, oe = oracle.encode(ob.lv, pts[i], ob.params)
+        assert np.array_equal(idx[i], oi), i
+        assert_fwd_close(feat[i].reshape(-1), oe, rtol=1e-5, atol=1e-6, what=f"feat {i}")
+    gl = g.loss_and_grad([gid])[0]
+    gg = g.get_params(gid, pk.GRAD)
+    ol, og, mass, allow, _ = oracle_grad(o, gid, 0, B)
+    assert_fwd_close([gl], [ol], what="loss")
+    assert_grad_close(gg, og, mass, allow, what="grad")
+    assert np.count_nonzero(gg[Pg - (1 << 25):Pg]) > 0  # the finest level is reached
+
+
 # ------------------------------------------------------------------ ABI contract
 def test_abi_errors_and_no_partial_state(tiny):
     frames, box = tiny
