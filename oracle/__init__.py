@@ -50,7 +50,7 @@ class Config(C.Structure):
 class Levels(C.Structure):
     _fields_ = [("L", C.c_int32), ("N", C.c_int32 * MAX_LEVELS), ("T", C.c_int64 * MAX_LEVELS),
                 ("hashed", C.c_int32 * MAX_LEVELS), ("off", C.c_int64 * (MAX_LEVELS + 1)),
-                ("mlp_layers", C.c_int32)]
+                ("mlp_layers", C.c_int32), ("mlp_bf16", C.c_int32)]
 
 
 class Keyframe(C.Structure):
@@ -89,18 +89,23 @@ def lib():
                                       C.c_int, C.c_int, P, P]
         _lib.or_object_frame.argtypes = [P, P, C.c_float, P, P]
         _lib.or_encode.argtypes = [C.POINTER(Levels), P, P, P, P, P]
-        _lib.or_mlp_forward.argtypes = [C.c_int, C.c_int, P, P, P, P, P, P, P]
+        _lib.or_mlp_forward.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, P]
+        _lib.or_bf16.argtypes = [C.c_double]
+        _lib.or_bf16.restype = C.c_double
+        _lib.or_bf16_gap.argtypes = [C.c_double]
+        _lib.or_bf16_gap.restype = C.c_double
+        _lib.or_bf16_set_jitter.argtypes = [C.c_double]
         _lib.or_composite.argtypes = [C.c_int, P, P, P, C.c_double, C.c_int, P, P, P, P, P]
         _lib.or_candidate_rect.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P]
         _lib.or_draw_ray.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, C.c_int,
                                      C.POINTER(Keyframe), C.c_int, C.POINTER(Ray)]
         _lib.or_object_step.argtypes = [C.POINTER(Config), C.POINTER(Levels), C.c_int, C.c_int, P,
                                         C.c_int, C.POINTER(Keyframe), C.c_int, C.c_int, P, P, P, P,
-                                        P, P, P, C.POINTER(Ray), C.c_int]
+                                        P, P, P, P, C.POINTER(Ray), C.c_int]
         _lib.or_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int, C.c_double, C.c_double,
                                  C.c_double, C.c_double]
         _lib.or_render.argtypes = [C.POINTER(Config), C.POINTER(Levels), P, C.POINTER(Keyframe), P,
-                                   P, P, P, P, C.c_int]
+                                   P, P, P, P, P, C.c_int]
         _lib.or_query_density.argtypes = [C.POINTER(Levels), P, P, C.c_int64, P, P]
         _lib.or_philox4x32_10.argtypes = [P, P, P]
         _lib.or_box_from_points.argtypes = [P, C.c_int64, P, P, P]
@@ -170,15 +175,17 @@ def philox(ctr, key) -> np.ndarray:
     return out
 
 
-def levels(L, nmin, nmax, log2T, mlp_layers=1) -> Levels:
+def levels(L, nmin, nmax, log2T, mlp_layers=1, bf16=False) -> Levels:
     """Level table of an object's grid; mlp_layers = hidden layers of its
-    density MLP (1, 2 or 3)."""
+    density MLP (1, 2 or 3); bf16: the MLP's BF16 mode (operands of every
+    contraction rounded to BF16, see bf16())."""
     if mlp_layers not in (1, 2, 3):
         raise ValueError("mlp_layers must be 1, 2 or 3")
     lv = Levels()
     if lib().or_make_levels(L, nmin, nmax, log2T, C.byref(lv)) != 0:
         raise ValueError("bad level parameters")
     lv.mlp_layers = mlp_layers
+    lv.mlp_bf16 = 1 if bf16 else 0
     return lv
 
 
@@ -240,8 +247,27 @@ def encode(lv: Levels, p, grid):
     return idx.reshape(L, 8), w.reshape(L, 8), e
 
 
-def mlp_forward(din, mlp, e, layers=1):
-    """h1: the density MLP's hidden activations, 64 per layer."""
+def bf16(x) -> float:
+    """x rounded to BF16 (8 significant bits, nearest, ties to even)."""
+    return float(lib().or_bf16(float(x)))
+
+
+def bf16_gap(x) -> float:
+    """Distance from x to the nearest midpoint between BF16 values."""
+    return float(lib().or_bf16_gap(float(x)))
+
+
+def set_bf16_jitter(rel: float) -> None:
+    """Tests only: move every rounded BF16 operand (not the weights) by at most
+    rel |x| before it is rounded, imitating a computation with rounding
+    error; 0 switches it off."""
+    lib().or_bf16_set_jitter(float(rel))
+
+
+def mlp_forward(din, mlp, e, layers=1, bf16=False):
+    """h1: the density MLP's hidden activations, 64 per layer.  bf16: the BF16
+    mode (weights and every layer's input rounded where a contraction reads
+    them)."""
     mlp = np.ascontiguousarray(mlp, np.float64)
     e = np.ascontiguousarray(e, np.float64)
     assert mlp.size >= mlp_params(din, layers)
@@ -250,7 +276,8 @@ def mlp_forward(din, mlp, e, layers=1):
     h2 = np.zeros(HIDDEN)
     sigma = np.zeros(1)
     rgb = np.zeros(3)
-    lib().or_mlp_forward(din, layers, _p(mlp), _p(e), _p(h1), _p(y), _p(h2), _p(sigma), _p(rgb))
+    lib().or_mlp_forward(din, layers, 1 if bf16 else 0, _p(mlp), _p(e), _p(h1), _p(y), _p(h2),
+                         _p(sigma), _p(rgb))
     return dict(h1=h1, y=y, h2=h2, sigma=float(sigma[0]), rgb=rgb)
 
 
@@ -284,6 +311,15 @@ def adam(p, g, m, v, k, lr, b1, b2, eps):
 
 # --------------------------------------------------------------------------
 # object / keyframe bookkeeping (same semantics as the GPU library's C ABI)
+
+def host_threads() -> int:
+    """Host threads the oracle uses by default: every core this process may
+    run on."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
+
 
 def make_config(L=16, nmin=16, nmax=1024, log2T=19, N=64, margin_pct=10, lambda_depth=0.5,
                 lambda_density=0.01, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, seed=0) -> Config:
@@ -326,18 +362,19 @@ class OracleContext:
     """Plain CPU counterpart of the GPU library's context (same verbs)."""
 
     def __init__(self, cfg: Config, alpha_deg: float = 25.0, nthreads: int | None = None,
-                 mlp_layers: int = 1):
+                 mlp_layers: int = 1, bf16: bool = False):
         self.cfg = cfg
         self.mlp_layers = mlp_layers
+        self.bf16 = bf16
         self.alpha_deg = alpha_deg
-        self.nthreads = nthreads or min(16, os.cpu_count() or 1)
+        self.nthreads = nthreads or host_threads()
         self.objects: list[_Obj] = []
         self.keyframes: list[_Kf] = []
 
     # register object with box and table size (Sec. V: a new model per new instance)
     def add_object(self, instance, t, yaw, half, log2T=None, params=None) -> int:
         log2T = self.cfg.log2T if log2T is None else log2T
-        lv = levels(self.cfg.L, self.cfg.nmin, self.cfg.nmax, log2T, self.mlp_layers)
+        lv = levels(self.cfg.L, self.cfg.nmin, self.cfg.nmax, log2T, self.mlp_layers, self.bf16)
         P = grid_params(lv) + mlp_params(2 * self.cfg.L, self.mlp_layers)
         p = np.zeros(P) if params is None else np.array(params, np.float64)
         assert p.size == P
@@ -384,7 +421,7 @@ class OracleContext:
         return arr
 
     def loss_and_grad(self, oid, step, B, rays=False, params=None, want_grad=True, mass=None,
-                      ambiguous=None, margin=None):
+                      ambiguous=None, margin=None, loss_allow=None):
         """Loss of one step and dL/dparams (no optimiser update).  mass: an array
         of the parameter count that receives the magnitude of every gradient
         entry, the same backward on absolute values, which bounds to first order
@@ -394,7 +431,11 @@ class OracleContext:
         1e-5 relative of a tie, the magnitude of their contributions with every
         branch taken: how far another branch choice can move each entry.
         margin: a 1-element array that receives the smallest relative distance
-        of a decision from its tie in the step."""
+        of a decision from its tie in the step.
+        loss_allow (BF16 mode): a 1-element array that receives the bound of
+        the change of the loss under the other choice of every ambiguous BF16
+        rounding (ambiguous then also holds that change for every gradient
+        entry)."""
         o = self.objects[oid]
         if not o.kfs:
             raise RuntimeError("object has no keyframes")
@@ -410,7 +451,8 @@ class OracleContext:
                                   _p(mass) if (want_grad and mass is not None) else None,
                                   None if ambiguous is None else _p(ambiguous),
                                   None if margin is None else _p(margin),
-                                  _p(loss), ray_buf, self.nthreads)
+                                  _p(loss), None if loss_allow is None else _p(loss_allow),
+                                  ray_buf, self.nthreads)
         if rc != 0:
             raise RuntimeError("oracle step failed")
         return float(loss[0]), grad, ray_buf
@@ -428,7 +470,10 @@ class OracleContext:
             losses.append(loss)
         return losses
 
-    def render(self, oid, cam, W, H):
+    def render(self, oid, cam, W, H, rgb_allow=None):
+        """rgb_allow (BF16 mode): an (H, W, 3) array that receives the bound of
+        the change of each colour under the other choice of every ambiguous
+        BF16 rounding."""
         o = self.objects[oid]
         kf = Keyframe()
         M, c = object_frame(np.asarray(cam["T_wc"], np.float32), o.t, o.yaw)
@@ -441,7 +486,7 @@ class OracleContext:
         opac = np.zeros((H, W))
         lib().or_render(C.byref(self.cfg), C.byref(o.lv), _p(o.half), C.byref(kf), _p(o.params),
                         None if o.occ is None else _p(o.occ), _p(rgb), _p(depth), _p(opac),
-                        self.nthreads)
+                        None if rgb_allow is None else _p(rgb_allow), self.nthreads)
         return rgb, depth, opac
 
     def field(self, oid, rays, params=None, d_rgb=None, d_depth=None, d_tend=None, grad=False,

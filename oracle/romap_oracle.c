@@ -12,7 +12,8 @@
  * hash-index path, which is IEEE FP32 in the fixed expression order written
  * below (build with -ffp-contract=off).  That path decides integers (grid
  * cells, hash indices), so both sides must take those decisions in the same
- * precision.
+ * precision.  A BF16 mode of the MLP (or_levels.mlp_bf16) rounds every
+ * operand of an MLP contraction to BF16 and keeps the rest FP64 (or_bf16).
  *
  * Readings where the paper is silent (all listed in the design notes):
  *  - hash grid: the multiresolution hash encoding the paper cites
@@ -219,14 +220,77 @@ void or_encode(const or_levels* lv, const float p[3], const double* grid, uint32
   }
 }
 
+/* BF16 mode of the MLP.  The paper does not state its precision; this mode
+ * is the precision choice of the GPU path's "BF16 MLP": every operand of an
+ * MLP contraction -- the weights, each layer's input, each adjoint entering
+ * a contraction, and both factors of every weight-gradient outer product --
+ * is rounded to BF16 (IEEE binary32's exponent range with 8 significant
+ * bits, round to nearest, ties to even); sums, activations, compositing,
+ * the loss and the encoding stay FP64. */
+double or_bf16(double x) {
+  if (x == 0.0 || !isfinite(x)) return x;
+  if (fabs(x) < 0x1p-126) /* BF16 subnormals: multiples of 2^-133 */
+    return ldexp(nearbyint(ldexp(x, 133)), -133);
+  /* keep 7 of the 52 stored fraction bits; the dropped 45 bits round to
+   * nearest, ties to the even kept value (a carry may move to the next
+   * binade, which is the correct result) */
+  uint64_t u;
+  memcpy(&u, &x, sizeof u);
+  const int drop = 45;
+  u += (((uint64_t)1 << (drop - 1)) - 1) + ((u >> drop) & 1u);
+  u &= ~(((uint64_t)1 << drop) - 1);
+  memcpy(&x, &u, sizeof x);
+  return x;
+}
+
+/* Distance from x to the nearest point where or_bf16 changes its result (a
+ * midpoint between two neighbouring BF16 values).  Test infrastructure: a
+ * value within rounding error of such a point may round either way. */
+double or_bf16_gap(double x) {
+  if (x == 0.0 || !isfinite(x)) return INFINITY;
+  int ex;
+  frexp(x, &ex); /* |x| in [2^(ex-1), 2^ex) */
+  int q = ex - 8;
+  if (q < -133) q = -133;
+  const double s = fabs(ldexp(x, -q)); /* in [128, 256) for normal values */
+  return fabs(s - floor(s) - 0.5) * ldexp(1.0, q);
+}
+
+/* Tests only: with a nonzero jitter every rounded operand other than a
+ * weight is first moved by at most rel |x| (a deterministic function of x),
+ * which imitates a computation of it with rounding error; the BF16
+ * allowances of the tests must cover the change this makes. */
+static double g_bf16_jitter = 0.0;
+void or_bf16_set_jitter(double rel) { g_bf16_jitter = rel; }
+
+static double jitter(double x) {
+  uint64_t u;
+  memcpy(&u, &x, sizeof u);
+  u += 0x9E3779B97F4A7C15ull; /* splitmix64 finaliser of the bits of x */
+  u = (u ^ (u >> 30)) * 0xBF58476D1CE4E5B9ull;
+  u = (u ^ (u >> 27)) * 0x94D049BB133111EBull;
+  u ^= u >> 31;
+  const double h = (double)(u >> 11) * 0x1p-53 * 2.0 - 1.0; /* [-1, 1) */
+  return x * (1.0 + g_bf16_jitter * h);
+}
+
+/* an operand of a contraction (activation or adjoint) */
+static inline double rbf(int on, double x) {
+  return on ? or_bf16(g_bf16_jitter != 0.0 ? jitter(x) : x) : x;
+}
+/* a weight (an FP32 value on either side: never jittered) */
+static inline double rbw(int on, double x) { return on ? or_bf16(x) : x; }
+
 /* Density / colour MLP (Sec. V: a single hidden layer of 64 per head; position
  * only, no view direction, Sec. V-B; the model-size study of Table 4 also
  * trains density MLPs of 2 and 3 hidden layers).  h_0 = ReLU(W1 e),
  * h_k = ReLU(Wh_k h_{k-1}) for k < layers, y = W2 h_{layers-1},
  * sigma = exp(min(y0, 15)), h2 = ReLU(W3 y[1..15]), rgb = sigmoid(W4 h2).
- * h1 receives the layers hidden activations, 64 each. */
-void or_mlp_forward(int din, int layers, const double* mlp, const double* e, double* h1, double* y,
-                    double* h2, double* sigma, double* rgb) {
+ * h1 receives the layers hidden activations, 64 each (unrounded).  With
+ * bf16, every weight and every layer input is rounded by or_bf16 where a
+ * contraction reads it. */
+void or_mlp_forward(int din, int layers, int bf16, const double* mlp, const double* e, double* h1,
+                    double* y, double* h2, double* sigma, double* rgb) {
   const double* W1 = mlp;
   const double* Wh = W1 + OR_HIDDEN * din;
   const double* W2 = Wh + (layers - 1) * OR_HIDDEN * OR_HIDDEN;
@@ -234,7 +298,7 @@ void or_mlp_forward(int din, int layers, const double* mlp, const double* e, dou
   const double* W4 = W3 + OR_HIDDEN * OR_GEO;
   for (int i = 0; i < OR_HIDDEN; ++i) {
     double s = 0.0;
-    for (int j = 0; j < din; ++j) s += W1[i * din + j] * e[j];
+    for (int j = 0; j < din; ++j) s += rbw(bf16, W1[i * din + j]) * rbf(bf16, e[j]);
     h1[i] = s > 0.0 ? s : 0.0;
   }
   for (int k = 1; k < layers; ++k) {
@@ -243,25 +307,25 @@ void or_mlp_forward(int din, int layers, const double* mlp, const double* e, dou
     double* hn = h1 + k * OR_HIDDEN;
     for (int i = 0; i < OR_HIDDEN; ++i) {
       double s = 0.0;
-      for (int j = 0; j < OR_HIDDEN; ++j) s += W[i * OR_HIDDEN + j] * hp[j];
+      for (int j = 0; j < OR_HIDDEN; ++j) s += rbw(bf16, W[i * OR_HIDDEN + j]) * rbf(bf16, hp[j]);
       hn[i] = s > 0.0 ? s : 0.0;
     }
   }
   const double* hl = h1 + (layers - 1) * OR_HIDDEN;
   for (int i = 0; i < OR_DOUT; ++i) {
     double s = 0.0;
-    for (int j = 0; j < OR_HIDDEN; ++j) s += W2[i * OR_HIDDEN + j] * hl[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) s += rbw(bf16, W2[i * OR_HIDDEN + j]) * rbf(bf16, hl[j]);
     y[i] = s;
   }
   *sigma = exp(fmin(y[0], 15.0));
   for (int i = 0; i < OR_HIDDEN; ++i) {
     double s = 0.0;
-    for (int j = 0; j < OR_GEO; ++j) s += W3[i * OR_GEO + j] * y[1 + j];
+    for (int j = 0; j < OR_GEO; ++j) s += rbw(bf16, W3[i * OR_GEO + j]) * rbf(bf16, y[1 + j]);
     h2[i] = s > 0.0 ? s : 0.0;
   }
   for (int i = 0; i < 3; ++i) {
     double s = 0.0;
-    for (int j = 0; j < OR_HIDDEN; ++j) s += W4[i * OR_HIDDEN + j] * h2[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) s += rbw(bf16, W4[i * OR_HIDDEN + j]) * rbf(bf16, h2[j]);
     rgb[i] = 1.0 / (1.0 + exp(-s));
   }
 }
@@ -375,6 +439,8 @@ typedef struct {
   double *w, *e, *h1, *y, *h2, *sigma, *rgb, *dist, *wts, *dsig, *dsig_m, *tnext;
   float *pos, *dist32;
   int* live; /* sample not skipped by the occupancy bitfield */
+  struct or_fpert_s* fp; /* tests only: BF16 forward bounds (bf16_ray_allowance) */
+  int fp_valid;          /* fp holds the bounds of the current ray */
 } or_scratch;
 
 static void scratch_alloc(or_scratch* s, int N, int L, int layers) {
@@ -394,22 +460,28 @@ static void scratch_alloc(or_scratch* s, int N, int L, int layers) {
   s->pos = (float*)malloc(sizeof(float) * N * 3);
   s->dist32 = (float*)malloc(sizeof(float) * N);
   s->live = (int*)malloc(sizeof(int) * N);
+  s->fp = NULL; /* allocated on first use (BF16 mode, tests) */
+  s->fp_valid = 0;
 }
 
 static void scratch_free(or_scratch* s) {
   free(s->idx); free(s->w); free(s->e); free(s->h1); free(s->y); free(s->h2);
   free(s->sigma); free(s->rgb); free(s->dist); free(s->wts); free(s->dsig); free(s->dsig_m); free(s->tnext);
   free(s->pos); free(s->dist32); free(s->live);
+  free(s->fp);
 }
 
 /* Backward of one sample through the MLPs and the encoding.  dsig, dc are
  * dl/dsigma and dl/dc of this sample; adds into grad (grid, then MLP).  h1
- * holds the hidden activations of the density MLP's lv->mlp_layers layers. */
+ * holds the hidden activations of the density MLP's lv->mlp_layers layers.
+ * In BF16 mode (lv->mlp_bf16) every operand of a contraction is rounded by
+ * or_bf16, as in the forward: the weights, the adjoint entering each
+ * transposed product, and both factors of each weight-gradient product. */
 static void sample_backward(const or_levels* lv, int din, const double* mlp, const uint32_t* idx,
                             const double* w, const double* e, const double* h1, const double* y,
                             const double* h2, double sigma, const double* rgb, double dsig,
                             const double* dc, double* grad) {
-  const int nh = lv->mlp_layers;
+  const int nh = lv->mlp_layers, bf = lv->mlp_bf16;
   const double* W1 = mlp;
   const double* Wh = W1 + OR_HIDDEN * din;
   const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
@@ -425,27 +497,27 @@ static void sample_backward(const or_levels* lv, int din, const double* mlp, con
       de[2 * OR_MAX_LEVELS];
   for (int k = 0; k < 3; ++k) dz4[k] = dc[k] * rgb[k] * (1.0 - rgb[k]);
   for (int k = 0; k < 3; ++k)
-    for (int j = 0; j < OR_HIDDEN; ++j) gW4[k * OR_HIDDEN + j] += dz4[k] * h2[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) gW4[k * OR_HIDDEN + j] += rbf(bf, dz4[k]) * rbf(bf, h2[j]);
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double s = 0.0;
-    for (int k = 0; k < 3; ++k) s += W4[k * OR_HIDDEN + j] * dz4[k];
+    for (int k = 0; k < 3; ++k) s += rbw(bf, W4[k * OR_HIDDEN + j]) * rbf(bf, dz4[k]);
     dh2[j] = h2[j] > 0.0 ? s : 0.0;
   }
   for (int j = 0; j < OR_HIDDEN; ++j)
-    for (int g = 0; g < OR_GEO; ++g) gW3[j * OR_GEO + g] += dh2[j] * y[1 + g];
+    for (int g = 0; g < OR_GEO; ++g) gW3[j * OR_GEO + g] += rbf(bf, dh2[j]) * rbf(bf, y[1 + g]);
   for (int g = 0; g < OR_GEO; ++g) {
     double s = 0.0;
-    for (int j = 0; j < OR_HIDDEN; ++j) s += W3[j * OR_GEO + g] * dh2[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) s += rbw(bf, W3[j * OR_GEO + g]) * rbf(bf, dh2[j]);
     dy[1 + g] = s;
   }
   dy[0] = y[0] < 15.0 ? dsig * sigma : 0.0;
   /* last hidden layer */
   const double* hl = h1 + (nh - 1) * OR_HIDDEN;
   for (int i = 0; i < OR_DOUT; ++i)
-    for (int j = 0; j < OR_HIDDEN; ++j) gW2[i * OR_HIDDEN + j] += dy[i] * hl[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) gW2[i * OR_HIDDEN + j] += rbf(bf, dy[i]) * rbf(bf, hl[j]);
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double s = 0.0;
-    for (int i = 0; i < OR_DOUT; ++i) s += W2[i * OR_HIDDEN + j] * dy[i];
+    for (int i = 0; i < OR_DOUT; ++i) s += rbw(bf, W2[i * OR_HIDDEN + j]) * rbf(bf, dy[i]);
     dh[j] = hl[j] > 0.0 ? s : 0.0;
   }
   /* hidden-to-hidden layers, last to first: dh is the adjoint of h_k */
@@ -454,19 +526,19 @@ static void sample_backward(const or_levels* lv, int din, const double* mlp, con
     double* gW = gWh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
     const double* hp = h1 + (k - 1) * OR_HIDDEN;
     for (int i = 0; i < OR_HIDDEN; ++i)
-      for (int j = 0; j < OR_HIDDEN; ++j) gW[i * OR_HIDDEN + j] += dh[i] * hp[j];
+      for (int j = 0; j < OR_HIDDEN; ++j) gW[i * OR_HIDDEN + j] += rbf(bf, dh[i]) * rbf(bf, hp[j]);
     for (int j = 0; j < OR_HIDDEN; ++j) {
       double s = 0.0;
-      for (int i = 0; i < OR_HIDDEN; ++i) s += W[i * OR_HIDDEN + j] * dh[i];
+      for (int i = 0; i < OR_HIDDEN; ++i) s += rbw(bf, W[i * OR_HIDDEN + j]) * rbf(bf, dh[i]);
       dp[j] = hp[j] > 0.0 ? s : 0.0;
     }
     memcpy(dh, dp, sizeof(dh));
   }
   for (int j = 0; j < OR_HIDDEN; ++j)
-    for (int q = 0; q < din; ++q) gW1[j * din + q] += dh[j] * e[q];
+    for (int q = 0; q < din; ++q) gW1[j * din + q] += rbf(bf, dh[j]) * rbf(bf, e[q]);
   for (int q = 0; q < din; ++q) {
     double s = 0.0;
-    for (int j = 0; j < OR_HIDDEN; ++j) s += W1[j * din + q] * dh[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) s += rbw(bf, W1[j * din + q]) * rbf(bf, dh[j]);
     de[q] = s;
   }
   for (int l = 0; l < lv->L; ++l)
@@ -488,7 +560,7 @@ static void sample_backward_magnitude(const or_levels* lv, int din, const double
                                       const double* h1, const double* y, const double* h2,
                                       double sigma, const double* rgb, double dsig_m,
                                       const double* dc_m, int all_branches, double* mag) {
-  const int nh = lv->mlp_layers;
+  const int nh = lv->mlp_layers, bf = lv->mlp_bf16;
   const double* W1 = mlp;
   const double* Wh = W1 + OR_HIDDEN * din;
   const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
@@ -500,30 +572,31 @@ static void sample_backward_magnitude(const or_levels* lv, int din, const double
   double* mW2 = mWh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
   double* mW3 = mW2 + OR_DOUT * OR_HIDDEN;
   double* mW4 = mW3 + OR_HIDDEN * OR_GEO;
+#define A(x) fabs(rbf(bf, (x)))
   double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], dh[OR_HIDDEN], dp[OR_HIDDEN],
       de[2 * OR_MAX_LEVELS];
   for (int k = 0; k < 3; ++k) dz4[k] = dc_m[k] * rgb[k] * (1.0 - rgb[k]);
   for (int k = 0; k < 3; ++k)
-    for (int j = 0; j < OR_HIDDEN; ++j) mW4[k * OR_HIDDEN + j] += dz4[k] * h2[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) mW4[k * OR_HIDDEN + j] += A(dz4[k]) * A(h2[j]);
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double s = 0.0;
-    for (int k = 0; k < 3; ++k) s += fabs(W4[k * OR_HIDDEN + j]) * dz4[k];
+    for (int k = 0; k < 3; ++k) s += A(W4[k * OR_HIDDEN + j]) * A(dz4[k]);
     dh2[j] = (h2[j] > 0.0 || all_branches) ? s : 0.0;
   }
   for (int j = 0; j < OR_HIDDEN; ++j)
-    for (int g = 0; g < OR_GEO; ++g) mW3[j * OR_GEO + g] += dh2[j] * fabs(y[1 + g]);
+    for (int g = 0; g < OR_GEO; ++g) mW3[j * OR_GEO + g] += A(dh2[j]) * A(y[1 + g]);
   for (int g = 0; g < OR_GEO; ++g) {
     double s = 0.0;
-    for (int j = 0; j < OR_HIDDEN; ++j) s += fabs(W3[j * OR_GEO + g]) * dh2[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) s += A(W3[j * OR_GEO + g]) * A(dh2[j]);
     dy[1 + g] = s;
   }
   dy[0] = (y[0] < 15.0 || all_branches) ? dsig_m * sigma : 0.0;
   const double* hl = h1 + (nh - 1) * OR_HIDDEN;
   for (int i = 0; i < OR_DOUT; ++i)
-    for (int j = 0; j < OR_HIDDEN; ++j) mW2[i * OR_HIDDEN + j] += dy[i] * hl[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) mW2[i * OR_HIDDEN + j] += A(dy[i]) * A(hl[j]);
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double s = 0.0;
-    for (int i = 0; i < OR_DOUT; ++i) s += fabs(W2[i * OR_HIDDEN + j]) * dy[i];
+    for (int i = 0; i < OR_DOUT; ++i) s += A(W2[i * OR_HIDDEN + j]) * A(dy[i]);
     dh[j] = (hl[j] > 0.0 || all_branches) ? s : 0.0;
   }
   for (int k = nh - 1; k >= 1; --k) {
@@ -531,21 +604,22 @@ static void sample_backward_magnitude(const or_levels* lv, int din, const double
     double* mW = mWh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
     const double* hp = h1 + (k - 1) * OR_HIDDEN;
     for (int i = 0; i < OR_HIDDEN; ++i)
-      for (int j = 0; j < OR_HIDDEN; ++j) mW[i * OR_HIDDEN + j] += dh[i] * hp[j];
+      for (int j = 0; j < OR_HIDDEN; ++j) mW[i * OR_HIDDEN + j] += A(dh[i]) * A(hp[j]);
     for (int j = 0; j < OR_HIDDEN; ++j) {
       double s = 0.0;
-      for (int i = 0; i < OR_HIDDEN; ++i) s += fabs(W[i * OR_HIDDEN + j]) * dh[i];
+      for (int i = 0; i < OR_HIDDEN; ++i) s += A(W[i * OR_HIDDEN + j]) * A(dh[i]);
       dp[j] = (hp[j] > 0.0 || all_branches) ? s : 0.0;
     }
     memcpy(dh, dp, sizeof(dh));
   }
   for (int j = 0; j < OR_HIDDEN; ++j)
-    for (int q = 0; q < din; ++q) mW1[j * din + q] += dh[j] * fabs(e[q]);
+    for (int q = 0; q < din; ++q) mW1[j * din + q] += A(dh[j]) * A(e[q]);
   for (int q = 0; q < din; ++q) {
     double s = 0.0;
-    for (int j = 0; j < OR_HIDDEN; ++j) s += fabs(W1[j * din + q]) * dh[j];
+    for (int j = 0; j < OR_HIDDEN; ++j) s += A(W1[j * din + q]) * A(dh[j]);
     de[q] = s;
   }
+#undef A
   for (int l = 0; l < lv->L; ++l)
     for (int b = 0; b < 8; ++b) {
       int64_t at = lv->off[l] + 2 * (int64_t)idx[8 * l + b];
@@ -580,11 +654,12 @@ static void ray_forward(const or_levels* lv, int N, const double* params, const 
   const int L = lv->L, din = 2 * L, nh = lv->mlp_layers;
   const double* mlp = params + or_grid_params(lv);
   or_sample_positions(o, d, half, tn, tf, N, delta, s->dist32, s->pos);
+  s->fp_valid = 0;
   for (int i = 0; i < N; ++i) s->dist[i] = (double)s->dist32[i];
   for (int i = 0; i < N; ++i) {
     s->live[i] = or_occupied(occ, s->pos + 3 * i);
     or_encode(lv, s->pos + 3 * i, params, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i);
-    or_mlp_forward(din, nh, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
+    or_mlp_forward(din, nh, lv->mlp_bf16, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
                    s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma + i, s->rgb + 3 * i);
     if (!s->live[i]) s->sigma[i] = 0.0;
   }
@@ -649,47 +724,378 @@ static void ray_backward(const or_levels* lv, int N, const double* params, doubl
  * error) that a computation with rounding error could take the other way.
  * The relative distance of a decision from its tie is |pre-activation| over
  * the sum of |terms| that form it; sample_ties returns the smallest one over
- * the sample's decisions. */
-static double sample_ties(int din, int nh, const double* mlp, const double* e, const double* h1,
-                          const double* y) {
+ * the sample's decisions.  In BF16 mode the pre-activations are formed from
+ * the rounded operands, and F (may be NULL) holds how far the BF16 decisions
+ * upstream can move each pre-activation: that distance is taken off. */
+struct or_fpert_s;
+static double sample_ties(const or_levels* lv, const double* mlp, const double* e,
+                          const double* h1, const double* y, const struct or_fpert_s* F);
+/* ---- BF16 rounding decisions (test infrastructure) ------------------------
+ * In BF16 mode each rounded operand is a discrete decision.  The GPU forms
+ * the value in FP32, the oracle in FP64: a value within FP32 rounding error
+ * of a BF16 midpoint may round to either neighbour, and both results are
+ * correct.  The functions below bound, per gradient entry, how far the
+ * other choices can move the result.  Each value x carries a bound P_x of
+ * how far such choices upstream can move it; its rounding can flip when
+ * its distance to the nearest midpoint is at most P_x + OR_KBF16 s_x, with
+ * s_x the error scale of its own FP32 computation (the sum of |terms| that
+ * form it: exact BF16 products, so only the FP32 sum rounds, at most about
+ * 64 FP32 units of s_x for a 64-term sum in any order), and a flip adds one
+ * BF16 unit in the last place to P.  Bounds combine as
+ * P(a b) <= |a| P_b + P_a |b| + P_a P_b and P(sum) <= sum P (rigorous for
+ * the products and sums; first order through exp and the sigmoid). */
+#define OR_KBF16 4e-6
+
+/* one BF16 unit in the last place at x (the spacing of BF16 values there) */
+static double bf16_ulp(double x) {
+  if (x == 0.0 || !isfinite(x)) return 0.0;
+  int ex;
+  frexp(x, &ex);
+  int q = ex - 8;
+  if (q < -133) q = -133;
+  return ldexp(1.0, q);
+}
+
+/* perturbation bound of the rounded value of x, given the bound Px of x */
+static double bf16_pert(double x, double Px, double scale) {
+  return Px + (or_bf16_gap(x) <= Px + OR_KBF16 * scale ? bf16_ulp(x) : 0.0);
+}
+
+typedef struct or_fpert_s {   /* perturbation bounds of one sample's forward */
+  double Pe[2 * OR_MAX_LEVELS];              /* rounded encodings */
+  double Ppre[OR_HIDDEN * OR_MAX_MLP_LAYERS]; /* hidden pre-activations */
+  double Ph[OR_HIDDEN * OR_MAX_MLP_LAYERS];   /* rounded hidden activations */
+  double Py[OR_DOUT];                         /* y (unrounded) */
+  double Pyr[OR_DOUT];                        /* rounded y */
+  double Ppre2[OR_HIDDEN], Ph2[OR_HIDDEN];    /* colour head */
+  double Pz[3];                               /* colour logits */
+} or_fpert;
+
+static double sample_ties(const or_levels* lv, const double* mlp, const double* e,
+                          const double* h1, const double* y, const struct or_fpert_s* F) {
+  const int din = 2 * lv->L, nh = lv->mlp_layers, bf = lv->mlp_bf16;
   const double* W1 = mlp;
   const double* Wh = W1 + OR_HIDDEN * din;
   const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
   const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
   double m = INFINITY;
-  for (int j = 0; j < OR_HIDDEN; ++j) {
-    double pre = 0.0, mag = 0.0;
-    for (int q = 0; q < din; ++q) {
-      pre += W1[j * din + q] * e[q];
-      mag += fabs(W1[j * din + q] * e[q]);
-    }
-    if (mag > 0.0) m = fmin(m, fabs(pre) / mag);
-  }
-  for (int k = 1; k < nh; ++k) {
-    const double* W = Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
-    const double* hp = h1 + (k - 1) * OR_HIDDEN;
+  for (int k = 0; k < nh; ++k) {
+    const double* W = k == 0 ? W1 : Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    const double* x = k == 0 ? e : h1 + (k - 1) * OR_HIDDEN;
+    const int K = k == 0 ? din : OR_HIDDEN;
     for (int i = 0; i < OR_HIDDEN; ++i) {
       double pre = 0.0, mag = 0.0;
-      for (int j = 0; j < OR_HIDDEN; ++j) {
-        pre += W[i * OR_HIDDEN + j] * hp[j];
-        mag += fabs(W[i * OR_HIDDEN + j] * hp[j]);
+      for (int j = 0; j < K; ++j) {
+        const double t = rbw(bf, W[i * K + j]) * rbf(bf, x[j]);
+        pre += t;
+        mag += fabs(t);
       }
-      if (mag > 0.0) m = fmin(m, fabs(pre) / mag);
+      const double P = F ? F->Ppre[k * OR_HIDDEN + i] : 0.0;
+      if (mag > 0.0) m = fmin(m, (fabs(pre) - P) / mag);
     }
   }
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double pre = 0.0, mag = 0.0;
     for (int g = 0; g < OR_GEO; ++g) {
-      pre += W3[j * OR_GEO + g] * y[1 + g];
-      mag += fabs(W3[j * OR_GEO + g] * y[1 + g]);
+      const double t = rbw(bf, W3[j * OR_GEO + g]) * rbf(bf, y[1 + g]);
+      pre += t;
+      mag += fabs(t);
     }
-    if (mag > 0.0) m = fmin(m, fabs(pre) / mag);
+    const double P = F ? F->Ppre2[j] : 0.0;
+    if (mag > 0.0) m = fmin(m, (fabs(pre) - P) / mag);
   }
   const double* hl = h1 + (nh - 1) * OR_HIDDEN;
   double mag0 = 0.0;
-  for (int j = 0; j < OR_HIDDEN; ++j) mag0 += fabs(W2[j] * hl[j]);
-  if (mag0 > 0.0) m = fmin(m, fabs(y[0] - 15.0) / mag0);
+  for (int j = 0; j < OR_HIDDEN; ++j) mag0 += fabs(rbw(bf, W2[j]) * rbf(bf, hl[j]));
+  const double P0 = F ? F->Py[0] : 0.0;
+  if (mag0 > 0.0) m = fmin(m, (fabs(y[0] - 15.0) - P0) / mag0);
   return m;
+}
+
+static void bf16_forward_pert(const or_levels* lv, const double* grid, const double* mlp,
+                              const uint32_t* idx, const double* w, const double* e,
+                              const double* h1, const double* y, const double* h2, or_fpert* F) {
+  const int L = lv->L, din = 2 * L, nh = lv->mlp_layers, bf = lv->mlp_bf16;
+  const double* W1 = mlp;
+  const double* Wh = W1 + OR_HIDDEN * din;
+  const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
+  const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
+  const double* W4 = W3 + OR_HIDDEN * OR_GEO;
+  for (int l = 0; l < L; ++l)
+    for (int j = 0; j < 2; ++j) {
+      double sc = 0.0;
+      for (int b = 0; b < 8; ++b)
+        sc += w[8 * l + b] * fabs(grid[lv->off[l] + 2 * (int64_t)idx[8 * l + b] + j]);
+      F->Pe[2 * l + j] = bf16_pert(e[2 * l + j], 0.0, sc);
+    }
+  for (int i = 0; i < OR_HIDDEN; ++i) {
+    double sc = 0.0, p = 0.0;
+    for (int q = 0; q < din; ++q) {
+      const double wr = fabs(rbw(bf, W1[i * din + q]));
+      sc += wr * fabs(rbf(bf, e[q]));
+      p += wr * F->Pe[q];
+    }
+    F->Ppre[i] = p;
+    F->Ph[i] = h1[i] > 0.0 ? bf16_pert(h1[i], p, sc) : 0.0;
+  }
+  for (int k = 1; k < nh; ++k) {
+    const double* W = Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    const double* hp = h1 + (k - 1) * OR_HIDDEN;
+    for (int i = 0; i < OR_HIDDEN; ++i) {
+      double sc = 0.0, p = 0.0;
+      for (int j = 0; j < OR_HIDDEN; ++j) {
+        const double wr = fabs(rbw(bf, W[i * OR_HIDDEN + j]));
+        sc += wr * fabs(rbf(bf, hp[j]));
+        p += wr * F->Ph[(k - 1) * OR_HIDDEN + j];
+      }
+      F->Ppre[k * OR_HIDDEN + i] = p;
+      const double hv = h1[k * OR_HIDDEN + i];
+      F->Ph[k * OR_HIDDEN + i] = hv > 0.0 ? bf16_pert(hv, p, sc) : 0.0;
+    }
+  }
+  const double* hl = h1 + (nh - 1) * OR_HIDDEN;
+  const double* Pl = F->Ph + (nh - 1) * OR_HIDDEN;
+  for (int i = 0; i < OR_DOUT; ++i) {
+    double sc = 0.0, p = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) {
+      const double wr = fabs(rbw(bf, W2[i * OR_HIDDEN + j]));
+      sc += wr * fabs(rbf(bf, hl[j]));
+      p += wr * Pl[j];
+    }
+    F->Py[i] = p;
+    F->Pyr[i] = i > 0 ? bf16_pert(y[i], p, sc) : p; /* y0 enters no contraction */
+  }
+  for (int i = 0; i < OR_HIDDEN; ++i) {
+    double sc = 0.0, p = 0.0;
+    for (int g = 0; g < OR_GEO; ++g) {
+      const double wr = fabs(rbw(bf, W3[i * OR_GEO + g]));
+      sc += wr * fabs(rbf(bf, y[1 + g]));
+      p += wr * F->Pyr[1 + g];
+    }
+    F->Ppre2[i] = p;
+    F->Ph2[i] = h2[i] > 0.0 ? bf16_pert(h2[i], p, sc) : 0.0;
+  }
+  for (int k = 0; k < 3; ++k) {
+    double p = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) p += fabs(rbw(bf, W4[k * OR_HIDDEN + j])) * F->Ph2[j];
+    F->Pz[k] = p;
+  }
+}
+
+static inline double pprod(double a, double Pa, double b, double Pb) {
+  return fabs(a) * Pb + Pa * fabs(b) + Pa * Pb;
+}
+
+/* Adds into amb the bound of the change of one sample's gradient
+ * contributions, given its forward perturbations F, the bounds dsigma and
+ * dcol of its density and colours, the bounds Pdsig and Pdc of its upstream
+ * adjoints, and the error scales sc_dz, sc_dy0 of the FP32 colour-logit and
+ * density-logit adjoints.  Mirrors sample_backward on (value, bound) pairs. */
+static void bf16_backward_pert(const or_levels* lv, const double* mlp, const uint32_t* idx,
+                               const double* w, const double* e, const double* h1,
+                               const double* y, const double* h2, double sigma, double dsigma,
+                               const double* rgb, const double dcol[3], double dsig, double Pdsig,
+                               const double dc[3], const double Pdc[3], const double sc_dz[3],
+                               double sc_dy0, const or_fpert* F, double* amb) {
+  const int din = 2 * lv->L, nh = lv->mlp_layers, bf = lv->mlp_bf16;
+  const double* W1 = mlp;
+  const double* Wh = W1 + OR_HIDDEN * din;
+  const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
+  const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
+  const double* W4 = W3 + OR_HIDDEN * OR_GEO;
+  double* aG = amb;
+  double* aW1 = amb + or_grid_params(lv);
+  double* aWh = aW1 + OR_HIDDEN * din;
+  double* aW2 = aWh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
+  double* aW3 = aW2 + OR_DOUT * OR_HIDDEN;
+  double* aW4 = aW3 + OR_HIDDEN * OR_GEO;
+  double dz[3], Pdz[3], dh2[OR_HIDDEN], Pdh2[OR_HIDDEN], dy[OR_DOUT], Pdy[OR_DOUT],
+      dh[OR_HIDDEN], Pdh[OR_HIDDEN], dp[OR_HIDDEN], Pdp[OR_HIDDEN], Pde[2 * OR_MAX_LEVELS];
+  for (int k = 0; k < 3; ++k) {
+    const double g = rgb[k] * (1.0 - rgb[k]);
+    const double Pg = fabs(1.0 - 2.0 * rgb[k]) * dcol[k] + dcol[k] * dcol[k];
+    dz[k] = dc[k] * g;
+    Pdz[k] = bf16_pert(dz[k], pprod(dc[k], Pdc[k], g, Pg), sc_dz[k]);
+  }
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < OR_HIDDEN; ++j)
+      aW4[k * OR_HIDDEN + j] += pprod(rbf(bf, dz[k]), Pdz[k], rbf(bf, h2[j]), F->Ph2[j]);
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double s = 0.0, p = 0.0, sc = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double wr = rbw(bf, W4[k * OR_HIDDEN + j]);
+      s += wr * rbf(bf, dz[k]);
+      sc += fabs(wr * rbf(bf, dz[k]));
+      p += fabs(wr) * Pdz[k];
+    }
+    dh2[j] = h2[j] > 0.0 ? s : 0.0;
+    Pdh2[j] = h2[j] > 0.0 ? bf16_pert(dh2[j], p, sc) : 0.0;
+  }
+  for (int j = 0; j < OR_HIDDEN; ++j)
+    for (int g = 0; g < OR_GEO; ++g)
+      aW3[j * OR_GEO + g] += pprod(rbf(bf, dh2[j]), Pdh2[j], rbf(bf, y[1 + g]), F->Pyr[1 + g]);
+  for (int g = 0; g < OR_GEO; ++g) {
+    double s = 0.0, p = 0.0, sc = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) {
+      const double wr = rbw(bf, W3[j * OR_GEO + g]);
+      s += wr * rbf(bf, dh2[j]);
+      sc += fabs(wr * rbf(bf, dh2[j]));
+      p += fabs(wr) * Pdh2[j];
+    }
+    dy[1 + g] = s;
+    Pdy[1 + g] = bf16_pert(s, p, sc);
+  }
+  dy[0] = y[0] < 15.0 ? dsig * sigma : 0.0;
+  Pdy[0] = y[0] < 15.0 ? bf16_pert(dy[0], pprod(dsig, Pdsig, sigma, dsigma), sc_dy0) : 0.0;
+  const double* hl = h1 + (nh - 1) * OR_HIDDEN;
+  const double* Phl = F->Ph + (nh - 1) * OR_HIDDEN;
+  for (int i = 0; i < OR_DOUT; ++i)
+    for (int j = 0; j < OR_HIDDEN; ++j)
+      aW2[i * OR_HIDDEN + j] += pprod(rbf(bf, dy[i]), Pdy[i], rbf(bf, hl[j]), Phl[j]);
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double s = 0.0, p = 0.0, sc = 0.0;
+    for (int i = 0; i < OR_DOUT; ++i) {
+      const double wr = rbw(bf, W2[i * OR_HIDDEN + j]);
+      s += wr * rbf(bf, dy[i]);
+      sc += fabs(wr * rbf(bf, dy[i]));
+      p += fabs(wr) * Pdy[i];
+    }
+    dh[j] = hl[j] > 0.0 ? s : 0.0;
+    Pdh[j] = hl[j] > 0.0 ? bf16_pert(dh[j], p, sc) : 0.0;
+  }
+  for (int k = nh - 1; k >= 1; --k) {
+    const double* W = Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    double* aW = aWh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    const double* hp = h1 + (k - 1) * OR_HIDDEN;
+    const double* Php = F->Ph + (k - 1) * OR_HIDDEN;
+    for (int i = 0; i < OR_HIDDEN; ++i)
+      for (int j = 0; j < OR_HIDDEN; ++j)
+        aW[i * OR_HIDDEN + j] += pprod(rbf(bf, dh[i]), Pdh[i], rbf(bf, hp[j]), Php[j]);
+    for (int j = 0; j < OR_HIDDEN; ++j) {
+      double s = 0.0, p = 0.0, sc = 0.0;
+      for (int i = 0; i < OR_HIDDEN; ++i) {
+        const double wr = rbw(bf, W[i * OR_HIDDEN + j]);
+        s += wr * rbf(bf, dh[i]);
+        sc += fabs(wr * rbf(bf, dh[i]));
+        p += fabs(wr) * Pdh[i];
+      }
+      dp[j] = hp[j] > 0.0 ? s : 0.0;
+      Pdp[j] = hp[j] > 0.0 ? bf16_pert(dp[j], p, sc) : 0.0;
+    }
+    memcpy(dh, dp, sizeof(dh));
+    memcpy(Pdh, Pdp, sizeof(Pdh));
+  }
+  for (int j = 0; j < OR_HIDDEN; ++j)
+    for (int q = 0; q < din; ++q)
+      aW1[j * din + q] += pprod(rbf(bf, dh[j]), Pdh[j], rbf(bf, e[q]), F->Pe[q]);
+  for (int q = 0; q < din; ++q) {
+    double p = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) p += fabs(rbw(bf, W1[j * din + q])) * Pdh[j];
+    Pde[q] = p;
+  }
+  for (int l = 0; l < lv->L; ++l)
+    for (int b = 0; b < 8; ++b) {
+      int64_t at = lv->off[l] + 2 * (int64_t)idx[8 * l + b];
+      aG[at + 0] += w[8 * l + b] * Pde[2 * l + 0];
+      aG[at + 1] += w[8 * l + b] * Pde[2 * l + 1];
+    }
+}
+
+/* What one ray's BF16 decisions can move (tests only).  Needs ray_forward
+ * and (for amb) ray_backward of the ray.  lossmode: gC came from the colour
+ * residual (its FP32 error then enters the adjoints' error scales, and its
+ * change follows the residual's); otherwise gC, gD, gT were given.  Writes
+ * the bounds of the change of the ray's colour (dC), depth (dD), T_end (dT)
+ * and summed density (dS) under any choice of the ambiguous roundings, the
+ * forward bounds of each sample into s->fp (for the widened ties), and adds
+ * into amb (may be NULL) the bound of the change of every gradient entry. */
+static void bf16_ray_allowance(const or_levels* lv, int N, const double* params, or_scratch* s,
+                               double delta, int bg, const double crand[3], double Tend,
+                               const double gC[3], double gD, double gT, int lossmode,
+                               const double target[3], double invB, double* amb, double dC[3],
+                               double* dD, double* dT, double* dS) {
+  const int L = lv->L, nh = lv->mlp_layers;
+  const double* mlp = params + or_grid_params(lv);
+  double Sx[N + 1], suf[N][3], dsg[N], dcl[N][3];
+  Sx[0] = 0.0;
+  for (int i = 0; i < N; ++i) Sx[i + 1] = Sx[i] + s->sigma[i] * delta;
+  {
+    double sc[3] = {0.0, 0.0, 0.0};
+    for (int i = N - 1; i >= 0; --i) {
+      for (int k = 0; k < 3; ++k) suf[i][k] = sc[k];
+      for (int k = 0; k < 3; ++k) sc[k] += s->wts[i] * fabs(s->rgb[3 * i + k]);
+    }
+  }
+  double bgt[3];
+  for (int k = 0; k < 3; ++k) bgt[k] = bg ? Tend * crand[k] : 0.0;
+  /* forward: bounds of each sample's density and colours */
+  if (!s->fp) s->fp = (or_fpert*)calloc((size_t)N, sizeof(or_fpert));
+  s->fp_valid = 1;
+  double sum_ds = 0.0;
+  for (int i = 0; i < N; ++i) {
+    dsg[i] = 0.0;
+    dcl[i][0] = dcl[i][1] = dcl[i][2] = 0.0;
+    if (!s->live[i]) continue;
+    or_fpert* F = s->fp + i;
+    bf16_forward_pert(lv, params, mlp, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i,
+                      s->h1 + OR_HIDDEN * nh * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, F);
+    dsg[i] = s->sigma[i] * expm1(F->Py[0]);
+    for (int k = 0; k < 3; ++k) {
+      const double c = s->rgb[3 * i + k];
+      dcl[i][k] = fmin(1.0, c * (1.0 - c) * expm1(F->Pz[k]));
+    }
+    sum_ds += dsg[i];
+  }
+  /* the ray: transmittances (relative), weights, colour, depth */
+  const double rhoT = expm1(delta * sum_ds);
+  double dw[N];
+  for (int k = 0; k < 3; ++k) dC[k] = bg ? Tend * rhoT * crand[k] : 0.0;
+  *dD = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double tau = s->sigma[i] * delta;
+    dw[i] = s->wts[i] * rhoT + exp(-Sx[i]) * (1.0 + rhoT) * exp(-tau) * expm1(delta * dsg[i]);
+    for (int k = 0; k < 3; ++k)
+      dC[k] += dw[i] * fabs(s->rgb[3 * i + k]) + (s->wts[i] + dw[i]) * dcl[i][k];
+    *dD += dw[i] * s->dist[i];
+  }
+  *dT = Tend * rhoT;
+  *dS = sum_ds;
+  if (!amb) return;
+  double eg[3] = {0.0, 0.0, 0.0}, dgC[3];
+  for (int k = 0; k < 3; ++k) {
+    if (lossmode) {
+      /* FP32 error scale of the residual, hence of gC (a weight carries the
+       * error of its transmittance, relative (1 + S) times the scale) */
+      double t = fabs(target[k]) + bgt[k] * (1.0 + Sx[N]);
+      for (int i = 0; i < N; ++i) t += s->wts[i] * fabs(s->rgb[3 * i + k]) * (1.0 + Sx[i + 1]);
+      eg[k] = 2.0 * invB * t;
+    }
+    dgC[k] = lossmode ? 2.0 * invB * dC[k] : 0.0;
+  }
+  for (int i = 0; i < N; ++i) {
+    if (!s->live[i]) continue;
+    const double Tn = exp(-Sx[i + 1]);
+    const double* rgb = s->rgb + 3 * i;
+    double dc[3], Pdc[3], sc_dz[3];
+    double Pds = fabs(gD) * (Tn * rhoT * s->dist[i] + *dD) + fabs(gT) * *dT;
+    double sc_dy0 = s->dsig_m[i] * (1.0 + Sx[i + 1]);
+    for (int k = 0; k < 3; ++k) {
+      dc[k] = s->wts[i] * gC[k];
+      Pdc[k] = pprod(s->wts[i], dw[i], gC[k], dgC[k]);
+      sc_dz[k] = fabs(dc[k] * rgb[k] * (1.0 - rgb[k])) * (1.0 + Sx[i + 1]) +
+                 s->wts[i] * rgb[k] * (1.0 - rgb[k]) * eg[k];
+      const double base = Tn * fabs(rgb[k]) + suf[i][k] + bgt[k];
+      Pds += fabs(dgC[k]) * base + fabs(gC[k]) * (Tn * rhoT * fabs(rgb[k]) + Tn * dcl[i][k] +
+                                                   dC[k] + (bg ? *dT * crand[k] : 0.0));
+      sc_dy0 += delta * base * eg[k];
+    }
+    Pds *= delta;
+    sc_dy0 *= s->sigma[i];
+    bf16_backward_pert(lv, mlp, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i,
+                       s->h1 + OR_HIDDEN * nh * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i,
+                       s->sigma[i], dsg[i], rgb, dcl[i], s->dsig[i], Pds, dc, Pdc, sc_dz, sc_dy0,
+                       s->fp + i, amb);
+  }
 }
 
 /* Tests only.  Smallest distance of a ray's decisions from their ties
@@ -697,7 +1103,9 @@ static double sample_ties(int din, int nh, const double* mlp, const double* e, c
  * sample with a decision closer than 1e-5: the magnitude of its gradient
  * contributions with every branch taken, which bounds the change another
  * branch choice can make (twice for every sample when the depth sign ties).
- * Needs the forward of the ray and the magnitudes dsig_m of ray_backward. */
+ * Needs the forward of the ray and the magnitudes dsig_m of ray_backward (in
+ * BF16 mode also bf16_ray_allowance: a pre-activation that BF16 decisions
+ * upstream can move by P ties when |pre| <= 1e-5 magnitude + P). */
 static double tie_allowance(const or_levels* lv, int N, const double* params, or_scratch* s,
                             const double gCabs[3], double dtie, double* amb) {
   const double kTie = 1e-5;
@@ -706,14 +1114,14 @@ static double tie_allowance(const or_levels* lv, int N, const double* params, or
   double rm = dtie;
   for (int i = 0; i < N; ++i) {
     if (!s->live[i]) continue;
-    const double sm = sample_ties(2 * L, nh, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
-                                  s->y + OR_DOUT * i);
+    const double sm = sample_ties(lv, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
+                                  s->y + OR_DOUT * i,
+                                  lv->mlp_bf16 && s->fp_valid ? s->fp + i : NULL);
     rm = fmin(rm, sm);
     const int reps = dtie < kTie ? 2 : (sm < kTie ? 1 : 0);
     if (amb && reps) {
       double dcm[3];
       for (int k = 0; k < 3; ++k) dcm[k] = s->wts[i] * gCabs[k];
-#pragma omp critical
       for (int rep = 0; rep < reps; ++rep)
         sample_backward_magnitude(lv, 2 * L, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
                                   s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
@@ -736,18 +1144,21 @@ static void reduce_threads(const double* t, int nthreads, int64_t P, double* out
 int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int instance,
                    const float half[3], int nkf, const or_keyframe* kfs, int step, int B,
                    const double* params, const uint8_t* occ, double* grad, double* grad_abs,
-                   double* ambiguous, double* min_margin, double* loss, or_ray* rays,
-                   int nthreads) {
+                   double* ambiguous, double* min_margin, double* loss, double* loss_allow,
+                   or_ray* rays, int nthreads) {
   if (nkf < 1 || B < 1 || cfg->N < 1) return -1;
   const int L = lv->L, N = cfg->N;
   const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L, lv->mlp_layers);
   if (nthreads < 1) nthreads = 1;
   double* ray_loss = (double*)calloc((size_t)B, sizeof(double));
   double* ray_margin = (double*)calloc((size_t)B, sizeof(double));
+  double* ray_lallow = (double*)calloc((size_t)B, sizeof(double));
   double* tgrad = NULL;
   double* tabs = NULL;
+  double* tamb = NULL;
   if (grad) tgrad = (double*)calloc((size_t)P * nthreads, sizeof(double));
   if (grad && grad_abs) tabs = (double*)calloc((size_t)P * nthreads, sizeof(double));
+  if (grad && ambiguous) tamb = (double*)calloc((size_t)P * nthreads, sizeof(double));
   if (ambiguous) memset(ambiguous, 0, sizeof(double) * (size_t)P);
 
 #pragma omp parallel num_threads(nthreads)
@@ -760,6 +1171,7 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
     scratch_alloc(&s, N, L, lv->mlp_layers);
     double* my_grad = grad ? tgrad + (int64_t)tid * P : NULL;
     double* my_abs = tabs ? tabs + (int64_t)tid * P : NULL;
+    double* my_amb = tamb ? tamb + (int64_t)tid * P : NULL;
 #pragma omp for schedule(static)
     for (int r = 0; r < B; ++r) {
       or_ray ray;
@@ -768,6 +1180,7 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
       or_pixel_ray(kf->M, kf->c, kf->fx, kf->fy, kf->cx, kf->cy, ray.u, ray.v, ray.o, ray.d);
       ray.hit = or_slab(ray.o, ray.d, half, &ray.tn, &ray.tf);
       ray.loss = 0.0;
+      ray_lallow[r] = 0.0;
       /* occluder rays carry no loss (Sec. V-B); rays missing the box have no samples */
       if (ray.cls != 0 && ray.hit) {
         double crand[3] = {ray.Crand[0], ray.Crand[1], ray.Crand[2]};
@@ -787,22 +1200,33 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
           l += cfg->lambda_density * ssum;
         }
         ray.loss = l / (double)B;
-        if (my_grad) {
-          double gC[3], gD = 0.0;
-          for (int k = 0; k < 3; ++k) gC[k] = 2.0 * (ray.Chat[k] - target[k]) / (double)B;
-          if (!bg && ray.has_depth) {
-            double diff = ray.Dhat - (double)ray.D;
-            gD = cfg->lambda_depth * (diff > 0.0 ? 1.0 : (diff < 0.0 ? -1.0 : 0.0)) / (double)B;
-          }
+        double gC[3], gD = 0.0;
+        for (int k = 0; k < 3; ++k) gC[k] = 2.0 * (ray.Chat[k] - target[k]) / (double)B;
+        if (!bg && ray.has_depth) {
+          double diff = ray.Dhat - (double)ray.D;
+          gD = cfg->lambda_depth * (diff > 0.0 ? 1.0 : (diff < 0.0 ? -1.0 : 0.0)) / (double)B;
+        }
+        if (my_grad)
           ray_backward(lv, N, params, (double)ray.delta, &s, bg, crand, ray.Tend, gC, gD, 0.0,
                        bg ? cfg->lambda_density / (double)B : 0.0, my_grad, my_abs);
-        }
+        /* tests only: what the BF16 decisions and the ties can move */
+        double dC[3] = {0.0, 0.0, 0.0}, dD = 0.0, dT = 0.0, dS = 0.0;
+        if (lv->mlp_bf16 && (loss_allow || my_amb))
+          bf16_ray_allowance(lv, N, params, &s, (double)ray.delta, bg, crand, ray.Tend, gC, gD,
+                             0.0, 1, target, 1.0 / (double)B, my_grad ? my_amb : NULL, dC, &dD,
+                             &dT, &dS);
+        double la = 0.0;
+        for (int k = 0; k < 3; ++k)
+          la += 2.0 * fabs(ray.Chat[k] - target[k]) * dC[k] + dC[k] * dC[k];
+        if (!bg && ray.has_depth) la += cfg->lambda_depth * dD;
+        if (bg) la += cfg->lambda_density * dS;
+        ray_lallow[r] = la / (double)B;
         double dtie = INFINITY;
         if (!bg && ray.has_depth)
-          dtie = fabs(ray.Dhat - (double)ray.D) / fmax(fabs((double)ray.D), 1e-30);
+          dtie = (fabs(ray.Dhat - (double)ray.D) - dD) / fmax(fabs((double)ray.D), 1e-30);
         double gCa[3];
-        for (int k = 0; k < 3; ++k) gCa[k] = fabs(2.0 * (ray.Chat[k] - (bg ? crand[k] : (double)ray.C[k])) / (double)B);
-        const double rm = tie_allowance(lv, N, params, &s, gCa, dtie, my_grad ? ambiguous : NULL);
+        for (int k = 0; k < 3; ++k) gCa[k] = fabs(gC[k]);
+        const double rm = tie_allowance(lv, N, params, &s, gCa, dtie, my_grad ? my_amb : NULL);
         ray_margin[r] = rm;
       } else {
         ray_margin[r] = INFINITY;
@@ -812,19 +1236,24 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
     }
     scratch_free(&s);
   }
-  double total = 0.0, mm = INFINITY;
+  double total = 0.0, mm = INFINITY, tla = 0.0;
   for (int r = 0; r < B; ++r) {
     total += ray_loss[r];
+    tla += ray_lallow[r];
     mm = fmin(mm, ray_margin[r]);
   }
   *loss = total;
+  if (loss_allow) *loss_allow = tla;
   if (min_margin) *min_margin = mm;
   if (grad) reduce_threads(tgrad, nthreads, P, grad);
   if (tabs) reduce_threads(tabs, nthreads, P, grad_abs);
+  if (tamb) reduce_threads(tamb, nthreads, P, ambiguous);
   free(tgrad);
   free(tabs);
+  free(tamb);
   free(ray_loss);
   free(ray_margin);
+  free(ray_lallow);
   return 0;
 }
 
@@ -842,6 +1271,7 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
   if (nthreads < 1) nthreads = 1;
   double* tgrad = grad ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
   double* tabs = (grad && grad_abs) ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
+  double* tamb = (grad && ambiguous) ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
   if (ambiguous) memset(ambiguous, 0, sizeof(double) * (size_t)P);
 #pragma omp parallel num_threads(nthreads)
   {
@@ -871,15 +1301,24 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
                      d_depth ? d_depth[r] : 0.0, d_tend ? d_tend[r] : 0.0, 0.0,
                      tgrad + (int64_t)tid * P, tabs ? tabs + (int64_t)tid * P : NULL);
         const double gCa[3] = {fabs(gC[0]), fabs(gC[1]), fabs(gC[2])};
-        if (ambiguous) tie_allowance(lv, N, params, &s, gCa, INFINITY, ambiguous);
+        double* my_amb = tamb ? tamb + (int64_t)tid * P : NULL;
+        if (my_amb && lv->mlp_bf16) {
+          double dC[3], dD, dT, dS;
+          bf16_ray_allowance(lv, N, params, &s, (double)delta, 0, zero, Tend, gC,
+                             d_depth ? d_depth[r] : 0.0, d_tend ? d_tend[r] : 0.0, 0, zero, 0.0,
+                             my_amb, dC, &dD, &dT, &dS);
+        }
+        if (my_amb) tie_allowance(lv, N, params, &s, gCa, INFINITY, my_amb);
       }
     }
     scratch_free(&s);
   }
   if (grad) reduce_threads(tgrad, nthreads, P, grad);
   if (tabs) reduce_threads(tabs, nthreads, P, grad_abs);
+  if (tamb) reduce_threads(tamb, nthreads, P, ambiguous);
   free(tgrad);
   free(tabs);
+  free(tamb);
   return 0;
 }
 
@@ -898,12 +1337,14 @@ void or_adam(int64_t P, double* p, double* g, double* m, double* v, int k, doubl
 }
 
 /* Render every pixel of a camera through the object's box (evaluation and
- * meshing); composited on black, opacity = 1 - T_end.  Misses give 0. */
+ * meshing); composited on black, opacity = 1 - T_end.  Misses give 0.
+ * rgb_allow (tests only, may be NULL; BF16 mode): per pixel and channel the
+ * bound of the change of the colour under the other choice of the
+ * ambiguous BF16 roundings (bf16_ray_allowance); 0 in FP32 mode. */
 int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
               const or_keyframe* cam, const double* params, const uint8_t* occ, double* rgb,
-              double* depth, double* opacity, int nthreads) {
-  const int L = lv->L, N = cfg->N, din = 2 * L;
-  const double* mlp = params + or_grid_params(lv);
+              double* depth, double* opacity, double* rgb_allow, int nthreads) {
+  const int L = lv->L, N = cfg->N;
   const int64_t npix = (int64_t)cam->W * cam->H;
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel num_threads(nthreads)
@@ -915,20 +1356,19 @@ int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
       int u = (int)(px % cam->W), v = (int)(px / cam->W);
       float o[3], d[3], tn, tf, dl;
       or_pixel_ray(cam->M, cam->c, cam->fx, cam->fy, cam->cx, cam->cy, u, v, o, d);
-      double C[3] = {0.0, 0.0, 0.0}, D = 0.0, Tend = 1.0;
+      double C[3] = {0.0, 0.0, 0.0}, D = 0.0, Tend = 1.0, dC[3] = {0.0, 0.0, 0.0};
       if (or_slab(o, d, half, &tn, &tf)) {
-        or_sample_positions(o, d, half, tn, tf, N, &dl, s.dist32, s.pos);
-        for (int i = 0; i < N; ++i) {
-          s.dist[i] = (double)s.dist32[i];
-          or_encode(lv, s.pos + 3 * i, params, s.idx, s.w, s.e);
-          or_mlp_forward(din, lv->mlp_layers, mlp, s.e, s.h1, s.y, s.h2, s.sigma + i,
-                         s.rgb + 3 * i);
-          if (!or_occupied(occ, s.pos + 3 * i)) s.sigma[i] = 0.0;
+        const double zero[3] = {0.0, 0.0, 0.0};
+        ray_forward(lv, N, params, o, d, half, tn, tf, &dl, &s, 0, zero, C, &D, &Tend, occ);
+        if (rgb_allow && lv->mlp_bf16) {
+          double dD, dT, dS;
+          bf16_ray_allowance(lv, N, params, &s, (double)dl, 0, zero, Tend, zero, 0.0, 0.0, 0,
+                             zero, 0.0, NULL, dC, &dD, &dT, &dS);
         }
-        double zero[3] = {0.0, 0.0, 0.0};
-        or_composite(N, s.sigma, s.rgb, s.dist, (double)dl, 0, zero, C, &D, &Tend, s.wts);
       }
       for (int k = 0; k < 3; ++k) rgb[3 * px + k] = C[k];
+      if (rgb_allow)
+        for (int k = 0; k < 3; ++k) rgb_allow[3 * px + k] = dC[k];
       if (depth) depth[px] = D;
       if (opacity) opacity[px] = 1.0 - Tend;
     }
@@ -952,7 +1392,8 @@ void or_query_density(const or_levels* lv, const float half[3], const double* pa
       p[k] = fminf(fmaxf(q, 0.0f), 1.0f);
     }
     or_encode(lv, p, params, idx, w, e);
-    or_mlp_forward(din, lv->mlp_layers, mlp, e, h1, y, h2, sigma + i, rgb);
+    /* the density query runs the FP32 MLP in either mode */
+    or_mlp_forward(din, lv->mlp_layers, 0, mlp, e, h1, y, h2, sigma + i, rgb);
   }
 }
 

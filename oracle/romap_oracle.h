@@ -36,6 +36,8 @@ typedef struct {
   int64_t off[OR_MAX_LEVELS + 1];/* offset of each level in floats (F = 2) */
   int32_t mlp_layers;            /* hidden layers of the density MLP, 1..3 (1 from
                                     or_make_levels; the caller may raise it) */
+  int32_t mlp_bf16;              /* 1: BF16 mode of the MLP contractions (see or_bf16);
+                                    0 from or_make_levels */
 } or_levels;
 
 typedef struct {
@@ -67,7 +69,10 @@ void or_sample_positions(const float o[3], const float d[3], const float half[3]
                          float tf, int N, float* delta, float* dist, float* pos);
 void or_encode(const or_levels* lv, const float p[3], const double* grid, uint32_t* idx,
                double* w, double* e);
-void or_mlp_forward(int din, int layers, const double* mlp, const double* e, double* h1,
+double or_bf16(double x);
+double or_bf16_gap(double x);
+void or_bf16_set_jitter(double rel); /* tests only */
+void or_mlp_forward(int din, int layers, int bf16, const double* mlp, const double* e, double* h1,
                     double* y, double* h2, double* sigma, double* rgb);
 void or_composite(int N, const double* sigma, const double* rgb, const double* dist, double delta,
                   int background, const double crand[3], double C[3], double* D, double* Tend,
@@ -79,8 +84,8 @@ void or_draw_ray(const or_config* cfg, int obj, int step, int r, int nkf, const 
 int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int instance,
                    const float half[3], int nkf, const or_keyframe* kfs, int step, int B,
                    const double* params, const uint8_t* occ, double* grad, double* grad_abs,
-                   double* ambiguous, double* min_margin, double* loss, or_ray* rays,
-                   int nthreads);
+                   double* ambiguous, double* min_margin, double* loss, double* loss_allow,
+                   or_ray* rays, int nthreads);
 int or_field(const or_config* cfg, const or_levels* lv, const float half[3], const double* params,
              int n, const float* rays, double* rgb, double* depth, double* tend,
              const double* d_rgb, const double* d_depth, const double* d_tend, double* grad,
@@ -89,7 +94,7 @@ void or_adam(int64_t P, double* p, double* g, double* m, double* v, int k, doubl
              double b2, double eps);
 int or_render(const or_config* cfg, const or_levels* lv, const float half[3],
               const or_keyframe* cam, const double* params, const uint8_t* occ, double* rgb,
-              double* depth, double* opacity, int nthreads);
+              double* depth, double* opacity, double* rgb_allow, int nthreads);
 int or_occupied(const uint8_t* occ, const float p[3]);
 void or_query_density(const or_levels* lv, const float half[3], const double* params, int64_t n,
                       const float* xyz, double* sigma);

@@ -616,3 +616,90 @@ def test_occupancy_bit_layout():
     bits[:] = 0
     bits[-1] = 0x80  # cell (63, 63, 63): p = 1 clamps into it
     assert occ([1.0, 1.0, 1.0]) == 1
+
+
+# ---------------------------------------------------------------- loss value (Eq. 7-11)
+@pytest.mark.parametrize("lam2", [0.0, 0.01, 0.37])
+def test_loss_value_closed_form_with_zero_grid(lam2):
+    """Grid = 0 makes every encoding 0, so with no biases every pre-activation
+    is 0: sigma = exp(0) = 1 and c = sigmoid(0) = 1/2 at every sample,
+    whatever the MLP weights.  A hit ray of extent d = t_f - t_n then has
+    T_end = e^-d and renders 1/2 (1 - T_end) (Eq. 6); a background ray adds
+    T_end C_rand and is compared with C_rand (Eq. 9), plus lambda_2 times the
+    density summed over its N samples, N x 1 (Eq. 10); an object ray is
+    compared with its pixel (Eq. 7) plus lambda_1 |D - D_target| (Eq. 8);
+    occluder rays and misses add nothing; the sum is divided by the rays
+    drawn.  This fixes the density term's value: lambda_2 N per background
+    ray (not lambda_2 sum tau = lambda_2 d, and not over other rays)."""
+    N, B = 8, 400
+    ctx, oid, _ = _tiny_ctx(N=N, lambda_density=lam2)
+    o = ctx.objects[oid]
+    p = random_params(oracle.grid_params(o.lv), 4)
+    p[:oracle.grid_params(o.lv)] = 0.0
+    loss, _, rays = ctx.loss_and_grad(oid, 0, B, rays=True, params=p, want_grad=False)
+    lam1 = ctx.cfg.lambda_depth
+    total, n_bg = 0.0, 0
+    classes = set()
+    for r in rays:
+        classes.add((r.cls, r.hit))
+        if r.cls == 0 or not r.hit:
+            continue
+        delta, dist, _ = oracle.sample_positions(np.array(r.o), np.array(r.d), o.half, r.tn, r.tf,
+                                                 N)
+        d = N * delta  # every sample uses delta (t_f - t_n = N delta up to FP32 rounding of delta)
+        Tend = math.exp(-d)
+        # weights of constant density 1: w_i = e^{-i delta} (1 - e^{-delta})
+        w = np.exp(-np.arange(N) * delta) * (1.0 - math.exp(-delta))
+        C = 0.5 * (1.0 - Tend) * np.ones(3)
+        if r.cls == 2:
+            cr = np.array(r.Crand, np.float64)
+            C = C + Tend * cr
+            ell = float(np.sum((C - cr) ** 2)) + lam2 * N
+            n_bg += 1
+        else:
+            ell = float(np.sum((C - np.array(r.C, np.float64)) ** 2))
+            if r.has_depth:
+                ell += lam1 * abs(float(np.dot(w, dist.astype(np.float64))) - r.D)
+        total += ell
+    assert {(2, 1), (1, 1), (0, 1)} <= classes and n_bg > 20
+    assert math.isclose(loss, total / B, rel_tol=1e-12, abs_tol=1e-15)
+    if lam2 > 0:
+        l0, _, _ = ctx.loss_and_grad(oid, 0, B, params=p, want_grad=False)
+        ctx.cfg.lambda_density = 0.0
+        l_off, _, _ = ctx.loss_and_grad(oid, 0, B, params=p, want_grad=False)
+        ctx.cfg.lambda_density = lam2
+        assert math.isclose(l0 - l_off, lam2 * N * n_bg / B, rel_tol=1e-10)
+
+
+# ---------------------------------------------------------------- ray draw index mapping
+def test_ray_draw_index_mapping_by_hand():
+    """Ray r of step s of object o: (x0, x1, x2, x3) = Philox4x32-10 with key
+    (seed_lo xor o, seed_hi) and counter (s, r, 0, 0) (pinned by its published
+    vectors); the candidate index is floor(x0 n_cand / 2^32) over the
+    candidates enumerated keyframe by keyframe, row-major inside each
+    candidate rectangle; C_random = (x_{k+1} >> 8) 2^-24.  Computed here with
+    Python integers and compared with the oracle's draws (a draw from x1, or
+    x0 mod n_cand, or column-major order would differ)."""
+    ctx, oid, _ = _tiny_ctx()
+    o = ctx.objects[oid]
+    p = random_params(oracle.grid_params(o.lv), 4)
+    rects = [rect for _, rect in o.kfs]
+    n_cand = sum(w * h for (_, _, w, h) in rects)
+    seed = int(ctx.cfg.seed)
+    for step in (0, 3, 77):
+        B = 64
+        _, _, rays = ctx.loss_and_grad(oid, step, B, rays=True, params=p, want_grad=False)
+        for r in range(B):
+            x = [int(v) for v in oracle.philox([step, r, 0, 0],
+                                               [(seed & 0xFFFFFFFF) ^ oid, seed >> 32])]
+            q = (x[0] * n_cand) >> 32
+            kf = 0
+            while q >= rects[kf][2] * rects[kf][3]:
+                q -= rects[kf][2] * rects[kf][3]
+                kf += 1
+            x0, y0, w, h = rects[kf]
+            want = (kf, x0 + q % w, y0 + q // w)
+            got = rays[r]
+            assert (got.kf, got.u, got.v) == want, (step, r)
+            for k in range(3):
+                assert float(got.Crand[k]) == (x[k + 1] >> 8) * 2.0 ** -24
