@@ -42,14 +42,6 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_05735_amd", "csrc", "romap_kernels.hip")
-# kernels of each timed phase (the phase's duration covers all of them)
-PHASE_KERNELS = {
-    "raygen": ["k_raygen"], "encode_fwd": ["k_encode_fwd"], "pack": ["k_pack"],
-    "field": ["k_field"], "reduce": ["k_reduce"], "bin_scatter": ["k_bin_scatter"],
-    "bin_acc": ["k_bin_acc"], "bin_finish": ["k_bin_finish"],
-}
-
-
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -154,11 +146,13 @@ def make_ctx(wl, precision, batch_mode, use_graph, autotune=1, profile=0, **kw):
     for ob in wl.objects:
         ids.append(ctx.add_object(ob.instance, ob.t, ob.yaw, ob.half, ob.log2T))
     ctx.sync()
+    held_out = set(wl.eval_views)
     t0 = time.perf_counter()
-    for cam, rgb, mask, depth in wl.frames:
-        ctx.add_keyframe(cam, rgb, mask, depth)
+    for f, (cam, rgb, mask, depth) in enumerate(wl.frames):
+        if f not in held_out:  # evaluation views are never trained on
+            ctx.add_keyframe(cam, rgb, mask, depth)
     ctx.sync()
-    ctx.keyframe_seconds = time.perf_counter() - t0  # host buffers -> HBM, all frames
+    ctx.keyframe_seconds = time.perf_counter() - t0  # host buffers -> HBM, training frames
     keep, rays = [], []
     for i, ob in zip(ids, wl.objects):
         if ctx.object_info(i).n_keyframes > 0:
@@ -205,10 +199,12 @@ def psnr_curve(ctx, wl, ids, rays, steps, chunk):
 
 def equal_psnr(wl, ids, rays, prec, steps, chunk, ms_batched, ms_plain):
     """Batched path vs the plain FP32 path from the same initialisation, PSNR
-    on the held-out views every `chunk` steps.  The common target is the lower
-    of the two final PSNRs less 0.1 dB (both curves reach it); each path's
-    time to the target is its first evaluated step count at or above it times
-    its measured time per step, and the speedup is the ratio of the two."""
+    on the held-out views (never keyframes) every `chunk` steps.  When the
+    final PSNRs differ by at most 0.1 dB the two are equal and the speedup is
+    the ratio of their rates at equal step counts; otherwise it is the ratio
+    of the times to reach the plain path's final PSNR (each path's first
+    evaluated step count at or above it, times its measured time per step),
+    null when the batched path does not reach it within the steps."""
     import paper_2304_05735_amd as pk
     qa, _, _ = make_ctx(wl, prec, pk.BATCH_ALL, 1)
     ca = psnr_curve(qa, wl, ids, rays, steps, chunk)
@@ -217,15 +213,21 @@ def equal_psnr(wl, ids, rays, prec, steps, chunk, ms_batched, ms_plain):
     cb = psnr_curve(qb, wl, ids, rays, steps, chunk)
     del qb
     pa, pb = ca[-1][1], cb[-1][1]
-    target = min(pa, pb) - 0.1
-    sa = next(k for k, v in ca if v >= target)
-    sb = next(k for k, v in cb if v >= target)
-    return dict(steps=steps, psnr_batched=round(pa, 3), psnr_plain_fp32=round(pb, 3),
-                target_psnr=round(target, 3), steps_batched_to_target=sa,
-                steps_plain_to_target=sb,
-                speedup_at_equal_psnr=round((sb * ms_plain) / (sa * ms_batched), 3),
-                curve_batched=[(k, round(v, 3)) for k, v in ca],
-                curve_plain_fp32=[(k, round(v, 3)) for k, v in cb])
+    out = dict(steps=steps, eval_views=list(wl.eval_views), psnr_batched=round(pa, 3),
+               psnr_plain_fp32=round(pb, 3), delta_psnr=round(pa - pb, 3))
+    if abs(pa - pb) <= 0.1:
+        out.update(rule="equal PSNR (|delta| <= 0.1 dB): ratio of rates at equal steps",
+                   speedup_at_equal_psnr=round(ms_plain / ms_batched, 3))
+    else:
+        sa = next((k for k, v in ca if v >= pb), None)
+        sb = next(k for k, v in cb if v >= pb)
+        out.update(rule="time to the plain path's final PSNR", target_psnr=round(pb, 3),
+                   steps_batched_to_target=sa, steps_plain_to_target=sb,
+                   speedup_at_equal_psnr=None if sa is None else
+                   round((sb * ms_plain) / (sa * ms_batched), 3))
+    out.update(curve_batched=[(k, round(v, 3)) for k, v in ca],
+               curve_plain_fp32=[(k, round(v, 3)) for k, v in cb])
+    return out
 
 
 def mesh_timing(ctx, ids, res=64, iso=10.0, reps=3):
@@ -308,30 +310,35 @@ def density_ablation(wl, ids, rays, prec, steps):
     return out
 
 
-def algorithmic_bytes(ctx, ids, rays, phase):
-    """Algorithmic bytes of one step of a kernel (all its launches).  The
-    binning kernels' records are the counted ones (fewer than 8 per sample
-    and level where runs of samples in one cell are merged)."""
-    L, N = ctx.cfg.n_levels, ctx.cfg.samples_per_ray
-    S = sum(rays) * N
+# Algorithmic work per the method (per evaluated sample: L levels x 8 corners
+# x F = 2 features x 4 B gathered, the same scattered; e and its adjoint
+# L x F x 4 B; dense Adam 32 B per parameter: p, g, m, v read, p, m, v, g
+# written; MLP 6 flops per weight and sample: forward, input and weight
+# adjoints).
+def evaluated_samples(ctx, ids, rays):
+    """Samples the method evaluates in one step: the draw of the context's
+    current step, rays that hit their box and are not occluders (classes 1,
+    2; misses and occluder rays carry no loss and are never evaluated)."""
+    n = 0
+    for i, B in zip(ids, rays):
+        _, cls, _, _ = ctx.debug_rays(i, B)
+        n += int(((cls == 1) | (cls == 2)).sum())
+    return n * ctx.cfg.samples_per_ray
+
+
+def method_work(ctx, ids, S):
+    """Bytes (or flops) of one step per phase, for S evaluated samples."""
+    L = ctx.cfg.n_levels
     grid = sum(ctx.object_info(i).n_grid_params for i in ids)
-    rec = ctx.step_records()
-    if phase == "encode_fwd":   # 8 corners x 8 B gathered + 8 B written, per sample and level
-        return S * L * (64 + 8)
-    if phase == "bin_scatter":  # 8 B adjoint read per sample and level + 10 B per record written
-        return S * L * 8 + 10 * rec
-    if phase == "bin_acc":      # 10 B per record read; Adam on the table: p, m, v read and written
-        return 10 * rec + 24 * grid
-    if phase == "field":        # encodings read twice (forward, recompute), adjoints written
-        return S * L * 8 * 3
-    return 0
-
-
-def field_flops(ctx, rays):
-    """MLP flops of the field kernel: forward 2*4224, recompute 2*4224,
-    adjoint 2*2*4224 (input and weight gradients) per sample."""
-    S = sum(rays) * ctx.cfg.samples_per_ray
-    return S * 4224 * 2 * 4
+    per_obj_mlp = ctx.object_info(ids[0]).n_mlp_params  # the same MLP shape for every object
+    payload = S * L * 8 * 2 * 4
+    ebytes = S * L * 2 * 4
+    return dict(
+        gather=payload + ebytes,                    # A5: corners gathered, e written
+        scatter_adam=payload + ebytes + 32 * grid,  # A12 + A13: adjoint read, corners scattered, Adam
+        field_bytes=2 * ebytes,                     # e read, adjoint written
+        mlp_flops=6 * per_obj_mlp * S,              # A6, A7, A11
+        grid_params=grid)
 
 
 def kernel_src_hash():
@@ -434,26 +441,49 @@ def traffic_of(workload, kernels):
     return sum(tab.get(k, 0.0) for k in kernels)
 
 
-def cpu_baseline(wl, seconds_target=15.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, seconds_target=12.0):
     """The oracle as it stands on the host cores, on a bounded sample: as many
-    full 4096-ray steps of the first object as fit in ~seconds_target."""
+    full training steps of the first object as fit in ~seconds_target, on
+    every core this process may use and then on one core."""
     import oracle
     ob = wl.objects[0]
-    cfg = oracle.make_config(N=64, log2T=ob.log2T)
-    o = oracle.OracleContext(cfg)
-    oid = o.add_object(ob.instance, ob.t, ob.yaw, ob.half, ob.log2T)
-    for cam, rgb, mask, depth in wl.frames:
-        o.add_keyframe(cam, rgb, mask, depth)
     B = wl.rays[ob.instance]
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < seconds_target and steps < 50:
-        o.train(oid, 1, B)
-        steps += 1
-    dt = time.perf_counter() - t0
-    return dict(value=steps * B / dt, unit="rays/s", cores=o.nthreads, kind="oracle",
-                sample=f"{steps} full training steps x {B} rays x 64 samples of object "
-                       f"instance {ob.instance} (FP64, {o.nthreads} threads)")
+    held_out = set(wl.eval_views)
+    runs = {}
+    for threads in (oracle.host_threads(), 1):
+        cfg = oracle.make_config(N=64, log2T=ob.log2T)
+        o = oracle.OracleContext(cfg, nthreads=threads)
+        oid = o.add_object(ob.instance, ob.t, ob.yaw, ob.half, ob.log2T)
+        for f, (cam, rgb, mask, depth) in enumerate(wl.frames):
+            if f not in held_out:
+                o.add_keyframe(cam, rgb, mask, depth)
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < seconds_target and steps < 50:
+            o.train(oid, 1, B)
+            steps += 1
+        dt = time.perf_counter() - t0
+        runs[threads] = (steps * B / dt, steps)
+        log(f"cpu oracle, {threads} threads: {steps} steps in {dt:.1f} s")
+        del o
+    allc = oracle.host_threads()
+    v, n = runs[allc]
+    v1, n1 = runs[1]
+    return dict(value=round(v, 1), unit="rays/s", cores=allc, kind="oracle",
+                sample=f"{n} full training steps x {B} rays x 64 samples of object instance "
+                       f"{ob.instance} (2^{ob.log2T} table, FP64) on {allc} threads; "
+                       f"{n1} such steps on 1 thread",
+                cpu_model=cpu_model(), one_core={"value": round(v1, 1), "cores": 1})
 
 
 def main():
@@ -469,8 +499,8 @@ def main():
     ap.add_argument("--table-sweep", action="store_true",
                     help="time one object for T = 2^14..2^20 and for 2- and 3-layer density MLPs "
                          "(the paper's Table 4 study) and exit")
-    ap.add_argument("--ablation-density", action="store_true",
-                    help="also train with lambda_2 = 0 and report PSNR and empty-space opacity")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the lambda_2 = 0 training run (PSNR and empty-space opacity)")
     ap.add_argument("--psnr-chunk", type=int, default=250)
     ap.add_argument("--only-headline", action="store_true",
                     help="time the batched path only (for profiler runs)")
@@ -525,51 +555,75 @@ def main():
         print(json.dumps(out), flush=True)
         return
     prec = pk.PREC_BF16 if args.workload == "objects24" else pk.PREC_FP32
-    # ---- headline: batched path, one hipGraph per step
-    ctx, ids, rays = make_ctx(wl, prec, pk.BATCH_ALL, 1)
+    # ---- headline: batched path, one hipGraph per step (captured by the
+    # untimed warm-up call, replayed by the timed one)
+    ctx, ids, rays = make_ctx(wl, prec, pk.BATCH_ALL, 2)
     rays_per_step = sum(rays)
     # RGB8, int32 mask, float depth where given
     kf_bytes = sum(rgb.shape[0] * rgb.shape[1] * (3 + 4 + (4 if depth is not None else 0))
-                   for _, rgb, _, depth in wl.frames)
-    keyframes = {"frames": len(wl.frames), "ms": round(ctx.keyframe_seconds * 1e3, 3),
-                 "MB": round(kf_bytes / 1e6, 1),
+                   for f, (_, rgb, _, depth) in enumerate(wl.frames) if f not in wl.eval_views)
+    keyframes = {"frames": len(wl.frames) - len(wl.eval_views),
+                 "ms": round(ctx.keyframe_seconds * 1e3, 3), "MB": round(kf_bytes / 1e6, 1),
                  "GB_per_s": round(kf_bytes / ctx.keyframe_seconds / 1e9, 2)}
     log("keyframes", json.dumps(keyframes))
     log(f"{len(ids)} trained objects, {rays_per_step} rays/step")
-    dt = timed_steps(ctx, ids, rays, args.warmup, args.steps)
+    dt = timed_steps(ctx, ids, rays, max(args.warmup, 1), args.steps)
     value = rays_per_step * args.steps / dt
     ms_step = dt / args.steps * 1e3
     log(f"batched: {ms_step:.4f} ms/step, {value / 1e6:.3f} M rays/s")
-    mesh = None
-    if not args.only_headline:
-        mesh = mesh_timing(ctx, ids)
-        log("mesh", json.dumps(mesh))
     if args.only_headline:
         print(json.dumps({"value": value, "ms_per_step": ms_step}), flush=True)
         return
+    mesh = mesh_timing(ctx, ids)
+    log("mesh", json.dumps(mesh))
+    del ctx
+    batched_fp32 = None
+    if prec == pk.PREC_BF16:  # the same batched path with the FP32 MLP
+        fctx, _, _ = make_ctx(wl, pk.PREC_FP32, pk.BATCH_ALL, 2)
+        dtf = timed_steps(fctx, ids, rays, max(args.warmup, 1), args.steps)
+        batched_fp32 = {"value": round(rays_per_step * args.steps / dtf, 1), "unit": "rays/s",
+                        "ms_per_step": round(dtf / args.steps * 1e3, 5)}
+        log("batched FP32", json.dumps(batched_fp32))
+        del fctx
     # ---- per-kernel durations (HIP events on the context stream, same kernels)
     pctx, _, _ = make_ctx(wl, prec, pk.BATCH_ALL, 0, profile=1)
     pctx.train(args.warmup, ids, rays, stats=False)
+    S = evaluated_samples(pctx, ids, rays)
     pctx.train(args.steps, ids, rays, stats=False)
     phases, nph = pctx.phase_times()
+    records = pctx.step_records()
     log("phase ms:", json.dumps({k: round(v, 5) for k, v in phases.items()}))
-    dominant = max(phases, key=phases.get)
-    byt = algorithmic_bytes(pctx, ids, rays, dominant)
-    achieved = byt / (phases[dominant] * 1e-3) / 1e9 if phases[dominant] > 0 else 0.0
-    traffic = traffic_of(args.workload, PHASE_KERNELS[dominant])
+    work = method_work(pctx, ids, S)
     copy_gbs = copy_bandwidth()
     log(f"copy bandwidth {copy_gbs:.0f} GB/s")
-    roofline = dict(bound="hbm", kernel=dominant, kernels=PHASE_KERNELS[dominant],
-                    achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    copy_gbs=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4),
-                    traffic=None if traffic is None else int(traffic),
-                    avg_ms=round(phases[dominant], 5), algorithmic_bytes=int(byt),
-                    phase_ms={k: round(v, 5) for k, v in phases.items()})
-    fl = field_flops(pctx, rays)
+
+    def hbm(name, kernels, byt):
+        ms = sum(phases[k] for k in kernels)
+        a = byt / (ms * 1e-3) / 1e9
+        return dict(bound="hbm", kernels=["k_" + k for k in kernels], avg_ms=round(ms, 5),
+                    algorithmic_bytes=int(byt), achieved=round(a, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(a / HBM_PEAK_GBS, 4), frac_of_copy=round(a / copy_gbs, 4))
+
     peak_f = BF16_PEAK_TFLOPS if prec == pk.PREC_BF16 else FP32_MFMA_PEAK_TFLOPS
-    mlp = dict(kernel="field", tflops=round(fl / (phases["field"] * 1e-3) / 1e12, 2),
-               peak=peak_f, frac=round(fl / (phases["field"] * 1e-3) / 1e12 / peak_f, 4))
+    tf = work["mlp_flops"] / (phases["field"] * 1e-3) / 1e12
+    units = {
+        "scatter_adam": hbm("scatter_adam", ["bin_scatter", "bin_acc", "bin_finish"],
+                            work["scatter_adam"]),
+        "gather": hbm("gather", ["encode_fwd"], work["gather"]),
+        "mlp": dict(bound="mfma", kernels=["k_field"], avg_ms=round(phases["field"], 5),
+                    algorithmic_flops=int(work["mlp_flops"]), achieved=round(tf, 2),
+                    peak=peak_f, unit="TFLOP/s", frac=round(tf / peak_f, 4),
+                    hbm_bytes=int(work["field_bytes"])),
+    }
+    dominant = max(units, key=lambda k: units[k]["avg_ms"])
+    roofline = dict(units[dominant])
+    tr = traffic_of(args.workload, roofline["kernels"])
+    roofline.update(unit_name=dominant, traffic=None if tr is None else int(tr),
+                    copy_gbs=round(copy_gbs, 1), units=units,
+                    evaluated_samples=S, samples_drawn=rays_per_step * pctx.cfg.samples_per_ray,
+                    grid_params=work["grid_params"],
+                    records_per_step=int(records), record_bytes_per_step=int(10 * records),
+                    phase_ms={k: round(v, 5) for k, v in phases.items()})
     del pctx
     # ---- plain path: FP32, one launch per object per phase, no graph
     plain_ctx, _, _ = make_ctx(wl, pk.PREC_FP32, pk.BATCH_PER_OBJECT, 0)
@@ -583,7 +637,7 @@ def main():
                              dtp / args.steps * 1e3)
         log("psnr", json.dumps(quality))
     ablation = None
-    if args.ablation_density:
+    if not args.no_ablation and not args.no_psnr:
         ablation = density_ablation(wl, ids, rays, prec, args.psnr_steps)
         log("ablation", json.dumps(ablation))
     cpu = None
@@ -600,9 +654,10 @@ def main():
         "config": {"workload": wl.name, "objects": len(ids), "rays_per_step": rays_per_step,
                    "samples_per_ray": 64, "levels": 16, "batched": True, "graph": True},
         "roofline": roofline,
-        "mlp_mfma": mlp,
+        "batched_fp32": batched_fp32,
         "plain_fp32": {"value": round(plain, 1), "unit": "rays/s",
-                       "speedup": round(value / plain, 3)},
+                       "ms_per_step": round(dtp / args.steps * 1e3, 5),
+                       "ratio_at_equal_steps": round(value / plain, 3)},
         "quality": quality,
         "ablation_density": ablation,
         "mesh": mesh,

@@ -79,9 +79,12 @@ typedef struct {
   int32_t bbox_margin_pct;                 /* detection-box margin, % per side */
   int32_t precision;                       /* ROMAP_PREC_* */
   int32_t batch_mode;                      /* ROMAP_BATCH_* */
-  int32_t use_graph;                       /* replay each step as one hipGraph (captured
-                                            * when the call has >= 8 steps or the
-                                            * graph of its shapes exists) */
+  int32_t use_graph;                       /* 1: replay each step as one hipGraph
+                                            * (captured when the call has >= 8 steps
+                                            * or the graph of its shapes exists);
+                                            * 2: capture on any training call, so a
+                                            * short untimed call prepares the graph;
+                                            * 0: launch every kernel */
   int32_t autotune;                        /* pick tile shapes by timing */
   int32_t profile_phases;                  /* time each kernel of a step with HIP
                                               events (launches without a graph and

@@ -834,6 +834,7 @@ romap_status romap_create(const romap_config* cfg, void* hip_stream, romap_ctx**
   if (k.mlp_layers < 1 || k.mlp_layers > RM_MAX_MLP_LAYERS)
     return fail(nullptr, ROMAP_E_INVALID_ARG, "mlp_layers must be 1..3");
   if (k.streams != 1 && k.streams != 2) return fail(nullptr, ROMAP_E_INVALID_ARG, "streams must be 1 or 2");
+  if (k.use_graph < 0 || k.use_graph > 2) return fail(nullptr, ROMAP_E_INVALID_ARG, "use_graph must be 0, 1 or 2");
   if (!ray_count_ok(k.rays_per_step, k.samples_per_ray))
     return fail(nullptr, ROMAP_E_INVALID_ARG, "bad rays_per_step");
   if (!(k.lr > 0.0f) || !(k.beta1 >= 0.0f && k.beta1 < 1.0f) || !(k.beta2 >= 0.0f && k.beta2 < 1.0f) ||
@@ -1235,9 +1236,10 @@ static std::vector<int64_t> graph_sig(romap_ctx* c, const std::vector<std::pair<
 // A graph is used when it exists for this step already, or when the call
 // replays it often enough to repay a capture (a few milliseconds); short
 // calls with new shapes (a mapping stream's per-frame steps) run eagerly.
+// use_graph = 2 captures on any call (a caller that warms up before timing).
 static bool graph_pays(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int rpi,
                        int blk, int n_steps) {
-  if (n_steps >= RM_GRAPH_MIN_STEPS) return true;
+  if (c->cfg.use_graph == 2 || n_steps >= RM_GRAPH_MIN_STEPS) return true;
   return c->gexec && graph_sig(c, list, rpi, blk) == c->gsig;
 }
 
@@ -2107,6 +2109,12 @@ romap_status romap_load(romap_ctx* c, const char* path) {
     R(&cam, sizeof(cam));
     int32_t hd = 0;
     R(&hd, 4);
+    if (!ok) break;
+    s = validate_camera(c, &cam);  // before sizing buffers from it
+    if (s != ROMAP_OK) {
+      std::fclose(f);
+      return s;
+    }
     const size_t npix = (size_t)cam.width * cam.height;
     std::vector<uint8_t> rgb(npix * 3);
     std::vector<int32_t> mask(npix);
@@ -2155,6 +2163,12 @@ romap_status romap_load(romap_ctx* c, const char* path) {
       if (!ok || v[0] < 0 || v[0] >= (int)c->kfs.size()) {
         ok = false;
         break;
+      }
+      // the ray draw reads the keyframe's pixels inside this rectangle
+      const int kw = c->kfs[v[0]].cam.width, kh = c->kfs[v[0]].cam.height;
+      if (v[1] < 0 || v[2] < 0 || v[3] < 1 || v[4] < 1 || v[3] > kw - v[1] || v[4] > kh - v[2]) {
+        std::fclose(f);
+        return fail(c, ROMAP_E_INVALID_ARG, "checkpoint: candidate rectangle outside its keyframe");
       }
       KfRef r{};
       r.kf = v[0];

@@ -52,7 +52,8 @@ def test_default_config_and_create_validation_without_gpu():
     h = ctypes.c_void_p()
     for field, bad in [("n_levels", 17), ("samples_per_ray", 48), ("log2_table_size", 30),
                        ("precision", 5), ("rays_per_step", 0), ("mlp_layers", 0),
-                       ("mlp_layers", 4), ("streams", 0), ("streams", 3)]:
+                       ("mlp_layers", 4), ("streams", 0), ("streams", 3), ("use_graph", 3),
+                       ("use_graph", -1)]:
         c = pk.default_config(**{field: bad})
         assert L.romap_create(ctypes.byref(c), None, ctypes.byref(h)) == pk.ROMAP_E_INVALID_ARG
         assert L.romap_last_error(None)

@@ -427,6 +427,44 @@ def test_checkpoint_roundtrip_continues_identically(tiny, tmp_path):
     assert abs(la - lb) <= 1e-6 * abs(la)
 
 
+def test_checkpoint_with_a_corrupt_rectangle_is_rejected(tiny, tmp_path):
+    """A keyframe reference whose candidate rectangle leaves its keyframe (or
+    is empty) makes load fail with E_INVALID_ARG; nothing is trained after
+    it (the ray draw would read outside the keyframe's pixels)."""
+    import struct
+    frames, box = tiny
+    cfg = dict(n_levels=8, base_res=16, max_res=128, log2_table_size=12, samples_per_ray=32,
+               rays_per_step=256, autotune=0)
+    a = pk.Context(pk.default_config(**cfg))
+    gid = a.add_object(1, box["t"], box["yaw"], box["half"])
+    for cam, rgb, mask, depth in frames:
+        a.add_keyframe(cam, rgb, mask, depth)
+    path = tmp_path / "ck.bin"
+    a.save(path)
+    raw = bytearray(path.read_bytes())
+    # one object: its keyframe references (5 int32 each) precede its
+    # parameters and Adam moments (3 x P rounded up to 64 floats)
+    P = a.get_params(gid).size
+    nref = a.object_info(gid).n_keyframes
+    first = len(raw) - 3 * 4 * (-(-P // 64) * 64) - 20 * nref
+    kf, x0, y0, w, h = struct.unpack_from("<5i", raw, first)
+    W, H = frames[kf][1].shape[1], frames[kf][1].shape[0]
+    for k, v in [(1, -1), (2, -1), (3, 0), (4, 0), (3, W - x0 + 1), (4, H - y0 + 1),
+                 (3, 2 ** 31 - 1)]:
+        bad = bytearray(raw)
+        struct.pack_into("<i", bad, first + 4 * k, v)
+        p2 = tmp_path / f"bad{k}_{v}.bin"
+        p2.write_bytes(bytes(bad))
+        b = pk.Context(pk.default_config(**cfg))
+        with pytest.raises(pk.RomapError) as e:
+            b.load(p2)
+        assert e.value.code == pk.ROMAP_E_INVALID_ARG, (k, v)
+        del b
+    b = pk.Context(pk.default_config(**cfg))  # the untouched file still loads
+    b.load(path)
+    assert np.array_equal(a.get_params(gid), b.get_params(0))
+
+
 # ------------------------------------------------------------------ occupancy skip
 def test_occupancy_skip_parity(tiny):
     _say("occupancy parity")
