@@ -208,8 +208,10 @@ romap_status romap_train(romap_ctx* ctx, const int32_t* object_ids, int32_t n_ob
 
 /* One step's loss and gradient without the Adam update or step advance: the
  * gradient buffer is cleared, then holds dL/dparams (read it with kind
- * ROMAP_GRAD).  Objects and ray counts as for romap_train.  losses (host,
- * n_objects floats) may be NULL. */
+ * ROMAP_GRAD).  Objects and ray counts as for romap_train, in one launch per
+ * kernel on the context stream with the launch shape a training step of
+ * these objects takes (autotuned, or the romap_debug_tiles shape).  losses
+ * (host, n_objects floats) may be NULL. */
 romap_status romap_loss_and_grad(romap_ctx* ctx, const int32_t* object_ids, int32_t n_objects,
                                  const int32_t* rays_per_object, float* losses);
 
@@ -311,6 +313,13 @@ romap_status romap_debug_encode(romap_ctx* ctx, int32_t object_id, const float* 
  * the region's accumulation: results are the same up to rounding order, the
  * step only slower.  ROMAP_E_INVALID_ARG if slots < 0. */
 romap_status romap_debug_bin_capacity(romap_ctx* ctx, int32_t slots);
+/* For tests of the launch shapes the autotuner chooses among: with
+ * autotune = 0, training steps and romap_loss_and_grad launch the field
+ * kernel with `rays_per_item` rays per workgroup (4, 8, 16 or 32) and the
+ * gather kernel with `gather_block` samples per block (128, 256 or 512);
+ * the defaults are 8 and 256.  Results are the same up to rounding order.
+ * ROMAP_E_INVALID_ARG for other values. */
+romap_status romap_debug_tiles(romap_ctx* ctx, int32_t rays_per_item, int32_t gather_block);
 
 /* ---- differentiable surface (for torch.autograd.Function) ----------------
  * rays_dev: n_rays*8 floats per ray: origin[3], unit direction[3], t_near,

@@ -95,13 +95,15 @@ def lib():
         _lib.or_bf16_gap.argtypes = [C.c_double]
         _lib.or_bf16_gap.restype = C.c_double
         _lib.or_bf16_set_jitter.argtypes = [C.c_double]
+        _lib.or_set_tie_jitter.argtypes = [C.c_double]
+        _lib.or_set_jitter_seed.argtypes = [C.c_uint64]
         _lib.or_composite.argtypes = [C.c_int, P, P, P, C.c_double, C.c_int, P, P, P, P, P]
         _lib.or_candidate_rect.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P]
         _lib.or_draw_ray.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, C.c_int,
                                      C.POINTER(Keyframe), C.c_int, C.POINTER(Ray)]
         _lib.or_object_step.argtypes = [C.POINTER(Config), C.POINTER(Levels), C.c_int, C.c_int, P,
                                         C.c_int, C.POINTER(Keyframe), C.c_int, C.c_int, P, P, P, P,
-                                        P, P, P, P, C.POINTER(Ray), C.c_int]
+                                        P, P, P, P, P, C.POINTER(Ray), C.c_int]
         _lib.or_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int, C.c_double, C.c_double,
                                  C.c_double, C.c_double]
         _lib.or_render.argtypes = [C.POINTER(Config), C.POINTER(Levels), P, C.POINTER(Keyframe), P,
@@ -115,7 +117,7 @@ def lib():
         _lib.or_marching_cubes.argtypes = [P, C.c_int, C.c_float, P, P, P, C.c_int64]
         _lib.or_marching_cubes.restype = C.c_int64
         _lib.or_field.argtypes = [C.POINTER(Config), C.POINTER(Levels), P, P, C.c_int, P, P, P, P,
-                                  P, P, P, P, P, P, C.c_int]
+                                  P, P, P, P, P, P, P, C.c_int]
     return _lib
 
 
@@ -262,6 +264,18 @@ def set_bf16_jitter(rel: float) -> None:
     rel |x| before it is rounded, imitating a computation with rounding
     error; 0 switches it off."""
     lib().or_bf16_set_jitter(float(rel))
+
+
+def set_tie_jitter(rel: float) -> None:
+    """Tests only: move every ReLU pre-activation by at most rel times the sum
+    of |terms| that form it before its branch is taken, imitating a
+    computation with rounding error; 0 switches it off."""
+    lib().or_set_tie_jitter(float(rel))
+
+
+def set_jitter_seed(seed: int) -> None:
+    """Tests only: another deterministic perturbation for both jitters."""
+    lib().or_set_jitter_seed(int(seed))
 
 
 def mlp_forward(din, mlp, e, layers=1, bf16=False):
@@ -421,21 +435,23 @@ class OracleContext:
         return arr
 
     def loss_and_grad(self, oid, step, B, rays=False, params=None, want_grad=True, mass=None,
-                      ambiguous=None, margin=None, loss_allow=None):
+                      ambiguous=None, margin=None, loss_allow=None, bf16_allow=None):
         """Loss of one step and dL/dparams (no optimiser update).  mass: an array
         of the parameter count that receives the magnitude of every gradient
         entry, the same backward on absolute values, which bounds to first order
         how far rounding (in any order of summation) can move the entry.
-        ambiguous: an array of the parameter count that receives, for samples
-        whose decisions (ReLU branch, density clamp, depth-error sign) lie within
-        1e-5 relative of a tie, the magnitude of their contributions with every
-        branch taken: how far another branch choice can move each entry.
+        ambiguous: an array of the parameter count that receives, for every
+        decision (ReLU branch, density clamp) that lies within 1e-5 relative
+        of its tie, the change of its sample's contributions under the other
+        branch (first order), and for rays whose depth-error sign ties, twice
+        the magnitude of their samples' contributions: how far other branch
+        choices can move each entry.
         margin: a 1-element array that receives the smallest relative distance
         of a decision from its tie in the step.
         loss_allow (BF16 mode): a 1-element array that receives the bound of
         the change of the loss under the other choice of every ambiguous BF16
-        rounding (ambiguous then also holds that change for every gradient
-        entry)."""
+        rounding; bf16_allow (BF16 mode) the same bound for every gradient
+        entry."""
         o = self.objects[oid]
         if not o.kfs:
             raise RuntimeError("object has no keyframes")
@@ -450,6 +466,7 @@ class OracleContext:
                                   _p(grad) if want_grad else None,
                                   _p(mass) if (want_grad and mass is not None) else None,
                                   None if ambiguous is None else _p(ambiguous),
+                                  None if bf16_allow is None else _p(bf16_allow),
                                   None if margin is None else _p(margin),
                                   _p(loss), None if loss_allow is None else _p(loss_allow),
                                   ray_buf, self.nthreads)
@@ -490,7 +507,7 @@ class OracleContext:
         return rgb, depth, opac
 
     def field(self, oid, rays, params=None, d_rgb=None, d_depth=None, d_tend=None, grad=False,
-              mass=None, ambiguous=None):
+              mass=None, ambiguous=None, bf16_allow=None):
         """rays: (n, 8) float32 object-frame rays (o, d, t_near, t_far).  Returns
         rgb, depth, T_end and, with grad, d(sum d_rgb.C + d_depth D + d_tend T_end)/dparams."""
         o = self.objects[oid]
@@ -506,7 +523,9 @@ class OracleContext:
                        None if dd is None else _p(dd), None if dt is None else _p(dt),
                        None if g is None else _p(g),
                        None if (g is None or mass is None) else _p(mass),
-                       None if (g is None or ambiguous is None) else _p(ambiguous), self.nthreads)
+                       None if (g is None or ambiguous is None) else _p(ambiguous),
+                       None if (g is None or bf16_allow is None) else _p(bf16_allow),
+                       self.nthreads)
         return rgb, depth, tend, g
 
     def set_occupancy(self, oid, bits):

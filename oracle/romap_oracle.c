@@ -262,17 +262,31 @@ double or_bf16_gap(double x) {
  * allowances of the tests must cover the change this makes. */
 static double g_bf16_jitter = 0.0;
 void or_bf16_set_jitter(double rel) { g_bf16_jitter = rel; }
+/* Tests only: with a nonzero tie jitter the backward takes the branch of
+ * every ReLU unit from its pre-activation moved by at most rel times the sum
+ * of |terms| that form it (a deterministic function of its value), with the
+ * forward unchanged: a branch taken the other way, as a computation with
+ * rounding error may take it near a tie; the tie allowances of the tests
+ * must cover the change this makes.  The seed selects another such function
+ * for both jitters. */
+static double g_tie_jitter = 0.0;
+static uint64_t g_jitter_seed = 0;
+void or_set_tie_jitter(double rel) { g_tie_jitter = rel; }
+void or_set_jitter_seed(uint64_t seed) { g_jitter_seed = seed; }
 
-static double jitter(double x) {
+/* a deterministic value in [-1, 1) from the bits of x and the seed */
+static double jitter_unit(double x) {
   uint64_t u;
   memcpy(&u, &x, sizeof u);
-  u += 0x9E3779B97F4A7C15ull; /* splitmix64 finaliser of the bits of x */
+  u += 0x9E3779B97F4A7C15ull * (1ull + 2ull * g_jitter_seed); /* splitmix64 finaliser */
   u = (u ^ (u >> 30)) * 0xBF58476D1CE4E5B9ull;
   u = (u ^ (u >> 27)) * 0x94D049BB133111EBull;
   u ^= u >> 31;
-  const double h = (double)(u >> 11) * 0x1p-53 * 2.0 - 1.0; /* [-1, 1) */
-  return x * (1.0 + g_bf16_jitter * h);
+  return (double)(u >> 11) * 0x1p-53 * 2.0 - 1.0;
 }
+
+static double jitter(double x) { return x * (1.0 + g_bf16_jitter * jitter_unit(x)); }
+
 
 /* an operand of a contraction (activation or adjoint) */
 static inline double rbf(int on, double x) {
@@ -280,6 +294,20 @@ static inline double rbf(int on, double x) {
 }
 /* a weight (an FP32 value on either side: never jittered) */
 static inline double rbw(int on, double x) { return on ? or_bf16(x) : x; }
+
+/* Branch of a ReLU unit in the backward: its output h is positive; under
+ * the tie jitter, its pre-activation (row W of K weights against the layer
+ * input x) moved as described above is. */
+static int relu_open(int bf, double h, const double* W, const double* x, int K) {
+  if (g_tie_jitter == 0.0) return h > 0.0;
+  double pre = 0.0, mag = 0.0;
+  for (int j = 0; j < K; ++j) {
+    const double t = rbw(bf, W[j]) * rbf(bf, x[j]);
+    pre += t;
+    mag += fabs(t);
+  }
+  return pre + g_tie_jitter * mag * jitter_unit(pre) > 0.0;
+}
 
 /* Density / colour MLP (Sec. V: a single hidden layer of 64 per head; position
  * only, no view direction, Sec. V-B; the model-size study of Table 4 also
@@ -501,7 +529,7 @@ static void sample_backward(const or_levels* lv, int din, const double* mlp, con
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double s = 0.0;
     for (int k = 0; k < 3; ++k) s += rbw(bf, W4[k * OR_HIDDEN + j]) * rbf(bf, dz4[k]);
-    dh2[j] = h2[j] > 0.0 ? s : 0.0;
+    dh2[j] = relu_open(bf, h2[j], W3 + j * OR_GEO, y + 1, OR_GEO) ? s : 0.0;
   }
   for (int j = 0; j < OR_HIDDEN; ++j)
     for (int g = 0; g < OR_GEO; ++g) gW3[j * OR_GEO + g] += rbf(bf, dh2[j]) * rbf(bf, y[1 + g]);
@@ -515,22 +543,31 @@ static void sample_backward(const or_levels* lv, int din, const double* mlp, con
   const double* hl = h1 + (nh - 1) * OR_HIDDEN;
   for (int i = 0; i < OR_DOUT; ++i)
     for (int j = 0; j < OR_HIDDEN; ++j) gW2[i * OR_HIDDEN + j] += rbf(bf, dy[i]) * rbf(bf, hl[j]);
-  for (int j = 0; j < OR_HIDDEN; ++j) {
-    double s = 0.0;
-    for (int i = 0; i < OR_DOUT; ++i) s += rbw(bf, W2[i * OR_HIDDEN + j]) * rbf(bf, dy[i]);
-    dh[j] = hl[j] > 0.0 ? s : 0.0;
+  {
+    /* the last hidden layer's rows and input */
+    const double* Wl = nh == 1 ? W1 : Wh + (nh - 2) * OR_HIDDEN * OR_HIDDEN;
+    const double* xl = nh == 1 ? e : h1 + (nh - 2) * OR_HIDDEN;
+    const int Kl = nh == 1 ? din : OR_HIDDEN;
+    for (int j = 0; j < OR_HIDDEN; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < OR_DOUT; ++i) s += rbw(bf, W2[i * OR_HIDDEN + j]) * rbf(bf, dy[i]);
+      dh[j] = relu_open(bf, hl[j], Wl + j * Kl, xl, Kl) ? s : 0.0;
+    }
   }
   /* hidden-to-hidden layers, last to first: dh is the adjoint of h_k */
   for (int k = nh - 1; k >= 1; --k) {
     const double* W = Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
     double* gW = gWh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
     const double* hp = h1 + (k - 1) * OR_HIDDEN;
+    const double* Wp = k == 1 ? W1 : Wh + (k - 2) * OR_HIDDEN * OR_HIDDEN;
+    const double* xp = k == 1 ? e : h1 + (k - 2) * OR_HIDDEN;
+    const int Kp = k == 1 ? din : OR_HIDDEN;
     for (int i = 0; i < OR_HIDDEN; ++i)
       for (int j = 0; j < OR_HIDDEN; ++j) gW[i * OR_HIDDEN + j] += rbf(bf, dh[i]) * rbf(bf, hp[j]);
     for (int j = 0; j < OR_HIDDEN; ++j) {
       double s = 0.0;
       for (int i = 0; i < OR_HIDDEN; ++i) s += rbw(bf, W[i * OR_HIDDEN + j]) * rbf(bf, dh[i]);
-      dp[j] = hp[j] > 0.0 ? s : 0.0;
+      dp[j] = relu_open(bf, hp[j], Wp + j * Kp, xp, Kp) ? s : 0.0;
     }
     memcpy(dh, dp, sizeof(dh));
   }
@@ -1098,35 +1135,204 @@ static void bf16_ray_allowance(const or_levels* lv, int N, const double* params,
   }
 }
 
+/* Tests only.  Adds into amb the change of one sample's gradient
+ * contributions when one of its decisions goes the other way.  The decision's
+ * pre-activation lies within rounding distance of its tie, so to first order
+ * the forward values stay and only the branch of one adjoint changes: the
+ * unmasked adjoint v of that unit is added or removed there, and carried
+ * down through the layers below with their own decisions; |each term| is
+ * added.  stage: 0 .. layers-1 a hidden layer of the density MLP, layers the
+ * colour head's hidden layer, layers + 1 the density clamp (unit unused). */
+static void flip_delta(const or_levels* lv, int din, const double* mlp, const uint32_t* idx,
+                       const double* w, const double* e, const double* h1, const double* y,
+                       int stage, int unit, double v, double* amb) {
+  const int nh = lv->mlp_layers, bf = lv->mlp_bf16;
+  const double* W1 = mlp;
+  const double* Wh = W1 + OR_HIDDEN * din;
+  const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
+  const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
+  double* aG = amb;
+  double* aW1 = amb + or_grid_params(lv);
+  double* aWh = aW1 + OR_HIDDEN * din;
+  double* aW2 = aWh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
+  double* aW3 = aW2 + OR_DOUT * OR_HIDDEN;
+  double dy[OR_DOUT], dh[OR_HIDDEN], dp[OR_HIDDEN], de[2 * OR_MAX_LEVELS];
+  int k;
+  if (stage >= nh) {
+    for (int i = 0; i < OR_DOUT; ++i) dy[i] = 0.0;
+    if (stage == nh) { /* colour head hidden unit */
+      for (int g = 0; g < OR_GEO; ++g) {
+        aW3[unit * OR_GEO + g] += fabs(v * rbf(bf, y[1 + g]));
+        dy[1 + g] = rbw(bf, W3[unit * OR_GEO + g]) * v;
+      }
+    } else {
+      dy[0] = v;
+    }
+    const double* hl = h1 + (nh - 1) * OR_HIDDEN;
+    for (int i = 0; i < OR_DOUT; ++i)
+      if (dy[i] != 0.0)
+        for (int j = 0; j < OR_HIDDEN; ++j) aW2[i * OR_HIDDEN + j] += fabs(dy[i] * rbf(bf, hl[j]));
+    for (int j = 0; j < OR_HIDDEN; ++j) {
+      double t = 0.0;
+      for (int i = 0; i < OR_DOUT; ++i) t += rbw(bf, W2[i * OR_HIDDEN + j]) * dy[i];
+      dh[j] = hl[j] > 0.0 ? t : 0.0;
+    }
+    k = nh - 1;
+  } else {
+    for (int j = 0; j < OR_HIDDEN; ++j) dh[j] = 0.0;
+    dh[unit] = v;
+    k = stage;
+  }
+  for (; k >= 1; --k) {
+    const double* W = Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    double* aW = aWh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    const double* hp = h1 + (k - 1) * OR_HIDDEN;
+    for (int i = 0; i < OR_HIDDEN; ++i)
+      if (dh[i] != 0.0)
+        for (int j = 0; j < OR_HIDDEN; ++j) aW[i * OR_HIDDEN + j] += fabs(dh[i] * rbf(bf, hp[j]));
+    for (int j = 0; j < OR_HIDDEN; ++j) {
+      double t = 0.0;
+      for (int i = 0; i < OR_HIDDEN; ++i) t += rbw(bf, W[i * OR_HIDDEN + j]) * dh[i];
+      dp[j] = hp[j] > 0.0 ? t : 0.0;
+    }
+    memcpy(dh, dp, sizeof(dh));
+  }
+  for (int j = 0; j < OR_HIDDEN; ++j)
+    if (dh[j] != 0.0)
+      for (int q = 0; q < din; ++q) aW1[j * din + q] += fabs(dh[j] * rbf(bf, e[q]));
+  for (int q = 0; q < din; ++q) {
+    double t = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) t += rbw(bf, W1[j * din + q]) * dh[j];
+    de[q] = t;
+  }
+  for (int l = 0; l < lv->L; ++l)
+    for (int b = 0; b < 8; ++b) {
+      const int64_t at = lv->off[l] + 2 * (int64_t)idx[8 * l + b];
+      aG[at + 0] += fabs(w[8 * l + b] * de[2 * l + 0]);
+      aG[at + 1] += fabs(w[8 * l + b] * de[2 * l + 1]);
+    }
+}
+
+/* Tests only.  For every decision of one sample that lies closer than kTie
+ * (relative to the sum of |terms| that form its pre-activation, less the
+ * bound F of what BF16 decisions upstream can move it; F may be NULL) to its
+ * tie, adds the change of the sample's contributions under the other branch
+ * (flip_delta).  dsig, dc: the sample's signed adjoints of density and
+ * colour, as in sample_backward. */
+static void sample_tie_deltas(const or_levels* lv, int din, const double* mlp,
+                              const uint32_t* idx, const double* w, const double* e,
+                              const double* h1, const double* y, const double* h2, double sigma,
+                              const double* rgb, double dsig, const double* dc,
+                              const struct or_fpert_s* F, double kTie, double* amb) {
+  const int nh = lv->mlp_layers, bf = lv->mlp_bf16;
+  const double* W1 = mlp;
+  const double* Wh = W1 + OR_HIDDEN * din;
+  const double* W2 = Wh + (nh - 1) * OR_HIDDEN * OR_HIDDEN;
+  const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
+  const double* W4 = W3 + OR_HIDDEN * OR_GEO;
+  double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], un[OR_HIDDEN], dh[OR_HIDDEN];
+  for (int k = 0; k < 3; ++k) dz4[k] = dc[k] * rgb[k] * (1.0 - rgb[k]);
+  /* colour head: unmasked adjoints of its hidden units, and their ties */
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double t = 0.0;
+    for (int k = 0; k < 3; ++k) t += rbw(bf, W4[k * OR_HIDDEN + j]) * rbf(bf, dz4[k]);
+    double pre = 0.0, mag = 0.0;
+    for (int g = 0; g < OR_GEO; ++g) {
+      const double q = rbw(bf, W3[j * OR_GEO + g]) * rbf(bf, y[1 + g]);
+      pre += q;
+      mag += fabs(q);
+    }
+    const double P = F ? F->Ppre2[j] : 0.0;
+    if (mag > 0.0 && (fabs(pre) - P) / mag < kTie)
+      flip_delta(lv, din, mlp, idx, w, e, h1, y, nh, j, rbf(bf, t), amb);
+    dh2[j] = h2[j] > 0.0 ? t : 0.0;
+  }
+  for (int g = 0; g < OR_GEO; ++g) {
+    double t = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) t += rbw(bf, W3[j * OR_GEO + g]) * rbf(bf, dh2[j]);
+    dy[1 + g] = t;
+  }
+  /* density clamp */
+  const double* hl = h1 + (nh - 1) * OR_HIDDEN;
+  {
+    double mag0 = 0.0;
+    for (int j = 0; j < OR_HIDDEN; ++j) mag0 += fabs(rbw(bf, W2[j]) * rbf(bf, hl[j]));
+    const double P0 = F ? F->Py[0] : 0.0;
+    if (mag0 > 0.0 && (fabs(y[0] - 15.0) - P0) / mag0 < kTie)
+      flip_delta(lv, din, mlp, idx, w, e, h1, y, nh + 1, 0, rbf(bf, dsig * sigma), amb);
+  }
+  dy[0] = y[0] < 15.0 ? dsig * sigma : 0.0;
+  /* density MLP, last hidden layer first: un = unmasked adjoint of h_k */
+  for (int j = 0; j < OR_HIDDEN; ++j) {
+    double t = 0.0;
+    for (int i = 0; i < OR_DOUT; ++i) t += rbw(bf, W2[i * OR_HIDDEN + j]) * rbf(bf, dy[i]);
+    un[j] = t;
+  }
+  for (int k = nh - 1; k >= 0; --k) {
+    const double* W = k == 0 ? W1 : Wh + (k - 1) * OR_HIDDEN * OR_HIDDEN;
+    const double* x = k == 0 ? e : h1 + (k - 1) * OR_HIDDEN;
+    const double* hk = h1 + k * OR_HIDDEN;
+    const int K = k == 0 ? din : OR_HIDDEN;
+    for (int i = 0; i < OR_HIDDEN; ++i) {
+      double pre = 0.0, mag = 0.0;
+      for (int j = 0; j < K; ++j) {
+        const double q = rbw(bf, W[i * K + j]) * rbf(bf, x[j]);
+        pre += q;
+        mag += fabs(q);
+      }
+      const double P = F ? F->Ppre[k * OR_HIDDEN + i] : 0.0;
+      if (mag > 0.0 && (fabs(pre) - P) / mag < kTie)
+        flip_delta(lv, din, mlp, idx, w, e, h1, y, k, i, rbf(bf, un[i]), amb);
+      dh[i] = hk[i] > 0.0 ? un[i] : 0.0;
+    }
+    if (k >= 1) {
+      for (int j = 0; j < OR_HIDDEN; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < OR_HIDDEN; ++i) t += rbw(bf, W[i * OR_HIDDEN + j]) * rbf(bf, dh[i]);
+        un[j] = t;
+      }
+    }
+  }
+}
+
 /* Tests only.  Smallest distance of a ray's decisions from their ties
- * (dtie: that of its depth-error sign), and into amb (may be NULL), for each
- * sample with a decision closer than 1e-5: the magnitude of its gradient
- * contributions with every branch taken, which bounds the change another
- * branch choice can make (twice for every sample when the depth sign ties).
- * Needs the forward of the ray and the magnitudes dsig_m of ray_backward (in
- * BF16 mode also bf16_ray_allowance: a pre-activation that BF16 decisions
- * upstream can move by P ties when |pre| <= 1e-5 magnitude + P). */
+ * (dtie: that of its depth-error sign), and into amb (may be NULL) what
+ * another choice of each decision closer than 1e-5 to its tie can change:
+ * for the ReLU branches and the density clamp of a sample, the change of its
+ * contributions under the other branch (sample_tie_deltas); when the ray's
+ * depth-error sign ties, twice the magnitude of every sample's contributions
+ * with every branch taken.  gC: the ray's colour adjoint.  Needs the forward
+ * and ray_backward of the ray (in BF16 mode also bf16_ray_allowance: a
+ * pre-activation that BF16 decisions upstream can move by P ties when
+ * |pre| <= 1e-5 magnitude + P). */
 static double tie_allowance(const or_levels* lv, int N, const double* params, or_scratch* s,
-                            const double gCabs[3], double dtie, double* amb) {
+                            const double gC[3], double dtie, double* amb) {
   const double kTie = 1e-5;
   const int L = lv->L, nh = lv->mlp_layers;
   const double* mlp = params + or_grid_params(lv);
   double rm = dtie;
   for (int i = 0; i < N; ++i) {
     if (!s->live[i]) continue;
+    const struct or_fpert_s* F = lv->mlp_bf16 && s->fp_valid ? s->fp + i : NULL;
     const double sm = sample_ties(lv, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
-                                  s->y + OR_DOUT * i,
-                                  lv->mlp_bf16 && s->fp_valid ? s->fp + i : NULL);
+                                  s->y + OR_DOUT * i, F);
     rm = fmin(rm, sm);
-    const int reps = dtie < kTie ? 2 : (sm < kTie ? 1 : 0);
-    if (amb && reps) {
+    if (!amb) continue;
+    if (dtie < kTie) {
       double dcm[3];
-      for (int k = 0; k < 3; ++k) dcm[k] = s->wts[i] * gCabs[k];
-      for (int rep = 0; rep < reps; ++rep)
+      for (int k = 0; k < 3; ++k) dcm[k] = s->wts[i] * fabs(gC[k]);
+      for (int rep = 0; rep < 2; ++rep)
         sample_backward_magnitude(lv, 2 * L, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
                                   s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
                                   s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma[i],
                                   s->rgb + 3 * i, s->dsig_m[i], dcm, 1, amb);
+    }
+    if (sm < kTie) {
+      double dc[3];
+      for (int k = 0; k < 3; ++k) dc[k] = s->wts[i] * gC[k];
+      sample_tie_deltas(lv, 2 * L, mlp, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i,
+                        s->h1 + OR_HIDDEN * nh * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i,
+                        s->sigma[i], s->rgb + 3 * i, s->dsig[i], dc, F, kTie, amb);
     }
   }
   return rm;
@@ -1144,8 +1350,8 @@ static void reduce_threads(const double* t, int nthreads, int64_t P, double* out
 int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int instance,
                    const float half[3], int nkf, const or_keyframe* kfs, int step, int B,
                    const double* params, const uint8_t* occ, double* grad, double* grad_abs,
-                   double* ambiguous, double* min_margin, double* loss, double* loss_allow,
-                   or_ray* rays, int nthreads) {
+                   double* ambiguous, double* bf16_allow, double* min_margin, double* loss,
+                   double* loss_allow, or_ray* rays, int nthreads) {
   if (nkf < 1 || B < 1 || cfg->N < 1) return -1;
   const int L = lv->L, N = cfg->N;
   const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L, lv->mlp_layers);
@@ -1158,8 +1364,11 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
   double* tamb = NULL;
   if (grad) tgrad = (double*)calloc((size_t)P * nthreads, sizeof(double));
   if (grad && grad_abs) tabs = (double*)calloc((size_t)P * nthreads, sizeof(double));
+  double* tbam = NULL;
   if (grad && ambiguous) tamb = (double*)calloc((size_t)P * nthreads, sizeof(double));
+  if (grad && bf16_allow) tbam = (double*)calloc((size_t)P * nthreads, sizeof(double));
   if (ambiguous) memset(ambiguous, 0, sizeof(double) * (size_t)P);
+  if (bf16_allow) memset(bf16_allow, 0, sizeof(double) * (size_t)P);
 
 #pragma omp parallel num_threads(nthreads)
   {
@@ -1172,6 +1381,7 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
     double* my_grad = grad ? tgrad + (int64_t)tid * P : NULL;
     double* my_abs = tabs ? tabs + (int64_t)tid * P : NULL;
     double* my_amb = tamb ? tamb + (int64_t)tid * P : NULL;
+    double* my_bam = tbam ? tbam + (int64_t)tid * P : NULL;
 #pragma omp for schedule(static)
     for (int r = 0; r < B; ++r) {
       or_ray ray;
@@ -1211,9 +1421,9 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
                        bg ? cfg->lambda_density / (double)B : 0.0, my_grad, my_abs);
         /* tests only: what the BF16 decisions and the ties can move */
         double dC[3] = {0.0, 0.0, 0.0}, dD = 0.0, dT = 0.0, dS = 0.0;
-        if (lv->mlp_bf16 && (loss_allow || my_amb))
+        if (lv->mlp_bf16 && (loss_allow || my_amb || my_bam))
           bf16_ray_allowance(lv, N, params, &s, (double)ray.delta, bg, crand, ray.Tend, gC, gD,
-                             0.0, 1, target, 1.0 / (double)B, my_grad ? my_amb : NULL, dC, &dD,
+                             0.0, 1, target, 1.0 / (double)B, my_grad ? my_bam : NULL, dC, &dD,
                              &dT, &dS);
         double la = 0.0;
         for (int k = 0; k < 3; ++k)
@@ -1224,9 +1434,7 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
         double dtie = INFINITY;
         if (!bg && ray.has_depth)
           dtie = (fabs(ray.Dhat - (double)ray.D) - dD) / fmax(fabs((double)ray.D), 1e-30);
-        double gCa[3];
-        for (int k = 0; k < 3; ++k) gCa[k] = fabs(gC[k]);
-        const double rm = tie_allowance(lv, N, params, &s, gCa, dtie, my_grad ? my_amb : NULL);
+        const double rm = tie_allowance(lv, N, params, &s, gC, dtie, my_grad ? my_amb : NULL);
         ray_margin[r] = rm;
       } else {
         ray_margin[r] = INFINITY;
@@ -1248,9 +1456,11 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
   if (grad) reduce_threads(tgrad, nthreads, P, grad);
   if (tabs) reduce_threads(tabs, nthreads, P, grad_abs);
   if (tamb) reduce_threads(tamb, nthreads, P, ambiguous);
+  if (tbam) reduce_threads(tbam, nthreads, P, bf16_allow);
   free(tgrad);
   free(tabs);
   free(tamb);
+  free(tbam);
   free(ray_loss);
   free(ray_margin);
   free(ray_lallow);
@@ -1265,14 +1475,16 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
 int or_field(const or_config* cfg, const or_levels* lv, const float half[3], const double* params,
              int n, const float* rays, double* rgb, double* depth, double* tend,
              const double* d_rgb, const double* d_depth, const double* d_tend, double* grad,
-             double* grad_abs, double* ambiguous, int nthreads) {
+             double* grad_abs, double* ambiguous, double* bf16_allow, int nthreads) {
   const int L = lv->L, N = cfg->N;
   const int64_t P = or_grid_params(lv) + or_mlp_params(2 * L, lv->mlp_layers);
   if (nthreads < 1) nthreads = 1;
   double* tgrad = grad ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
   double* tabs = (grad && grad_abs) ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
   double* tamb = (grad && ambiguous) ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
+  double* tbam = (grad && bf16_allow) ? (double*)calloc((size_t)P * nthreads, sizeof(double)) : NULL;
   if (ambiguous) memset(ambiguous, 0, sizeof(double) * (size_t)P);
+  if (bf16_allow) memset(bf16_allow, 0, sizeof(double) * (size_t)P);
 #pragma omp parallel num_threads(nthreads)
   {
     int tid = 0;
@@ -1300,15 +1512,15 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
         ray_backward(lv, N, params, (double)delta, &s, 0, zero, Tend, gC,
                      d_depth ? d_depth[r] : 0.0, d_tend ? d_tend[r] : 0.0, 0.0,
                      tgrad + (int64_t)tid * P, tabs ? tabs + (int64_t)tid * P : NULL);
-        const double gCa[3] = {fabs(gC[0]), fabs(gC[1]), fabs(gC[2])};
         double* my_amb = tamb ? tamb + (int64_t)tid * P : NULL;
-        if (my_amb && lv->mlp_bf16) {
+        double* my_bam = tbam ? tbam + (int64_t)tid * P : NULL;
+        if ((my_amb || my_bam) && lv->mlp_bf16) {
           double dC[3], dD, dT, dS;
           bf16_ray_allowance(lv, N, params, &s, (double)delta, 0, zero, Tend, gC,
                              d_depth ? d_depth[r] : 0.0, d_tend ? d_tend[r] : 0.0, 0, zero, 0.0,
-                             my_amb, dC, &dD, &dT, &dS);
+                             my_bam, dC, &dD, &dT, &dS);
         }
-        if (my_amb) tie_allowance(lv, N, params, &s, gCa, INFINITY, my_amb);
+        if (my_amb) tie_allowance(lv, N, params, &s, gC, INFINITY, my_amb);
       }
     }
     scratch_free(&s);
@@ -1316,9 +1528,11 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
   if (grad) reduce_threads(tgrad, nthreads, P, grad);
   if (tabs) reduce_threads(tabs, nthreads, P, grad_abs);
   if (tamb) reduce_threads(tamb, nthreads, P, ambiguous);
+  if (tbam) reduce_threads(tbam, nthreads, P, bf16_allow);
   free(tgrad);
   free(tabs);
   free(tamb);
+  free(tbam);
   return 0;
 }
 

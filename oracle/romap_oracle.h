@@ -72,6 +72,8 @@ void or_encode(const or_levels* lv, const float p[3], const double* grid, uint32
 double or_bf16(double x);
 double or_bf16_gap(double x);
 void or_bf16_set_jitter(double rel); /* tests only */
+void or_set_tie_jitter(double rel);  /* tests only */
+void or_set_jitter_seed(uint64_t seed); /* tests only */
 void or_mlp_forward(int din, int layers, int bf16, const double* mlp, const double* e, double* h1,
                     double* y, double* h2, double* sigma, double* rgb);
 void or_composite(int N, const double* sigma, const double* rgb, const double* dist, double delta,
@@ -84,12 +86,12 @@ void or_draw_ray(const or_config* cfg, int obj, int step, int r, int nkf, const 
 int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int instance,
                    const float half[3], int nkf, const or_keyframe* kfs, int step, int B,
                    const double* params, const uint8_t* occ, double* grad, double* grad_abs,
-                   double* ambiguous, double* min_margin, double* loss, double* loss_allow,
-                   or_ray* rays, int nthreads);
+                   double* ambiguous, double* bf16_allow, double* min_margin, double* loss,
+                   double* loss_allow, or_ray* rays, int nthreads);
 int or_field(const or_config* cfg, const or_levels* lv, const float half[3], const double* params,
              int n, const float* rays, double* rgb, double* depth, double* tend,
              const double* d_rgb, const double* d_depth, const double* d_tend, double* grad,
-             double* grad_abs, double* ambiguous, int nthreads);
+             double* grad_abs, double* ambiguous, double* bf16_allow, int nthreads);
 void or_adam(int64_t P, double* p, double* g, double* m, double* v, int k, double lr, double b1,
              double b2, double eps);
 int or_render(const or_config* cfg, const or_levels* lv, const float half[3],

@@ -81,7 +81,7 @@ EXPORTS = ["romap_default_config", "romap_create", "romap_destroy", "romap_last_
            "romap_field_backward", "romap_get_phase_times", "romap_sync", "romap_set_occupancy",
            "romap_update_occupancy", "romap_get_occupancy", "romap_marching_cubes",
            "romap_extract_mesh", "romap_mc_case", "romap_box_from_points",
-           "romap_debug_bin_capacity", "romap_get_step_records"]
+           "romap_debug_bin_capacity", "romap_get_step_records", "romap_debug_tiles"]
 
 
 def lib():
@@ -124,6 +124,7 @@ def lib():
             "romap_extract_mesh": [P, i32, i32, C.c_float, i32, P, i64, C.POINTER(i64), i32],
             "romap_mc_case": [i32, P],
             "romap_debug_bin_capacity": [P, i32],
+            "romap_debug_tiles": [P, i32, i32],
             "romap_get_step_records": [P, C.POINTER(C.c_double)],
             "romap_box_from_points": [P, i64, C.POINTER(romap_box)],
         }
@@ -265,6 +266,10 @@ class Context:
     def debug_bin_capacity(self, slots: int):
         """Cap every gradient bin at `slots` records (0 = sized capacity)."""
         self._check(lib().romap_debug_bin_capacity(self.h, int(slots)))
+
+    def debug_tiles(self, rays_per_item: int, gather_block: int):
+        """Launch shape of the field and gather kernels when autotune is off."""
+        self._check(lib().romap_debug_tiles(self.h, int(rays_per_item), int(gather_block)))
 
     def marching_cubes(self, grid, res, iso, lo, hi):
         """Marching cubes on a (res+1)^3 grid (x fastest; numpy or a device

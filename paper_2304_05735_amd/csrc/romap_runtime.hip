@@ -110,6 +110,7 @@ hipError_t grow(T** p, size_t* cap, size_t need) {
 struct romap_ctx {
   romap_config cfg{};
   int debug_bin_cap = 0;  // romap_debug_bin_capacity (0: sized capacity)
+  int fixed_rpi = 8, fixed_blk = 256;  // launch shape without the autotuner (romap_debug_tiles)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipStream_t stream2 = nullptr;   // second half of a split batched step
@@ -1252,7 +1253,7 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
   if (s != ROMAP_OK) return s;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (list.empty() || n_steps == 0) return ROMAP_OK;
-  int rpi = 8, blk = 256;
+  int rpi = c->fixed_rpi, blk = c->fixed_blk;
   if (c->cfg.autotune) {
     s = autotune(c, list, &rpi, &blk);
     if (s != ROMAP_OK) return s;
@@ -1422,8 +1423,13 @@ romap_status romap_loss_and_grad(romap_ctx* c, const int32_t* ids, int32_t n, co
   romap_status s = resolve_list(c, ids, n, rays, list);
   if (s != ROMAP_OK) return s;
   if (list.empty()) return ROMAP_OK;
+  int rpi = c->fixed_rpi, blk = c->fixed_blk;  // the launch shape of a training step
+  if (c->cfg.autotune) {
+    s = autotune(c, list, &rpi, &blk);
+    if (s != ROMAP_OK) return s;
+  }
   Plan p;
-  build_plan(c, list, 8, 256, p);
+  build_plan(c, list, rpi, blk, p);
   s = stage_plans(c, {&p});
   if (s != ROMAP_OK) return s;
   for (auto& pr : list) {
@@ -1920,6 +1926,17 @@ romap_status romap_debug_rays(romap_ctx* c, int32_t id, int32_t n_rays, int32_t*
       q[15] = (R.flags & RM_F_DEPTH) ? 1.0f : 0.0f;
     }
   }
+  return ROMAP_OK;
+}
+
+romap_status romap_debug_tiles(romap_ctx* c, int32_t rays_per_item, int32_t gather_block) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  if (rays_per_item != 4 && rays_per_item != 8 && rays_per_item != 16 && rays_per_item != 32)
+    return fail(c, ROMAP_E_INVALID_ARG, "rays_per_item must be 4, 8, 16 or 32");
+  if (gather_block != 128 && gather_block != 256 && gather_block != 512)
+    return fail(c, ROMAP_E_INVALID_ARG, "gather_block must be 128, 256 or 512");
+  c->fixed_rpi = rays_per_item;
+  c->fixed_blk = gather_block;
   return ROMAP_OK;
 }
 

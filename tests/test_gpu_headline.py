@@ -1,22 +1,27 @@
 """The benchmark's workloads at their full shapes, in the launch
 configurations it times (the stream's case is described at its test).
 
-The 24-object workload: BF16 MLP, all objects batched, two streams, the captured
-step graph and the autotuned launch shape; 16 levels, tables of 2^15 ... 2^19
+The 24-object workload: all objects batched, two streams, the captured step
+graph and the autotuned launch shape; 16 levels, tables of 2^15 ... 2^19
 entries by box volume, 64 samples per ray, 640 x 480 keyframes, 256 ... 8192
 rays per object.  The scene is the benchmark's, seen from 15 of its 60
 cameras (every fourth: the same objects and tables; the ray counts follow
 those 15 masks), so that it renders in seconds in a process that already
-holds the GPU.
+holds the GPU.  With the BF16 MLP (the benchmark's default) and with the
+FP32 MLP (its batched FP32 comparison).
 
 On three sampled objects (largest, middle and smallest table):
 - ray draws, classes and every sample position of every 37th ray equal the
   oracle's bit for bit;
-- the loss and gradient of the batched BF16 step are within the BF16 bounds
-  of the FP64 oracle (2 % on the loss, 10 % norm-wise on the gradient);
+- BF16: the loss and gradient of the batched step match the oracle's BF16
+  mode (MLP operands rounded to BF16 as on the GPU, everything else FP64)
+  entry by entry, within the FP32 bounds plus what the BF16 rounding
+  decisions near a midpoint can move (per entry the oracle's bound, per
+  tensor three times the spread that FP32-sized operand perturbations make);
+- FP32: loss within 1e-5, gradient within 1e-4 per tensor and per entry;
 - after 20 graph-replayed two-stream training steps every object has
   advanced 20 steps with finite parameters, the mean loss has fallen, and the
-  trained fields still match the oracle within the same bounds.
+  trained fields match the oracle to the same bars.
 """
 import numpy as np
 import pytest
@@ -24,6 +29,8 @@ import pytest
 import oracle
 import paper_2304_05735_amd as pk
 import scenes
+from tests.gpu_common import (assert_bf16_close, assert_fwd_close, assert_grad_close,
+                              bf16_reference, oracle_grad, tensor_cuts)
 
 pytestmark = pytest.mark.gpu
 
@@ -32,21 +39,25 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _bf16_close(g, o, oid, step, B, gl, gg, what):
-    ol, og, _ = o.loss_and_grad(oid, step, B)
-    rel = float(np.linalg.norm(gg - og) / np.linalg.norm(og))
-    _say(f"  {what}: loss {gl:.6f} vs FP64 {ol:.6f} (rel {abs(gl - ol) / ol:.2e}); grad rel {rel:.2e}")
-    assert abs(gl - ol) <= 2e-2 * abs(ol), what
-    assert rel < 0.1, what
+def _check(o, i, step, B, gl, gg, what):
+    if o.bf16:
+        ref = bf16_reference(o, i, step, B, seeds=(1, 2))
+        assert_bf16_close(gl, gg, ref, what=what)
+    else:
+        ol, og, mass, allow, _ = oracle_grad(o, i, step, B)
+        assert_fwd_close([gl], [ol], what=f"{what} loss")
+        assert_grad_close(gg, og, mass, allow, what=what, cuts=tensor_cuts(o, i))
 
 
-def test_headline_workload_sampled():
-    _say("headline workload: building the scene")
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_objects24_workload_sampled(prec):
+    _say(f"24-object workload ({prec}): building the scene")
     wl = scenes.room_scene(n_obj=24, n_views=15)
-    cfg = pk.default_config(samples_per_ray=64, precision=pk.PREC_BF16, batch_mode=pk.BATCH_ALL,
-                            use_graph=1, autotune=1, streams=2)
+    bf = prec == "bf16"
+    cfg = pk.default_config(samples_per_ray=64, precision=pk.PREC_BF16 if bf else pk.PREC_FP32,
+                            batch_mode=pk.BATCH_ALL, use_graph=1, autotune=1, streams=2)
     g = pk.Context(cfg)
-    o = oracle.OracleContext(oracle.make_config(N=64))
+    o = oracle.OracleContext(oracle.make_config(N=64), bf16=bf)
     for ob in wl.objects:
         a = g.add_object(ob.instance, ob.t, ob.yaw, ob.half, ob.log2T)
         b = o.add_object(ob.instance, ob.t, ob.yaw, ob.half, ob.log2T)
@@ -79,11 +90,11 @@ def test_headline_workload_sampled():
                 _, _, opos = oracle.sample_positions(ra.o, ra.d, ob.half, ra.tn, ra.tf, 64)
                 assert np.array_equal(pos[r], opos), (i, r)
 
-    # the batched BF16 step at the initial parameters
+    # the batched step at the initial parameters, in the autotuned launch shape
     l0 = g.loss_and_grad(ids, rays)
     for i in picks:
-        _bf16_close(g, o, i, 0, rays[i], float(l0[i]), g.get_params(i, pk.GRAD),
-                    f"object {i} at initialisation")
+        _check(o, i, 0, rays[i], float(l0[i]), g.get_params(i, pk.GRAD),
+               f"object {i} at initialisation")
 
     # 20 steps through the graph, two streams
     st = g.train(20, ids, rays)
@@ -96,8 +107,8 @@ def test_headline_workload_sampled():
     assert np.isfinite(l20).all() and l20.mean() < l0.mean()
     for i in picks:
         o.objects[i].params[:] = g.get_params(i).astype(np.float64)
-        _bf16_close(g, o, i, 20, rays[i], float(l20[i]), g.get_params(i, pk.GRAD),
-                    f"object {i} after 20 steps")
+        _check(o, i, 20, rays[i], float(l20[i]), g.get_params(i, pk.GRAD),
+               f"object {i} after 20 steps")
 
 
 def test_stream_workload_sampled():
@@ -109,7 +120,7 @@ def test_stream_workload_sampled():
     sampled objects (fewest rays, median, upper quartile) the library's
     occupancy bits are handed to the oracle; the draws and positions of every
     37th ray equal the oracle's bit for bit, and the loss and gradient of the
-    next step are within the BF16 bounds of the FP64 oracle."""
+    next step match the oracle's BF16 mode entry by entry (as above)."""
     _say("stream workload: building the scene")
     wl = scenes.stream_scene(n_frames=20)
     counts = {}
@@ -126,7 +137,7 @@ def test_stream_workload_sampled():
     order = sorted(range(len(seen)), key=lambda k: (rays[k], k))
     picks = [order[0], order[len(order) // 2], order[(3 * len(order)) // 4]]
     g = pk.Context(cfg)
-    o = oracle.OracleContext(oracle.make_config(N=128))
+    o = oracle.OracleContext(oracle.make_config(N=128), bf16=True)
     ids = []
     for k, ob in enumerate(seen):
         a = g.add_object(ob.instance, ob.t, ob.yaw, ob.half, ob.log2T)
@@ -162,5 +173,5 @@ def test_stream_workload_sampled():
                 _, _, opos = oracle.sample_positions(ra.o, ra.d, ob.half, ra.tn, ra.tf, 128)
                 assert np.array_equal(pos[r], opos), (i, r)
         gl = float(g.loss_and_grad([i], [B])[0])
-        _bf16_close(g, o, i, 25, B, gl, g.get_params(i, pk.GRAD),
-                    f"object {i} ({B} rays, {occ:.3f} of cells occupied)")
+        _check(o, i, 25, B, gl, g.get_params(i, pk.GRAD),
+               f"object {i} ({B} rays, {occ:.3f} of cells occupied)")

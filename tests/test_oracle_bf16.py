@@ -136,9 +136,11 @@ def test_bf16_allowance_bounds_operand_rounding_error(case):
     o, oid = ctx[True]
     B = 256
     P = o.n_params(oid)
-    mass, amb, la = np.zeros(P), np.zeros(P), np.zeros(1)
-    l0, g0, _ = o.loss_and_grad(oid, 0, B, mass=mass, ambiguous=amb, loss_allow=la)
-    assert la[0] > 0 and amb.max() > 0
+    mass, amb, bam, la = np.zeros(P), np.zeros(P), np.zeros(P), np.zeros(1)
+    l0, g0, _ = o.loss_and_grad(oid, 0, B, mass=mass, ambiguous=amb, loss_allow=la,
+                                bf16_allow=bam)
+    assert la[0] > 0 and bam.max() > 0
+    amb = amb + bam
     try:
         for rel in (3e-7, 1e-6, 3e-6):
             oracle.set_bf16_jitter(rel)
@@ -157,5 +159,7 @@ def test_fp32_mode_has_no_bf16_allowance():
     o, oid = ctx[False]
     la = np.zeros(1)
     P = o.n_params(oid)
-    o.loss_and_grad(oid, 0, 128, mass=np.zeros(P), ambiguous=np.zeros(P), loss_allow=la)
-    assert la[0] == 0.0
+    bam = np.ones(P)
+    o.loss_and_grad(oid, 0, 128, mass=np.zeros(P), ambiguous=np.zeros(P), loss_allow=la,
+                    bf16_allow=bam)
+    assert la[0] == 0.0 and not bam.any()
