@@ -1138,9 +1138,9 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
       if (g == 0) {
         float* q = rv + (16 * b + n) * 4;
         q[0] = Y[0][0];
-        q[1] = sigmoidf_(Z[0][0]);
-        q[2] = sigmoidf_(Z[0][1]);
-        q[3] = sigmoidf_(Z[0][2]);
+        q[1] = Z[0][0];  // colour logits: the adjoint needs sigmoid(-z) as well
+        q[2] = Z[0][1];
+        q[3] = Z[0][2];
       }
     }
     wave_lds_sync();
@@ -1150,7 +1150,7 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
       const uint32_t cls = R.flags & RM_F_CLS;
       const bool bg = (mode == RM_MODE_TRAIN) && cls == RM_CLS_BACKGROUND;
       const bool valid = lane * SPL < NS;
-      float y0[SPL], c[SPL][3], sig[SPL], tau[SPL], dist[SPL], w[SPL], Sx[SPL];
+      float y0[SPL], c[SPL][3], zc[SPL][3], sig[SPL], tau[SPL], dist[SPL], w[SPL], Sx[SPL];
       float lane_tau = 0.0f, lane_sig = 0.0f;
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
@@ -1158,9 +1158,11 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
         if (valid) {
           const float* q = rv + i * 4;
           y0[j] = q[0];
-          c[j][0] = q[1];
-          c[j][1] = q[2];
-          c[j][2] = q[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            zc[j][k] = q[1 + k];
+            c[j][k] = sigmoidf_(zc[j][k]);
+          }
           bool live = true;
           if (ob.occ) {
             float p[3];
@@ -1174,6 +1176,7 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
         } else {
           y0[j] = 0.0f;
           c[j][0] = c[j][1] = c[j][2] = 0.0f;
+          zc[j][0] = zc[j][1] = zc[j][2] = 0.0f;
           sig[j] = tau[j] = dist[j] = 0.0f;
         }
         lane_tau += tau[j];
@@ -1268,7 +1271,8 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
           float* q = rv + i * 4;
           q[0] = y0[j] < 15.0f ? dsig * sig[j] : 0.0f;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) q[1 + k] = w[j] * gC[k] * c[j][k] * (1.0f - c[j][k]);
+          // sigmoid'(z) = sigmoid(z) sigmoid(-z): no cancellation where c rounds to 1
+          for (int k = 0; k < 3; ++k) q[1 + k] = w[j] * gC[k] * c[j][k] * sigmoidf_(-zc[j][k]);
         }
       }
     }

@@ -72,9 +72,17 @@ def assert_grad_close(gpu, ref, mass, allow=None, rtol=1e-4, mtol=1e-4, what="",
     extra = np.zeros_like(ref) if extra is None else np.asarray(extra, np.float64)
     d = gpu - ref
     bad = np.abs(d) > rtol * np.abs(ref) + mtol * mass + allow + extra
-    assert not bad.any(), (what, int(bad.sum()), float(np.abs(d).max()), np.flatnonzero(bad)[:5])
     if cuts is None:
         cuts = [("all", 0, ref.size)]
+    if bad.any():
+        rows = []
+        for j in np.flatnonzero(bad)[:12]:
+            name, a, _ = next(c for c in cuts if c[1] <= j < c[2])
+            rows.append(f"{name}[{j - a}] gpu {gpu[j]:.6e} ref {ref[j]:.6e} mass {mass[j]:.3e} "
+                        f"allow {allow[j]:.3e} extra {extra[j]:.3e}")
+        print(f"  {what}: {int(bad.sum())} entries beyond the bound:\n    " + "\n    ".join(rows),
+              flush=True)
+    assert not bad.any(), (what, int(bad.sum()), float(np.abs(d).max()), np.flatnonzero(bad)[:5])
     worst, rows = 0.0, []
     for name, a, b in cuts:
         nr = np.linalg.norm(ref[a:b])
