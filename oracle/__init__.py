@@ -89,7 +89,7 @@ def lib():
                                       C.c_int, C.c_int, P, P]
         _lib.or_object_frame.argtypes = [P, P, C.c_float, P, P]
         _lib.or_encode.argtypes = [C.POINTER(Levels), P, P, P, P, P]
-        _lib.or_mlp_forward.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, P]
+        _lib.or_mlp_forward.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, P, P]
         _lib.or_bf16.argtypes = [C.c_double]
         _lib.or_bf16.restype = C.c_double
         _lib.or_bf16_gap.argtypes = [C.c_double]
@@ -290,9 +290,10 @@ def mlp_forward(din, mlp, e, layers=1, bf16=False):
     h2 = np.zeros(HIDDEN)
     sigma = np.zeros(1)
     rgb = np.zeros(3)
+    rgbc = np.zeros(3)
     lib().or_mlp_forward(din, layers, 1 if bf16 else 0, _p(mlp), _p(e), _p(h1), _p(y), _p(h2),
-                         _p(sigma), _p(rgb))
-    return dict(h1=h1, y=y, h2=h2, sigma=float(sigma[0]), rgb=rgb)
+                         _p(sigma), _p(rgb), _p(rgbc))
+    return dict(h1=h1, y=y, h2=h2, sigma=float(sigma[0]), rgb=rgb, rgb_complement=rgbc)
 
 
 def composite(sigma, rgb, dist, delta, background=False, crand=(0.0, 0.0, 0.0)):

@@ -318,7 +318,7 @@ static int relu_open(int bf, double h, const double* W, const double* x, int K) 
  * bf16, every weight and every layer input is rounded by or_bf16 where a
  * contraction reads it. */
 void or_mlp_forward(int din, int layers, int bf16, const double* mlp, const double* e, double* h1,
-                    double* y, double* h2, double* sigma, double* rgb) {
+                    double* y, double* h2, double* sigma, double* rgb, double* rgbc) {
   const double* W1 = mlp;
   const double* Wh = W1 + OR_HIDDEN * din;
   const double* W2 = Wh + (layers - 1) * OR_HIDDEN * OR_HIDDEN;
@@ -355,6 +355,7 @@ void or_mlp_forward(int din, int layers, int bf16, const double* mlp, const doub
     double s = 0.0;
     for (int j = 0; j < OR_HIDDEN; ++j) s += rbw(bf16, W4[i * OR_HIDDEN + j]) * rbf(bf16, h2[j]);
     rgb[i] = 1.0 / (1.0 + exp(-s));
+    if (rgbc) rgbc[i] = 1.0 / (1.0 + exp(s)); /* 1 - rgb without cancellation */
   }
 }
 
@@ -464,7 +465,7 @@ void or_draw_ray(const or_config* cfg, int obj, int step, int r, int nkf, const 
  * record.  The loss is L = (1/B) sum_r l_r. */
 typedef struct {
   uint32_t* idx;
-  double *w, *e, *h1, *y, *h2, *sigma, *rgb, *dist, *wts, *dsig, *dsig_m, *tnext;
+  double *w, *e, *h1, *y, *h2, *sigma, *rgb, *rgbc, *dist, *wts, *dsig, *dsig_m, *tnext;
   float *pos, *dist32;
   int* live; /* sample not skipped by the occupancy bitfield */
   struct or_fpert_s* fp; /* tests only: BF16 forward bounds (bf16_ray_allowance) */
@@ -480,6 +481,7 @@ static void scratch_alloc(or_scratch* s, int N, int L, int layers) {
   s->h2 = (double*)malloc(sizeof(double) * N * OR_HIDDEN);
   s->sigma = (double*)malloc(sizeof(double) * N);
   s->rgb = (double*)malloc(sizeof(double) * N * 3);
+  s->rgbc = (double*)malloc(sizeof(double) * N * 3);
   s->dist = (double*)malloc(sizeof(double) * N);
   s->wts = (double*)malloc(sizeof(double) * N);
   s->dsig = (double*)malloc(sizeof(double) * N);
@@ -494,7 +496,7 @@ static void scratch_alloc(or_scratch* s, int N, int L, int layers) {
 
 static void scratch_free(or_scratch* s) {
   free(s->idx); free(s->w); free(s->e); free(s->h1); free(s->y); free(s->h2);
-  free(s->sigma); free(s->rgb); free(s->dist); free(s->wts); free(s->dsig); free(s->dsig_m); free(s->tnext);
+  free(s->sigma); free(s->rgb); free(s->rgbc); free(s->dist); free(s->wts); free(s->dsig); free(s->dsig_m); free(s->tnext);
   free(s->pos); free(s->dist32); free(s->live);
   free(s->fp);
 }
@@ -507,8 +509,8 @@ static void scratch_free(or_scratch* s) {
  * transposed product, and both factors of each weight-gradient product. */
 static void sample_backward(const or_levels* lv, int din, const double* mlp, const uint32_t* idx,
                             const double* w, const double* e, const double* h1, const double* y,
-                            const double* h2, double sigma, const double* rgb, double dsig,
-                            const double* dc, double* grad) {
+                            const double* h2, double sigma, const double* rgb,
+                            const double* rgbc, double dsig, const double* dc, double* grad) {
   const int nh = lv->mlp_layers, bf = lv->mlp_bf16;
   const double* W1 = mlp;
   const double* Wh = W1 + OR_HIDDEN * din;
@@ -523,7 +525,8 @@ static void sample_backward(const or_levels* lv, int din, const double* mlp, con
   double* gW4 = gW3 + OR_HIDDEN * OR_GEO;
   double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], dh[OR_HIDDEN], dp[OR_HIDDEN],
       de[2 * OR_MAX_LEVELS];
-  for (int k = 0; k < 3; ++k) dz4[k] = dc[k] * rgb[k] * (1.0 - rgb[k]);
+  /* sigmoid'(z) = sigmoid(z) sigmoid(-z): rgbc = 1 - rgb formed without cancellation */
+  for (int k = 0; k < 3; ++k) dz4[k] = dc[k] * rgb[k] * rgbc[k];
   for (int k = 0; k < 3; ++k)
     for (int j = 0; j < OR_HIDDEN; ++j) gW4[k * OR_HIDDEN + j] += rbf(bf, dz4[k]) * rbf(bf, h2[j]);
   for (int j = 0; j < OR_HIDDEN; ++j) {
@@ -595,8 +598,9 @@ static void sample_backward(const or_levels* lv, int din, const double* mlp, con
 static void sample_backward_magnitude(const or_levels* lv, int din, const double* mlp,
                                       const uint32_t* idx, const double* w, const double* e,
                                       const double* h1, const double* y, const double* h2,
-                                      double sigma, const double* rgb, double dsig_m,
-                                      const double* dc_m, int all_branches, double* mag) {
+                                      double sigma, const double* rgb, const double* rgbc,
+                                      double dsig_m, const double* dc_m, int all_branches,
+                                      double* mag) {
   const int nh = lv->mlp_layers, bf = lv->mlp_bf16;
   const double* W1 = mlp;
   const double* Wh = W1 + OR_HIDDEN * din;
@@ -612,7 +616,7 @@ static void sample_backward_magnitude(const or_levels* lv, int din, const double
 #define A(x) fabs(rbf(bf, (x)))
   double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], dh[OR_HIDDEN], dp[OR_HIDDEN],
       de[2 * OR_MAX_LEVELS];
-  for (int k = 0; k < 3; ++k) dz4[k] = dc_m[k] * rgb[k] * (1.0 - rgb[k]);
+  for (int k = 0; k < 3; ++k) dz4[k] = dc_m[k] * rgb[k] * rgbc[k];
   for (int k = 0; k < 3; ++k)
     for (int j = 0; j < OR_HIDDEN; ++j) mW4[k * OR_HIDDEN + j] += A(dz4[k]) * A(h2[j]);
   for (int j = 0; j < OR_HIDDEN; ++j) {
@@ -697,7 +701,8 @@ static void ray_forward(const or_levels* lv, int N, const double* params, const 
     s->live[i] = or_occupied(occ, s->pos + 3 * i);
     or_encode(lv, s->pos + 3 * i, params, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i);
     or_mlp_forward(din, nh, lv->mlp_bf16, mlp, s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
-                   s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma + i, s->rgb + 3 * i);
+                   s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma + i, s->rgb + 3 * i,
+                   s->rgbc + 3 * i);
     if (!s->live[i]) s->sigma[i] = 0.0;
   }
   or_composite(N, s->sigma, s->rgb, s->dist, (double)*delta, bg, crand, C, D, Tend, s->wts);
@@ -745,13 +750,13 @@ static void ray_backward(const or_levels* lv, int N, const double* params, doubl
     for (int k = 0; k < 3; ++k) dci[k] = s->wts[i] * gC[k];
     sample_backward(lv, din, mlp, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i,
                     s->h1 + OR_HIDDEN * nh * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i,
-                    s->sigma[i], s->rgb + 3 * i, s->dsig[i], dci, grad);
+                    s->sigma[i], s->rgb + 3 * i, s->rgbc + 3 * i, s->dsig[i], dci, grad);
     if (mag) {
       for (int k = 0; k < 3; ++k) dci[k] = s->wts[i] * fabs(gC[k]);
       sample_backward_magnitude(lv, din, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
                                 s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
                                 s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma[i],
-                                s->rgb + 3 * i, s->dsig_m[i], dci, 0, mag);
+                                s->rgb + 3 * i, s->rgbc + 3 * i, s->dsig_m[i], dci, 0, mag);
     }
   }
 }
@@ -931,7 +936,8 @@ static inline double pprod(double a, double Pa, double b, double Pb) {
 static void bf16_backward_pert(const or_levels* lv, const double* mlp, const uint32_t* idx,
                                const double* w, const double* e, const double* h1,
                                const double* y, const double* h2, double sigma, double dsigma,
-                               const double* rgb, const double dcol[3], double dsig, double Pdsig,
+                               const double* rgb, const double* rgbc, const double dcol[3],
+                               double dsig, double Pdsig,
                                const double dc[3], const double Pdc[3], const double sc_dz[3],
                                double sc_dy0, const or_fpert* F, double* amb) {
   const int din = 2 * lv->L, nh = lv->mlp_layers, bf = lv->mlp_bf16;
@@ -949,7 +955,7 @@ static void bf16_backward_pert(const or_levels* lv, const double* mlp, const uin
   double dz[3], Pdz[3], dh2[OR_HIDDEN], Pdh2[OR_HIDDEN], dy[OR_DOUT], Pdy[OR_DOUT],
       dh[OR_HIDDEN], Pdh[OR_HIDDEN], dp[OR_HIDDEN], Pdp[OR_HIDDEN], Pde[2 * OR_MAX_LEVELS];
   for (int k = 0; k < 3; ++k) {
-    const double g = rgb[k] * (1.0 - rgb[k]);
+    const double g = rgb[k] * rgbc[k];
     const double Pg = fabs(1.0 - 2.0 * rgb[k]) * dcol[k] + dcol[k] * dcol[k];
     dz[k] = dc[k] * g;
     Pdz[k] = bf16_pert(dz[k], pprod(dc[k], Pdc[k], g, Pg), sc_dz[k]);
@@ -1079,7 +1085,7 @@ static void bf16_ray_allowance(const or_levels* lv, int N, const double* params,
     dsg[i] = s->sigma[i] * expm1(F->Py[0]);
     for (int k = 0; k < 3; ++k) {
       const double c = s->rgb[3 * i + k];
-      dcl[i][k] = fmin(1.0, c * (1.0 - c) * expm1(F->Pz[k]));
+      dcl[i][k] = fmin(1.0, c * s->rgbc[3 * i + k] * expm1(F->Pz[k]));
     }
     sum_ds += dsg[i];
   }
@@ -1119,8 +1125,8 @@ static void bf16_ray_allowance(const or_levels* lv, int N, const double* params,
     for (int k = 0; k < 3; ++k) {
       dc[k] = s->wts[i] * gC[k];
       Pdc[k] = pprod(s->wts[i], dw[i], gC[k], dgC[k]);
-      sc_dz[k] = fabs(dc[k] * rgb[k] * (1.0 - rgb[k])) * (1.0 + Sx[i + 1]) +
-                 s->wts[i] * rgb[k] * (1.0 - rgb[k]) * eg[k];
+      sc_dz[k] = fabs(dc[k] * rgb[k] * s->rgbc[3 * i + k]) * (1.0 + Sx[i + 1]) +
+                 s->wts[i] * rgb[k] * s->rgbc[3 * i + k] * eg[k];
       const double base = Tn * fabs(rgb[k]) + suf[i][k] + bgt[k];
       Pds += fabs(dgC[k]) * base + fabs(gC[k]) * (Tn * rhoT * fabs(rgb[k]) + Tn * dcl[i][k] +
                                                    dC[k] + (bg ? *dT * crand[k] : 0.0));
@@ -1130,8 +1136,8 @@ static void bf16_ray_allowance(const or_levels* lv, int N, const double* params,
     sc_dy0 *= s->sigma[i];
     bf16_backward_pert(lv, mlp, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i,
                        s->h1 + OR_HIDDEN * nh * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i,
-                       s->sigma[i], dsg[i], rgb, dcl[i], s->dsig[i], Pds, dc, Pdc, sc_dz, sc_dy0,
-                       s->fp + i, amb);
+                       s->sigma[i], dsg[i], rgb, s->rgbc + 3 * i, dcl[i], s->dsig[i], Pds, dc, Pdc,
+                       sc_dz, sc_dy0, s->fp + i, amb);
   }
 }
 
@@ -1222,8 +1228,9 @@ static void flip_delta(const or_levels* lv, int din, const double* mlp, const ui
 static void sample_tie_deltas(const or_levels* lv, int din, const double* mlp,
                               const uint32_t* idx, const double* w, const double* e,
                               const double* h1, const double* y, const double* h2, double sigma,
-                              const double* rgb, double dsig, const double* dc,
-                              const struct or_fpert_s* F, double kTie, double* amb) {
+                              const double* rgb, const double* rgbc, double dsig,
+                              const double* dc, const struct or_fpert_s* F, double kTie,
+                              double* amb) {
   const int nh = lv->mlp_layers, bf = lv->mlp_bf16;
   const double* W1 = mlp;
   const double* Wh = W1 + OR_HIDDEN * din;
@@ -1231,7 +1238,7 @@ static void sample_tie_deltas(const or_levels* lv, int din, const double* mlp,
   const double* W3 = W2 + OR_DOUT * OR_HIDDEN;
   const double* W4 = W3 + OR_HIDDEN * OR_GEO;
   double dz4[3], dh2[OR_HIDDEN], dy[OR_DOUT], un[OR_HIDDEN], dh[OR_HIDDEN];
-  for (int k = 0; k < 3; ++k) dz4[k] = dc[k] * rgb[k] * (1.0 - rgb[k]);
+  for (int k = 0; k < 3; ++k) dz4[k] = dc[k] * rgb[k] * rgbc[k];
   /* colour head: unmasked adjoints of its hidden units, and their ties */
   for (int j = 0; j < OR_HIDDEN; ++j) {
     double t = 0.0;
@@ -1306,7 +1313,7 @@ static void sample_tie_deltas(const or_levels* lv, int din, const double* mlp,
  * pre-activation that BF16 decisions upstream can move by P ties when
  * |pre| <= 1e-5 magnitude + P). */
 static double tie_allowance(const or_levels* lv, int N, const double* params, or_scratch* s,
-                            const double gC[3], double dtie, double* amb) {
+                            const double gC[3], double dtie, double* amb, double* bam) {
   const double kTie = 1e-5;
   const int L = lv->L, nh = lv->mlp_layers;
   const double* mlp = params + or_grid_params(lv);
@@ -1325,14 +1332,25 @@ static double tie_allowance(const or_levels* lv, int N, const double* params, or
         sample_backward_magnitude(lv, 2 * L, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
                                   s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
                                   s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma[i],
-                                  s->rgb + 3 * i, s->dsig_m[i], dcm, 1, amb);
+                                  s->rgb + 3 * i, s->rgbc + 3 * i, s->dsig_m[i], dcm, 1, amb);
+    }
+    if (sm < kTie && bam && lv->mlp_bf16) {
+      /* BF16 mode: the other branch also moves the BF16 roundings of the
+       * adjoints below the tied unit, each by at most one BF16 unit (2^-8 of
+       * the value): within 2^-6 of the sample's contributions, per entry */
+      double dcm[3];
+      for (int k = 0; k < 3; ++k) dcm[k] = 0x1p-6 * s->wts[i] * fabs(gC[k]);
+      sample_backward_magnitude(lv, 2 * L, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
+                                s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i, s->y + OR_DOUT * i,
+                                s->h2 + OR_HIDDEN * i, s->sigma[i], s->rgb + 3 * i,
+                                s->rgbc + 3 * i, 0x1p-6 * s->dsig_m[i], dcm, 1, bam);
     }
     if (sm < kTie) {
       double dc[3];
       for (int k = 0; k < 3; ++k) dc[k] = s->wts[i] * gC[k];
       sample_tie_deltas(lv, 2 * L, mlp, s->idx + 8 * L * i, s->w + 8 * L * i, s->e + 2 * L * i,
                         s->h1 + OR_HIDDEN * nh * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i,
-                        s->sigma[i], s->rgb + 3 * i, s->dsig[i], dc, F, kTie, amb);
+                        s->sigma[i], s->rgb + 3 * i, s->rgbc + 3 * i, s->dsig[i], dc, F, kTie, amb);
     }
   }
   return rm;
@@ -1434,7 +1452,8 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
         double dtie = INFINITY;
         if (!bg && ray.has_depth)
           dtie = (fabs(ray.Dhat - (double)ray.D) - dD) / fmax(fabs((double)ray.D), 1e-30);
-        const double rm = tie_allowance(lv, N, params, &s, gC, dtie, my_grad ? my_amb : NULL);
+        const double rm = tie_allowance(lv, N, params, &s, gC, dtie, my_grad ? my_amb : NULL,
+                                        my_grad ? my_bam : NULL);
         ray_margin[r] = rm;
       } else {
         ray_margin[r] = INFINITY;
@@ -1520,7 +1539,7 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
                              d_depth ? d_depth[r] : 0.0, d_tend ? d_tend[r] : 0.0, 0, zero, 0.0,
                              my_bam, dC, &dD, &dT, &dS);
         }
-        if (my_amb) tie_allowance(lv, N, params, &s, gC, INFINITY, my_amb);
+        if (my_amb) tie_allowance(lv, N, params, &s, gC, INFINITY, my_amb, my_bam);
       }
     }
     scratch_free(&s);
@@ -1607,7 +1626,7 @@ void or_query_density(const or_levels* lv, const float half[3], const double* pa
     }
     or_encode(lv, p, params, idx, w, e);
     /* the density query runs the FP32 MLP in either mode */
-    or_mlp_forward(din, lv->mlp_layers, 0, mlp, e, h1, y, h2, sigma + i, rgb);
+    or_mlp_forward(din, lv->mlp_layers, 0, mlp, e, h1, y, h2, sigma + i, rgb, NULL);
   }
 }
 

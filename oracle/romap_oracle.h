@@ -75,7 +75,7 @@ void or_bf16_set_jitter(double rel); /* tests only */
 void or_set_tie_jitter(double rel);  /* tests only */
 void or_set_jitter_seed(uint64_t seed); /* tests only */
 void or_mlp_forward(int din, int layers, int bf16, const double* mlp, const double* e, double* h1,
-                    double* y, double* h2, double* sigma, double* rgb);
+                    double* y, double* h2, double* sigma, double* rgb, double* rgbc);
 void or_composite(int N, const double* sigma, const double* rgb, const double* dist, double delta,
                   int background, const double crand[3], double C[3], double* D, double* Tend,
                   double* w);

@@ -745,3 +745,31 @@ def test_tie_allowance_covers_other_branches(case):
         oracle.set_tie_jitter(0.0)
         oracle.set_jitter_seed(0)
     assert beyond > 0
+
+
+def test_colour_sigmoid_complement_has_no_cancellation():
+    """The colour head's sigmoid and its complement 1 - c (the derivative is
+    c (1 - c)): the two sum to 1, and for large logits the complement is
+    e^-z (1 - e^-z + ...) to full relative precision, where 1 - c itself
+    would have cancelled (c rounds to 1 in FP64 above z = 37)."""
+    din = 4
+    for z in (0.3, 5.0, 20.0, 36.0, 40.0, 60.0, -40.0):
+        # W1 = 0 except one unit; W2 passes it to y1; W3 passes y1 to h2_0; W4 sums h2_0
+        mlp = np.zeros(oracle.mlp_params(din, 1))
+        W1 = mlp[:64 * din].reshape(64, din)
+        W2 = mlp[64 * din:64 * din + 1024].reshape(16, 64)
+        W3 = mlp[64 * din + 1024:64 * din + 1984].reshape(64, 15)
+        W4 = mlp[64 * din + 1984:].reshape(3, 64)
+        W1[0, 0] = 1.0
+        W2[1, 0] = 1.0
+        W3[0, 0] = 1.0
+        W4[:, 0] = [z, -z, 0.0]
+        e = np.zeros(din)
+        e[0] = 1.0
+        out = oracle.mlp_forward(din, mlp, e)
+        c, cc = out["rgb"], out["rgb_complement"]
+        assert np.allclose(c + cc, 1.0, rtol=0, atol=4.5e-16)
+        for k, zk in enumerate((z, -z, 0.0)):
+            assert math.isclose(cc[k], 1.0 / (1.0 + math.exp(zk)), rel_tol=1e-14)
+            if zk > 30:
+                assert math.isclose(cc[k], math.exp(-zk) / (1.0 + math.exp(-zk)), rel_tol=1e-14)
