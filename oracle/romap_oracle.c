@@ -713,13 +713,16 @@ static void ray_forward(const or_levels* lv, int N, const double* params, const 
  * Adjoint of Eq. 6: dC/dtau_i = T_{i+1} c_i - sum_{j>i} w_j c_j, and every
  * tau_i enters T_end = exp(-sum tau) (background rays composite T_end C_rand).
  * Adds dl/dparams into grad and, if mag is not NULL, the magnitude of the same
- * backward into mag. */
+ * backward into mag, with gCm (may be NULL: |gC|) the magnitude of the terms
+ * that form gC (a colour residual's is that of the colour and its target). */
 static void ray_backward(const or_levels* lv, int N, const double* params, double delta,
                          or_scratch* s, int bg, const double crand[3], double Tend,
-                         const double gC[3], double gD, double gT, double dens, double* grad,
-                         double* mag) {
+                         const double gC[3], const double* gCm, double gD, double gT, double dens,
+                         double* grad, double* mag) {
   const int L = lv->L, din = 2 * L, nh = lv->mlp_layers;
   const double* mlp = params + or_grid_params(lv);
+  double gA[3];
+  for (int k = 0; k < 3; ++k) gA[k] = gCm ? gCm[k] : fabs(gC[k]);
   double suf_c[3] = {0.0, 0.0, 0.0}, suf_d = 0.0;
   double S_i = 0.0;
   for (int i = 0; i < N; ++i) {
@@ -736,9 +739,9 @@ static void ray_backward(const or_levels* lv, int N, const double* params, doubl
     a -= gT * Tend;
     s->dsig[i] = s->live[i] ? a * delta + dens : 0.0;
     /* magnitude of the same adjoint (for the tolerance of the tests) */
-    for (int k = 0; k < 3; ++k) am += fabs(gC[k]) * (Tnext[i] * s->rgb[3 * i + k] + suf_c[k]);
+    for (int k = 0; k < 3; ++k) am += gA[k] * (Tnext[i] * s->rgb[3 * i + k] + suf_c[k]);
     if (bg)
-      for (int k = 0; k < 3; ++k) am += fabs(gC[k]) * Tend * crand[k];
+      for (int k = 0; k < 3; ++k) am += gA[k] * Tend * crand[k];
     am += fabs(gD) * (Tnext[i] * s->dist[i] + suf_d) + fabs(gT) * Tend;
     s->dsig_m[i] = s->live[i] ? am * delta + dens : 0.0;
     for (int k = 0; k < 3; ++k) suf_c[k] += s->wts[i] * s->rgb[3 * i + k];
@@ -752,7 +755,7 @@ static void ray_backward(const or_levels* lv, int N, const double* params, doubl
                     s->h1 + OR_HIDDEN * nh * i, s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i,
                     s->sigma[i], s->rgb + 3 * i, s->rgbc + 3 * i, s->dsig[i], dci, grad);
     if (mag) {
-      for (int k = 0; k < 3; ++k) dci[k] = s->wts[i] * fabs(gC[k]);
+      for (int k = 0; k < 3; ++k) dci[k] = s->wts[i] * gA[k];
       sample_backward_magnitude(lv, din, mlp, s->idx + 8 * L * i, s->w + 8 * L * i,
                                 s->e + 2 * L * i, s->h1 + OR_HIDDEN * nh * i,
                                 s->y + OR_DOUT * i, s->h2 + OR_HIDDEN * i, s->sigma[i],
@@ -1428,15 +1431,21 @@ int or_object_step(const or_config* cfg, const or_levels* lv, int obj, int insta
           l += cfg->lambda_density * ssum;
         }
         ray.loss = l / (double)B;
-        double gC[3], gD = 0.0;
-        for (int k = 0; k < 3; ++k) gC[k] = 2.0 * (ray.Chat[k] - target[k]) / (double)B;
+        double gC[3], gCm[3], gD = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          gC[k] = 2.0 * (ray.Chat[k] - target[k]) / (double)B;
+          /* the residual's terms: the colour (its samples' and, on a background
+           * ray, T_end C_rand) and the target; where they cancel, rounding of
+           * the colour moves gC and with it every term of the ray */
+          gCm[k] = 2.0 * (fabs(ray.Chat[k]) + fabs(target[k])) / (double)B;
+        }
         if (!bg && ray.has_depth) {
           double diff = ray.Dhat - (double)ray.D;
           gD = cfg->lambda_depth * (diff > 0.0 ? 1.0 : (diff < 0.0 ? -1.0 : 0.0)) / (double)B;
         }
         if (my_grad)
-          ray_backward(lv, N, params, (double)ray.delta, &s, bg, crand, ray.Tend, gC, gD, 0.0,
-                       bg ? cfg->lambda_density / (double)B : 0.0, my_grad, my_abs);
+          ray_backward(lv, N, params, (double)ray.delta, &s, bg, crand, ray.Tend, gC, gCm, gD,
+                       0.0, bg ? cfg->lambda_density / (double)B : 0.0, my_grad, my_abs);
         /* tests only: what the BF16 decisions and the ties can move */
         double dC[3] = {0.0, 0.0, 0.0}, dD = 0.0, dT = 0.0, dS = 0.0;
         if (lv->mlp_bf16 && (loss_allow || my_amb || my_bam))
@@ -1528,7 +1537,7 @@ int or_field(const or_config* cfg, const or_levels* lv, const float half[3], con
       if (grad && hit) {
         const double gC[3] = {d_rgb ? d_rgb[3 * r] : 0.0, d_rgb ? d_rgb[3 * r + 1] : 0.0,
                               d_rgb ? d_rgb[3 * r + 2] : 0.0};
-        ray_backward(lv, N, params, (double)delta, &s, 0, zero, Tend, gC,
+        ray_backward(lv, N, params, (double)delta, &s, 0, zero, Tend, gC, NULL,
                      d_depth ? d_depth[r] : 0.0, d_tend ? d_tend[r] : 0.0, 0.0,
                      tgrad + (int64_t)tid * P, tabs ? tabs + (int64_t)tid * P : NULL);
         double* my_amb = tamb ? tamb + (int64_t)tid * P : NULL;
