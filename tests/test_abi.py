@@ -65,9 +65,12 @@ def test_default_config_and_create_validation_without_gpu():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libromap.so not built")
 def test_library_mc_table_equals_oracle_table():
-    """Two independent derivations of the marching-cubes case table (host code
-    of the library, C of the oracle) from the same face rules agree case by
-    case, triangle by triangle."""
+    """The library's marching-cubes case table (host code) equals the
+    oracle's case by case, triangle by triangle.  Both are built from the same
+    face rules, so this checks the library's transcription of them (the
+    bit-for-bit triangle comparison needs the same table); what pins the
+    table itself are the oracle's geometric tests (area, volume, Euler
+    characteristic, watertight surfaces)."""
     import oracle
     import paper_2304_05735_amd as pk
     for m in range(256):
