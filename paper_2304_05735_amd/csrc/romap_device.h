@@ -184,7 +184,8 @@ struct StepArgs {
   int32_t n_fins;
   RayRec* rays;
   int32_t n_rays;
-  float2* e;            // [L][S] encodings
+  float2* e;            // [L][S] encodings (e_bf16: [L][S] uint32, a BF16 pair each)
+  int e_bf16;           // encodings stored rounded to BF16 (the BF16 MLP reads nothing else)
   float2* de;           // [L][S] their adjoints
   int64_t S;            // samples = n_rays * N
   float* partials;      // n_items * RM_REC_STRIDE_NH(mlp_layers)

@@ -27,6 +27,8 @@
 // contraction (this file is built with -ffp-contract=off; FMAs are written
 // out where wanted), so positions and indices are reproducible bit for bit.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <math.h>
 #include <stdint.h>
 
@@ -60,7 +62,18 @@ __device__ inline void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint
   out[3] = c3;
 }
 
-// FP32 -> BF16, round to nearest even.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx2_t __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16 with round to nearest, ties to even (gfx950 v_cvt_pk_bf16_f32)
+__device__ inline uint32_t pack_bf16x2(float x, float y) {
+  const floatx2_t v = {x, y};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
+// FP32 -> BF16, round to nearest even (integer form, for the weight images)
 __device__ inline uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);
@@ -383,7 +396,10 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
     float p[3];
     sample_pos(R, (int)(s % NS), ob.half, p);
     if (!occupied(ob.occ, p)) {  // skipped sample: no gather, zero encoding
-      a.e[(int64_t)l * a.S + s] = make_float2(0.0f, 0.0f);
+      if (a.e_bf16)
+        ((uint32_t*)a.e)[(int64_t)l * a.S + s] = 0u;
+      else
+        a.e[(int64_t)l * a.S + s] = make_float2(0.0f, 0.0f);
       continue;
     }
     Cell cl;
@@ -417,7 +433,10 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
       ex = fmaf(w[b], g[b].x, ex);
       ey = fmaf(w[b], g[b].y, ey);
     }
-    a.e[(int64_t)l * a.S + s] = make_float2(ex, ey);
+    if (a.e_bf16)  // the BF16 MLP reads the encoding rounded to BF16, nothing else
+      ((uint32_t*)a.e)[(int64_t)l * a.S + s] = pack_bf16x2(ex, ey);
+    else
+      a.e[(int64_t)l * a.S + s] = make_float2(ex, ey);
   }
 }
 
@@ -563,10 +582,17 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
     const int lane = tid & 63;
     const uint32_t key = has ? (idx[0] | (((uint32_t)((bp.s_begin + k) / NS) & 1u) << 31))
                              : 0xFFFFFFFFu - (uint32_t)lane;
+    // runs are maximal groups of consecutive lanes with one key, named by
+    // their first lane: a sample without records (skipped by the occupancy
+    // test, or a zero adjoint) ends a run even where the cell goes on, so
+    // lanes are merged only within one run
+    const uint32_t kp = __shfl_up(key, 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || kp != key);
+    const int start = 63 - __clzll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)));
 #pragma unroll
     for (int o = 1; o < 4; o <<= 1) {
-      const uint32_t kn = __shfl_down(key, o, 64);
-      const bool same = lane + o < 64 && kn == key;
+      const int sn = __shfl_down(start, o, 64);
+      const bool same = lane + o < 64 && sn == start;
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
         const float yx = __shfl_down(v[b].x, o, 64), yy = __shfl_down(v[b].y, o, 64);
@@ -576,9 +602,6 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
         }
       }
     }
-    const uint32_t kp = __shfl_up(key, 1, 64);
-    const uint64_t heads = __ballot(lane == 0 || kp != key);
-    const int start = 63 - __clzll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)));
     has = has && ((lane - start) & 3) == 0;
   }
   if (has) {
@@ -818,7 +841,10 @@ __global__ __launch_bounds__(RM_FIN_WG) void k_bin_finish(StepArgs a) {
 // A(M x K) X(K x 16), operand element (t, q, r, lane) is
 // A[16t + lane%16][16q + 4(lane/16) + r]; the FP32 image orders it
 // ((t Q + q) 4 + r) 64 + lane (one 16x16x4 operand per 64 contiguous values),
-// the BF16 image ((t Q + q) 64 + lane) 4 + r (one 16x16x16 operand per lane).
+// the BF16 image ((t Q + q) 64 + lane) 4 + r (one 16x16x16 operand per lane)
+// when K = 16, and for K a multiple of 32 ((t C + c) 64 + lane) 8 + q8 with
+// A[16t + lane%16][32c + (q8 < 4 ? 4g + q8 : 16 + 4g + q8 - 4)], g = lane/16
+// (one 16x16x32 operand per lane, in the slot order of Mma<1>).
 // Operands 8 + 2(k-1) and 9 + 2(k-1) are the k-th hidden-to-hidden matrix of
 // a deeper density MLP (nh hidden layers) and its transpose.
 __device__ inline float mlp_A(const float* W, int din, int nh, int gemm, int m, int k) {
@@ -874,7 +900,12 @@ __global__ __launch_bounds__(256) void k_pack(StepArgs a, int K1) {
         const int q = tq % Q, t = tq / Q;
         o32[off + j] = mlp_A(W, din, nh, gm, 16 * t + (lane & 15), 16 * q + 4 * (lane >> 4) + r);
       }
-      {  // BF16 image
+      if (K % 32 == 0) {  // BF16 image of a 16x16x32 operand (slot order of Mma<1>)
+        const int q8 = j & 7, lane = (j >> 3) & 63, tc = j >> 9, C = K / 32;
+        const int c = tc % C, t = tc / C, g = lane >> 4;
+        const int col = 32 * c + (q8 < 4 ? 4 * g + q8 : 16 + 4 * g + (q8 - 4));
+        o16[off + j] = f2bf(mlp_A(W, din, nh, gm, 16 * t + (lane & 15), col));
+      } else {  // BF16 image of a 16x16x16 operand
         const int r = j & 3, lane = (j >> 2) & 63, tq = j >> 8;
         const int q = tq % Q, t = tq / Q;
         o16[off + j] =
@@ -941,42 +972,75 @@ struct Mma<0> {
   }
 };
 
-__device__ inline shortx4 pack_bf16x4(floatx4 v) {
-  shortx4 s;
-  s[0] = (short)f2bf(v[0]);
-  s[1] = (short)f2bf(v[1]);
-  s[2] = (short)f2bf(v[2]);
-  s[3] = (short)f2bf(v[3]);
-  return s;
-}
+__device__ inline bf16x4_t cvt_bf16x4(floatx4 v) { return __builtin_convertvector(v, bf16x4_t); }
 
+// PREC 1 operands.  A contraction over K >= 32 runs as 16x16x32 MFMAs whose K
+// slots are ordered so that two consecutive [feature][sample] result
+// fragments (features 32c..32c+15 and 32c+16..32c+31) are, concatenated per
+// lane, its B operand: lane (g, n) feeds slots 8g..8g+7 = features
+// 32c + 4g + 0..3 and 32c + 16 + 4g + 0..3 of sample n; the weight image
+// holds A in the same slot order (k_pack).  K = 16 runs as 16x16x16.
 template <>
 struct Mma<1> {
   typedef uint16_t wtype;
   static constexpr int STRIDE = 20;  // staging row stride (bf16), keeps 8-byte alignment
+  // Out(M x 16 samples) = A(M x K) X(K x 16), X given as BF16 fragments
+  template <int M, int K>
+  __device__ static inline void gemm_b(const uint16_t* wA, const bf16x4_t* xb, floatx4* Out,
+                                       int lane) {
+    if constexpr (K % 32 == 0) {
+      constexpr int C = K / 32;
+      bf16x8_t x8[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        x8[c] = __builtin_shufflevector(xb[2 * c], xb[2 * c + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+#pragma unroll
+      for (int t = 0; t < M / 16; ++t) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const bf16x8_t av = *(const bf16x8_t*)(wA + ((t * C + c) * 64 + lane) * 8);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, x8[c], acc, 0, 0, 0);
+        }
+        Out[t] = acc;
+      }
+    } else {
+      constexpr int Q = K / 16;
+#pragma unroll
+      for (int t = 0; t < M / 16; ++t) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const shortx4 av = *(const shortx4*)(wA + ((t * Q + q) * 64 + lane) * 4);
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+              av, __builtin_bit_cast(shortx4, xb[q]), acc, 0, 0, 0);
+        }
+        Out[t] = acc;
+      }
+    }
+  }
   template <int M, int K>
   __device__ static inline void gemm(const uint16_t* wA, const floatx4* X, floatx4* Out,
                                      int lane) {
-    constexpr int Q = K / 16;
-    shortx4 xb[Q];
+    bf16x4_t xb[K / 16];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) xb[q] = pack_bf16x4(X[q]);
+    for (int q = 0; q < K / 16; ++q) xb[q] = cvt_bf16x4(X[q]);
+    gemm_b<M, K>(wA, xb, Out, lane);
+  }
+  __device__ static inline void stage_b(uint16_t* buf, const bf16x4_t* F, int nf, int lane) {
+    const int g = lane >> 4, n = lane & 15;
+    for (int f = 0; f < nf; ++f) {
+      const shortx4 v = __builtin_bit_cast(shortx4, F[f]);
 #pragma unroll
-    for (int t = 0; t < M / 16; ++t) {
-      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const shortx4 av = *(const shortx4*)(wA + ((t * Q + q) * 64 + lane) * 4);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, xb[q], acc, 0, 0, 0);
-      }
-      Out[t] = acc;
+      for (int r = 0; r < 4; ++r) buf[(16 * f + 4 * g + r) * STRIDE + n] = (uint16_t)v[r];
     }
   }
   __device__ static inline void stage(uint16_t* buf, const floatx4* F, int nf, int lane) {
     const int g = lane >> 4, n = lane & 15;
     for (int f = 0; f < nf; ++f) {
+      const shortx4 v = __builtin_bit_cast(shortx4, cvt_bf16x4(F[f]));
 #pragma unroll
-      for (int r = 0; r < 4; ++r) buf[(16 * f + 4 * g + r) * STRIDE + n] = f2bf(F[f][r]);
+      for (int r = 0; r < 4; ++r) buf[(16 * f + 4 * g + r) * STRIDE + n] = (uint16_t)v[r];
     }
   }
   template <int MG, int MX>
@@ -995,6 +1059,30 @@ struct Mma<1> {
     }
   }
 };
+
+// ReLU of FP32 pre-activations, rounded to BF16: rounding to nearest
+// commutes with max(x, 0), and a BF16 value read as int16 is negative exactly
+// when its sign bit is set, so one packed 16-bit integer max does two units.
+__device__ inline bf16x4_t relu_b(floatx4 x) {
+  const shortx4 v = __builtin_bit_cast(shortx4, cvt_bf16x4(x));
+  const shortx4 z = {0, 0, 0, 0};
+  return __builtin_bit_cast(bf16x4_t, __builtin_elementwise_max(v, z));
+}
+
+// An FP32 adjoint rounded to BF16 and kept where the unit's ReLU output h
+// (BF16, >= 0) is positive: min(h, 1) * 0xFFFF as 16-bit lanes is the mask.
+// (op_sel_hi:[1,0]: the high lane also reads the constant's low half, which
+// is where an inline constant of a packed instruction sits.)
+__device__ inline bf16x4_t mask_b(floatx4 d, bf16x4_t h) {
+  const uint2 hb = __builtin_bit_cast(uint2, h);
+  uint32_t m0, m1;
+  asm("v_pk_min_u16 %0, %1, 1 op_sel_hi:[1,0]" : "=v"(m0) : "v"(hb.x));
+  asm("v_pk_min_u16 %0, %1, 1 op_sel_hi:[1,0]" : "=v"(m1) : "v"(hb.y));
+  asm("v_pk_mul_lo_u16 %0, %1, -1 op_sel_hi:[1,0]" : "=v"(m0) : "v"(m0));
+  asm("v_pk_mul_lo_u16 %0, %1, -1 op_sel_hi:[1,0]" : "=v"(m1) : "v"(m1));
+  const uint2 db = __builtin_bit_cast(uint2, cvt_bf16x4(d));
+  return __builtin_bit_cast(bf16x4_t, make_uint2(db.x & m0, db.y & m1));
+}
 
 __device__ inline void relu4(floatx4* F, int n) {
   for (int f = 0; f < n; ++f) {
@@ -1022,12 +1110,28 @@ __device__ inline void load_e(const float2* e, int64_t S, int64_t s, int L, int 
   }
 }
 
+// The same fragments from the BF16 pairs of an e_bf16 buffer (bits as stored).
+template <int K1>
+__device__ inline void load_e_b(const uint32_t* e, int64_t S, int64_t s, int L, int g,
+                                bf16x4_t* E) {
+#pragma unroll
+  for (int q = 0; q < K1 / 16; ++q) {
+    const int l0 = 8 * q + 2 * g, l1 = l0 + 1;
+    const uint32_t v0 = l0 < L ? e[(int64_t)l0 * S + s] : 0u;
+    const uint32_t v1 = l1 < L ? e[(int64_t)l1 * S + s] : 0u;
+    E[q] = __builtin_bit_cast(bf16x4_t, (uint64_t)v0 | ((uint64_t)v1 << 32));
+  }
+}
+
 // NH: hidden layers of the density MLP (1, or 2 and 3 for the model-size
 // study); the deeper variants run one wave per SIMD (their 64 x 64 weight
 // gradients are accumulated in registers), and their work-item record shares
 // LDS with the weights, which are no longer read when it is written.
 template <int PREC, int NS, int K1, int NH>
-__global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 1 : 2))) void k_field(StepArgs a) {
+#ifndef RM_FIELD_BF16_WAVES
+#define RM_FIELD_BF16_WAVES 2
+#endif
+__global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 1 : (PREC == 1 ? RM_FIELD_BF16_WAVES : 2)))) void k_field(StepArgs a) {
   typedef Mma<PREC> MM;
   typedef typename MM::wtype wt;
   constexpr int NB = NS / 16;             // 16-sample blocks per ray
@@ -1037,12 +1141,16 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
   // a ray's encodings stay in registers from the forward to the backward
   // pass when they fit (NS <= 64, one hidden layer), else the backward reads
   // them again
-  constexpr bool KEEP_E = NH == 1 && NB * KQ <= 8;
+  constexpr bool KEEP_E = NH == 1 && NB * KQ <= 8 && (PREC == 0 || RM_FIELD_BF16_WAVES < 3);
   constexpr int NBK = KEEP_E ? NB : 1;
   constexpr int WP = RM_WPACK_NH(NH);
   constexpr int RL = RM_REC_LOSS_NH(NH);
   constexpr int WBYTES = WP * (int)sizeof(wt), RBYTES = (RL + 1) * 4;
-  constexpr bool ALIAS = NH > 1;
+  // the work-item record shares LDS with the weights, which are no longer
+  // read when it is written (fewer bytes per workgroup, more workgroups per CU)
+  constexpr bool ALIAS = NH > 1 || PREC == 1;
+  // BF16 with one hidden layer: activations kept as rounded BF16 pairs
+  constexpr bool PACKED = PREC == 1 && NH == 1;
 
   __shared__ __align__(16) char s_wraw[ALIAS && RBYTES > WBYTES ? RBYTES : WBYTES];
   __shared__ __align__(16) wt s_stage[4][2][STG];
@@ -1081,6 +1189,21 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
   wt* gbuf = s_stage[wave][0];
   wt* xbuf = s_stage[wave][1];
   float* rv = s_rv[wave];
+  // encodings: FP32 fragments, or with the BF16 MLP the stored BF16 pairs as
+  // they are (the MLP reads nothing else of them)
+  typedef typename std::conditional<PREC == 1, bf16x4_t, floatx4>::type etype;
+  auto load_enc = [&](int64_t s, etype* E) {
+    if constexpr (PREC == 1)
+      load_e_b<K1>((const uint32_t*)a.e, S, s, L, g, E);
+    else
+      load_e<K1>(a.e, S, s, L, g, E);
+  };
+  auto gemm_e = [&](const etype* E, floatx4* H) {
+    if constexpr (PREC == 1)
+      MM::template gemm_b<64, K1>(wF1, E, H, lane);
+    else
+      MM::template gemm<64, K1>(wF1, E, H, lane);
+  };
 
   floatx4 acc1[4 * KQ], acc2[4], acc3[4], acc4[4];
   floatx4 accH[NH > 1 ? NH - 1 : 1][16];  // hidden-to-hidden weight gradients
@@ -1112,29 +1235,43 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
     const int64_t sray = (int64_t)ray * NS;
 
     // ---- forward: sigma, colour of every sample ----
-    floatx4 EK[NBK][KQ];
+    etype EK[NBK][KQ];
 #pragma unroll(KEEP_E ? NB : 1)
     for (int b = 0; b < NB; ++b) {
-      floatx4 E[KQ], H1[4], Y[1], H2[4], Z[1];
-      load_e<K1>(a.e, S, sray + 16 * b + n, L, g, E);
+      etype E[KQ];
+      floatx4 H1[4], Y[1], H2[4], Z[1];
+      load_enc(sray + 16 * b + n, E);
       if (KEEP_E) {
 #pragma unroll
         for (int q = 0; q < KQ; ++q) EK[KEEP_E ? b : 0][q] = E[q];
       }
-      MM::template gemm<64, K1>(wF1, E, H1, lane);
-      relu4(H1, 4);
+      if constexpr (PACKED) {  // activations as rounded BF16 pairs
+        bf16x4_t H1b[4], Yb[1], H2b[4];
+        gemm_e(E, H1);
 #pragma unroll
-      for (int k = 1; k < NH; ++k) {  // deeper density MLP: H1 <- ReLU(Wh_k H1)
-        floatx4 Hn[4];
-        MM::template gemm<64, 64>(s_w + RM_OFF_HF(k), H1, Hn, lane);
-        relu4(Hn, 4);
+        for (int f = 0; f < 4; ++f) H1b[f] = relu_b(H1[f]);
+        MM::template gemm_b<16, 64>(wF2, H1b, Y, lane);
+        Yb[0] = cvt_bf16x4(Y[0]);
+        MM::template gemm_b<64, 16>(wF3, Yb, H2, lane);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) H1[f] = Hn[f];
+        for (int f = 0; f < 4; ++f) H2b[f] = relu_b(H2[f]);
+        MM::template gemm_b<16, 64>(wF4, H2b, Z, lane);
+      } else {
+        gemm_e(E, H1);
+        relu4(H1, 4);
+#pragma unroll
+        for (int k = 1; k < NH; ++k) {  // deeper density MLP: H1 <- ReLU(Wh_k H1)
+          floatx4 Hn[4];
+          MM::template gemm<64, 64>(s_w + RM_OFF_HF(k), H1, Hn, lane);
+          relu4(Hn, 4);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) H1[f] = Hn[f];
+        }
+        MM::template gemm<16, 64>(wF2, H1, Y, lane);
+        MM::template gemm<64, 16>(wF3, Y, H2, lane);
+        relu4(H2, 4);
+        MM::template gemm<16, 64>(wF4, H2, Z, lane);
       }
-      MM::template gemm<16, 64>(wF2, H1, Y, lane);
-      MM::template gemm<64, 16>(wF3, Y, H2, lane);
-      relu4(H2, 4);
-      MM::template gemm<16, 64>(wF4, H2, Z, lane);
       if (g == 0) {
         float* q = rv + (16 * b + n) * 4;
         q[0] = Y[0][0];
@@ -1282,15 +1419,81 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
 #pragma unroll(KEEP_E ? NB : 1)
     for (int b = 0; b < NB; ++b) {
       const int64_t s = sray + 16 * b + n;
-      floatx4 E[KQ], HH[NH][4], Y[1], H2[4];
+      etype E[KQ];
+      floatx4 HH[NH][4], Y[1], H2[4];
       floatx4* H1 = HH[NH - 1];  // the last hidden layer of the density MLP
       if (KEEP_E) {
 #pragma unroll
         for (int q = 0; q < KQ; ++q) E[q] = EK[KEEP_E ? b : 0][q];
       } else {
-        load_e<K1>(a.e, S, s, L, g, E);
+        load_enc(s, E);
       }
-      MM::template gemm<64, K1>(wF1, E, HH[0], lane);
+      if constexpr (PACKED) {
+        // recompute the rounded activations; adjoints rounded once, used by
+        // both their MFMA and their staging for the weight gradients
+        bf16x4_t H1b[4], Yb[1], H2b[4], dZb[1], dH2b[4], dYb[1], dH1b[4];
+        floatx4 P[4], Yf[1], dYf[1], dEf[KQ];
+        gemm_e(E, P);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) H1b[f] = relu_b(P[f]);
+        MM::template gemm_b<16, 64>(wF2, H1b, Yf, lane);
+        Yb[0] = cvt_bf16x4(Yf[0]);
+        MM::template gemm_b<64, 16>(wF3, Yb, P, lane);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) H2b[f] = relu_b(P[f]);
+        float dy0 = 0.0f;
+        {
+          floatx4 dz = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (g == 0) {
+            const float* q = rv + (16 * b + n) * 4;
+            dy0 = q[0];
+            dz = floatx4{q[1], q[2], q[3], 0.0f};
+          }
+          dZb[0] = cvt_bf16x4(dz);
+        }
+        // colour head: dW4 += dZ^T H2, dH2 = W4^T dZ masked by ReLU
+        MM::stage_b(gbuf, dZb, 1, lane);
+        MM::stage_b(xbuf, H2b, 4, lane);
+        wave_lds_sync();
+        MM::template dw<16, 64>(gbuf, xbuf, acc4, lane);
+        wave_lds_sync();
+        MM::template gemm_b<64, 16>(wB4, dZb, P, lane);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) dH2b[f] = mask_b(P[f], H2b[f]);
+        // dW3 += dH2^T Y, dY = W3^T dH2 (+ density adjoint in row 0)
+        MM::stage_b(gbuf, dH2b, 4, lane);
+        MM::stage_b(xbuf, Yb, 1, lane);
+        wave_lds_sync();
+        MM::template dw<64, 16>(gbuf, xbuf, acc3, lane);
+        wave_lds_sync();
+        MM::template gemm_b<16, 64>(wB3, dH2b, dYf, lane);
+        if (g == 0) dYf[0][0] += dy0;
+        dYb[0] = cvt_bf16x4(dYf[0]);
+        // dW2 += dY^T H1, dH1 = W2^T dY masked
+        MM::stage_b(gbuf, dYb, 1, lane);
+        MM::stage_b(xbuf, H1b, 4, lane);
+        wave_lds_sync();
+        MM::template dw<16, 64>(gbuf, xbuf, acc2, lane);
+        wave_lds_sync();
+        MM::template gemm_b<64, 16>(wB2, dYb, P, lane);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) dH1b[f] = mask_b(P[f], H1b[f]);
+        // dW1 += dH1^T E, dE = W1^T dH1
+        MM::stage_b(gbuf, dH1b, 4, lane);
+        MM::stage_b(xbuf, E, KQ, lane);
+        wave_lds_sync();
+        MM::template dw<64, K1>(gbuf, xbuf, acc1, lane);
+        wave_lds_sync();
+        MM::template gemm_b<K1, 64>(wB1, dH1b, dEf, lane);
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+          const int l0 = 8 * q + 2 * g, l1 = l0 + 1;
+          if (l0 < L) a.de[(int64_t)l0 * S + s] = make_float2(dEf[q][0], dEf[q][1]);
+          if (l1 < L) a.de[(int64_t)l1 * S + s] = make_float2(dEf[q][2], dEf[q][3]);
+        }
+        continue;
+      }
+      gemm_e(E, HH[0]);
       relu4(HH[0], 4);
 #pragma unroll
       for (int k = 1; k < NH; ++k) {
@@ -1357,7 +1560,10 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
       }
       // dW1 += dH^T E, dE = W1^T dH  (dH of the first hidden layer)
       MM::stage(gbuf, dH1, 4, lane);
-      MM::stage(xbuf, E, KQ, lane);
+      if constexpr (PREC == 1)
+        MM::stage_b(xbuf, E, KQ, lane);
+      else
+        MM::stage(xbuf, E, KQ, lane);
       wave_lds_sync();
       MM::template dw<64, K1>(gbuf, xbuf, acc1, lane);
       wave_lds_sync();

@@ -309,6 +309,7 @@ StepArgs base_args(romap_ctx* c) {
   a.eps = c->cfg.eps;
   a.mode = RM_MODE_TRAIN;
   a.mlp_layers = c->cfg.mlp_layers;
+  a.e_bf16 = c->cfg.precision == ROMAP_PREC_BF16 ? 1 : 0;
   return a;
 }
 

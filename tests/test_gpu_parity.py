@@ -546,6 +546,35 @@ def test_occupancy_skip_parity(tiny):
         g.get_occupancy(gid)
 
 
+@pytest.mark.parametrize("N", [64, 128])
+def test_occupancy_gaps_on_merged_dense_levels(tiny, N):
+    """Regression: on coarse dense levels the binning sums the records of
+    consecutive samples of a ray that share a cell.  A sample skipped by the
+    occupancy test in the middle of such a cell ended the run, but the sums
+    reached across it, so samples after the gap were counted twice (first
+    seen on the 128-object stream).  Here a checkerboard of occupancy cells
+    (every other 64^3 cell off) puts gaps inside nearly every coarse cell of
+    16 levels x 2^19 (six dense levels): loss and gradient match the
+    oracle."""
+    _say("occupancy gaps on merged levels", N)
+    frames, box = tiny
+    B = 256
+    g, o, gid = make_pair(16, 16, 1024, 19, N, B, frames, box)
+    _set_same_params(g, o, gid, seed=8, grid_scale=1.0)
+    c = np.arange(64)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    on = ((x + y + z) % 2 == 0).reshape(-1)
+    bits = np.packbits(on, bitorder="little")
+    g.set_occupancy(gid, bits)
+    o.set_occupancy(gid, bits)
+    gl = g.loss_and_grad([gid])[0]
+    gg = g.get_params(gid, pk.GRAD)
+    ol, og, mass, allow, _ = oracle_grad(o, gid, 0, B)
+    assert_fwd_close([gl], [ol], what="loss with occupancy gaps")
+    assert_grad_close(gg, og, mass, allow, what="grad with occupancy gaps",
+                      cuts=tensor_cuts(o, gid))
+
+
 # ------------------------------------------------------------------ gradient bins that overflow
 @pytest.mark.parametrize("B", [48, 512])
 def test_bin_overflow_path_matches_oracle(tiny, B):
