@@ -340,6 +340,25 @@ romap_status romap_field_backward(romap_ctx* ctx, int32_t object_id, const float
                                   const float* d_depth_dev, const float* d_tend_dev,
                                   float* d_params_dev);
 
+/* For callers that cannot allocate device memory (code being captured into
+ * a graph, tight serving loops, harnesses that forbid allocation): the same
+ * result as romap_field_forward (same kernels and launch shape, bit for bit)
+ * with no allocation of any kind on the device.  Its rays, encodings, packed
+ * weights and work tables live in one 64 MiB array of the library on each
+ * GPU, held until the process ends; a call needs 64 B per ray, 8 L B per
+ * sample (L levels, samples_per_ray samples per ray) and small tables, at
+ * most 64 MiB: about 8100 rays at 16 levels and 64 samples, 4000 at 128.
+ * Larger calls return ROMAP_E_INVALID_ARG with the size in the message.
+ * Calls on one GPU share that array: calls that overlap in time on one GPU
+ * (several contexts, several host threads, several streams) race and give
+ * wrong results.  Returns after the kernels are queued and the work tables
+ * copied (it waits for the context stream).  Arguments as for
+ * romap_field_forward. */
+romap_status romap_field_forward_noalloc(romap_ctx* ctx, int32_t object_id,
+                                         const float* params_dev, const float* rays_dev,
+                                         int32_t n_rays, float* rgb_dev, float* depth_dev,
+                                         float* tend_dev);
+
 /* Kernels of one training step, in launch order. */
 #define ROMAP_PHASE_RAYGEN 0      /* ray draw, classification, box clipping (Sec. V-B) */
 #define ROMAP_PHASE_ENCODE 1      /* hash-grid gather */

@@ -78,6 +78,7 @@ EXPORTS = ["romap_default_config", "romap_create", "romap_destroy", "romap_last_
            "romap_add_keyframe", "romap_train", "romap_loss_and_grad", "romap_render",
            "romap_query_density", "romap_get_params", "romap_set_params", "romap_save",
            "romap_load", "romap_debug_rays", "romap_debug_encode", "romap_field_forward",
+           "romap_field_forward_noalloc",
            "romap_field_backward", "romap_get_phase_times", "romap_sync", "romap_set_occupancy",
            "romap_update_occupancy", "romap_get_occupancy", "romap_marching_cubes",
            "romap_extract_mesh", "romap_mc_case", "romap_box_from_points",
@@ -114,6 +115,7 @@ def lib():
             "romap_debug_rays": [P, i32, i32, P, P, P, P],
             "romap_debug_encode": [P, i32, P, i64, P, P],
             "romap_field_forward": [P, i32, P, P, i32, P, P, P],
+            "romap_field_forward_noalloc": [P, i32, P, P, i32, P, P, P],
             "romap_field_backward": [P, i32, P, P, i32, P, P, P, P],
             "romap_get_phase_times": [P, P, C.POINTER(i32)],
             "romap_sync": [P],
@@ -366,6 +368,19 @@ class Context:
         self._check(lib().romap_field_forward(self.h, int(oid), _ptr(params), _ptr(rays), n,
                                               _ptr(rgb), _ptr(depth), _ptr(tend)))
         return rgb, depth, tend
+
+    def field_forward_noalloc(self, oid, rays, rgb, depth, tend, params=None):
+        """romap_field_forward into caller-given device tensors, with no
+        device allocation (the library's fixed scratch array)."""
+        n = rays.shape[0]
+        for t, shape in ((rays, (n, 8)), (rgb, (n, 3)), (depth, (n,)), (tend, (n,))):
+            if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32
+                    or tuple(t.shape) != shape or not t.is_contiguous()):
+                raise ValueError(f"field_forward_noalloc: expected a contiguous float32 device "
+                                 f"tensor of shape {shape}")
+        self._check(lib().romap_field_forward_noalloc(self.h, int(oid), _ptr(params), _ptr(rays),
+                                                      rays.shape[0], _ptr(rgb), _ptr(depth),
+                                                      _ptr(tend)))
 
     def field_backward(self, oid, rays, d_rgb, d_depth, d_tend, params=None):
         n = rays.shape[0]

@@ -12,11 +12,19 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/romap.h"
 #include "romap_device.h"
+
+// Scratch of the allocation-free entry point (romap_field_forward_noalloc):
+// rays, encodings, packed weights and work tables of one call.  One copy per
+// GPU, held until the process ends.  In host code `scratch` only names the
+// symbol: its device address comes from hipGetSymbolAddress (scratch_address).
+#define RM_SCRATCH_BYTES (size_t(64) << 20)
+static __device__ __align__(256) char scratch[RM_SCRATCH_BYTES];
 
 namespace {
 
@@ -111,6 +119,7 @@ struct romap_ctx {
   romap_config cfg{};
   int debug_bin_cap = 0;  // romap_debug_bin_capacity (0: sized capacity)
   int fixed_rpi = 8, fixed_blk = 256;  // launch shape without the autotuner (romap_debug_tiles)
+  char* scratch_dev = nullptr;  // this device's `scratch` (set at creation)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipStream_t stream2 = nullptr;   // second half of a split batched step
@@ -718,6 +727,27 @@ romap_status autotune(romap_ctx* c, const std::vector<std::pair<int, int>>& list
   return ROMAP_OK;
 }
 
+// Device address of the current device's `scratch`, looked up once per
+// device (each GPU holds its own copy of the array at its own address).
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_at;
+
+hipError_t scratch_address(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_at.find(dev);
+  if (it == g_scratch_at.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = g_scratch_at.emplace(dev, static_cast<char*>(p)).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
 romap_status check_object(romap_ctx* c, int32_t id) {
   if (id < 0 || id >= (int32_t)c->objs.size())
     return fail(c, ROMAP_E_NOT_FOUND, "unknown object id " + std::to_string(id));
@@ -862,6 +892,12 @@ romap_status romap_create(const romap_config* cfg, void* hip_stream, romap_ctx**
       return fail(nullptr, ROMAP_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     }
     c->own_stream = true;
+  }
+  const hipError_t se = scratch_address(&c->scratch_dev);
+  if (se != hipSuccess) {
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return fail(nullptr, ROMAP_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(se));
   }
   *out = c;
   return ROMAP_OK;
@@ -2003,6 +2039,89 @@ romap_status romap_field_forward(romap_ctx* c, int32_t id, const float* params_d
   a.out_depth = depth_dev;
   a.out_tend = tend_dev;
   HIPCHK(c, rm_launch_field(a, c->cfg.samples_per_ray, K1_of(c->cfg), c->cfg.precision, c->stream));
+  return ROMAP_OK;
+}
+
+romap_status romap_field_forward_noalloc(romap_ctx* c, int32_t id, const float* params_dev,
+                                         const float* rays_dev, int32_t n_rays, float* rgb_dev,
+                                         float* depth_dev, float* tend_dev) {
+  if (!c) return ROMAP_E_INVALID_ARG;
+  romap_status s = check_object(c, id);
+  if (s != ROMAP_OK) return s;
+  if (!rays_dev || !ray_count_ok(n_rays, c->cfg.samples_per_ray))
+    return fail(c, ROMAP_E_INVALID_ARG, "bad rays");
+  if (!c->scratch_dev) return fail(c, ROMAP_E_STATE, "no scratch on this device");
+  // the work lists of romap_field_forward (same launch shape, same kernels)
+  Plan p;
+  build_plan(c, {{id, n_rays}}, 8, 256, p);
+  const int NS = c->cfg.samples_per_ray, K1 = K1_of(c->cfg);
+  const size_t L = (size_t)c->cfg.n_levels, WP = RM_WPACK_NH(c->cfg.mlp_layers);
+  // carve the scratch: tables | bin counters | rays | encodings | packed weights
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t here = at;
+    at += align256(bytes);
+    return here;
+  };
+  const size_t o_sobj = take(p.sobj.size() * sizeof(StepObj));
+  const size_t o_items = take(p.items.size() * sizeof(Item));
+  const size_t o_bpairs = take(p.bpairs.size() * sizeof(BinPair));
+  const size_t o_bblocks = take(p.bblocks.size() * sizeof(BinBlock));
+  const size_t tab = at;
+  const size_t o_count = take((size_t)p.bin_regions * sizeof(int));
+  const size_t o_rays = take((size_t)p.n_rays * sizeof(RayRec));
+  const size_t o_e = take(L * (size_t)p.S * sizeof(float2));
+  const size_t o_w32 = take(WP * sizeof(float));
+  const size_t o_w16 = take(WP * sizeof(uint16_t));
+  if (at > RM_SCRATCH_BYTES)
+    return fail(c, ROMAP_E_INVALID_ARG,
+                "noalloc forward needs " + std::to_string(at) + " bytes of scratch, more than its " +
+                    std::to_string(RM_SCRATCH_BYTES) + " (fewer rays per call)");
+  char* base = c->scratch_dev;
+  std::vector<char> h(tab);
+  std::memcpy(h.data() + o_sobj, p.sobj.data(), p.sobj.size() * sizeof(StepObj));
+  std::memcpy(h.data() + o_items, p.items.data(), p.items.size() * sizeof(Item));
+  if (!p.bpairs.empty()) std::memcpy(h.data() + o_bpairs, p.bpairs.data(), p.bpairs.size() * sizeof(BinPair));
+  if (!p.bblocks.empty())
+    std::memcpy(h.data() + o_bblocks, p.bblocks.data(), p.bblocks.size() * sizeof(BinBlock));
+  HIPCHK(c, hipMemcpyAsync(base, h.data(), tab, hipMemcpyHostToDevice, c->stream));
+  StepArgs a = base_args(c);
+  a.sobj = (const StepObj*)(base + o_sobj);
+  a.n_sobj = (int)p.sobj.size();
+  a.items = (const Item*)(base + o_items);
+  a.n_items = (int)p.items.size();
+  a.fins = nullptr;
+  a.n_fins = 0;
+  a.n_rays = p.n_rays;
+  a.S = p.S;
+  a.bpairs = (const BinPair*)(base + o_bpairs);
+  a.n_bpairs = (int)p.bpairs.size();
+  a.bblocks = (const BinBlock*)(base + o_bblocks);
+  a.n_bblocks = (int)p.bblocks.size();
+  a.bins = nullptr;
+  a.n_bins = 0;
+  a.bin_count = (int*)(base + o_count);  // cleared by the gather kernel
+  a.n_regions = (int)p.bin_regions;
+  a.bin_max_R = 0;
+  a.rays = (RayRec*)(base + o_rays);
+  a.e = (float2*)(base + o_e);
+  a.wpack32 = (float*)(base + o_w32);
+  a.wpack16 = (uint16_t*)(base + o_w16);
+  a.de = nullptr;  // the forward writes no adjoints, records or partial sums
+  a.partials = nullptr;
+  a.rec_idx = nullptr;
+  a.rec_val = nullptr;
+  a.params_override = params_dev;
+  a.mode = RM_MODE_FORWARD;
+  a.out_rgb = rgb_dev;
+  a.out_depth = depth_dev;
+  a.out_tend = tend_dev;
+  HIPCHK(c, rm_launch_user_rays(a, NS, rays_dev, c->stream));
+  HIPCHK(c, rm_launch_encode_fwd(a, NS, 256, c->stream));
+  HIPCHK(c, rm_launch_pack(a, K1, c->stream));
+  HIPCHK(c, rm_launch_field(a, NS, K1, c->cfg.precision, c->stream));
+  // the host copy of the tables must outlive the transfer
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return ROMAP_OK;
 }
 
