@@ -82,36 +82,53 @@ __device__ inline uint16_t f2bf(float f) {
 
 // Orders this wave's LDS traffic: every lane's earlier LDS accesses are
 // complete before any lane's later ones (cross-lane exchange inside a wave).
-__device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Orders a wave's LDS writes before its later LDS reads of other lanes' data
+// (and reads before later writes): the LDS executes one wave's operations in
+// issue order, so only the compiler must keep them in program order; the
+// hardware waits where a read's result is used.
+__device__ inline void wave_lds_sync() { asm volatile("" ::: "memory"); }
 
-__device__ inline float wave_sum(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+// Wave-wide scans in registers with DPP (no LDS round trips): row shifts
+// build the scan inside each 16-lane row, row broadcasts carry the row
+// totals across.  Lanes a shift reads from outside the row (or the wave)
+// read 0.
+template <int CTRL, int ROWM = 0xf, int BANKM = 0xf, bool BC = true>
+__device__ inline float dppf(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWM, BANKM, BC));
+}
+
+__device__ inline float readlane_f(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// inclusive prefix sum over the 64 lanes
+__device__ inline float wave_incl_prefix(float x) {
+  x += dppf<0x111>(x);                   // row_shr:1
+  x += dppf<0x112>(x);                   // row_shr:2
+  x += dppf<0x114>(x);                   // row_shr:4
+  x += dppf<0x118>(x);                   // row_shr:8
+  x += dppf<0x142, 0xa, 0xf, false>(x);  // row_bcast:15 into rows 1 and 3
+  x += dppf<0x143, 0xc, 0xf, false>(x);  // row_bcast:31 into rows 2 and 3
   return x;
 }
 
+__device__ inline float wave_sum(float x) { return readlane_f(wave_incl_prefix(x), 63); }
+
 // exclusive suffix sum over the 64 lanes (sum over lanes > lane)
 __device__ inline float wave_excl_suffix(float x, int lane) {
-  float inc = x;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    float y = __shfl_down(inc, o, 64);
-    if (lane + o < 64) inc += y;
-  }
-  float nxt = __shfl_down(inc, 1, 64);
-  return lane < 63 ? nxt : 0.0f;
+  x += dppf<0x101>(x);  // row_shl:1
+  x += dppf<0x102>(x);  // row_shl:2
+  x += dppf<0x104>(x);  // row_shl:4
+  x += dppf<0x108>(x);  // row_shl:8: inclusive suffix inside the row
+  const float t1 = readlane_f(x, 16), t2 = readlane_f(x, 32), t3 = readlane_f(x, 48);
+  const int row = lane >> 4;
+  x += row == 0 ? (t1 + t2) + t3 : (row == 1 ? t2 + t3 : (row == 2 ? t3 : 0.0f));
+  return dppf<0x130>(x);  // wave_shl:1: the next lane's inclusive suffix
 }
 
 // exclusive prefix without the subtraction: shift the inclusive scan by one lane
 __device__ inline float wave_excl_prefix(float x, int lane) {
-  float inc = x;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    float y = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += y;
-  }
-  float prv = __shfl_up(inc, 1, 64);
-  return lane > 0 ? prv : 0.0f;
+  return dppf<0x138>(wave_incl_prefix(x));  // wave_shr:1
 }
 
 // Position of sample i of a ray in the unit cube of the object's box:
