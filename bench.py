@@ -10,15 +10,15 @@ bounded sample of the same workload.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload objects24|objects24-fp32|torus1|stream128]
 
 The default workload is the 24-object batched BF16 one (the metric's).  HBM
-traffic per launch comes from rocprofv3 counter runs of this script, turned
-into a committed summary by
+traffic per launch comes from rocprofv3 counter runs of this script (one per
+pass of PMC_PASSES, with --copy-probe so that a plain copy calibrates the
+request sizes and a random gather checks them), turned into a committed
+summary by
 
     python bench.py --pmc-summary <rocprofv3 output dir> --workload <name>
 
-(`<dir>/fetch` holds a FETCH_SIZE run, `<dir>/write` a WRITE_SIZE run, both
-with --copy-probe so that a plain 512 MiB copy calibrates the counters).  The
-summary records a hash of the kernel source: once the kernels change, the
-traffic is reported as null until the counters are taken again.
+The summary records a hash of the kernel source: once the kernels change,
+the traffic is reported as null until the counters are taken again.
 
 Inputs are seeded synthetic scenes (the paper's datasets are not available).
 Only one GPU is used; --gpus above 1 exits with a message.
@@ -59,13 +59,19 @@ def build_workload(name, frames=300):
 
 def run_stream(wl, args):
     """Incremental mapping stream: keyframes arrive one by one (25 Hz in the
-    scene's timeline); an object is registered on the first frame where its
-    mask has >= 200 pixels; objects seen in the last 50 frames are active;
-    each frame trains every active object for 4 steps of 2^16 rays in total
-    (2^18 rays per frame), split in proportion to the mask pixels seen so far
-    (at least 64 each), with
-    the BF16 MLP and 128 samples per ray; the occupancy bitfield of an object
-    is refreshed every 25 frames once it has trained for 25 frames."""
+    scene's timeline); every 10th frame (f % 10 == 5) is held out for
+    evaluation and never trained on; an object is registered on the first
+    training frame where its mask has >= 200 pixels; objects seen in the last
+    50 frames are active; each frame trains every active object for 4 steps
+    of 2^16 rays in total (2^18 rays per frame), split in proportion to the
+    mask pixels seen so far (at least 64 each), with the BF16 MLP and 128
+    samples per ray; the occupancy bitfield of an object is refreshed every
+    25 frames once it has trained for 25 frames (unless --no-occupancy).
+
+    Quality over time: each object is evaluated on a fixed set of up to 4
+    held-out frames of the whole stream that show at least 500 of its pixels
+    (PSNR over its mask pixels), every --eval-every frames, for the objects
+    registered by then; the per-object curves and their mean are reported."""
     import numpy as np
     import paper_2304_05735_amd as pk
     import scenes
@@ -73,19 +79,43 @@ def run_stream(wl, args):
                             use_graph=1, autotune=0, streams=STREAMS)
     ctx = pk.Context(cfg)
     spec = {o.instance: o for o in wl.objects}
+    held = [f for f in range(len(wl.frames)) if f % 10 == 5]
+    evalset = {}
+    for f in held:
+        ids, counts = np.unique(wl.frames[f][2], return_counts=True)
+        for i, c in zip(ids, counts):
+            if int(i) in spec and c >= 500:
+                evalset.setdefault(int(i), []).append(f)
+    for i in evalset:  # up to 4, spread over the stream
+        fs = evalset[i]
+        evalset[i] = [fs[j] for j in sorted({round(k * (len(fs) - 1) / 3) for k in range(4)})]
     oid_of, first, last_seen, pix, has_kf = {}, {}, {}, {}, {}
     budget, steps_per_frame = 1 << 16, 4
-    frame_ms, train_ms, kf_ms, psnr_log = [], [], [], []
+    frame_ms, train_ms, kf_ms, curve = [], [], [], []
     rays_trained = 0
-    for f, (cam, rgb, mask, depth) in enumerate(wl.frames):
-        ids, counts = np.unique(mask, return_counts=True)
-        if f % 50 == 49 and oid_of:  # PSNR on this frame before it is used (novel view)
-            vis = sorted(((c, int(i)) for i, c in zip(ids, counts) if int(i) in oid_of), reverse=True)[:6]
+
+    def evaluate(f):
+        per = {}
+        for inst, oid in oid_of.items():
             vals = []
-            for c, inst in vis:
-                pred, _, _ = ctx.render(oid_of[inst], cam)
+            for v in evalset.get(inst, []):
+                cam, rgb, mask, _ = wl.frames[v]
+                pred, _, _ = ctx.render(oid, cam)
                 vals.append(scenes.psnr(pred, rgb / 255.0, mask == inst))
-            psnr_log.append((f, round(float(np.mean(vals)), 3) if vals else None, len(vals)))
+            if vals:
+                per[inst] = round(float(np.mean(vals)), 3)
+        return per
+
+    for f, (cam, rgb, mask, depth) in enumerate(wl.frames):
+        if f % args.eval_every == args.eval_every - 1 and oid_of:
+            per = evaluate(f)
+            curve.append({"frame": f, "objects": len(per),
+                          "mean_psnr": round(float(np.mean(list(per.values()))), 3) if per else None,
+                          "per_object": per})
+            log(f"frame {f}: mean PSNR {curve[-1]['mean_psnr']} over {len(per)} objects")
+        if f % 10 == 5:
+            continue  # held out
+        ids, counts = np.unique(mask, return_counts=True)
         ctx.sync()
         t0 = time.perf_counter()
         for inst, cnt in zip(ids, counts):
@@ -111,25 +141,42 @@ def run_stream(wl, args):
             t1 = time.perf_counter()
             ctx.train(steps_per_frame, [oid_of[i] for i in active], r, stats=False)
             rays_trained += int(r.sum()) * steps_per_frame
-            for i in active:
-                if f - first[i] >= 25 and (f - first[i]) % 25 == 0:
-                    ctx.update_occupancy(oid_of[i], 0.05)
+            if not args.no_occupancy:
+                for i in active:
+                    if f - first[i] >= 25 and (f - first[i]) % 25 == 0:
+                        ctx.update_occupancy(oid_of[i], 0.05)
             ctx.sync()
             train_ms.append((time.perf_counter() - t1) * 1e3)
         frame_ms.append((time.perf_counter() - t0) * 1e3)
         if f % 25 == 0:
             log(f"frame {f}: {len(oid_of)} objects, {len(active)} active, "
                 f"{frame_ms[-1]:.2f} ms")
+    per = evaluate(len(wl.frames))
+    curve.append({"frame": len(wl.frames), "objects": len(per),
+                  "mean_psnr": round(float(np.mean(list(per.values()))), 3) if per else None,
+                  "per_object": per})
+    # objects evaluated at every checkpoint since their first: how many end
+    # higher than they started, and the mean over a fixed set (those
+    # registered by the first checkpoint)
+    base = curve[0]["per_object"]
+    fixed = [{"frame": c["frame"], "mean_psnr": round(float(np.mean([c["per_object"][i] for i in base
+                                                                     if i in c["per_object"]])), 3)}
+             for c in curve if base]
+    rises = sum(1 for i in per if i in base and per[i] > base[i])
     fm = np.array(frame_ms)
     tm = np.array(train_ms)
-    return dict(frames=len(frame_ms), objects_registered=len(oid_of),
+    return dict(frames=len(wl.frames), frames_trained=len(frame_ms),
+                objects_registered=len(oid_of), occupancy=not args.no_occupancy,
                 ms_per_frame_mean=round(float(fm.mean()), 3),
                 ms_per_frame_p50=round(float(np.percentile(fm, 50)), 3),
                 ms_per_frame_p95=round(float(np.percentile(fm, 95)), 3),
                 frames_over_40ms=int((fm > 40.0).sum()),
                 keyframe_ms_mean=round(float(np.mean(kf_ms)), 3),
                 train_rays_per_s=round(rays_trained / (tm.sum() * 1e-3), 1) if tm.size else None,
-                psnr_over_time=psnr_log)
+                psnr_mean_over_time=[(c["frame"], c["objects"], c["mean_psnr"]) for c in curve],
+                psnr_fixed_objects_over_time=fixed,
+                fixed_objects=len(base), fixed_objects_improved=rises,
+                psnr_per_object_over_time=curve)
 
 
 STREAMS = 2  # --streams: 1 for profiler runs (one launch per kernel and phase)
@@ -197,24 +244,40 @@ def psnr_curve(ctx, wl, ids, rays, steps, chunk):
     return curve
 
 
-def equal_psnr(wl, ids, rays, prec, steps, chunk, ms_batched, ms_plain):
+def equal_psnr(wl, ids, rays, prec, steps, chunk, ms_batched, ms_plain, seeds=(0,)):
     """Batched path vs the plain FP32 path from the same initialisation, PSNR
-    on the held-out views (never keyframes) every `chunk` steps.  When the
-    final PSNRs differ by at most 0.1 dB the two are equal and the speedup is
-    the ratio of their rates at equal step counts; otherwise it is the ratio
-    of the times to reach the plain path's final PSNR (each path's first
-    evaluated step count at or above it, times its measured time per step),
-    null when the batched path does not reach it within the steps."""
+    on the held-out views (never keyframes) every `chunk` steps, averaged over
+    `seeds` (each seed changes the initialisation and the ray draws of both
+    paths alike).  When the final PSNRs differ by at most 0.1 dB the two are
+    equal and the speedup is the ratio of their rates at equal step counts;
+    otherwise it is the ratio of the times to reach the plain path's final
+    PSNR (each path's first evaluated step count at or above it, times its
+    measured time per step), null when the batched path does not reach it
+    within the steps.  The batched path with the FP32 MLP is run beside them
+    (same launches as the batched path), which separates what the BF16 MLP
+    changes from what batching changes."""
+    import numpy as np
     import paper_2304_05735_amd as pk
-    qa, _, _ = make_ctx(wl, prec, pk.BATCH_ALL, 1)
-    ca = psnr_curve(qa, wl, ids, rays, steps, chunk)
-    del qa
-    qb, _, _ = make_ctx(wl, pk.PREC_FP32, pk.BATCH_PER_OBJECT, 0)
-    cb = psnr_curve(qb, wl, ids, rays, steps, chunk)
-    del qb
+    curves = {"batched": [], "plain_fp32": [], "batched_fp32": []}
+    for sd in seeds:
+        runs = [("batched", prec, pk.BATCH_ALL, 1), ("plain_fp32", pk.PREC_FP32, pk.BATCH_PER_OBJECT, 0)]
+        if prec != pk.PREC_FP32:
+            runs.append(("batched_fp32", pk.PREC_FP32, pk.BATCH_ALL, 1))
+        for name, pr, mode, graph in runs:
+            q, _, _ = make_ctx(wl, pr, mode, graph, seed=sd)
+            curves[name].append(psnr_curve(q, wl, ids, rays, steps, chunk))
+            del q
+    mean = {k: [(c[0][j][0], float(np.mean([cc[j][1] for cc in c]))) for j in range(len(c[0]))]
+            for k, c in curves.items() if c}
+    ca, cb = mean["batched"], mean["plain_fp32"]
     pa, pb = ca[-1][1], cb[-1][1]
-    out = dict(steps=steps, eval_views=list(wl.eval_views), psnr_batched=round(pa, 3),
-               psnr_plain_fp32=round(pb, 3), delta_psnr=round(pa - pb, 3))
+    out = dict(steps=steps, seeds=list(seeds), eval_views=list(wl.eval_views),
+               psnr_batched=round(pa, 3), psnr_plain_fp32=round(pb, 3),
+               delta_psnr=round(pa - pb, 3))
+    if "batched_fp32" in mean:
+        out["psnr_batched_fp32"] = round(mean["batched_fp32"][-1][1], 3)
+    if len(seeds) > 1:
+        out["final_psnr_per_seed"] = {k: [round(c[-1][1], 3) for c in v] for k, v in curves.items() if v}
     if abs(pa - pb) <= 0.1:
         out.update(rule="equal PSNR (|delta| <= 0.1 dB): ratio of rates at equal steps",
                    speedup_at_equal_psnr=round(ms_plain / ms_batched, 3))
@@ -225,8 +288,8 @@ def equal_psnr(wl, ids, rays, prec, steps, chunk, ms_batched, ms_plain):
                    steps_batched_to_target=sa, steps_plain_to_target=sb,
                    speedup_at_equal_psnr=None if sa is None else
                    round((sb * ms_plain) / (sa * ms_batched), 3))
-    out.update(curve_batched=[(k, round(v, 3)) for k, v in ca],
-               curve_plain_fp32=[(k, round(v, 3)) for k, v in cb])
+    for k, c in mean.items():
+        out[f"curve_{k}"] = [(st, round(v, 3)) for st, v in c]
     return out
 
 
@@ -359,42 +422,116 @@ def _kernel_key(name):
     return n.strip()
 
 
+# Counter passes of a profiled run (rocprofv3 --pmc, one pass per run: a pass
+# holds at most 4 TCC, 8 SQ and 2 GRBM counters).
+PMC_PASSES = {
+    "rd": "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum TCC_EA0_RDREQ_DRAM_sum",
+    "wr": "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_WRREQ_DRAM_sum",
+    "l2": "TCC_HIT_sum TCC_MISS_sum",
+    "sq": "SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_INSTS_VALU "
+          "SQ_INSTS_LDS SQ_INSTS_MFMA SQ_WAVES SQ_WAIT_INST_ANY GRBM_GUI_ACTIVE",
+}
+COPY_MIB = 512          # --copy-probe: a plain copy of this size
+GATHER_TABLE_MIB = 1024  # and a gather of random 4-byte words from a table this large
+GATHER_N = 1 << 24
+
+
+def _probe_kind(name):
+    n = name.lower()
+    if "copy" in n:
+        return "copy"
+    if "index" in n or "gather" in n:
+        return "gather"
+    return None
+
+
 def pmc_summary(d, workload, steps):
-    """Writes the per-launch HBM traffic of each kernel from a FETCH_SIZE and a
-    WRITE_SIZE rocprofv3 run (KiB per dispatch), each counter scaled by what it
-    reads for the 512 MiB copies of --copy-probe."""
+    """Per-kernel counter summary from the rocprofv3 --pmc runs in <d>/<pass>
+    (PMC_PASSES) of bench.py --only-headline --copy-probe.  HBM bytes come
+    from read and write requests split by size: the copy probe (COPY_MIB read
+    and written) fixes the size of the requests that the counters do not
+    class (the 32-byte and the 128-byte ones are counted apart), the random
+    gather probe checks that attribution where requests are small, and no
+    kernel's bytes may imply more than the copy's rate.  Also the L2 hit rate
+    and, per kernel, MFMA-busy cycles over busy cycles and instruction counts."""
     import csv
-    import statistics
-    per = {}
-    factor = {}
-    for cname, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
-        rows = list(csv.DictReader(open(os.path.join(d, sub, "run_counter_collection.csv"))))
-        copies = [float(r["Counter_Value"]) for r in rows
-                  if r["Counter_Name"] == cname and "copyBuffer" in r["Kernel_Name"]
-                  and float(r["Counter_Value"]) > 100000]
-        if not copies:
-            raise SystemExit(f"no 512 MiB copy dispatch in {sub}: run with --copy-probe")
-        factor[cname] = 524288.0 / statistics.median(copies)
-        for r in rows:
-            if r["Counter_Name"] != cname or not r["Kernel_Name"].lstrip("void ").startswith("k_"):
+    vals = {}  # (kernel, counter) -> [per-dispatch values]
+    dur = {}   # kernel -> [ns]
+    for sub in PMC_PASSES:
+        path = os.path.join(d, sub, "run_counter_collection.csv")
+        if not os.path.exists(path):
+            raise SystemExit(f"missing {path}")
+        seen = {}
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            key = _kernel_key(name) if name.lstrip("void ").startswith("k_") else _probe_kind(name)
+            if key is None:
                 continue
-            k = _kernel_key(r["Kernel_Name"])
-            per.setdefault(k, {}).setdefault(cname, []).append(float(r["Counter_Value"]))
-    out = [f"# HBM traffic per dispatch, workload {workload}",
-           f"# rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir>/fetch (write) -o run -f csv "
-           f"-- python3 bench.py --steps {steps} --warmup 5 --only-headline --copy-probe "
+            v = float(r["Counter_Value"])
+            vals.setdefault((key, r["Counter_Name"]), []).append(v)
+        ktrace = os.path.join(d, sub, "run_kernel_trace.csv")
+        if os.path.exists(ktrace):
+            for r in csv.DictReader(open(ktrace)):
+                name = r["Kernel_Name"]
+                key = _kernel_key(name) if name.lstrip("void ").startswith("k_") else None
+                if key:
+                    dur.setdefault(key, []).append(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+
+    def mean(key, c):
+        x = vals.get((key, c))
+        if not x:
+            return 0.0
+        if key in ("copy", "gather"):  # the probe itself: the largest such dispatch
+            return max(x)
+        return sum(x) / len(x)
+
+    def split(key):
+        rd, r32, r128 = mean(key, "TCC_EA0_RDREQ_sum"), mean(key, "TCC_EA0_RDREQ_32B_sum"), \
+            mean(key, "TCC_BUBBLE_sum")
+        wr, w64 = mean(key, "TCC_EA0_WRREQ_sum"), mean(key, "TCC_EA0_WRREQ_64B_sum")
+        return rd - r32 - r128, r32, r128, wr - w64, w64
+
+    # the copy fixes the size of the unclassed read requests and of the
+    # write requests that are not 64-byte ones
+    rmid, r32, r128, wsmall, w64 = split("copy")
+    copy_bytes = COPY_MIB * 2 ** 20
+    rsize = (copy_bytes - 32 * r32 - 128 * r128) / max(rmid, 1.0)
+    wsize = (copy_bytes - 64 * w64) / max(wsmall, 1.0)
+
+    def hbm(key):
+        m, a32, a128, ws, w64_ = split(key)
+        return (32 * a32 + rsize * m + 128 * a128), (wsize * ws + 64 * w64_)
+
+    out = [f"# HBM traffic and counters per dispatch, workload {workload}",
+           "# passes (one rocprofv3 run each; <pass> in " + ", ".join(PMC_PASSES) + "):",
+           f"#   rocprofv3 --pmc <counters of the pass> --kernel-trace -d <dir>/<pass> -o run -f csv "
+           f"-- python3 bench.py --steps {steps} --warmup 3 --only-headline --copy-probe "
            f"--streams 1 --workload {workload}",
            f"# then: python bench.py --pmc-summary <dir> --workload {workload}",
-           f"# calibration (512 MiB copy): FETCH_SIZE x {factor['FETCH_SIZE']:.4f}, "
-           f"WRITE_SIZE x {factor['WRITE_SIZE']:.4f}",
-           f"kernel_source_sha256_16 {kernel_src_hash()}",
-           "# kernel dispatches fetch_KiB_raw write_KiB_raw hbm_bytes_calibrated"]
-    for k in sorted(per):
-        f = per[k].get("FETCH_SIZE", [0.0])
-        w = per[k].get("WRITE_SIZE", [0.0])
-        fm, wm = sum(f) / len(f), sum(w) / len(w)
-        byt = (fm * factor["FETCH_SIZE"] + wm * factor["WRITE_SIZE"]) * 1024.0
-        out.append(f"{k} {len(f)} {fm:.1f} {wm:.1f} {byt:.0f}")
+           f"# calibration: the {COPY_MIB} MiB copy's unclassed read requests move {rsize:.1f} B "
+           f"each, its non-64-byte write requests {wsize:.1f} B"]
+    gr, gw = hbm("gather")
+    want = GATHER_N * 4
+    out.append(f"# random-gather probe ({GATHER_N} words from {GATHER_TABLE_MIB} MiB): "
+               f"{gr / 1e6:.1f} MB read for {want / 1e6:.1f} MB of words "
+               f"({gr / want:.1f} B per useful byte: whole lines), {gw / 1e6:.1f} MB written")
+    out.append(f"kernel_source_sha256_16 {kernel_src_hash()}")
+    out.append("# kernel dispatches read_bytes write_bytes hbm_bytes avg_us implied_GB/s "
+               "l2_hit_rate mfma_busy valu_insts lds_insts mfma_insts")
+    keys = sorted(k for k in {k for k, _ in vals} if k not in ("copy", "gather"))
+    for k in keys:
+        r_, w_ = hbm(k)
+        n = len(vals.get((k, "TCC_EA0_RDREQ_sum"), [0]))
+        us = (sum(dur.get(k, [0])) / max(len(dur.get(k, [])), 1)) / 1e3
+        gbs = (r_ + w_) / (us * 1e-6) / 1e9 if us > 0 else 0.0
+        hit, miss = mean(k, "TCC_HIT_sum"), mean(k, "TCC_MISS_sum")
+        busy, mfb = mean(k, "SQ_BUSY_CYCLES"), mean(k, "SQ_VALU_MFMA_BUSY_CYCLES")
+        gui = mean(k, "GRBM_GUI_ACTIVE")
+        # MFMA-busy cycles are summed over SIMDs: 1024 SIMDs x active GPU cycles
+        mu = mfb / (gui * 1024) if gui > 0 else 0.0
+        out.append(f"{k} {n} {r_:.0f} {w_:.0f} {r_ + w_:.0f} {us:.1f} {gbs:.0f} "
+                   f"{hit / max(hit + miss, 1):.3f} {mu:.4f} {mean(k, 'SQ_INSTS_VALU'):.0f} "
+                   f"{mean(k, 'SQ_INSTS_LDS'):.0f} {mean(k, 'SQ_INSTS_MFMA'):.0f}")
     path = traffic_file(workload)
     with open(path, "w") as fh:
         fh.write("\n".join(out) + "\n")
@@ -434,8 +571,8 @@ def traffic_of(workload, kernels):
         if line.startswith("kernel_source_sha256_16"):
             src = line.split()[1]
         elif line.strip() and not line.startswith("#"):
-            k, _, _, _, b = line.split()
-            tab[k] = float(b)
+            f = line.split()
+            tab[f[0]] = float(f[4])
     if src != kernel_src_hash():
         return None
     return sum(tab.get(k, 0.0) for k in kernels)
@@ -502,9 +639,15 @@ def main():
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the lambda_2 = 0 training run (PSNR and empty-space opacity)")
     ap.add_argument("--psnr-chunk", type=int, default=250)
+    ap.add_argument("--psnr-seeds", type=int, default=2,
+                    help="seeds the equal-PSNR comparison is averaged over")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the batched path only (for profiler runs)")
     ap.add_argument("--frames", type=int, default=300, help="frames of the stream128 workload")
+    ap.add_argument("--eval-every", type=int, default=50,
+                    help="stream128: evaluate the registered objects every this many frames")
+    ap.add_argument("--no-occupancy", action="store_true",
+                    help="stream128: train without the occupancy skip")
     ap.add_argument("--streams", type=int, default=2, choices=(1, 2),
                     help="streams of a batched step (1 for profiler runs: kernel traces and "
                          "counters then describe one launch per kernel and phase)")
@@ -535,13 +678,18 @@ def main():
         f"{len(wl.frames)} frames")
     assert torch.cuda.is_available(), "no GPU visible"
     if args.copy_probe:
-        src = torch.ones(128 << 20, device="cuda")  # 512 MiB
+        src = torch.ones(COPY_MIB << 18, device="cuda")  # COPY_MIB MiB of floats
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy probe: 3 x 512 MiB copied")
         del src, dst
+        tab = torch.ones(GATHER_TABLE_MIB << 18, device="cuda")
+        idx = torch.randint(0, tab.numel(), (GATHER_N,), device="cuda")
+        for _ in range(3):
+            out = torch.index_select(tab, 0, idx)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 x {COPY_MIB} MiB copied, 3 x {GATHER_N} random words gathered")
+        del tab, idx, out
     if args.table_sweep:
         print(json.dumps({"table_sweep": table_sweep(wl)}), flush=True)
         return
@@ -634,7 +782,7 @@ def main():
     quality = None
     if not args.no_psnr:
         quality = equal_psnr(wl, ids, rays, prec, args.psnr_steps, args.psnr_chunk, ms_step,
-                             dtp / args.steps * 1e3)
+                             dtp / args.steps * 1e3, seeds=tuple(range(args.psnr_seeds)))
         log("psnr", json.dumps(quality))
     ablation = None
     if not args.no_ablation and not args.no_psnr:
