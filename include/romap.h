@@ -376,7 +376,7 @@ romap_status romap_field_forward_noalloc(romap_ctx* ctx, int32_t object_id,
  * NULL) receives the number of steps averaged (0 if none). */
 romap_status romap_get_phase_times(romap_ctx* ctx, float* avg_ms, int32_t* n_steps);
 /* Gradient records per step (written by the binning kernel, read by the
- * accumulation; 10 B each) averaged over the same profiled steps: the work
+ * accumulation; 8 B each) averaged over the same profiled steps: the work
  * measure of the two binning kernels (fewer than 8 per sample and level
  * where runs of samples in one cell are merged). */
 romap_status romap_get_step_records(romap_ctx* ctx, double* avg_records);

@@ -37,11 +37,18 @@
 #define RM_RB_BITS 11       /* binned scatter: table entries per region = 2048 */
 #define RM_RB (1 << RM_RB_BITS)
 #define RM_ACC_WG 512       /* threads of the region accumulation kernel */
+#ifndef RM_SCAT_WG
 #define RM_SCAT_WG 512      /* samples (threads) per block of the binning kernel */
+#endif
+#ifndef RM_ENC_SPLIT
 #define RM_ENC_SPLIT 2      /* gather workgroups per block (measured: 1, 2, 4 -> 535, 512, 517 us) */
+#endif
 #define RM_ACC_CHUNK 32768  /* records per accumulation workgroup (about; 8192, 16384, 32768: 2.33, 2.23, 2.22 ms per step) */
 #define RM_ACC_MAXK 256     /* accumulation workgroups per region, at most */
 #define RM_GROUP_RECORDS (1ll << 29) /* record slots of one bin group (5 GiB) */
+#ifndef RM_ACC_RQ
+#define RM_ACC_RQ 4         /* quads of records per thread the accumulation keeps in registers */
+#endif
 #define RM_FX_BITS 38       /* fixed-point fraction bits of the region sums */
 #define RM_MAX_REGIONS 8192 /* 2^24 / 2^11 */
 
@@ -219,8 +226,7 @@ struct StepArgs {
   int32_t n_regions;    // bins over all pairs
   int32_t bin_max_R;    // most regions of one pair
   int32_t* bin_count;   // records per bin (zeroed by the gather kernel)
-  uint16_t* rec_idx;    // entry index within the region
-  float2* rec_val;
+  float2* rec_val;      // records: values with the entry index in their low mantissa bits
 };
 
 // Launch helpers implemented in romap_kernels.hip.

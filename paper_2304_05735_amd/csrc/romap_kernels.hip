@@ -126,6 +126,22 @@ __device__ inline float wave_excl_suffix(float x, int lane) {
   return dppf<0x130>(x);  // wave_shl:1: the next lane's inclusive suffix
 }
 
+// integer inclusive prefix sum over the 64 lanes (same steps)
+template <int CTRL, int ROWM = 0xf, int BANKM = 0xf, bool BC = true>
+__device__ inline int dppi(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWM, BANKM, BC);
+}
+
+__device__ inline int wave_incl_prefix_i(int x) {
+  x += dppi<0x111>(x);
+  x += dppi<0x112>(x);
+  x += dppi<0x114>(x);
+  x += dppi<0x118>(x);
+  x += dppi<0x142, 0xa, 0xf, false>(x);
+  x += dppi<0x143, 0xc, 0xf, false>(x);
+  return x;
+}
+
 // exclusive prefix without the subtraction: shift the inclusive scan by one lane
 __device__ inline float wave_excl_prefix(float x, int lane) {
   return dppf<0x138>(wave_incl_prefix(x));  // wave_shr:1
@@ -495,17 +511,49 @@ __device__ inline void adam_entry(const ObjStatic& ob, int64_t off, float gx, fl
 //                  otherwise, and read-modify-write if the bin overflowed)
 // The bins' fill counters are zeroed by the gather kernel of the same pass.
 
+// A record of the gradient scatter: the two feature values of one corner,
+// each rounded to nearest at 17 mantissa bits (a change of at most 2^-18 of
+// the value; the sums are then taken to about 2^-38 of an entry's largest
+// term), with the entry's index within its region (RM_RB_BITS <= 12 bits) in
+// the 6 mantissa bits freed in each.  Zero stays zero, infinities and NaNs
+// keep their class.
+static_assert(RM_RB_BITS <= 12, "the entry index takes 6 mantissa bits of each value");
+
+__device__ inline uint32_t rec_round(float x) { return (__float_as_uint(x) + 0x20u) & ~0x3Fu; }
+
+__device__ inline float2 rec_pack(float2 v, uint32_t e) {
+  return make_float2(__uint_as_float(rec_round(v.x) | (e & 0x3Fu)),
+                     __uint_as_float(rec_round(v.y) | ((e >> 6) & 0x3Fu)));
+}
+
+__device__ inline uint32_t rec_entry(float x, float y) {
+  return (__float_as_uint(x) & 0x3Fu) | ((__float_as_uint(y) & 0x3Fu) << 6);
+}
+
+__device__ inline float rec_value(float x) { return __uint_as_float(__float_as_uint(x) & ~0x3Fu); }
+
 // The 8 corner records of sample s at level l of object ob; false if none.
 template <int NS>
 __device__ inline bool bin_records(const StepArgs& a, const ObjStatic& ob, int l, uint32_t N,
                                    uint32_t T, bool hashed, int64_t s, uint32_t idx[8],
                                    float2 v[8]) {
-  const RayRec R = a.rays[s / NS];
-  if (!ray_active(R.flags)) return false;
+  // the ray's origin, direction, t_n, delta and flags and the sample's
+  // adjoint are loaded together, before either test (one memory round trip)
+  const float4* rp = (const float4*)(a.rays + s / NS);
+  const float4 r0 = rp[0], r1 = rp[1];
+  const uint32_t flags = a.rays[s / NS].flags;
   const float2 g = a.de[(int64_t)l * a.S + s];
+  const float half[3] = {ob.half[0], ob.half[1], ob.half[2]};
+  asm volatile("" ::"v"(r0.x), "v"(r1.x), "v"(flags), "v"(g.x), "v"(half[0]), "v"(half[1]),
+               "v"(half[2]));
+  if (!ray_active(flags)) return false;
   if (g.x == 0.0f && g.y == 0.0f) return false;
+  RayRec R;
+  R.o[0] = r0.x, R.o[1] = r0.y, R.o[2] = r0.z;
+  R.d[0] = r0.w, R.d[1] = r1.x, R.d[2] = r1.y;
+  R.tn = r1.z, R.delta = r1.w;
   float p[3];
-  sample_pos(R, (int)(s % NS), ob.half, p);
+  sample_pos(R, (int)(s % NS), half, p);
   Cell cl;
   make_cell(p, N, cl);
   cell_corners(cl, N, T, hashed, idx);
@@ -526,12 +574,7 @@ __device__ inline int block_exclusive_scan(const int* cnt, int* base, int n, int
   const int j0 = tid * per;
   int mine = 0;
   for (int j = j0; j < j0 + per && j < n; ++j) mine += cnt[j];
-  int inc = mine;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += y;
-  }
+  const int inc = wave_incl_prefix_i(mine);
   if (lane == 63) s_wsum[wave] = inc;
   __syncthreads();
   int woff = 0, tot = 0;
@@ -587,6 +630,8 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
   const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];  // uniform in the block
   const uint32_t NL = ob.N_l[bp.l], TL = ob.T_l[bp.l];
   const bool hashed = (ob.hashed_mask >> bp.l) & 1u;
+  float* gl = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l];
+  float2* rval = a.rec_val + bp.rec_base;
   bool has =
       k < bp.n_samples && bin_records<NS>(a, ob, bp.l, NL, TL, hashed, bp.s_begin + k, idx, v);
   if (bp.merge) {
@@ -636,19 +681,23 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
     }
   }
   __syncthreads();
-  const int n = block_exclusive_scan<RM_SCAT_WG>(lcnt, lbase, bp.R, s_wsum);
-  // reserve the block's share of each bin; with at most one region per
-  // thread the reservation is in flight while the records are staged
+  // reserve the block's share of each bin first; with at most one region
+  // per thread the reservations are in flight through the scan and the
+  // staging (the barriers wait for LDS operations only)
   int mine = 0;
   const bool one = bp.R <= RM_SCAT_WG;
   if (one && tid < bp.R && lcnt[tid]) mine = atomicAdd(&a.bin_count[bp.bin_base + tid], lcnt[tid]);
   if (!one)
     for (int r = tid; r < bp.R; r += RM_SCAT_WG)
       gpos[r] = lcnt[r] ? atomicAdd(&a.bin_count[bp.bin_base + r], lcnt[r]) : 0;
+  const int n = block_exclusive_scan<RM_SCAT_WG>(lcnt, lbase, bp.R, s_wsum);
   if (has) {
+    int lb[8];  // all eight bases first: one LDS round trip
+#pragma unroll
+    for (int b = 0; b < 8; ++b) lb[b] = lbase[idx[b] >> RM_RB_BITS];
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const int j = lbase[idx[b] >> RM_RB_BITS] + rank[b];
+      const int j = lb[b] + rank[b];
       s_id[j] = idx[b];
       s_val[j] = v[b];
     }
@@ -666,20 +715,35 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
     lim[r] = b0 + bp.cap;
   }
   __syncthreads();
-  float* gl = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l];
-  uint16_t* ridx = a.rec_idx + bp.rec_base;
-  float2* rval = a.rec_val + bp.rec_base;
-  for (int j = tid; j < n; j += RM_SCAT_WG) {
-    const uint32_t id = s_id[j];
-    const int r = (int)(id >> RM_RB_BITS);
-    const int slot = dst[r] + j;
-    const float2 val = s_val[j];
-    if (slot < lim[r]) {
-      ridx[slot] = (uint16_t)(id & (RM_RB - 1));
-      rval[slot] = val;
-    } else {  // bin full: direct atomics (correct, only slower)
-      unsafeAtomicAdd(gl + 2 * (int64_t)id, val.x);
-      unsafeAtomicAdd(gl + 2 * (int64_t)id + 1, val.y);
+  // four records per thread and round: their LDS reads are issued together
+  constexpr int U = 4;
+  for (int j0 = tid; j0 < n; j0 += U * RM_SCAT_WG) {
+    uint32_t id[U];
+    float2 val[U];
+    int d[U], lm[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * RM_SCAT_WG;
+      id[u] = j < n ? s_id[j] : 0u;
+      val[u] = j < n ? s_val[j] : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = (int)(id[u] >> RM_RB_BITS);
+      d[u] = dst[r];
+      lm[u] = lim[r];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * RM_SCAT_WG;
+      if (j >= n) break;
+      const int slot = d[u] + j;
+      if (slot < lm[u]) {
+        rval[slot] = rec_pack(val[u], id[u] & (RM_RB - 1));
+      } else {  // bin full: direct atomics (correct, only slower)
+        unsafeAtomicAdd(gl + 2 * (int64_t)id[u], val[u].x);
+        unsafeAtomicAdd(gl + 2 * (int64_t)id[u] + 1, val[u].y);
+      }
     }
   }
 }
@@ -705,6 +769,14 @@ __device__ inline void fx_add(unsigned long long* acc, const uint32_t* emax, uin
   const double sc = pow2d(RM_FX_BITS + 127 - (int)eb);  // |v| < 2^(eb - 126)
   atomicAdd(&acc[2 * e], (unsigned long long)__double2ll_rn((double)vx * sc));
   atomicAdd(&acc[2 * e + 1], (unsigned long long)__double2ll_rn((double)vy * sc));
+}
+
+__device__ inline void rec_max(uint32_t* emax, float x, float y) {
+  atomicMax(&emax[rec_entry(x, y)], max(exp_field(x), exp_field(y)));
+}
+
+__device__ inline void rec_add(unsigned long long* acc, const uint32_t* emax, float x, float y) {
+  fx_add(acc, emax, rec_entry(x, y), rec_value(x), rec_value(y));
 }
 
 __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
@@ -756,37 +828,64 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
   }
   __syncthreads();
   const int64_t base = bp.rec_base + (int64_t)bn.region * bp.cap;  // multiple of 4
-  const ushort4* ri = (const ushort4*)(a.rec_idx + base);
-  const float4* rv = (const float4*)(a.rec_val + base);
+  const float4* rv = (const float4*)(a.rec_val + base);  // two records per float4
   const int q0 = i0 >> 2, q1 = i1 >> 2;
+  // The first RM_ACC_RQ quads of records of each thread stay in registers
+  // from the first pass to the second: a share of up to RM_ACC_RQ * 4 *
+  // RM_ACC_WG records is read once (the shares of all workgroups in flight
+  // do not fit in the L2 between the passes).
+  constexpr int RQ = RM_ACC_RQ;
+  float4 ca[RQ], cb[RQ];
+#pragma unroll
+  for (int i = 0; i < RQ; ++i) {
+    const int q = q0 + threadIdx.x + i * RM_ACC_WG;
+    if (q < q1) {
+      ca[i] = rv[2 * q];
+      cb[i] = rv[2 * q + 1];
+    }
+  }
   // pass 1: largest exponent per entry
-  for (int q = q0 + threadIdx.x; q < q1; q += RM_ACC_WG) {  // 4 records per lane
-    const ushort4 e4 = ri[q];
+#pragma unroll
+  for (int i = 0; i < RQ; ++i) {
+    if (q0 + (int)threadIdx.x + i * RM_ACC_WG < q1) {
+      rec_max(emax, ca[i].x, ca[i].y);
+      rec_max(emax, ca[i].z, ca[i].w);
+      rec_max(emax, cb[i].x, cb[i].y);
+      rec_max(emax, cb[i].z, cb[i].w);
+    }
+  }
+  for (int q = q0 + threadIdx.x + RQ * RM_ACC_WG; q < q1; q += RM_ACC_WG) {  // 4 records per lane
     const float4 va = rv[2 * q], vb = rv[2 * q + 1];
-    atomicMax(&emax[e4.x], max(exp_field(va.x), exp_field(va.y)));
-    atomicMax(&emax[e4.y], max(exp_field(va.z), exp_field(va.w)));
-    atomicMax(&emax[e4.z], max(exp_field(vb.x), exp_field(vb.y)));
-    atomicMax(&emax[e4.w], max(exp_field(vb.z), exp_field(vb.w)));
+    rec_max(emax, va.x, va.y);
+    rec_max(emax, va.z, va.w);
+    rec_max(emax, vb.x, vb.y);
+    rec_max(emax, vb.z, vb.w);
   }
   for (int i = (q1 << 2) + threadIdx.x; i < i1; i += RM_ACC_WG) {  // tail
-    const uint32_t e = a.rec_idx[base + i];
     const float2 v = a.rec_val[base + i];
-    atomicMax(&emax[e], max(exp_field(v.x), exp_field(v.y)));
+    rec_max(emax, v.x, v.y);
   }
   __syncthreads();
-  // pass 2: fixed-point sums (the records are read again, mostly from cache)
-  for (int q = q0 + threadIdx.x; q < q1; q += RM_ACC_WG) {
-    const ushort4 e4 = ri[q];
+  // pass 2: fixed-point sums (records beyond the registers are read again)
+#pragma unroll
+  for (int i = 0; i < RQ; ++i) {
+    if (q0 + (int)threadIdx.x + i * RM_ACC_WG < q1) {
+      rec_add(acc, emax, ca[i].x, ca[i].y);
+      rec_add(acc, emax, ca[i].z, ca[i].w);
+      rec_add(acc, emax, cb[i].x, cb[i].y);
+      rec_add(acc, emax, cb[i].z, cb[i].w);
+    }
+  }
+  for (int q = q0 + threadIdx.x + RQ * RM_ACC_WG; q < q1; q += RM_ACC_WG) {
     const float4 va = rv[2 * q], vb = rv[2 * q + 1];
-    fx_add(acc, emax, e4.x, va.x, va.y);
-    fx_add(acc, emax, e4.y, va.z, va.w);
-    fx_add(acc, emax, e4.z, vb.x, vb.y);
-    fx_add(acc, emax, e4.w, vb.z, vb.w);
+    rec_add(acc, emax, va.x, va.y);
+    rec_add(acc, emax, va.z, va.w);
+    rec_add(acc, emax, vb.x, vb.y);
+    rec_add(acc, emax, vb.z, vb.w);
   }
   for (int i = (q1 << 2) + threadIdx.x; i < i1; i += RM_ACC_WG) {
-    const uint32_t e = a.rec_idx[base + i];
     const float2 v = a.rec_val[base + i];
-    fx_add(acc, emax, e, v.x, v.y);
+    rec_add(acc, emax, v.x, v.y);
   }
   __syncthreads();
   float2* g = (float2*)((a.grad_override ? a.grad_override : ob.grad) + off0);

@@ -156,8 +156,6 @@ struct romap_ctx {
   size_t cap_tables = 0;
   int32_t* d_bin_count = nullptr;
   size_t cap_bin_count = 0;
-  uint16_t* d_rec_idx = nullptr;
-  size_t cap_rec_idx = 0;
   float2* d_rec_val = nullptr;
   size_t cap_rec_val = 0;
   // graph of the last batched step
@@ -302,7 +300,6 @@ StepArgs base_args(romap_ctx* c) {
   a.rays = c->d_rays;
   a.e = c->d_e;
   a.bin_count = c->d_bin_count;
-  a.rec_idx = c->d_rec_idx;
   a.rec_val = c->d_rec_val;
   a.de = c->d_de;
   a.partials = c->d_partials;
@@ -481,7 +478,6 @@ romap_status stage_plans(romap_ctx* c, std::vector<Plan*> plans, bool concurrent
   HIPALLOC(c, regrow(&c->d_wpack16, &c->cap_w16, std::max<size_t>(max_sobj * RM_WPACK_NH(nh), 1)));
   HIPALLOC(c, regrow(&c->d_tables, &c->cap_tables, std::max<size_t>(tab, 256)));
   HIPALLOC(c, regrow(&c->d_bin_count, &c->cap_bin_count, std::max<size_t>(max_bins, 1)));
-  HIPALLOC(c, regrow(&c->d_rec_idx, &c->cap_rec_idx, std::max<size_t>(max_rec, 1)));
   HIPALLOC(c, regrow(&c->d_rec_val, &c->cap_rec_val, std::max<size_t>(max_rec, 1)));
   std::vector<char> h(tab);
   for (Plan* p : plans) {
@@ -520,7 +516,6 @@ StepArgs plan_args(romap_ctx* c, const Plan& p) {
   a.wpack32 = c->d_wpack32 + p.so_wpack;
   a.wpack16 = c->d_wpack16 + p.so_wpack;
   a.bin_count = c->d_bin_count + p.so_bins;
-  a.rec_idx = c->d_rec_idx + p.so_rec;
   a.rec_val = c->d_rec_val + p.so_rec;
   a.n_regions = (int)p.bin_regions;
   a.bin_max_R = 0;
@@ -940,7 +935,6 @@ romap_status romap_destroy(romap_ctx* c) {
   hipFree(c->d_mcnt);
   hipFree(c->d_mbsum);
   hipFree(c->d_mtris);
-  hipFree(c->d_rec_idx);
   hipFree(c->d_rec_val);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
@@ -2109,7 +2103,6 @@ romap_status romap_field_forward_noalloc(romap_ctx* c, int32_t id, const float* 
   a.wpack16 = (uint16_t*)(base + o_w16);
   a.de = nullptr;  // the forward writes no adjoints, records or partial sums
   a.partials = nullptr;
-  a.rec_idx = nullptr;
   a.rec_val = nullptr;
   a.params_override = params_dev;
   a.mode = RM_MODE_FORWARD;
