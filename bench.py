@@ -425,11 +425,17 @@ def _kernel_key(name):
 # Counter passes of a profiled run (rocprofv3 --pmc, one pass per run: a pass
 # holds at most 4 TCC, 8 SQ and 2 GRBM counters).
 PMC_PASSES = {
-    "rd": "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum TCC_EA0_RDREQ_DRAM_sum",
-    "wr": "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_WRREQ_DRAM_sum",
+    "rd": "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum",
+    "wr": "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_WRREQ_DRAM_sum TCC_EA0_RDREQ_DRAM_sum",
     "l2": "TCC_HIT_sum TCC_MISS_sum",
-    "sq": "SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_INSTS_VALU "
-          "SQ_INSTS_LDS SQ_INSTS_MFMA SQ_WAVES SQ_WAIT_INST_ANY GRBM_GUI_ACTIVE",
+    # MfmaUtil: MFMA-busy cycles summed over SIMDs / (active cycles x SIMDs)
+    "sq": "MfmaUtil SQ_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_INSTS_VALU "
+          "SQ_INSTS_LDS SQ_INSTS_MFMA SQ_WAVES SQ_WAIT_INST_ANY",
+    # where waves spend their time (wave-cycles) and what the LDS does
+    "st": "SQ_WAVE_CYCLES SQ_BUSY_CU_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_LDS SQ_LDS_BANK_CONFLICT "
+          "SQ_LDS_ADDR_CONFLICT SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM",
+    "st2": "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_ANY SQ_INSTS_LDS_ATOMIC SQ_LDS_ATOMIC_RETURN "
+           "SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU SQ_INSTS_SMEM",
 }
 COPY_MIB = 512          # --copy-probe: a plain copy of this size
 GATHER_TABLE_MIB = 1024  # and a gather of random 4-byte words from a table this large
@@ -445,37 +451,91 @@ def _probe_kind(name):
     return None
 
 
+def _find_csv(d, name):
+    """rocprofv3 writes <d>/<name> or nests it under host and process folders."""
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", name), recursive=True))
+    if not hits:
+        raise SystemExit(f"no {name} under {d}")
+    return hits[0]
+
+
+WORKLOAD_NOTES = {
+    "objects24": "24 objects, 16 levels, T 2^15..2^19 by box volume, 25201 rays x 64 samples "
+                 "per step, BF16 MLP, batched, step graph",
+    "objects24-fp32": "the objects24 scene and rays with the FP32 MLP, batched, step graph",
+    "torus1": "1 object, 16 levels, T 2^19, 4096 rays x 64 samples per step, FP32 MLP, step graph",
+}
+
+
+def trace_summary(d, workload, steps, warmup):
+    """Kernel-time table (calls, average/min/max us, share) of a rocprofv3
+    --kernel-trace --stats run of bench.py --only-headline --streams 1,
+    written to profiles/step_kernels_<workload>.txt."""
+    import csv
+    rows = list(csv.DictReader(open(_find_csv(d, "run_kernel_stats.csv"))))
+    out = [f"# rocprofv3 kernel-trace summary: training-step kernels, workload {workload} "
+           f"({WORKLOAD_NOTES.get(workload, workload)})",
+           "# command (from the repository root, after __graft_entry__.build()):",
+           "#   export TMPDIR=/tmp",
+           f"#   rocprofv3 --kernel-trace --stats -d <out> -o run -f csv -- python3 bench.py "
+           f"--workload {workload} --steps {steps} --warmup {warmup} --only-headline --streams 1",
+           f"#   python bench.py --trace-summary <out> --workload {workload} --steps {steps} "
+           f"--warmup {warmup}",
+           f"# {steps + warmup} steps ({warmup} warm-up + {steps} timed) replay the step graph on one "
+           "stream; extra calls of k_field / k_encode_fwd / k_pack / k_raygen come from the "
+           "autotuner and the graph capture; k_field<PREC, NS, K1, layers>",
+           f"kernel_source_sha256_16 {kernel_src_hash()}",
+           "# columns: kernel | calls | average us | min us | max us | share of kernel time %"]
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows:
+        name = r["Name"].replace("void ", "").strip()
+        if "(" in name and "<" in name:
+            name = name.split("(")[0]
+        out.append(f"{name[:48]:48s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                   f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                   f"{float(r['Percentage']):7.2f}")
+    path = os.path.join(ROOT, "profiles", f"step_kernels_{workload}.txt")
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+    log("wrote", path)
+
+
 def pmc_summary(d, workload, steps):
     """Per-kernel counter summary from the rocprofv3 --pmc runs in <d>/<pass>
     (PMC_PASSES) of bench.py --only-headline --copy-probe.  HBM bytes come
-    from read and write requests split by size: the copy probe (COPY_MIB read
-    and written) fixes the size of the requests that the counters do not
-    class (the 32-byte and the 128-byte ones are counted apart), the random
-    gather probe checks that attribution where requests are small, and no
-    kernel's bytes may imply more than the copy's rate.  Also the L2 hit rate
-    and, per kernel, MFMA-busy cycles over busy cycles and instruction counts."""
+    from read requests counted by size (32, 64 and 128 bytes) and write
+    requests (64 bytes, else 32).  The copy probe (COPY_MIB read and written)
+    checks that these sizes account for its bytes; read requests of no
+    counted size (none expected) would take the size that balances the copy.
+    The random-gather probe and every kernel are checked against the copy's
+    rate: bytes that imply more than it are flagged.  Also the L2 hit rate
+    and, per kernel, MFMA utilisation, BF16 MFMA flops and instruction
+    counts."""
     import csv
+    import glob
     vals = {}  # (kernel, counter) -> [per-dispatch values]
-    dur = {}   # kernel -> [ns]
+    dur = {}   # kernel or probe -> [ns]
+    missing = [sub for sub in PMC_PASSES if not glob.glob(
+        os.path.join(d, sub, "**", "run_counter_collection.csv"), recursive=True)]
     for sub in PMC_PASSES:
-        path = os.path.join(d, sub, "run_counter_collection.csv")
-        if not os.path.exists(path):
-            raise SystemExit(f"missing {path}")
-        seen = {}
+        if sub in missing:
+            continue
+        path = _find_csv(os.path.join(d, sub), "run_counter_collection.csv")
         for r in csv.DictReader(open(path)):
             name = r["Kernel_Name"]
-            key = _kernel_key(name) if name.lstrip("void ").startswith("k_") else _probe_kind(name)
+            key = _kernel_key(name) if _kernel_key(name).startswith("k_") else _probe_kind(name)
             if key is None:
                 continue
-            v = float(r["Counter_Value"])
-            vals.setdefault((key, r["Counter_Name"]), []).append(v)
-        ktrace = os.path.join(d, sub, "run_kernel_trace.csv")
-        if os.path.exists(ktrace):
+            vals.setdefault((key, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+        for ktrace in glob.glob(os.path.join(d, sub, "**", "run_kernel_trace.csv"), recursive=True)[:1]:
             for r in csv.DictReader(open(ktrace)):
                 name = r["Kernel_Name"]
-                key = _kernel_key(name) if name.lstrip("void ").startswith("k_") else None
+                key = _kernel_key(name) if _kernel_key(name).startswith("k_") else _probe_kind(name)
                 if key:
-                    dur.setdefault(key, []).append(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+                    dur.setdefault(key, []).append(float(r["End_Timestamp"]) -
+                                                   float(r["Start_Timestamp"]))
 
     def mean(key, c):
         x = vals.get((key, c))
@@ -485,53 +545,96 @@ def pmc_summary(d, workload, steps):
             return max(x)
         return sum(x) / len(x)
 
-    def split(key):
-        rd, r32, r128 = mean(key, "TCC_EA0_RDREQ_sum"), mean(key, "TCC_EA0_RDREQ_32B_sum"), \
-            mean(key, "TCC_BUBBLE_sum")
-        wr, w64 = mean(key, "TCC_EA0_WRREQ_sum"), mean(key, "TCC_EA0_WRREQ_64B_sum")
-        return rd - r32 - r128, r32, r128, wr - w64, w64
+    def avg_us(key):
+        x = dur.get(key, [])
+        if key in ("copy", "gather"):  # the median of the probe's repeats (all passes)
+            top = sorted(t for t in x if t >= 0.5 * max(x)) if x else []
+            return top[len(top) // 2] / 1e3 if top else 0.0
+        return sum(x) / len(x) / 1e3 if x else 0.0
 
-    # the copy fixes the size of the unclassed read requests and of the
-    # write requests that are not 64-byte ones
-    rmid, r32, r128, wsmall, w64 = split("copy")
+    def reads(key):
+        n, n32, n64, n128 = (mean(key, "TCC_EA0_RDREQ_sum"), mean(key, "TCC_EA0_RDREQ_32B_sum"),
+                             mean(key, "TCC_EA0_RDREQ_64B_sum"), mean(key, "TCC_EA0_RDREQ_128B_sum"))
+        return 32 * n32 + 64 * n64 + 128 * n128, max(n - n32 - n64 - n128, 0.0)
+
+    def writes(key):
+        w, w64 = mean(key, "TCC_EA0_WRREQ_sum"), mean(key, "TCC_EA0_WRREQ_64B_sum")
+        return 64 * w64 + 32 * (w - w64)
+
     copy_bytes = COPY_MIB * 2 ** 20
-    rsize = (copy_bytes - 32 * r32 - 128 * r128) / max(rmid, 1.0)
-    wsize = (copy_bytes - 64 * w64) / max(wsmall, 1.0)
+    cr, crest = reads("copy")
+    rsize = (copy_bytes - cr) / crest if crest > 0 else 0.0
 
     def hbm(key):
-        m, a32, a128, ws, w64_ = split(key)
-        return (32 * a32 + rsize * m + 128 * a128), (wsize * ws + 64 * w64_)
+        r, rest = reads(key)
+        return r + rsize * rest, writes(key), rest
 
+    cw = writes("copy")
+    copy_us = avg_us("copy")
+    copy_gbs = (sum(hbm("copy")[:2])) / (copy_us * 1e-6) / 1e9 if copy_us > 0 else 0.0
     out = [f"# HBM traffic and counters per dispatch, workload {workload}",
            "# passes (one rocprofv3 run each; <pass> in " + ", ".join(PMC_PASSES) + "):",
            f"#   rocprofv3 --pmc <counters of the pass> --kernel-trace -d <dir>/<pass> -o run -f csv "
            f"-- python3 bench.py --steps {steps} --warmup 3 --only-headline --copy-probe "
            f"--streams 1 --workload {workload}",
-           f"# then: python bench.py --pmc-summary <dir> --workload {workload}",
-           f"# calibration: the {COPY_MIB} MiB copy's unclassed read requests move {rsize:.1f} B "
-           f"each, its non-64-byte write requests {wsize:.1f} B"]
-    gr, gw = hbm("gather")
+           f"# then: python bench.py --pmc-summary <dir> --workload {workload} --steps {steps}",
+           "# counters of the passes: " + "; ".join(f"{k}: {v}" for k, v in PMC_PASSES.items()),
+           "# passes not taken: " + (", ".join(missing) or "none"),
+           f"# read bytes = 32 n32 + 64 n64 + 128 n128 (+ unsized requests at the size that "
+           f"balances the copy); write bytes = 64 n64 + 32 (n - n64)",
+           f"# copy probe ({COPY_MIB} MiB read and written): counted reads {cr / copy_bytes:.4f}, "
+           f"writes {cw / copy_bytes:.4f} of its bytes; unsized read requests {crest:.0f}"
+           + (f" (taken at {rsize:.1f} B)" if crest > 0 else "")
+           + f"; {copy_us:.1f} us, {copy_gbs:.0f} GB/s"]
+    gr, gw, _ = hbm("gather")
     want = GATHER_N * 4
-    out.append(f"# random-gather probe ({GATHER_N} words from {GATHER_TABLE_MIB} MiB): "
-               f"{gr / 1e6:.1f} MB read for {want / 1e6:.1f} MB of words "
-               f"({gr / want:.1f} B per useful byte: whole lines), {gw / 1e6:.1f} MB written")
+    g_us = avg_us("gather")
+    g_gbs = (gr + gw) / (g_us * 1e-6) / 1e9 if g_us > 0 else 0.0
+    out.append(f"# random-gather probe ({GATHER_N} words from {GATHER_TABLE_MIB} MiB, int64 "
+               f"indices): {gr / 1e6:.1f} MB read for {want / 1e6:.1f} MB of words, "
+               f"{gw / 1e6:.1f} MB written; {g_us:.1f} us, {g_gbs:.0f} GB/s"
+               + (" (ABOVE the copy's rate: sizes do not hold)" if g_gbs > copy_gbs > 0 else
+                  " (within the copy's rate)"))
     out.append(f"kernel_source_sha256_16 {kernel_src_hash()}")
     out.append("# kernel dispatches read_bytes write_bytes hbm_bytes avg_us implied_GB/s "
-               "l2_hit_rate mfma_busy valu_insts lds_insts mfma_insts")
+               "l2_hit_rate mfma_util bf16_mfma_flops valu_insts lds_insts mfma_insts "
+               "wait_inst_any_quads waves")
     keys = sorted(k for k in {k for k, _ in vals} if k not in ("copy", "gather"))
+    over = []
     for k in keys:
-        r_, w_ = hbm(k)
+        r_, w_, _ = hbm(k)
         n = len(vals.get((k, "TCC_EA0_RDREQ_sum"), [0]))
-        us = (sum(dur.get(k, [0])) / max(len(dur.get(k, [])), 1)) / 1e3
+        us = avg_us(k)
         gbs = (r_ + w_) / (us * 1e-6) / 1e9 if us > 0 else 0.0
+        if copy_gbs > 0 and gbs > copy_gbs:
+            over.append(k)
         hit, miss = mean(k, "TCC_HIT_sum"), mean(k, "TCC_MISS_sum")
-        busy, mfb = mean(k, "SQ_BUSY_CYCLES"), mean(k, "SQ_VALU_MFMA_BUSY_CYCLES")
-        gui = mean(k, "GRBM_GUI_ACTIVE")
-        # MFMA-busy cycles are summed over SIMDs: 1024 SIMDs x active GPU cycles
-        mu = mfb / (gui * 1024) if gui > 0 else 0.0
+        mu = mean(k, "MfmaUtil") / 100.0
+        bf16_flops = 512.0 * mean(k, "SQ_INSTS_VALU_MFMA_MOPS_BF16")
         out.append(f"{k} {n} {r_:.0f} {w_:.0f} {r_ + w_:.0f} {us:.1f} {gbs:.0f} "
-                   f"{hit / max(hit + miss, 1):.3f} {mu:.4f} {mean(k, 'SQ_INSTS_VALU'):.0f} "
-                   f"{mean(k, 'SQ_INSTS_LDS'):.0f} {mean(k, 'SQ_INSTS_MFMA'):.0f}")
+                   f"{hit / max(hit + miss, 1):.3f} {mu:.4f} {bf16_flops:.4g} "
+                   f"{mean(k, 'SQ_INSTS_VALU'):.0f} {mean(k, 'SQ_INSTS_LDS'):.0f} "
+                   f"{mean(k, 'SQ_INSTS_MFMA'):.0f} {mean(k, 'SQ_WAIT_INST_ANY'):.4g} "
+                   f"{mean(k, 'SQ_WAVES'):.0f}")
+    out.append("# kernels whose bytes imply more than the copy's rate: " + (", ".join(over) or "none"))
+    out.append("# where the waves' time goes (ratios of wave-cycle counters; per wave: averages "
+               "over the dispatch's waves)")
+    out.append("# kernel wave_cycles_per_wave wait_any wait_inst_lds active_valu active_vmem "
+               "active_lds lds_bank_conflict_per_lds_cycle lds_addr_conflict_per_lds_cycle "
+               "lds_atomic_insts vmem_rd_insts vmem_wr_insts salu_insts")
+    for k in keys:
+        wc = mean(k, "SQ_WAVE_CYCLES")
+        if wc <= 0:
+            continue
+        nw = max(mean(k, "SQ_WAVES"), 1.0)
+        lds = max(mean(k, "SQ_ACTIVE_INST_LDS"), 1.0)
+        out.append(f"{k} {wc / nw:.0f} {mean(k, 'SQ_WAIT_ANY') / wc:.3f} "
+                   f"{mean(k, 'SQ_WAIT_INST_LDS') / wc:.3f} {mean(k, 'SQ_ACTIVE_INST_VALU') / wc:.3f} "
+                   f"{mean(k, 'SQ_ACTIVE_INST_VMEM') / wc:.3f} {mean(k, 'SQ_ACTIVE_INST_LDS') / wc:.3f} "
+                   f"{mean(k, 'SQ_LDS_BANK_CONFLICT') / lds:.3f} "
+                   f"{mean(k, 'SQ_LDS_ADDR_CONFLICT') / lds:.3f} "
+                   f"{mean(k, 'SQ_INSTS_LDS_ATOMIC'):.0f} {mean(k, 'SQ_INSTS_VMEM_RD'):.0f} "
+                   f"{mean(k, 'SQ_INSTS_VMEM_WR'):.0f} {mean(k, 'SQ_INSTS_SALU'):.0f}")
     path = traffic_file(workload)
     with open(path, "w") as fh:
         fh.write("\n".join(out) + "\n")
@@ -655,11 +758,17 @@ def main():
                     help="first copy 512 MiB three times (calibrates the HBM byte counters)")
     ap.add_argument("--pmc-summary", metavar="DIR",
                     help="write the HBM traffic summary from rocprofv3 counter runs and exit")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="write the kernel-time summary of a rocprofv3 --kernel-trace --stats "
+                         "run and exit")
     args = ap.parse_args()
     global STREAMS
     STREAMS = args.streams
     if args.pmc_summary:
         pmc_summary(args.pmc_summary, args.workload, args.steps)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.workload, args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the path is the "
@@ -770,7 +879,7 @@ def main():
                     copy_gbs=round(copy_gbs, 1), units=units,
                     evaluated_samples=S, samples_drawn=rays_per_step * pctx.cfg.samples_per_ray,
                     grid_params=work["grid_params"],
-                    records_per_step=int(records), record_bytes_per_step=int(10 * records),
+                    records_per_step=int(records), record_bytes_per_step=int(8 * records),
                     phase_ms={k: round(v, 5) for k, v in phases.items()})
     del pctx
     # ---- plain path: FP32, one launch per object per phase, no graph

@@ -356,8 +356,15 @@ def _render_frames(wl: Workload, depth_frac=0.0, seed=0, workers=None):
     workers = workers or min(16, os.cpu_count() or 1)
     if workers > 1 and len(jobs) > 2 and not _gpu_open():
         ctx = mp.get_context("fork")
-        with ctx.Pool(workers) as pool:
+        pool = ctx.Pool(workers)
+        try:
             outs = pool.map(_render_one, jobs)
+            pool.close()  # let the workers exit on their own (no SIGTERM)
+        except BaseException:
+            pool.terminate()
+            raise
+        finally:
+            pool.join()
     else:
         outs = [_render_one(j) for j in jobs]
     for cam, (rgb, mask, dz) in zip(wl.cameras, outs):
