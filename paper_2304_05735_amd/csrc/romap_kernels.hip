@@ -532,6 +532,18 @@ __device__ inline uint32_t rec_entry(float x, float y) {
 
 __device__ inline float rec_value(float x) { return __uint_as_float(__float_as_uint(x) & ~0x3Fu); }
 
+// Stores of data that no kernel reads back while it could still be in the
+// L2 (gradient records, read by the next kernel after the whole scatter;
+// parameters and moments after their Adam update): written past the L2's
+// allocation (measured: the accumulation that follows runs 6 % faster).
+typedef float rm_f2v __attribute__((ext_vector_type(2)));
+__device__ inline void nt_store2(float2* p, float2 v) {
+  rm_f2v w;
+  w[0] = v.x;
+  w[1] = v.y;
+  __builtin_nontemporal_store(w, (rm_f2v*)p);
+}
+
 // The 8 corner records of sample s at level l of object ob; false if none.
 template <int NS>
 __device__ inline bool bin_records(const StepArgs& a, const ObjStatic& ob, int l, uint32_t N,
@@ -739,7 +751,7 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
       if (j >= n) break;
       const int slot = d[u] + j;
       if (slot < lm[u]) {
-        rval[slot] = rec_pack(val[u], id[u] & (RM_RB - 1));
+        nt_store2(&rval[slot], rec_pack(val[u], id[u] & (RM_RB - 1)));
       } else {  // bin full: direct atomics (correct, only slower)
         unsafeAtomicAdd(gl + 2 * (int64_t)id[u], val[u].x);
         unsafeAtomicAdd(gl + 2 * (int64_t)id[u] + 1, val[u].y);
@@ -913,9 +925,9 @@ __global__ __launch_bounds__(RM_ACC_WG) void k_bin_acc(StepArgs a) {
       }
       adam1(ap[k].x, am[k].x, av[k].x, dx, a, bc1, bc2);
       adam1(ap[k].y, am[k].y, av[k].y, dy, a, bc1, bc2);
-      Pp[e] = ap[k];
-      Pm[e] = am[k];
-      Pv[e] = av[k];
+      nt_store2(&Pp[e], ap[k]);
+      nt_store2(&Pm[e], am[k]);
+      nt_store2(&Pv[e], av[k]);
       continue;
     }
     if (em == 0u && sx == 0 && sy == 0) continue;  // untouched (or only zeros)
