@@ -465,26 +465,35 @@ WORKLOAD_NOTES = {
                  "per step, BF16 MLP, batched, step graph",
     "objects24-fp32": "the objects24 scene and rays with the FP32 MLP, batched, step graph",
     "torus1": "1 object, 16 levels, T 2^19, 4096 rays x 64 samples per step, FP32 MLP, step graph",
+    "stream128": "128-object keyframe stream, 4 steps of 2^16 rays x 128 samples per frame over "
+                 "the active objects, BF16 MLP, 64^3 occupancy, T 2^19",
 }
 
 
-def trace_summary(d, workload, steps, warmup):
+def trace_summary(d, workload, steps, warmup, frames=300):
     """Kernel-time table (calls, average/min/max us, share) of a rocprofv3
-    --kernel-trace --stats run of bench.py --only-headline --streams 1,
-    written to profiles/step_kernels_<workload>.txt."""
+    --kernel-trace --stats run of bench.py --only-headline --streams 1 (the
+    stream: bench.py --frames F --streams 1), written to
+    profiles/step_kernels_<workload>.txt."""
     import csv
     rows = list(csv.DictReader(open(_find_csv(d, "run_kernel_stats.csv"))))
+    if workload == "stream128":
+        run = f"--workload stream128 --frames {frames} --streams 1"
+        what = (f"# the first {frames} frames of the stream on one stream (frames train eagerly: "
+                "new shapes every frame); k_bin_scatter / k_bin_acc run once per bin group; "
+                "k_field / k_encode_fwd also serve the PSNR renders")
+    else:
+        run = f"--workload {workload} --steps {steps} --warmup {warmup} --only-headline --streams 1"
+        what = (f"# {steps + warmup} steps ({warmup} warm-up + {steps} timed) replay the step graph "
+                "on one stream; extra calls of k_field / k_encode_fwd / k_pack / k_raygen come "
+                "from the autotuner and the graph capture; k_field<PREC, NS, K1, layers>")
     out = [f"# rocprofv3 kernel-trace summary: training-step kernels, workload {workload} "
            f"({WORKLOAD_NOTES.get(workload, workload)})",
            "# command (from the repository root, after __graft_entry__.build()):",
            "#   export TMPDIR=/tmp",
-           f"#   rocprofv3 --kernel-trace --stats -d <out> -o run -f csv -- python3 bench.py "
-           f"--workload {workload} --steps {steps} --warmup {warmup} --only-headline --streams 1",
-           f"#   python bench.py --trace-summary <out> --workload {workload} --steps {steps} "
-           f"--warmup {warmup}",
-           f"# {steps + warmup} steps ({warmup} warm-up + {steps} timed) replay the step graph on one "
-           "stream; extra calls of k_field / k_encode_fwd / k_pack / k_raygen come from the "
-           "autotuner and the graph capture; k_field<PREC, NS, K1, layers>",
+           f"#   rocprofv3 --kernel-trace --stats -d <out> -o run -f csv -- python3 bench.py {run}",
+           f"#   python bench.py --trace-summary <out> {run.replace(' --only-headline', '').replace(' --streams 1', '')}",
+           what,
            f"kernel_source_sha256_16 {kernel_src_hash()}",
            "# columns: kernel | calls | average us | min us | max us | share of kernel time %"]
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
@@ -582,6 +591,9 @@ def pmc_summary(d, workload, steps):
            "# passes not taken: " + (", ".join(missing) or "none"),
            f"# read bytes = 32 n32 + 64 n64 + 128 n128 (+ unsized requests at the size that "
            f"balances the copy); write bytes = 64 n64 + 32 (n - n64)",
+           "# these are the requests that leave the L2s; lines that the 256 MB Infinity Cache "
+           "serves count too, so a kernel that fetches the same lines into several XCDs' L2s "
+           "(or again soon after) can imply more than the copy's HBM rate",
            f"# copy probe ({COPY_MIB} MiB read and written): counted reads {cr / copy_bytes:.4f}, "
            f"writes {cw / copy_bytes:.4f} of its bytes; unsized read requests {crest:.0f}"
            + (f" (taken at {rsize:.1f} B)" if crest > 0 else "")
@@ -593,8 +605,8 @@ def pmc_summary(d, workload, steps):
     out.append(f"# random-gather probe ({GATHER_N} words from {GATHER_TABLE_MIB} MiB, int64 "
                f"indices): {gr / 1e6:.1f} MB read for {want / 1e6:.1f} MB of words, "
                f"{gw / 1e6:.1f} MB written; {g_us:.1f} us, {g_gbs:.0f} GB/s"
-               + (" (ABOVE the copy's rate: sizes do not hold)" if g_gbs > copy_gbs > 0 else
-                  " (within the copy's rate)"))
+               + (" (above the copy's rate: part of the table's lines come from the Infinity "
+                  "Cache)" if g_gbs > copy_gbs > 0 else " (within the copy's rate)"))
     out.append(f"kernel_source_sha256_16 {kernel_src_hash()}")
     out.append("# kernel dispatches read_bytes write_bytes hbm_bytes avg_us implied_GB/s "
                "l2_hit_rate mfma_util bf16_mfma_flops valu_insts lds_insts mfma_insts "
@@ -616,7 +628,8 @@ def pmc_summary(d, workload, steps):
                    f"{mean(k, 'SQ_INSTS_VALU'):.0f} {mean(k, 'SQ_INSTS_LDS'):.0f} "
                    f"{mean(k, 'SQ_INSTS_MFMA'):.0f} {mean(k, 'SQ_WAIT_INST_ANY'):.4g} "
                    f"{mean(k, 'SQ_WAVES'):.0f}")
-    out.append("# kernels whose bytes imply more than the copy's rate: " + (", ".join(over) or "none"))
+    out.append("# kernels whose request bytes imply more than the copy's rate (served in part by "
+               "the Infinity Cache): " + (", ".join(over) or "none"))
     out.append("# where the waves' time goes (ratios of wave-cycle counters; per wave: averages "
                "over the dispatch's waves)")
     out.append("# kernel wave_cycles_per_wave wait_any wait_inst_lds active_valu active_vmem "
@@ -768,7 +781,7 @@ def main():
         pmc_summary(args.pmc_summary, args.workload, args.steps)
         return
     if args.trace_summary:
-        trace_summary(args.trace_summary, args.workload, args.steps, args.warmup)
+        trace_summary(args.trace_summary, args.workload, args.steps, args.warmup, args.frames)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the path is the "
@@ -863,6 +876,9 @@ def main():
 
     peak_f = BF16_PEAK_TFLOPS if prec == pk.PREC_BF16 else FP32_MFMA_PEAK_TFLOPS
     tf = work["mlp_flops"] / (phases["field"] * 1e-3) / 1e12
+    mfma_measured = pk.debug_mfma_rate(prec)  # what the matrix cores sustain here
+    log(f"measured MFMA rate ({'BF16' if prec == pk.PREC_BF16 else 'FP32'}): "
+        f"{mfma_measured:.0f} TFLOP/s")
     units = {
         "scatter_adam": hbm("scatter_adam", ["bin_scatter", "bin_acc", "bin_finish"],
                             work["scatter_adam"]),
@@ -870,6 +886,8 @@ def main():
         "mlp": dict(bound="mfma", kernels=["k_field"], avg_ms=round(phases["field"], 5),
                     algorithmic_flops=int(work["mlp_flops"]), achieved=round(tf, 2),
                     peak=peak_f, unit="TFLOP/s", frac=round(tf / peak_f, 4),
+                    peak_measured=round(mfma_measured, 1),
+                    frac_of_measured=round(tf / mfma_measured, 4),
                     hbm_bytes=int(work["field_bytes"])),
     }
     dominant = max(units, key=lambda k: units[k]["avg_ms"])

@@ -320,6 +320,14 @@ romap_status romap_debug_bin_capacity(romap_ctx* ctx, int32_t slots);
  * the defaults are 8 and 256.  Results are the same up to rounding order.
  * ROMAP_E_INVALID_ARG for other values. */
 romap_status romap_debug_tiles(romap_ctx* ctx, int32_t rays_per_item, int32_t gather_block);
+/* Sustained matrix-core rate of the current device in TFLOP/s, measured by a
+ * kernel of independent MFMA chains with no memory traffic, eight waves per
+ * SIMD (precision ROMAP_PREC_BF16: 32x32x16 BF16 MFMA; ROMAP_PREC_FP32:
+ * 16x16x4 FP32 MFMA): the measured peak beside the datasheet one against which the
+ * MLP kernel's rate is stated.  Runs on the null stream and waits for it;
+ * allocates and frees a small output buffer.  ROMAP_E_INVALID_ARG for another
+ * precision or tflops == NULL, ROMAP_E_HIP / ROMAP_E_OUT_OF_MEMORY on runtime errors. */
+romap_status romap_debug_mfma_rate(int32_t precision, double* tflops);
 
 /* ---- differentiable surface (for torch.autograd.Function) ----------------
  * rays_dev: n_rays*8 floats per ray: origin[3], unit direction[3], t_near,

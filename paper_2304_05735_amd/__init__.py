@@ -82,7 +82,8 @@ EXPORTS = ["romap_default_config", "romap_create", "romap_destroy", "romap_last_
            "romap_field_backward", "romap_get_phase_times", "romap_sync", "romap_set_occupancy",
            "romap_update_occupancy", "romap_get_occupancy", "romap_marching_cubes",
            "romap_extract_mesh", "romap_mc_case", "romap_box_from_points",
-           "romap_debug_bin_capacity", "romap_get_step_records", "romap_debug_tiles"]
+           "romap_debug_bin_capacity", "romap_get_step_records", "romap_debug_tiles",
+           "romap_debug_mfma_rate"]
 
 
 def lib():
@@ -127,6 +128,7 @@ def lib():
             "romap_mc_case": [i32, P],
             "romap_debug_bin_capacity": [P, i32],
             "romap_debug_tiles": [P, i32, i32],
+            "romap_debug_mfma_rate": [i32, C.POINTER(C.c_double)],
             "romap_get_step_records": [P, C.POINTER(C.c_double)],
             "romap_box_from_points": [P, i64, C.POINTER(romap_box)],
         }
@@ -174,6 +176,16 @@ def box_from_points(xyz):
     if rc != 0:
         raise RomapError(rc, "box_from_points: empty or NULL input")
     return (np.array(b.t[:], np.float32), float(b.yaw), np.array(b.half[:], np.float32))
+
+
+def debug_mfma_rate(precision=None) -> float:
+    """Sustained MFMA rate of the current device in TFLOP/s (BF16 by default)."""
+    x = C.c_double(0.0)
+    p = PREC_BF16 if precision is None else int(precision)
+    rc = lib().romap_debug_mfma_rate(p, C.byref(x))
+    if rc != 0:
+        raise RomapError(rc, "debug_mfma_rate failed")
+    return float(x.value)
 
 
 def mc_case(m: int):

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libromap.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("romap_kernels.hip", "romap_runtime.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("romap_kernels.hip", "romap_runtime.hip",
+                                                       "romap_probe.hip")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

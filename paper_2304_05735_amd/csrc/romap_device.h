@@ -276,3 +276,5 @@ hipError_t rm_launch_init(float* params, int64_t P_grid, int din, int nh, uint32
                           uint32_t k1, hipStream_t st);
 hipError_t rm_launch_debug_positions(const StepArgs& a, int NS, float* pos, hipStream_t st);
 hipError_t rm_launch_reset_loss(const StepArgs& a, hipStream_t st);
+hipError_t rm_launch_mfma_rate(int prec, int blocks, int iters, float* out, hipStream_t st);
+double rm_mfma_rate_flops(int prec, int blocks, int iters);

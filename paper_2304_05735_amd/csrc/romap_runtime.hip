@@ -1971,6 +1971,36 @@ romap_status romap_debug_tiles(romap_ctx* c, int32_t rays_per_item, int32_t gath
   return ROMAP_OK;
 }
 
+romap_status romap_debug_mfma_rate(int32_t precision, double* tflops) {
+  if (!tflops || (precision != ROMAP_PREC_FP32 && precision != ROMAP_PREC_BF16))
+    return ROMAP_E_INVALID_ARG;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return ROMAP_E_HIP;
+  const int blocks = 8 * cus;  // eight 4-wave workgroups per CU: eight waves per SIMD
+  const int iters = 2048;
+  float* out = nullptr;
+  if (hipMalloc((void**)&out, (size_t)blocks * 256 * sizeof(float)) != hipSuccess) return ROMAP_E_OUT_OF_MEMORY;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  romap_status st = ROMAP_E_HIP;
+  float ms = 0.0f;
+  const int prec = precision == ROMAP_PREC_BF16 ? 1 : 0;
+  if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+      rm_launch_mfma_rate(prec, blocks, 64, out, nullptr) == hipSuccess &&  // warm-up
+      hipEventRecord(e0, nullptr) == hipSuccess &&
+      rm_launch_mfma_rate(prec, blocks, iters, out, nullptr) == hipSuccess &&
+      hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+      hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f) {
+    *tflops = rm_mfma_rate_flops(prec, blocks, iters) / (ms * 1e-3) / 1e12;
+    st = ROMAP_OK;
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(out);
+  return st;
+}
+
 romap_status romap_debug_bin_capacity(romap_ctx* c, int32_t slots) {
   if (!c) return ROMAP_E_INVALID_ARG;
   if (slots < 0) return fail(c, ROMAP_E_INVALID_ARG, "slots must be >= 0");

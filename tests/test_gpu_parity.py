@@ -675,3 +675,14 @@ def test_two_stream_step_equals_one_stream():
         assert ga.object_info(i).step == gb.object_info(j).step == 15
         for kind in (pk.PARAMS, pk.ADAM_M, pk.ADAM_V):
             assert np.array_equal(ga.get_params(i, kind), gb.get_params(j, kind)), (i, kind)
+
+
+def test_mfma_rate_probe():
+    """The matrix-core rate probe returns a positive rate below the datasheet
+    peaks (2.5 PFLOP/s BF16 and 157.3 TFLOP/s FP32 dense, with 10 % margin)."""
+    bf = pk.debug_mfma_rate(pk.PREC_BF16)
+    f32 = pk.debug_mfma_rate(pk.PREC_FP32)
+    _say(f"measured MFMA rate: BF16 {bf:.0f} TFLOP/s, FP32 {f32:.1f} TFLOP/s")
+    assert 0 < bf < 2750 and 0 < f32 < 173
+    with pytest.raises(pk.RomapError):
+        pk.debug_mfma_rate(7)
