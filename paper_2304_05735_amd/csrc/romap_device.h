@@ -23,12 +23,11 @@
 #define RM_WG 256           /* threads of the fused field kernel (4 waves) */
 #define RM_FIN_WG 512       /* entries per workgroup of the finishing kernel */
 #define RM_GRAPH_MIN_STEPS 8 /* steps of a romap_train call that repay a graph capture */
-// Work share of the first half of a two-stream step.  Uneven halves overlap
-// different phases of the two (gathers of one with the MLP of the other);
-// measured on 24 objects, ms per step: 0.5 2.203, 0.6 2.193, 0.7 2.180,
-// 0.75 2.175, 0.8 2.193, 0.85 2.186 (one stream: 2.233).
+// Work share of the first group of a two-stream step (the second starts
+// once the first has passed its gather); measured on 24 objects, ms per
+// step: 0.4 1.816, 0.45 1.816, 0.5 1.818, 0.55 1.827, 0.6 1.827.
 #ifndef RM_SPLIT_SHARE
-#define RM_SPLIT_SHARE 0.75
+#define RM_SPLIT_SHARE 0.45
 #endif
 #ifndef RM_MERGE_NUM         /* merge same-cell sample runs where N_l <= NUM/DEN * samples */
 #define RM_MERGE_NUM 1       /* 1/2, 3/4, 1: 2.37, 2.33, 2.33 ms per step, 24 objects x 64 samples */

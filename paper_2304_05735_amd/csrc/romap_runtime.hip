@@ -540,7 +540,8 @@ hipError_t mark_phase(romap_ctx* c, int ph) {
 }
 
 hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a0, bool adam,
-                        bool prof = false, hipStream_t st = nullptr) {
+                        bool prof = false, hipStream_t st = nullptr, hipEvent_t ev_mid = nullptr,
+                        int mid_phase = -1) {
   const int NS = c->cfg.samples_per_ray, K1 = K1_of(c->cfg);
   if (!st) st = c->stream;
   StepArgs a = a0;
@@ -553,6 +554,8 @@ hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a0, bool ad
   RM_MARK(ROMAP_PHASE_RAYGEN);
   if ((e = rm_launch_encode_fwd(a, NS, p.enc_block, st)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_ENCODE);
+  if (ev_mid && mid_phase == ROMAP_PHASE_ENCODE && (e = hipEventRecord(ev_mid, st)) != hipSuccess)
+    return e;
   if ((e = rm_launch_pack(a, K1, st)) != hipSuccess) return e;
   RM_MARK(ROMAP_PHASE_PACK);
   if ((e = rm_launch_field(a, NS, K1, c->cfg.precision, st)) != hipSuccess) return e;
@@ -572,16 +575,21 @@ hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a0, bool ad
 }
 
 // One step of two plans at the same time: the second on the context's second
-// stream, forked from and joined back into the context stream (also under
-// graph capture).  Their objects differ and each has its own scratch, so the
-// two only share the device (bandwidth-bound phases of one overlap
-// latency-bound phases of the other).
+// stream, joined back into the context stream (also under graph capture).
+// Their objects differ and each has its own scratch, so the two only share
+// the device.  The second group starts once the first has passed its
+// gather, so that the groups run different phases at any time: the first
+// group's latency-bound MLP kernel overlaps the second's bandwidth-bound
+// gather, and so on down the step (measured on the 24-object workload:
+// 1.898 ms per step with both groups started together, 1.816 with the
+// offset; waiting for the first group's MLP instead: 1.877).
 hipError_t enqueue_pair(romap_ctx* c, const Plan* p, const StepArgs* a) {
   hipError_t e;
-  if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
+  if ((e = enqueue_step(c, p[0], a[0], true, false, c->stream, c->ev_fork, ROMAP_PHASE_ENCODE)) !=
+      hipSuccess)
+    return e;
   if ((e = hipStreamWaitEvent(c->stream2, c->ev_fork, 0)) != hipSuccess) return e;
   if ((e = enqueue_step(c, p[1], a[1], true, false, c->stream2)) != hipSuccess) return e;
-  if ((e = enqueue_step(c, p[0], a[0], true, false, c->stream)) != hipSuccess) return e;
   if ((e = hipEventRecord(c->ev_join, c->stream2)) != hipSuccess) return e;
   return hipStreamWaitEvent(c->stream, c->ev_join, 0);
 }
