@@ -437,6 +437,7 @@ PMC_PASSES = {
     "st2": "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_ANY SQ_INSTS_LDS_ATOMIC SQ_LDS_ATOMIC_RETURN "
            "SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU SQ_INSTS_SMEM",
 }
+STALL_TABLE_HEADER = "# where the waves' time goes"
 COPY_MIB = 512          # --copy-probe: a plain copy of this size
 GATHER_TABLE_MIB = 1024  # and a gather of random 4-byte words from a table this large
 GATHER_N = 1 << 24
@@ -630,7 +631,7 @@ def pmc_summary(d, workload, steps):
                    f"{mean(k, 'SQ_WAVES'):.0f}")
     out.append("# kernels whose request bytes imply more than the copy's rate (served in part by "
                "the Infinity Cache): " + (", ".join(over) or "none"))
-    out.append("# where the waves' time goes (ratios of wave-cycle counters; per wave: averages "
+    out.append(STALL_TABLE_HEADER + " (ratios of wave-cycle counters; per wave: averages "
                "over the dispatch's waves)")
     out.append("# kernel wave_cycles_per_wave wait_any wait_inst_lds active_valu active_vmem "
                "active_lds lds_bank_conflict_per_lds_cycle lds_addr_conflict_per_lds_cycle "
@@ -686,6 +687,8 @@ def traffic_of(workload, kernels):
     for line in open(path):
         if line.startswith("kernel_source_sha256_16"):
             src = line.split()[1]
+        elif line.startswith(STALL_TABLE_HEADER):
+            break  # the byte table ends here (the stall table repeats the kernel names)
         elif line.strip() and not line.startswith("#"):
             f = line.split()
             tab[f[0]] = float(f[4])

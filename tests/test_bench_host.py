@@ -48,7 +48,9 @@ def test_pmc_summary_bytes(tmp_path, monkeypatch):
           names["field"]: {"TCC_EA0_WRREQ_sum": 30, "TCC_EA0_WRREQ_64B_sum": 10}}
     l2 = {n: {"TCC_HIT_sum": 3, "TCC_MISS_sum": 1} for n in names.values()}
     sq = {n: {"MfmaUtil": 12.5, "SQ_INSTS_VALU_MFMA_MOPS_BF16": 2} for n in names.values()}
-    for sub, tab in (("rd", rd), ("wr", wr), ("l2", l2), ("sq", sq)):
+    st = {n: {"SQ_WAVE_CYCLES": 100, "SQ_WAIT_ANY": 50, "SQ_ACTIVE_INST_VALU": 7,
+              "SQ_ACTIVE_INST_LDS": 4} for n in names.values()}
+    for sub, tab in (("rd", rd), ("wr", wr), ("l2", l2), ("sq", sq), ("st", st)):
         _counters(d, sub, tab)
     bench.pmc_summary(d, "unit", 5)
     lines = open(bench.traffic_file("unit")).read().splitlines()
@@ -59,6 +61,9 @@ def test_pmc_summary_bytes(tmp_path, monkeypatch):
     write = 32 * 20 + 64 * 10
     assert (float(row[2]), float(row[3]), float(row[4])) == (read, write, read + write)
     assert float(row[7]) == 0.75 and float(row[8]) == 0.125 and float(row[9]) == 1024
+    # the stall table repeats the kernel names after the byte table
+    stall = [l.split() for l in lines if l.startswith("k_field ")][1]
+    assert float(stall[2]) == 0.5 and float(stall[4]) == 0.07
     # a current summary feeds the benchmark's traffic figure; a stale one not
     assert bench.traffic_of("unit", ["k_field"]) == read + write
     with open(bench.traffic_file("unit"), "w") as fh:
