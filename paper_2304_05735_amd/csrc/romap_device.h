@@ -23,6 +23,9 @@
 #define RM_WG 256           /* threads of the fused field kernel (4 waves) */
 #define RM_FIN_WG 512       /* entries per workgroup of the finishing kernel */
 #define RM_GRAPH_MIN_STEPS 8 /* steps of a romap_train call that repay a graph capture */
+#ifndef RM_GRAPH_STEPS
+#define RM_GRAPH_STEPS 4     /* training steps captured in one graph */
+#endif
 // Work share of the first group of a two-stream step (the second starts
 // once the first has passed its gather); measured on 24 objects, ms per
 // step: 0.4 1.816, 0.45 1.816, 0.5 1.818, 0.55 1.827, 0.6 1.827.

@@ -583,13 +583,21 @@ hipError_t enqueue_step(romap_ctx* c, const Plan& p, const StepArgs& a0, bool ad
 // gather, and so on down the step (measured on the 24-object workload:
 // 1.898 ms per step with both groups started together, 1.816 with the
 // offset; waiting for the first group's MLP instead: 1.877).
-hipError_t enqueue_pair(romap_ctx* c, const Plan* p, const StepArgs* a) {
+// `steps` steps in a row: each group's next step waits only for its own
+// previous one (the groups' objects and scratch are disjoint), and the
+// second group's step k for the first group's gather of step k; the groups
+// join once at the end.  Eager steps use steps = 1; a captured graph holds
+// RM_GRAPH_STEPS of them, so the first group does not wait at every step for
+// the second group's tail.
+hipError_t enqueue_pair(romap_ctx* c, const Plan* p, const StepArgs* a, int steps = 1) {
   hipError_t e;
-  if ((e = enqueue_step(c, p[0], a[0], true, false, c->stream, c->ev_fork, ROMAP_PHASE_ENCODE)) !=
-      hipSuccess)
-    return e;
-  if ((e = hipStreamWaitEvent(c->stream2, c->ev_fork, 0)) != hipSuccess) return e;
-  if ((e = enqueue_step(c, p[1], a[1], true, false, c->stream2)) != hipSuccess) return e;
+  for (int k = 0; k < steps; ++k) {
+    if ((e = enqueue_step(c, p[0], a[0], true, false, c->stream, c->ev_fork,
+                          ROMAP_PHASE_ENCODE)) != hipSuccess)
+      return e;
+    if ((e = hipStreamWaitEvent(c->stream2, c->ev_fork, 0)) != hipSuccess) return e;
+    if ((e = enqueue_step(c, p[1], a[1], true, false, c->stream2)) != hipSuccess) return e;
+  }
   if ((e = hipEventRecord(c->ev_join, c->stream2)) != hipSuccess) return e;
   return hipStreamWaitEvent(c->stream, c->ev_join, 0);
 }
@@ -1263,13 +1271,17 @@ romap_status romap_add_keyframe(romap_ctx* c, const romap_camera* cam, const uin
 
 // The captured step graph is keyed by the objects, their ray counts, the
 // tile choice and the work-table arena.
+// Steps held by one captured graph of a call of n_steps steps.
+static int graph_steps(int n_steps) { return n_steps >= RM_GRAPH_STEPS ? RM_GRAPH_STEPS : 1; }
+
 static std::vector<int64_t> graph_sig(romap_ctx* c, const std::vector<std::pair<int, int>>& list,
-                                      int rpi, int blk) {
+                                      int rpi, int blk, int steps) {
   std::vector<int64_t> sig = signature(c, list);
   sig.push_back(rpi);
   sig.push_back(blk);
   sig.push_back((int64_t)(uintptr_t)c->d_tables);
   sig.push_back(c->cfg.streams);
+  sig.push_back(steps);
   return sig;
 }
 
@@ -1280,7 +1292,7 @@ static std::vector<int64_t> graph_sig(romap_ctx* c, const std::vector<std::pair<
 static bool graph_pays(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int rpi,
                        int blk, int n_steps) {
   if (c->cfg.use_graph == 2 || n_steps >= RM_GRAPH_MIN_STEPS) return true;
-  return c->gexec && graph_sig(c, list, rpi, blk) == c->gsig;
+  return c->gexec && graph_sig(c, list, rpi, blk, graph_steps(n_steps)) == c->gsig;
 }
 
 romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_steps,
@@ -1369,7 +1381,8 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
         ++c->phase_steps;
       }
     } else if (c->cfg.use_graph && graph_pays(c, list, rpi, blk, n_steps)) {
-      std::vector<int64_t> sig = graph_sig(c, list, rpi, blk);
+      const int G = graph_steps(n_steps);
+      std::vector<int64_t> sig = graph_sig(c, list, rpi, blk, G);
       if (!c->gexec || sig != c->gsig) {
         if (c->gexec) {
           hipGraphExecDestroy(c->gexec);
@@ -1377,7 +1390,11 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
         }
         hipGraph_t graph;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t le = one_step();
+        hipError_t le = hipSuccess;
+        if (split)
+          le = enqueue_pair(c, half, ah, G);
+        else
+          for (int k = 0; k < G && le == hipSuccess; ++k) le = enqueue_step(c, all, a, true);
         hipError_t ce = hipStreamEndCapture(c->stream, &graph);
         if (le != hipSuccess) return fail(c, ROMAP_E_HIP, std::string("capture: ") + hipGetErrorString(le));
         if (ce != hipSuccess) return fail(c, ROMAP_E_HIP, std::string("end capture: ") + hipGetErrorString(ce));
@@ -1389,7 +1406,9 @@ romap_status romap_train(romap_ctx* c, const int32_t* ids, int32_t n, int32_t n_
         }
         c->gsig = sig;
       }
-      for (int i = 0; i < n_steps; ++i) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      int i = 0;
+      for (; i + G <= n_steps; i += G) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      for (; i < n_steps; ++i) HIPCHK(c, one_step());  // the remainder, eagerly
     } else {
       for (int i = 0; i < n_steps; ++i) HIPCHK(c, one_step());
     }
