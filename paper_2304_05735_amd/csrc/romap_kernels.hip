@@ -1186,6 +1186,36 @@ struct Mma<1> {
       }
     }
   }
+  // Tiles of 32 samples (two 16-sample blocks side by side): rows of
+  // STRIDE2 values, 16-byte aligned, so a lane reads 8 consecutive samples.
+  static constexpr int STRIDE2 = 40;
+  __device__ static inline void stage_b2(uint16_t* buf, const bf16x4_t* F, int nf, int lane,
+                                         int col0) {
+    const int g = lane >> 4, n = lane & 15;
+    for (int f = 0; f < nf; ++f) {
+      const shortx4 v = __builtin_bit_cast(shortx4, F[f]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[(16 * f + 4 * g + r) * STRIDE2 + col0 + n] = (uint16_t)v[r];
+    }
+  }
+  // dW += G X^T over 32 samples, one 16x16x32 MFMA per output tile: lane
+  // (i, g) holds samples 8g .. 8g+7 of row i of both operands (the same
+  // order of the contracted index on both sides)
+  template <int MG, int MX>
+  __device__ static inline void dw32(const uint16_t* gb, const uint16_t* xb, floatx4* acc,
+                                     int lane) {
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < MG / 16; ++t) {
+      const bf16x8_t av = *(const bf16x8_t*)(gb + (16 * t + i) * STRIDE2 + 8 * g);
+#pragma unroll
+      for (int u = 0; u < MX / 16; ++u) {
+        const bf16x8_t bv = *(const bf16x8_t*)(xb + (16 * u + i) * STRIDE2 + 8 * g);
+        acc[t * (MX / 16) + u] =
+            __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t * (MX / 16) + u], 0, 0, 0);
+      }
+    }
+  }
 };
 
 // ReLU of FP32 pre-activations, rounded to BF16: rounding to nearest
@@ -1281,7 +1311,9 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
   constexpr bool PACKED = PREC == 1 && NH == 1;
 
   __shared__ __align__(16) char s_wraw[ALIAS && RBYTES > WBYTES ? RBYTES : WBYTES];
-  __shared__ __align__(16) wt s_stage[4][2][STG];
+  // BF16 with one hidden layer stages tiles of 32 samples (pairs of blocks)
+  constexpr int STGS = PACKED ? 64 * Mma<1>::STRIDE2 : STG;
+  __shared__ __align__(16) wt s_stage[4][2][STGS];
   __shared__ __align__(16) float s_rv[4][NS * 4];
   __shared__ float s_rec_own[ALIAS ? 1 : RL + 1];
   wt* s_w = (wt*)s_wraw;
@@ -1544,6 +1576,116 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
     wave_lds_sync();
 
     // ---- backward: recompute activations per block, adjoints, dW ----
+    if constexpr (PACKED) {
+      // BF16, one hidden layer: blocks in pairs, so that each weight
+      // gradient is one product over 32 samples (half the LDS round trips
+      // and MFMA instructions of per-block products); activations recomputed
+      // and rounded as in the forward, adjoints rounded once and used by
+      // both their MFMA and their staging
+#pragma unroll(KEEP_E ? NB / 2 : 1)
+      for (int bp = 0; bp < NB; bp += 2) {
+        bf16x4_t E2[2][KQ], H1b[2][4], Yb[2][1], H2b[2][4], dZb[2][1], dH2b[2][4], dYb[2][1],
+            dH1b[2][4];
+        float dy0[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int b = bp + h;
+          if (KEEP_E) {
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) E2[h][q] = EK[KEEP_E ? b : 0][q];
+          } else {
+            load_enc(sray + 16 * b + n, E2[h]);
+          }
+          floatx4 P[4], Yf[1];
+          gemm_e(E2[h], P);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) H1b[h][f] = relu_b(P[f]);
+          MM::template gemm_b<16, 64>(wF2, H1b[h], Yf, lane);
+          Yb[h][0] = cvt_bf16x4(Yf[0]);
+          MM::template gemm_b<64, 16>(wF3, Yb[h], P, lane);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) H2b[h][f] = relu_b(P[f]);
+          floatx4 dz = {0.0f, 0.0f, 0.0f, 0.0f};
+          dy0[h] = 0.0f;
+          if (g == 0) {
+            const float* q = rv + (16 * b + n) * 4;
+            dy0[h] = q[0];
+            dz = floatx4{q[1], q[2], q[3], 0.0f};
+          }
+          dZb[h][0] = cvt_bf16x4(dz);
+        }
+        // colour head: dW4 += dZ^T H2, dH2 = W4^T dZ masked by ReLU
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          MM::stage_b2(gbuf, dZb[h], 1, lane, 16 * h);
+          MM::stage_b2(xbuf, H2b[h], 4, lane, 16 * h);
+        }
+        wave_lds_sync();
+        MM::template dw32<16, 64>(gbuf, xbuf, acc4, lane);
+        wave_lds_sync();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          floatx4 P[4];
+          MM::template gemm_b<64, 16>(wB4, dZb[h], P, lane);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) dH2b[h][f] = mask_b(P[f], H2b[h][f]);
+        }
+        // dW3 += dH2^T Y, dY = W3^T dH2 (+ density adjoint in row 0)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          MM::stage_b2(gbuf, dH2b[h], 4, lane, 16 * h);
+          MM::stage_b2(xbuf, Yb[h], 1, lane, 16 * h);
+        }
+        wave_lds_sync();
+        MM::template dw32<64, 16>(gbuf, xbuf, acc3, lane);
+        wave_lds_sync();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          floatx4 dYf[1];
+          MM::template gemm_b<16, 64>(wB3, dH2b[h], dYf, lane);
+          if (g == 0) dYf[0][0] += dy0[h];
+          dYb[h][0] = cvt_bf16x4(dYf[0]);
+        }
+        // dW2 += dY^T H1, dH1 = W2^T dY masked
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          MM::stage_b2(gbuf, dYb[h], 1, lane, 16 * h);
+          MM::stage_b2(xbuf, H1b[h], 4, lane, 16 * h);
+        }
+        wave_lds_sync();
+        MM::template dw32<16, 64>(gbuf, xbuf, acc2, lane);
+        wave_lds_sync();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          floatx4 P[4];
+          MM::template gemm_b<64, 16>(wB2, dYb[h], P, lane);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) dH1b[h][f] = mask_b(P[f], H1b[h][f]);
+        }
+        // dW1 += dH1^T E, dE = W1^T dH1
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          MM::stage_b2(gbuf, dH1b[h], 4, lane, 16 * h);
+          MM::stage_b2(xbuf, E2[h], KQ, lane, 16 * h);
+        }
+        wave_lds_sync();
+        MM::template dw32<64, K1>(gbuf, xbuf, acc1, lane);
+        wave_lds_sync();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          floatx4 dEf[KQ];
+          MM::template gemm_b<K1, 64>(wB1, dH1b[h], dEf, lane);
+          const int64_t s = sray + 16 * (bp + h) + n;
+#pragma unroll
+          for (int q = 0; q < KQ; ++q) {
+            const int l0 = 8 * q + 2 * g, l1 = l0 + 1;
+            if (l0 < L) a.de[(int64_t)l0 * S + s] = make_float2(dEf[q][0], dEf[q][1]);
+            if (l1 < L) a.de[(int64_t)l1 * S + s] = make_float2(dEf[q][2], dEf[q][3]);
+          }
+        }
+      }
+      continue;
+    }
 #pragma unroll(KEEP_E ? NB : 1)
     for (int b = 0; b < NB; ++b) {
       const int64_t s = sray + 16 * b + n;
@@ -1555,71 +1697,6 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
         for (int q = 0; q < KQ; ++q) E[q] = EK[KEEP_E ? b : 0][q];
       } else {
         load_enc(s, E);
-      }
-      if constexpr (PACKED) {
-        // recompute the rounded activations; adjoints rounded once, used by
-        // both their MFMA and their staging for the weight gradients
-        bf16x4_t H1b[4], Yb[1], H2b[4], dZb[1], dH2b[4], dYb[1], dH1b[4];
-        floatx4 P[4], Yf[1], dYf[1], dEf[KQ];
-        gemm_e(E, P);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) H1b[f] = relu_b(P[f]);
-        MM::template gemm_b<16, 64>(wF2, H1b, Yf, lane);
-        Yb[0] = cvt_bf16x4(Yf[0]);
-        MM::template gemm_b<64, 16>(wF3, Yb, P, lane);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) H2b[f] = relu_b(P[f]);
-        float dy0 = 0.0f;
-        {
-          floatx4 dz = {0.0f, 0.0f, 0.0f, 0.0f};
-          if (g == 0) {
-            const float* q = rv + (16 * b + n) * 4;
-            dy0 = q[0];
-            dz = floatx4{q[1], q[2], q[3], 0.0f};
-          }
-          dZb[0] = cvt_bf16x4(dz);
-        }
-        // colour head: dW4 += dZ^T H2, dH2 = W4^T dZ masked by ReLU
-        MM::stage_b(gbuf, dZb, 1, lane);
-        MM::stage_b(xbuf, H2b, 4, lane);
-        wave_lds_sync();
-        MM::template dw<16, 64>(gbuf, xbuf, acc4, lane);
-        wave_lds_sync();
-        MM::template gemm_b<64, 16>(wB4, dZb, P, lane);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) dH2b[f] = mask_b(P[f], H2b[f]);
-        // dW3 += dH2^T Y, dY = W3^T dH2 (+ density adjoint in row 0)
-        MM::stage_b(gbuf, dH2b, 4, lane);
-        MM::stage_b(xbuf, Yb, 1, lane);
-        wave_lds_sync();
-        MM::template dw<64, 16>(gbuf, xbuf, acc3, lane);
-        wave_lds_sync();
-        MM::template gemm_b<16, 64>(wB3, dH2b, dYf, lane);
-        if (g == 0) dYf[0][0] += dy0;
-        dYb[0] = cvt_bf16x4(dYf[0]);
-        // dW2 += dY^T H1, dH1 = W2^T dY masked
-        MM::stage_b(gbuf, dYb, 1, lane);
-        MM::stage_b(xbuf, H1b, 4, lane);
-        wave_lds_sync();
-        MM::template dw<16, 64>(gbuf, xbuf, acc2, lane);
-        wave_lds_sync();
-        MM::template gemm_b<64, 16>(wB2, dYb, P, lane);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) dH1b[f] = mask_b(P[f], H1b[f]);
-        // dW1 += dH1^T E, dE = W1^T dH1
-        MM::stage_b(gbuf, dH1b, 4, lane);
-        MM::stage_b(xbuf, E, KQ, lane);
-        wave_lds_sync();
-        MM::template dw<64, K1>(gbuf, xbuf, acc1, lane);
-        wave_lds_sync();
-        MM::template gemm_b<K1, 64>(wB1, dH1b, dEf, lane);
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-          const int l0 = 8 * q + 2 * g, l1 = l0 + 1;
-          if (l0 < L) a.de[(int64_t)l0 * S + s] = make_float2(dEf[q][0], dEf[q][1]);
-          if (l1 < L) a.de[(int64_t)l1 * S + s] = make_float2(dEf[q][2], dEf[q][3]);
-        }
-        continue;
       }
       gemm_e(E, HH[0]);
       relu4(HH[0], 4);
