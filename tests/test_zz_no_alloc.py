@@ -1,5 +1,6 @@
 """The allocation-free forward (romap_field_forward_noalloc) against the
-allocating one (romap_field_forward), through the C ABI: the same colours,
+allocating one (romap_field_forward), through the C ABI, with the FP32 and
+the BF16 MLP: the same colours,
 depths and transmittances bit for bit (both run the same kernels in the same
 launch shape; the parity bar of a forward output, 1e-5 relative, is implied),
 on two calls in a row (the second smaller, so it reads what the first left
@@ -33,12 +34,12 @@ def _rays(rng, n, half):
     return out
 
 
-@pytest.mark.parametrize("N", [64, 128])
-def test_noalloc_forward_equals_allocating_forward(N):
+@pytest.mark.parametrize("N,prec", [(64, pk.PREC_FP32), (128, pk.PREC_FP32), (64, pk.PREC_BF16)])
+def test_noalloc_forward_equals_allocating_forward(N, prec):
     torch.cuda.set_device(0)
     L = 16
     cfg = pk.default_config(n_levels=L, base_res=16, max_res=1024, log2_table_size=14,
-                            samples_per_ray=N, autotune=0)
+                            samples_per_ray=N, autotune=0, precision=prec)
     g = pk.Context(cfg, stream=torch.cuda.current_stream())
     half = np.array([0.4, 0.3, 0.25], np.float32)
     gid = g.add_object(1, np.zeros(3, np.float32), 0.3, half)
