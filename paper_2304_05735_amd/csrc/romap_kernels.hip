@@ -411,9 +411,21 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t j = gtid; j < a.n_regions; j += (int64_t)gridDim.x * blockDim.x)
     a.bin_count[j] = 0;  // fresh fill counters for the binned scatter of this pass
-  const BinBlock bb = a.bblocks[blockIdx.x / RM_ENC_SPLIT];
+  // Workgroup i runs on XCD i mod 8; numbered so that each XCD takes a
+  // contiguous range of (object, level) blocks, a level's table is gathered
+  // by one XCD at a time and stays in its L2: the L2 hit rate goes from 0.67
+  // to 0.93 and the lines fetched beyond the L2 from 2.8 to 0.5 GB per step
+  // on the 24-object workload.  The kernel alone is no faster (it is bound by
+  // the L2's request rate, the same either way, and the XCDs' ranges differ
+  // in cost: 492 -> 522 us), but the bandwidth it no longer takes goes to
+  // the other object group's kernels: 1.812 -> 1.800 ms per step.
+  const int nwg = a.n_bblocks * RM_ENC_SPLIT;
+  const int per_xcd = (nwg + 7) >> 3;
+  const int jw = (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3);
+  if (jw >= nwg) return;
+  const BinBlock bb = a.bblocks[jw / RM_ENC_SPLIT];
   constexpr int SPAN = RM_SCAT_WG / RM_ENC_SPLIT;  // samples of this workgroup
-  const int k0 = (int)(blockIdx.x % RM_ENC_SPLIT) * SPAN;
+  const int k0 = (jw % RM_ENC_SPLIT) * SPAN;
   const BinPair bp = a.bpairs[bb.pair];
   const ObjStatic& ob = a.objs[a.sobj[bp.so].obj];
   const int l = bp.l;
@@ -2247,7 +2259,8 @@ hipError_t rm_launch_raygen(const StepArgs& a, int NS, hipStream_t st) {
 
 hipError_t rm_launch_encode_fwd(const StepArgs& a, int NS, int block, hipStream_t st) {
   if (a.n_bblocks <= 0) return hipSuccess;
-  RM_NS_SWITCH(NS, (k_encode_fwd<NSC><<<a.n_bblocks * RM_ENC_SPLIT, block, 0, st>>>(a)));
+  const int nwg = a.n_bblocks * RM_ENC_SPLIT;  // rounded up to whole rounds of the 8 XCDs
+  RM_NS_SWITCH(NS, (k_encode_fwd<NSC><<<8 * ((nwg + 7) / 8), block, 0, st>>>(a)));
   return hipGetLastError();
 }
 
