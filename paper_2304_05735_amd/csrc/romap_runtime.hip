@@ -1269,11 +1269,11 @@ romap_status romap_add_keyframe(romap_ctx* c, const romap_camera* cam, const uin
   return ROMAP_OK;
 }
 
-// The captured step graph is keyed by the objects, their ray counts, the
-// tile choice and the work-table arena.
 // Steps held by one captured graph of a call of n_steps steps.
 static int graph_steps(int n_steps) { return n_steps >= RM_GRAPH_STEPS ? RM_GRAPH_STEPS : 1; }
 
+// The captured step graph is keyed by the objects, their ray counts, the
+// tile choice, the work-table arena, the stream count and the steps it holds.
 static std::vector<int64_t> graph_sig(romap_ctx* c, const std::vector<std::pair<int, int>>& list,
                                       int rpi, int blk, int steps) {
   std::vector<int64_t> sig = signature(c, list);
