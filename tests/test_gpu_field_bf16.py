@@ -36,7 +36,7 @@ def _pixel_rays(o, cam, half, W, H):
 def test_autograd_field_matches_oracle(L, lt, N):
     _say("field autograd", L, lt, N)
     frames, box = tiny_scene(W=32, H=24, n_views=2)
-    nmax = 32 if L == 2 else 1024
+    nmax = {2: 32, 8: 128}.get(L, 1024)
     cfg = pk.default_config(n_levels=L, base_res=16, max_res=nmax, log2_table_size=lt,
                             samples_per_ray=N, autotune=0)
     rctx = pk.Context(cfg, stream=torch.cuda.current_stream())
@@ -106,15 +106,19 @@ def test_bf16_mlp_error_against_fp64():
     assert np.isfinite(st.loss_mean)
 
 
-@pytest.mark.parametrize("L,lt,N,B", [(2, 8, 32, 256), (16, 14, 64, 512)])
+@pytest.mark.parametrize("L,lt,N,B", [(2, 8, 32, 256), (16, 14, 64, 512), (8, 12, 64, 384),
+                                      (16, 14, 128, 256)])
 def test_bf16_step_matches_bf16_oracle(L, lt, N, B):
     """The BF16 MLP step (BF16 operands, FP32 accumulation) against the
     oracle's BF16 mode entry by entry: FP32 bounds, plus per entry what the
     BF16 rounding decisions near a midpoint can move, per tensor three times
-    the spread that FP32-sized operand perturbations make."""
+    the spread that FP32-sized operand perturbations make.  The cases cover
+    the backward's pairs of 16-sample blocks with 16 and 32 MLP inputs, one
+    and two pairs per ray with the encodings kept in registers, and four
+    pairs per ray with the encodings read again (128 samples)."""
     _say("bf16 step vs bf16 oracle", L, lt, N)
     frames, box = tiny_scene(W=32, H=24, n_views=3)
-    nmax = 32 if L == 2 else 1024
+    nmax = {2: 32, 8: 128}.get(L, 1024)
     g, o, gid = make_pair(L, 16, nmax, lt, N, B, frames, box, precision=pk.PREC_BF16,
                           bf16_oracle=True)
     ob = o.objects[gid]
