@@ -32,8 +32,8 @@
 #ifndef RM_SPLIT_SHARE
 #define RM_SPLIT_SHARE 0.45
 #endif
-#ifndef RM_MERGE_NUM         /* merge same-cell sample runs where N_l <= NUM/DEN * samples */
-#define RM_MERGE_NUM 1       /* 1/2, 3/4, 1: 2.37, 2.33, 2.33 ms per step, 24 objects x 64 samples */
+#ifndef RM_MERGE_NUM         /* merge shared corners of consecutive samples where N_l <= NUM/DEN * samples */
+#define RM_MERGE_NUM 4
 #define RM_MERGE_DEN 1
 #endif
 #define RM_RB_BITS 11       /* binned scatter: table entries per region = 2048 */

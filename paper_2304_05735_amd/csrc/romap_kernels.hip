@@ -556,11 +556,14 @@ __device__ inline void nt_store2(float2* p, float2 v) {
   __builtin_nontemporal_store(w, (rm_f2v*)p);
 }
 
-// The 8 corner records of sample s at level l of object ob; false if none.
+// The 8 corner records of sample s at level l of object ob and its cell;
+// false (values zero) if none.
 template <int NS>
 __device__ inline bool bin_records(const StepArgs& a, const ObjStatic& ob, int l, uint32_t N,
                                    uint32_t T, bool hashed, int64_t s, uint32_t idx[8],
-                                   float2 v[8]) {
+                                   float2 v[8], Cell& cl) {
+#pragma unroll
+  for (int b = 0; b < 8; ++b) v[b] = make_float2(0.0f, 0.0f);
   // the ray's origin, direction, t_n, delta and flags and the sample's
   // adjoint are loaded together, before either test (one memory round trip)
   const float4* rp = (const float4*)(a.rays + s / NS);
@@ -578,13 +581,90 @@ __device__ inline bool bin_records(const StepArgs& a, const ObjStatic& ob, int l
   R.tn = r1.z, R.delta = r1.w;
   float p[3];
   sample_pos(R, (int)(s % NS), half, p);
-  Cell cl;
   make_cell(p, N, cl);
   cell_corners(cl, N, T, hashed, idx);
   float w[8];
   cell_weights(cl, w);
 #pragma unroll
   for (int b = 0; b < 8; ++b) v[b] = make_float2(w[b] * g.x, w[b] * g.y);
+  return true;
+}
+
+// Shared corners of consecutive samples.  Cells c and n = c + d share a
+// vertex only if |d| <= 1 on every axis; corner b of c (vertex c + bits(b))
+// is then a corner of n where d is 0, or where d = +1 and bit b is 1, or
+// d = -1 and bit b is 0.
+__device__ inline uint32_t shared_corners(int c0, int c1, int c2, int n0, int n1, int n2) {
+  const int d0 = n0 - c0, d1 = n1 - c1, d2 = n2 - c2;
+  if (abs(d0) > 1 || abs(d1) > 1 || abs(d2) > 1) return 0u;
+  const uint32_t m = (uint32_t)(d0 != 0) | ((uint32_t)(d1 != 0) << 1) | ((uint32_t)(d2 != 0) << 2);
+  const uint32_t up = (uint32_t)(d0 > 0) | ((uint32_t)(d1 > 0) << 1) | ((uint32_t)(d2 > 0) << 2);
+  uint32_t r = 0u;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) r |= (uint32_t)(((uint32_t)b & m) == up) << b;
+  return r;
+}
+
+// Parity slots: slot q of a cell holds its corner b = q ^ pc, pc the
+// cell's coordinate parities (bit k: c_k & 1), so slot q is the corner whose
+// vertex has parities q, and a vertex takes the same slot in every cell it
+// is a corner of.  Corner b and corner b ^ 1 stay an x-pair.
+
+// bit b of the result is bit b ^ m of x (8 bits)
+__device__ inline uint32_t xor_permute_bits(uint32_t x, uint32_t m) {
+  if (m & 1u) x = ((x & 0x55u) << 1) | ((x >> 1) & 0x55u);
+  if (m & 2u) x = ((x & 0x33u) << 2) | ((x >> 2) & 0x33u);
+  if (m & 4u) x = ((x & 0x0Fu) << 4) | ((x >> 4) & 0x0Fu);
+  return x;
+}
+
+// y[b] <- y[b ^ m], as three conditional exchanges
+template <typename T>
+__device__ inline void xor_permute(T y[8], uint32_t m) {
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const bool sw = (m >> t) & 1u;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (b & (1 << t)) continue;
+      const T p = y[b], q = y[b | (1 << t)];
+      y[b] = sw ? q : p;
+      y[b | (1 << t)] = sw ? p : q;
+    }
+  }
+}
+
+// the value of lane + O (undefined past the wave's last lane)
+template <int O>
+__device__ inline int lane_down(int x) {
+  if constexpr (O == 1) return dppi<0x130>(x);  // wave_shl:1
+  else return __shfl_down(x, O, 64);
+}
+
+template <int O>
+__device__ inline float lane_down_f(float x) {
+  return __int_as_float(lane_down<O>(__float_as_int(x)));
+}
+
+// One step of a segmented suffix sum over chains of lanes, in parity slots.
+// Bit q of open says that the sum in v[q] covers lanes lane .. lane + O - 1
+// of its vertex's chain and the chain goes on; the sum of lane + O (the
+// same slot there) is added and the chain's end there carried over.
+// Returns false, adding nothing, once no chain of the wave is open.
+template <int O>
+__device__ inline bool chain_step(float2 v[8], uint32_t& open) {
+  if (__ballot(open != 0u) == 0ull) return false;
+  float2 y[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) y[q] = make_float2(lane_down_f<O>(v[q].x), lane_down_f<O>(v[q].y));
+  const uint32_t yo = (uint32_t)lane_down<O>((int)open);
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if ((open >> q) & 1u) {
+      v[q].x += y[q].x;
+      v[q].y += y[q].y;
+    }
+  open &= yo;
   return true;
 }
 
@@ -656,51 +736,52 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
   const bool hashed = (ob.hashed_mask >> bp.l) & 1u;
   float* gl = (a.grad_override ? a.grad_override : ob.grad) + ob.off[bp.l];
   float2* rval = a.rec_val + bp.rec_base;
-  bool has =
-      k < bp.n_samples && bin_records<NS>(a, ob, bp.l, NL, TL, hashed, bp.s_begin + k, idx, v);
+  Cell cl;
+  const bool has = k < bp.n_samples &&
+                   bin_records<NS>(a, ob, bp.l, NL, TL, hashed, bp.s_begin + k, idx, v, cl);
+  uint32_t keep = has ? 0xFFu : 0u;  // bit b: corner b is written as a record
   if (bp.merge) {
-    // Coarse dense level: consecutive samples of a ray (consecutive lanes)
-    // often share a cell and so all 8 entries.  Sums over runs of equal cells
-    // (key: the cell's first corner index, which is unique on a dense level,
-    // and the ray's parity within the wave); a lane gathers its run's next 3
-    // samples, so the run's head and every 4th sample after it carry the
-    // records of the run.
+    // Consecutive samples of a ray (consecutive lanes) share corners where
+    // their cells touch, and runs of samples share a whole cell.  A vertex's
+    // occurrences along the ray form a chain of lanes linked corner to
+    // corner; every chain is summed into its first lane (a segmented suffix
+    // sum by doubling, at most 6 steps, in parity slots so that a vertex
+    // keeps its slot from lane to lane), which alone writes the record.  A
+    // sample without records (a zero adjoint, or skipped by the occupancy
+    // test) breaks the chains through it.
     const int lane = tid & 63;
-    const uint32_t key = has ? (idx[0] | (((uint32_t)((bp.s_begin + k) / NS) & 1u) << 31))
-                             : 0xFFFFFFFFu - (uint32_t)lane;
-    // runs are maximal groups of consecutive lanes with one key, named by
-    // their first lane: a sample without records (skipped by the occupancy
-    // test, or a zero adjoint) ends a run even where the cell goes on, so
-    // lanes are merged only within one run
-    const uint32_t kp = __shfl_up(key, 1, 64);
-    const uint64_t heads = __ballot(lane == 0 || kp != key);
-    const int start = 63 - __clzll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)));
-#pragma unroll
-    for (int o = 1; o < 4; o <<= 1) {
-      const int sn = __shfl_down(start, o, 64);
-      const bool same = lane + o < 64 && sn == start;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const float yx = __shfl_down(v[b].x, o, 64), yy = __shfl_down(v[b].y, o, 64);
-        if (same) {
-          v[b].x += yx;
-          v[b].y += yy;
-        }
-      }
-    }
-    has = has && ((lane - start) & 3) == 0;
+    const int ray = (int)((bp.s_begin + k) / NS);
+    const int c0 = has ? (int)cl.c[0] : -2, c1 = has ? (int)cl.c[1] : -2,
+              c2 = has ? (int)cl.c[2] : -2;
+    // the next lane's values (wave_shl:1), read by every lane of the wave
+    const int nh = dppi<0x130>(has ? 1 : 0), nr = dppi<0x130>(ray);
+    const int n0 = dppi<0x130>(c0), n1 = dppi<0x130>(c1), n2 = dppi<0x130>(c2);
+    const bool next_in = has && lane < 63 && nh != 0 && nr == ray;
+    const uint32_t pc = (uint32_t)(c0 & 1) | ((uint32_t)(c1 & 1) << 1) | ((uint32_t)(c2 & 1) << 2);
+    xor_permute(v, pc);
+    xor_permute(idx, pc);
+    uint32_t open = next_in ? xor_permute_bits(shared_corners(c0, c1, c2, n0, n1, n2), pc) : 0u;
+    // vertices the previous lane's chains continue into are summed there
+    // (wave_shr:1; lane 0 reads 0: no chain comes in)
+    keep &= ~(uint32_t)dppi<0x138>((int)open);
+    if (chain_step<1>(v, open))
+      if (chain_step<2>(v, open))
+        if (chain_step<4>(v, open))
+          if (chain_step<8>(v, open))
+            if (chain_step<16>(v, open)) chain_step<32>(v, open);
   }
-  if (has) {
+  if (keep) {
     // an x-pair of corners in one region takes both ranks with one atomic
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      const bool k0 = (keep >> (2 * q)) & 1u, k1 = (keep >> (2 * q + 1)) & 1u;
       const uint32_t r0 = idx[2 * q] >> RM_RB_BITS, r1 = idx[2 * q + 1] >> RM_RB_BITS;
-      if (r0 == r1) {
+      if (k0 && k1 && r0 == r1) {
         rank[2 * q] = atomicAdd(&lcnt[r0], 2);
         rank[2 * q + 1] = rank[2 * q] + 1;
       } else {
-        rank[2 * q] = atomicAdd(&lcnt[r0], 1);
-        rank[2 * q + 1] = atomicAdd(&lcnt[r1], 1);
+        if (k0) rank[2 * q] = atomicAdd(&lcnt[r0], 1);
+        if (k1) rank[2 * q + 1] = atomicAdd(&lcnt[r1], 1);
       }
     }
   }
@@ -715,16 +796,17 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
     for (int r = tid; r < bp.R; r += RM_SCAT_WG)
       gpos[r] = lcnt[r] ? atomicAdd(&a.bin_count[bp.bin_base + r], lcnt[r]) : 0;
   const int n = block_exclusive_scan<RM_SCAT_WG>(lcnt, lbase, bp.R, s_wsum);
-  if (has) {
+  if (keep) {
     int lb[8];  // all eight bases first: one LDS round trip
 #pragma unroll
     for (int b = 0; b < 8; ++b) lb[b] = lbase[idx[b] >> RM_RB_BITS];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int j = lb[b] + rank[b];
-      s_id[j] = idx[b];
-      s_val[j] = v[b];
-    }
+    for (int b = 0; b < 8; ++b)
+      if ((keep >> b) & 1u) {
+        const int j = lb[b] + rank[b];
+        s_id[j] = idx[b];
+        s_val[j] = v[b];
+      }
   }
   if (one && tid < bp.R) gpos[tid] = mine;
   __syncthreads();

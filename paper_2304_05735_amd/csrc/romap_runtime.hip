@@ -365,9 +365,10 @@ void build_plan(romap_ctx* c, const std::vector<std::pair<int, int>>& list, int 
       bp.l = l;
       bp.nb = (int)((So + RM_SCAT_WG - 1) / RM_SCAT_WG);
       bp.R = (int)((o.T_l[l] + RM_RB - 1) >> RM_RB_BITS);
-      // runs of samples in one cell are merged on dense levels with at most
-      // RM_MERGE_NUM / RM_MERGE_DEN cells per sample along a ray's span
-      bp.merge = !((o.hashed_mask >> l) & 1u) && RM_MERGE_DEN * (int)o.N_l[l] <= RM_MERGE_NUM * NS;
+      // corners shared by consecutive samples of a ray are merged on levels
+      // with at most RM_MERGE_NUM / RM_MERGE_DEN cells per sample along a
+      // box's side (on finer levels consecutive samples rarely touch)
+      bp.merge = RM_MERGE_DEN * (int)o.N_l[l] <= RM_MERGE_NUM * NS;
       // records per region: 8 So / R on average (uniform hash, z-slabs of a
       // dense level); twice that plus a margin, a full bin falls back to atomics
       const int64_t expect = (8 * So + bp.R - 1) / bp.R;

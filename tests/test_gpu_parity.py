@@ -547,15 +547,15 @@ def test_occupancy_skip_parity(tiny):
 
 
 @pytest.mark.parametrize("N", [64, 128])
-def test_occupancy_gaps_on_merged_dense_levels(tiny, N):
-    """Regression: on coarse dense levels the binning sums the records of
-    consecutive samples of a ray that share a cell.  A sample skipped by the
-    occupancy test in the middle of such a cell ended the run, but the sums
-    reached across it, so samples after the gap were counted twice (first
-    seen on the 128-object stream).  Here a checkerboard of occupancy cells
-    (every other 64^3 cell off) puts gaps inside nearly every coarse cell of
-    16 levels x 2^19 (six dense levels): loss and gradient match the
-    oracle."""
+def test_occupancy_gaps_on_merged_levels(tiny, N):
+    """On coarse levels the binning sums the records of corners that
+    consecutive samples of a ray share, along chains of samples.  A sample
+    skipped by the occupancy test must end every chain through it (a merge
+    whose sums reached across such a gap once counted the samples after it
+    twice, first seen on the 128-object stream).  Here a checkerboard of
+    occupancy cells (every other 64^3 cell off) puts gaps inside nearly every
+    chain of 16 levels x 2^19 (merged up to N_l = 4 x samples per ray, dense
+    and hashed levels): loss and gradient match the oracle."""
     _say("occupancy gaps on merged levels", N)
     frames, box = tiny
     B = 256
