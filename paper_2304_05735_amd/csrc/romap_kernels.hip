@@ -213,13 +213,20 @@ __device__ inline float corner_weight(const Cell& cl, int b) {
 
 // All 8 corner indices of a cell, with the products shared between corners:
 // (c + 1) * P = c * P + P mod 2^32 for the hash, and the dense index of
-// corner b is the cell's index plus b's offsets.  Same values as corner_index.
+// corner b is the cell's index plus b's offsets.  Same values as corner_index
+// for slot b ^ flip: flip = 0 gives the corners in order b, flip = the
+// cell's coordinate parities gives parity slots (slot q is the corner whose
+// vertex has parities q, the same slot in every cell sharing that vertex).
 __device__ inline void cell_corners(const Cell& cl, uint32_t N, uint32_t T, bool hashed,
-                                    uint32_t idx[8]) {
+                                    uint32_t idx[8], uint32_t flip = 0u) {
+  // per axis, the two vertex offsets in slot order
+  const uint32_t fx = flip & 1u, fy = (flip >> 1) & 1u, fz = (flip >> 2) & 1u;
   if (hashed) {
-    const uint32_t x0 = cl.c[0], x1 = x0 + 1u;
-    const uint32_t y0 = cl.c[1] * 2654435761u, y1 = y0 + 2654435761u;
-    const uint32_t z0 = cl.c[2] * 805459861u, z1 = z0 + 805459861u;
+    const uint32_t xa = cl.c[0], ya = cl.c[1] * 2654435761u, za = cl.c[2] * 805459861u;
+    const uint32_t xb = xa + 1u, yb = ya + 2654435761u, zb = za + 805459861u;
+    const uint32_t x0 = fx ? xb : xa, x1 = fx ? xa : xb;
+    const uint32_t y0 = fy ? yb : ya, y1 = fy ? ya : yb;
+    const uint32_t z0 = fz ? zb : za, z1 = fz ? za : zb;
     const uint32_t m = T - 1u;
     idx[0] = (x0 ^ y0 ^ z0) & m;
     idx[1] = (x1 ^ y0 ^ z0) & m;
@@ -232,22 +239,30 @@ __device__ inline void cell_corners(const Cell& cl, uint32_t N, uint32_t T, bool
   } else {
     const uint32_t n1 = N + 1u, n2 = n1 * n1;
     const uint32_t b0 = cl.c[0] + cl.c[1] * n1 + cl.c[2] * n2;
+    const uint32_t ox[2] = {fx, 1u - fx}, oy[2] = {fy * n1, (1u - fy) * n1},
+                   oz[2] = {fz * n2, (1u - fz) * n2};
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
-      idx[b] = b0 + (uint32_t)(b & 1) + ((b >> 1) & 1) * n1 + ((b >> 2) & 1) * n2;
+    for (int b = 0; b < 8; ++b) idx[b] = b0 + ox[b & 1] + oy[(b >> 1) & 1] + oz[b >> 2];
   }
 }
 
-// All 8 trilinear weights, (wx * wy) * wz as corner_weight, sharing wx * wy.
-__device__ inline void cell_weights(const Cell& cl, float w[8]) {
-  const float wx[2] = {1.0f - cl.f[0], cl.f[0]};
-  const float wy[2] = {1.0f - cl.f[1], cl.f[1]};
-  const float wz[2] = {1.0f - cl.f[2], cl.f[2]};
+// All 8 trilinear weights, (wx * wy) * wz as corner_weight, sharing wx * wy,
+// in the slots of cell_corners with the same flip.
+__device__ inline void cell_weights(const Cell& cl, float w[8], uint32_t flip = 0u) {
+  const float gx = 1.0f - cl.f[0], gy = 1.0f - cl.f[1], gz = 1.0f - cl.f[2];
+  const float wx[2] = {(flip & 1u) ? cl.f[0] : gx, (flip & 1u) ? gx : cl.f[0]};
+  const float wy[2] = {(flip & 2u) ? cl.f[1] : gy, (flip & 2u) ? gy : cl.f[1]};
+  const float wz[2] = {(flip & 4u) ? cl.f[2] : gz, (flip & 4u) ? gz : cl.f[2]};
   float wxy[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) wxy[q] = wx[q & 1] * wy[q >> 1];
 #pragma unroll
   for (int b = 0; b < 8; ++b) w[b] = wxy[b & 3] * wz[b >> 2];
+}
+
+// the cell's coordinate parities (bit k: c_k & 1)
+__device__ inline uint32_t cell_parity(const Cell& cl) {
+  return (cl.c[0] & 1u) | ((cl.c[1] & 1u) << 1) | ((cl.c[2] & 1u) << 2);
 }
 
 __device__ inline int find_sobj(const StepObj* so, int n, int r) {
@@ -451,8 +466,11 @@ __global__ __launch_bounds__(512) void k_encode_fwd(StepArgs a) {
     make_cell(p, N, cl);
     uint32_t idx[8];
     float w[8];
-    cell_corners(cl, N, T, hashed, idx);
-    cell_weights(cl, w);
+    // on levels where consecutive samples of a ray touch, parity slots: a
+    // vertex two lanes share is then loaded by one instruction at one address
+    const uint32_t flip = bp.merge ? cell_parity(cl) : 0u;
+    cell_corners(cl, N, T, hashed, idx, flip);
+    cell_weights(cl, w, flip);
     // The two corners of an x-pair are neighbouring entries on dense levels
     // (index + 1) and, when the cell's x is even, on hashed ones (x enters
     // the hash with factor 1: index ^ 1): then one 16-byte load brings both,
@@ -560,8 +578,8 @@ __device__ inline void nt_store2(float2* p, float2 v) {
 // false (values zero) if none.
 template <int NS>
 __device__ inline bool bin_records(const StepArgs& a, const ObjStatic& ob, int l, uint32_t N,
-                                   uint32_t T, bool hashed, int64_t s, uint32_t idx[8],
-                                   float2 v[8], Cell& cl) {
+                                   uint32_t T, bool hashed, bool par, int64_t s,
+                                   uint32_t idx[8], float2 v[8], Cell& cl) {
 #pragma unroll
   for (int b = 0; b < 8; ++b) v[b] = make_float2(0.0f, 0.0f);
   // the ray's origin, direction, t_n, delta and flags and the sample's
@@ -582,9 +600,10 @@ __device__ inline bool bin_records(const StepArgs& a, const ObjStatic& ob, int l
   float p[3];
   sample_pos(R, (int)(s % NS), half, p);
   make_cell(p, N, cl);
-  cell_corners(cl, N, T, hashed, idx);
+  const uint32_t flip = par ? cell_parity(cl) : 0u;
+  cell_corners(cl, N, T, hashed, idx, flip);
   float w[8];
-  cell_weights(cl, w);
+  cell_weights(cl, w, flip);
 #pragma unroll
   for (int b = 0; b < 8; ++b) v[b] = make_float2(w[b] * g.x, w[b] * g.y);
   return true;
@@ -616,22 +635,6 @@ __device__ inline uint32_t xor_permute_bits(uint32_t x, uint32_t m) {
   if (m & 2u) x = ((x & 0x33u) << 2) | ((x >> 2) & 0x33u);
   if (m & 4u) x = ((x & 0x0Fu) << 4) | ((x >> 4) & 0x0Fu);
   return x;
-}
-
-// y[b] <- y[b ^ m], as three conditional exchanges
-template <typename T>
-__device__ inline void xor_permute(T y[8], uint32_t m) {
-#pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    const bool sw = (m >> t) & 1u;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      if (b & (1 << t)) continue;
-      const T p = y[b], q = y[b | (1 << t)];
-      y[b] = sw ? q : p;
-      y[b | (1 << t)] = sw ? p : q;
-    }
-  }
 }
 
 // the value of lane + O (undefined past the wave's last lane)
@@ -738,7 +741,8 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
   float2* rval = a.rec_val + bp.rec_base;
   Cell cl;
   const bool has = k < bp.n_samples &&
-                   bin_records<NS>(a, ob, bp.l, NL, TL, hashed, bp.s_begin + k, idx, v, cl);
+                   bin_records<NS>(a, ob, bp.l, NL, TL, hashed, bp.merge, bp.s_begin + k, idx,
+                                   v, cl);
   uint32_t keep = has ? 0xFFu : 0u;  // bit b: corner b is written as a record
   if (bp.merge) {
     // Consecutive samples of a ray (consecutive lanes) share corners where
@@ -757,9 +761,8 @@ __global__ __launch_bounds__(RM_SCAT_WG) void k_bin_scatter(StepArgs a) {
     const int nh = dppi<0x130>(has ? 1 : 0), nr = dppi<0x130>(ray);
     const int n0 = dppi<0x130>(c0), n1 = dppi<0x130>(c1), n2 = dppi<0x130>(c2);
     const bool next_in = has && lane < 63 && nh != 0 && nr == ray;
+    // idx and v are in parity slots (bin_records with par)
     const uint32_t pc = (uint32_t)(c0 & 1) | ((uint32_t)(c1 & 1) << 1) | ((uint32_t)(c2 & 1) << 2);
-    xor_permute(v, pc);
-    xor_permute(idx, pc);
     uint32_t open = next_in ? xor_permute_bits(shared_corners(c0, c1, c2, n0, n1, n2), pc) : 0u;
     // vertices the previous lane's chains continue into are summed there
     // (wave_shr:1; lane 0 reads 0: no chain comes in)
