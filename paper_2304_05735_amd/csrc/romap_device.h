@@ -28,9 +28,10 @@
 #endif
 // Work share of the first group of a two-stream step (the second starts
 // once the first has passed its gather); measured on 24 objects, ms per
-// step: 0.4 1.816, 0.45 1.816, 0.5 1.818, 0.55 1.827, 0.6 1.827.
+// step (two runs each): 0.4 1.718, 0.45 1.722 1.719, 0.5 1.705 1.703,
+// 0.55 1.709 1.705, 0.6 1.756.
 #ifndef RM_SPLIT_SHARE
-#define RM_SPLIT_SHARE 0.45
+#define RM_SPLIT_SHARE 0.50
 #endif
 #ifndef RM_MERGE_NUM         /* merge shared corners of consecutive samples where N_l <= NUM/DEN * samples */
 #define RM_MERGE_NUM 4
