@@ -77,6 +77,58 @@ def test_autograd_field_matches_oracle(L, lt, N):
     assert not torch.equal(field.params.detach().cpu(), torch.from_numpy(p))
 
 
+@pytest.mark.parametrize("N", [32, 64, 128])
+def test_long_corner_chains_match_oracle(N):
+    """Short ray segments (from a hundredth of a finest-level cell to a few
+    coarse cells) put many consecutive samples of a ray in one cell, or in
+    cells that touch, on most levels: the binning's shared-corner merge then
+    sums chains of up to a whole wave of lanes (every step of its doubling;
+    at 128 samples a ray's chains also meet the boundary between its two
+    waves).  Outputs and parameter gradient of the field match the oracle."""
+    _say("long corner chains", N)
+    L, lt, nmax = 16, 16, 1024
+    cfg = pk.default_config(n_levels=L, base_res=16, max_res=nmax, log2_table_size=lt,
+                            samples_per_ray=N, autotune=0)
+    rctx = pk.Context(cfg, stream=torch.cuda.current_stream())
+    o = oracle.OracleContext(oracle.make_config(L=L, nmin=16, nmax=nmax, log2T=lt, N=N))
+    t, yaw, half = np.zeros(3, np.float32), 0.1, np.array([0.4, 0.3, 0.35], np.float32)
+    gid = rctx.add_object(1, t, yaw, half)
+    oid = o.add_object(1, t, yaw, half)
+    ob = o.objects[oid]
+    p = random_params(oracle.grid_params(ob.lv), 2 * L, seed=43).astype(np.float32)
+    rctx.set_params(gid, p)
+    ob.params[:] = p.astype(np.float64)
+    rng = np.random.default_rng(44)
+    n = 192
+    org = rng.uniform(-0.9, 0.9, (n, 3)) * half
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d[:16] = np.eye(3)[rng.integers(0, 3, 16)]  # some along an axis: runs on one cell row
+    span = np.exp(rng.uniform(np.log(2e-5), np.log(0.2), n))
+    rays_np = np.concatenate([org, d, np.zeros((n, 1)), span[:, None]], 1).astype(np.float32)
+    field = RomapField(rctx, gid)
+    rays = torch.from_numpy(rays_np).cuda()
+    rgb, depth, tend = field(rays)
+    orgb, odepth, otend, _ = o.field(oid, rays_np)
+    torch.cuda.synchronize()
+    assert_fwd_close(rgb.detach().cpu().numpy(), orgb, what="rgb")
+    assert_fwd_close(depth.detach().cpu().numpy(), odepth, what="depth")
+    assert_fwd_close(tend.detach().cpu().numpy(), otend, what="tend")
+    a = rng.standard_normal((n, 3)).astype(np.float32)
+    b = rng.standard_normal(n).astype(np.float32)
+    c = rng.standard_normal(n).astype(np.float32)
+    loss = (rgb * torch.from_numpy(a).cuda()).sum() + (depth * torch.from_numpy(b).cuda()).sum() \
+        + (tend * torch.from_numpy(c).cuda()).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    mass, allow = np.zeros(p.size), np.zeros(p.size)
+    _, _, _, og = o.field(oid, rays_np, d_rgb=a, d_depth=b, d_tend=c, grad=True, mass=mass,
+                          ambiguous=allow)
+    err = assert_grad_close(field.params.grad.cpu().numpy(), og, mass, allow,
+                            what="field grad, long chains", cuts=tensor_cuts(o, oid))
+    _say(f"  field grad rel err {err:.2e}")
+
+
 def test_bf16_mlp_error_against_fp64():
     """BF16 MFMA MLP (FP32 accumulate, FP32 grid, transmittance and Adam):
     rendered colour, loss and gradient errors against the FP64 oracle."""
