@@ -48,7 +48,9 @@
 #endif
 #define RM_ACC_CHUNK 32768  /* records per accumulation workgroup (about; 8192, 16384, 32768: 2.33, 2.23, 2.22 ms per step) */
 #define RM_ACC_MAXK 256     /* accumulation workgroups per region, at most */
-#define RM_GROUP_RECORDS (1ll << 29) /* record slots of one bin group (5 GiB) */
+#ifndef RM_GROUP_RECORDS
+#define RM_GROUP_RECORDS (1ll << 29) /* record slots of one bin group (4 GiB) */
+#endif
 #ifndef RM_ACC_RQ
 #define RM_ACC_RQ 4         /* quads of records per thread the accumulation keeps in registers */
 #endif
