@@ -1946,35 +1946,43 @@ __global__ __launch_bounds__(RM_WG) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 
 // applied here, else the gradient is written.  A block owns
 // 256 record columns, 4 per lane (column RM_REC_LOSS_NH is the loss); its 16
 // waves sum interleaved sixteenths of the items, then combine in LDS.
-__global__ __launch_bounds__(1024) void k_reduce(StepArgs a) {
-  __shared__ float4 s_part[16][64];
+__global__ __launch_bounds__(RM_RED_WG) void k_reduce(StepArgs a) {
+  constexpr int NW = RM_RED_WG / 64;
+  __shared__ float4 s_part[NW][64];
   const StepObj so = a.sobj[blockIdx.y];
   const ObjStatic& ob = a.objs[so.obj];
   const int nm = (int)(ob.P - ob.P_grid);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j0 = blockIdx.x * 256 + 4 * lane;  // 4 columns per lane (the stride is a multiple of 4)
-  float4 s0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), s1 = s0;
+  float4 s[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) s[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   const int stride = RM_REC_STRIDE_NH(a.mlp_layers), rloss = RM_REC_LOSS_NH(a.mlp_layers);
   if (j0 < stride) {
+    // wave w sums items w, w + NW, ...: four per lane in flight, each into
+    // its own partial sum (a fixed order: deterministic)
     const float* col = a.partials + j0;
-    int it = so.item_begin + wave;
-    for (; it + 16 < so.item_end; it += 32) {  // two items per lane in flight
-      const float4 x = *(const float4*)(col + (int64_t)it * stride);
-      const float4 y = *(const float4*)(col + (int64_t)(it + 16) * stride);
-      s0.x += x.x; s0.y += x.y; s0.z += x.z; s0.w += x.w;
-      s1.x += y.x; s1.y += y.y; s1.z += y.z; s1.w += y.w;
-    }
-    if (it < so.item_end) {
-      const float4 x = *(const float4*)(col + (int64_t)it * stride);
-      s0.x += x.x; s0.y += x.y; s0.z += x.z; s0.w += x.w;
+    for (int it = so.item_begin + wave; it < so.item_end; it += 4 * NW) {
+      float4 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        x[u] = it + u * NW < so.item_end ? *(const float4*)(col + (int64_t)(it + u * NW) * stride)
+                                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        s[u].x += x[u].x; s[u].y += x[u].y; s[u].z += x[u].z; s[u].w += x[u].w;
+      }
     }
   }
-  s_part[wave][lane] = make_float4(s0.x + s1.x, s0.y + s1.y, s0.z + s1.z, s0.w + s1.w);
+  s_part[wave][lane] = make_float4((s[0].x + s[1].x) + (s[2].x + s[3].x),
+                                   (s[0].y + s[1].y) + (s[2].y + s[3].y),
+                                   (s[0].z + s[1].z) + (s[2].z + s[3].z),
+                                   (s[0].w + s[1].w) + (s[2].w + s[3].w));
   __syncthreads();
   if (wave != 0 || j0 >= stride) return;
   float4 t = s_part[0][lane];
 #pragma unroll
-  for (int w = 1; w < 16; ++w) {  // fixed order: deterministic
+  for (int w = 1; w < NW; ++w) {  // fixed order: deterministic
     const float4 u = s_part[w][lane];
     t.x += u.x; t.y += u.y; t.z += u.z; t.w += u.w;
   }
@@ -2409,7 +2417,7 @@ hipError_t rm_launch_field(const StepArgs& a, int NS, int K1, int prec, hipStrea
 hipError_t rm_launch_reduce(const StepArgs& a, hipStream_t st) {
   if (a.n_sobj <= 0) return hipSuccess;
   dim3 grid(cdiv(RM_REC_LOSS_NH(a.mlp_layers) + 1, 256), a.n_sobj);
-  k_reduce<<<grid, 1024, 0, st>>>(a);
+  k_reduce<<<grid, RM_RED_WG, 0, st>>>(a);
   return hipGetLastError();
 }
 
