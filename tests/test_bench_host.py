@@ -89,3 +89,47 @@ def test_trace_summary_table(tmp_path, monkeypatch):
                                                                      "75.00", "90.00"]
     assert body[1][0] == "k_pack(StepArgs," and body[1][-4] == "8.00"
     assert "--steps 100 --warmup 10 --only-headline --streams 1" in text
+
+
+def _fake_psnr(monkeypatch, batched):
+    """equal_psnr over synthetic curves: the plain path rises 0.1 dB over the
+    steps from a per-seed base; `batched(step, base)` gives the batched path."""
+    import types
+    import paper_2304_05735_amd as pk
+    monkeypatch.setattr(pk, "BATCH_ALL", "all", raising=False)
+    monkeypatch.setattr(pk, "BATCH_PER_OBJECT", "per", raising=False)
+    monkeypatch.setattr(pk, "PREC_FP32", 0, raising=False)
+
+    def make_ctx(wl, pr, mode, graph, seed=0, **k):
+        return types.SimpleNamespace(key=(pr, mode, seed)), None, None
+
+    def curve(q, wl, ids, rays, n, chunk):
+        pr, mode, seed = q.key
+        base = 27.0 + 0.4 * seed
+        f = (lambda s: batched(s, base)) if (mode == "all" and pr == 1) else \
+            (lambda s: base + 0.1 * s / 2000)
+        return [(s, f(s)) for s in range(chunk, n + 1, chunk)]
+
+    monkeypatch.setattr(bench, "make_ctx", make_ctx)
+    monkeypatch.setattr(bench, "psnr_curve", curve)
+    wl = types.SimpleNamespace(eval_views=[0])
+    return bench.equal_psnr(wl, [0], [1], 1, 2000, 250, 2.0, 6.0, seeds=(0, 1))
+
+
+def test_equal_psnr_rule(monkeypatch):
+    # within 0.1 dB after the steps: the ratio of rates at equal steps
+    out = _fake_psnr(monkeypatch, lambda s, b: b + 0.1 * s / 2000 - 0.05)
+    assert out["speedup_at_equal_psnr"] == 3.0 and out["delta_psnr"] == -0.05
+    assert len(out["curve_batched"]) == 16 and len(out["curve_plain_fp32"]) == 8
+    # below: the batched path trains on and its time to the plain path's PSNR
+    # (27.3 dB; its mean is 26.8 + 0.15 dB per 1000 steps, first at or above
+    # it at the 3500-step checkpoint) is compared with the plain path's 2000
+    out = _fake_psnr(monkeypatch, lambda s, b: b - 0.4 + 0.3 * s / 2000)
+    assert out["psnr_batched"] == 27.1 and out["steps_batched_to_target"] == 3500
+    assert out["speedup_at_equal_psnr"] == round(2000 * 6.0 / (3500 * 2.0), 3)
+    # above: reached before the steps end
+    out = _fake_psnr(monkeypatch, lambda s, b: b + 0.3 * s / 1000)
+    assert out["steps_batched_to_target"] == 500
+    # never reached within twice the steps: null
+    out = _fake_psnr(monkeypatch, lambda s, b: b - 1.0)
+    assert out["steps_batched_to_target"] is None and out["speedup_at_equal_psnr"] is None
