@@ -40,7 +40,10 @@
 #ifndef RM_SPLIT_SHARE
 #define RM_SPLIT_SHARE 0.50
 #endif
-#ifndef RM_MERGE_NUM         /* merge shared corners of consecutive samples where N_l <= NUM/DEN * samples */
+// The binning merges the corners consecutive samples of a ray share on
+// levels with N_l <= NUM/DEN * samples per ray (NUM/DEN = 2, 4, 8: 1.741,
+// 1.742, 1.746 ms per step on 24 objects; finer levels rarely share any).
+#ifndef RM_MERGE_NUM
 #define RM_MERGE_NUM 4
 #define RM_MERGE_DEN 1
 #endif
